@@ -1,0 +1,126 @@
+/*
+ * oracle.h -- plain, slow, FP64 CPU reference of the banded operator set of
+ * "Banded Matrix Operators for Gaussian Markov Models in the Automatic
+ * Differentiation Era" (Durrande et al., AISTATS 2019).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this code; only the test-suite, the smoke check and the CPU-baseline leg
+ * of the benchmark do.  It shares no source with the HIP path.
+ *
+ * Storage (Section 4.3, "Storage footprint"): a banded n x n matrix B with lower
+ * bandwidth l and upper bandwidth u is kept as n records of l+u+1 values; record
+ * j is column j of B restricted to the band, B[j-u .. j+l, j], and the value
+ * B[i,j] sits at slot u+i-j of record j.  Records are ld >= l+u+1 doubles apart.
+ * For lower-banded / symmetric-stored matrices u = 0 and slot d = i-j holds
+ * B[j+d, j].  Slots that fall outside the matrix (i < 0 or i >= n) are never read
+ * and are written as 0 in outputs.
+ *
+ * All pointers are host pointers owned by the caller.  Every routine is a direct
+ * transcription of the operator's definition or of the paper's algorithm using
+ * dense (i,j) indices mapped onto the band, as the appendix on algorithms does.
+ */
+#ifndef BANDED_ORACLE_H
+#define BANDED_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* C: banded Cholesky Q = L L^T (Algorithm 1; Section 4.1).  Q symmetric, stored
+ * as its lower band with k sub-diagonals.  Returns 0, or r > 0 when the leading
+ * minor of order r is not positive definite (pivot <= 0 or NaN); rows >= r-1 of
+ * L are then zero. */
+int or_chol(int64_t n, int k, int64_t ld, const double *Q, double *L);
+
+/* log det(L L^T) = 2 sum_i log L_ii (Eq. (2), Eq. (3)), Neumaier-compensated. */
+double or_logdet(int64_t n, int k, int64_t ld, const double *L);
+
+/* S: triangular solve (Section 4.1).  trans = 0: x = L^{-1} b;
+ * trans = 1: x = L^{-T} b (the upper-banded variant). */
+void or_trsv(int64_t n, int k, int64_t ld, const double *L, int trans,
+             const double *b, double *x);
+
+/* I: lower band of width kout >= k of (L L^T)^{-1} (Algorithm 3, Takahashi),
+ * output records of stride lds >= kout+1. */
+void or_subset_inv(int64_t n, int k, int64_t ld, const double *L, int kout,
+                   int64_t lds, double *S);
+
+/* Reverse mode of C (Algorithm 2): Qbar = d c / d Q for the stored lower-band
+ * entries of Q, given Lbar = d c / d L.  Lbar is not modified. */
+void or_chol_bwd(int64_t n, int k, int64_t ld, const double *L,
+                 const double *Lbar, double *Qbar);
+
+/* Reverse mode of I (Algorithm 4): Lbar = d c / d L given S = I(L) and
+ * Sbar = d c / d S for the stored lower-band entries of S (width k). */
+void or_subset_inv_bwd(int64_t n, int k, int64_t ld, const double *L,
+                       const double *S, const double *Sbar, double *Lbar);
+
+/* Reverse mode of S (Table 1, solve matrix-vector).  x is the forward output
+ * (L^{-1} b for trans = 0, L^{-T} b for trans = 1), xbar its sensitivity.
+ * Writes bbar and Lbar (overwrites both). */
+void or_trsv_bwd(int64_t n, int k, int64_t ld, const double *L, int trans,
+                 const double *x, const double *xbar, double *bbar,
+                 double *Lbar);
+
+/* Reverse mode of the log-determinant: Lbar_ii += 2 gbar / L_ii. */
+void or_logdet_bwd(int64_t n, int k, int64_t ld, const double *L, double gbar,
+                   double *Lbar);
+
+/* P: band of op(A) op(B) restricted to lower/upper widths (lc, uc); op = ^T
+ * when the flag is set (Section 4.1, Products; appendix derivation of P). */
+void or_gbmm(int64_t n,
+             int la, int ua, int64_t lda, const double *A, int tA,
+             int lb, int ub, int64_t ldb, const double *B, int tB,
+             int lc, int uc, int64_t ldc, double *C);
+
+/* P: y = op(A) x for a (l,u)-banded A. */
+void or_gbmv(int64_t n, int l, int u, int64_t ld, const double *A, int tA,
+             const double *x, double *y);
+
+/* O: band (l,u) of the outer product m v^T (Section 4.1). */
+void or_outer_band(int64_t n, int l, int u, int64_t ld, const double *m,
+                   const double *v, double *O);
+
+/* Solve of a lower-banded L (k sub-diagonals) against a banded right-hand side
+ * R with upper width u (Algorithm 5): band (k,u) of L^{-1} R. */
+void or_solve_band_mat(int64_t n, int k, int64_t ldl, const double *L, int lr,
+                       int ur, int64_t ldr, const double *R, int64_t ldo,
+                       double *O);
+
+/* The Gaussian loss of a banded precision and its gradients, composed from the
+ * operators above (Table 1 and Algorithms 1-4):
+ *   loss = log det Q - y^T Q^{-1} y + tr(Q^{-1} S)
+ * Q and S are symmetric, stored as lower bands with k sub-diagonals.
+ * parts[0] = log det Q, parts[1] = y^T Q^{-1} y, parts[2] = tr(Q^{-1} S).
+ * Qbar is the gradient with respect to the stored lower-band entries of Q, ybar
+ * the gradient with respect to y.  Any of L, z, Sig, Lbar may be NULL (then
+ * scratch memory is used); when given they receive the intermediates
+ * L = C(Q), z = L^{-1} y, Sig = I(L), Lbar = d loss / d L.
+ * Returns the Cholesky info. */
+int or_gauss_loss(int64_t n, int k, int64_t ld, const double *Q,
+                  const double *y, const double *S, double *parts,
+                  double *Qbar, double *ybar, double *L, double *z,
+                  double *Sig, double *Lbar);
+
+/* The same over a batch of independent problems with OpenMP across problems
+ * (one problem per thread).  Problem p has n[p] rows, k[p] sub-diagonals,
+ * records of stride k[p]+1 starting at element offset boff[p] of the band
+ * arrays, and vectors starting at element voff[p].  parts is 3*nprob, info is nprob.  Returns the number of threads
+ * used. */
+int or_gauss_loss_batch(int nprob, const int64_t *n, const int *k,
+                        const int64_t *boff, const int64_t *voff,
+                        const double *Q, const double *y, const double *S,
+                        double *parts, double *Qbar, double *ybar, int *info);
+
+/* Forward list over a batch (chol, logdet, L^{-1}y, L^{-T}L^{-1}y, band of
+ * Q^{-1}), OpenMP across problems.  Outputs may be NULL except logdet/info. */
+int or_forward_batch(int nprob, const int64_t *n, const int *k,
+                     const int64_t *boff, const int64_t *voff, const double *Q,
+                     const double *y, double *L, double *z, double *x,
+                     double *Sig, double *logdet, int *info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

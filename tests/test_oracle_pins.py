@@ -1,0 +1,500 @@
+"""Pins for the FP64 oracle against what the mathematics fixes: dense numpy /
+LAPACK routines, closed forms, invariants, finite differences and dense
+autograd.  Each test is chosen so that a dropped term, a wrong sign or index or
+a transposed operand anywhere in the oracle fails at least one of them."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import torch
+
+import oracle
+from bandutil import (band_mask, dense_to_gen, dense_to_lower, gen_to_dense,
+                      lower_to_dense, rel_err, sym_to_dense)
+from paper_1902_10078_amd import inputs
+
+SHAPES = [(1, 0), (1, 3), (2, 1), (3, 2), (4, 3), (5, 5), (6, 11), (7, 0),
+          (12, 3), (17, 5), (23, 11), (64, 3), (64, 11), (40, 1)]
+
+
+def make_spd(n, k, seed):
+    rng = np.random.default_rng(seed)
+    L0 = inputs.random_lower_band(n, k, rng)
+    Ld = lower_to_dense(L0)
+    Qd = Ld @ Ld.T
+    return L0, dense_to_lower(Qd, k), Qd
+
+
+# ---------------------------------------------------------------- forward ops
+
+@pytest.mark.parametrize("n,k", SHAPES)
+def test_chol_matches_dense_and_recovers_factor(n, k):
+    L0, Q, Qd = make_spd(n, k, 10 + n + 7 * k)
+    L, info = oracle.chol(Q, k)
+    assert info == 0
+    Lref = np.linalg.cholesky(Qd)
+    assert rel_err(lower_to_dense(L), Lref) < 1e-13
+    assert rel_err(L * band_mask(n, k), L0) < 1e-12
+    # pad slots are written as zero
+    assert np.all(L[band_mask(n, k) == 0] == 0)
+
+
+def test_chol_matches_lapack_banded():
+    n, k = 5000, 5
+    rng = np.random.default_rng(3)
+    L0 = inputs.random_lower_band(n, k, rng)
+    Q = oracle.gbmm(L0, k, 0, L0, k, 0, tB=1, lc=k, uc=0)
+    L, info = oracle.chol(Q, k)
+    assert info == 0
+    ab = sla.cholesky_banded(Q.T.copy(), lower=True)
+    assert rel_err(L, ab.T) < 1e-12
+    assert rel_err(L * band_mask(n, k), L0) < 1e-11
+
+
+def test_gbmm_llt_matches_dense():
+    n, k = 50, 4
+    rng = np.random.default_rng(1)
+    L0 = inputs.random_lower_band(n, k, rng)
+    Q = oracle.gbmm(L0, k, 0, L0, k, 0, tB=1, lc=k, uc=0)
+    Ld = lower_to_dense(L0)
+    assert rel_err(sym_to_dense(Q), Ld @ Ld.T) < 1e-15
+
+
+@pytest.mark.parametrize("la,ua,lb,ub,tA,tB", [
+    (2, 1, 1, 3, 0, 0), (3, 0, 3, 0, 0, 1), (0, 2, 1, 1, 1, 0), (2, 2, 0, 3, 1, 1),
+    (0, 0, 2, 1, 0, 0), (4, 1, 2, 0, 1, 0)])
+def test_gbmm_general_transposes(la, ua, lb, ub, tA, tB):
+    n = 19
+    rng = np.random.default_rng(la * 7 + ub + 3 * tA + tB)
+    A = dense_to_gen(rng.normal(size=(n, n)), la, ua)
+    B = dense_to_gen(rng.normal(size=(n, n)), lb, ub)
+    Ad, Bd = gen_to_dense(A, la, ua), gen_to_dense(B, lb, ub)
+    C = oracle.gbmm(A, la, ua, B, lb, ub, tA=tA, tB=tB)
+    lA, uA = (ua, la) if tA else (la, ua)
+    lB, uB = (ub, lb) if tB else (lb, ub)
+    Cd = (Ad.T if tA else Ad) @ (Bd.T if tB else Bd)
+    assert rel_err(gen_to_dense(C, lA + lB, uA + uB), Cd) < 1e-14
+    # restricted output band
+    C2 = oracle.gbmm(A, la, ua, B, lb, ub, tA=tA, tB=tB, lc=1, uc=0)
+    assert rel_err(gen_to_dense(C2, 1, 0), gen_to_dense(dense_to_gen(Cd, 1, 0), 1, 0)) < 1e-14
+
+
+@pytest.mark.parametrize("l,u,t", [(2, 1, 0), (2, 1, 1), (0, 3, 0), (3, 0, 1)])
+def test_gbmv_and_outer(l, u, t):
+    n = 21
+    rng = np.random.default_rng(5 + l + 3 * u + t)
+    A = dense_to_gen(rng.normal(size=(n, n)), l, u)
+    x = rng.normal(size=n)
+    Ad = gen_to_dense(A, l, u)
+    assert rel_err(oracle.gbmv(A, l, u, x, tA=t), (Ad.T if t else Ad) @ x) < 1e-14
+    m, v = rng.normal(size=n), rng.normal(size=n)
+    O = oracle.outer_band(m, v, l, u)
+    assert rel_err(gen_to_dense(O, l, u), gen_to_dense(dense_to_gen(np.outer(m, v), l, u), l, u)) == 0
+
+
+@pytest.mark.parametrize("n,k", SHAPES)
+def test_logdet_and_solves(n, k):
+    L0, Q, Qd = make_spd(n, k, 100 + n + k)
+    L, _ = oracle.chol(Q, k)
+    sign, ld = np.linalg.slogdet(Qd)
+    assert sign > 0 and abs(oracle.logdet(L, k) - ld) <= 1e-12 * max(1, abs(ld))
+    b = np.random.default_rng(n).normal(size=n)
+    Ld = lower_to_dense(L)
+    z = oracle.trsv(L, k, b, 0)
+    assert rel_err(z, sla.solve_triangular(Ld, b, lower=True)) < 1e-13
+    x = oracle.trsv(L, k, b, 1)
+    assert rel_err(x, sla.solve_triangular(Ld.T, b, lower=False)) < 1e-13
+
+
+@pytest.mark.parametrize("n,k", SHAPES)
+def test_subset_inverse_matches_dense_inverse(n, k):
+    _, Q, Qd = make_spd(n, k, 200 + n + k)
+    L, _ = oracle.chol(Q, k)
+    Sinv = np.linalg.inv(Qd)
+    S = oracle.subset_inv(L, k)
+    assert rel_err(lower_to_dense(S), np.tril(np.triu(Sinv, -k))) < 1e-12 or n == 0
+    # wider output band (kout > k) reaches further entries of Q^{-1}
+    kout = 2 * k + 1
+    S2 = oracle.subset_inv(L, k, kout)
+    assert rel_err(lower_to_dense(S2), np.tril(np.triu(Sinv, -kout))) < 1e-12
+
+
+def test_takahashi_identity_large():
+    """band_k(Sigma L) = diag(1/L_ii): Sigma L = L^{-T} is upper triangular, so
+    its strictly-lower band vanishes and its diagonal is 1/L_ii.  Checked from
+    the k-band of Sigma alone, at a size where no dense inverse is formed."""
+    n, k = 4000, 5
+    rng = np.random.default_rng(7)
+    L0 = inputs.random_lower_band(n, k, rng)
+    Q = oracle.gbmm(L0, k, 0, L0, k, 0, tB=1, lc=k, uc=0)
+    L, _ = oracle.chol(Q, k)
+    S = oracle.subset_inv(L, k)
+    # (Sigma L)[i, j] for 0 <= i-j <= k needs only the symmetric k-band of
+    # Sigma, held here as a (k,k) general band
+    Sg = np.zeros((n, 2 * k + 1))
+    Sd_low = S
+    for d in range(k + 1):
+        Sg[:, k + d] = Sd_low[:, d]
+    for d in range(1, k + 1):
+        Sg[d:, k - d] = Sd_low[: n - d, d]       # upper element (j-d, j) = lower (j, j-d)
+    prod = oracle.gbmm(Sg, k, k, L, k, 0, lc=k, uc=0)
+    expect = np.zeros_like(prod)
+    expect[:, 0] = 1.0 / L[:, 0]
+    assert rel_err(prod * band_mask(n, k), expect) < 1e-12
+
+
+def test_solve_band_mat_alg5():
+    n, k, lr, ur = 25, 3, 2, 2
+    rng = np.random.default_rng(11)
+    L0 = inputs.random_lower_band(n, k, rng)
+    R = dense_to_gen(rng.normal(size=(n, n)), lr, ur)
+    O = oracle.solve_band_mat(L0, k, R, lr, ur)
+    ref = np.linalg.solve(lower_to_dense(L0), gen_to_dense(R, lr, ur))
+    assert rel_err(gen_to_dense(O, k, ur), gen_to_dense(dense_to_gen(ref, k, ur), k, ur)) < 1e-12
+
+
+# ------------------------------------------------------------------- failure
+
+def test_non_spd_info_matches_lapack():
+    n, k, r = 300, 3, 123
+    L0, Q, _ = make_spd(n, k, 9)
+    Q = Q.copy()
+    # make the leading minor of order r+1 indefinite
+    L, _ = oracle.chol(Q, k)
+    Q[r, 0] -= L[r, 0] ** 2 * 1.5
+    _, info = oracle.chol(Q, k)
+    _, linfo = sla.lapack.dpbtrf(Q.T.copy(), lower=1)
+    assert info == r + 1 == linfo
+    Q2 = Q.copy()
+    Q2[r, 0] = np.nan
+    Q2[r - 10, 0] = np.nan
+    _, info2 = oracle.chol(Q2, k)
+    assert info2 == r - 10 + 1
+
+
+# ------------------------------------------------------ reverse mode (torch)
+
+def _tsym_from_band(Bt, n, k):
+    """Differentiable dense symmetric matrix from the stored lower band."""
+    M = torch.zeros((n, n), dtype=torch.float64)
+    for d in range(min(k, n - 1) + 1):
+        idx = torch.arange(n - d)
+        M = M.index_put((idx + d, idx), Bt[: n - d, d], accumulate=True)
+        if d > 0:
+            M = M.index_put((idx, idx + d), Bt[: n - d, d], accumulate=True)
+    return M
+
+
+def _tlow_from_band(Bt, n, k):
+    M = torch.zeros((n, n), dtype=torch.float64)
+    for d in range(min(k, n - 1) + 1):
+        idx = torch.arange(n - d)
+        M = M.index_put((idx + d, idx), Bt[: n - d, d], accumulate=True)
+    return M
+
+
+def _tband_of(M, n, k):
+    cols = []
+    for d in range(k + 1):
+        idx = torch.arange(max(n - d, 0))
+        v = M[idx + d, idx]
+        cols.append(torch.cat([v, torch.zeros(min(d, n), dtype=torch.float64)]))
+    return torch.stack(cols, dim=1)
+
+
+@pytest.mark.parametrize("n,k", [(1, 0), (3, 1), (9, 2), (17, 3), (30, 5), (24, 11), (5, 7)])
+def test_chol_bwd_vs_dense_autograd(n, k):
+    _, Q, _ = make_spd(n, k, 300 + n + k)
+    L, _ = oracle.chol(Q, k)
+    rng = np.random.default_rng(n * k + 1)
+    Lbar = rng.normal(size=L.shape) * band_mask(n, k)
+    Qt = torch.tensor(Q, requires_grad=True)
+    Lt = torch.linalg.cholesky(_tsym_from_band(Qt, n, k))
+    loss = (_tband_of(Lt, n, k) * torch.tensor(Lbar)).sum()
+    loss.backward()
+    ref = Qt.grad.numpy() * band_mask(n, k)
+    got = oracle.chol_bwd(L, k, Lbar)
+    assert rel_err(got, ref) < 1e-11
+
+
+@pytest.mark.parametrize("n,k", [(1, 0), (4, 0), (3, 1), (9, 2), (17, 3), (30, 5), (24, 11), (5, 7)])
+def test_subset_inv_bwd_vs_dense_autograd(n, k):
+    rng = np.random.default_rng(400 + n + k)
+    L0 = inputs.random_lower_band(n, k, rng)
+    S = oracle.subset_inv(L0, k)
+    Sbar = rng.normal(size=S.shape) * band_mask(n, k)
+    Lt = torch.tensor(L0, requires_grad=True)
+    Ld = _tlow_from_band(Lt, n, k)
+    Sig = torch.cholesky_inverse(Ld)
+    loss = (_tband_of(Sig, n, k) * torch.tensor(Sbar)).sum()
+    loss.backward()
+    ref = Lt.grad.numpy() * band_mask(n, k)
+    got = oracle.subset_inv_bwd(L0, k, S, Sbar)
+    assert rel_err(got, ref) < 1e-11
+
+
+def test_subset_inv_bwd_diagonal_closed_form():
+    """k = 0: Sigma_ii = 1/L_ii^2, so Lbar_ii = -2 Sbar_ii / L_ii^3."""
+    n = 50
+    rng = np.random.default_rng(3)
+    L = rng.uniform(1, 2, size=(n, 1))
+    Sbar = rng.normal(size=(n, 1))
+    S = oracle.subset_inv(L, 0)
+    assert rel_err(S[:, 0], 1 / L[:, 0] ** 2) < 1e-15
+    got = oracle.subset_inv_bwd(L, 0, S, Sbar)
+    assert rel_err(got[:, 0], -2 * Sbar[:, 0] / L[:, 0] ** 3) < 1e-15
+
+
+@pytest.mark.parametrize("trans", [0, 1])
+@pytest.mark.parametrize("n,k", [(1, 0), (7, 2), (20, 3), (16, 11)])
+def test_trsv_bwd_vs_dense_autograd(n, k, trans):
+    rng = np.random.default_rng(500 + n + k + trans)
+    L0 = inputs.random_lower_band(n, k, rng)
+    b = rng.normal(size=n)
+    xbar = rng.normal(size=n)
+    Lt = torch.tensor(L0, requires_grad=True)
+    bt = torch.tensor(b, requires_grad=True)
+    Ld = _tlow_from_band(Lt, n, k)
+    A = Ld.T if trans else Ld
+    xt = torch.linalg.solve_triangular(A, bt[:, None], upper=bool(trans))[:, 0]
+    (xt * torch.tensor(xbar)).sum().backward()
+    x = oracle.trsv(L0, k, b, trans)
+    bbar, Lbar = oracle.trsv_bwd(L0, k, x, xbar, trans)
+    assert rel_err(bbar, bt.grad.numpy()) < 1e-12
+    assert rel_err(Lbar, Lt.grad.numpy() * band_mask(n, k)) < 1e-12
+
+
+@pytest.mark.parametrize("n,k", [(1, 0), (2, 1), (13, 3), (31, 5), (20, 11)])
+def test_gauss_loss_vs_dense_autograd(n, k):
+    rng = np.random.default_rng(600 + n + k)
+    L0 = inputs.random_lower_band(n, k, rng)
+    Q = oracle.gbmm(L0, k, 0, L0, k, 0, tB=1, lc=k, uc=0)
+    y = rng.normal(size=n)
+    S = inputs.random_sym_band_dd(n, k, rng)
+    out = oracle.gauss_loss(Q, k, y, S)
+    assert out["info"] == 0
+    Qt = torch.tensor(Q, requires_grad=True)
+    yt = torch.tensor(y, requires_grad=True)
+    Qd = _tsym_from_band(Qt, n, k)
+    Sd = torch.tensor(sym_to_dense(S))
+    Qi = torch.linalg.inv(Qd)
+    parts = [torch.logdet(Qd), yt @ Qi @ yt, torch.trace(Qi @ Sd)]
+    loss = parts[0] - parts[1] + parts[2]
+    loss.backward()
+    for i in range(3):
+        assert abs(out["parts"][i] - parts[i].item()) <= 1e-11 * max(1, abs(parts[i].item()))
+    assert rel_err(out["Qbar"], Qt.grad.numpy() * band_mask(n, k)) < 1e-10
+    assert rel_err(out["ybar"], yt.grad.numpy()) < 1e-11
+
+
+def test_gauss_loss_finite_differences():
+    """Central differences with Richardson extrapolation along random band
+    directions (independent of any autodiff)."""
+    n, k = 40, 3
+    rng = np.random.default_rng(8)
+    L0 = inputs.random_lower_band(n, k, rng)
+    Q = oracle.gbmm(L0, k, 0, L0, k, 0, tB=1, lc=k, uc=0)
+    y = rng.normal(size=n)
+    S = inputs.random_sym_band_dd(n, k, rng)
+
+    def f(Qx, yx):
+        p = oracle.gauss_loss(Qx, k, yx, S)["parts"]
+        return p[0] - p[1] + p[2]
+
+    out = oracle.gauss_loss(Q, k, y, S)
+    for trial in range(3):
+        dQ = rng.normal(size=Q.shape) * band_mask(n, k)
+        dy = rng.normal(size=n)
+
+        def g(h):
+            return (f(Q + h * dQ, y + h * dy) - f(Q - h * dQ, y - h * dy)) / (2 * h)
+
+        h = 1e-3
+        fd = (4 * g(h / 2) - g(h)) / 3
+        an = np.sum(out["Qbar"] * dQ) + out["ybar"] @ dy
+        assert abs(fd - an) <= 1e-7 * max(1, abs(an))
+
+
+def test_alg2_alg3_cross_identity():
+    """d logdet Q / d Q (stored entries) = Sigma_ii on the diagonal and
+    2 Sigma_ij off it; via Algorithm 2 with Lbar = diag(2 / L_ii) it must equal
+    the subset inverse of Algorithm 3."""
+    n, k = 500, 5
+    rng = np.random.default_rng(12)
+    L0 = inputs.random_lower_band(n, k, rng)
+    Q = oracle.gbmm(L0, k, 0, L0, k, 0, tB=1, lc=k, uc=0)
+    L, _ = oracle.chol(Q, k)
+    Lbar = np.zeros_like(L)
+    Lbar[:, 0] = 2.0 / L[:, 0]
+    g = oracle.chol_bwd(L, k, Lbar)
+    S = oracle.subset_inv(L, k)
+    w = np.full((k + 1,), 2.0)
+    w[0] = 1.0
+    assert rel_err(g, S * w * band_mask(n, k)) < 1e-12
+
+
+def test_quadratic_form_gradient_identity():
+    """d (y^T Q^{-1} y) / d Q (stored) = -x_i^2 diagonal, -2 x_i x_j off it,
+    with x = Q^{-1} y; composed from the solve reverse mode and Algorithm 2."""
+    n, k = 300, 3
+    rng = np.random.default_rng(13)
+    L0 = inputs.random_lower_band(n, k, rng)
+    Q = oracle.gbmm(L0, k, 0, L0, k, 0, tB=1, lc=k, uc=0)
+    y = rng.normal(size=n)
+    L, _ = oracle.chol(Q, k)
+    z = oracle.trsv(L, k, y, 0)
+    x = oracle.trsv(L, k, z, 1)
+    ybar, Lbar = oracle.trsv_bwd(L, k, z, 2 * z, 0)
+    g = oracle.chol_bwd(L, k, Lbar)
+    O = oracle.outer_band(x, x, k, 0)
+    w = np.full((k + 1,), 2.0)
+    w[0] = 1.0
+    assert rel_err(g, -O * w * band_mask(n, k)) < 1e-12
+    assert rel_err(ybar, 2 * x) < 1e-12
+
+
+# ------------------------------------------------------ closed-form models
+
+def test_laplacian_closed_form():
+    """1-D Laplacian tridiag(-1, 2, -1): det = n+1 and
+    (T^{-1})_{ij} = i (n+1-j)/(n+1) for i <= j (1-based)."""
+    n = 200
+    Q = np.zeros((n, 2))
+    Q[:, 0] = 2.0
+    Q[: n - 1, 1] = -1.0
+    L, info = oracle.chol(Q, 1)
+    assert info == 0
+    assert abs(oracle.logdet(L, 1) - np.log(n + 1)) < 1e-12
+    S = oracle.subset_inv(L, 1)
+    i = np.arange(1, n + 1, dtype=np.float64)
+    assert rel_err(S[:, 0], i * (n + 1 - i) / (n + 1)) < 1e-12
+    assert rel_err(S[: n - 1, 1], i[:-1] * (n + 1 - i[1:]) / (n + 1)) < 1e-12
+
+
+def test_brownian_motion_closed_form():
+    """Brownian motion at 0 < x_1 < ... < x_n: covariance min(x_i, x_j); the
+    precision is tridiagonal with Q_ii = 1/(x_i - x_{i-1}) + 1/(x_{i+1} - x_i)
+    (x_0 = 0, no second term for i = n) and Q_{i+1,i} = -1/(x_{i+1} - x_i);
+    log det Q = -sum log(x_i - x_{i-1})."""
+    n = 1000
+    rng = np.random.default_rng(4)
+    x = np.cumsum(rng.uniform(0.1, 1.0, size=n))
+    dx = np.diff(np.concatenate([[0.0], x]))
+    Q = np.zeros((n, 2))
+    Q[:, 0] = 1 / dx
+    Q[:-1, 0] += 1 / dx[1:]
+    Q[:-1, 1] = -1 / dx[1:]
+    L, info = oracle.chol(Q, 1)
+    assert info == 0
+    assert abs(oracle.logdet(L, 1) + np.sum(np.log(dx))) < 1e-10
+    S = oracle.subset_inv(L, 1)
+    # kappa(Q) grows like n^2 here; the forward error bound is ~ kappa * u
+    assert rel_err(S[:, 0], x) < 1e-10
+    assert rel_err(S[:-1, 1], x[:-1]) < 1e-10
+
+
+def _ssm_cov_band(m, k):
+    """Band of the covariance of the stacked SSM states from the forward
+    covariance recursion P_t = A_t P_{t-1} A_t^T + Q_t, Cov(s_{t+1}, s_t) =
+    A_{t+1} P_t (Kalman-style propagation, no precision involved)."""
+    A, Qt, d = m.A, m.Qt, m.d
+    T = A.shape[0]
+    P = np.zeros((T, d, d))
+    P[0] = Qt[0]
+    for t in range(1, T):
+        P[t] = A[t] @ P[t - 1] @ A[t].T + Qt[t]
+    C1 = np.einsum("tab,tbc->tac", A[1:], P[:-1])        # Cov(s_{t+1}, s_t)
+    C2 = np.einsum("tab,tbc->tac", A[2:], C1[:-1])       # Cov(s_{t+2}, s_t)
+    B = np.zeros((T, d, k + 1))
+    for a in range(d):
+        for s in range(k + 1):
+            b = a + s
+            if b < d:
+                B[:, a, s] = P[:, b, a]
+            elif b < 2 * d:
+                B[:-1, a, s] = C1[:, b - d, a]
+            else:
+                B[:-2, a, s] = C2[:, b - 2 * d, a]
+    return B.reshape(T * d, k + 1), P
+
+
+@pytest.mark.parametrize("ell", [10.0, 0.1])
+def test_matern32_ssm_closed_forms(ell):
+    n_in = 3000
+    Q, y, m, x = inputs.config1_inputs(seed=1, n_in=n_in, ell=ell)
+    k = 3
+    L, info = oracle.chol(Q, k)
+    assert info == 0
+    ld_closed = np.sum(np.linalg.slogdet(m.Qinv)[1])
+    ld = oracle.logdet(L, k)
+    tol = 1e-9 if ell == 10.0 else 1e-12
+    assert abs(ld - ld_closed) <= tol * abs(ld_closed)
+    Sband, P = _ssm_cov_band(m, k)
+    S = oracle.subset_inv(L, k)
+    err = np.max(np.abs(S - Sband) * band_mask(len(S), k)) / np.max(np.abs(Sband))
+    # ell = 10 on spacing 0.01 is ill-conditioned (kappa ~ 1e12 at this size):
+    # the forward error floor is kappa * u, not u
+    assert err < (1e-5 if ell == 10.0 else 1e-12), err
+    # stationarity: the marginal variance stays sigma^2 = 1
+    assert np.max(np.abs(P[:, 0, 0] - 1)) < 1e-9
+
+
+def test_matern52_grid_closed_forms():
+    T, h, ell = 4000, 0.1, 1.0
+    m = inputs.matern52_grid_ssm(T, h, ell)
+    Q = inputs.ssm_precision_band(m)
+    k = 5
+    L, info = oracle.chol(Q, k)
+    assert info == 0
+    # log|Lambda| = log|P0^{-1}| + sum_t log|Q_t^{-1}| for the blocks Lambda is
+    # assembled from (the inverse blocks carry their own rounding, so the
+    # identity is stated on them rather than on Q_t)
+    ld_closed = np.sum(np.linalg.slogdet(m.Qinv)[1])
+    # This precision is ill-conditioned for its factor: L_ii ~ 0.2 comes out of
+    # Q_ii ~ 5e2 by cancellation, so every FP64 factorisation (this one and
+    # LAPACK's alike) carries ~1e-10 relative error per pivot.  A 40-digit
+    # factorisation of the same band (T = 300) puts both within 1e-11 relative
+    # of the exact log-determinant, on opposite sides; the closed form carries
+    # the rounding of the assembled entries on top.  Bound: 1e-10 relative.
+    assert abs(oracle.logdet(L, k) - ld_closed) <= 1e-10 * abs(ld_closed)
+    ab = sla.cholesky_banded(Q.T.copy(), lower=True)
+    ld_lapack = 2 * np.sum(np.log(ab[0]))
+    assert abs(oracle.logdet(L, k) - ld_lapack) <= 1e-10 * abs(ld_lapack)
+    ld_cov = -np.linalg.slogdet(m.Qt[0])[1] - (T - 1) * np.linalg.slogdet(m.Qt[1])[1]
+    assert abs(oracle.logdet(L, k) - ld_cov) <= 1e-10 * abs(ld_cov)
+    # stationary covariance Cov(s_{t+1}, s_t) = A Pinf and Var(s_t) = Pinf
+    S = oracle.subset_inv(L, k)
+    Pinf = inputs.matern52_stationary(ell)
+    B = np.zeros((T, 3, k + 1))
+    AP = m.A[1] @ Pinf
+    AAP = m.A[1] @ AP
+    for a in range(3):
+        for s in range(k + 1):
+            b = a + s
+            if b < 3:
+                B[:, a, s] = Pinf[b, a]
+            elif b < 6:
+                B[:-1, a, s] = AP[b - 3, a]
+            else:
+                B[:-2, a, s] = AAP[b - 6, a]
+    B = B.reshape(T * 3, k + 1)
+    assert np.max(np.abs(S - B) * band_mask(len(S), k)) < 1e-9 * np.max(np.abs(B))
+
+
+def test_batch_matches_single():
+    ns, ks = [50, 7, 130, 1], [3, 1, 5, 0]
+    Ls, ys = inputs.config2_factors(21, ns, ks)
+    Qs = [oracle.gbmm(L, k, 0, L, k, 0, tB=1, lc=k, uc=0) for L, k in zip(Ls, ks)]
+    rng = np.random.default_rng(2)
+    Ss = [inputs.random_sym_band_dd(n, k, rng) for n, k in zip(ns, ks)]
+    parts, Qbar, ybar, info, th = oracle.gauss_loss_batch(
+        ns, ks, np.concatenate([q.ravel() for q in Qs]), np.concatenate(ys),
+        np.concatenate([s.ravel() for s in Ss]))
+    assert th >= 1 and np.all(info == 0)
+    off, voff = 0, 0
+    for p, (n, k) in enumerate(zip(ns, ks)):
+        o = oracle.gauss_loss(Qs[p], k, ys[p], Ss[p])
+        assert np.allclose(parts[p], o["parts"], rtol=0, atol=0)
+        assert np.array_equal(Qbar[off: off + n * (k + 1)].reshape(n, k + 1), o["Qbar"])
+        assert np.array_equal(ybar[voff: voff + n], o["ybar"])
+        off += n * (k + 1)
+        voff += n
