@@ -1,0 +1,213 @@
+/*
+ * bandops.h -- C ABI of the MI355X (gfx950) banded-matrix operator library.
+ *
+ * Operators of "Banded Matrix Operators for Gaussian Markov Models in the
+ * Automatic Differentiation Era" (Durrande et al., AISTATS 2019):
+ * Cholesky C, triangular solves S, subset inverse I, products P, band-restricted
+ * outer product O (Section 4.1) and their reverse-mode sensitivities (Section
+ * 4.2, Table 1, Algorithms 2 and 4).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Storage (Section 4.3): a banded n x n matrix B with lower width l and upper
+ *    width u is n records of ld >= l+u+1 elements; record j is column j of B on
+ *    its band, B[j-u .. j+l, j], element (i,j) at slot u+i-j.  Lower-triangular
+ *    factors use (l,u) = (k,0); symmetric matrices (Q, Sigma and their
+ *    sensitivities) are stored as their lower band, (k,0).  Slots that fall
+ *    outside the matrix are never read; outputs write them as 0.
+ *  - Precision: BO_F64 stores everything as double.  BO_MIXED stores band
+ *    records and vectors as float and keeps every diagonal in the FP64 side
+ *    array `diag64` (n doubles); slot 0 of a mixed record then holds an FP32
+ *    copy that is ignored on input.  All arithmetic is FP64 in both modes, and
+ *    log-determinants are accumulated in FP64.
+ *  - Memory: every data pointer is a DEVICE pointer owned by the caller.  The
+ *    library never allocates inside a call; `ws` is caller-provided device
+ *    workspace of at least the size reported by the matching *_workspace_size
+ *    query.  Inputs are never modified.  Outputs may not alias inputs.
+ *  - Execution: calls are asynchronous and ordered on `stream`; no call
+ *    synchronises the host.  They contain no allocation, no host sync and no
+ *    memset, so they may be captured into a HIP graph.
+ *  - Errors: the return value reports argument and launch errors only
+ *    (negative bo_status), detected before any work is queued where possible;
+ *    bo_last_error() then gives a thread-local message.  Numerical failure is
+ *    reported on the device in `info`: 0, or r > 0 when the leading minor of
+ *    order r is not positive definite (pivot <= 0 or NaN; LAPACK convention).
+ *    Outputs of such a problem are unspecified from row r-1 on; other problems
+ *    of a batch are unaffected.
+ *  - Gradients are with respect to the stored band entries: an off-diagonal
+ *    stored entry of a symmetric matrix stands for both (i,j) and (j,i).
+ */
+#ifndef BANDOPS_H
+#define BANDOPS_H
+
+#include <hip/hip_runtime_api.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { BO_F64 = 0, BO_MIXED = 1 } bo_prec;
+
+typedef enum {
+  BO_OK = 0,
+  BO_EINVAL = -1,        /* bad argument (null pointer, shape, stride, width) */
+  BO_EDEVICE = -2,       /* HIP launch or runtime error                       */
+  BO_EWORKSPACE = -3,    /* workspace too small                               */
+  BO_EUNSUPPORTED = -4   /* bandwidth or variant without compiled kernels     */
+} bo_status;
+
+/* Largest lower bandwidth k with compiled kernels. */
+#define BO_KMAX 12
+
+typedef struct {
+  void *band;       /* n records of ld elements (double, or float for BO_MIXED) */
+  double *diag64;   /* BO_MIXED: FP64 diagonal (n); must be NULL for BO_F64    */
+  int64_t n;        /* order of the matrix                                     */
+  int32_t l;        /* lower width (sub-diagonals)                             */
+  int32_t u;        /* upper width (0 for lower / symmetric-stored bands)      */
+  int32_t ld;       /* record stride in elements, >= l+u+1                     */
+  int32_t reserved;
+} bo_band;
+
+/* Workspace (bytes) that any single-problem call below needs for an n x n
+ * matrix with k sub-diagonals. */
+size_t bo_workspace_size(int64_t n, int32_t k);
+
+/* ------------------------------------------------------------ forward ops */
+
+/* C (Algorithm 1, Section 4.1): L with L L^T = Q; also log det Q =
+ * 2 sum log L_ii (Eq. (2) and the KL term of Section 3.3), and optionally
+ * z = L^{-1} y (S, Section 4.1) in the same pass.  Q, L: (k,0) bands with the
+ * same ld.  y, z: n-vectors or both NULL.  logdet: one device double (may be
+ * NULL).  info: one device int32 (required). */
+bo_status bo_chol(bo_prec prec, const bo_band *Q, bo_band *L, const void *y, void *z,
+                  double *logdet, int32_t *info, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* S (Section 4.1): x = L^{-1} b (trans = 0) or x = L^{-T} b (trans = 1, the
+ * upper-banded variant the gradients need, Section 4.1 "transposes"). */
+bo_status bo_trsv(bo_prec prec, const bo_band *L, int trans, const void *b, void *x, void *ws,
+                  size_t ws_bytes, hipStream_t stream);
+
+/* I (Algorithm 3, Takahashi): Sigma = lower band (width k) of (L L^T)^{-1}. */
+bo_status bo_subset_inv(bo_prec prec, const bo_band *L, bo_band *Sigma, void *ws, size_t ws_bytes,
+                        hipStream_t stream);
+
+/* P (Section 4.1, "Products"): C = band of op(A) op(B) on C's (l,u), op = ^T
+ * when the flag is set.  A, B, C are general bands. */
+bo_status bo_gbmm(bo_prec prec, const bo_band *A, int tA, const bo_band *B, int tB, bo_band *C,
+                  hipStream_t stream);
+
+/* P: y = op(A) x. */
+bo_status bo_gbmv(bo_prec prec, const bo_band *A, int tA, const void *x, void *y,
+                  hipStream_t stream);
+
+/* O (Section 4.1, outer product restricted to a band): O = alpha m v^T on O's
+ * (l,u) band, or O += alpha m v^T when accumulate is set. */
+bo_status bo_outer_band(bo_prec prec, const void *m, const void *v, double alpha, int accumulate,
+                        bo_band *O, hipStream_t stream);
+
+/* ---------------------------------------------------------- reverse mode */
+
+/* Reverse mode of C (Algorithm 2): Qbar = d c/d Q (stored lower entries) from
+ * L and Lbar = d c/d L. */
+bo_status bo_chol_bwd(bo_prec prec, const bo_band *L, const bo_band *Lbar, bo_band *Qbar,
+                      void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Reverse mode of I (Algorithm 4): Lbar (=, or += when accumulate) from L,
+ * Sigma = I(L) and Sigmabar = d c/d Sigma (stored lower entries; the strict
+ * upper triangle of Algorithm 4's local copy of the sensitivity is zero). */
+bo_status bo_subset_inv_bwd(bo_prec prec, const bo_band *L, const bo_band *Sigma,
+                            const bo_band *Sigmabar, bo_band *Lbar, int accumulate, void *ws,
+                            size_t ws_bytes, hipStream_t stream);
+
+/* Reverse mode of S (Table 1, solve matrix-vector).  x is the forward output
+ * (L^{-1} b, or L^{-T} b for trans = 1) and xbar its sensitivity.  Writes
+ * bbar = L^{-T} xbar (L^{-1} xbar for trans = 1) and the band of
+ * Lbar = -bbar x^T (trans = 0) or -x bbar^T (trans = 1), assigned or added. */
+bo_status bo_trsv_bwd(bo_prec prec, const bo_band *L, int trans, const void *x, const void *xbar,
+                      void *bbar, bo_band *Lbar, int accumulate, void *ws, size_t ws_bytes,
+                      hipStream_t stream);
+
+/* Reverse mode of log det: Lbar_ii (=, +=) 2 gbar / L_ii; gbar is one device
+ * double. */
+bo_status bo_logdet_bwd(bo_prec prec, const bo_band *L, const double *gbar, bo_band *Lbar,
+                        int accumulate, hipStream_t stream);
+
+/* ------------------------------------------------ batched, uneven problems */
+
+/* Problem p of a batch: n rows, k sub-diagonals; its band records (stride k+1)
+ * start at element boff of every band array of the call, its vector entries at
+ * element voff of every vector (and of every diag64 array). */
+typedef struct {
+  int64_t n;
+  int32_t k;
+  int32_t reserved;
+  int64_t boff;
+  int64_t voff;
+} bo_problem;
+
+typedef struct bo_plan bo_plan;
+
+/* Arrays of one batched call (device pointers).  diag arrays are used in
+ * BO_MIXED only.  Outputs that a call does not produce may be NULL. */
+typedef struct {
+  const void *Q;   const double *Qd;     /* precision, lower band              */
+  const void *y;                          /* right-hand sides                  */
+  const void *S;   const double *Sd;     /* S of tr(Q^{-1} S) (gauss_loss)     */
+  void *L;         double *Ld;           /* Cholesky factor                    */
+  void *z;                                /* L^{-1} y                          */
+  void *x;                                /* forward: Q^{-1} y; loss: ybar     */
+  void *Sig;       double *Sigd;         /* band of Q^{-1}                     */
+  void *Lbar;      double *Lbard;        /* loss: subset-inverse part of Lbar  */
+  void *Qbar;      double *Qbard;        /* loss: d loss / d Q (stored)        */
+  double *logdet;                         /* per problem                       */
+  double *parts;                          /* per problem: logdet, yQ^-1y, trace */
+  int32_t *info;                          /* per problem                       */
+} bo_batch_io;
+
+/* Build a plan (host object): chunking of every problem into about
+ * target_chunks lanes (0: library default), bandwidth ranges, workspace
+ * layout.  Problems may have any n >= 0 and k in [0, BO_KMAX]. */
+bo_status bo_plan_create(const bo_problem *probs, int32_t nprob, int64_t target_chunks,
+                         bo_plan **out);
+bo_status bo_plan_workspace_size(const bo_plan *plan, size_t *bytes);
+/* Copy the plan's device tables into ws (stream-ordered; do this once, before
+ * capture, and again whenever ws is a new buffer). */
+bo_status bo_plan_upload(const bo_plan *plan, void *ws, hipStream_t stream);
+/* Forward list (Section 3 operations): L = C(Q), log det Q, z = L^{-1} y,
+ * x = L^{-T} z = Q^{-1} y, Sig = I(L).  Any of z, x, Sig may be NULL. */
+bo_status bo_plan_forward(const bo_plan *plan, bo_prec prec, const bo_batch_io *io, void *ws,
+                          hipStream_t stream);
+/* loss = log det Q - y^T Q^{-1} y + tr(Q^{-1} S) per problem and its reverse
+ * mode: forward (C, log det, S, I), then Algorithm 4 with Sigmabar = S, the
+ * solve sensitivity of Table 1 with zbar = -2z, the log-determinant
+ * sensitivity and Algorithm 2.  Writes L, z, Sig, Lbar, x (= ybar), Qbar,
+ * parts and info. */
+bo_status bo_plan_gauss_loss(const bo_plan *plan, bo_prec prec, const bo_batch_io *io, void *ws,
+                             hipStream_t stream);
+/* Plan statistics: out[0] problems, out[1] chunks, out[2] groups, out[3] rows,
+ * out[4] largest k. */
+bo_status bo_plan_stats(const bo_plan *plan, int64_t out[5]);
+bo_status bo_plan_destroy(bo_plan *plan);
+
+/* ------------------------------------------------------------- profiling */
+/* Kernel timing on the launch stream (a tracing aid).  While enabled, every
+ * launch issued by this process is bracketed by two HIP events; do not enable
+ * it around graph capture.  bo_profile_read waits for the recorded events and
+ * returns, per step kind (slot), the summed duration in ms and the number of
+ * launches since the last read, then resets.  Slot names come from
+ * bo_profile_slot_name; bo_profile_slots gives their number. */
+bo_status bo_profile_enable(int on);
+bo_status bo_profile_read(double *ms, int64_t *launches, int nslots);
+int bo_profile_slots(void);
+const char *bo_profile_slot_name(int slot);
+
+const char *bo_status_string(int status);
+const char *bo_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BANDOPS_H */

@@ -1,0 +1,645 @@
+// bandops_lib.hip -- host side of the C ABI (include/bandops.h): argument
+// checks, schedules, launch sequences; plus the bandwidth-independent kernels
+// (per-problem finalisation, band products, band-restricted outer products,
+// log-determinant sensitivity).
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstdlib>
+#include <string>
+
+#include "../../include/bandops.h"
+#include "bandops_driver.hpp"
+
+using bo::Args;
+using bo::Sched;
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_err;
+
+static bo_status fail(bo_status st, const std::string &msg) {
+  g_err = msg;
+  return st;
+}
+
+extern "C" const char *bo_last_error(void) { return g_err.c_str(); }
+
+extern "C" const char *bo_status_string(int s) {
+  switch (s) {
+    case BO_OK: return "ok";
+    case BO_EINVAL: return "invalid argument";
+    case BO_EDEVICE: return "device error";
+    case BO_EWORKSPACE: return "workspace too small";
+    case BO_EUNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+  }
+}
+
+// ----------------------------------------------------- per-bandwidth steps
+typedef int (*StepFn)(int, int, const Args *, int64_t, hipStream_t);
+extern "C" {
+int bo_step_k0(int, int, const Args *, int64_t, hipStream_t);
+int bo_step_k1(int, int, const Args *, int64_t, hipStream_t);
+int bo_step_k2(int, int, const Args *, int64_t, hipStream_t);
+int bo_step_k3(int, int, const Args *, int64_t, hipStream_t);
+int bo_step_k4(int, int, const Args *, int64_t, hipStream_t);
+int bo_step_k5(int, int, const Args *, int64_t, hipStream_t);
+int bo_step_k6(int, int, const Args *, int64_t, hipStream_t);
+int bo_step_k7(int, int, const Args *, int64_t, hipStream_t);
+int bo_step_k8(int, int, const Args *, int64_t, hipStream_t);
+int bo_step_k9(int, int, const Args *, int64_t, hipStream_t);
+int bo_step_k10(int, int, const Args *, int64_t, hipStream_t);
+int bo_step_k11(int, int, const Args *, int64_t, hipStream_t);
+int bo_step_k12(int, int, const Args *, int64_t, hipStream_t);
+}
+static const StepFn g_steps[bo::KMAX_SUPPORTED + 1] = {
+    bo_step_k0, bo_step_k1, bo_step_k2, bo_step_k3, bo_step_k4,  bo_step_k5, bo_step_k6,
+    bo_step_k7, bo_step_k8, bo_step_k9, bo_step_k10, bo_step_k11, bo_step_k12};
+
+namespace {
+
+constexpr int kBlock = 64;
+
+template <class Item>
+__global__ void __launch_bounds__(kBlock) k_item(const Args a, int64_t count) {
+  int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < count) Item::run(a, i);
+}
+
+template <class Item> int launch_items(const Args &a, int64_t count, hipStream_t s) {
+  if (count <= 0) return 0;
+  int64_t grid = (count + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_item<Item>, dim3((unsigned)grid), dim3(kBlock), 0, s, a, count);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+// ------------------------------------------------------------ profiling
+// When enabled, every launch is bracketed by a pair of events on its stream;
+// bo_profile_read() waits for them and sums the durations per step kind.
+constexpr int kProfSlots = bo::ST_COUNT + 2;   // + clear, finalize
+struct ProfRec {
+  int slot;
+  hipEvent_t a, b;
+};
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof_pending;
+std::vector<hipEvent_t> g_prof_pool;
+double g_prof_ms[kProfSlots];
+int64_t g_prof_n[kProfSlots];
+
+hipEvent_t prof_event() {
+  if (!g_prof_pool.empty()) {
+    hipEvent_t e = g_prof_pool.back();
+    g_prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+template <class F> int profiled(int slot, hipStream_t s, F &&launch) {
+  if (!g_prof_on) return launch();
+  ProfRec r{slot, prof_event(), prof_event()};
+  (void)hipEventRecord(r.a, s);
+  int e = launch();
+  (void)hipEventRecord(r.b, s);
+  g_prof_pending.push_back(r);
+  return e;
+}
+
+struct GpuBE {
+  hipStream_t s;
+  int step(int st, int K, int prec, const Args &a, int64_t count) {
+    if (K < 0 || K > bo::KMAX_SUPPORTED) return -4;
+    if (count <= 0) return 0;
+    return profiled(st, s, [&] { return g_steps[K](st, prec, &a, count, s); });
+  }
+  int clear(const Args &a, int64_t count) {
+    if (count <= 0) return 0;
+    return profiled(bo::ST_COUNT, s, [&] { return launch_items<bo::ClearPart>(a, count, s); });
+  }
+  int finalize(const Args &a, int64_t count) {
+    if (count <= 0) return 0;
+    return profiled(bo::ST_COUNT + 1, s, [&] { return launch_items<bo::Finalize>(a, count, s); });
+  }
+};
+
+int64_t default_target_chunks() {
+  static int64_t v = [] {
+    const char *e = std::getenv("BANDOPS_TARGET_CHUNKS");
+    long long t = e ? std::atoll(e) : 0;
+    return (int64_t)(t > 0 ? t : 65536);
+  }();
+  return v;
+}
+int64_t default_min_len() {
+  static int64_t v = [] {
+    const char *e = std::getenv("BANDOPS_MIN_CHUNK");
+    long long t = e ? std::atoll(e) : 0;
+    return (int64_t)(t > 0 ? t : 32);
+  }();
+  return v;
+}
+constexpr int32_t kGroup = 64;
+
+bo_status dev_status(int e, const char *what) {
+  if (e == 0) return BO_OK;
+  if (e == -4) return fail(BO_EUNSUPPORTED, std::string(what) + ": bandwidth without compiled kernels");
+  return fail(BO_EDEVICE, std::string(what) + ": kernel launch failed: " +
+                              hipGetErrorString(hipGetLastError()));
+}
+
+// ---------------------------------------------------------- argument checks
+bo_status check_band(const bo_band *b, bo_prec prec, const char *name, bool need_lower) {
+  if (!b) return fail(BO_EINVAL, std::string(name) + ": null descriptor");
+  if (b->n < 0 || b->l < 0 || b->u < 0) return fail(BO_EINVAL, std::string(name) + ": negative size");
+  if (b->ld < b->l + b->u + 1) return fail(BO_EINVAL, std::string(name) + ": ld < l+u+1");
+  if (need_lower && b->u != 0) return fail(BO_EINVAL, std::string(name) + ": must be a lower band (u = 0)");
+  if (b->n > 0 && !b->band) return fail(BO_EINVAL, std::string(name) + ": null band pointer");
+  if (prec == BO_MIXED && b->n > 0 && !b->diag64)
+    return fail(BO_EINVAL, std::string(name) + ": BO_MIXED needs the FP64 diagonal array");
+  if (prec == BO_F64 && b->diag64) return fail(BO_EINVAL, std::string(name) + ": diag64 must be NULL for BO_F64");
+  if (prec != BO_F64 && prec != BO_MIXED) return fail(BO_EINVAL, "unknown precision");
+  return BO_OK;
+}
+
+bo_status check_same(const bo_band *a, const bo_band *b, const char *what) {
+  if (a->n != b->n) return fail(BO_EINVAL, std::string(what) + ": matrix orders differ");
+  if (a->l != b->l) return fail(BO_EINVAL, std::string(what) + ": bandwidths differ");
+  if (a->ld != b->ld) return fail(BO_EINVAL, std::string(what) + ": record strides differ");
+  return BO_OK;
+}
+
+// Schedule of one problem (n, k, ld) and the kernel arguments bound to ws.
+bo_status single_sched(int64_t n, int32_t k, int32_t ld, void *ws, size_t ws_bytes, Sched &s,
+                       Args &A) {
+  if (k > bo::KMAX_SUPPORTED)
+    return fail(BO_EUNSUPPORTED, "bandwidth k = " + std::to_string(k) + " exceeds BO_KMAX");
+  bo::ProbIn pi{n, k, ld, 0, 0};
+  if (!bo::build_sched(&pi, 1, default_target_chunks(), default_min_len(), kGroup, s))
+    return fail(BO_EINVAL, "bad problem shape");
+  if (!ws || ws_bytes < s.bytes)
+    return fail(BO_EWORKSPACE, "workspace needs " + std::to_string(s.bytes) + " bytes");
+  A = Args{};
+  bo::bind_sched(s, ws, true, A);
+  return BO_OK;
+}
+
+// ------------------------------------------------- bandwidth-free kernels
+template <typename T> struct GB {   // general band view
+  T *p;
+  double *diag;
+  int64_t ld;
+  int32_t l, u;
+  __device__ __forceinline__ double get(int64_t i, int64_t j) const {
+    int64_t d = i - j;
+    if (d > l || d < -u) return 0.0;
+    if (d == 0 && diag) return diag[j];
+    return (double)p[j * ld + u + d];
+  }
+};
+
+template <typename T> GB<T> gb(const bo_band *b) {
+  return GB<T>{(T *)b->band, b->diag64, (int64_t)b->ld, b->l, b->u};
+}
+
+// C(i,j) = sum_m op(A)(i,m) op(B)(m,j) over the band overlap, one lane per
+// stored entry of C.
+template <typename T>
+__global__ void k_gbmm(int64_t n, GB<T> A, int tA, GB<T> B, int tB, GB<T> C) {
+  int64_t w = C.l + C.u + 1;
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * w) return;
+  int64_t j = t / w, s = t - j * w;
+  int64_t i = j - C.u + s;
+  double acc = 0.0;
+  if (i >= 0 && i < n) {
+    int lA = tA ? A.u : A.l, uA = tA ? A.l : A.u;
+    int lB = tB ? B.u : B.l, uB = tB ? B.l : B.u;
+    int64_t m0 = i - lA, m1 = i + uA;
+    if (j - uB > m0) m0 = j - uB;
+    if (j + lB < m1) m1 = j + lB;
+    if (m0 < 0) m0 = 0;
+    if (m1 > n - 1) m1 = n - 1;
+    for (int64_t m = m0; m <= m1; ++m) {
+      double a = tA ? A.get(m, i) : A.get(i, m);
+      double b = tB ? B.get(j, m) : B.get(m, j);
+      acc += a * b;
+    }
+  }
+  C.p[j * C.ld + s] = (T)acc;
+  if (s == C.u && C.diag) C.diag[j] = acc;
+}
+
+template <typename T>
+__global__ void k_gbmv(int64_t n, GB<T> A, int tA, const T *x, T *y) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int64_t m0 = tA ? i - A.u : i - A.l, m1 = tA ? i + A.l : i + A.u;
+  if (m0 < 0) m0 = 0;
+  if (m1 > n - 1) m1 = n - 1;
+  double acc = 0.0;
+  for (int64_t m = m0; m <= m1; ++m) acc += (tA ? A.get(m, i) : A.get(i, m)) * (double)x[m];
+  y[i] = (T)acc;
+}
+
+template <typename T>
+__global__ void k_outer(int64_t n, const T *m, const T *v, double alpha, int acc, GB<T> O) {
+  int64_t w = O.l + O.u + 1;
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * w) return;
+  int64_t j = t / w, s = t - j * w;
+  int64_t i = j - O.u + s;
+  double val = 0.0;
+  if (i >= 0 && i < n) {
+    val = alpha * (double)m[i] * (double)v[j];
+    if (acc) val += O.get(i, j);
+  }
+  O.p[j * O.ld + s] = (T)val;
+  if (s == O.u && O.diag) O.diag[j] = val;
+}
+
+template <typename T>
+__global__ void k_logdet_bwd(int64_t n, GB<T> L, const double *g, int acc, GB<T> Lb) {
+  int64_t w = Lb.l + 1;
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * w) return;
+  int64_t j = t / w, s = t - j * w;
+  double val = (acc && j + s < n) ? Lb.get(j + s, j) : 0.0;
+  if (s == 0) val += 2.0 * g[0] / L.get(j, j);
+  Lb.p[j * Lb.ld + s] = (T)val;
+  if (s == 0 && Lb.diag) Lb.diag[j] = val;
+}
+
+unsigned blocks_for(int64_t count, int block) { return (unsigned)((count + block - 1) / block); }
+
+}  // namespace
+
+// ======================================================== C ABI: profiling
+static const char *const kStepNames[kProfSlots] = {
+    "f1_summary", "f1_group_compose", "f1_group_sweep", "f1_chunk_sweep", "f1_replay",
+    "chunk_product", "fs_summary", "fs_replay", "f2_summary", "f2_replay", "b1_summary",
+    "b1_replay", "b2_summary", "b2_replay", "asc_group_compose", "asc_group_sweep",
+    "asc_chunk_sweep", "desc_group_compose", "desc_group_sweep", "desc_chunk_sweep",
+    "clear_partials", "finalize"};
+
+extern "C" int bo_profile_slots(void) { return kProfSlots; }
+
+extern "C" const char *bo_profile_slot_name(int slot) {
+  return (slot >= 0 && slot < kProfSlots) ? kStepNames[slot] : "";
+}
+
+extern "C" bo_status bo_profile_enable(int on) {
+  g_prof_on = on != 0;
+  return BO_OK;
+}
+
+extern "C" bo_status bo_profile_read(double *ms, int64_t *launches, int nslots) {
+  for (const ProfRec &r : g_prof_pending) {
+    if (hipEventSynchronize(r.b) != hipSuccess) return fail(BO_EDEVICE, "bo_profile_read: event wait failed");
+    float t = 0.f;
+    (void)hipEventElapsedTime(&t, r.a, r.b);
+    g_prof_ms[r.slot] += t;
+    g_prof_n[r.slot] += 1;
+    g_prof_pool.push_back(r.a);
+    g_prof_pool.push_back(r.b);
+  }
+  g_prof_pending.clear();
+  for (int i = 0; i < nslots && i < kProfSlots; ++i) {
+    if (ms) ms[i] = g_prof_ms[i];
+    if (launches) launches[i] = g_prof_n[i];
+    g_prof_ms[i] = 0.0;
+    g_prof_n[i] = 0;
+  }
+  return BO_OK;
+}
+
+// ========================================================== C ABI: queries
+extern "C" size_t bo_workspace_size(int64_t n, int32_t k) {
+  if (n < 0 || k < 0 || k > bo::KMAX_SUPPORTED) return 0;
+  bo::ProbIn pi{n, k, k + 1, 0, 0};
+  Sched s;
+  if (!bo::build_sched(&pi, 1, default_target_chunks(), default_min_len(), kGroup, s)) return 0;
+  return s.bytes;
+}
+
+// ====================================================== C ABI: forward ops
+extern "C" bo_status bo_chol(bo_prec prec, const bo_band *Q, bo_band *L, const void *y, void *z,
+                             double *logdet, int32_t *info, void *ws, size_t ws_bytes,
+                             hipStream_t stream) {
+  if (bo_status e = check_band(Q, prec, "Q", true)) return e;
+  if (bo_status e = check_band(L, prec, "L", true)) return e;
+  if (bo_status e = check_same(Q, L, "bo_chol")) return e;
+  if ((y == nullptr) != (z == nullptr)) return fail(BO_EINVAL, "bo_chol: y and z go together");
+  if (!info) return fail(BO_EINVAL, "bo_chol: info is required");
+  Sched s;
+  Args A;
+  if (bo_status e = single_sched(Q->n, Q->l, Q->ld, ws, ws_bytes, s, A)) return e;
+  A.Q = Q->band;
+  A.Qd = Q->diag64;
+  A.L = L->band;
+  A.Ld = L->diag64;
+  A.y = y;
+  A.z = z;
+  A.logdet = logdet;
+  A.info = info;
+  GpuBE be{stream};
+  return dev_status(bo::pipe_forward(be, s, A, (int)prec), "bo_chol");
+}
+
+extern "C" bo_status bo_trsv(bo_prec prec, const bo_band *L, int trans, const void *b, void *x,
+                             void *ws, size_t ws_bytes, hipStream_t stream) {
+  if (bo_status e = check_band(L, prec, "L", true)) return e;
+  if (L->n > 0 && (!b || !x)) return fail(BO_EINVAL, "bo_trsv: null vector");
+  Sched s;
+  Args A;
+  if (bo_status e = single_sched(L->n, L->l, L->ld, ws, ws_bytes, s, A)) return e;
+  A.L = L->band;
+  A.Ld = L->diag64;
+  A.bx = b;
+  A.x = x;
+  A.xscale = 1.0;
+  GpuBE be{stream};
+  return dev_status(bo::pipe_linear(be, s, A, (int)prec, trans ? bo::PASS_F2 : bo::PASS_FS), "bo_trsv");
+}
+
+extern "C" bo_status bo_subset_inv(bo_prec prec, const bo_band *L, bo_band *Sig, void *ws,
+                                   size_t ws_bytes, hipStream_t stream) {
+  if (bo_status e = check_band(L, prec, "L", true)) return e;
+  if (bo_status e = check_band(Sig, prec, "Sigma", true)) return e;
+  if (bo_status e = check_same(L, Sig, "bo_subset_inv")) return e;
+  Sched s;
+  Args A;
+  if (bo_status e = single_sched(L->n, L->l, L->ld, ws, ws_bytes, s, A)) return e;
+  A.L = L->band;
+  A.Ld = L->diag64;
+  A.S = Sig->band;
+  A.Sd = Sig->diag64;
+  GpuBE be{stream};
+  return dev_status(bo::pipe_linear(be, s, A, (int)prec, bo::PASS_F2), "bo_subset_inv");
+}
+
+extern "C" bo_status bo_gbmm(bo_prec prec, const bo_band *A, int tA, const bo_band *B, int tB,
+                             bo_band *C, hipStream_t stream) {
+  if (bo_status e = check_band(A, prec, "A", false)) return e;
+  if (bo_status e = check_band(B, prec, "B", false)) return e;
+  if (bo_status e = check_band(C, prec, "C", false)) return e;
+  if (A->n != B->n || A->n != C->n) return fail(BO_EINVAL, "bo_gbmm: matrix orders differ");
+  int64_t n = C->n, w = (int64_t)C->l + C->u + 1;
+  if (n == 0) return BO_OK;
+  if (prec == BO_F64)
+    hipLaunchKernelGGL(k_gbmm<double>, dim3(blocks_for(n * w, 256)), dim3(256), 0, stream, n,
+                       gb<double>(A), tA, gb<double>(B), tB, gb<double>(C));
+  else
+    hipLaunchKernelGGL(k_gbmm<float>, dim3(blocks_for(n * w, 256)), dim3(256), 0, stream, n,
+                       gb<float>(A), tA, gb<float>(B), tB, gb<float>(C));
+  return dev_status(hipGetLastError() == hipSuccess ? 0 : -2, "bo_gbmm");
+}
+
+extern "C" bo_status bo_gbmv(bo_prec prec, const bo_band *A, int tA, const void *x, void *y,
+                             hipStream_t stream) {
+  if (bo_status e = check_band(A, prec, "A", false)) return e;
+  int64_t n = A->n;
+  if (n == 0) return BO_OK;
+  if (!x || !y) return fail(BO_EINVAL, "bo_gbmv: null vector");
+  if (prec == BO_F64)
+    hipLaunchKernelGGL(k_gbmv<double>, dim3(blocks_for(n, 256)), dim3(256), 0, stream, n,
+                       gb<double>(A), tA, (const double *)x, (double *)y);
+  else
+    hipLaunchKernelGGL(k_gbmv<float>, dim3(blocks_for(n, 256)), dim3(256), 0, stream, n,
+                       gb<float>(A), tA, (const float *)x, (float *)y);
+  return dev_status(hipGetLastError() == hipSuccess ? 0 : -2, "bo_gbmv");
+}
+
+extern "C" bo_status bo_outer_band(bo_prec prec, const void *m, const void *v, double alpha,
+                                   int accumulate, bo_band *O, hipStream_t stream) {
+  if (bo_status e = check_band(O, prec, "O", false)) return e;
+  int64_t n = O->n, w = (int64_t)O->l + O->u + 1;
+  if (n == 0) return BO_OK;
+  if (!m || !v) return fail(BO_EINVAL, "bo_outer_band: null vector");
+  if (prec == BO_F64)
+    hipLaunchKernelGGL(k_outer<double>, dim3(blocks_for(n * w, 256)), dim3(256), 0, stream, n,
+                       (const double *)m, (const double *)v, alpha, accumulate, gb<double>(O));
+  else
+    hipLaunchKernelGGL(k_outer<float>, dim3(blocks_for(n * w, 256)), dim3(256), 0, stream, n,
+                       (const float *)m, (const float *)v, alpha, accumulate, gb<float>(O));
+  return dev_status(hipGetLastError() == hipSuccess ? 0 : -2, "bo_outer_band");
+}
+
+// ===================================================== C ABI: reverse mode
+extern "C" bo_status bo_chol_bwd(bo_prec prec, const bo_band *L, const bo_band *Lbar,
+                                 bo_band *Qbar, void *ws, size_t ws_bytes, hipStream_t stream) {
+  if (bo_status e = check_band(L, prec, "L", true)) return e;
+  if (bo_status e = check_band(Lbar, prec, "Lbar", true)) return e;
+  if (bo_status e = check_band(Qbar, prec, "Qbar", true)) return e;
+  if (bo_status e = check_same(L, Lbar, "bo_chol_bwd")) return e;
+  if (bo_status e = check_same(L, Qbar, "bo_chol_bwd")) return e;
+  Sched s;
+  Args A;
+  if (bo_status e = single_sched(L->n, L->l, L->ld, ws, ws_bytes, s, A)) return e;
+  A.L = L->band;
+  A.Ld = L->diag64;
+  A.Lb = Lbar->band;
+  A.Lbd = Lbar->diag64;
+  A.Qb = Qbar->band;
+  A.Qbd = Qbar->diag64;
+  A.gl = 0.0;
+  GpuBE be{stream};
+  return dev_status(bo::pipe_linear(be, s, A, (int)prec, bo::PASS_B2), "bo_chol_bwd");
+}
+
+extern "C" bo_status bo_subset_inv_bwd(bo_prec prec, const bo_band *L, const bo_band *Sig,
+                                       const bo_band *Sigbar, bo_band *Lbar, int accumulate,
+                                       void *ws, size_t ws_bytes, hipStream_t stream) {
+  if (bo_status e = check_band(L, prec, "L", true)) return e;
+  if (bo_status e = check_band(Sig, prec, "Sigma", true)) return e;
+  if (bo_status e = check_band(Sigbar, prec, "Sigmabar", true)) return e;
+  if (bo_status e = check_band(Lbar, prec, "Lbar", true)) return e;
+  if (bo_status e = check_same(L, Sig, "bo_subset_inv_bwd")) return e;
+  if (bo_status e = check_same(L, Sigbar, "bo_subset_inv_bwd")) return e;
+  if (bo_status e = check_same(L, Lbar, "bo_subset_inv_bwd")) return e;
+  Sched s;
+  Args A;
+  if (bo_status e = single_sched(L->n, L->l, L->ld, ws, ws_bytes, s, A)) return e;
+  A.L = L->band;
+  A.Ld = L->diag64;
+  A.S = Sig->band;
+  A.Sd = Sig->diag64;
+  A.Sb = Sigbar->band;
+  A.Sbd = Sigbar->diag64;
+  A.Lb = Lbar->band;
+  A.Lbd = Lbar->diag64;
+  A.sb_is_S = 0;
+  A.accumulate = accumulate ? 1 : 0;
+  GpuBE be{stream};
+  return dev_status(bo::pipe_linear(be, s, A, (int)prec, bo::PASS_B1), "bo_subset_inv_bwd");
+}
+
+extern "C" bo_status bo_trsv_bwd(bo_prec prec, const bo_band *L, int trans, const void *x,
+                                 const void *xbar, void *bbar, bo_band *Lbar, int accumulate,
+                                 void *ws, size_t ws_bytes, hipStream_t stream) {
+  if (bo_status e = check_band(L, prec, "L", true)) return e;
+  if (Lbar) {
+    if (bo_status e = check_band(Lbar, prec, "Lbar", true)) return e;
+    if (bo_status e = check_same(L, Lbar, "bo_trsv_bwd")) return e;
+  }
+  if (L->n > 0 && (!x || !xbar || !bbar)) return fail(BO_EINVAL, "bo_trsv_bwd: null vector");
+  Sched s;
+  Args A;
+  if (bo_status e = single_sched(L->n, L->l, L->ld, ws, ws_bytes, s, A)) return e;
+  A.L = L->band;
+  A.Ld = L->diag64;
+  A.bx = xbar;
+  A.x = bbar;
+  A.xscale = 1.0;
+  GpuBE be{stream};
+  // bbar = L^{-T} xbar (trans = 0) or L^{-1} xbar (trans = 1)
+  if (bo_status e = dev_status(bo::pipe_linear(be, s, A, (int)prec, trans ? bo::PASS_FS : bo::PASS_F2),
+                               "bo_trsv_bwd"))
+    return e;
+  if (!Lbar) return BO_OK;
+  // Lbar = -bbar x^T (trans = 0) or -x bbar^T (trans = 1) on the lower band
+  return bo_outer_band(prec, trans ? x : bbar, trans ? bbar : x, -1.0, accumulate, Lbar, stream);
+}
+
+extern "C" bo_status bo_logdet_bwd(bo_prec prec, const bo_band *L, const double *gbar,
+                                   bo_band *Lbar, int accumulate, hipStream_t stream) {
+  if (bo_status e = check_band(L, prec, "L", true)) return e;
+  if (bo_status e = check_band(Lbar, prec, "Lbar", true)) return e;
+  if (bo_status e = check_same(L, Lbar, "bo_logdet_bwd")) return e;
+  if (!gbar) return fail(BO_EINVAL, "bo_logdet_bwd: null gbar");
+  int64_t n = L->n, w = (int64_t)L->l + 1;
+  if (n == 0) return BO_OK;
+  if (prec == BO_F64)
+    hipLaunchKernelGGL(k_logdet_bwd<double>, dim3(blocks_for(n * w, 256)), dim3(256), 0, stream, n,
+                       gb<double>(L), gbar, accumulate, gb<double>(Lbar));
+  else
+    hipLaunchKernelGGL(k_logdet_bwd<float>, dim3(blocks_for(n * w, 256)), dim3(256), 0, stream, n,
+                       gb<float>(L), gbar, accumulate, gb<float>(Lbar));
+  return dev_status(hipGetLastError() == hipSuccess ? 0 : -2, "bo_logdet_bwd");
+}
+
+// ============================================================ C ABI: plans
+struct bo_plan {
+  Sched s;
+  void *pinned = nullptr;   // host copy of the device tables (pinned)
+};
+
+extern "C" bo_status bo_plan_create(const bo_problem *probs, int32_t nprob, int64_t target_chunks,
+                                    bo_plan **out) {
+  if (!out) return fail(BO_EINVAL, "bo_plan_create: null output");
+  *out = nullptr;
+  if (nprob <= 0 || !probs) return fail(BO_EINVAL, "bo_plan_create: no problems");
+  std::vector<bo::ProbIn> in(nprob);
+  for (int i = 0; i < nprob; ++i) {
+    const bo_problem &p = probs[i];
+    if (p.n < 0 || p.k < 0 || p.boff < 0 || p.voff < 0)
+      return fail(BO_EINVAL, "bo_plan_create: problem " + std::to_string(i) + " has a negative field");
+    if (p.k > bo::KMAX_SUPPORTED)
+      return fail(BO_EUNSUPPORTED, "bo_plan_create: problem " + std::to_string(i) + " has k > BO_KMAX");
+    in[i] = bo::ProbIn{p.n, p.k, p.k + 1, p.boff, p.voff};
+  }
+  bo_plan *pl = new bo_plan();
+  if (!bo::build_sched(in.data(), nprob, target_chunks > 0 ? target_chunks : default_target_chunks(),
+                       default_min_len(), kGroup, pl->s)) {
+    delete pl;
+    return fail(BO_EINVAL, "bo_plan_create: bad problem table");
+  }
+  size_t tb = pl->s.table_blob.size();
+  if (hipHostMalloc(&pl->pinned, tb ? tb : 1, hipHostMallocDefault) != hipSuccess) {
+    delete pl;
+    return fail(BO_EDEVICE, "bo_plan_create: pinned host allocation failed");
+  }
+  if (tb) std::memcpy(pl->pinned, pl->s.table_blob.data(), tb);
+  *out = pl;
+  return BO_OK;
+}
+
+extern "C" bo_status bo_plan_workspace_size(const bo_plan *plan, size_t *bytes) {
+  if (!plan || !bytes) return fail(BO_EINVAL, "bo_plan_workspace_size: null argument");
+  *bytes = plan->s.bytes;
+  return BO_OK;
+}
+
+extern "C" bo_status bo_plan_upload(const bo_plan *plan, void *ws, hipStream_t stream) {
+  if (!plan || !ws) return fail(BO_EINVAL, "bo_plan_upload: null argument");
+  size_t tb = plan->s.table_blob.size();
+  if (!tb) return BO_OK;
+  if (hipMemcpyAsync((char *)ws + plan->s.off_tables, plan->pinned, tb, hipMemcpyHostToDevice,
+                     stream) != hipSuccess)
+    return fail(BO_EDEVICE, "bo_plan_upload: copy failed");
+  return BO_OK;
+}
+
+static bo_status plan_args(const bo_plan *plan, bo_prec prec, const bo_batch_io *io, void *ws,
+                           Args &A) {
+  if (!plan || !io || !ws) return fail(BO_EINVAL, "plan call: null argument");
+  if (prec != BO_F64 && prec != BO_MIXED) return fail(BO_EINVAL, "unknown precision");
+  if (!io->Q || !io->L) return fail(BO_EINVAL, "plan call: Q and L are required");
+  if (prec == BO_MIXED && (!io->Qd || !io->Ld))
+    return fail(BO_EINVAL, "plan call: BO_MIXED needs FP64 diagonals of Q and L");
+  A = Args{};
+  bo::bind_sched(plan->s, ws, false, A);
+  A.Q = io->Q;
+  A.Qd = io->Qd;
+  A.L = io->L;
+  A.Ld = io->Ld;
+  A.y = io->y;
+  A.z = io->z;
+  A.x = io->x;
+  A.S = io->Sig;
+  A.Sd = io->Sigd;
+  A.Sb = io->S;
+  A.Sbd = io->Sd;
+  A.Lb = io->Lbar;
+  A.Lbd = io->Lbard;
+  A.Qb = io->Qbar;
+  A.Qbd = io->Qbard;
+  A.logdet = io->logdet;
+  A.parts = io->parts;
+  A.info = io->info;
+  return BO_OK;
+}
+
+extern "C" bo_status bo_plan_forward(const bo_plan *plan, bo_prec prec, const bo_batch_io *io,
+                                     void *ws, hipStream_t stream) {
+  Args A;
+  if (bo_status e = plan_args(plan, prec, io, ws, A)) return e;
+  if ((io->z || io->x) && !io->y) return fail(BO_EINVAL, "bo_plan_forward: solves need y");
+  if (io->x && !io->z) return fail(BO_EINVAL, "bo_plan_forward: x needs z");
+  if (io->Sig && prec == BO_MIXED && !io->Sigd) return fail(BO_EINVAL, "bo_plan_forward: Sigd needed");
+  A.Sb = nullptr;
+  GpuBE be{stream};
+  return dev_status(bo::pipe_forward(be, plan->s, A, (int)prec), "bo_plan_forward");
+}
+
+extern "C" bo_status bo_plan_gauss_loss(const bo_plan *plan, bo_prec prec, const bo_batch_io *io,
+                                        void *ws, hipStream_t stream) {
+  Args A;
+  if (bo_status e = plan_args(plan, prec, io, ws, A)) return e;
+  if (!io->y || !io->S || !io->z || !io->x || !io->Sig || !io->Lbar || !io->Qbar || !io->parts ||
+      !io->info)
+    return fail(BO_EINVAL, "bo_plan_gauss_loss: y, S, z, x, Sig, Lbar, Qbar, parts, info required");
+  if (prec == BO_MIXED && (!io->Sd || !io->Sigd || !io->Lbard || !io->Qbard))
+    return fail(BO_EINVAL, "bo_plan_gauss_loss: BO_MIXED needs every FP64 diagonal");
+  GpuBE be{stream};
+  return dev_status(bo::pipe_gauss_loss(be, plan->s, A, (int)prec), "bo_plan_gauss_loss");
+}
+
+extern "C" bo_status bo_plan_stats(const bo_plan *plan, int64_t out[5]) {
+  if (!plan || !out) return fail(BO_EINVAL, "bo_plan_stats: null argument");
+  out[0] = plan->s.nprob;
+  out[1] = plan->s.nchunk;
+  out[2] = plan->s.ngroup;
+  out[3] = plan->s.rows;
+  out[4] = plan->s.Kmax;
+  return BO_OK;
+}
+
+extern "C" bo_status bo_plan_destroy(bo_plan *plan) {
+  if (!plan) return BO_OK;
+  if (plan->pinned) (void)hipHostFree(plan->pinned);
+  delete plan;
+  return BO_OK;
+}

@@ -62,5 +62,7 @@ def band_mask(n, k):
 def rel_err(a, b):
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
+    if a.size == 0:
+        return 0.0
     den = max(np.max(np.abs(b)), 1e-300)
-    return float(np.max(np.abs(a - b)) / den) if a.size else 0.0
+    return float(np.max(np.abs(a - b)) / den)

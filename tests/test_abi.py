@@ -1,0 +1,107 @@
+"""The C-ABI library loads, exports every symbol include/bandops.h declares, and
+rejects bad arguments before launching anything (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bandops.h")
+LIBPATH = os.path.join(ROOT, "paper_1902_10078_amd", "libbandops.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIBPATH), reason="libbandops.so not built")
+
+
+def declared_symbols():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(bo_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_header_declares_the_binding_surface():
+    from paper_1902_10078_amd import bandops
+    assert set(declared_symbols()) == set(bandops.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIBPATH)
+    missing = [s for s in declared_symbols() if not hasattr(lib, s)]
+    assert not missing, missing
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1902_10078_amd import bandops
+    return bandops.lib()
+
+
+def _band(n, l, u, ld, ptr=1, diag=None):
+    from paper_1902_10078_amd.bandops import _Band
+    return _Band(ctypes.c_void_p(ptr), ctypes.c_void_p(diag) if diag else None, n, l, u, ld, 0)
+
+
+def test_status_strings(L):
+    assert L.bo_status_string(0) == b"ok"
+    assert L.bo_status_string(-1) == b"invalid argument"
+    assert L.bo_status_string(-3) == b"workspace too small"
+
+
+def test_workspace_query(L):
+    assert L.bo_workspace_size(1000, 3) > 0
+    assert L.bo_workspace_size(1000, 13) == 0      # beyond BO_KMAX
+    assert L.bo_workspace_size(-1, 3) == 0
+    # grows with n
+    assert L.bo_workspace_size(10 ** 6, 5) > L.bo_workspace_size(10 ** 4, 5)
+
+
+def test_argument_errors_return_before_launch(L):
+    bp = ctypes.byref
+    info = ctypes.c_void_p(8)
+    Q = _band(100, 3, 0, 4)
+    Lb = _band(100, 3, 0, 4)
+    # null descriptor
+    assert L.bo_chol(0, None, bp(Lb), None, None, None, info, None, 0, None) == -1
+    assert b"null descriptor" in L.bo_last_error()
+    # ld < l+u+1
+    bad = _band(100, 3, 0, 3)
+    assert L.bo_chol(0, bp(bad), bp(Lb), None, None, None, info, None, 0, None) == -1
+    assert b"ld" in L.bo_last_error()
+    # negative n
+    neg = _band(-5, 3, 0, 4)
+    assert L.bo_chol(0, bp(neg), bp(Lb), None, None, None, info, None, 0, None) == -1
+    # upper width on a factor
+    up = _band(100, 3, 1, 5)
+    assert L.bo_chol(0, bp(up), bp(Lb), None, None, None, info, None, 0, None) == -1
+    # mismatched shapes
+    L2 = _band(99, 3, 0, 4)
+    assert L.bo_chol(0, bp(Q), bp(L2), None, None, None, info, None, 0, None) == -1
+    # y without z
+    assert L.bo_chol(0, bp(Q), bp(Lb), ctypes.c_void_p(16), None, None, info, None, 0, None) == -1
+    # missing info
+    assert L.bo_chol(0, bp(Q), bp(Lb), None, None, None, None, None, 0, None) == -1
+    # mixed without the FP64 diagonal; F64 with one
+    assert L.bo_chol(1, bp(Q), bp(Lb), None, None, None, info, None, 0, None) == -1
+    Qd = _band(100, 3, 0, 4, diag=64)
+    assert L.bo_chol(0, bp(Qd), bp(Lb), None, None, None, info, None, 0, None) == -1
+    # bandwidth beyond the compiled range
+    wide = _band(100, 13, 0, 14)
+    wideL = _band(100, 13, 0, 14)
+    assert L.bo_chol(0, bp(wide), bp(wideL), None, None, None, info, None, 0, None) == -4
+    # workspace too small
+    assert L.bo_chol(0, bp(Q), bp(Lb), None, None, None, info, ctypes.c_void_p(4096), 16, None) == -3
+    # unknown precision
+    assert L.bo_trsv(7, bp(Q), 0, ctypes.c_void_p(8), ctypes.c_void_p(8), None, 0, None) == -1
+    # null vectors
+    assert L.bo_trsv(0, bp(Q), 0, None, None, None, 0, None) == -1
+
+
+def test_plan_errors_and_stats(L):
+    from paper_1902_10078_amd.bandops import _Problem
+    h = ctypes.c_void_p()
+    probs = (_Problem * 2)(_Problem(100, 3, 0, 0, 0), _Problem(50, 14, 0, 400, 100))
+    assert L.bo_plan_create(probs, 2, 0, ctypes.byref(h)) == -4
+    probs = (_Problem * 2)(_Problem(100, 3, 0, 0, 0), _Problem(-1, 1, 0, 400, 100))
+    assert L.bo_plan_create(probs, 2, 0, ctypes.byref(h)) == -1
+    assert L.bo_plan_create(probs, 0, 0, ctypes.byref(h)) == -1
+    assert L.bo_plan_create(None, 1, 0, ctypes.byref(h)) == -1
