@@ -26,6 +26,11 @@ enum Step : int {
 
 // Bandwidths with compiled kernels.
 constexpr int KMAX_SUPPORTED = 12;
+// Largest bandwidth whose replays also produce the next pass's chunk maps.
+// Above it the fused replay kernels no longer fit in registers (they spill)
+// and gave wrong next-pass maps on gfx950 while the same code is exact on the
+// host; those bandwidths run separate summary kernels instead.
+constexpr int KMAX_FUSED = 5;
 
 struct KRange {
   int K;
@@ -42,7 +47,7 @@ struct Sched {
   int64_t rows = 0;
   // workspace layout (bytes offsets from the workspace base)
   size_t off_tables = 0, off_f1map = 0, off_f1st = 0, off_f1gmap = 0, off_f1gst = 0, off_Pc = 0,
-         off_Pg = 0, off_lmap = 0, off_lst = 0, off_lgmap = 0, off_lgst = 0, off_part = 0,
+         off_Pg = 0, off_lmap = 0, off_lmap2 = 0, off_lst = 0, off_lgmap = 0, off_lgst = 0, off_part = 0,
          off_out = 0, bytes = 0;
   int32_t sw_f1map = 1, sw_f1st = 1, sw_mat = 1, sw_lin = 1;
   std::vector<unsigned char> table_blob;   // probs | chunk_prob | group_prob (device image)
@@ -153,6 +158,7 @@ inline bool build_sched(const ProbIn *in, int nprob, int64_t target_chunks, int6
   s.off_Pc = take((size_t)s.nchunk * s.sw_mat);
   s.off_Pg = take((size_t)s.ngroup * s.sw_mat);
   s.off_lmap = take((size_t)s.nchunk * s.sw_lin);
+  s.off_lmap2 = take((size_t)s.nchunk * s.sw_lin);
   s.off_lst = take((size_t)s.nchunk * s.sw_lin);
   s.off_lgmap = take((size_t)s.ngroup * s.sw_lin);
   s.off_lgst = take((size_t)s.ngroup * s.sw_lin);
@@ -189,6 +195,8 @@ inline void bind_sched(const Sched &s, void *ws, bool single, Args &A) {
   A.Pc = (double *)(w + s.off_Pc);
   A.Pg = (double *)(w + s.off_Pg);
   A.lmap = (double *)(w + s.off_lmap);
+  A.lmap2 = (double *)(w + s.off_lmap2);
+  A.lmap_out = nullptr;
   A.lst = (double *)(w + s.off_lst);
   A.lgmap = (double *)(w + s.off_lgmap);
   A.lgst = (double *)(w + s.off_lgst);
@@ -224,7 +232,11 @@ template <class BE> int seq_f1(BE &be, const Sched &s, Args A, int prec, bool wa
       if (int e = be.step(ST_F1_CSWEEP, r.K, prec, A, r.g_cnt)) return e;
     }
     Args B = A;
-    if (!want_P || r.K == 0 || r.max_nchunk <= 1) B.Pc = nullptr;
+    if (!want_P || r.K == 0 || r.max_nchunk <= 1) {
+      B.Pc = nullptr;
+      B.lmap_out = nullptr;
+    }
+    if (r.K > KMAX_FUSED) B.lmap_out = nullptr;
     if (int e = be.step(ST_F1_REP, r.K, prec, B, r.c_cnt)) return e;
   }
   return 0;
@@ -240,19 +252,23 @@ template <class BE> int seq_pc(BE &be, const Sched &s, Args A, int prec) {
 }
 
 // One linear pass: zero-state summaries, the two-level scan, the replay.
-template <class BE> int seq_lin(BE &be, const Sched &s, Args A, int prec, int pass) {
+template <class BE> int seq_lin(BE &be, const Sched &s, Args A, int prec, int pass,
+                                 bool have_maps = false) {
   static const int sum_step[4] = {ST_FS_SUM, ST_F2_SUM, ST_B1_SUM, ST_B2_SUM};
   static const int rep_step[4] = {ST_FS_REP, ST_F2_REP, ST_B1_REP, ST_B2_REP};
   const bool desc = (pass == PASS_F2 || pass == PASS_B2);
   for (const KRange &r : s.ranges) {
     set_range(A, r);
     if (r.K > 0 && r.max_nchunk > 1) {
-      if (int e = be.step(sum_step[pass], r.K, prec, A, r.c_cnt)) return e;
+      if (!have_maps || r.K > KMAX_FUSED)
+        if (int e = be.step(sum_step[pass], r.K, prec, A, r.c_cnt)) return e;
       if (int e = be.step(desc ? ST_DESC_GCOMP : ST_ASC_GCOMP, r.K, prec, A, r.g_cnt)) return e;
       if (int e = be.step(desc ? ST_DESC_GSWEEP : ST_ASC_GSWEEP, r.K, prec, A, r.p_cnt)) return e;
       if (int e = be.step(desc ? ST_DESC_CSWEEP : ST_ASC_CSWEEP, r.K, prec, A, r.g_cnt)) return e;
     }
-    if (int e = be.step(rep_step[pass], r.K, prec, A, r.c_cnt)) return e;
+    Args B = A;
+    if (r.K == 0 || r.max_nchunk <= 1 || r.K > KMAX_FUSED) B.lmap_out = nullptr;
+    if (int e = be.step(rep_step[pass], r.K, prec, B, r.c_cnt)) return e;
   }
   return 0;
 }
@@ -270,13 +286,15 @@ template <class BE> int pipe_forward(BE &be, const Sched &s, Args A, int prec) {
   if (int e = seq_clear(be, s, A)) return e;
   bool lin = (A.S != nullptr) || (A.x != nullptr && A.y != nullptr);
   Args F1 = A;
+  F1.lmap_out = lin ? A.lmap : nullptr;   // F1's replay also summarises F2
   if (int e = seq_f1(be, s, F1, prec, lin)) return e;
   if (lin) {
     Args F2 = A;
     F2.bx = (A.x && A.y) ? A.z : nullptr;
     F2.x = (A.x && A.y) ? A.x : nullptr;
     F2.xscale = 1.0;
-    if (int e = seq_lin(be, s, F2, prec, PASS_F2)) return e;
+    F2.Sb = nullptr;
+    if (int e = seq_lin(be, s, F2, prec, PASS_F2, true)) return e;
   }
   return seq_finalize(be, s, A);
 }
@@ -287,22 +305,57 @@ template <class BE> int pipe_forward(BE &be, const Sched &s, Args A, int prec) {
 //   B1 (up):   Lbar from Algorithm 4 with Sigmabar = (S_jj, 2 S_ij), trace
 //   B2 (down): Qbar from Algorithm 2 with the log-determinant and solve terms
 // A.Sb is the band S; A.L, A.z, A.S, A.Lb, A.x (= ybar) and A.Qb are outputs.
-template <class BE> int pipe_gauss_loss(BE &be, const Sched &s, Args A, int prec) {
+//
+// Each replay also produces the next pass's chunk maps (fused summaries), so
+// after F1's own summary no pass re-reads its inputs for a summary; the maps
+// alternate between the two map buffers.
+template <class BE> int pipe_gauss_loss(BE &be, const Sched &s, Args A, int prec, bool fuse = true) {
+  double *mapA = A.lmap, *mapB = A.lmap2;
   if (int e = seq_clear(be, s, A)) return e;
-  if (int e = seq_f1(be, s, A, prec, true)) return e;
+  if (!fuse) {   // separate summary kernels (reference schedule)
+    if (int e = seq_f1(be, s, A, prec, true)) return e;
+    Args F2 = A;
+    F2.bx = A.z;
+    F2.xscale = -2.0;
+    F2.Sb = nullptr;
+    if (int e = seq_lin(be, s, F2, prec, PASS_F2)) return e;
+    Args B1 = A;
+    B1.sb_is_S = 1;
+    B1.accumulate = 0;
+    if (int e = seq_lin(be, s, B1, prec, PASS_B1)) return e;
+    Args B2 = A;
+    B2.gl = 1.0;
+    B2.yb = A.x;
+    B2.zf = A.z;
+    if (int e = seq_lin(be, s, B2, prec, PASS_B2)) return e;
+    return seq_finalize(be, s, A);
+  }
+  Args F1 = A;
+  F1.lmap_out = mapA;
+  if (int e = seq_f1(be, s, F1, prec, true)) return e;
   Args F2 = A;
   F2.bx = A.z;
   F2.xscale = -2.0;
-  if (int e = seq_lin(be, s, F2, prec, PASS_F2)) return e;
+  F2.sb_is_S = 1;
+  F2.lmap = mapA;
+  F2.lmap_out = mapB;
+  if (int e = seq_lin(be, s, F2, prec, PASS_F2, true)) return e;
   Args B1 = A;
   B1.sb_is_S = 1;
   B1.accumulate = 0;
-  if (int e = seq_lin(be, s, B1, prec, PASS_B1)) return e;
+  B1.gl = 1.0;
+  B1.yb = A.x;
+  B1.zf = A.z;
+  B1.lmap = mapB;
+  B1.lmap_out = mapA;
+  if (int e = seq_lin(be, s, B1, prec, PASS_B1, true)) return e;
   Args B2 = A;
   B2.gl = 1.0;
   B2.yb = A.x;
   B2.zf = A.z;
-  if (int e = seq_lin(be, s, B2, prec, PASS_B2)) return e;
+  B2.lmap = mapA;
+  B2.lmap_out = nullptr;
+  if (int e = seq_lin(be, s, B2, prec, PASS_B2, true)) return e;
   return seq_finalize(be, s, A);
 }
 

@@ -6,7 +6,7 @@
 // bandops_algo.hpp and move summaries and states through the workspace.
 // Every kernel of the library is `one lane = one item`.
 #pragma once
-#include "bandops_algo.hpp"
+#include "bandops_step.hpp"
 
 namespace bo {
 
@@ -55,6 +55,8 @@ struct Args {
   double *f1map, *f1st, *f1gmap, *f1gst;  // F1 chunk maps / states, group maps / states
   double *Pc, *Pg;                        // chunk / group products
   double *lmap, *lst, *lgmap, *lgst;      // linear pass maps / states
+  double *lmap2;                          // second map buffer (fused summaries alternate)
+  double *lmap_out;                       // replays: where the next pass's chunk maps go (or null)
   double *part;                           // 4 words per chunk: logsum, quad, trace, fail row
   // ---- per-problem outputs
   double *logdet;   // per problem
@@ -170,9 +172,13 @@ template <int K, typename T> struct F1Replay {
     else
       f1_zero_state<K>(s);
     double ls = 0.0, qs = 0.0;
+    LinMap<K> f2m;
+    const bool fuse = A.lmap_out && A.Pc;
     int64_t fail = f1_replay_chunk<K, T>(a, b, pd.n, cband<T>(A.Q, A.Qd, pd), band<T>(A.L, A.Ld, pd),
                                          cvec<T>(A.y, pd), vec<T>(A.z, pd), s,
-                                         A.Pc ? A.Pc + (int64_t)c * A.sw_mat : nullptr, ls, qs);
+                                         A.Pc ? A.Pc + (int64_t)c * A.sw_mat : nullptr, ls, qs,
+                                         fuse ? &f2m : nullptr);
+    if (fuse) lin_store<K>(A.lmap_out + (int64_t)c * A.sw_lin, f2m);
     double *pt = A.part + 4 * (int64_t)c;
     pt[0] = ls;
     pt[1] = qs;
@@ -195,18 +201,21 @@ template <int K, typename T> struct PcItem {
 enum PassKind { PASS_FS = 0, PASS_F2 = 1, PASS_B1 = 2, PASS_B2 = 3 };
 
 template <int K, typename T, int PASS, bool REPLAY>
-BO_HD void run_pass(const Args &A, const ProbDesc &pd, int64_t a, int64_t b, LinMap<K> &st, double &aux) {
+BO_HD void run_pass(const Args &A, const ProbDesc &pd, int64_t a, int64_t b, LinMap<K> &st, double &aux,
+                    LinMap<K> *next = nullptr) {
   aux = 0.0;
   if (PASS == PASS_FS) {
     fs_chunk<K, T, REPLAY>(a, b, pd.n, cband<T>(A.L, A.Ld, pd), cvec<T>(A.bx, pd), vec<T>(A.x, pd),
                            A.xscale, st);
   } else if (PASS == PASS_F2) {
     f2_chunk<K, T, REPLAY>(a, b, pd.n, cband<T>(A.L, A.Ld, pd), band<T>(A.S, A.Sd, pd),
-                           cvec<T>(A.bx, pd), vec<T>(A.x, pd), A.xscale, st);
+                           cvec<T>(A.bx, pd), vec<T>(A.x, pd), A.xscale, st,
+                           cband<T>(A.Sb, A.Sbd, pd), A.sb_is_S != 0, next);
   } else if (PASS == PASS_B1) {
     b1_chunk<K, T, REPLAY>(a, b, pd.n, cband<T>(A.L, A.Ld, pd), cband<T>(A.S, A.Sd, pd),
                            cband<T>(A.Sb, A.Sbd, pd), A.sb_is_S != 0, band<T>(A.Lb, A.Lbd, pd),
-                           A.accumulate != 0, aux, st);
+                           A.accumulate != 0, aux, st, cvec<T>(A.yb, pd), cvec<T>(A.zf, pd), A.gl,
+                           next);
   } else {
     b2_chunk<K, T, REPLAY>(a, b, pd.n, cband<T>(A.L, A.Ld, pd), cband<T>(A.Lb, A.Lbd, pd), A.gl,
                            cvec<T>(A.yb, pd), cvec<T>(A.zf, pd), band<T>(A.Qb, A.Qbd, pd), st);
@@ -239,7 +248,10 @@ template <int K, typename T, int PASS> struct LinReplay {
     else
       lin_zero<K>(st);
     double aux;
-    run_pass<K, T, PASS, true>(A, pd, a, b, st, aux);
+    LinMap<K> nm;
+    const bool fuse = A.lmap_out && (PASS == PASS_F2 || PASS == PASS_B1);
+    run_pass<K, T, PASS, true>(A, pd, a, b, st, aux, fuse ? &nm : nullptr);
+    if (fuse) lin_store<K>(A.lmap_out + (int64_t)c * A.sw_lin, nm);
     if (PASS == PASS_B1) A.part[4 * (int64_t)c + 2] = aux;
   }
 };

@@ -73,6 +73,57 @@ template <class Item> int launch_items(const Args &a, int64_t count, hipStream_t
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
+// Per-problem results from the per-chunk partials: one workgroup per problem;
+// lane t takes chunks t, t+64, ... (Neumaier-compensated sums), the partial
+// sums are combined in LDS.  Same quantities as bo::Finalize.
+__global__ void __launch_bounds__(kBlock) k_finalize(const Args A) {
+  __shared__ double sh_s[kBlock], sh_c[kBlock], sh_q[kBlock], sh_t[kBlock];
+  __shared__ long long sh_f[kBlock];
+  const int32_t p = A.p_beg + (int32_t)blockIdx.x;
+  const bo::ProbDesc &pd = bo::prob_at(A, p);
+  double s = 0.0, comp = 0.0, q = 0.0, tr = 0.0;
+  long long fail = -1;
+  for (int32_t c = pd.chunk0 + (int32_t)threadIdx.x; c < pd.chunk0 + pd.nchunk; c += kBlock) {
+    const double *pt = A.part + 4 * (int64_t)c;
+    double t = pt[0], u = s + t;
+    comp += (fabs(s) >= fabs(t)) ? (s - u) + t : (t - u) + s;
+    s = u;
+    q += pt[1];
+    tr += pt[2];
+    if (pt[3] >= 0.0 && fail < 0) fail = (long long)pt[3];   // chunks ascend in rows
+  }
+  sh_s[threadIdx.x] = s;
+  sh_c[threadIdx.x] = comp;
+  sh_q[threadIdx.x] = q;
+  sh_t[threadIdx.x] = tr;
+  sh_f[threadIdx.x] = fail;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  s = 0.0;
+  comp = 0.0;
+  q = 0.0;
+  tr = 0.0;
+  fail = -1;
+  for (int i = 0; i < kBlock; ++i) {
+    double t = sh_s[i], u = s + t;
+    comp += (fabs(s) >= fabs(t)) ? (s - u) + t : (t - u) + s;
+    s = u;
+    comp += sh_c[i];
+    q += sh_q[i];
+    tr += sh_t[i];
+    if (sh_f[i] >= 0 && (fail < 0 || sh_f[i] < fail)) fail = sh_f[i];
+  }
+  double ld = 2.0 * (s + comp);
+  int32_t o = pd.orig;
+  if (A.logdet) A.logdet[o] = fail >= 0 ? NAN : ld;
+  if (A.parts) {
+    A.parts[3 * (int64_t)o + 0] = fail >= 0 ? NAN : ld;
+    A.parts[3 * (int64_t)o + 1] = q;
+    A.parts[3 * (int64_t)o + 2] = tr;
+  }
+  if (A.info) A.info[o] = fail >= 0 ? (int32_t)(fail + 1) : 0;
+}
+
 // ------------------------------------------------------------ profiling
 // When enabled, every launch is bracketed by a pair of events on its stream;
 // bo_profile_read() waits for them and sums the durations per step kind.
@@ -121,7 +172,10 @@ struct GpuBE {
   }
   int finalize(const Args &a, int64_t count) {
     if (count <= 0) return 0;
-    return profiled(bo::ST_COUNT + 1, s, [&] { return launch_items<bo::Finalize>(a, count, s); });
+    return profiled(bo::ST_COUNT + 1, s, [&] {
+      hipLaunchKernelGGL(k_finalize, dim3((unsigned)count), dim3(kBlock), 0, s, a);
+      return hipGetLastError() == hipSuccess ? 0 : -2;
+    });
   }
 };
 
@@ -141,7 +195,22 @@ int64_t default_min_len() {
   }();
   return v;
 }
-constexpr int32_t kGroup = 64;
+bool fuse_summaries() {
+  static bool v = [] {
+    const char *e = std::getenv("BANDOPS_FUSE");
+    return !(e && e[0] == '0');
+  }();
+  return v;
+}
+
+int32_t group_size() {
+  static int32_t v = [] {
+    const char *e = std::getenv("BANDOPS_GROUP");
+    int t = e ? std::atoi(e) : 0;
+    return (int32_t)(t >= 2 && t <= 1024 ? t : 64);
+  }();
+  return v;
+}
 
 bo_status dev_status(int e, const char *what) {
   if (e == 0) return BO_OK;
@@ -177,7 +246,7 @@ bo_status single_sched(int64_t n, int32_t k, int32_t ld, void *ws, size_t ws_byt
   if (k > bo::KMAX_SUPPORTED)
     return fail(BO_EUNSUPPORTED, "bandwidth k = " + std::to_string(k) + " exceeds BO_KMAX");
   bo::ProbIn pi{n, k, ld, 0, 0};
-  if (!bo::build_sched(&pi, 1, default_target_chunks(), default_min_len(), kGroup, s))
+  if (!bo::build_sched(&pi, 1, default_target_chunks(), default_min_len(), group_size(), s))
     return fail(BO_EINVAL, "bad problem shape");
   if (!ws || ws_bytes < s.bytes)
     return fail(BO_EWORKSPACE, "workspace needs " + std::to_string(s.bytes) + " bytes");
@@ -320,7 +389,7 @@ extern "C" size_t bo_workspace_size(int64_t n, int32_t k) {
   if (n < 0 || k < 0 || k > bo::KMAX_SUPPORTED) return 0;
   bo::ProbIn pi{n, k, k + 1, 0, 0};
   Sched s;
-  if (!bo::build_sched(&pi, 1, default_target_chunks(), default_min_len(), kGroup, s)) return 0;
+  if (!bo::build_sched(&pi, 1, default_target_chunks(), default_min_len(), group_size(), s)) return 0;
   return s.bytes;
 }
 
@@ -542,7 +611,7 @@ extern "C" bo_status bo_plan_create(const bo_problem *probs, int32_t nprob, int6
   }
   bo_plan *pl = new bo_plan();
   if (!bo::build_sched(in.data(), nprob, target_chunks > 0 ? target_chunks : default_target_chunks(),
-                       default_min_len(), kGroup, pl->s)) {
+                       default_min_len(), group_size(), pl->s)) {
     delete pl;
     return fail(BO_EINVAL, "bo_plan_create: bad problem table");
   }
@@ -624,7 +693,8 @@ extern "C" bo_status bo_plan_gauss_loss(const bo_plan *plan, bo_prec prec, const
   if (prec == BO_MIXED && (!io->Sd || !io->Sigd || !io->Lbard || !io->Qbard))
     return fail(BO_EINVAL, "bo_plan_gauss_loss: BO_MIXED needs every FP64 diagonal");
   GpuBE be{stream};
-  return dev_status(bo::pipe_gauss_loss(be, plan->s, A, (int)prec), "bo_plan_gauss_loss");
+  return dev_status(bo::pipe_gauss_loss(be, plan->s, A, (int)prec, fuse_summaries()),
+                    "bo_plan_gauss_loss");
 }
 
 extern "C" bo_status bo_plan_stats(const bo_plan *plan, int64_t out[5]) {

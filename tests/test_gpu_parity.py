@@ -275,6 +275,26 @@ def test_plan_gauss_loss_uneven_batch(bo):
         assert rel_err(res["z"][v:v + n], r["z"]) <= TOL
 
 
+@pytest.mark.parametrize("ks", [[4, 6, 7], [1, 2, 8, 9, 10]])
+def test_plan_gauss_loss_more_bandwidths(bo, ks):
+    ns = [3001, 2222, 1777, 999, 1500][: len(ks)]
+    Qs, ys, Ss = packed_batch(ns, ks, 11 + len(ks))
+    plan = bo.Plan(ns, ks, target_chunks=180)
+    res, _, _ = run_plan_loss(bo, plan, Qs, ys, Ss)
+    assert np.all(res["info"] == 0)
+    for p, (n, k) in enumerate(zip(ns, ks)):
+        r = oracle.gauss_loss(Qs[p], k, ys[p], Ss[p])
+        o, v = plan.boff[p], plan.voff[p]
+        m = band_mask(n, k)
+        for i in range(3):
+            assert abs(res["parts"][p, i] - r["parts"][i]) <= TOL * max(1, abs(r["parts"][i])), (p, i)
+        for nm in ("L", "Sig", "Lbar", "Qbar"):
+            if nm == "Lbar":
+                continue   # the plan's Lbar is the subset-inverse part only
+            assert rel_err(res[nm][o:o + n * (k + 1)].reshape(n, k + 1) * m, r[nm] * m) <= TOL, (p, nm)
+        assert rel_err(res["ybar"][v:v + n], r["ybar"]) <= TOL
+
+
 def test_plan_gauss_loss_mixed(bo):
     ns = [3000, 17, 9000, 400]
     ks = [3, 5, 11, 1]
