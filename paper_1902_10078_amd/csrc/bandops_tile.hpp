@@ -37,35 +37,87 @@ __device__ __forceinline__ int64_t wave_max(int64_t v) {
   return v;
 }
 
-// LDS layout of one staged array: 64 segments (one per lane) of TR rows x W
-// elements, copied as 4-byte pieces.  The segment pitch (in pieces) is padded
-// so that lanes reading the same row offset hit different banks.
+// LDS layout of one staged array: 64 segments (one per lane) of up to TR rows
+// x W elements, packed back to back.  A segment occupies PPI pieces (16-byte
+// pieces when every segment start of the tile is 16-byte aligned, else 4-byte
+// pieces); PPI is made odd so that lanes reading the same row offset fall in
+// different banks.  Geom gives both layouts and the LDS size of the larger.
 template <typename E, int W, int TR> struct Geom {
-  static constexpr int PPS = TR * W * (int)sizeof(E) / 4;   // pieces per segment
-  static constexpr int PITCH = sizeof(E) == 8 ? (((PPS / 2) % 2 == 0) ? PPS + 2 : PPS)
-                                              : ((PPS % 2 == 0) ? PPS + 1 : PPS);
-  static constexpr int WORDS = kWave * PITCH;               // 4-byte words
+  static constexpr int SEGB = TR * W * (int)sizeof(E);   // data bytes per segment
+  static constexpr int odd(int x) { return x % 2 == 0 ? x + 1 : x; }
+  static constexpr int PPI16 = odd((SEGB + 15) / 16);
+  static constexpr int PPI4 = odd((SEGB + 3) / 4);
+  static constexpr int BYTES16 = kWave * PPI16 * 16, BYTES4 = kWave * PPI4 * 4;
+  static constexpr int WORDS = (BYTES16 > BYTES4 ? BYTES16 : BYTES4) / 4;
 };
 
 typedef __attribute__((address_space(3))) void *lds_ptr_t;
+template <typename E> using lds_cptr = const __attribute__((address_space(3))) E *;
 
-// Fill an LDS tile: for every lane s of the wave, the first cnt[s] * W
-// elements at src[s] (contiguous records) land at dst + s * PITCH words.  Each
-// instruction moves 64 consecutive 4-byte pieces of the flattened tile
-// straight from global memory into LDS (no registers), so all loads of a tile
-// are in flight together; the caller waits once.
-template <typename E, int W, int TR>
-__device__ __forceinline__ void lds_fill(uint32_t *dst, const E *const *src, const int *cnt, int lane) {
-  using G = Geom<E, W, TR>;
-#pragma unroll 8
-  for (int k = 0; k < G::PITCH; ++k) {
-    const int p = k * kWave + lane;
-    const int s = p / G::PITCH;
-    const int q = p - s * G::PITCH;
-    const char *sp = (const char *)src[s];
-    if (sp && q * 4 < cnt[s] * W * (int)sizeof(E))
-      __builtin_amdgcn_global_load_lds((const void *)(sp + q * 4), (lds_ptr_t)(dst + k * kWave), 4, 0, 0);
+// Load the pieces of every segment of a tile, PPI pieces of PIECE bytes per
+// segment, segment s at d + s * PPI * PIECE.  When a segment fits in one
+// instruction (PPI <= 64), each instruction covers 64 / PPI consecutive
+// segments and a lane learns its segment's source address by a cross-lane
+// shuffle; otherwise each segment takes ceil(PPI / 64) instructions and its
+// address is read from its lane (uniform).
+// One piece load into LDS (the size operand of the builtin must be a literal).
+template <int PIECE>
+__device__ __forceinline__ void load_piece(uint64_t src, __attribute__((address_space(3))) char *dst) {
+  if constexpr (PIECE == 16)
+    __builtin_amdgcn_global_load_lds((const void *)src, (lds_ptr_t)dst, 16, 0, 0);
+  else
+    __builtin_amdgcn_global_load_lds((const void *)src, (lds_ptr_t)dst, 4, 0, 0);
+}
+
+template <int PPI, int PIECE>
+__device__ __forceinline__ void fill_pieces(__attribute__((address_space(3))) char *d, uint64_t my_src,
+                                            int my_bytes, int lane) {
+  if constexpr (PPI <= kWave) {
+    constexpr int NSEG = kWave / PPI;
+    constexpr int NI = (kWave + NSEG - 1) / NSEG;
+    const int sl = lane / PPI, q = lane - sl * PPI;
+#pragma unroll 4
+    for (int i = 0; i < NI; ++i) {
+      const int s = i * NSEG + sl;
+      const int ss = s < kWave ? s : kWave - 1;
+      const uint64_t sp = __shfl(my_src, ss, kWave);
+      const int nb = __shfl(my_bytes, ss, kWave);
+      if (sl < NSEG && s < kWave && q * PIECE < nb) load_piece<PIECE>(sp + q * PIECE, d + i * NSEG * PPI * PIECE);
+    }
+  } else {
+    constexpr int IPS = (PPI + kWave - 1) / kWave;
+#pragma unroll 2
+    for (int s = 0; s < kWave; ++s) {
+      const uint64_t sp = ((uint64_t)__builtin_amdgcn_readlane((uint32_t)(my_src >> 32), s) << 32) |
+                          (uint32_t)__builtin_amdgcn_readlane((uint32_t)my_src, s);
+      const int nb = __builtin_amdgcn_readlane(my_bytes, s);
+      if (nb <= 0) continue;
+#pragma unroll
+      for (int p = 0; p < IPS; ++p) {
+        const int q = p * kWave + lane;
+        if (q * PIECE < nb) load_piece<PIECE>(sp + q * PIECE, d + (s * PPI + p * kWave) * PIECE);
+      }
+    }
   }
+}
+
+// Fill an LDS tile: lane s's cnt_s * W elements at src_s (contiguous records;
+// src_s, cnt_s are lane s's my_src, my_cnt) land in segment s, straight from
+// global memory into LDS so that every load of a tile is in flight at once;
+// the caller waits once.  Uses 16-byte pieces when every segment start is
+// 16-byte aligned, else 4-byte pieces.  Returns the segment pitch in bytes.
+template <typename E, int W, int TR>
+__device__ __forceinline__ int lds_fill(uint32_t *dst, const E *my_src, int my_cnt, int lane) {
+  using G = Geom<E, W, TR>;
+  const int my_bytes = (my_src && my_cnt > 0) ? my_cnt * W * (int)sizeof(E) : 0;
+  const bool ok16 = my_bytes == 0 || (((uint64_t)my_src & 15) == 0);
+  __attribute__((address_space(3))) char *d = (__attribute__((address_space(3))) char *)(lds_ptr_t)dst;
+  if (__all(ok16)) {
+    fill_pieces<G::PPI16, 16>(d, (uint64_t)my_src, my_bytes, lane);
+    return G::PPI16 * 16;
+  }
+  fill_pieces<G::PPI4, 4>(d, (uint64_t)my_src, my_bytes, lane);
+  return G::PPI4 * 4;
 }
 
 // A staged band input: records of the lane's problem (null when absent) and,
@@ -95,14 +147,9 @@ __device__ __forceinline__ void stream_rows(const BandIn<T> (&bands)[NB > 0 ? NB
   using GB = Geom<T, W, TR>;
   using GD = Geom<double, 1, TR>;
   using GV = Geom<T, 1, TR>;
-  __shared__ uint32_t sb[NB1][GB::WORDS];
-  __shared__ uint32_t sd[MIXED ? NB1 : 1][MIXED ? GD::WORDS : 1];
-  __shared__ uint32_t sv[NV1][NV > 0 ? GV::WORDS : 1];
-  __shared__ const T *pb[NB1][kWave];
-  __shared__ const double *pd[NB1][kWave];
-  __shared__ const T *pv[NV1][kWave];
-  __shared__ int cb[NB1][kWave];
-  __shared__ int cv[NV1][kWave];
+  __shared__ __attribute__((aligned(16))) uint32_t sb[NB1][GB::WORDS];
+  __shared__ __attribute__((aligned(16))) uint32_t sd[MIXED ? NB1 : 1][MIXED ? GD::WORDS : 1];
+  __shared__ __attribute__((aligned(16))) uint32_t sv[NV1][NV > 0 ? GV::WORDS : 1];
 
   const int lane = threadIdx.x;
   const int64_t len = hi > lo ? hi - lo : 0;
@@ -110,32 +157,26 @@ __device__ __forceinline__ void stream_rows(const BandIn<T> (&bands)[NB > 0 ? NB
   for (int64_t t0 = 0; t0 < maxlen; t0 += TR) {
     const int cnt = (int)(len - t0 < TR ? (len - t0 > 0 ? len - t0 : 0) : TR);
     const int64_t r0 = DESC ? hi - t0 - cnt : lo + t0;   // first row of this tile
+    int pitch_b[NB1], pitch_d[NB1], pitch_v[NV1];
 #pragma unroll
     for (int bi = 0; bi < NB; ++bi) {
       int64_t s0 = r0 + bands[bi].shift;
       int c = cnt;
       if (s0 + c > n) c = (int)(n - s0 > 0 ? n - s0 : 0);
       const bool on = bands[bi].p && c > 0;
-      pb[bi][lane] = on ? bands[bi].p + s0 * ld : nullptr;
-      pd[bi][lane] = (on && bands[bi].diag) ? bands[bi].diag + s0 : nullptr;
-      cb[bi][lane] = c;
+      pitch_b[bi] = lds_fill<T, W, TR>(sb[bi], on ? bands[bi].p + s0 * ld : nullptr, c, lane);
+      pitch_d[bi] = 0;
+      if (MIXED)
+        pitch_d[bi] = lds_fill<double, 1, TR>(sd[MIXED ? bi : 0],
+                                              (on && bands[bi].diag) ? bands[bi].diag + s0 : nullptr, c, lane);
     }
 #pragma unroll
     for (int vi = 0; vi < NV; ++vi) {
       int64_t s0 = r0 + vecs[vi].shift;
       int c = cnt;
       if (s0 + c > n) c = (int)(n - s0 > 0 ? n - s0 : 0);
-      pv[vi][lane] = (vecs[vi].p && c > 0) ? vecs[vi].p + s0 : nullptr;
-      cv[vi][lane] = c;
+      pitch_v[vi] = lds_fill<T, 1, TR>(sv[vi], (vecs[vi].p && c > 0) ? vecs[vi].p + s0 : nullptr, c, lane);
     }
-    __syncthreads();
-#pragma unroll
-    for (int bi = 0; bi < NB; ++bi) {
-      lds_fill<T, W, TR>(sb[bi], pb[bi], cb[bi], lane);
-      if (MIXED) lds_fill<double, 1, TR>(sd[MIXED ? bi : 0], pd[bi], cb[bi], lane);
-    }
-#pragma unroll
-    for (int vi = 0; vi < NV; ++vi) lds_fill<T, 1, TR>(sv[vi], pv[vi], cv[vi], lane);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
 #pragma unroll 1
@@ -148,19 +189,20 @@ __device__ __forceinline__ void stream_rows(const BandIn<T> (&bands)[NB > 0 ? NB
 #pragma unroll
         for (int bi = 0; bi < NB; ++bi) {
           const int64_t js = j + bands[bi].shift;
-          const T *row = (const T *)(sb[bi] + lane * GB::PITCH) + r * W;
+          lds_cptr<T> row = (lds_cptr<T>)((lds_cptr<char>)(lds_ptr_t)sb[bi] + lane * pitch_b[bi]) + r * W;
 #pragma unroll
           for (int d = 0; d <= K; ++d) {
             double x = (double)row[d];
             if (d == 0 && MIXED && bands[bi].diag)
-              x = ((const double *)(sd[MIXED ? bi : 0] + lane * GD::PITCH))[r];
+              x = ((lds_cptr<double>)((lds_cptr<char>)(lds_ptr_t)sd[MIXED ? bi : 0] + lane * pitch_d[bi]))[r];
             rec[bi][d] = (bands[bi].p && js + d < n) ? x : 0.0;
           }
         }
 #pragma unroll
         for (int vi = 0; vi < NV; ++vi)
           val[vi] = (vecs[vi].p && j + vecs[vi].shift < n)
-                        ? (double)((const T *)(sv[vi] + lane * GV::PITCH))[r] : 0.0;
+                        ? (double)((lds_cptr<T>)((lds_cptr<char>)(lds_ptr_t)sv[vi] + lane * pitch_v[vi]))[r]
+                        : 0.0;
         body(j, rec, val);
       }
     }
