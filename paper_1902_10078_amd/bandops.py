@@ -19,7 +19,7 @@ from typing import Optional
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libbandops.so")
+LIB_PATH = os.environ.get("BANDOPS_LIB") or os.path.join(_HERE, "libbandops.so")
 
 F64, MIXED = 0, 1
 KMAX = 12

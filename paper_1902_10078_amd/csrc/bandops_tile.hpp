@@ -16,7 +16,10 @@ namespace tile {
 
 constexpr int kWave = 64;
 // LDS bytes one wavefront may use for its tiles (tiles plus tables stay under 40 KB: four wavefronts per CU).
-constexpr int kTileBytes = 34816;
+#ifndef BO_TILE_BYTES
+#define BO_TILE_BYTES 34816
+#endif
+constexpr int kTileBytes = BO_TILE_BYTES;
 
 template <typename T> constexpr int band_row_bytes(int K) {
   return (K + 1) * (int)sizeof(T) + (sizeof(T) == 4 ? 8 : 0);   // + FP64 diagonal
