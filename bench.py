@@ -77,6 +77,27 @@ def cpu_baseline(Qs, ys, Ss, ks, nsample: int):
                        f"OpenMP across problems, {dt:.2f} s wall"), parts
 
 
+def copy_probe(torch, mib: int):
+    """A plain copy of a known number of bytes: the reference reading for the
+    HBM byte counters (it reads and writes exactly mib MiB each)."""
+    dev = torch.device("cuda", 0)
+    nbytes = mib << 20
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    reps = 5
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    print(json.dumps(dict(copy_bytes=nbytes, launches=reps + 1, avg_ms=ms,
+                          gbs=2 * nbytes / (ms / 1e3) / 1e9)), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +112,9 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--kernels-json", default="")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (a known-size kernel "
+                         "that calibrates HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         log("bench.py measures one GPU: this build has no multi-GPU path (the batch shards "
@@ -98,6 +122,9 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_probe:
+        copy_probe(torch, args.copy_probe)
+        return
     from paper_1902_10078_amd import bandops as bo
 
     prec = bo.F64 if args.prec == "f64" else bo.MIXED

@@ -15,20 +15,12 @@ namespace bo {
 namespace tile {
 
 constexpr int kWave = 64;
-// LDS bytes one wavefront may use for its tiles (tiles plus tables stay under 40 KB: four wavefronts per CU).
+// LDS bytes one wavefront may use for its tiles: a quarter of the CU's 160 KB,
+// so that four wavefronts (one per SIMD) stay resident.
 #ifndef BO_TILE_BYTES
-#define BO_TILE_BYTES 34816
+#define BO_TILE_BYTES 40960
 #endif
 constexpr int kTileBytes = BO_TILE_BYTES;
-
-template <typename T> constexpr int band_row_bytes(int K) {
-  return (K + 1) * (int)sizeof(T) + (sizeof(T) == 4 ? 8 : 0);   // + FP64 diagonal
-}
-template <int K, typename T, int NB, int NV> constexpr int tile_rows() {
-  int bytes = NB * band_row_bytes<T>(K) + NV * (int)sizeof(T);
-  int tr = bytes > 0 ? kTileBytes / (kWave * bytes) : 16;
-  return tr < 2 ? 2 : (tr > 32 ? 32 : tr);
-}
 
 // Maximum over the wavefront (one workgroup = one wavefront).
 __device__ __forceinline__ int64_t wave_max(int64_t v) {
@@ -53,6 +45,21 @@ template <typename E, int W, int TR> struct Geom {
   static constexpr int BYTES16 = kWave * PPI16 * 16, BYTES4 = kWave * PPI4 * 4;
   static constexpr int WORDS = (BYTES16 > BYTES4 ? BYTES16 : BYTES4) / 4;
 };
+
+// LDS bytes of the tiles of NB bands and NV vectors at TR rows per tile.
+template <int K, typename T, int NB, int NV, int TR> constexpr int tile_lds_bytes() {
+  return NB * Geom<T, K + 1, TR>::WORDS * 4 + (sizeof(T) == 4 ? NB * Geom<double, 1, TR>::WORDS * 4 : 0) +
+         NV * Geom<T, 1, TR>::WORDS * 4;
+}
+// Rows per tile: the most (up to 32) whose tiles fit the budget, at least 2.
+template <int K, typename T, int NB, int NV, int TR = 32> constexpr int tile_rows() {
+  if constexpr (TR <= 2) {
+    return 2;
+  } else {
+    if constexpr (tile_lds_bytes<K, T, NB, NV, TR>() <= kTileBytes) return TR;
+    else return tile_rows<K, T, NB, NV, TR - 1>();
+  }
+}
 
 typedef __attribute__((address_space(3))) void *lds_ptr_t;
 template <typename E> using lds_cptr = const __attribute__((address_space(3))) E *;
