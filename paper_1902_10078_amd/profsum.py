@@ -1,0 +1,168 @@
+"""Summaries of rocprofv3 output for the banded kernels.
+
+  python -m paper_1902_10078_amd.profsum stats KERNEL_STATS_CSV --cmd "..."
+      per-kernel call counts and durations (rocprofv3 --kernel-trace --stats)
+  python -m paper_1902_10078_amd.profsum traffic --fetch CSV --write CSV \\
+      --copy-fetch CSV --copy-write CSV --copy-bytes B --rows R --cmd "..."
+      HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counters (KiB per
+      dispatch), each scaled by what the same counter reads for a plain copy of
+      a known size.
+
+Both print short text on stdout.  The traffic summary records a hash of the
+kernel sources: bench.py reports the measured traffic only while the kernels
+are unchanged since the counters were taken.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import os
+import re
+import sys
+from collections import defaultdict
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+# rocprofv3 kernel name -> the library's profiling slot name
+_KERNEL_SLOTS = [
+    (r"k_f1_sum<", "f1_summary"),
+    (r"k_f1_rep<", "f1_replay"),
+    (r"k_pc<", "chunk_product"),
+    (r"k_fs<\d+, \w+, false>", "fs_summary"),
+    (r"k_fs<\d+, \w+, true>", "fs_replay"),
+    (r"k_f2<\d+, \w+, false", "f2_summary"),
+    (r"k_f2<\d+, \w+, true", "f2_replay"),
+    (r"k_b1<\d+, \w+, false", "b1_summary"),
+    (r"k_b1<\d+, \w+, true", "b1_replay"),
+    (r"k_b2<\d+, \w+, false>", "b2_summary"),
+    (r"k_b2<\d+, \w+, true>", "b2_replay"),
+    (r"F1GroupCompose", "f1_group_compose"),
+    (r"F1GroupSweep", "f1_group_sweep"),
+    (r"F1ChunkSweep", "f1_chunk_sweep"),
+    (r"LinGroupCompose<\d+, true>", "desc_group_compose"),
+    (r"LinGroupSweep<\d+, true>", "desc_group_sweep"),
+    (r"LinChunkSweep<\d+, true>", "desc_chunk_sweep"),
+    (r"LinGroupCompose<\d+, false>", "asc_group_compose"),
+    (r"LinGroupSweep<\d+, false>", "asc_group_sweep"),
+    (r"LinChunkSweep<\d+, false>", "asc_chunk_sweep"),
+    (r"k_finalize", "finalize"),
+    (r"ClearPart", "clear_partials"),
+    (r"k_gbmm", "gbmm"),
+    (r"k_gbmv", "gbmv"),
+    (r"k_outer", "outer_band"),
+    (r"k_logdet_bwd", "logdet_bwd"),
+]
+
+
+def slot_of(kernel_name: str) -> str | None:
+    for pat, slot in _KERNEL_SLOTS:
+        if re.search(pat, kernel_name):
+            return slot
+    return None
+
+
+def source_hash() -> str:
+    """Hash of the device sources that decide what the kernels execute."""
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(HERE, "csrc", "*.hpp")) +
+                   glob.glob(os.path.join(HERE, "csrc", "*.hip")))
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _counter_means(path: str, counter: str):
+    vals = defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] == counter:
+            vals[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+    return {k: (sum(v) / len(v), len(v)) for k, v in vals.items()}
+
+
+def stats(args):
+    rows = list(csv.DictReader(open(args.csv)))
+    print(f"# rocprofv3 kernel trace summary")
+    print(f"# command: {args.cmd}")
+    print(f"# {'slot':22s} {'calls':>6s} {'avg_ms':>10s} {'total_%':>8s}  kernel")
+    for r in rows:
+        name = r["Name"]
+        slot = slot_of(name) or "-"
+        print(f"  {slot:22s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e6:10.4f} "
+              f"{float(r['Percentage']):8.2f}  {name[:110]}")
+
+
+def traffic(args):
+    cf = _counter_means(args.copy_fetch, "FETCH_SIZE")
+    cw = _counter_means(args.copy_write, "WRITE_SIZE")
+    copy_k = [k for k in cf if "copy" in k.lower()]
+    if not copy_k:
+        sys.exit("no copy kernel in the calibration run")
+    kib = args.copy_bytes / 1024.0
+    fscale = kib / cf[copy_k[0]][0]
+    wscale = kib / cw[copy_k[0]][0]
+    fe = _counter_means(args.fetch, "FETCH_SIZE")
+    wr = _counter_means(args.write, "WRITE_SIZE")
+    print("# HBM traffic per launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE (KiB per dispatch)")
+    print(f"# command (fetch): {args.cmd_fetch or args.cmd}")
+    print(f"# command (write): {args.cmd_write or args.cmd}")
+    print(f"# calibration: a plain copy of {args.copy_bytes} bytes ({copy_k[0]}) reads "
+          f"FETCH_SIZE {cf[copy_k[0]][0]:.1f} KiB and WRITE_SIZE {cw[copy_k[0]][0]:.1f} KiB")
+    print(f"fetch_scale: {fscale:.4f}")
+    print(f"write_scale: {wscale:.4f}")
+    print(f"rows_per_launch: {args.rows}")
+    print(f"source_hash: {source_hash()}")
+    print(f"# {'slot':20s} {'fetch_GB':>10s} {'write_GB':>10s} {'traffic_GB':>11s} {'B/row':>8s}")
+    seen = set()
+    for k, (fv, n) in fe.items():
+        slot = slot_of(k)
+        if slot is None or slot in seen or k not in wr:
+            continue
+        seen.add(slot)
+        fb = fv * 1024 * fscale
+        wb = wr[k][0] * 1024 * wscale
+        print(f"traffic {slot:20s} {fb / 1e9:10.4f} {wb / 1e9:10.4f} {(fb + wb) / 1e9:11.4f} "
+              f"{(fb + wb) / args.rows:8.1f}")
+
+
+def read_traffic(path: str):
+    """Parse a traffic summary: {slot: bytes per launch}, plus its source hash."""
+    out, meta = {}, {}
+    if not os.path.exists(path):
+        return out, meta
+    for line in open(path):
+        if line.startswith("#"):
+            continue
+        parts = line.split()
+        if not parts:
+            continue
+        if parts[0] == "traffic" and len(parts) >= 5:
+            out[parts[1]] = float(parts[4]) * 1e9
+        elif parts[0].endswith(":") and len(parts) == 2:
+            meta[parts[0][:-1]] = parts[1]
+    return out, meta
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd_name", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("csv")
+    s.add_argument("--cmd", required=True)
+    t = sub.add_parser("traffic")
+    for nm in ("--fetch", "--write", "--copy-fetch", "--copy-write"):
+        t.add_argument(nm, required=True)
+    t.add_argument("--copy-bytes", type=int, required=True)
+    t.add_argument("--rows", type=int, required=True)
+    t.add_argument("--cmd", default="")
+    t.add_argument("--cmd-fetch", default="")
+    t.add_argument("--cmd-write", default="")
+    a = ap.parse_args(argv)
+    (stats if a.cmd_name == "stats" else traffic)(a)
+
+
+if __name__ == "__main__":
+    main()
