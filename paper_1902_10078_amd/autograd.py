@@ -1,0 +1,262 @@
+"""torch.autograd.Function wrappers of the banded operators.
+
+Every forward and backward runs the library's HIP kernels; the functions here
+only allocate outputs and route sensitivities (Table 1 of the paper).
+
+Tensors are FP64 bands of shape (n, l+u+1) in record-major storage (row j =
+column j of the band, slot u+i-j holds B[i,j]; lower-banded and symmetric
+matrices use u = 0).  Symmetric inputs (the precision Q) are given by their
+lower band, and their gradients are with respect to those stored entries: an
+off-diagonal stored value stands for both Q_ij and Q_ji.
+
+  chol(Q)            -> (L, logdet)        Algorithm 1 / Algorithm 2
+  trsv(L, b, trans)  -> L^{-1} b or L^{-T} b      Table 1, solve row
+  subset_inv(L)      -> band of (L L^T)^{-1}       Algorithm 3 / Algorithm 4
+  gbmm(A, B, ...)    -> band of op(A) op(B)        Table 1, product row
+  gbmv(A, x, tA)     -> op(A) x                    Table 1, product row
+  outer_band(m, v)   -> band of m v^T              Table 1, outer-product row
+  gauss_loss(plan, Q, y, S) -> per-problem logdet Q - y^T Q^{-1} y + tr(Q^{-1} S)
+                                  (fused forward and backward over a batch)
+"""
+from __future__ import annotations
+
+import torch
+
+from . import bandops as bo
+
+
+def _band(t: torch.Tensor, l: int, u: int = 0) -> bo.Band:
+    if t.dtype != torch.float64:
+        raise TypeError("the autograd wrappers take FP64 bands")
+    return bo.Band(t.contiguous(), l, u)
+
+
+def _vec(t: torch.Tensor) -> torch.Tensor:
+    if t.dtype != torch.float64:
+        raise TypeError("the autograd wrappers take FP64 vectors")
+    return t.contiguous()
+
+
+def _check_info(info: torch.Tensor):
+    r = int(info.max().item())
+    if r != 0:
+        raise bo.BandOpsError(f"matrix is not positive definite (leading minor of order {r})")
+
+
+class Chol(torch.autograd.Function):
+    """Q (lower band, k = Q.shape[1]-1) -> (L, log det Q)."""
+
+    @staticmethod
+    def forward(ctx, Q):
+        k = Q.shape[1] - 1
+        L, _, logdet, info = bo.bo_chol(_band(Q, k))
+        _check_info(info)
+        ctx.save_for_backward(L.band)
+        ctx.k = k
+        return L.band, logdet.reshape(())
+
+    @staticmethod
+    def backward(ctx, gL, glogdet):
+        (Lt,) = ctx.saved_tensors
+        L = bo.Band(Lt, ctx.k)
+        Lbar = bo.Band(gL.contiguous().clone() if gL is not None else torch.zeros_like(Lt), ctx.k)
+        if glogdet is not None:
+            bo.bo_logdet_bwd(L, glogdet, out=Lbar, accumulate=True)
+        return bo.bo_chol_bwd(L, Lbar).band
+
+
+class Trsv(torch.autograd.Function):
+    """x = L^{-1} b (trans = 0) or L^{-T} b (trans = 1)."""
+
+    @staticmethod
+    def forward(ctx, L, b, trans: int = 0):
+        k = L.shape[1] - 1
+        Lb = _band(L, k)
+        x = bo.bo_trsv(Lb, _vec(b), trans)
+        ctx.save_for_backward(Lb.band, x)
+        ctx.k, ctx.trans = k, trans
+        return x
+
+    @staticmethod
+    def backward(ctx, gx):
+        Lt, x = ctx.saved_tensors
+        bbar, Lbar = bo.bo_trsv_bwd(bo.Band(Lt, ctx.k), x, gx.contiguous(), ctx.trans)
+        return Lbar.band, bbar, None
+
+
+class SubsetInv(torch.autograd.Function):
+    """Lower band (width k) of (L L^T)^{-1}."""
+
+    @staticmethod
+    def forward(ctx, L):
+        k = L.shape[1] - 1
+        Lb = _band(L, k)
+        S = bo.bo_subset_inv(Lb)
+        ctx.save_for_backward(Lb.band, S.band)
+        ctx.k = k
+        return S.band
+
+    @staticmethod
+    def backward(ctx, gS):
+        Lt, St = ctx.saved_tensors
+        k = ctx.k
+        return bo.bo_subset_inv_bwd(bo.Band(Lt, k), bo.Band(St, k), bo.Band(gS.contiguous(), k)).band
+
+
+class Gbmm(torch.autograd.Function):
+    """Band (l, u) of op(A) op(B) for (la, ua)- and (lb, ub)-banded A, B."""
+
+    @staticmethod
+    def forward(ctx, A, B, la, ua, lb, ub, tA, tB, l, u):
+        Ab, Bb = _band(A, la, ua), _band(B, lb, ub)
+        C = bo.bo_gbmm(Ab, Bb, tA, tB, l, u)
+        ctx.save_for_backward(Ab.band, Bb.band)
+        ctx.meta = (la, ua, lb, ub, tA, tB, l, u)
+        return C.band
+
+    @staticmethod
+    def backward(ctx, gC):
+        At, Bt = ctx.saved_tensors
+        la, ua, lb, ub, tA, tB, l, u = ctx.meta
+        A, B, Cb = bo.Band(At, la, ua), bo.Band(Bt, lb, ub), bo.Band(gC.contiguous(), l, u)
+        gA = gB = None
+        if ctx.needs_input_grad[0]:
+            # d/dA of <Cbar, op(A) op(B)>: band_A(Cbar op(B)^T), transposed when tA
+            gA = (bo.bo_gbmm(Cb, B, 0, 1 - tB, la, ua) if not tA
+                  else bo.bo_gbmm(B, Cb, tB, 1, la, ua)).band
+        if ctx.needs_input_grad[1]:
+            gB = (bo.bo_gbmm(A, Cb, 1 - tA, 0, lb, ub) if not tB
+                  else bo.bo_gbmm(Cb, A, 1, tA, lb, ub)).band
+        return gA, gB, None, None, None, None, None, None, None, None
+
+
+class Gbmv(torch.autograd.Function):
+    """op(A) x for an (l, u)-banded A."""
+
+    @staticmethod
+    def forward(ctx, A, x, l, u, tA):
+        Ab = _band(A, l, u)
+        y = bo.bo_gbmv(Ab, _vec(x), tA)
+        ctx.save_for_backward(Ab.band, x)
+        ctx.meta = (l, u, tA)
+        return y
+
+    @staticmethod
+    def backward(ctx, gy):
+        At, x = ctx.saved_tensors
+        l, u, tA = ctx.meta
+        A, gy = bo.Band(At, l, u), gy.contiguous()
+        gA = gx = None
+        if ctx.needs_input_grad[0]:
+            gA = (bo.bo_outer_band(gy, x, l, u) if not tA else bo.bo_outer_band(x, gy, l, u)).band
+        if ctx.needs_input_grad[1]:
+            gx = bo.bo_gbmv(A, gy, 1 - tA)
+        return gA, gx, None, None, None
+
+
+class OuterBand(torch.autograd.Function):
+    """Band (l, u) of m v^T."""
+
+    @staticmethod
+    def forward(ctx, m, v, l, u):
+        O = bo.bo_outer_band(_vec(m), _vec(v), l, u)
+        ctx.save_for_backward(m, v)
+        ctx.meta = (l, u)
+        return O.band
+
+    @staticmethod
+    def backward(ctx, gO):
+        m, v = ctx.saved_tensors
+        l, u = ctx.meta
+        Ob = bo.Band(gO.contiguous(), l, u)
+        gm = bo.bo_gbmv(Ob, v, 0) if ctx.needs_input_grad[0] else None
+        gv = bo.bo_gbmv(Ob, m, 1) if ctx.needs_input_grad[1] else None
+        return gm, gv, None, None
+
+
+class GaussLoss(torch.autograd.Function):
+    """Per-problem loss_p = log det Q_p - y_p^T Q_p^{-1} y_p + tr(Q_p^{-1} S_p)
+    over a plan's batch.  Q, S: packed lower bands (all problems' records back
+    to back); y: packed vectors.  The forward pass runs the fused forward and
+    backward passes once and keeps dloss/dQ and dloss/dy for backward."""
+
+    @staticmethod
+    def forward(ctx, plan, Q, y, S):
+        Q, y, S = _vec(Q), _vec(y), _vec(S)
+        dev = Q.device
+        E, N = Q.numel(), y.numel()
+        bufs = {nm: torch.empty(E, dtype=torch.float64, device=dev) for nm in ("L", "Sig", "Lbar", "Qbar")}
+        z = torch.empty(N, dtype=torch.float64, device=dev)
+        ybar = torch.empty(N, dtype=torch.float64, device=dev)
+        parts = torch.zeros((plan.nprob, 3), dtype=torch.float64, device=dev)
+        info = torch.zeros(plan.nprob, dtype=torch.int32, device=dev)
+        io = plan.io(Q=Q, y=y, S=S, z=z, x=ybar, parts=parts, info=info, **bufs)
+        plan.gauss_loss(bo.F64, io)
+        _check_info(info)
+        ctx.save_for_backward(bufs["Qbar"], ybar, bufs["Sig"])
+        ctx.plan = plan
+        return parts[:, 0] - parts[:, 1] + parts[:, 2]
+
+    @staticmethod
+    def backward(ctx, g):
+        Qbar, ybar, Sig = ctx.saved_tensors
+        plan = ctx.plan
+        band_sizes = torch.tensor([n * (k + 1) for n, k in zip(plan.ns, plan.ks)], device=g.device)
+        rows = torch.tensor(plan.ns, device=g.device)
+        gb = torch.repeat_interleave(g, band_sizes)
+        gQ = Qbar * gb if ctx.needs_input_grad[1] else None
+        gy = ybar * torch.repeat_interleave(g, rows) if ctx.needs_input_grad[2] else None
+        gS = None
+        if ctx.needs_input_grad[3]:
+            # d tr(Q^{-1} S) / d S on the stored lower band: Sigma_ii, 2 Sigma_ij
+            w = torch.cat([torch.ones(1, dtype=torch.float64, device=g.device),
+                           torch.full((1,), 2.0, dtype=torch.float64, device=g.device)])
+            slot_w = torch.cat([torch.where(torch.arange(k + 1, device=g.device) == 0, w[0], w[1]).repeat(n)
+                                for n, k in zip(plan.ns, plan.ks)])
+            gS = Sig * slot_w * gb
+        return None, gQ, gy, gS
+
+
+def chol(Q):
+    return Chol.apply(Q)
+
+
+def trsv(L, b, trans: int = 0):
+    return Trsv.apply(L, b, trans)
+
+
+def subset_inv(L):
+    return SubsetInv.apply(L)
+
+
+def gbmm(A, B, la, ua, lb, ub, tA=0, tB=0, l=None, u=None):
+    lA, uA = (ua, la) if tA else (la, ua)
+    lB, uB = (ub, lb) if tB else (lb, ub)
+    l = lA + lB if l is None else l
+    u = uA + uB if u is None else u
+    return Gbmm.apply(A, B, la, ua, lb, ub, tA, tB, l, u)
+
+
+def gbmv(A, x, l, u=0, tA=0):
+    return Gbmv.apply(A, x, l, u, tA)
+
+
+def outer_band(m, v, l, u=0):
+    return OuterBand.apply(m, v, l, u)
+
+
+def gauss_loss(plan, Q, y, S):
+    return GaussLoss.apply(plan, Q, y, S)
+
+
+def gauss_loss_composed(Q, y, S):
+    """The same loss for one problem composed from the separate operators
+    (Table 1 compositions through autograd): logdet from C, the quadratic
+    term from S twice, the trace from I."""
+    k = Q.shape[1] - 1
+    L, logdet = chol(Q)
+    z = trsv(L, y, 0)
+    Sig = subset_inv(L)
+    w = torch.full((k + 1,), 2.0, dtype=torch.float64, device=Q.device)
+    w[0] = 1.0
+    return logdet - (z * z).sum() + (Sig * S * w).sum()
