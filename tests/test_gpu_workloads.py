@@ -1,0 +1,268 @@
+"""GPU parity at the workloads' full sizes, through the C ABI, in the launch
+configuration the benchmark uses (one plan over the whole batch, default chunk
+policy).  The oracle checks sampled problems one by one.
+
+Tolerances:
+* well-conditioned inputs (random band factors): FP64 1e-12 relative per
+  output array; the mixed format (FP32 band, FP64 diagonals) 1e-4 relative
+  per output against the FP64 oracle on the original FP64 inputs;
+* Matérn state-space precisions are ill-conditioned for their factors, so an
+  output's floor is set by conditioning, not by the arithmetic.  e_ref is the
+  relative change of the oracle's output when the stored entries of Q are
+  perturbed by one unit in the last place (random signs); the bound is
+  max(1e-12, 10 e_ref)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from bandutil import band_mask, rel_err
+from paper_1902_10078_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+TOL_MIXED = 1e-4
+
+
+@pytest.fixture(scope="module")
+def bo():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1902_10078_amd import bandops
+    bandops.lib()
+    return bandops
+
+
+def dev(a, dtype=torch.float64):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def ulp_perturbed(Q, seed):
+    rng = np.random.default_rng(seed)
+    return Q * (1.0 + np.where(rng.random(Q.shape) < 0.5, -1.0, 1.0) * 2.0 ** -52)
+
+
+def rel(a, b):
+    return abs(a - b) / max(abs(b), 1e-300)
+
+
+def forward_plan(bo, ns, ks, Qs, ys, prec):
+    plan = bo.Plan(ns, ks)
+    vdt = torch.float64 if prec == 0 else torch.float32
+    Qf = np.concatenate([q.ravel() for q in Qs])
+    yf = np.concatenate(ys)
+    Qt, yt = dev(Qf, vdt), dev(yf, vdt)
+    L, Sig = torch.zeros_like(Qt), torch.zeros_like(Qt)
+    z, x = torch.zeros_like(yt), torch.zeros_like(yt)
+    logdet = torch.zeros(len(ns), dtype=torch.float64, device="cuda")
+    info = torch.zeros(len(ns), dtype=torch.int32, device="cuda")
+    kw = dict(Q=Qt, y=yt, L=L, z=z, x=x, Sig=Sig, logdet=logdet, info=info)
+    if prec == 1:
+        N = yt.numel()
+        kw["Qd"] = dev(np.concatenate([q[:, 0] for q in Qs]))
+        for nm in ("Ld", "Sigd"):
+            kw[nm] = torch.zeros(N, dtype=torch.float64, device="cuda")
+    plan.forward(prec, plan.io(**kw))
+    torch.cuda.synchronize()
+    out = {nm: host(t) for nm, t in kw.items() if nm not in ("Q", "y", "Qd")}
+    if prec == 1:   # the FP64 diagonals are authoritative
+        for nm, d in (("L", "Ld"), ("Sig", "Sigd")):
+            for p, (n, k) in enumerate(zip(ns, ks)):
+                o, v = plan.boff[p], plan.voff[p]
+                out[nm][o:o + n * (k + 1)].reshape(n, k + 1)[:, 0] = out[d][v:v + n]
+    return plan, out
+
+
+def oracle_forward(Q, y, k):
+    L, info = oracle.chol(Q, k)
+    assert info == 0
+    z = oracle.trsv(L, k, y, 0)
+    return dict(L=L, z=z, x=oracle.trsv(L, k, z, 1), Sig=oracle.subset_inv(L, k),
+                logdet=oracle.logdet(L, k))
+
+
+def forward_errors(got, ref, n, k):
+    m = band_mask(n, k)
+    e = {nm: rel_err(got[nm] * m, ref[nm]) for nm in ("L", "Sig")}
+    e.update({nm: rel_err(got[nm], ref[nm]) for nm in ("z", "x")})
+    e["logdet"] = rel(got["logdet"], ref["logdet"])
+    return e
+
+
+def mixed_inputs(Q, y):
+    """The inputs as the mixed format stores them: FP32 off-diagonals and
+    vectors, FP64 diagonal."""
+    Qr = Q.astype(np.float32).astype(np.float64)
+    Qr[:, 0] = Q[:, 0]
+    return Qr, y.astype(np.float32).astype(np.float64)
+
+
+def check_forward_problem(plan, out, p, n, k, Q, y, tol, prec=0):
+    """Every forward output of problem p against the FP64 oracle.  In the
+    mixed format the error is also bounded by what storing the inputs in that
+    format costs: the FP64 oracle run on the rounded inputs sets that floor,
+    and the GPU must match that run to 1e-6 (its own arithmetic is FP64)."""
+    o, v = plan.boff[p], plan.voff[p]
+    got = dict(L=out["L"][o:o + n * (k + 1)].reshape(n, k + 1), Sig=out["Sig"][o:o + n * (k + 1)].reshape(n, k + 1),
+               z=out["z"][v:v + n], x=out["x"][v:v + n], logdet=out["logdet"][p])
+    ref = oracle_forward(Q, y, k)
+    errs = forward_errors(got, ref, n, k)
+    floor = {}
+    if prec == 1:
+        refr = oracle_forward(*mixed_inputs(Q, y), k)
+        floor = forward_errors(refr, ref, n, k)
+        arith = forward_errors(got, refr, n, k)
+        for nm, e in arith.items():
+            assert e <= 1e-6, (p, n, k, nm, "vs oracle on the stored inputs", e)
+    for nm, e in errs.items():
+        t = tol[nm] if isinstance(tol, dict) else tol
+        if prec == 1:
+            t = max(t, 2 * floor[nm])
+        assert e <= t, (p, n, k, nm, e, t)
+    return errs, floor
+
+
+def test_single_band_n1000_k3_all_ops(bo):
+    """The single-band workload (n = 1000, k = 3, seed 0) through the
+    single-problem entry points and through a plan (loss unit, S = Q)."""
+    L0, y = inputs.config0(seed=0)
+    n, k = 1000, 3
+    Q = oracle.gbmm(L0, k, 0, L0, k, 0, tB=1, lc=k, uc=0)
+    Qb = bo.band_from(dev(Q), k)
+    L, z, logdet, info = bo.bo_chol(Qb, dev(y))
+    x = bo.bo_trsv(L, z, 1)
+    S = bo.bo_subset_inv(L)
+    torch.cuda.synchronize()
+    Lr, _ = oracle.chol(Q, k)
+    assert int(info.item()) == 0
+    assert rel_err(host(L.band), Lr) <= TOL
+    assert rel_err(host(L.band), L0) <= 1e-12 * 10       # recovers the generating factor
+    zr = oracle.trsv(Lr, k, y, 0)
+    assert rel_err(host(z), zr) <= TOL
+    assert rel_err(host(x), oracle.trsv(Lr, k, zr, 1)) <= TOL
+    assert rel_err(host(S.band), oracle.subset_inv(Lr, k)) <= TOL
+    assert rel(float(logdet.item()), oracle.logdet(Lr, k)) <= TOL
+    plan = bo.Plan([n], [k])
+    kw = dict(Q=dev(Q), y=dev(y), S=dev(Q))
+    E = Q.size
+    for nm in ("L", "Sig", "Lbar", "Qbar"):
+        kw[nm] = torch.zeros(E, dtype=torch.float64, device="cuda")
+    kw["z"] = torch.zeros(n, dtype=torch.float64, device="cuda")
+    kw["x"] = torch.zeros(n, dtype=torch.float64, device="cuda")
+    kw["parts"] = torch.zeros((1, 3), dtype=torch.float64, device="cuda")
+    kw["info"] = torch.zeros(1, dtype=torch.int32, device="cuda")
+    plan.gauss_loss(0, plan.io(**kw))
+    torch.cuda.synchronize()
+    r = oracle.gauss_loss(Q, k, y, Q)
+    for i in range(3):
+        assert rel(host(kw["parts"])[0, i], r["parts"][i]) <= TOL
+    assert rel_err(host(kw["Qbar"]).reshape(n, k + 1), r["Qbar"]) <= TOL
+    assert rel_err(host(kw["x"]), r["ybar"]) <= TOL
+    # tr(Q^{-1} Q) = n
+    assert abs(host(kw["parts"])[0, 2] - n) <= 1e-9 * n
+
+
+@pytest.mark.parametrize("ell,prec", [(10.0, 0), (0.1, 0), (0.1, 1)])
+def test_matern32_single_long_matrix(bo, ell, prec):
+    """Matérn-3/2 state space, 1e5 jittered inputs (N = 2e5, k = 3): Cholesky,
+    logdet, y^T Q^{-1} y (from z), back solve and subset inverse in one plan."""
+    Q, y, m, _ = inputs.config1_inputs(seed=1, n_in=100_000, ell=ell)
+    n, k = Q.shape[0], 3
+    plan, out = forward_plan(bo, [n], [k], [Q], [y], prec)
+    assert int(out["info"][0]) == 0
+    if prec == 0:
+        Qp = ulp_perturbed(Q, 5)
+        Lr, _ = oracle.chol(Q, k)
+        Lp, _ = oracle.chol(Qp, k)
+        zr, zp = oracle.trsv(Lr, k, y, 0), oracle.trsv(Lp, k, y, 0)
+        e = dict(L=rel_err(Lp, Lr), z=rel_err(zp, zr),
+                 x=rel_err(oracle.trsv(Lp, k, zp, 1), oracle.trsv(Lr, k, zr, 1)),
+                 Sig=rel_err(oracle.subset_inv(Lp, k), oracle.subset_inv(Lr, k)),
+                 logdet=rel(oracle.logdet(Lp, k), oracle.logdet(Lr, k)))
+        tol = {nm: max(TOL, 10 * v) for nm, v in e.items()}
+    else:
+        tol = TOL_MIXED
+    errs, floor = check_forward_problem(plan, out, 0, n, k, Q, y, tol, prec)
+    # the quadratic form y^T Q^{-1} y = z^T z, and the closed-form logdet
+    zg = out["z"][:n]
+    zr = oracle.trsv(oracle.chol(Q, k)[0], k, y, 0)
+    assert rel(float(zg @ zg), float(zr @ zr)) <= (max(1e-10, 20 * tol["z"]) if prec == 0
+                                                   else max(TOL_MIXED, 4 * floor["z"]))
+    ld_closed = float(np.sum(np.linalg.slogdet(m.Qinv)[1]))
+    assert rel(out["logdet"][0], ld_closed) <= (1e-9 if prec == 0 else TOL_MIXED)
+    print(f"matern32 ell={ell} prec={prec}: per-output errors vs FP64 oracle {errs}"
+          + (f"; input-rounding floor {floor}" if prec else ""))
+
+
+def test_uneven_batch_4096_forward(bo):
+    """4096 problems, n log-uniform in [256, 65536], k in {1,3,5,11}: the
+    forward list in one plan, FP64 (1e-12) and mixed (1e-4 against the FP64
+    oracle on the FP64 inputs), checked on sampled problems including the
+    longest one and every bandwidth."""
+    ns, ks = inputs.config2_shapes()
+    ns, ks = [int(v) for v in ns], [int(v) for v in ks]
+    Ls, ys = inputs.config2_factors(2, ns, ks)
+    Qs = [oracle.gbmm(L, k, 0, L, k, 0, tB=1, lc=k, uc=0) for L, k in zip(Ls, ks)]
+    rng = np.random.default_rng(7)
+    sample = set(rng.choice(len(ns), size=24, replace=False).tolist())
+    sample.add(int(np.argmax(ns)))
+    sample.add(int(np.argmin(ns)))
+    for kk in (1, 3, 5, 11):
+        sample.add(ks.index(kk))
+    for prec, tol in ((0, TOL), (1, TOL_MIXED)):
+        plan, out = forward_plan(bo, ns, ks, Qs, ys, prec)
+        assert np.all(out["info"] == 0)
+        worst = {}
+        for p in sorted(sample):
+            errs, _ = check_forward_problem(plan, out, p, ns[p], ks[p], Qs[p], ys[p], tol, prec)
+            for nm, e in errs.items():
+                worst[nm] = max(worst.get(nm, 0.0), e)
+        print(f"uneven batch prec={prec}: worst per-output error vs FP64 oracle {worst}")
+
+
+def test_matern52_loss_full_size_sampled(bo):
+    """The loss unit on the 16-problem Matérn-5/2 batch (3e6 rows each), as the
+    benchmark runs it; problems 0 and 15 (shortest and longest lengthscale)
+    against the oracle."""
+    nb = 16
+    Qs, ys, Ss = [], [], []
+    for b in range(nb):
+        Q, y, S, _ = inputs.config3_problem(b)
+        Qs.append(Q)
+        ys.append(y)
+        Ss.append(S)
+    ns, ks = [q.shape[0] for q in Qs], [5] * nb
+    plan = bo.Plan(ns, ks)
+    Qt = dev(np.concatenate([q.ravel() for q in Qs]))
+    E, N = Qt.numel(), sum(ns)
+    kw = dict(Q=Qt, y=dev(np.concatenate(ys)), S=dev(np.concatenate([s.ravel() for s in Ss])))
+    for nm in ("L", "Sig", "Lbar", "Qbar"):
+        kw[nm] = torch.zeros(E, dtype=torch.float64, device="cuda")
+    kw["z"] = torch.zeros(N, dtype=torch.float64, device="cuda")
+    kw["x"] = torch.zeros(N, dtype=torch.float64, device="cuda")
+    kw["parts"] = torch.zeros((nb, 3), dtype=torch.float64, device="cuda")
+    kw["info"] = torch.zeros(nb, dtype=torch.int32, device="cuda")
+    plan.gauss_loss(0, plan.io(**kw))
+    torch.cuda.synchronize()
+    parts, info = host(kw["parts"]), host(kw["info"])
+    assert np.all(info == 0)
+    Qbar, ybar, Lg, Sg = host(kw["Qbar"]), host(kw["x"]), host(kw["L"]), host(kw["Sig"])
+    for b in (0, nb - 1):
+        n, k = ns[b], 5
+        r = oracle.gauss_loss(Qs[b], k, ys[b], Ss[b])
+        rp = oracle.gauss_loss(ulp_perturbed(Qs[b], 11 + b), k, ys[b], Ss[b])
+        o, v = plan.boff[b], plan.voff[b]
+        m = band_mask(n, k)
+        got = dict(L=Lg[o:o + n * (k + 1)].reshape(n, k + 1) * m, Sig=Sg[o:o + n * (k + 1)].reshape(n, k + 1) * m,
+                   Qbar=Qbar[o:o + n * (k + 1)].reshape(n, k + 1) * m, ybar=ybar[v:v + n])
+        for nm, g in got.items():
+            e_ref = rel_err(rp[nm], r[nm])
+            e = rel_err(g, r[nm])
+            assert e <= max(TOL, 10 * e_ref), (b, nm, e, e_ref)
+        for i in range(3):
+            e_ref = rel(rp["parts"][i], r["parts"][i])
+            assert rel(parts[b, i], r["parts"][i]) <= max(TOL, 10 * e_ref), (b, i)
