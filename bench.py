@@ -1,13 +1,22 @@
-"""Benchmark of the banded Gaussian-loss hot path on one MI355X.
+"""Benchmark of the banded Gaussian-model hot path on one MI355X.
 
-One step = one pass of the whole fused forward + backward unit over the batch:
+Default workload (the headline): one step = the fused forward + backward loss
+unit over a batch,
   loss_b = log det Q_b - y_b^T Q_b^{-1} y_b + tr(Q_b^{-1} S_b)   (per problem)
   forward: Cholesky, log-determinant, forward solve, subset inverse;
   backward: Algorithm 4, the solve sensitivity, the log-determinant
-  sensitivity and Algorithm 2 -> dloss/dQ (stored band), dloss/dy.
-Workload (default): 16 Matérn-5/2 state-space precisions (state dimension 3,
-so k = 5) on a regular grid of 10^6 inputs each (N = 3e6 rows per problem),
-lengthscales 1 + b/16, y ~ N(0, I), S a diagonally dominant symmetric band.
+  sensitivity and Algorithm 2 -> dloss/dQ (stored band), dloss/dy,
+on 16 Matérn-5/2 state-space precisions (state dimension 3, so k = 5) on a
+regular grid of 10^6 inputs each (N = 3e6 rows per problem), lengthscales
+1 + b/16, y ~ N(0, I), S a diagonally dominant symmetric band.
+
+Other workloads (--workload):
+  uneven_forward   4096 problems, n log-uniform in [256, 65536], k in
+                   {1,3,5,11}: the forward list (Cholesky, logdet, L^{-1} y,
+                   L^{-T} L^{-1} y, band of Q^{-1}) in one plan, mixed format
+                   by default;
+  matern32_forward one Matérn-3/2 precision of 1e5 jittered inputs (N = 2e5,
+                   k = 3), lengthscale 10: the same forward list, FP64.
 
 Prints ONE JSON line on stdout; diagnostics go to stderr.
 """
@@ -25,18 +34,30 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+METRIC = "band-rows/s fwd+bwd (Cholesky+solve+subset-inverse), % HBM roofline, vs FP64 plain"
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def bytes_per_row(k: int, prec: int):
+def record_bytes(k: int, prec: int):
+    """(w_b, w_v): bytes of one band record and of one vector entry."""
+    return (8 * (k + 1), 8) if prec == 0 else (4 * (k + 1) + 8, 4)
+
+
+def bytes_per_row(k: int, prec: int, forward_only: bool = False):
     """Algorithmic bytes per row of each kernel kind (what the kernel must read
     and write from HBM, nothing re-read).  w_b: one band record, w_v: one
     vector entry."""
-    wb = 8 * (k + 1) if prec == 0 else 4 * (k + 1) + 8
-    wv = 8 if prec == 0 else 4
+    wb, wv = record_bytes(k, prec)
+    if forward_only:
+        return {
+            "f1_summary": wb + wv,            # Q, y
+            "f1_replay": 2 * wb + 2 * wv,     # Q, y -> L, z
+            "f2_replay": 2 * wb + 2 * wv,     # L, z -> Sigma, x
+            "unit": 4 * wb + 4 * wv,          # the forward list's traffic per row
+        }
     return {
         "f1_summary": wb + wv,            # Q, y
         "f1_replay": 2 * wb + 2 * wv,     # Q, y -> L, z
@@ -50,43 +71,26 @@ def bytes_per_row(k: int, prec: int):
     }
 
 
-def make_c3(nbatch: int, n_in: int):
-    from paper_1902_10078_amd import inputs
-    Qs, ys, Ss = [], [], []
-    for b in range(nbatch):
-        Q, y, S, _ = inputs.config3_problem(b, n_in=n_in, nbatch=16)
-        Qs.append(Q)
-        ys.append(y)
-        Ss.append(S)
-    return Qs, ys, Ss, [5] * nbatch
+def batch_bytes(ns, ks, prec, forward_only):
+    """Algorithmic bytes of one step of each kernel kind over the batch."""
+    tot = {}
+    for n, k in zip(ns, ks):
+        for nm, b in bytes_per_row(k, prec, forward_only).items():
+            tot[nm] = tot.get(nm, 0) + b * n
+    return tot
 
 
-def cpu_baseline(Qs, ys, Ss, ks, nsample: int):
-    """The FP64 oracle, OpenMP across problems, on the first nsample problems."""
-    import oracle
-    ns = [q.shape[0] for q in Qs[:nsample]]
-    Qf = np.concatenate([q.ravel() for q in Qs[:nsample]])
-    yf = np.concatenate(ys[:nsample])
-    Sf = np.concatenate([s.ravel() for s in Ss[:nsample]])
-    t0 = time.perf_counter()
-    parts, _, _, info, threads = oracle.gauss_loss_batch(ns, ks[:nsample], Qf, yf, Sf)
-    dt = time.perf_counter() - t0
-    rows = sum(ns)
-    return dict(value=rows / dt, unit="band-rows/s", cores=int(threads), kind="oracle",
-                sample=f"{nsample} of the batch's problems ({rows} rows), FP64 C oracle, "
-                       f"OpenMP across problems, {dt:.2f} s wall"), parts
+def traffic_profile_path(workload: str, prec: str, nbatch: int, n_in: int) -> str:
+    if workload == "matern52_loss":
+        return os.path.join(ROOT, "profiles", f"traffic_matern52_b{nbatch}_nin{n_in}_{prec}.txt")
+    return os.path.join(ROOT, "profiles", f"traffic_{workload}_{prec}.txt")
 
 
-def traffic_profile_path(prec: str, nbatch: int, n_in: int) -> str:
-    return os.path.join(ROOT, "profiles", f"traffic_matern52_b{nbatch}_nin{n_in}_{prec}.txt")
-
-
-def measured_traffic(slot: str, args, rows: int):
+def measured_traffic(slot: str, path: str, rows: int):
     """HBM bytes per launch of `slot` from the committed rocprofv3 counter
     summary of this workload, or None when there is none, it covers another
     workload, or the kernels have changed since it was taken."""
     from paper_1902_10078_amd import profsum
-    path = traffic_profile_path(args.prec, args.batch, args.n_in)
     tr, meta = profsum.read_traffic(path)
     if slot not in tr or meta.get("source_hash") != profsum.source_hash():
         return None
@@ -116,16 +120,153 @@ def copy_probe(torch, mib: int):
                           gbs=2 * nbytes / (ms / 1e3) / 1e9)), flush=True)
 
 
+# ------------------------------------------------------------------ workloads
+
+class Workload:
+    """Inputs resident on the device, a plan over the batch, and the step."""
+
+    def __init__(self, bo, torch, dev, ns, ks, prec, host_inputs, forward_only):
+        self.bo, self.torch, self.dev = bo, torch, dev
+        self.ns, self.ks, self.prec = ns, ks, prec
+        self.forward_only = forward_only
+        vdt = torch.float64 if prec == bo.F64 else torch.float32
+        Qs, ys, Ss = host_inputs
+
+        def upload(arrs, dt):
+            return torch.from_numpy(np.concatenate([a.ravel() for a in arrs])).to(dev, dt)
+
+        def diag(arrs):
+            return torch.from_numpy(np.concatenate([a[:, 0] for a in arrs])).to(dev)
+
+        Qt, yt = upload(Qs, vdt), upload(ys, vdt)
+        E, N = Qt.numel(), yt.numel()
+        nprob = len(ns)
+        kw = dict(Q=Qt, y=yt, z=torch.zeros(N, dtype=vdt, device=dev), x=torch.zeros(N, dtype=vdt, device=dev),
+                  info=torch.zeros(nprob, dtype=torch.int32, device=dev))
+        names = ("L", "Sig") if forward_only else ("L", "Sig", "Lbar", "Qbar")
+        for nm in names:
+            kw[nm] = torch.zeros(E, dtype=vdt, device=dev)
+        if forward_only:
+            kw["logdet"] = torch.zeros(nprob, dtype=torch.float64, device=dev)
+        else:
+            kw["S"] = upload(Ss, vdt)
+            kw["parts"] = torch.zeros((nprob, 3), dtype=torch.float64, device=dev)
+        if prec == bo.MIXED:
+            kw["Qd"] = diag(Qs)
+            if not forward_only:
+                kw["Sd"] = diag(Ss)
+            for nm in names:
+                kw[nm + "d"] = torch.zeros(N, dtype=torch.float64, device=dev)
+        self.kw = kw
+        self.plan = bo.Plan(ns, ks, device=dev)
+        self.io = self.plan.io(**kw)
+
+    def step(self):
+        if self.forward_only:
+            self.plan.forward(self.prec, self.io)
+        else:
+            self.plan.gauss_loss(self.prec, self.io)
+
+    def plain_steps(self):
+        """The plain FP64 form: one plan per matrix, launched from a host loop,
+        no graph (on the FP64 inputs)."""
+        bo = self.bo
+        out = []
+        for p in range(len(self.ns)):
+            n, k = self.ns[p], self.ks[p]
+            pl = bo.Plan([n], [k], device=self.dev)
+            o, v, sz = self.plan.boff[p], self.plan.voff[p], n * (k + 1)
+            kw = {}
+            for nm, t in self.kw.items():
+                if nm == "parts":
+                    kw[nm] = t[p]
+                elif nm in ("info", "logdet"):
+                    kw[nm] = t[p:p + 1]
+                elif nm in ("y", "z", "x") or nm.endswith("d"):
+                    kw[nm] = t[v:v + n]
+                else:
+                    kw[nm] = t[o:o + sz]
+            out.append((pl, pl.io(**kw)))
+
+        def run():
+            for pl, pio in out:
+                if self.forward_only:
+                    pl.forward(bo.F64, pio)
+                else:
+                    pl.gauss_loss(bo.F64, pio)
+        return run
+
+
+def make_matern52(args):
+    from paper_1902_10078_amd import inputs
+    Qs, ys, Ss = [], [], []
+    for b in range(args.batch):
+        Q, y, S, _ = inputs.config3_problem(b, n_in=args.n_in, nbatch=16)
+        Qs.append(Q)
+        ys.append(y)
+        Ss.append(S)
+    return [q.shape[0] for q in Qs], [5] * args.batch, (Qs, ys, Ss)
+
+
+def make_uneven(args, bo, torch, dev):
+    """The uneven batch; Q_b = band(L_b L_b^T) is formed on the device with
+    the library's banded product (input construction, untimed)."""
+    from paper_1902_10078_amd import inputs
+    ns, ks = inputs.config2_shapes(nprob=args.nprob)
+    ns, ks = [int(v) for v in ns], [int(v) for v in ks]
+    Ls, ys = inputs.config2_factors(2, ns, ks)
+    Qs = []
+    for L, k in zip(Ls, ks):
+        Lb = bo.band_from(torch.from_numpy(L).to(dev), k)
+        Qs.append(bo.bo_gbmm(Lb, Lb, 0, 1, k, 0).band.cpu().numpy())
+    return ns, ks, (Qs, ys, None)
+
+
+def make_matern32(args):
+    from paper_1902_10078_amd import inputs
+    Q, y, _, _ = inputs.config1_inputs(seed=1, n_in=args.n_in32, ell=args.ell)
+    return [Q.shape[0]], [3], ([Q], [y], None)
+
+
+def cpu_baseline(host_inputs, ns, ks, nsample: int):
+    """The FP64 oracle as it stands, OpenMP across problems, on a bounded
+    sample of the workload's problems."""
+    import oracle
+    Qs, ys, Ss = host_inputs
+    idx = list(range(min(nsample, len(ns))))
+    sn, sk = [ns[i] for i in idx], [ks[i] for i in idx]
+    Qf = np.concatenate([Qs[i].ravel() for i in idx])
+    yf = np.concatenate([ys[i] for i in idx])
+    t0 = time.perf_counter()
+    if Ss is not None:
+        Sf = np.concatenate([Ss[i].ravel() for i in idx])
+        ref, _, _, _, threads = oracle.gauss_loss_batch(sn, sk, Qf, yf, Sf)
+    else:
+        _, _, _, _, ref, _, threads = oracle.forward_batch(sn, sk, Qf, yf)
+    dt = time.perf_counter() - t0
+    rows = sum(sn)
+    return dict(value=rows / dt, unit="band-rows/s", cores=int(threads), kind="oracle",
+                sample=f"{len(idx)} of the workload's {len(ns)} problems ({rows} rows), FP64 C oracle, "
+                       f"OpenMP across problems, {dt:.2f} s wall"), ref
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--prec", choices=["f64", "mixed"], default="f64")
+    ap.add_argument("--workload", choices=["matern52_loss", "uneven_forward", "matern32_forward"],
+                    default="matern52_loss")
+    ap.add_argument("--prec", choices=["f64", "mixed"], default=None,
+                    help="storage format (default: f64; mixed for uneven_forward)")
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--n-in", type=int, default=1_000_000)
-    ap.add_argument("--target-chunks", type=int, default=0)
-    ap.add_argument("--cpu-sample", type=int, default=8)
+    ap.add_argument("--nprob", type=int, default=4096)
+    ap.add_argument("--n-in32", type=int, default=100_000)
+    ap.add_argument("--ell", type=float, default=10.0)
+    ap.add_argument("--cpu-sample", type=int, default=0,
+                    help="problems timed on the CPU oracle (default: 8 for the loss batch, "
+                         "256 for the uneven batch, 1 otherwise)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
@@ -145,44 +286,37 @@ def main():
         return
     from paper_1902_10078_amd import bandops as bo
 
+    if args.prec is None:
+        args.prec = "mixed" if args.workload == "uneven_forward" else "f64"
     prec = bo.F64 if args.prec == "f64" else bo.MIXED
-    t0 = time.perf_counter()
-    Qs, ys, Ss, ks = make_c3(args.batch, args.n_in)
-    log(f"inputs: {len(Qs)} problems x {Qs[0].shape[0]} rows, k=5 ({time.perf_counter() - t0:.1f} s)")
-    ns = [q.shape[0] for q in Qs]
-    rows = sum(ns)
-
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    vdt = torch.float64 if prec == bo.F64 else torch.float32
 
-    def upload(arrs, dt):
-        return torch.from_numpy(np.concatenate([a.ravel() for a in arrs])).to(dev, dt)
+    t0 = time.perf_counter()
+    forward_only = args.workload != "matern52_loss"
+    if args.workload == "matern52_loss":
+        ns, ks, host_inputs = make_matern52(args)
+        cfg = {"workload": f"matern52_ssm_batch{len(ns)}_rows{ns[0]}_k5_gauss_loss_fwd_bwd",
+               "batch": len(ns), "rows_per_problem": ns[0], "k": 5}
+        nsample = args.cpu_sample or 8
+    elif args.workload == "uneven_forward":
+        ns, ks, host_inputs = make_uneven(args, bo, torch, dev)
+        cfg = {"workload": f"uneven_batch{len(ns)}_n256-65536_k1-3-5-11_forward",
+               "batch": len(ns), "rows": sum(ns), "k": "1,3,5,11"}
+        nsample = args.cpu_sample or 256
+    else:
+        ns, ks, host_inputs = make_matern32(args)
+        cfg = {"workload": f"matern32_ssm_rows{ns[0]}_k3_ell{args.ell:g}_forward",
+               "batch": 1, "rows_per_problem": ns[0], "k": 3}
+        nsample = args.cpu_sample or 1
+    rows = sum(ns)
+    log(f"inputs: {len(ns)} problems, {rows} rows ({time.perf_counter() - t0:.1f} s)")
 
-    Qt = upload(Qs, vdt)
-    St = upload(Ss, vdt)
-    yt = upload(ys, vdt)
-    E, N = Qt.numel(), yt.numel()
-    bufs = {nm: torch.zeros(E, dtype=vdt, device=dev) for nm in ("L", "Sig", "Lbar", "Qbar")}
-    z = torch.zeros(N, dtype=vdt, device=dev)
-    ybar = torch.zeros(N, dtype=vdt, device=dev)
-    parts = torch.zeros((len(ns), 3), dtype=torch.float64, device=dev)
-    info = torch.zeros(len(ns), dtype=torch.int32, device=dev)
-    kw = dict(Q=Qt, y=yt, S=St, z=z, x=ybar, parts=parts, info=info, **bufs)
-    if prec == bo.MIXED:
-        diag = lambda arrs: torch.from_numpy(np.concatenate([a[:, 0] for a in arrs])).to(dev)
-        kw.update(Qd=diag(Qs), Sd=diag(Ss),
-                  **{nm: torch.zeros(N, dtype=torch.float64, device=dev)
-                     for nm in ("Ld", "Sigd", "Lbard", "Qbard")})
-    plan = bo.Plan(ns, ks, target_chunks=args.target_chunks, device=dev)
-    io = plan.io(**kw)
-    log(f"plan: {plan.stats}, workspace {plan.ws.numel() / 2**20:.1f} MiB")
-
-    def step():
-        plan.gauss_loss(prec, io)
-
+    W = Workload(bo, torch, dev, ns, ks, prec, host_inputs, forward_only)
+    log(f"plan: {W.plan.stats}, workspace {W.plan.ws.numel() / 2**20:.1f} MiB")
+    info = W.kw["info"]
     for _ in range(max(args.warmup, 1)):
-        step()
+        W.step()
     torch.cuda.synchronize()
     assert int(info.max().item()) == 0, "Cholesky failed on the benchmark inputs"
 
@@ -193,13 +327,13 @@ def main():
         g = torch.cuda.CUDAGraph()
         with torch.cuda.stream(s):
             with torch.cuda.graph(g, stream=s):
-                step()
+                W.step()
         torch.cuda.current_stream().wait_stream(s)
         run = g.replay
         run()
         torch.cuda.synchronize()
     else:
-        run = step
+        run = W.step
 
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -217,26 +351,27 @@ def main():
     bo.profile_enable(True)
     nprof = 3
     for _ in range(nprof):
-        step()
+        W.step()
     prof = bo.profile_read()
     bo.profile_enable(False)
-    bpr = bytes_per_row(5, prec)
+    bb = batch_bytes(ns, ks, prec, forward_only)
     kern = {}
     for name, (tms, cnt) in prof.items():
-        avg = tms / cnt
-        entry = dict(avg_ms=avg, launches_per_step=cnt / nprof)
-        if name in bpr:
-            entry["alg_bytes_per_launch"] = bpr[name] * rows
-            entry["gbs"] = bpr[name] * rows / (avg / 1e3) / 1e9
+        entry = dict(avg_ms=tms / cnt, launches_per_step=cnt / nprof, ms_per_step=tms / nprof)
+        if name in bb:
+            entry["alg_bytes_per_step"] = bb[name]
+            entry["gbs"] = bb[name] / (tms / nprof / 1e3) / 1e9
         kern[name] = entry
-        log(f"  {name:20s} {avg:8.3f} ms x{cnt / nprof:.0f}"
+        log(f"  {name:20s} {tms / nprof:8.3f} ms/step x{cnt / nprof:.0f}"
             + (f"  {entry['gbs']:8.1f} GB/s" if "gbs" in entry else ""))
-    dom = max((k_ for k_ in kern if "gbs" in kern[k_]), key=lambda k_: kern[k_]["avg_ms"])
+    dom = max((k_ for k_ in kern if "gbs" in kern[k_]), key=lambda k_: kern[k_]["ms_per_step"])
     d = kern[dom]
+    path = traffic_profile_path(args.workload, args.prec, args.batch, args.n_in)
     roof = dict(bound="hbm", kernel=dom, achieved=round(d["gbs"], 2), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(d["gbs"] / HBM_PEAK_GBS, 4), traffic=measured_traffic(dom, args, rows),
-                bytes_per_row=bpr[dom], rows_per_launch=rows)
-    unit_gbs = bpr["unit"] * rows / (ms / 1e3) / 1e9
+                frac=round(d["gbs"] / HBM_PEAK_GBS, 4),
+                traffic=measured_traffic(dom, path, rows) if d["launches_per_step"] == 1 else None,
+                bytes_per_step=bb[dom], launches_per_step=d["launches_per_step"], rows=rows)
+    unit_gbs = bb["unit"] / (ms / 1e3) / 1e9
     if args.kernels_json:
         with open(args.kernels_json, "w") as f:
             json.dump(dict(kernels=kern, ms_per_step=ms, rows=rows), f, indent=1)
@@ -244,41 +379,23 @@ def main():
     # the plain FP64 one-matrix-per-launch form: per-problem plans, host loop, no graph
     vs_plain = None
     if not args.no_plain:
-        plains = []
-        for p in range(len(ns)):
-            pl = bo.Plan([ns[p]], [5], device=dev)
-            o, v, sz = plan.boff[p], plan.voff[p], ns[p] * 6
-            sl = lambda t, a, b_: t[a:a + b_]
-            kw64 = {}
-            for nm, t in kw.items():
-                if nm in ("parts",):
-                    kw64[nm] = t[p]
-                elif nm == "info":
-                    kw64[nm] = t[p:p + 1]
-                elif nm in ("Qd", "Sd", "Ld", "Sigd", "Lbard", "Qbard", "y", "z", "x"):
-                    kw64[nm] = sl(t, v, ns[p])
-                else:
-                    kw64[nm] = sl(t, o, sz)
-            plains.append((pl, pl.io(**kw64)))
-
-        def plain_step():
-            for pl, pio in plains:
-                pl.gauss_loss(prec, pio)
-
-        if prec == bo.F64:
+        W64 = W if prec == bo.F64 else Workload(bo, torch, dev, ns, ks, bo.F64, host_inputs, forward_only)
+        plain_step = W64.plain_steps()
+        plain_step()
+        torch.cuda.synchronize()
+        reps = max(args.steps // 4, 2)
+        e0.record()
+        for _ in range(reps):
             plain_step()
-            torch.cuda.synchronize()
-            e0.record()
-            for _ in range(max(args.steps // 4, 2)):
-                plain_step()
-            e1.record()
-            torch.cuda.synchronize()
-            ms_plain = e0.elapsed_time(e1) / max(args.steps // 4, 2)
-            vs_plain = ms_plain / ms
-            log(f"plain FP64 one-matrix-per-launch: {ms_plain:.3f} ms/step -> batched is {vs_plain:.2f}x")
+        e1.record()
+        torch.cuda.synchronize()
+        ms_plain = e0.elapsed_time(e1) / reps
+        vs_plain = ms_plain / ms
+        log(f"plain FP64 one-matrix-per-launch: {ms_plain:.3f} ms/step -> batched is {vs_plain:.2f}x")
 
+    cfg.update(storage=args.prec, graph=use_graph, chunks=W.plan.stats["nchunk"])
     out = {
-        "metric": "band-rows/s fwd+bwd (Cholesky+solve+subset-inverse), % HBM roofline, vs FP64 plain",
+        "metric": METRIC,
         "value": value,
         "unit": "band-rows/s",
         "n_gpus": 1,
@@ -288,19 +405,18 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == bo.F64 else "f64 (f32 band storage, f64 diagonals)",
+        "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"matern52_ssm_batch{len(ns)}_rows{ns[0]}_k5_gauss_loss_fwd_bwd",
-                   "batch": len(ns), "rows_per_problem": ns[0], "k": 5,
-                   "storage": args.prec, "graph": use_graph, "chunks": plan.stats["nchunk"]},
+        "config": cfg,
         "roofline": roof,
         "unit_hbm_frac": round(unit_gbs / HBM_PEAK_GBS, 4),
         "vs_fp64_plain": vs_plain,
     }
     if not args.no_cpu:
-        cb, cparts = cpu_baseline(Qs, ys, Ss, ks, min(args.cpu_sample, len(Qs)))
-        gp = parts.cpu().numpy()[: len(cparts)]
-        cb["max_rel_diff_loss_parts_vs_gpu"] = float(np.max(np.abs(gp - cparts) / np.abs(cparts)))
+        cb, ref = cpu_baseline(host_inputs, ns, ks, nsample)
+        src = W.kw["logdet"] if forward_only else W.kw["parts"]
+        gp = src.cpu().numpy()[: len(ref)]
+        cb["max_rel_diff_vs_gpu"] = float(np.max(np.abs(gp - ref) / np.maximum(np.abs(ref), 1e-300)))
         out["cpu_baseline"] = cb
         log(f"cpu baseline: {cb}")
     print(json.dumps(out), flush=True)

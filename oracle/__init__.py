@@ -220,3 +220,20 @@ def gauss_loss_batch(ns, ks, Q, y, S):
     th = _load().or_gauss_loss_batch(len(ns), _p(ns), _p(ks), _p(boff), _p(voff), _p(Q), _p(y),
                                      _p(S), _p(parts), _p(Qbar), _p(ybar), _p(info))
     return parts, Qbar, ybar, info, int(th)
+
+
+def forward_batch(ns, ks, Q, y):
+    """Packed batch forward list (Cholesky, logdet, L^{-1} y, L^{-T} L^{-1} y,
+    band of Q^{-1}), OpenMP across problems.  Returns (L, z, x, Sig, logdet,
+    info, threads)."""
+    ns, ks, voff = _batch_tables(ns, ks)
+    Q, y = _f64(Q), _f64(y)
+    boff = np.zeros(len(ns), dtype=np.int64)
+    boff[1:] = np.cumsum(ns * (ks.astype(np.int64) + 1))[:-1]
+    L, Sig = np.zeros_like(Q), np.zeros_like(Q)
+    z, x = np.zeros_like(y), np.zeros_like(y)
+    logdet = np.zeros(len(ns))
+    info = np.zeros(len(ns), dtype=np.int32)
+    th = _load().or_forward_batch(len(ns), _p(ns), _p(ks), _p(boff), _p(voff), _p(Q), _p(y), _p(L),
+                                  _p(z), _p(x), _p(Sig), _p(logdet), _p(info))
+    return L, z, x, Sig, logdet, info, int(th)

@@ -98,7 +98,11 @@ inline bool build_sched(const ProbIn *in, int nprob, int64_t target_chunks, int6
     d.clen = p.n > 0 ? chunk_len_for(p.n, p.k, s.rows, target_chunks, min_len, G) : 1;
     d.nchunk = p.n > 0 ? (int32_t)((p.n + d.clen - 1) / d.clen) : 0;
     d.chunk0 = c;
-    d.ngroup = (d.nchunk + G - 1) / G;
+    // Two-level scan: about sqrt(nchunk) chunks per group balances the serial
+    // work of a group's composition against that of the problem's group sweep.
+    d.gsize = 1;
+    while (d.gsize < G && (int64_t)d.gsize * d.gsize < d.nchunk) d.gsize *= 2;
+    d.ngroup = (d.nchunk + d.gsize - 1) / d.gsize;
     d.group0 = g;
     for (int32_t t = 0; t < d.nchunk; ++t) s.chunk_prob.push_back(ii);
     for (int32_t t = 0; t < d.ngroup; ++t) s.group_prob.push_back(ii);

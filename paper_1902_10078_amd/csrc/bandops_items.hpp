@@ -13,7 +13,8 @@ namespace bo {
 // One banded problem of a batch.  Chunks of a problem are consecutive global
 // chunk ids [chunk0, chunk0 + nchunk); chunk c covers rows
 // [(c - chunk0) * clen, min(... + clen, n)).  Groups of G consecutive chunks
-// are consecutive global group ids [group0, group0 + ngroup).
+// are consecutive global group ids [group0, group0 + ngroup); G = gsize is
+// chosen per problem.
 struct ProbDesc {
   int64_t n;
   int64_t boff;   // element offset of record 0 in every band array
@@ -23,7 +24,7 @@ struct ProbDesc {
   int32_t chunk0, nchunk;
   int32_t group0, ngroup;
   int32_t orig;   // index of the problem in the caller's order
-  int32_t pad_;
+  int32_t gsize;  // chunks per group of this problem
 };
 
 // Kernel arguments (passed by value to every kernel).
@@ -34,7 +35,7 @@ struct Args {
   const int32_t *group_prob;  // group id -> problem id (batched)
   ProbDesc one;
   int32_t c_beg, g_beg, p_beg;  // first chunk / group / problem of this launch
-  int32_t G;                    // chunks per group
+  int32_t G;                    // largest chunks per group (each problem has its own, gsize)
   // workspace slot strides (words)
   int32_t sw_f1map, sw_f1st, sw_mat, sw_lin;
   // ---- data (typed by the item's storage type T)
@@ -72,7 +73,8 @@ BO_HD void chunk_rows(const ProbDesc &pd, int32_t c, int64_t &a, int64_t &b) {
   a = (int64_t)(c - pd.chunk0) * pd.clen;
   b = a + pd.clen < pd.n ? a + pd.clen : pd.n;
 }
-BO_HD void group_chunks(const ProbDesc &pd, int32_t g, int32_t G, int32_t &c0, int32_t &c1) {
+BO_HD void group_chunks(const ProbDesc &pd, int32_t g, int32_t &c0, int32_t &c1) {
+  const int32_t G = pd.gsize;
   c0 = pd.chunk0 + (g - pd.group0) * G;
   int32_t e = pd.chunk0 + pd.nchunk;
   c1 = c0 + G < e ? c0 + G : e;
@@ -110,7 +112,7 @@ template <int K> struct F1GroupCompose {
     const ProbDesc &pd = prob_at(A, prob_of_group(A, g));
     if (g == pd.group0 + pd.ngroup - 1) return;   // the last group's map is never applied
     int32_t c0, c1;
-    group_chunks(pd, g, A.G, c0, c1);
+    group_chunks(pd, g, c0, c1);
     F1Map<K> acc, m, t;
     f1_load_map<K>(A.f1map + (int64_t)c0 * A.sw_f1map, acc);
     for (int32_t c = c0 + 1; c < c1; ++c) {
@@ -145,7 +147,7 @@ template <int K> struct F1ChunkSweep {
     int32_t g = A.g_beg + (int32_t)i;
     const ProbDesc &pd = prob_at(A, prob_of_group(A, g));
     int32_t c0, c1;
-    group_chunks(pd, g, A.G, c0, c1);
+    group_chunks(pd, g, c0, c1);
     F1State<K> s, t;
     f1_load_state<K>(A.f1gst + (int64_t)g * A.sw_f1st, s);
     for (int32_t c = c0; c < c1; ++c) {
@@ -263,7 +265,7 @@ template <int K, bool DESC> struct LinGroupCompose {
     int32_t g = A.g_beg + (int32_t)i;
     const ProbDesc &pd = prob_at(A, prob_of_group(A, g));
     int32_t c0, c1;
-    group_chunks(pd, g, A.G, c0, c1);
+    group_chunks(pd, g, c0, c1);
     double Gp[K1][K1], P[K1][K1];
     LinMap<K> acc, m;
     lin_zero<K>(acc);
@@ -309,7 +311,7 @@ template <int K, bool DESC> struct LinChunkSweep {
     int32_t g = A.g_beg + (int32_t)i;
     const ProbDesc &pd = prob_at(A, prob_of_group(A, g));
     int32_t c0, c1;
-    group_chunks(pd, g, A.G, c0, c1);
+    group_chunks(pd, g, c0, c1);
     LinMap<K> s, m;
     double P[K1][K1];
     lin_load<K>(A.lgst + (int64_t)g * A.sw_lin, s);
