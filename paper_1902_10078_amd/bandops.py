@@ -75,6 +75,10 @@ def lib():
         "bo_plan_gauss_loss": (_I32, [_P, _I32, ctypes.POINTER(_BatchIO), _P, _P]),
         "bo_plan_stats": (_I32, [_P, ctypes.POINTER(_I64)]),
         "bo_plan_destroy": (_I32, [_P]),
+        "bo_wide_workspace_size": (_I32, [ctypes.POINTER(_Problem), _I32, ctypes.POINTER(ctypes.c_size_t)]),
+        "bo_wide_upload": (_I32, [ctypes.POINTER(_Problem), _I32, _P, ctypes.c_size_t]),
+        "bo_wide_forward": (_I32, [_I32, ctypes.POINTER(_BatchIO), _P, _P]),
+        "bo_wide_gauss_loss": (_I32, [_I32, ctypes.POINTER(_BatchIO), _P, _P]),
         "bo_profile_enable": (_I32, [_I32]),
         "bo_profile_read": (_I32, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64), _I32]),
         "bo_profile_slots": (_I32, []),
@@ -93,7 +97,8 @@ def lib():
 EXPORTED = ("bo_workspace_size", "bo_chol", "bo_trsv", "bo_subset_inv", "bo_gbmm", "bo_gbmv",
             "bo_outer_band", "bo_chol_bwd", "bo_subset_inv_bwd", "bo_trsv_bwd", "bo_logdet_bwd",
             "bo_plan_create", "bo_plan_workspace_size", "bo_plan_upload", "bo_plan_forward",
-            "bo_plan_gauss_loss", "bo_plan_stats", "bo_plan_destroy", "bo_profile_enable",
+            "bo_plan_gauss_loss", "bo_plan_stats", "bo_plan_destroy", "bo_wide_workspace_size",
+            "bo_wide_upload", "bo_wide_forward", "bo_wide_gauss_loss", "bo_profile_enable",
             "bo_profile_read", "bo_profile_slots", "bo_profile_slot_name", "bo_status_string",
             "bo_last_error")
 
@@ -359,3 +364,42 @@ class Plan:
     def gauss_loss(self, prec: int, io: _BatchIO):
         _check(lib().bo_plan_gauss_loss(self.h, prec, ctypes.byref(io), _ptr(self.ws), _stream()),
                "bo_plan_gauss_loss")
+
+
+class WidePlan:
+    """Batched wide block-banded problems (k = 64, mixed storage): packed
+    records of 65 FP32 values (problem p's follow problem p-1's), packed FP64
+    diagonals and vectors."""
+
+    K = 64
+
+    def __init__(self, ns, device="cuda"):
+        self.ns = [int(v) for v in ns]
+        self.nprob = len(self.ns)
+        probs = (_Problem * self.nprob)()
+        boff = voff = 0
+        self.boff, self.voff = [], []
+        for i, n in enumerate(self.ns):
+            probs[i] = _Problem(n, self.K, 0, boff, voff)
+            self.boff.append(boff)
+            self.voff.append(voff)
+            boff += n * (self.K + 1)
+            voff += n
+        self.band_elems, self.rows = boff, voff
+        sz = ctypes.c_size_t()
+        _check(lib().bo_wide_workspace_size(probs, self.nprob, ctypes.byref(sz)), "bo_wide_workspace_size")
+        self.ws = torch.empty(max(sz.value, 256), dtype=torch.uint8, device=device)
+        _check(lib().bo_wide_upload(probs, self.nprob, _ptr(self.ws), self.ws.numel()), "bo_wide_upload")
+
+    def io(self, **arrays) -> _BatchIO:
+        io = _BatchIO()
+        for k_, v in arrays.items():
+            setattr(io, k_, _ptr(v))
+        return io
+
+    def forward(self, io: _BatchIO):
+        _check(lib().bo_wide_forward(self.nprob, ctypes.byref(io), _ptr(self.ws), _stream()), "bo_wide_forward")
+
+    def gauss_loss(self, io: _BatchIO):
+        _check(lib().bo_wide_gauss_loss(self.nprob, ctypes.byref(io), _ptr(self.ws), _stream()),
+               "bo_wide_gauss_loss")

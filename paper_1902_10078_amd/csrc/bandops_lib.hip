@@ -22,6 +22,9 @@ static bo_status fail(bo_status st, const std::string &msg) {
   return st;
 }
 
+// Shared with the other translation units of the library (C++ linkage).
+bo_status bo_set_error(bo_status st, const std::string &msg) { return fail(st, msg); }
+
 extern "C" const char *bo_last_error(void) { return g_err.c_str(); }
 
 extern "C" const char *bo_status_string(int s) {

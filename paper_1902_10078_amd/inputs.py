@@ -252,6 +252,16 @@ def config3_problem(b: int, seed: int = 3, n_in: int = 1_000_000, h: float = 0.1
     return Q, y, S, m
 
 
+def config4_factors(b: int, seed: int = 4, n: int = 200_000, k: int = 64):
+    """Problem b of the wide block-banded workload: B lower-banded with k+1
+    diagonals (main included), entries N(0, 1/k); D diagonal U[1, 2].  The
+    precision is Q = D + band_k(B B^T), formed by the caller."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, b]))
+    B = _zero_pads(rng.normal(scale=1.0 / math.sqrt(k), size=(n, k + 1)))
+    D = rng.uniform(1.0, 2.0, size=n)
+    return B, D
+
+
 def to_mixed(B: np.ndarray):
     """Split a band into the mixed-precision storage: FP32 band (diagonal slot
     kept too, as an FP32 copy) plus the FP64 diagonal side array."""

@@ -1,0 +1,126 @@
+"""The wide block-banded path (k = 64, 64 x 64 blocks on the matrix cores in
+FP32, FP64 pivots and log-determinant) against the FP64 oracle's scalar band
+recurrences on the same inputs, through the C ABI.
+
+Inputs: B lower-banded with 65 diagonals, entries N(0, 1/64); D diagonal
+U[1, 2]; Q = D + band(B B^T) (bandwidth exactly 64, well conditioned), and W
+built the same way from another seed.  Both are stored in the mixed format
+(FP32 off-diagonals, FP64 diagonal); the oracle runs on the same stored values.
+Tolerance: 1e-4 relative per output array (FP32 block products)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from bandutil import band_mask, rel_err
+from paper_1902_10078_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+K = 64
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def bo():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1902_10078_amd import bandops
+    bandops.lib()
+    return bandops
+
+
+def wide_matrix(b, seed, n):
+    B, D = inputs.config4_factors(b, seed=seed, n=n)
+    Q = oracle.gbmm(B, K, 0, B, K, 0, tB=1, lc=K, uc=0)
+    Q[:, 0] += D
+    Qr = Q.astype(np.float32).astype(np.float64)   # the stored (mixed) values
+    Qr[:, 0] = Q[:, 0]
+    return Qr
+
+
+def run_wide(bo, ns, Qs, Ws, loss=True):
+    plan = bo.WidePlan(ns)
+    cat = lambda arrs: np.concatenate([a.ravel() for a in arrs])
+    f32 = lambda a: torch.tensor(cat(a), dtype=torch.float32, device="cuda")
+    f64 = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")
+    E, N = plan.band_elems, plan.rows
+    kw = dict(Q=f32(Qs), Qd=f64(np.concatenate([q[:, 0] for q in Qs])),
+              info=torch.zeros(len(ns), dtype=torch.int32, device="cuda"),
+              parts=torch.zeros((len(ns), 3), dtype=torch.float64, device="cuda"))
+    names = ("L", "Sig", "Lbar", "Qbar") if loss else ("L", "Sig")
+    for nm in names:
+        kw[nm] = torch.full((E,), float("nan"), dtype=torch.float32, device="cuda")
+        kw[nm + "d"] = torch.full((N,), float("nan"), dtype=torch.float64, device="cuda")
+    if loss:
+        kw["S"] = f32(Ws)
+        kw["Sd"] = f64(np.concatenate([w[:, 0] for w in Ws]))
+        plan.gauss_loss(plan.io(**kw))
+    else:
+        plan.forward(plan.io(**kw))
+    torch.cuda.synchronize()
+    out = {}
+    for nm in names:
+        band = kw[nm].cpu().numpy().astype(np.float64)
+        diag = kw[nm + "d"].cpu().numpy()
+        per = []
+        for p, n in enumerate(ns):
+            Bp = band[plan.boff[p]:plan.boff[p] + n * (K + 1)].reshape(n, K + 1).copy()
+            Bp[:, 0] = diag[plan.voff[p]:plan.voff[p] + n]
+            per.append(Bp)
+        out[nm] = per
+    out["parts"] = kw["parts"].cpu().numpy()
+    out["info"] = kw["info"].cpu().numpy()
+    return out
+
+
+@pytest.mark.parametrize("ns", [[461, 64, 1, 130], [2000], [127, 129]])
+def test_wide_loss_vs_oracle(bo, ns):
+    Qs = [wide_matrix(p, 4, n) for p, n in enumerate(ns)]
+    Ws = [wide_matrix(p, 5, n) for p, n in enumerate(ns)]
+    out = run_wide(bo, ns, Qs, Ws)
+    assert np.all(out["info"] == 0)
+    for p, n in enumerate(ns):
+        r = oracle.gauss_loss(Qs[p], K, np.zeros(n), Ws[p])
+        m = band_mask(n, K)
+        errs = {}
+        errs["L"] = rel_err(out["L"][p] * m, r["L"])
+        errs["Sig"] = rel_err(out["Sig"][p] * m, r["Sig"])
+        errs["Qbar"] = rel_err(out["Qbar"][p] * m, r["Qbar"])
+        # the oracle's Lbar also holds the log-determinant term 2 / L_ii
+        Lb = out["Lbar"][p].copy()
+        Lb[:, 0] += 2.0 / r["L"][:, 0]
+        errs["Lbar"] = rel_err(Lb * m, r["Lbar"])
+        for i, nm in ((0, "logdet"), (2, "trace")):
+            errs[nm] = abs(out["parts"][p, i] - r["parts"][i]) / max(abs(r["parts"][i]), 1e-300)
+        print(f"n={n}: per-output relative errors {errs}")
+        for nm, e in errs.items():
+            assert e <= TOL, (n, nm, e)
+        # pads are written as zeros
+        for nm in ("L", "Sig", "Lbar", "Qbar"):
+            assert np.all(out[nm][p][m == 0] == 0.0), nm
+
+
+def test_wide_forward_vs_oracle(bo):
+    ns = [300, 1000]
+    Qs = [wide_matrix(p, 6, n) for p, n in enumerate(ns)]
+    out = run_wide(bo, ns, Qs, None, loss=False)
+    assert np.all(out["info"] == 0)
+    for p, n in enumerate(ns):
+        Lr, _ = oracle.chol(Qs[p], K)
+        m = band_mask(n, K)
+        assert rel_err(out["L"][p] * m, Lr) <= TOL
+        assert rel_err(out["Sig"][p] * m, oracle.subset_inv(Lr, K)) <= TOL
+        ld = oracle.logdet(Lr, K)
+        assert abs(out["parts"][p, 0] - ld) <= TOL * abs(ld)
+
+
+def test_wide_non_spd_isolated(bo):
+    ns = [500, 400]
+    Qs = [wide_matrix(p, 7, n) for p, n in enumerate(ns)]
+    Qbad = [q.copy() for q in Qs]
+    Qbad[0][300, 0] = -1.0
+    out = run_wide(bo, ns, Qbad, None, loss=False)
+    assert out["info"][0] == 301
+    assert out["info"][1] == 0
+    good = run_wide(bo, ns, Qs, None, loss=False)
+    assert np.array_equal(out["L"][1], good["L"][1])
