@@ -17,6 +17,9 @@ Other workloads (--workload):
                    by default;
   matern32_forward one Matérn-3/2 precision of 1e5 jittered inputs (N = 2e5,
                    k = 3), lengthscale 10: the same forward list, FP64.
+  wide_loss        8 wide block-banded problems (n = 2e5, k = 64, Q = D +
+                   band(B B^T)): loss = log det Q + tr(Q^{-1} W) forward and
+                   backward on 64 x 64 blocks (FP32 MFMA products, FP64 pivots).
 
 Prints ONE JSON line on stdout; diagnostics go to stderr.
 """
@@ -69,6 +72,16 @@ def bytes_per_row(k: int, prec: int, forward_only: bool = False):
         "b2_replay": 3 * wb + 2 * wv,     # L, Lbar, ybar, z -> Qbar
         "unit": 11 * wb + 4 * wv,         # the loss unit's algorithmic traffic per row
     }
+
+
+def wide_bytes_per_row():
+    """Algorithmic bytes per row of the wide passes (mixed storage, k = 64)."""
+    wb, _ = record_bytes(64, 1)
+    return {"wide_f1": 2 * wb,      # Q -> L
+            "wide_f2": 2 * wb,      # W -> Sigma (trace term)
+            "wide_b1": 4 * wb,      # L, Sigma, W -> Lbar
+            "wide_b2": 3 * wb,      # L, Lbar -> Qbar
+            "unit": 11 * wb}
 
 
 def batch_bytes(ns, ks, prec, forward_only):
@@ -228,6 +241,51 @@ def make_matern32(args):
     return [Q.shape[0]], [3], ([Q], [y], None)
 
 
+class WideWorkload:
+    """The wide block-banded batch on the device (mixed storage)."""
+
+    def __init__(self, bo, torch, dev, ns, host_inputs):
+        Qs, _, Ws = host_inputs
+        self.plan = bo.WidePlan(ns, device=dev)
+        f32 = lambda arrs: torch.from_numpy(np.concatenate([a.ravel() for a in arrs])).to(dev, torch.float32)
+        f64 = lambda arrs: torch.from_numpy(np.concatenate([a[:, 0] for a in arrs])).to(dev)
+        E, N = self.plan.band_elems, self.plan.rows
+        kw = dict(Q=f32(Qs), Qd=f64(Qs), S=f32(Ws), Sd=f64(Ws),
+                  parts=torch.zeros((len(ns), 3), dtype=torch.float64, device=dev),
+                  info=torch.zeros(len(ns), dtype=torch.int32, device=dev))
+        for nm in ("L", "Sig", "Lbar", "Qbar"):
+            kw[nm] = torch.zeros(E, dtype=torch.float32, device=dev)
+            kw[nm + "d"] = torch.zeros(N, dtype=torch.float64, device=dev)
+        self.kw = kw
+        self.io = self.plan.io(**kw)
+        self.stats = {"nprob": len(ns), "blocks": sum((n + 63) // 64 for n in ns)}
+
+    def step(self):
+        self.plan.gauss_loss(self.io)
+
+
+def make_wide(args, bo, torch, dev):
+    """Q = D + band(B B^T) and W likewise (another seed), formed on the device
+    with the library's banded product (input construction, untimed), then
+    stored in the mixed format."""
+    from paper_1902_10078_amd import inputs
+
+    def build(b, seed):
+        B, D = inputs.config4_factors(b, seed=seed, n=args.n_wide)
+        Bb = bo.band_from(torch.from_numpy(B).to(dev), 64)
+        Q = bo.bo_gbmm(Bb, Bb, 0, 1, 64, 0).band.cpu().numpy()
+        Q[:, 0] += D
+        Qr = Q.astype(np.float32).astype(np.float64)
+        Qr[:, 0] = Q[:, 0]
+        return Qr
+
+    ns = [args.n_wide] * args.nwide
+    Qs = [build(b, 4) for b in range(args.nwide)]
+    Ws = [build(b, 5) for b in range(args.nwide)]
+    ys = [np.zeros(n) for n in ns]
+    return ns, [64] * len(ns), (Qs, ys, Ws)
+
+
 def cpu_baseline(host_inputs, ns, ks, nsample: int):
     """The FP64 oracle as it stands, OpenMP across problems, on a bounded
     sample of the workload's problems."""
@@ -255,7 +313,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["matern52_loss", "uneven_forward", "matern32_forward"],
+    ap.add_argument("--workload", choices=["matern52_loss", "uneven_forward", "matern32_forward", "wide_loss"],
                     default="matern52_loss")
     ap.add_argument("--prec", choices=["f64", "mixed"], default=None,
                     help="storage format (default: f64; mixed for uneven_forward)")
@@ -264,6 +322,8 @@ def main():
     ap.add_argument("--nprob", type=int, default=4096)
     ap.add_argument("--n-in32", type=int, default=100_000)
     ap.add_argument("--ell", type=float, default=10.0)
+    ap.add_argument("--nwide", type=int, default=8)
+    ap.add_argument("--n-wide", type=int, default=200_000)
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="problems timed on the CPU oracle (default: 8 for the loss batch, "
                          "256 for the uneven batch, 1 otherwise)")
@@ -287,13 +347,16 @@ def main():
     from paper_1902_10078_amd import bandops as bo
 
     if args.prec is None:
-        args.prec = "mixed" if args.workload == "uneven_forward" else "f64"
+        args.prec = "mixed" if args.workload in ("uneven_forward", "wide_loss") else "f64"
+    if args.workload == "wide_loss" and args.prec != "mixed":
+        sys.exit("wide_loss runs in the mixed format only")
     prec = bo.F64 if args.prec == "f64" else bo.MIXED
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
 
     t0 = time.perf_counter()
-    forward_only = args.workload != "matern52_loss"
+    forward_only = args.workload in ("uneven_forward", "matern32_forward")
+    wide = args.workload == "wide_loss"
     if args.workload == "matern52_loss":
         ns, ks, host_inputs = make_matern52(args)
         cfg = {"workload": f"matern52_ssm_batch{len(ns)}_rows{ns[0]}_k5_gauss_loss_fwd_bwd",
@@ -304,6 +367,11 @@ def main():
         cfg = {"workload": f"uneven_batch{len(ns)}_n256-65536_k1-3-5-11_forward",
                "batch": len(ns), "rows": sum(ns), "k": "1,3,5,11"}
         nsample = args.cpu_sample or 256
+    elif wide:
+        ns, ks, host_inputs = make_wide(args, bo, torch, dev)
+        cfg = {"workload": f"wide_blockband_batch{len(ns)}_rows{ns[0]}_k64_loss_fwd_bwd",
+               "batch": len(ns), "rows_per_problem": ns[0], "k": 64}
+        nsample = args.cpu_sample or 1
     else:
         ns, ks, host_inputs = make_matern32(args)
         cfg = {"workload": f"matern32_ssm_rows{ns[0]}_k3_ell{args.ell:g}_forward",
@@ -312,8 +380,12 @@ def main():
     rows = sum(ns)
     log(f"inputs: {len(ns)} problems, {rows} rows ({time.perf_counter() - t0:.1f} s)")
 
-    W = Workload(bo, torch, dev, ns, ks, prec, host_inputs, forward_only)
-    log(f"plan: {W.plan.stats}, workspace {W.plan.ws.numel() / 2**20:.1f} MiB")
+    if wide:
+        W = WideWorkload(bo, torch, dev, ns, host_inputs)
+        log(f"wide plan: {W.stats}, workspace {W.plan.ws.numel() / 2**20:.1f} MiB")
+    else:
+        W = Workload(bo, torch, dev, ns, ks, prec, host_inputs, forward_only)
+        log(f"plan: {W.plan.stats}, workspace {W.plan.ws.numel() / 2**20:.1f} MiB")
     info = W.kw["info"]
     for _ in range(max(args.warmup, 1)):
         W.step()
@@ -354,7 +426,10 @@ def main():
         W.step()
     prof = bo.profile_read()
     bo.profile_enable(False)
-    bb = batch_bytes(ns, ks, prec, forward_only)
+    if wide:
+        bb = {nm: b * rows for nm, b in wide_bytes_per_row().items()}
+    else:
+        bb = batch_bytes(ns, ks, prec, forward_only)
     kern = {}
     for name, (tms, cnt) in prof.items():
         entry = dict(avg_ms=tms / cnt, launches_per_step=cnt / nprof, ms_per_step=tms / nprof)
@@ -378,7 +453,7 @@ def main():
 
     # the plain FP64 one-matrix-per-launch form: per-problem plans, host loop, no graph
     vs_plain = None
-    if not args.no_plain:
+    if not args.no_plain and not wide:
         W64 = W if prec == bo.F64 else Workload(bo, torch, dev, ns, ks, bo.F64, host_inputs, forward_only)
         plain_step = W64.plain_steps()
         plain_step()
@@ -393,7 +468,11 @@ def main():
         vs_plain = ms_plain / ms
         log(f"plain FP64 one-matrix-per-launch: {ms_plain:.3f} ms/step -> batched is {vs_plain:.2f}x")
 
-    cfg.update(storage=args.prec, graph=use_graph, chunks=W.plan.stats["nchunk"])
+    cfg.update(storage=args.prec, graph=use_graph)
+    if wide:
+        cfg.update(blocks=W.stats["blocks"])
+    else:
+        cfg.update(chunks=W.plan.stats["nchunk"])
     out = {
         "metric": METRIC,
         "value": value,
@@ -405,7 +484,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32+f64" if wide else "f64",
         "data": "synthetic",
         "config": cfg,
         "roofline": roof,

@@ -6,6 +6,7 @@
 
 #include <cstdio>
 #include <cstdlib>
+#include <functional>
 #include <string>
 
 #include "../../include/bandops.h"
@@ -130,7 +131,7 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const Args A) {
 // ------------------------------------------------------------ profiling
 // When enabled, every launch is bracketed by a pair of events on its stream;
 // bo_profile_read() waits for them and sums the durations per step kind.
-constexpr int kProfSlots = bo::ST_COUNT + 2;   // + clear, finalize
+constexpr int kProfSlots = bo::ST_COUNT + 6;   // + clear, finalize, the four wide passes
 struct ProfRec {
   int slot;
   hipEvent_t a, b;
@@ -161,6 +162,16 @@ template <class F> int profiled(int slot, hipStream_t s, F &&launch) {
   g_prof_pending.push_back(r);
   return e;
 }
+
+}  // namespace
+
+// Launch timing for the other translation units of the library (C++ linkage):
+// the wide passes use slots ST_COUNT + 2 + which, which = 0..3.
+int bo_profile_wide(int which, hipStream_t s, const std::function<int()> &launch) {
+  return profiled(bo::ST_COUNT + 2 + which, s, launch);
+}
+
+namespace {
 
 struct GpuBE {
   hipStream_t s;
@@ -354,7 +365,7 @@ static const char *const kStepNames[kProfSlots] = {
     "chunk_product", "fs_summary", "fs_replay", "f2_summary", "f2_replay", "b1_summary",
     "b1_replay", "b2_summary", "b2_replay", "asc_group_compose", "asc_group_sweep",
     "asc_chunk_sweep", "desc_group_compose", "desc_group_sweep", "desc_chunk_sweep",
-    "clear_partials", "finalize"};
+    "clear_partials", "finalize", "wide_f1", "wide_f2", "wide_b1", "wide_b2"};
 
 extern "C" int bo_profile_slots(void) { return kProfSlots; }
 

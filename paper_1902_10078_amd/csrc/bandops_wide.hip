@@ -30,6 +30,7 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -68,14 +69,32 @@ struct Args {
 __device__ __forceinline__ int64_t nblocks(int64_t n) { return (n + NB - 1) / NB; }
 
 // ----------------------------------------------------------- block I/O
-// Visit the 64 records of block b (all 65 slots): f(c, d, j, valid) with
+constexpr int kSlotIters = (NB * W + NT - 1) / NT;   // slots of a block per thread
+
+// Visit the 64 records of block b (all 65 slots): f(it, c, d, j, valid) with
 // j = 64 b + c; valid when the slot lies inside the matrix.
 template <class F> __device__ __forceinline__ void for_block_slots(int64_t b, int64_t n, F &&f) {
-  for (int idx = threadIdx.x; idx < NB * W; idx += NT) {
-    const int c = idx / W, d = idx - c * W;
-    const int64_t j = NB * b + c;
-    f(c, d, j, j < n && j + d < n);
+#pragma unroll
+  for (int it = 0; it < kSlotIters; ++it) {
+    const int idx = threadIdx.x + it * NT;
+    if (idx < NB * W) {
+      const int c = idx / W, d = idx - c * W;
+      const int64_t j = NB * b + c;
+      f(it, c, d, j, j < n && j + d < n);
+    }
   }
+}
+
+// Every slot of block b of band Bp/Bd into registers (all loads issued before
+// any is used); slots past the matrix end read 1 on the diagonal, else 0.
+__device__ __forceinline__ void read_block(const float *Bp, const double *Bd, const Prob &p, int64_t b,
+                                           double (&v)[kSlotIters]) {
+#pragma unroll
+  for (int it = 0; it < kSlotIters; ++it) v[it] = 0.0;
+  for_block_slots(b, p.n, [&](int it, int c, int d, int64_t j, bool valid) {
+    if (valid) v[it] = d == 0 ? Bd[p.voff + j] : (double)Bp[(p.boff + j * W) + d];
+    else if (d == 0) v[it] = 1.0;   // identity past the matrix end
+  });
 }
 
 // Diagonal block (symmetric, full; E = double or float) and coupling block
@@ -84,19 +103,30 @@ template <class F> __device__ __forceinline__ void for_block_slots(int64_t b, in
 template <typename E>
 __device__ void load_blocks(const float *Bp, const double *Bd, const Prob &p, int64_t b, E (&S)[NB][LDF],
                             MatF *Cf) {
+  double v[kSlotIters];
+  read_block(Bp, Bd, p, b, v);
   if (Cf)
     for (int e = threadIdx.x; e < NB * NB; e += NT) (*Cf)[e / NB][e % NB] = 0.f;
   __syncthreads();
-  for_block_slots(b, p.n, [&](int c, int d, int64_t j, bool valid) {
-    double v = 0.0;
-    if (valid) v = d == 0 ? Bd[p.voff + j] : (double)Bp[(p.boff + j * W) + d];
-    else if (d == 0) v = 1.0;   // identity past the matrix end
+  for_block_slots(b, p.n, [&](int it, int c, int d, int64_t, bool) {
     if (d <= NB - 1 - c) {
-      S[c + d][c] = (E)v;
-      S[c][c + d] = (E)v;
+      S[c + d][c] = (E)v[it];
+      S[c][c + d] = (E)v[it];
     } else if (Cf) {
-      (*Cf)[d - NB + c][c] = (float)v;
+      (*Cf)[d - NB + c][c] = (float)v[it];
     }
+  });
+  __syncthreads();
+}
+
+// The coupling block alone (upper triangular, zero below).
+__device__ void load_coupling(const float *Bp, const double *Bd, const Prob &p, int64_t b, MatF &Cf) {
+  double v[kSlotIters];
+  read_block(Bp, Bd, p, b, v);
+  for (int e = threadIdx.x; e < NB * NB; e += NT) Cf[e / NB][e % NB] = 0.f;
+  __syncthreads();
+  for_block_slots(b, p.n, [&](int it, int c, int d, int64_t, bool) {
+    if (d > NB - 1 - c) Cf[d - NB + c][c] = (float)v[it];
   });
   __syncthreads();
 }
@@ -107,7 +137,7 @@ __device__ void load_blocks(const float *Bp, const double *Bd, const Prob &p, in
 template <class DiagF, class LowF, class CoupF>
 __device__ void store_blocks(float *Bp, double *Bd, const Prob &p, int64_t b, DiagF &&diag, LowF &&low,
                              CoupF &&coup) {
-  for_block_slots(b, p.n, [&](int c, int d, int64_t j, bool valid) {
+  for_block_slots(b, p.n, [&](int, int c, int d, int64_t j, bool valid) {
     if (j >= p.n) return;
     double v = 0.0;
     if (valid) v = d == 0 ? diag(c) : (d <= NB - 1 - c ? low(c + d, c) : coup(d - NB + c, c));
@@ -132,7 +162,7 @@ __device__ __forceinline__ void gemm64(const MatF &A, const MatF &B, float alpha
   float4_ acc[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) acc[t] = float4_{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 4
+#pragma unroll
   for (int s = 0; s < NB / 4; ++s) {
     const int k = 4 * s + kq;
     const float bv = TB ? B[jl][k] : B[k][jl];
@@ -151,20 +181,18 @@ __device__ __forceinline__ void gemm64(const MatF &A, const MatF &B, float alpha
   __syncthreads();
 }
 
+
 // FP64 Cholesky of the symmetric block S in place: the strict lower triangle
-// of S becomes L's, the diagonal goes to dg (S's diagonal is left as is).
-// Returns 0, or 1 + the first column whose pivot is not positive.  Thread 0
-// adds the log of every pivot to lsum.
-__device__ int potrf64(MatD &S, double *dg, double &lsum) {
+// of S becomes L's, the diagonal goes to dg and its reciprocal to rdg (S's
+// diagonal is left as is).  Returns 0, or 1 + the first column whose pivot is
+// not positive.  Thread 0 adds the log-determinant of L to lsum.
+__device__ int potrf64(MatD &S, double *dg, double *rdg, double &lsum) {
   const int tid = threadIdx.x;
   for (int j = 0; j < NB; ++j) {
     const double piv = S[j][j];
-    if (!(piv > 0.0)) return j + 1;   // the same value in every thread
+    if (!(piv > 0.0)) return j + 1;
     const double d = sqrt(piv), r = 1.0 / d;
-    if (tid == 0) {
-      dg[j] = d;
-      lsum += log(d);
-    }
+    if (tid == 0) { dg[j] = d; rdg[j] = r; }
     if (tid > j && tid < NB) S[tid][j] *= r;
     __syncthreads();
     const int c = tid & 63, q = tid >> 6;
@@ -175,13 +203,19 @@ __device__ int potrf64(MatD &S, double *dg, double &lsum) {
     }
     __syncthreads();
   }
+  if (tid < NB) {
+    double lg = log(dg[tid]);
+    for (int off = 32; off >= 1; off >>= 1) lg += __shfl_xor(lg, off, 64);
+    if (tid == 0) lsum += lg;
+  }
+  __syncthreads();
   return 0;
 }
 
-// X = L^{-1} for L = (strict lower triangle of S, diagonal dg), in FP64.
-// Four lanes per column j: lane q sums the terms k = j + q (mod 4) and keeps
-// (writes, then reads back) exactly those entries of column j.
-__device__ void trtri64(const MatD &S, const double *dg, MatD &X) {
+// X = L^{-1} for L = (strict lower triangle of S, reciprocal diagonal rdg),
+// in FP64.  Four lanes per column j: lane q sums the terms k = j + q (mod 4)
+// and keeps (writes, then reads back) exactly those entries of column j.
+__device__ void trtri64(const MatD &S, const double *rdg, MatD &X) {
   const int tid = threadIdx.x, j = tid >> 2, q = tid & 3;
   for (int i = q; i < j; i += 4) X[i][j] = 0.0;
   for (int i = j; i < NB; ++i) {
@@ -189,14 +223,24 @@ __device__ void trtri64(const MatD &S, const double *dg, MatD &X) {
     for (int k = j + q; k < i; k += 4) s += S[i][k] * X[k][j];
     s += __shfl_xor(s, 1, 64);
     s += __shfl_xor(s, 2, 64);
-    const double x = ((i == j ? 1.0 : 0.0) - s) / dg[i];
+    const double x = ((i == j ? 1.0 : 0.0) - s) * rdg[i];
     if (((i - j) & 3) == q) X[i][j] = x;
   }
   __syncthreads();
 }
 
 __device__ __forceinline__ void ws_load(const float *src, MatF &M) {
-  for (int e = threadIdx.x; e < NB * NB; e += NT) M[e / NB][e % NB] = src[e];
+  float4 v[NB * NB / (4 * NT)];
+#pragma unroll
+  for (int it = 0; it < NB * NB / (4 * NT); ++it) v[it] = reinterpret_cast<const float4 *>(src)[threadIdx.x + it * NT];
+#pragma unroll
+  for (int it = 0; it < NB * NB / (4 * NT); ++it) {
+    const int e = 4 * (threadIdx.x + it * NT), r = e / NB, c = e % NB;
+    M[r][c] = v[it].x;
+    M[r][c + 1] = v[it].y;
+    M[r][c + 2] = v[it].z;
+    M[r][c + 3] = v[it].w;
+  }
   __syncthreads();
 }
 __device__ __forceinline__ void ws_store(float *dst, const MatF &M) {
@@ -217,7 +261,7 @@ __device__ double block_sum(double v, double *red) {
 __global__ void __launch_bounds__(NT) k_wide_f1(const Args A) {
   __shared__ MatD S, X;
   __shared__ MatF Cf, Mf, Xf;
-  __shared__ double dg[NB];
+  __shared__ double dg[NB], rdg[NB];
   __shared__ int fail_s;
   const Prob p = A.probs[blockIdx.x];
   const int64_t nb = nblocks(p.n);
@@ -227,12 +271,12 @@ __global__ void __launch_bounds__(NT) k_wide_f1(const Args A) {
     load_blocks(A.Q, A.Qd, p, b, S, &Cf);
     if (b > 0)   // S_b = Q_bb - M_{b-1} M_{b-1}^T
       gemm64<false, true>(Mf, Mf, 1.f, [&](int i, int j, float v) { S[i][j] -= (double)v; });
-    const int r = potrf64(S, dg, lsum);
+    const int r = potrf64(S, dg, rdg, lsum);
     if (r) {
       fail = (int)(NB * b + r);
       break;
     }
-    trtri64(S, dg, X);
+    trtri64(S, rdg, X);
     for (int e = threadIdx.x; e < NB * NB; e += NT) Xf[e / NB][e % NB] = (float)X[e / NB][e % NB];
     // M_b = C_b X_b^T (upper triangular)
     gemm64<false, true>(Cf, Xf, 1.f, [&](int i, int j, float v) { Mf[i][j] = v; });
@@ -290,11 +334,12 @@ __global__ void __launch_bounds__(NT) k_wide_f2(const Args A) {
                  [&](int i, int c) { return (double)Tf[i][c]; },
                  [&](int rr, int c) { return last ? 0.0 : (double)Ef[rr][c]; });
     if (A.Wm) {   // tr(Sigma W) over the stored entries (off-diagonal ones twice)
-      for_block_slots(b, p.n, [&](int c, int d, int64_t j, bool valid) {
+      double wv[kSlotIters];
+      read_block(A.Wm, A.Wmd, p, b, wv);
+      for_block_slots(b, p.n, [&](int it, int c, int d, int64_t, bool valid) {
         if (!valid) return;
-        const double w = d == 0 ? A.Wmd[p.voff + j] : (double)A.Wm[p.boff + j * W + d];
-        const double s = d == 0 ? sdg[c] : (d <= NB - 1 - c ? (double)Tf[c + d][c] : (double)Ef[d - NB + c][c]);
-        tr += (d == 0 ? 1.0 : 2.0) * w * s;
+        const double sv = d == 0 ? sdg[c] : (d <= NB - 1 - c ? (double)Tf[c + d][c] : (double)Ef[d - NB + c][c]);
+        tr += (d == 0 ? 1.0 : 2.0) * wv[it] * sv;
       });
     }
     __syncthreads();
@@ -348,12 +393,7 @@ __global__ void __launch_bounds__(NT) k_wide_b1(const Args A) {
       // Mbar = Pbar X^T: Lbar's coupling block (upper triangle kept), in A1
       gemm64<false, true>(A2, Xf, 1.f, [&](int i, int j, float v) { A1[i][j] = v; });
       // M_b from L's coupling slots (into EMf, free now)
-      for (int e = threadIdx.x; e < NB * NB; e += NT) EMf[e / NB][e % NB] = 0.f;
-      __syncthreads();
-      for_block_slots(b, p.n, [&](int c, int d, int64_t j, bool valid) {
-        if (valid && d > NB - 1 - c) EMf[d - NB + c][c] = A.L[p.boff + j * W + d];
-      });
-      __syncthreads();
+      load_coupling(A.L, A.Ld, p, b, EMf);
       // Xbar = 2 X Sbar + M^T Pbar   (Wf)
       gemm64<false, false>(Xf, Sf, 2.f, [&](int i, int j, float v) { Wf[i][j] = v; });
       gemm64<true, false>(EMf, A2, 1.f, [&](int i, int j, float v) { Wf[i][j] += v; });
@@ -375,7 +415,7 @@ __global__ void __launch_bounds__(NT) k_wide_b1(const Args A) {
 // sensitivity gl (per unit loss weight).  Carried: the adjoint of S_{b+1}.
 __global__ void __launch_bounds__(NT) k_wide_b2(const Args A, double gl) {
   __shared__ MatF Lf, Xf, Mf, MBf, LBf, Sc, A1, A2;
-  __shared__ double dg[NB];
+  __shared__ double dg[NB], lbd[NB];
   const Prob p = A.probs[blockIdx.x];
   if (A.info[blockIdx.x] != 0) return;
   const int64_t nb = nblocks(p.n);
@@ -396,13 +436,15 @@ __global__ void __launch_bounds__(NT) k_wide_b2(const Args A, double gl) {
     }
     __syncthreads();
     // Lbar_bb (lower, with the log-determinant term) and Mbar_b (upper)
+    if (threadIdx.x < NB) {
+      const int64_t j = NB * b + threadIdx.x;
+      lbd[threadIdx.x] = j < p.n ? A.Lbd[p.voff + j] + 2.0 * gl / dg[threadIdx.x] : 0.0;
+    }
     load_blocks(A.Lb, A.Lbd, p, b, LBf, &MBf);
     for (int e = threadIdx.x; e < NB * NB; e += NT) {
       const int i = e / NB, j = e % NB;
       const bool pad = NB * b + i >= p.n;
-      double v = i >= j && !pad ? (double)LBf[i][j] : 0.0;
-      if (i == j && !pad) v = A.Lbd[p.voff + NB * b + i] + 2.0 * gl / dg[i];
-      LBf[i][j] = (float)v;
+      LBf[i][j] = i == j ? (float)lbd[i] : (i > j && !pad ? LBf[i][j] : 0.f);
     }
     __syncthreads();
     if (!last) {
@@ -441,6 +483,8 @@ __global__ void __launch_bounds__(NT) k_wide_b2(const Args A, double gl) {
 // ====================================================================== C ABI
 // The library's thread-local error message (defined with the other entry points).
 bo_status bo_set_error(bo_status s, const std::string &msg);
+// Launch timing hook of the library (slot per wide pass, which = 0..3).
+int bo_profile_wide(int which, hipStream_t s, const std::function<int()> &launch);
 
 namespace {
 bo_status wfail(bo_status s, const std::string &m) { return bo_set_error(s, m); }
@@ -496,6 +540,17 @@ static bo_status wide_args(int32_t nprob, const bo_batch_io *io, void *ws, wide:
   return BO_OK;
 }
 
+static void launch_f1_f2(int32_t nprob, const wide::Args &A, hipStream_t stream) {
+  bo_profile_wide(0, stream, [&] {
+    hipLaunchKernelGGL(wide::k_wide_f1, dim3(nprob), dim3(wide::NT), 0, stream, A);
+    return 0;
+  });
+  bo_profile_wide(1, stream, [&] {
+    hipLaunchKernelGGL(wide::k_wide_f2, dim3(nprob), dim3(wide::NT), 0, stream, A);
+    return 0;
+  });
+}
+
 static bo_status wide_launch_status(const char *what) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return wfail(BO_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
@@ -508,8 +563,7 @@ extern "C" bo_status bo_wide_forward(int32_t nprob, const bo_batch_io *io, void 
   if (!io->Sig || !io->Sigd) return wfail(BO_EINVAL, "bo_wide_forward: Sig and Sigd are required");
   A.Wm = nullptr;
   A.Wmd = nullptr;
-  hipLaunchKernelGGL(wide::k_wide_f1, dim3(nprob), dim3(wide::NT), 0, stream, A);
-  hipLaunchKernelGGL(wide::k_wide_f2, dim3(nprob), dim3(wide::NT), 0, stream, A);
+  launch_f1_f2(nprob, A, stream);
   return wide_launch_status("bo_wide_forward");
 }
 
@@ -519,9 +573,14 @@ extern "C" bo_status bo_wide_gauss_loss(int32_t nprob, const bo_batch_io *io, vo
   if (!io->S || !io->Sd || !io->Sig || !io->Sigd || !io->Lbar || !io->Lbard || !io->Qbar || !io->Qbard ||
       !io->parts)
     return wfail(BO_EINVAL, "bo_wide_gauss_loss: S, Sig, Lbar, Qbar (with diagonals) and parts are required");
-  hipLaunchKernelGGL(wide::k_wide_f1, dim3(nprob), dim3(wide::NT), 0, stream, A);
-  hipLaunchKernelGGL(wide::k_wide_f2, dim3(nprob), dim3(wide::NT), 0, stream, A);
-  hipLaunchKernelGGL(wide::k_wide_b1, dim3(nprob), dim3(wide::NT), 0, stream, A);
-  hipLaunchKernelGGL(wide::k_wide_b2, dim3(nprob), dim3(wide::NT), 0, stream, A, 1.0);
+  launch_f1_f2(nprob, A, stream);
+  bo_profile_wide(2, stream, [&] {
+    hipLaunchKernelGGL(wide::k_wide_b1, dim3(nprob), dim3(wide::NT), 0, stream, A);
+    return 0;
+  });
+  bo_profile_wide(3, stream, [&] {
+    hipLaunchKernelGGL(wide::k_wide_b2, dim3(nprob), dim3(wide::NT), 0, stream, A, 1.0);
+    return 0;
+  });
   return wide_launch_status("bo_wide_gauss_loss");
 }

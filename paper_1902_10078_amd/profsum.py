@@ -47,6 +47,10 @@ _KERNEL_SLOTS = [
     (r"LinGroupCompose<\d+, false>", "asc_group_compose"),
     (r"LinGroupSweep<\d+, false>", "asc_group_sweep"),
     (r"LinChunkSweep<\d+, false>", "asc_chunk_sweep"),
+    (r"k_wide_f1", "wide_f1"),
+    (r"k_wide_f2", "wide_f2"),
+    (r"k_wide_b1", "wide_b1"),
+    (r"k_wide_b2", "wide_b2"),
     (r"k_finalize", "finalize"),
     (r"ClearPart", "clear_partials"),
     (r"k_gbmm", "gbmm"),
