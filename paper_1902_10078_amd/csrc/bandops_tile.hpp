@@ -61,6 +61,20 @@ template <int K, typename T, int NB, int NV, int TR = 32> constexpr int tile_row
   }
 }
 
+// Vectors are staged VM band tiles at a time (VM * TR rows per vector tile):
+// a vector segment is only 8 bytes per row, so short vector tiles waste most
+// of every cache line they touch.  VM is the largest (up to 8) that keeps all
+// tiles inside the budget, with 2 KB left for the compiler's own LDS.
+template <int K, typename T, int NB, int NV, int TR, int VM = 8> constexpr int vec_mult() {
+  if constexpr (VM <= 1 || NV == 0) {
+    return 1;
+  } else {
+    constexpr int bands = NB * Geom<T, K + 1, TR>::WORDS * 4 + (sizeof(T) == 4 ? NB * Geom<double, 1, TR>::WORDS * 4 : 0);
+    if constexpr (bands + NV * Geom<T, 1, TR * VM>::WORDS * 4 <= kTileBytes - 2048) return VM;
+    else return vec_mult<K, T, NB, NV, TR, VM - 1>();
+  }
+}
+
 typedef __attribute__((address_space(3))) void *lds_ptr_t;
 template <typename E> using lds_cptr = const __attribute__((address_space(3))) E *;
 
@@ -152,11 +166,13 @@ __device__ __forceinline__ void stream_rows(const BandIn<T> (&bands)[NB > 0 ? NB
                                             int64_t hi, int64_t n, int64_t ld, Body &&body) {
   constexpr int W = K + 1;
   constexpr int TR = tile_rows<K, T, NB, NV>();
+  constexpr int VM = vec_mult<K, T, NB, NV, TR>();
+  constexpr int VR = TR * VM;   // rows per vector tile
   constexpr bool MIXED = sizeof(T) == 4;
   constexpr int NB1 = NB > 0 ? NB : 1, NV1 = NV > 0 ? NV : 1;
   using GB = Geom<T, W, TR>;
   using GD = Geom<double, 1, TR>;
-  using GV = Geom<T, 1, TR>;
+  using GV = Geom<T, 1, VR>;
   __shared__ __attribute__((aligned(16))) uint32_t sb[NB1][GB::WORDS];
   __shared__ __attribute__((aligned(16))) uint32_t sd[MIXED ? NB1 : 1][MIXED ? GD::WORDS : 1];
   __shared__ __attribute__((aligned(16))) uint32_t sv[NV1][NV > 0 ? GV::WORDS : 1];
@@ -164,10 +180,14 @@ __device__ __forceinline__ void stream_rows(const BandIn<T> (&bands)[NB > 0 ? NB
   const int lane = threadIdx.x;
   const int64_t len = hi > lo ? hi - lo : 0;
   const int64_t maxlen = wave_max(len);
+  int pitch_v[NV1];
+  int64_t vbase = 0;   // first processed row of the current vector tile
+#pragma unroll
+  for (int vi = 0; vi < NV1; ++vi) pitch_v[vi] = 0;
   for (int64_t t0 = 0; t0 < maxlen; t0 += TR) {
     const int cnt = (int)(len - t0 < TR ? (len - t0 > 0 ? len - t0 : 0) : TR);
     const int64_t r0 = DESC ? hi - t0 - cnt : lo + t0;   // first row of this tile
-    int pitch_b[NB1], pitch_d[NB1], pitch_v[NV1];
+    int pitch_b[NB1], pitch_d[NB1];
 #pragma unroll
     for (int bi = 0; bi < NB; ++bi) {
       int64_t s0 = r0 + bands[bi].shift;
@@ -180,12 +200,16 @@ __device__ __forceinline__ void stream_rows(const BandIn<T> (&bands)[NB > 0 ? NB
         pitch_d[bi] = lds_fill<double, 1, TR>(sd[MIXED ? bi : 0],
                                               (on && bands[bi].diag) ? bands[bi].diag + s0 : nullptr, c, lane);
     }
+    if ((t0 / TR) % VM == 0) {   // next vector tile: rows of the following VM band tiles
+      const int vcnt = (int)(len - t0 < VR ? (len - t0 > 0 ? len - t0 : 0) : VR);
+      vbase = DESC ? hi - t0 - vcnt : lo + t0;
 #pragma unroll
-    for (int vi = 0; vi < NV; ++vi) {
-      int64_t s0 = r0 + vecs[vi].shift;
-      int c = cnt;
-      if (s0 + c > n) c = (int)(n - s0 > 0 ? n - s0 : 0);
-      pitch_v[vi] = lds_fill<T, 1, TR>(sv[vi], (vecs[vi].p && c > 0) ? vecs[vi].p + s0 : nullptr, c, lane);
+      for (int vi = 0; vi < NV; ++vi) {
+        int64_t s0 = vbase + vecs[vi].shift;
+        int c = vcnt;
+        if (s0 + c > n) c = (int)(n - s0 > 0 ? n - s0 : 0);
+        pitch_v[vi] = lds_fill<T, 1, VR>(sv[vi], (vecs[vi].p && c > 0) ? vecs[vi].p + s0 : nullptr, c, lane);
+      }
     }
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
@@ -208,10 +232,11 @@ __device__ __forceinline__ void stream_rows(const BandIn<T> (&bands)[NB > 0 ? NB
             rec[bi][d] = (bands[bi].p && js + d < n) ? x : 0.0;
           }
         }
+        const int rv = (int)(j - vbase);
 #pragma unroll
         for (int vi = 0; vi < NV; ++vi)
           val[vi] = (vecs[vi].p && j + vecs[vi].shift < n)
-                        ? (double)((lds_cptr<T>)((lds_cptr<char>)(lds_ptr_t)sv[vi] + lane * pitch_v[vi]))[r]
+                        ? (double)((lds_cptr<T>)((lds_cptr<char>)(lds_ptr_t)sv[vi] + lane * pitch_v[vi]))[rv]
                         : 0.0;
         body(j, rec, val);
       }
