@@ -386,4 +386,13 @@ BO_HD void mat_mul_acc(double (&G)[Dim<K>::K1][Dim<K>::K1], const double (&P)[Di
     for (int q = 0; q < K; ++q) G[p][q] = R[p][q];
 }
 
+// Composite of two consecutive linear maps, first (P1, m1) then (P2, m2),
+// written into (P1, m1).
+template <int K, bool DESC>
+BO_HD void lin_compose(double (&P1)[Dim<K>::K1][Dim<K>::K1], LinMap<K> &m1,
+                       const double (&P2)[Dim<K>::K1][Dim<K>::K1], const LinMap<K> &m2) {
+  mat_mul_acc<K, DESC>(P1, P2);
+  lin_apply<K, DESC>(P2, m2, m1);
+}
+
 }  // namespace bo

@@ -47,7 +47,7 @@ struct Sched {
   int64_t rows = 0;
   // workspace layout (bytes offsets from the workspace base)
   size_t off_tables = 0, off_f1map = 0, off_f1st = 0, off_f1gmap = 0, off_f1gst = 0, off_Pc = 0,
-         off_Pg = 0, off_lmap = 0, off_lmap2 = 0, off_lst = 0, off_lgmap = 0, off_lgst = 0, off_part = 0,
+         off_Pg = 0, off_Pex = 0, off_lmap = 0, off_lmap2 = 0, off_lst = 0, off_lgmap = 0, off_lgst = 0, off_part = 0,
          off_out = 0, bytes = 0;
   int32_t sw_f1map = 1, sw_f1st = 1, sw_mat = 1, sw_lin = 1;
   std::vector<unsigned char> table_blob;   // probs | chunk_prob | group_prob (device image)
@@ -161,6 +161,7 @@ inline bool build_sched(const ProbIn *in, int nprob, int64_t target_chunks, int6
   s.off_f1gst = take((size_t)s.ngroup * s.sw_f1st);
   s.off_Pc = take((size_t)s.nchunk * s.sw_mat);
   s.off_Pg = take((size_t)s.ngroup * s.sw_mat);
+  s.off_Pex = take((size_t)s.nchunk * s.sw_mat);
   s.off_lmap = take((size_t)s.nchunk * s.sw_lin);
   s.off_lmap2 = take((size_t)s.nchunk * s.sw_lin);
   s.off_lst = take((size_t)s.nchunk * s.sw_lin);
@@ -198,6 +199,7 @@ inline void bind_sched(const Sched &s, void *ws, bool single, Args &A) {
   A.f1gst = (double *)(w + s.off_f1gst);
   A.Pc = (double *)(w + s.off_Pc);
   A.Pg = (double *)(w + s.off_Pg);
+  A.Pex = (double *)(w + s.off_Pex);
   A.lmap = (double *)(w + s.off_lmap);
   A.lmap2 = (double *)(w + s.off_lmap2);
   A.lmap_out = nullptr;

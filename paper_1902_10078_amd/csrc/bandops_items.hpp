@@ -55,6 +55,7 @@ struct Args {
   // ---- workspace
   double *f1map, *f1st, *f1gmap, *f1gst;  // F1 chunk maps / states, group maps / states
   double *Pc, *Pg;                        // chunk / group products
+  double *Pex;                            // exclusive prefix products within a group
   double *lmap, *lst, *lgmap, *lgst;      // linear pass maps / states
   double *lmap2;                          // second map buffer (fused summaries alternate)
   double *lmap_out;                       // replays: where the next pass's chunk maps go (or null)

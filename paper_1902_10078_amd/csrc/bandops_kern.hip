@@ -276,6 +276,193 @@ __global__ void __launch_bounds__(kBlock) k_b2(const Args A, int64_t count) {
   }
 }
 
+// ------------------------------------------------------------ scans
+// The chunk summaries of a pass are combined by parallel prefix scans of
+// depth log2(64): one wavefront per group scans its chunks' maps, one per
+// problem scans the group totals, and every chunk then applies its exclusive
+// prefix to its group's entering state.  (The serial work items do the same
+// with depth 64 per level.)  A map travels between lanes through LDS, 64
+// doubles per lane at a time.
+constexpr int kXch = 64;
+
+template <int N>
+__device__ __forceinline__ void wave_xch(const double (&own)[N], double (&got)[N], int src, double *buf) {
+  const int lane = threadIdx.x;
+#pragma unroll
+  for (int b = 0; b < N; b += kXch) {
+#pragma unroll
+    for (int e = 0; e < kXch; ++e)
+      if (b + e < N) buf[e * kBlock + lane] = own[b + e];
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < kXch; ++e)
+      if (b + e < N) got[b + e] = buf[e * kBlock + src];
+    __syncthreads();
+  }
+}
+
+template <int K> struct LinPair {   // a linear map: product P and (M, v)
+  double P[Dim<K>::K1][Dim<K>::K1];
+  LinMap<K> m;
+};
+template <class M> struct Flat {
+  static constexpr int N = sizeof(M) / sizeof(double);
+  static __device__ __forceinline__ double (&of(M &x))[N] { return *reinterpret_cast<double(*)[N]>(&x); }
+};
+
+// Inclusive scan of `cur` over lanes [0, n) with compose(earlier, later).
+template <class M, class Compose>
+__device__ __forceinline__ void wave_scan(M &cur, int n, double *buf, Compose &&compose) {
+  const int q = threadIdx.x;
+  M got;
+  for (int off = 1; off < n; off <<= 1) {
+    wave_xch(Flat<M>::of(cur), Flat<M>::of(got), q >= off ? q - off : 0, buf);
+    if (q >= off && q < n) {
+      compose(got, cur);   // got <- got then cur
+      cur = got;
+    }
+  }
+}
+
+template <int K, bool DESC> __global__ void __launch_bounds__(kBlock) k_lin_gscan(const Args A, int64_t) {
+  __shared__ double buf[kXch * kBlock];
+  const int32_t g = A.g_beg + (int32_t)blockIdx.x;
+  const ProbDesc &pd = prob_at(A, prob_of_group(A, g));
+  int32_t c0, c1;
+  group_chunks(pd, g, c0, c1);
+  const int n = c1 - c0, q = threadIdx.x;
+  const int32_t c = DESC ? c1 - 1 - q : c0 + q;
+  LinPair<K> cur;
+  if (q < n) {
+    mat_load<K>(A.Pc + (int64_t)c * A.sw_mat, cur.P);
+    lin_load<K>(A.lmap + (int64_t)c * A.sw_lin, cur.m);
+  }
+  auto comp = [](LinPair<K> &a, const LinPair<K> &b) { lin_compose<K, DESC>(a.P, a.m, b.P, b.m); };
+  wave_scan(cur, n, buf, comp);
+  LinPair<K> prev;
+  wave_xch(Flat<LinPair<K>>::of(cur), Flat<LinPair<K>>::of(prev), q >= 1 ? q - 1 : 0, buf);
+  if (q >= 1 && q < n) {   // the exclusive prefix replaces the chunk's own map
+    mat_store<K>(A.Pex + (int64_t)c * A.sw_mat, prev.P);
+    lin_store<K>(A.lmap + (int64_t)c * A.sw_lin, prev.m);
+  }
+  if (q == n - 1) {
+    mat_store<K>(A.Pg + (int64_t)g * A.sw_mat, cur.P);
+    lin_store<K>(A.lgmap + (int64_t)g * A.sw_lin, cur.m);
+  }
+}
+
+template <int K, bool DESC> __global__ void __launch_bounds__(kBlock) k_lin_pscan(const Args A, int64_t) {
+  __shared__ double buf[kXch * kBlock];
+  const ProbDesc &pd = prob_at(A, A.p_beg + (int32_t)blockIdx.x);
+  const int n = pd.ngroup, q = threadIdx.x;
+  const int32_t g = DESC ? pd.group0 + n - 1 - q : pd.group0 + q;
+  LinPair<K> cur;
+  if (q < n) {
+    mat_load<K>(A.Pg + (int64_t)g * A.sw_mat, cur.P);
+    lin_load<K>(A.lgmap + (int64_t)g * A.sw_lin, cur.m);
+  }
+  auto comp = [](LinPair<K> &a, const LinPair<K> &b) { lin_compose<K, DESC>(a.P, a.m, b.P, b.m); };
+  wave_scan(cur, n, buf, comp);
+  LinPair<K> prev;
+  wave_xch(Flat<LinPair<K>>::of(cur), Flat<LinPair<K>>::of(prev), q >= 1 ? q - 1 : 0, buf);
+  if (q < n) {   // entering state of a group: the groups before it applied to the zero state
+    LinMap<K> st;
+    if (q == 0) lin_zero<K>(st);
+    else st = prev.m;
+    lin_store<K>(A.lgst + (int64_t)g * A.sw_lin, st);
+  }
+}
+
+template <int K, bool DESC> __global__ void __launch_bounds__(kBlock) k_lin_capply(const Args A, int64_t) {
+  constexpr int K1 = Dim<K>::K1;
+  const int32_t g = A.g_beg + (int32_t)blockIdx.x;
+  const ProbDesc &pd = prob_at(A, prob_of_group(A, g));
+  int32_t c0, c1;
+  group_chunks(pd, g, c0, c1);
+  const int n = c1 - c0, q = threadIdx.x;
+  if (q >= n) return;
+  const int32_t c = DESC ? c1 - 1 - q : c0 + q;
+  LinMap<K> st;
+  lin_load<K>(A.lgst + (int64_t)g * A.sw_lin, st);
+  if (q >= 1) {
+    double P[K1][K1];
+    LinMap<K> m;
+    mat_load<K>(A.Pex + (int64_t)c * A.sw_mat, P);
+    lin_load<K>(A.lmap + (int64_t)c * A.sw_lin, m);
+    lin_apply<K, DESC>(P, m, st);
+  }
+  lin_store<K>(A.lst + (int64_t)c * A.sw_lin, st);
+}
+
+// F1: the last chunk of a problem has no map (nothing follows it), so neither
+// does the last group; they are never read.
+template <int K> __global__ void __launch_bounds__(kBlock) k_f1_gscan(const Args A, int64_t) {
+  __shared__ double buf[kXch * kBlock];
+  const int32_t g = A.g_beg + (int32_t)blockIdx.x;
+  const ProbDesc &pd = prob_at(A, prob_of_group(A, g));
+  int32_t c0, c1;
+  group_chunks(pd, g, c0, c1);
+  const int32_t cend = pd.chunk0 + pd.nchunk;
+  const int n = (c1 == cend ? c1 - 1 : c1) - c0;   // chunks with a map
+  const int q = threadIdx.x;
+  const int32_t c = c0 + q;
+  F1Map<K> cur;
+  if (q < n) f1_load_map<K>(A.f1map + (int64_t)c * A.sw_f1map, cur);
+  auto comp = [](F1Map<K> &a, const F1Map<K> &b) {
+    F1Map<K> o;
+    f1_compose<K>(a, b, o);
+    a = o;
+  };
+  wave_scan(cur, n, buf, comp);
+  F1Map<K> prev;
+  wave_xch(Flat<F1Map<K>>::of(cur), Flat<F1Map<K>>::of(prev), q >= 1 ? q - 1 : 0, buf);
+  if (q >= 1 && q < c1 - c0) f1_store_map<K>(A.f1map + (int64_t)c * A.sw_f1map, prev);
+  if (q == n - 1 && c1 < cend) f1_store_map<K>(A.f1gmap + (int64_t)g * A.sw_f1map, cur);
+}
+
+template <int K> __global__ void __launch_bounds__(kBlock) k_f1_pscan(const Args A, int64_t) {
+  __shared__ double buf[kXch * kBlock];
+  const ProbDesc &pd = prob_at(A, A.p_beg + (int32_t)blockIdx.x);
+  const int ng = pd.ngroup, n = ng - 1, q = threadIdx.x;   // the last group has no map
+  const int32_t g = pd.group0 + q;
+  F1Map<K> cur;
+  if (q < n) f1_load_map<K>(A.f1gmap + (int64_t)g * A.sw_f1map, cur);
+  auto comp = [](F1Map<K> &a, const F1Map<K> &b) {
+    F1Map<K> o;
+    f1_compose<K>(a, b, o);
+    a = o;
+  };
+  wave_scan(cur, n, buf, comp);
+  F1Map<K> prev;
+  wave_xch(Flat<F1Map<K>>::of(cur), Flat<F1Map<K>>::of(prev), q >= 1 ? q - 1 : 0, buf);
+  if (q < ng) {
+    F1State<K> z, st;
+    f1_zero_state<K>(z);
+    if (q == 0) st = z;
+    else f1_apply<K>(prev, z, st);
+    f1_store_state<K>(A.f1gst + (int64_t)g * A.sw_f1st, st);
+  }
+}
+
+template <int K> __global__ void __launch_bounds__(kBlock) k_f1_capply(const Args A, int64_t) {
+  const int32_t g = A.g_beg + (int32_t)blockIdx.x;
+  const ProbDesc &pd = prob_at(A, prob_of_group(A, g));
+  int32_t c0, c1;
+  group_chunks(pd, g, c0, c1);
+  const int q = threadIdx.x;
+  if (q >= c1 - c0) return;
+  const int32_t c = c0 + q;
+  F1State<K> st, t;
+  f1_load_state<K>(A.f1gst + (int64_t)g * A.sw_f1st, st);
+  if (q >= 1) {
+    F1Map<K> m;
+    f1_load_map<K>(A.f1map + (int64_t)c * A.sw_f1map, m);
+    f1_apply<K>(m, st, t);
+    st = t;
+  }
+  f1_store_state<K>(A.f1st + (int64_t)c * A.sw_f1st, st);
+}
+
 template <typename T> struct Launch {
   const Args &a;
   int64_t count;
@@ -288,6 +475,8 @@ template <typename T> struct Launch {
   }
 };
 
+inline int hip_ok() { return hipGetLastError() == hipSuccess ? 0 : -2; }
+
 template <typename T> int run_step(int step, const Args &a, int64_t count, hipStream_t s) {
   if (count <= 0) return 0;
   const dim3 grid((unsigned)((count + kBlock - 1) / kBlock)), block(kBlock);
@@ -295,6 +484,25 @@ template <typename T> int run_step(int step, const Args &a, int64_t count, hipSt
   // LDS-tiled streaming needs packed records (plans always are); other
   // strides run the per-lane items.
   const bool packed = a.probs != nullptr || a.one.ld == K + 1;
+  // Scans: one wavefront per group or problem (groups hold at most 64 chunks,
+  // problems at most 64 groups, when the plan's group size is at most 64).
+  // Wider maps (K > 6) are too large to trade between lanes cheaply: their
+  // scans stay with the serial work items.
+  if (K <= 6 && a.G <= kBlock) {
+    const dim3 wg((unsigned)count);
+    switch (step) {
+      case ST_F1_GCOMP: hipLaunchKernelGGL((k_f1_gscan<K>), wg, block, 0, s, a, count); return hip_ok();
+      case ST_F1_GSWEEP: hipLaunchKernelGGL((k_f1_pscan<K>), wg, block, 0, s, a, count); return hip_ok();
+      case ST_F1_CSWEEP: hipLaunchKernelGGL((k_f1_capply<K>), wg, block, 0, s, a, count); return hip_ok();
+      case ST_ASC_GCOMP: hipLaunchKernelGGL((k_lin_gscan<K, false>), wg, block, 0, s, a, count); return hip_ok();
+      case ST_ASC_GSWEEP: hipLaunchKernelGGL((k_lin_pscan<K, false>), wg, block, 0, s, a, count); return hip_ok();
+      case ST_ASC_CSWEEP: hipLaunchKernelGGL((k_lin_capply<K, false>), wg, block, 0, s, a, count); return hip_ok();
+      case ST_DESC_GCOMP: hipLaunchKernelGGL((k_lin_gscan<K, true>), wg, block, 0, s, a, count); return hip_ok();
+      case ST_DESC_GSWEEP: hipLaunchKernelGGL((k_lin_pscan<K, true>), wg, block, 0, s, a, count); return hip_ok();
+      case ST_DESC_CSWEEP: hipLaunchKernelGGL((k_lin_capply<K, true>), wg, block, 0, s, a, count); return hip_ok();
+      default: break;
+    }
+  }
   switch (packed ? step : -1) {
     case ST_F1_SUM: hipLaunchKernelGGL((k_f1_sum<K, T>), grid, block, 0, s, a, count); break;
     case ST_F1_REP: hipLaunchKernelGGL((k_f1_rep<K, T>), grid, block, 0, s, a, count); break;
