@@ -262,6 +262,7 @@ template <int K, typename T, bool REPLAY> struct F2Step {
   static constexpr int K1 = Dim<K>::K1, NS = Dim<K>::NS;
   double W[NS], xw[K1];
   double Rb[K1][K1], Mb[NS];   // fused summary of the B1 pass (see row_b1())
+  double u_[K1];               // u_j of the last row() (row_b1() reuses it)
   BandP<T> S;
   T *x;
   double xscale;
@@ -301,12 +302,11 @@ template <int K, typename T, bool REPLAY> struct F2Step {
     }
   }
 
-  // sbin = Sigmabar record j (or the band S of the trace term when sb_is_S).
-  BO_HD void row_b1(const double (&r)[K + 1], const double (&sbin)[K + 1]) {
-    double inv = 1.0 / r[0];
-    double u[K1], w[K1], w2[K1];
-#pragma unroll
-    for (int p = 0; p < K; ++p) u[p] = r[p + 1] * inv;
+  // sbin = Sigmabar record j (or the band S of the trace term when sb_is_S);
+  // called after row() of the same record j, whose u_j it reuses.
+  BO_HD void row_b1(const double (&)[K + 1], const double (&sbin)[K + 1]) {
+    const double(&u)[K1] = u_;
+    double w[K1], w2[K1];
     const double f = sb_is_S ? 2.0 : 1.0;
 #pragma unroll
     for (int p = 0; p < K; ++p) {
@@ -335,7 +335,7 @@ template <int K, typename T, bool REPLAY> struct F2Step {
 
   BO_HD void row(int64_t j, const double (&r)[K + 1], double bj) {
     double inv = 1.0 / r[0];
-    double u[K1];
+    double(&u)[K1] = u_;
 #pragma unroll
     for (int p = 0; p < K; ++p) u[p] = r[p + 1] * inv;
     if (want_s) {
@@ -436,10 +436,9 @@ template <int K, typename T, bool REPLAY> struct B1Step {
     }
   }
 
-  // o = Lbar record j just produced, r = L record j, zj = z[j], yahead =
-  // ybar[j+K+1] (0 past the end).
-  BO_HD void row_b2(const double (&r)[K + 1], const double (&o)[K + 1], double zj, double yahead) {
-    double inv = 1.0 / r[0];
+  // o = Lbar record j just produced, r = L record j (inv = 1 / L_jj), zj =
+  // z[j], yahead = ybar[j+K+1] (0 past the end).
+  BO_HD void row_b2(const double (&r)[K + 1], double inv, const double (&o)[K + 1], double zj, double yahead) {
     double Lt[K + 1];
 #pragma unroll
     for (int d = 0; d <= K; ++d) Lt[d] = o[d] - yw[d] * zj;
@@ -550,7 +549,7 @@ template <int K, typename T, bool REPLAY> struct B1Step {
         for (int d = 0; d <= K; ++d) o[d] += old[d];
       }
       store_rec<K, T>(Lb.p, Lb.diag, Lb.ld, j, o);
-      if (want_b2) row_b2(r, o, zj, yahead);
+      if (want_b2) row_b2(r, inv, o, zj, yahead);
 #pragma unroll
       for (int i = 0; i < K; ++i)
 #pragma unroll
