@@ -38,6 +38,15 @@ _KERNEL_SLOTS = [
     (r"k_b1<\d+, \w+, true", "b1_replay"),
     (r"k_b2<\d+, \w+, false>", "b2_summary"),
     (r"k_b2<\d+, \w+, true>", "b2_replay"),
+    (r"k_f1_gscan", "f1_group_compose"),
+    (r"k_f1_pscan", "f1_group_sweep"),
+    (r"k_f1_capply", "f1_chunk_sweep"),
+    (r"k_lin_gscan<\d+, true>", "desc_group_compose"),
+    (r"k_lin_pscan<\d+, true>", "desc_group_sweep"),
+    (r"k_lin_capply<\d+, true>", "desc_chunk_sweep"),
+    (r"k_lin_gscan<\d+, false>", "asc_group_compose"),
+    (r"k_lin_pscan<\d+, false>", "asc_group_sweep"),
+    (r"k_lin_capply<\d+, false>", "asc_chunk_sweep"),
     (r"F1GroupCompose", "f1_group_compose"),
     (r"F1GroupSweep", "f1_group_sweep"),
     (r"F1ChunkSweep", "f1_chunk_sweep"),
