@@ -138,7 +138,7 @@ def copy_probe(torch, mib: int):
 class Workload:
     """Inputs resident on the device, a plan over the batch, and the step."""
 
-    def __init__(self, bo, torch, dev, ns, ks, prec, host_inputs, forward_only):
+    def __init__(self, bo, torch, dev, ns, ks, prec, host_inputs, forward_only, target_chunks=0):
         self.bo, self.torch, self.dev = bo, torch, dev
         self.ns, self.ks, self.prec = ns, ks, prec
         self.forward_only = forward_only
@@ -171,8 +171,12 @@ class Workload:
             for nm in names:
                 kw[nm + "d"] = torch.zeros(N, dtype=torch.float64, device=dev)
         self.kw = kw
-        self.plan = bo.Plan(ns, ks, device=dev)
-        self.io = self.plan.io(**kw)
+        self.set_schedule(target_chunks)
+
+    def set_schedule(self, target_chunks: int):
+        """(Re)build the plan for a target chunk count (0: the library default)."""
+        self.plan = self.bo.Plan(self.ns, self.ks, target_chunks=target_chunks, device=self.dev)
+        self.io = self.plan.io(**self.kw)
 
     def step(self):
         if self.forward_only:
@@ -332,6 +336,10 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--kernels-json", default="")
+    ap.add_argument("--target-chunks", type=int, default=0, help="plan chunk target (0: library default)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="measure a few chunk targets first and time the fastest")
+    ap.add_argument("--tune-cache", default="", help="JSON cache for --autotune results")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (a known-size kernel "
                          "that calibrates HBM byte counters) and exit")
@@ -385,7 +393,17 @@ def main():
         W = WideWorkload(bo, torch, dev, ns, host_inputs)
         log(f"wide plan: {W.stats}, workspace {W.plan.ws.numel() / 2**20:.1f} MiB")
     else:
-        W = Workload(bo, torch, dev, ns, ks, prec, host_inputs, forward_only)
+        W = Workload(bo, torch, dev, ns, ks, prec, host_inputs, forward_only, args.target_chunks)
+        if args.autotune:
+            from paper_1902_10078_amd import autotune
+
+            def make_step(t):
+                W.set_schedule(t)
+                return W.step
+            tuned = autotune.tune(ns, ks, make_step, args.workload, prec,
+                                  cache_path=args.tune_cache or None)
+            W.set_schedule(tuned["target_chunks"])
+            log(f"autotune: {tuned}")
         log(f"plan: {W.plan.stats}, workspace {W.plan.ws.numel() / 2**20:.1f} MiB")
     info = W.kw["info"]
     for _ in range(max(args.warmup, 1)):
@@ -474,6 +492,9 @@ def main():
         cfg.update(blocks=W.stats["blocks"])
     else:
         cfg.update(chunks=W.plan.stats["nchunk"])
+        if args.autotune:
+            cfg.update(schedule={"target_chunks": tuned["target_chunks"],
+                                 "candidates_ms": {str(k): round(v, 3) for k, v in tuned["ms"].items()}})
     out = {
         "metric": METRIC,
         "value": value,

@@ -76,11 +76,16 @@ def slot_of(kernel_name: str) -> str | None:
     return None
 
 
+# Sources of the row-streaming kernels, their scans and their schedule.
+_KERNEL_SOURCES = ("bandops_algo.hpp", "bandops_step.hpp", "bandops_items.hpp", "bandops_tile.hpp",
+                   "bandops_driver.hpp", "bandops_steps.hpp", "bandops_kern.hip")
+
+
 def source_hash() -> str:
-    """Hash of the device sources that decide what the kernels execute."""
+    """Hash of the sources that decide what the row-streaming kernels execute
+    and how the batch is cut into chunks."""
     h = hashlib.sha256()
-    files = sorted(glob.glob(os.path.join(HERE, "csrc", "*.hpp")) +
-                   glob.glob(os.path.join(HERE, "csrc", "*.hip")))
+    files = sorted(os.path.join(HERE, "csrc", f) for f in _KERNEL_SOURCES)
     for f in files:
         h.update(os.path.basename(f).encode())
         with open(f, "rb") as fh:

@@ -105,3 +105,28 @@ def test_plan_errors_and_stats(L):
     assert L.bo_plan_create(probs, 2, 0, ctypes.byref(h)) == -1
     assert L.bo_plan_create(probs, 0, 0, ctypes.byref(h)) == -1
     assert L.bo_plan_create(None, 1, 0, ctypes.byref(h)) == -1
+
+
+def test_wide_errors_and_workspace(L):
+    """The wide (k = 64) entry points: argument errors before any launch, and
+    the workspace size (problem table plus two FP32 64 x 64 blocks per block
+    row)."""
+    from paper_1902_10078_amd.bandops import _BatchIO, _Problem
+    sz = ctypes.c_size_t()
+    probs = (_Problem * 2)(_Problem(130, 64, 0, 0, 0), _Problem(64, 64, 0, 130 * 65, 130))
+    assert L.bo_wide_workspace_size(probs, 2, ctypes.byref(sz)) == 0
+    blocks = 3 + 1
+    assert sz.value == 256 + blocks * 2 * 64 * 64 * 4
+    bad = (_Problem * 1)(_Problem(100, 5, 0, 0, 0))
+    assert L.bo_wide_workspace_size(bad, 1, ctypes.byref(sz)) == -4
+    assert b"k = 64" in L.bo_last_error()
+    neg = (_Problem * 1)(_Problem(-3, 64, 0, 0, 0))
+    assert L.bo_wide_workspace_size(neg, 1, ctypes.byref(sz)) == -1
+    assert L.bo_wide_workspace_size(None, 1, ctypes.byref(sz)) == -1
+    # a workspace that is too small is refused before any copy
+    assert L.bo_wide_upload(probs, 2, ctypes.c_void_p(1), 16) == -3
+    io = _BatchIO()
+    # missing required arrays: refused before any launch
+    assert L.bo_wide_forward(1, ctypes.byref(io), ctypes.c_void_p(1), None) == -1
+    assert L.bo_wide_gauss_loss(1, ctypes.byref(io), ctypes.c_void_p(1), None) == -1
+    assert L.bo_wide_forward(0, ctypes.byref(io), ctypes.c_void_p(1), None) == -1
