@@ -503,7 +503,11 @@ template <typename T> int run_step(int step, const Args &a, int64_t count, hipSt
       default: break;
     }
   }
-  switch (packed ? step : -1) {
+  if (!packed) {
+    Launch<T> l{a, count, s};
+    return with_item<K, T>(step, l);
+  }
+  switch (step) {
     case ST_F1_SUM: hipLaunchKernelGGL((k_f1_sum<K, T>), grid, block, 0, s, a, count); break;
     case ST_F1_REP: hipLaunchKernelGGL((k_f1_rep<K, T>), grid, block, 0, s, a, count); break;
     case ST_PC: hipLaunchKernelGGL((k_pc<K, T>), grid, block, 0, s, a, count); break;
@@ -529,7 +533,6 @@ template <typename T> int run_step(int step, const Args &a, int64_t count, hipSt
       Launch<T> l{a, count, s};
       return with_item<K, T>(step, l);
     }
-    case -1: break;
   }
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }

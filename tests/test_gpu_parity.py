@@ -391,3 +391,38 @@ def test_graph_capture_replays(bo):
     for p, (n, k) in enumerate(zip(ns, ks)):
         r = oracle.gauss_loss(Qs[p], k, y2[p], Ss[p])
         assert abs(host(kw["parts"])[p, 1] - r["parts"][1]) <= TOL * abs(r["parts"][1])
+
+
+@pytest.mark.parametrize("n,k", [(3001, 5), (4099, 2), (257, 1)])
+def test_padded_record_stride(bo, n, k):
+    """Records with stride ld = k + 3 (two padding slots after the band) go
+    through the per-lane work items; the factor, solve and subset inverse must
+    equal the oracle's and the padding must stay untouched."""
+    import ctypes
+    print(f"case padded stride n={n} k={k}", flush=True)
+    Q, y, _ = problem(n, k, 5000 + n + k)
+    Lref, _ = oracle.chol(Q, k)
+    ld = k + 3
+    Qp = np.zeros((n, ld))
+    Qp[:, :k + 1] = Q
+    Qb = bo.Band(dev(Qp), k)
+    Lb = bo.Band(torch.full((n, ld), 7.0, dtype=torch.float64, device="cuda"), k)
+    Sb = bo.Band(torch.full((n, ld), 7.0, dtype=torch.float64, device="cuda"), k)
+    yd, z = dev(y), torch.empty(n, dtype=torch.float64, device="cuda")
+    logdet = torch.zeros(1, dtype=torch.float64, device="cuda")
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ws = bo.workspace(n, k)
+    qc, lc, sc = Qb.c(), Lb.c(), Sb.c()
+    bo._check(bo.lib().bo_chol(0, ctypes.byref(qc), ctypes.byref(lc), bo._ptr(yd), bo._ptr(z),
+                               bo._ptr(logdet), bo._ptr(info), bo._ptr(ws), ws.numel(), bo._stream()),
+              "bo_chol")
+    bo._check(bo.lib().bo_subset_inv(0, ctypes.byref(lc), ctypes.byref(sc), bo._ptr(ws), ws.numel(),
+                                     bo._stream()), "bo_subset_inv")
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    Lg, Sg = host(Lb.band), host(Sb.band)
+    assert bands_close(Lg[:, :k + 1], Lref, n, k, TOL)
+    assert np.all(Lg[:, k + 1:] == 7.0) and np.all(Sg[:, k + 1:] == 7.0)
+    assert rel_err(host(z), oracle.trsv(Lref, k, y, 0)) <= TOL
+    assert abs(logdet.item() - oracle.logdet(Lref, k)) <= TOL * abs(oracle.logdet(Lref, k))
+    assert bands_close(Sg[:, :k + 1], oracle.subset_inv(Lref, k), n, k, TOL)
