@@ -61,6 +61,8 @@ def _load():
         "or_gauss_loss": (i32, [i64, i32, i64, P, P, P, P, P, P, P, P, P, P]),
         "or_gauss_loss_batch": (i32, [i32, P, P, P, P, P, P, P, P, P, P, P]),
         "or_forward_batch": (i32, [i32, P, P, P, P, P, P, P, P, P, P, P, P]),
+        "or_vi_kl": (None, [i64, i32, i64, P, P, P, P, P, P, P, P, P, P]),
+        "or_vi_kl_batch": (i32, [i32, P, P, P, P, P, P, P, P, P, P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -237,3 +239,34 @@ def forward_batch(ns, ks, Q, y):
     th = _load().or_forward_batch(len(ns), _p(ns), _p(ks), _p(boff), _p(voff), _p(Q), _p(y), _p(L),
                                   _p(z), _p(x), _p(Sig), _p(logdet), _p(info))
     return L, z, x, Sig, logdet, info, int(th)
+
+
+def vi_kl(Lq, Lp, k, mq, mp):
+    """KL(q || p) of Eq. (KL) / Algorithm 7 and its reverse mode.
+
+    Returns dict with parts (4,) = (KL, trace, sum log-diagonal difference,
+    squared norm), Lqbar, Lpbar, mqbar, mpbar, Sig (= I(L_q))."""
+    Lq, Lp, mq, mp = _f64(Lq), _f64(Lp), _f64(mq), _f64(mp)
+    n, ld = Lq.shape
+    parts = np.zeros(4)
+    out = {k_: np.zeros_like(Lq) for k_ in ("Lqbar", "Lpbar", "Sig")}
+    mqbar, mpbar = np.zeros_like(mq), np.zeros_like(mp)
+    _load().or_vi_kl(n, k, ld, _p(Lq), _p(Lp), _p(mq), _p(mp), _p(parts), _p(out["Lqbar"]),
+                     _p(out["Lpbar"]), _p(mqbar), _p(mpbar), _p(out["Sig"]))
+    out.update(parts=parts, mqbar=mqbar, mpbar=mpbar)
+    return out
+
+
+def vi_kl_batch(ns, ks, Lq, Lp, mq, mp):
+    """Packed batch of KL terms (layout as gauss_loss_batch).  Returns (parts
+    (nprob, 4), Lqbar, Lpbar, mqbar, mpbar, threads)."""
+    ns, ks, voff = _batch_tables(ns, ks)
+    Lq, Lp, mq, mp = _f64(Lq), _f64(Lp), _f64(mq), _f64(mp)
+    boff = np.zeros(len(ns), dtype=np.int64)
+    boff[1:] = np.cumsum(ns * (ks.astype(np.int64) + 1))[:-1]
+    parts = np.zeros((len(ns), 4))
+    Lqbar, Lpbar = np.zeros_like(Lq), np.zeros_like(Lp)
+    mqbar, mpbar = np.zeros_like(mq), np.zeros_like(mp)
+    th = _load().or_vi_kl_batch(len(ns), _p(ns), _p(ks), _p(boff), _p(voff), _p(Lq), _p(Lp), _p(mq),
+                                _p(mp), _p(parts), _p(Lqbar), _p(Lpbar), _p(mqbar), _p(mpbar))
+    return parts, Lqbar, Lpbar, mqbar, mpbar, int(th)

@@ -399,6 +399,95 @@ int or_gauss_loss(int64_t n, int k, int64_t ld, const double *Q,
   return info;
 }
 
+/* --------------------------------------------------------------------------
+ * Variational KL term (Section 3.3, Eq. (KL), Algorithm 7), in the order of
+ * Algorithm 7: the band of I(L_q), the product P(L_p, L_p^T), the trace as the
+ * element-wise product over the band, the log-diagonals, P(L_p^T, m_p - m_q).
+ * Reverse mode (Table 1 compositions):
+ *   Sigmabar_q = 1/2 w Q_p (w = 1 on the diagonal, 2 off it: a stored
+ *     off-diagonal entry of a symmetric band stands for two entries), then
+ *     Algorithm 4 gives Lqbar, plus 1/[L_q]_ii from the log term;
+ *   Lpbar = band(I(L_q) L_p) from the trace (the symmetric band of I(L_q)
+ *     suffices on the band of L_p), + d v^T restricted to the band
+ *     (v = L_p^T d, d = m_p - m_q), - 1/[L_p]_ii;
+ *   mpbar = L_p v = -mqbar.
+ * ------------------------------------------------------------------------ */
+void or_vi_kl(int64_t n, int k, int64_t ld, const double *Lq, const double *Lp,
+              const double *mq, const double *mp, double *parts, double *Lqbar,
+              double *Lpbar, double *mqbar, double *mpbar, double *Sig) {
+  size_t bsz = (size_t)(n * ld + 1) * sizeof(double);
+  size_t vsz = (size_t)(n + 1) * sizeof(double);
+  int64_t lds = 2 * (int64_t)k + 1;
+  double *Sw = Sig ? Sig : (double *)malloc(bsz);
+  double *Qp = (double *)calloc((size_t)(n * ld + 1), sizeof(double));
+  double *Sb = (double *)calloc((size_t)(n * ld + 1), sizeof(double));
+  double *Ssym = (double *)calloc((size_t)(n * lds + 1), sizeof(double));
+  double *Ob = (double *)calloc((size_t)(n * ld + 1), sizeof(double));
+  double *d = (double *)malloc(vsz);
+  double *v = (double *)malloc(vsz);
+  /* forward */
+  or_subset_inv(n, k, ld, Lq, k, ld, Sw);
+  or_gbmm(n, k, 0, ld, Lp, 0, k, 0, ld, Lp, 1, k, 0, ld, Qp);
+  double tr = 0.0, lq = 0.0, lp = 0.0, maha = 0.0;
+  for (int64_t j = 0; j < n; ++j)
+    for (int s = 0; s <= k && j + s < n; ++s) tr += (s == 0 ? 1.0 : 2.0) * Sw[j * ld + s] * Qp[j * ld + s];
+  for (int64_t i = 0; i < n; ++i) {
+    lq += log(LOW(Lq, ld, i, i));
+    lp += log(LOW(Lp, ld, i, i));
+    d[i] = mp[i] - mq[i];
+  }
+  or_gbmv(n, k, 0, ld, Lp, 1, d, v);
+  for (int64_t i = 0; i < n; ++i) maha += v[i] * v[i];
+  parts[0] = 0.5 * (tr + 2.0 * (lq - lp) + maha - (double)n);
+  parts[1] = tr;
+  parts[2] = lq - lp;
+  parts[3] = maha;
+  /* reverse: L_q */
+  for (int64_t j = 0; j < n; ++j)
+    for (int s = 0; s <= k && j + s < n; ++s) Sb[j * ld + s] = 0.5 * (s == 0 ? 1.0 : 2.0) * Qp[j * ld + s];
+  or_subset_inv_bwd(n, k, ld, Lq, Sw, Sb, Lqbar);
+  or_logdet_bwd(n, k, ld, Lq, 0.5, Lqbar);
+  /* reverse: L_p */
+  for (int64_t j = 0; j < n; ++j)
+    for (int64_t i = imax64(0, j - k); i <= imin64(n - 1, j + k); ++i)
+      Ssym[j * lds + k + (i - j)] = i >= j ? LOW(Sw, ld, i, j) : LOW(Sw, ld, j, i);
+  or_gbmm(n, k, k, lds, Ssym, 0, k, 0, ld, Lp, 0, k, 0, ld, Lpbar);
+  or_outer_band(n, k, 0, ld, d, v, Ob);
+  for (int64_t t = 0; t < n * ld; ++t) Lpbar[t] += Ob[t];
+  or_logdet_bwd(n, k, ld, Lp, -0.5, Lpbar);
+  /* reverse: means */
+  or_gbmv(n, k, 0, ld, Lp, 0, v, mpbar);
+  for (int64_t i = 0; i < n; ++i) mqbar[i] = -mpbar[i];
+  if (!Sig) free(Sw);
+  free(Qp);
+  free(Sb);
+  free(Ssym);
+  free(Ob);
+  free(d);
+  free(v);
+}
+
+int or_vi_kl_batch(int nprob, const int64_t *n, const int *k,
+                   const int64_t *boff, const int64_t *voff, const double *Lq,
+                   const double *Lp, const double *mq, const double *mp,
+                   double *parts, double *Lqbar, double *Lpbar, double *mqbar,
+                   double *mpbar) {
+  int nthreads = 1;
+#ifdef _OPENMP
+#pragma omp parallel
+  {
+#pragma omp single
+    nthreads = omp_get_num_threads();
+  }
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+  for (int p = 0; p < nprob; ++p)
+    or_vi_kl(n[p], k[p], (int64_t)k[p] + 1, Lq + boff[p], Lp + boff[p], mq + voff[p],
+             mp + voff[p], parts + 4 * p, Lqbar + boff[p], Lpbar + boff[p],
+             mqbar + voff[p], mpbar + voff[p], NULL);
+  return nthreads;
+}
+
 int or_gauss_loss_batch(int nprob, const int64_t *n, const int *k,
                         const int64_t *boff, const int64_t *voff,
                         const double *Q, const double *y, const double *S,

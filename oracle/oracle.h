@@ -103,6 +103,28 @@ int or_gauss_loss(int64_t n, int k, int64_t ld, const double *Q,
                   double *Qbar, double *ybar, double *L, double *z,
                   double *Sig, double *Lbar);
 
+/* Kullback-Leibler term of the variational objective (Section 3.3, Eq. (KL);
+ * Algorithm 7): q = N(m_q, (L_q L_q^T)^{-1}), p = N(m_p, (L_p L_p^T)^{-1}), with
+ * L_q and L_p lower bands of the same width k (stride ld), composed from I, P
+ * and the log-determinant:
+ *   KL = 1/2 (tr(I(L_q) P(L_p, L_p^T)) + 2 sum_i (log[L_q]_ii - log[L_p]_ii)
+ *             + ||P(L_p^T, m_p - m_q)||^2 - n).
+ * parts[0] = KL, parts[1] = the trace, parts[2] = sum_i log[L_q]_ii -
+ * log[L_p]_ii, parts[3] = the squared norm.  Reverse mode: Lqbar, Lpbar (stored
+ * lower-band entries), mqbar, mpbar = d KL / d (L_q, L_p, m_q, m_p); Sig (may
+ * be NULL) receives I(L_q), whose diagonal holds the marginal variances of q. */
+void or_vi_kl(int64_t n, int k, int64_t ld, const double *Lq, const double *Lp,
+              const double *mq, const double *mp, double *parts, double *Lqbar,
+              double *Lpbar, double *mqbar, double *mpbar, double *Sig);
+
+/* The KL term over a batch (layout as or_gauss_loss_batch), OpenMP across
+ * problems; parts is 4*nprob.  Returns the number of threads used. */
+int or_vi_kl_batch(int nprob, const int64_t *n, const int *k,
+                   const int64_t *boff, const int64_t *voff, const double *Lq,
+                   const double *Lp, const double *mq, const double *mp,
+                   double *parts, double *Lqbar, double *Lpbar, double *mqbar,
+                   double *mpbar);
+
 /* The same over a batch of independent problems with OpenMP across problems
  * (one problem per thread).  Problem p has n[p] rows, k[p] sub-diagonals,
  * records of stride k[p]+1 starting at element offset boff[p] of the band
