@@ -431,11 +431,10 @@ void or_vi_kl(int64_t n, int k, int64_t ld, const double *Lq, const double *Lp,
   double tr = 0.0, lq = 0.0, lp = 0.0, maha = 0.0;
   for (int64_t j = 0; j < n; ++j)
     for (int s = 0; s <= k && j + s < n; ++s) tr += (s == 0 ? 1.0 : 2.0) * Sw[j * ld + s] * Qp[j * ld + s];
-  for (int64_t i = 0; i < n; ++i) {
-    lq += log(LOW(Lq, ld, i, i));
-    lp += log(LOW(Lp, ld, i, i));
-    d[i] = mp[i] - mq[i];
-  }
+  /* the log-diagonal sums are compensated, as the log-determinant is */
+  lq = 0.5 * or_logdet(n, k, ld, Lq);
+  lp = 0.5 * or_logdet(n, k, ld, Lp);
+  for (int64_t i = 0; i < n; ++i) d[i] = mp[i] - mq[i];
   or_gbmv(n, k, 0, ld, Lp, 1, d, v);
   for (int64_t i = 0; i < n; ++i) maha += v[i] * v[i];
   parts[0] = 0.5 * (tr + 2.0 * (lq - lp) + maha - (double)n);
