@@ -187,6 +187,32 @@ bo_status bo_plan_forward(const bo_plan *plan, bo_prec prec, const bo_batch_io *
  * parts and info. */
 bo_status bo_plan_gauss_loss(const bo_plan *plan, bo_prec prec, const bo_batch_io *io, void *ws,
                              hipStream_t stream);
+/* Kullback-Leibler term of the variational objective (Section 3.3, Eq. (KL);
+ * Algorithm 7) for every problem of the plan: q = N(m_q, (L_q L_q^T)^{-1}),
+ * p = N(m_p, (L_p L_p^T)^{-1}), L_q and L_p lower bands of the plan's widths
+ * (records at boff, vectors at voff as for the other plan calls):
+ *   KL = 1/2 (tr(I(L_q) P(L_p, L_p^T)) + 2 sum_i (log[L_q]_ii - log[L_p]_ii)
+ *             + ||P(L_p^T, m_p - m_q)||^2 - n),
+ * and its reverse mode (Algorithm 4 on L_q with Sigmabar = P(L_p, L_p^T)/2,
+ * Table 1 for the products and the log-determinants).  Every array is
+ * required (the diagonals only in BO_MIXED); all are device arrays of the
+ * caller.  Outputs: Sig = I(L_q) (its diagonal holds the marginal variances of
+ * q), Lqbar, Lpbar (stored lower-band entries; Lpbar also serves as scratch
+ * during the call), mqbar, mpbar, parts[4 p .. 4 p + 3] = (KL, the trace, sum
+ * of log-diagonal differences, the squared norm).  The diagonals of L_q and
+ * L_p must be positive (else the parts are NaN); the workspace is the plan's. */
+typedef struct {
+  const void *Lq;  const double *Lqd;    /* variational factor L_q              */
+  const void *Lp;  const double *Lpd;    /* prior factor L_p                    */
+  const void *mq;  const void *mp;       /* means of q and p                    */
+  void *Sig;       double *Sigd;         /* out: I(L_q)                         */
+  void *Lqbar;     double *Lqbard;       /* out: d KL / d L_q                   */
+  void *Lpbar;     double *Lpbard;       /* out: d KL / d L_p                   */
+  void *mqbar;     void *mpbar;          /* out: d KL / d m_q, d KL / d m_p     */
+  double *parts;                          /* out: 4 per problem                  */
+} bo_kl_io;
+bo_status bo_plan_vi_kl(const bo_plan *plan, bo_prec prec, const bo_kl_io *io, void *ws,
+                        hipStream_t stream);
 /* Plan statistics: out[0] problems, out[1] chunks, out[2] groups, out[3] rows,
  * out[4] largest k. */
 bo_status bo_plan_stats(const bo_plan *plan, int64_t out[5]);

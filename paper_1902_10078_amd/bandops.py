@@ -44,6 +44,12 @@ class _BatchIO(ctypes.Structure):
         "Qbar", "Qbard", "logdet", "parts", "info")]
 
 
+class _KLIO(ctypes.Structure):
+    _fields_ = [(name, _P) for name in (
+        "Lq", "Lqd", "Lp", "Lpd", "mq", "mp", "Sig", "Sigd", "Lqbar", "Lqbard", "Lpbar", "Lpbard",
+        "mqbar", "mpbar", "parts")]
+
+
 _lib = None
 
 
@@ -73,6 +79,7 @@ def lib():
         "bo_plan_upload": (_I32, [_P, _P, _P]),
         "bo_plan_forward": (_I32, [_P, _I32, ctypes.POINTER(_BatchIO), _P, _P]),
         "bo_plan_gauss_loss": (_I32, [_P, _I32, ctypes.POINTER(_BatchIO), _P, _P]),
+        "bo_plan_vi_kl": (_I32, [_P, _I32, ctypes.POINTER(_KLIO), _P, _P]),
         "bo_plan_stats": (_I32, [_P, ctypes.POINTER(_I64)]),
         "bo_plan_destroy": (_I32, [_P]),
         "bo_wide_workspace_size": (_I32, [ctypes.POINTER(_Problem), _I32, ctypes.POINTER(ctypes.c_size_t)]),
@@ -97,7 +104,7 @@ def lib():
 EXPORTED = ("bo_workspace_size", "bo_chol", "bo_trsv", "bo_subset_inv", "bo_gbmm", "bo_gbmv",
             "bo_outer_band", "bo_chol_bwd", "bo_subset_inv_bwd", "bo_trsv_bwd", "bo_logdet_bwd",
             "bo_plan_create", "bo_plan_workspace_size", "bo_plan_upload", "bo_plan_forward",
-            "bo_plan_gauss_loss", "bo_plan_stats", "bo_plan_destroy", "bo_wide_workspace_size",
+            "bo_plan_gauss_loss", "bo_plan_vi_kl", "bo_plan_stats", "bo_plan_destroy", "bo_wide_workspace_size",
             "bo_wide_upload", "bo_wide_forward", "bo_wide_gauss_loss", "bo_profile_enable",
             "bo_profile_read", "bo_profile_slots", "bo_profile_slot_name", "bo_status_string",
             "bo_last_error")
@@ -364,6 +371,18 @@ class Plan:
     def gauss_loss(self, prec: int, io: _BatchIO):
         _check(lib().bo_plan_gauss_loss(self.h, prec, ctypes.byref(io), _ptr(self.ws), _stream()),
                "bo_plan_gauss_loss")
+
+    def kl_io(self, **arrays) -> _KLIO:
+        io = _KLIO()
+        for k_, v in arrays.items():
+            setattr(io, k_, _ptr(v))
+        return io
+
+    def vi_kl(self, prec: int, io: _KLIO):
+        """KL term of the variational objective for every problem (see
+        bo_plan_vi_kl): fills io.Sig, the four gradients and io.parts."""
+        _check(lib().bo_plan_vi_kl(self.h, prec, ctypes.byref(io), _ptr(self.ws), _stream()),
+               "bo_plan_vi_kl")
 
 
 class WidePlan:

@@ -11,6 +11,7 @@
 
 #include "../../include/bandops.h"
 #include "bandops_driver.hpp"
+#include "bandops_vi.hpp"
 
 using bo::Args;
 using bo::Sched;
@@ -131,7 +132,8 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const Args A) {
 // ------------------------------------------------------------ profiling
 // When enabled, every launch is bracketed by a pair of events on its stream;
 // bo_profile_read() waits for them and sums the durations per step kind.
-constexpr int kProfSlots = bo::ST_COUNT + 6;   // + clear, finalize, the four wide passes
+constexpr int kProfSlots = bo::ST_COUNT + 8;   // + clear, finalize, the four wide passes, the KL term's two
+constexpr int kSlotViPre = bo::ST_COUNT + 6, kSlotViPost = bo::ST_COUNT + 7;   // row kernels
 struct ProfRec {
   int slot;
   hipEvent_t a, b;
@@ -365,7 +367,7 @@ static const char *const kStepNames[kProfSlots] = {
     "chunk_product", "fs_summary", "fs_replay", "f2_summary", "f2_replay", "b1_summary",
     "b1_replay", "b2_summary", "b2_replay", "asc_group_compose", "asc_group_sweep",
     "asc_chunk_sweep", "desc_group_compose", "desc_group_sweep", "desc_chunk_sweep",
-    "clear_partials", "finalize", "wide_f1", "wide_f2", "wide_b1", "wide_b2"};
+    "clear_partials", "finalize", "wide_f1", "wide_f2", "wide_b1", "wide_b2", "vi_pre", "vi_post"};
 
 extern "C" int bo_profile_slots(void) { return kProfSlots; }
 
@@ -709,6 +711,58 @@ extern "C" bo_status bo_plan_gauss_loss(const bo_plan *plan, bo_prec prec, const
   GpuBE be{stream};
   return dev_status(bo::pipe_gauss_loss(be, plan->s, A, (int)prec, fuse_summaries()),
                     "bo_plan_gauss_loss");
+}
+
+extern "C" bo_status bo_plan_vi_kl(const bo_plan *plan, bo_prec prec, const bo_kl_io *io, void *ws,
+                                   hipStream_t stream) {
+  if (!plan || !io || !ws) return fail(BO_EINVAL, "bo_plan_vi_kl: null argument");
+  if (prec != BO_F64 && prec != BO_MIXED) return fail(BO_EINVAL, "unknown precision");
+  if (!io->Lq || !io->Lp || !io->mq || !io->mp || !io->Sig || !io->Lqbar || !io->Lpbar || !io->mqbar ||
+      !io->mpbar || !io->parts)
+    return fail(BO_EINVAL, "bo_plan_vi_kl: every array is required");
+  if (prec == BO_MIXED && (!io->Lqd || !io->Lpd || !io->Sigd || !io->Lqbard || !io->Lpbard))
+    return fail(BO_EINVAL, "bo_plan_vi_kl: BO_MIXED needs every FP64 diagonal");
+  if (prec == BO_F64 && (io->Lqd || io->Lpd || io->Sigd || io->Lqbard || io->Lpbard))
+    return fail(BO_EINVAL, "bo_plan_vi_kl: FP64 diagonals are for BO_MIXED only");
+  Args A = Args{};
+  bo::bind_sched(plan->s, ws, false, A);
+  A.L = const_cast<void *>(io->Lq);   // read only: the passes below never write L
+  A.Ld = const_cast<double *>(io->Lqd);
+  A.S = io->Sig;
+  A.Sd = io->Sigd;
+  A.Sb = io->Lpbar;
+  A.Sbd = io->Lpbard;
+  A.Lb = io->Lqbar;
+  A.Lbd = io->Lqbard;
+  const bo_vi::KLP P{io->Lp, io->Lpd, io->mq, io->mp, io->Lpbar, io->Lpbard, io->mqbar, io->mpbar, io->parts};
+  GpuBE be{stream};
+  auto launch = [&](int which, int64_t count, const Args &a) -> int {
+    if (count <= 0) return 0;
+    const dim3 grid((unsigned)count);
+    const int slot = which == 0 ? kSlotViPre : which == 3 ? bo::ST_COUNT + 1 : kSlotViPost;
+    return profiled(slot, stream, [&] {
+      const bool f64 = prec == BO_F64;
+      const dim3 rows(bo_vi::kRowBlock);
+      switch (which) {
+        case 0:
+          if (f64) hipLaunchKernelGGL(bo_vi::k_kl_pre<double>, grid, rows, 0, stream, a, P);
+          else hipLaunchKernelGGL(bo_vi::k_kl_pre<float>, grid, rows, 0, stream, a, P);
+          break;
+        case 1:
+          if (f64) hipLaunchKernelGGL(bo_vi::k_kl_post<double>, grid, rows, 0, stream, a, P);
+          else hipLaunchKernelGGL(bo_vi::k_kl_post<float>, grid, rows, 0, stream, a, P);
+          break;
+        case 2:
+          if (f64) hipLaunchKernelGGL(bo_vi::k_kl_neg<double>, grid, rows, 0, stream, a, P);
+          else hipLaunchKernelGGL(bo_vi::k_kl_neg<float>, grid, rows, 0, stream, a, P);
+          break;
+        default:
+          hipLaunchKernelGGL(bo_vi::k_kl_finalize, grid, dim3(64), 0, stream, a, P.parts);
+      }
+      return hipGetLastError() == hipSuccess ? 0 : -2;
+    });
+  };
+  return dev_status(bo_vi::pipe_vi_kl(be, plan->s, A, (int)prec, launch), "bo_plan_vi_kl");
 }
 
 extern "C" bo_status bo_plan_stats(const bo_plan *plan, int64_t out[5]) {
