@@ -74,6 +74,19 @@ def bytes_per_row(k: int, prec: int, forward_only: bool = False):
     }
 
 
+def vi_bytes_per_row(k: int, prec: int):
+    """Algorithmic bytes per row of the KL term's kernels (Algorithm 7)."""
+    wb, wv = record_bytes(k, prec)
+    return {"vi_pre": 2 * wb + 8 + 3 * wv,          # L_p, diag L_q, m_q, m_p -> Q_p / 2, v
+            "chunk_product": wb,                     # L_q
+            "f2_summary": wb,                        # L_q
+            "f2_replay": 3 * wb,                     # L_q, Q_p / 2 -> Sigma
+            "b1_summary": 2 * wb,                    # L_q, Q_p / 2
+            "b1_replay": 4 * wb,                     # L_q, Sigma, Q_p / 2 -> Lqbar
+            "vi_post": 4 * wb + 24 + 6 * wv,         # L_p, Sigma, diags, m_q, m_p, v -> Lpbar, mpbar, mqbar
+            "unit": 5 * wb + 4 * wv}                 # inputs L_q, L_p, m_q, m_p; outputs Sigma and the gradients
+
+
 def wide_bytes_per_row():
     """Algorithmic bytes per row of the wide passes (mixed storage, k = 64)."""
     wb, _ = record_bytes(64, 1)
@@ -84,11 +97,12 @@ def wide_bytes_per_row():
             "unit": 11 * wb}
 
 
-def batch_bytes(ns, ks, prec, forward_only):
+def batch_bytes(ns, ks, prec, forward_only, vi=False):
     """Algorithmic bytes of one step of each kernel kind over the batch."""
     tot = {}
     for n, k in zip(ns, ks):
-        for nm, b in bytes_per_row(k, prec, forward_only).items():
+        per = vi_bytes_per_row(k, prec) if vi else bytes_per_row(k, prec, forward_only)
+        for nm, b in per.items():
             tot[nm] = tot.get(nm, 0) + b * n
     return tot
 
@@ -245,6 +259,77 @@ def make_matern32(args):
     return [Q.shape[0]], [3], ([Q], [y], None)
 
 
+class VIWorkload:
+    """The KL term of the variational objective over a batch (inputs resident
+    on the device): L_q, L_p, m_q, m_p in, I(L_q), the four gradients and the
+    parts out."""
+
+    def __init__(self, bo, torch, dev, ns, ks, prec, host_inputs, target_chunks=0):
+        self.bo, self.torch, self.dev = bo, torch, dev
+        self.ns, self.ks, self.prec = ns, ks, prec
+        Lqs, Lps, mqs, mps = host_inputs
+        vdt = torch.float64 if prec == bo.F64 else torch.float32
+        up = lambda arrs: torch.from_numpy(np.concatenate([a.ravel() for a in arrs])).to(dev, vdt)
+        diag = lambda arrs: torch.from_numpy(np.concatenate([a[:, 0] for a in arrs])).to(dev)
+        kw = dict(Lq=up(Lqs), Lp=up(Lps), mq=up(mqs), mp=up(mps))
+        E, N = kw["Lq"].numel(), kw["mq"].numel()
+        for nm in ("Sig", "Lqbar", "Lpbar"):
+            kw[nm] = torch.zeros(E, dtype=vdt, device=dev)
+        for nm in ("mqbar", "mpbar"):
+            kw[nm] = torch.zeros(N, dtype=vdt, device=dev)
+        kw["parts"] = torch.zeros((len(ns), 4), dtype=torch.float64, device=dev)
+        if prec == bo.MIXED:
+            kw["Lqd"], kw["Lpd"] = diag(Lqs), diag(Lps)
+            for nm in ("Sigd", "Lqbard", "Lpbard"):
+                kw[nm] = torch.zeros(N, dtype=torch.float64, device=dev)
+        self.kw = kw
+        self.set_schedule(target_chunks)
+
+    def set_schedule(self, target_chunks: int):
+        self.plan = self.bo.Plan(self.ns, self.ks, target_chunks=target_chunks, device=self.dev)
+        self.io = self.plan.kl_io(**self.kw)
+
+    def step(self):
+        self.plan.vi_kl(self.prec, self.io)
+
+    def plain_steps(self):
+        """The plain FP64 form: one plan per matrix, host loop, no graph."""
+        bo = self.bo
+        out = []
+        for p in range(len(self.ns)):
+            n, k = self.ns[p], self.ks[p]
+            pl = bo.Plan([n], [k], device=self.dev)
+            o, v, sz = self.plan.boff[p], self.plan.voff[p], n * (k + 1)
+            kw = {}
+            for nm, t in self.kw.items():
+                if nm == "parts":
+                    kw[nm] = t[p]
+                elif nm in ("mq", "mp", "mqbar", "mpbar") or nm.endswith("d"):
+                    kw[nm] = t[v:v + n]
+                else:
+                    kw[nm] = t[o:o + sz]
+            out.append((pl, pl.kl_io(**kw)))
+
+        def run():
+            for pl, pio in out:
+                pl.vi_kl(bo.F64, pio)
+        return run
+
+
+def make_vi(args):
+    """L_q, L_p lower bands (diagonal U[1,2], off-diagonal N(0, 0.3^2)) and
+    normal means: the variational and prior factors of Algorithm 7."""
+    from paper_1902_10078_amd import inputs
+    Lqs, Lps, mqs, mps = [], [], [], []
+    for b in range(args.batch):
+        rng = np.random.default_rng(7000 + b)
+        Lqs.append(inputs.random_lower_band(args.n_vi, 5, rng))
+        Lps.append(inputs.random_lower_band(args.n_vi, 5, rng))
+        mqs.append(rng.normal(size=args.n_vi))
+        mps.append(rng.normal(size=args.n_vi))
+    return [args.n_vi] * args.batch, [5] * args.batch, (Lqs, Lps, mqs, mps)
+
+
 class WideWorkload:
     """The wide block-banded batch on the device (mixed storage)."""
 
@@ -290,13 +375,23 @@ def make_wide(args, bo, torch, dev):
     return ns, [64] * len(ns), (Qs, ys, Ws)
 
 
-def cpu_baseline(host_inputs, ns, ks, nsample: int):
+def cpu_baseline(host_inputs, ns, ks, nsample: int, vi: bool = False):
     """The FP64 oracle as it stands, OpenMP across problems, on a bounded
     sample of the workload's problems."""
     import oracle
-    Qs, ys, Ss = host_inputs
     idx = list(range(min(nsample, len(ns))))
     sn, sk = [ns[i] for i in idx], [ks[i] for i in idx]
+    if vi:
+        cat = lambda arrs: np.concatenate([arrs[i].ravel() for i in idx])
+        Lqs, Lps, mqs, mps = host_inputs
+        t0 = time.perf_counter()
+        parts, _, _, _, _, threads = oracle.vi_kl_batch(sn, sk, cat(Lqs), cat(Lps), cat(mqs), cat(mps))
+        dt = time.perf_counter() - t0
+        rows = sum(sn)
+        return dict(value=rows / dt, unit="band-rows/s", cores=int(min(threads, len(idx))), kind="oracle",
+                    sample=f"{len(idx)} of the workload's {len(ns)} problems ({rows} rows), FP64 C oracle, "
+                           f"OpenMP across problems, {dt:.2f} s wall"), parts
+    Qs, ys, Ss = host_inputs
     Qf = np.concatenate([Qs[i].ravel() for i in idx])
     yf = np.concatenate([ys[i] for i in idx])
     t0 = time.perf_counter()
@@ -318,8 +413,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["matern52_loss", "uneven_forward", "matern32_forward", "wide_loss"],
-                    default="matern52_loss")
+    ap.add_argument("--workload", choices=["matern52_loss", "uneven_forward", "matern32_forward", "wide_loss",
+                                           "vi_kl"], default="matern52_loss")
     ap.add_argument("--prec", choices=["f64", "mixed"], default=None,
                     help="storage format (default: f64; mixed for uneven_forward)")
     ap.add_argument("--batch", type=int, default=16)
@@ -329,6 +424,7 @@ def main():
     ap.add_argument("--ell", type=float, default=10.0)
     ap.add_argument("--nwide", type=int, default=8)
     ap.add_argument("--n-wide", type=int, default=200_000)
+    ap.add_argument("--n-vi", type=int, default=1_000_000, help="rows per problem of the KL batch")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="problems timed on the CPU oracle (default: 8 for the loss batch, "
                          "256 for the uneven batch, 1 otherwise)")
@@ -366,6 +462,7 @@ def main():
     t0 = time.perf_counter()
     forward_only = args.workload in ("uneven_forward", "matern32_forward")
     wide = args.workload == "wide_loss"
+    vi = args.workload == "vi_kl"
     if args.workload == "matern52_loss":
         ns, ks, host_inputs = make_matern52(args)
         cfg = {"workload": f"matern52_ssm_batch{len(ns)}_rows{ns[0]}_k5_gauss_loss_fwd_bwd",
@@ -376,6 +473,11 @@ def main():
         cfg = {"workload": f"uneven_batch{len(ns)}_n256-65536_k1-3-5-11_forward",
                "batch": len(ns), "rows": sum(ns), "k": "1,3,5,11"}
         nsample = args.cpu_sample or 256
+    elif vi:
+        ns, ks, host_inputs = make_vi(args)
+        cfg = {"workload": f"vi_kl_batch{len(ns)}_rows{ns[0]}_k5_fwd_bwd",
+               "batch": len(ns), "rows_per_problem": ns[0], "k": 5}
+        nsample = args.cpu_sample or 8
     elif wide:
         ns, ks, host_inputs = make_wide(args, bo, torch, dev)
         cfg = {"workload": f"wide_blockband_batch{len(ns)}_rows{ns[0]}_k64_loss_fwd_bwd",
@@ -393,7 +495,10 @@ def main():
         W = WideWorkload(bo, torch, dev, ns, host_inputs)
         log(f"wide plan: {W.stats}, workspace {W.plan.ws.numel() / 2**20:.1f} MiB")
     else:
-        W = Workload(bo, torch, dev, ns, ks, prec, host_inputs, forward_only, args.target_chunks)
+        if vi:
+            W = VIWorkload(bo, torch, dev, ns, ks, prec, host_inputs, args.target_chunks)
+        else:
+            W = Workload(bo, torch, dev, ns, ks, prec, host_inputs, forward_only, args.target_chunks)
         if args.autotune:
             from paper_1902_10078_amd import autotune
 
@@ -405,11 +510,13 @@ def main():
             W.set_schedule(tuned["target_chunks"])
             log(f"autotune: {tuned}")
         log(f"plan: {W.plan.stats}, workspace {W.plan.ws.numel() / 2**20:.1f} MiB")
-    info = W.kw["info"]
     for _ in range(max(args.warmup, 1)):
         W.step()
     torch.cuda.synchronize()
-    assert int(info.max().item()) == 0, "Cholesky failed on the benchmark inputs"
+    if "info" in W.kw:
+        assert int(W.kw["info"].max().item()) == 0, "Cholesky failed on the benchmark inputs"
+    else:
+        assert bool(torch.isfinite(W.kw["parts"]).all()), "non-finite KL on the benchmark inputs"
 
     use_graph = not args.no_graph
     if use_graph:
@@ -448,7 +555,7 @@ def main():
     if wide:
         bb = {nm: b * rows for nm, b in wide_bytes_per_row().items()}
     else:
-        bb = batch_bytes(ns, ks, prec, forward_only)
+        bb = batch_bytes(ns, ks, prec, forward_only, vi)
     kern = {}
     for name, (tms, cnt) in prof.items():
         entry = dict(avg_ms=tms / cnt, launches_per_step=cnt / nprof, ms_per_step=tms / nprof)
@@ -473,7 +580,12 @@ def main():
     # the plain FP64 one-matrix-per-launch form: per-problem plans, host loop, no graph
     vs_plain = None
     if not args.no_plain and not wide:
-        W64 = W if prec == bo.F64 else Workload(bo, torch, dev, ns, ks, bo.F64, host_inputs, forward_only)
+        if prec == bo.F64:
+            W64 = W
+        elif vi:
+            W64 = VIWorkload(bo, torch, dev, ns, ks, bo.F64, host_inputs)
+        else:
+            W64 = Workload(bo, torch, dev, ns, ks, bo.F64, host_inputs, forward_only)
         plain_step = W64.plain_steps()
         plain_step()
         torch.cuda.synchronize()
@@ -514,7 +626,7 @@ def main():
         "vs_fp64_plain": vs_plain,
     }
     if not args.no_cpu:
-        cb, ref = cpu_baseline(host_inputs, ns, ks, nsample)
+        cb, ref = cpu_baseline(host_inputs, ns, ks, nsample, vi)
         src = W.kw["logdet"] if forward_only else W.kw["parts"]
         gp = src.cpu().numpy()[: len(ref)]
         cb["max_rel_diff_vs_gpu"] = float(np.max(np.abs(gp - ref) / np.maximum(np.abs(ref), 1e-300)))

@@ -736,21 +736,22 @@ extern "C" bo_status bo_plan_vi_kl(const bo_plan *plan, bo_prec prec, const bo_k
   A.Lbd = io->Lqbard;
   const bo_vi::KLP P{io->Lp, io->Lpd, io->mq, io->mp, io->Lpbar, io->Lpbard, io->mqbar, io->mpbar, io->parts};
   GpuBE be{stream};
-  auto launch = [&](int which, int64_t count, const Args &a) -> int {
+  auto launch = [&](int which, int64_t count, const Args &a, int k) -> int {
     if (count <= 0) return 0;
     const dim3 grid((unsigned)count);
+    const size_t pre_lds = bo_vi::pre_lds_bytes(k + 1), post_lds = bo_vi::post_lds_bytes(k + 1);
     const int slot = which == 0 ? kSlotViPre : which == 3 ? bo::ST_COUNT + 1 : kSlotViPost;
     return profiled(slot, stream, [&] {
       const bool f64 = prec == BO_F64;
       const dim3 rows(bo_vi::kRowBlock);
       switch (which) {
         case 0:
-          if (f64) hipLaunchKernelGGL(bo_vi::k_kl_pre<double>, grid, rows, 0, stream, a, P);
-          else hipLaunchKernelGGL(bo_vi::k_kl_pre<float>, grid, rows, 0, stream, a, P);
+          if (f64) hipLaunchKernelGGL(bo_vi::k_kl_pre<double>, grid, rows, pre_lds, stream, a, P);
+          else hipLaunchKernelGGL(bo_vi::k_kl_pre<float>, grid, rows, pre_lds, stream, a, P);
           break;
         case 1:
-          if (f64) hipLaunchKernelGGL(bo_vi::k_kl_post<double>, grid, rows, 0, stream, a, P);
-          else hipLaunchKernelGGL(bo_vi::k_kl_post<float>, grid, rows, 0, stream, a, P);
+          if (f64) hipLaunchKernelGGL(bo_vi::k_kl_post<double>, grid, rows, post_lds, stream, a, P);
+          else hipLaunchKernelGGL(bo_vi::k_kl_post<float>, grid, rows, post_lds, stream, a, P);
           break;
         case 2:
           if (f64) hipLaunchKernelGGL(bo_vi::k_kl_neg<double>, grid, rows, 0, stream, a, P);

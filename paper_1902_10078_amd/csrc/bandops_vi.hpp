@@ -76,33 +76,83 @@ __device__ __forceinline__ ChunkRows chunk_of_block(const bo::Args &A) {
   return r;
 }
 
+// LDS staging.  A workgroup takes its chunk's rows in tiles of kRowBlock
+// (one thread per row); the records a tile needs, with a halo of up to k
+// records on either side, are copied into LDS as FP64 by consecutive threads
+// reading consecutive elements (records of a problem are contiguous), and
+// output records go back the same way.  Slots past the matrix end are never
+// read by the row formulas, so pads in the inputs are harmless.
+constexpr int kMaxW = 13;   // record length at the widest compiled k
+
+// Records [r0, r1) of a band (clipped to [0, n)) into dst[(r - r0) * W + s].
+template <typename T>
+__device__ __forceinline__ void stage_band(double *dst, const T *rec, const double *diag, int64_t r0, int64_t r1,
+                                           int64_t n, int W) {
+  const int64_t lo = r0 > 0 ? r0 : 0, hi = r1 < n ? r1 : n;
+  const int skip = (int)(lo - r0);
+  for (int64_t e = threadIdx.x; e < (hi - lo) * W; e += kRowBlock)
+    if (!(diag && e % W == 0)) dst[skip * W + e] = (double)rec[lo * W + e];
+  if (diag)
+    for (int64_t r = lo + threadIdx.x; r < hi; r += kRowBlock) dst[(r - r0) * W] = diag[r];
+}
+// src[(r - r0) * W + s] into records [r0, r1) of a band (and its FP64 diagonal).
+template <typename T>
+__device__ __forceinline__ void store_band(T *rec, double *diag, const double *src, int64_t r0, int64_t r1, int W) {
+  for (int64_t e = threadIdx.x; e < (r1 - r0) * W; e += kRowBlock) rec[r0 * W + e] = (T)src[e];
+  if (diag)
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += kRowBlock) diag[r] = src[(r - r0) * W];
+}
+
+// LDS of the row kernels for records of W elements (launch size, bytes).
+__host__ __device__ constexpr int pre_lds_bytes(int W) {
+  return (kRowBlock + (kRowBlock + W - 1) * W + kRowBlock * W + (kRowBlock + W - 1)) * 8;
+}
+__host__ __device__ constexpr int post_lds_bytes(int W) { return (2 * (kRowBlock + W - 1) * (W + 1)) * 8; }
+
 template <typename T> __global__ void __launch_bounds__(kRowBlock) k_kl_pre(const bo::Args A, const KLP P) {
-  __shared__ double sh[kRowBlock];
+  extern __shared__ double dyn[];
   const ChunkRows C = chunk_of_block(A);
   const bo::ProbDesc &pd = *C.pd;
-  const int K = pd.k;
-  const int64_t n = pd.n, ld = pd.ld;
-  const LB<T> Lq{(const T *)A.L + pd.boff, A.Ld ? A.Ld + pd.voff : nullptr, ld};
-  const LB<T> Lp{(const T *)P.Lp + pd.boff, P.Lpd ? P.Lpd + pd.voff : nullptr, ld};
+  const int K = pd.k, W = K + 1, TL = kRowBlock + K;
+  double *sh = dyn;                    // block sums
+  double *sLp = sh + kRowBlock;        // L_p records [t0 - k, t1)
+  double *sQ = sLp + TL * W;           // Q_p / 2 records [t0, t1)
+  double *sd = sQ + kRowBlock * W;     // d = m_p - m_q on [t0, t1 + k)
+  const int64_t n = pd.n;
+  const LB<T> Lq{(const T *)A.L + pd.boff, A.Ld ? A.Ld + pd.voff : nullptr, pd.ld};
+  const T *Lp = (const T *)P.Lp + pd.boff;
+  const double *Lpd = P.Lpd ? P.Lpd + pd.voff : nullptr;
   const T *mq = (const T *)P.mq + pd.voff, *mp = (const T *)P.mp + pd.voff;
   T *sb = (T *)P.Lpbar + pd.boff;
   double *sbd = P.Lpbard ? P.Lpbard + pd.voff : nullptr;
   T *v = (T *)P.mqbar + pd.voff;
   double lsum = 0.0, vsum = 0.0;
-  for (int64_t j = C.a + threadIdx.x; j < C.b; j += kRowBlock) {
-    for (int s = 0; s <= K; ++s) {
-      const int64_t i = j + s;
-      double q = 0.0;   // (L_p L_p^T)_ij over the columns m both rows reach
-      if (i < n)
-        for (int64_t m = (i - K > 0 ? i - K : 0); m <= j; ++m) q += Lp.at(i, m) * Lp.at(j, m);
-      sb[j * ld + s] = (T)(0.5 * q);
-      if (s == 0 && sbd) sbd[j] = 0.5 * q;
+  for (int64_t t0 = C.a; t0 < C.b; t0 += kRowBlock) {
+    const int64_t t1 = (t0 + kRowBlock < C.b) ? t0 + kRowBlock : C.b;
+    __syncthreads();   // the previous tile's reads of LDS are done
+    stage_band(sLp, Lp, Lpd, t0 - K, t1, n, W);
+    for (int64_t r = t0 + threadIdx.x; r < t1 + K; r += kRowBlock)
+      sd[r - t0] = r < n ? (double)mp[r] - (double)mq[r] : 0.0;
+    __syncthreads();
+    const int64_t j = t0 + threadIdx.x;
+    if (j < t1) {
+      // element (r, m) of L_p, m in [t0 - k, t1)
+      auto lp = [&](int64_t r, int64_t m) { return sLp[(m - (t0 - K)) * W + (r - m)]; };
+      for (int s = 0; s < W; ++s) {
+        const int64_t i = j + s;
+        double q = 0.0;   // (L_p L_p^T)_ij over the columns both rows reach
+        if (i < n)
+          for (int64_t m = (i - K > 0 ? i - K : 0); m <= j; ++m) q += lp(i, m) * lp(j, m);
+        sQ[threadIdx.x * W + s] = 0.5 * q;
+      }
+      double vj = 0.0;
+      for (int s = 0; s < W && j + s < n; ++s) vj += lp(j + s, j) * sd[j + s - t0];
+      v[j] = (T)vj;
+      vsum += vj * vj;
+      lsum += log(Lq.at(j, j)) - log(lp(j, j));
     }
-    double vj = 0.0;
-    for (int s = 0; s <= K && j + s < n; ++s) vj += Lp.at(j + s, j) * ((double)mp[j + s] - (double)mq[j + s]);
-    v[j] = (T)vj;
-    vsum += vj * vj;
-    lsum += log(Lq.at(j, j)) - log(Lp.at(j, j));
+    __syncthreads();
+    store_band(sb, sbd, sQ, t0, t1, W);
   }
   lsum = block_sum(lsum, sh);
   vsum = block_sum(vsum, sh);
@@ -113,13 +163,20 @@ template <typename T> __global__ void __launch_bounds__(kRowBlock) k_kl_pre(cons
 }
 
 template <typename T> __global__ void __launch_bounds__(kRowBlock) k_kl_post(const bo::Args A, const KLP P) {
+  extern __shared__ double dyn[];
   const ChunkRows C = chunk_of_block(A);
   const bo::ProbDesc &pd = *C.pd;
-  const int K = pd.k;
+  const int K = pd.k, W = K + 1, TL = kRowBlock + K;
+  double *sLp = dyn;                   // L_p records [t0 - k, t1)
+  double *sS = sLp + TL * W;           // Sigma records [t0, t1 + k); reused for the Lpbar output
+  double *sd = sS + TL * W;            // d on [t0, t1 + k)
+  double *sv = sd + TL;                // v on [t0 - k, t1)
   const int64_t n = pd.n, ld = pd.ld;
   const LB<T> Lq{(const T *)A.L + pd.boff, A.Ld ? A.Ld + pd.voff : nullptr, ld};
-  const LB<T> Lp{(const T *)P.Lp + pd.boff, P.Lpd ? P.Lpd + pd.voff : nullptr, ld};
-  const LB<T> Sg{(const T *)A.S + pd.boff, A.Sd ? A.Sd + pd.voff : nullptr, ld};
+  const T *Lp = (const T *)P.Lp + pd.boff;
+  const double *Lpd = P.Lpd ? P.Lpd + pd.voff : nullptr;
+  const T *Sg = (const T *)A.S + pd.boff;
+  const double *Sgd = A.Sd ? A.Sd + pd.voff : nullptr;
   const T *mq = (const T *)P.mq + pd.voff, *mp = (const T *)P.mp + pd.voff;
   const T *v = (const T *)P.mqbar + pd.voff;
   T *lqb = (T *)A.Lb + pd.boff;
@@ -127,29 +184,49 @@ template <typename T> __global__ void __launch_bounds__(kRowBlock) k_kl_post(con
   T *lpb = (T *)P.Lpbar + pd.boff;
   double *lpbd = P.Lpbard ? P.Lpbard + pd.voff : nullptr;
   T *mpb = (T *)P.mpbar + pd.voff;
-  for (int64_t j = C.a + threadIdx.x; j < C.b; j += kRowBlock) {
-    // log-determinant term of L_q
-    const double g0 = (lqbd ? lqbd[j] : (double)lqb[j * ld]) + 1.0 / Lq.at(j, j);
-    lqb[j * ld] = (T)g0;
-    if (lqbd) lqbd[j] = g0;
-    // L_p: trace, squared-norm and log terms
-    const double vj = (double)v[j];
-    const int64_t m1 = (j + K < n - 1) ? j + K : n - 1;
-    for (int s = 0; s <= K; ++s) {
-      const int64_t i = j + s;
-      double g = 0.0;
-      if (i < n) {
-        for (int64_t m = j; m <= m1; ++m) g += (i >= m ? Sg.at(i, m) : Sg.at(m, i)) * Lp.at(m, j);
-        g += ((double)mp[i] - (double)mq[i]) * vj;
-        if (s == 0) g -= 1.0 / Lp.at(j, j);
+  for (int64_t t0 = C.a; t0 < C.b; t0 += kRowBlock) {
+    const int64_t t1 = (t0 + kRowBlock < C.b) ? t0 + kRowBlock : C.b;
+    __syncthreads();
+    stage_band(sLp, Lp, Lpd, t0 - K, t1, n, W);
+    stage_band(sS, Sg, Sgd, t0, t1 + K, n, W);
+    for (int64_t r = t0 + threadIdx.x; r < t1 + K; r += kRowBlock)
+      sd[r - t0] = r < n ? (double)mp[r] - (double)mq[r] : 0.0;
+    for (int64_t r = t0 - K + threadIdx.x; r < t1; r += kRowBlock) sv[r - (t0 - K)] = r >= 0 ? (double)v[r] : 0.0;
+    __syncthreads();
+    const int64_t j = t0 + threadIdx.x;
+    double g[kMaxW];
+    if (j < t1) {
+      auto lp = [&](int64_t r, int64_t m) { return sLp[(m - (t0 - K)) * W + (r - m)]; };
+      auto sg = [&](int64_t r, int64_t m) {   // symmetric: element (r, m) from the stored lower band
+        return r >= m ? sS[(m - t0) * W + (r - m)] : sS[(r - t0) * W + (m - r)];
+      };
+      // log-determinant term of L_q
+      const double g0 = (lqbd ? lqbd[j] : (double)lqb[j * ld]) + 1.0 / Lq.at(j, j);
+      lqb[j * ld] = (T)g0;
+      if (lqbd) lqbd[j] = g0;
+      // L_p: trace, squared-norm and log terms
+      const double vj = sv[j - (t0 - K)];
+      const int64_t m1 = (j + K < n - 1) ? j + K : n - 1;
+      for (int s = 0; s < W; ++s) {
+        const int64_t i = j + s;
+        double a = 0.0;
+        if (i < n) {
+          for (int64_t m = j; m <= m1; ++m) a += sg(i, m) * lp(m, j);
+          a += sd[i - t0] * vj;
+          if (s == 0) a -= 1.0 / lp(j, j);
+        }
+        g[s] = a;
       }
-      lpb[j * ld + s] = (T)g;
-      if (s == 0 && lpbd) lpbd[j] = g;
+      // means: L_p v
+      double mb = 0.0;
+      for (int64_t m = (j - K > 0 ? j - K : 0); m <= j; ++m) mb += lp(j, m) * sv[m - (t0 - K)];
+      mpb[j] = (T)mb;
     }
-    // means: L_p v
-    double mb = 0.0;
-    for (int64_t m = (j - K > 0 ? j - K : 0); m <= j; ++m) mb += Lp.at(j, m) * (double)v[m];
-    mpb[j] = (T)mb;
+    __syncthreads();   // every read of sS is done: reuse it for the output records
+    if (j < t1)
+      for (int s = 0; s < W; ++s) sS[threadIdx.x * W + s] = g[s];
+    __syncthreads();
+    store_band(lpb, lpbd, sS, t0, t1, W);
   }
 }
 
@@ -202,7 +279,7 @@ __global__ void __launch_bounds__(64) k_kl_finalize(const bo::Args A, double *pa
 // chunk maps fused in for k <= KMAX_FUSED), B1 (Algorithm 4 with Sigmabar =
 // Q_p / 2 and its trace), post, neg, finalize.  A carries the schedule, L =
 // L_q, S = Sig, Sb = Lpbar (Q_p / 2), Lb = Lqbar; `launch(which, grid,
-// range)` runs pre (0), post (1), neg (2) or finalize (3).
+// range, k)` runs pre (0), post (1), neg (2) or finalize (3).
 template <class BE, class Launch>
 int pipe_vi_kl(BE &be, const bo::Sched &s, bo::Args A, int prec, Launch &&launch) {
   A.sb_is_S = 1;
@@ -214,7 +291,7 @@ int pipe_vi_kl(BE &be, const bo::Sched &s, bo::Args A, int prec, Launch &&launch
   if (int e = bo::seq_clear(be, s, A)) return e;
   for (const bo::KRange &r : s.ranges) {
     bo::set_range(A, r);
-    if (int e = launch(0, r.c_cnt, A)) return e;
+    if (int e = launch(0, r.c_cnt, A, r.K)) return e;
   }
   if (int e = bo::seq_pc(be, s, A, prec)) return e;
   bo::Args F2 = A;
@@ -227,10 +304,10 @@ int pipe_vi_kl(BE &be, const bo::Sched &s, bo::Args A, int prec, Launch &&launch
   for (int which = 1; which <= 2; ++which)
     for (const bo::KRange &r : s.ranges) {
       bo::set_range(A, r);
-      if (int e = launch(which, r.c_cnt, A)) return e;
+      if (int e = launch(which, r.c_cnt, A, r.K)) return e;
     }
   A.p_beg = 0;
-  return launch(3, s.nprob, A);
+  return launch(3, s.nprob, A, 0);
 }
 
 }  // namespace bo_vi

@@ -60,7 +60,9 @@ _KERNEL_SLOTS = [
     (r"k_wide_f2", "wide_f2"),
     (r"k_wide_b1", "wide_b1"),
     (r"k_wide_b2", "wide_b2"),
-    (r"k_finalize", "finalize"),
+    (r"k_kl_pre", "vi_pre"),
+    (r"k_kl_post|k_kl_neg", "vi_post"),
+    (r"k_kl_finalize|k_finalize", "finalize"),
     (r"ClearPart", "clear_partials"),
     (r"k_gbmm", "gbmm"),
     (r"k_gbmv", "gbmv"),
