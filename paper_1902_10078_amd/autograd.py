@@ -17,6 +17,8 @@ off-diagonal stored value stands for both Q_ij and Q_ji.
   outer_band(m, v)   -> band of m v^T              Table 1, outer-product row
   gauss_loss(plan, Q, y, S) -> per-problem logdet Q - y^T Q^{-1} y + tr(Q^{-1} S)
                                   (fused forward and backward over a batch)
+  vi_kl(plan, Lq, Lp, mq, mp) -> per-problem KL(q || p) of the variational
+                                  objective (Eq. (KL), Algorithm 7; batched)
 """
 from __future__ import annotations
 
@@ -217,6 +219,39 @@ class GaussLoss(torch.autograd.Function):
         return None, gQ, gy, gS
 
 
+class ViKL(torch.autograd.Function):
+    """Per-problem KL(q_p || p_p) of the variational objective (Eq. (KL),
+    Algorithm 7) over a plan's batch: q = N(m_q, (L_q L_q^T)^{-1}),
+    p = N(m_p, (L_p L_p^T)^{-1}).  Lq, Lp: packed lower bands; mq, mp: packed
+    vectors.  The forward pass runs the fused forward and reverse passes once
+    and keeps the four gradients for backward."""
+
+    @staticmethod
+    def forward(ctx, plan, Lq, Lp, mq, mp):
+        Lq, Lp, mq, mp = _vec(Lq), _vec(Lp), _vec(mq), _vec(mp)
+        dev = Lq.device
+        E, N = Lq.numel(), mq.numel()
+        bufs = {nm: torch.empty(E, dtype=torch.float64, device=dev) for nm in ("Sig", "Lqbar", "Lpbar")}
+        bufs.update({nm: torch.empty(N, dtype=torch.float64, device=dev) for nm in ("mqbar", "mpbar")})
+        parts = torch.zeros((plan.nprob, 4), dtype=torch.float64, device=dev)
+        plan.vi_kl(bo.F64, plan.kl_io(Lq=Lq, Lp=Lp, mq=mq, mp=mp, parts=parts, **bufs))
+        ctx.save_for_backward(bufs["Lqbar"], bufs["Lpbar"], bufs["mqbar"], bufs["mpbar"])
+        ctx.plan = plan
+        return parts[:, 0]
+
+    @staticmethod
+    def backward(ctx, g):
+        Lqbar, Lpbar, mqbar, mpbar = ctx.saved_tensors
+        plan = ctx.plan
+        gb = torch.repeat_interleave(g, torch.tensor([n * (k + 1) for n, k in zip(plan.ns, plan.ks)],
+                                                     device=g.device))
+        gr = torch.repeat_interleave(g, torch.tensor(plan.ns, device=g.device))
+        return (None, Lqbar * gb if ctx.needs_input_grad[1] else None,
+                Lpbar * gb if ctx.needs_input_grad[2] else None,
+                mqbar * gr if ctx.needs_input_grad[3] else None,
+                mpbar * gr if ctx.needs_input_grad[4] else None)
+
+
 def chol(Q):
     return Chol.apply(Q)
 
@@ -260,3 +295,22 @@ def gauss_loss_composed(Q, y, S):
     w = torch.full((k + 1,), 2.0, dtype=torch.float64, device=Q.device)
     w[0] = 1.0
     return logdet - (z * z).sum() + (Sig * S * w).sum()
+
+
+def vi_kl(plan, Lq, Lp, mq, mp):
+    return ViKL.apply(plan, Lq, Lp, mq, mp)
+
+
+def vi_kl_composed(Lq, Lp, mq, mp):
+    """KL(q || p) for one problem composed from the separate operators as
+    Algorithm 7 writes it: tr(I(L_q) P(L_p, L_p^T)) as the weighted sum over
+    the band, the log-diagonals, ||P(L_p^T, m_p - m_q)||^2."""
+    k = Lq.shape[1] - 1
+    n = Lq.shape[0]
+    Sig = subset_inv(Lq)
+    Qp = gbmm(Lp, Lp, k, 0, k, 0, 0, 1, k, 0)
+    w = torch.full((k + 1,), 2.0, dtype=torch.float64, device=Lq.device)
+    w[0] = 1.0
+    tr = (Sig * Qp * w).sum()
+    v = gbmv(Lp, mp - mq, k, 0, 1)
+    return 0.5 * (tr + 2.0 * (torch.log(Lq[:, 0]).sum() - torch.log(Lp[:, 0]).sum()) + (v * v).sum() - n)

@@ -146,3 +146,50 @@ def test_vi_kl_full_size_rows(bo):
     plan = bo.Plan(ns, ks)
     res = run_kl(bo, plan, Lq, Lp, mq, mp)
     check(bo, plan, Lq, Lp, mq, mp, res, TOL)
+
+
+def test_vi_kl_autograd_vs_dense_and_composed(bo):
+    """The autograd Function against dense torch autograd (CPU, FP64) and
+    against the same KL composed from the separate operators' Functions."""
+    from paper_1902_10078_amd import autograd as ag
+    ns, ks = [9, 23, 4], [2, 3, 1]
+    Lq, Lp, mq, mp = draw(ns, ks, 61)
+    plan = bo.Plan(ns, ks)
+    cat = lambda a: np.concatenate([x.ravel() for x in a])
+    cu = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda", requires_grad=True)
+    tq, tp, tmq, tmp = cu(cat(Lq)), cu(cat(Lp)), cu(cat(mq)), cu(cat(mp))
+    g = torch.tensor([1.0, -0.5, 2.0], dtype=torch.float64, device="cuda")
+    kl = ag.vi_kl(plan, tq, tp, tmq, tmp)
+    (kl * g).sum().backward()
+    grads = [t.grad.cpu().numpy() for t in (tq, tp, tmq, tmp)]
+    for p, (n, k) in enumerate(zip(ns, ks)):
+        o, v = plan.boff[p], plan.voff[p]
+        # dense reference: scatter the band parameters into dense factors
+        c = [torch.tensor(a, dtype=torch.float64, requires_grad=True) for a in (Lq[p], Lp[p], mq[p], mp[p])]
+
+        def dense(B):
+            M = torch.zeros((n, n), dtype=torch.float64)
+            for d in range(k + 1):
+                idx = torch.arange(n - d)
+                M = M.index_put((idx + d, idx), B[: n - d, d])
+            return M
+        Dq, Dp = dense(c[0]), dense(c[1])
+        Qq, Qp = Dq @ Dq.T, Dp @ Dp.T
+        dm = c[3] - c[2]
+        ref = 0.5 * (torch.trace(torch.linalg.solve(Qq, Qp)) + torch.logdet(Qq) - torch.logdet(Qp)
+                     + dm @ Qp @ dm - n)
+        assert abs(kl[p].item() - ref.item()) <= 1e-11 * max(1.0, abs(ref.item()))
+        (ref * float(g[p])).backward()
+        m = band_mask(n, k)
+        sz = n * (k + 1)
+        for got, rt in ((grads[0][o:o + sz].reshape(n, k + 1), c[0].grad.numpy() * m),
+                        (grads[1][o:o + sz].reshape(n, k + 1), c[1].grad.numpy() * m),
+                        (grads[2][v:v + n], c[2].grad.numpy()), (grads[3][v:v + n], c[3].grad.numpy())):
+            assert np.max(np.abs(got - rt)) <= 1e-10 * max(1.0, np.max(np.abs(rt)))
+        # composed from the operators' own Functions
+        cq, cp = cu(Lq[p]), cu(Lp[p])
+        lc = ag.vi_kl_composed(cq, cp, cu(mq[p]), cu(mp[p]))
+        lc.backward()
+        assert abs(lc.item() - kl[p].item()) <= 1e-11 * max(1.0, abs(ref.item()))
+        refq = grads[0][o:o + sz].reshape(n, k + 1) / float(g[p])
+        assert np.max(np.abs(cq.grad.cpu().numpy() * m - refq)) <= 1e-10 * max(1.0, np.max(np.abs(refq)))
