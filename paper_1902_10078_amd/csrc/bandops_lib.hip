@@ -132,8 +132,8 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const Args A) {
 // ------------------------------------------------------------ profiling
 // When enabled, every launch is bracketed by a pair of events on its stream;
 // bo_profile_read() waits for them and sums the durations per step kind.
-constexpr int kProfSlots = bo::ST_COUNT + 8;   // + clear, finalize, the four wide passes, the KL term's two
-constexpr int kSlotViPre = bo::ST_COUNT + 6, kSlotViPost = bo::ST_COUNT + 7;   // row kernels
+constexpr int kProfSlots = bo::ST_COUNT + 9;   // + clear, finalize, the four wide passes, the KL term's
+constexpr int kSlotViPre = bo::ST_COUNT + 6, kSlotViPost = bo::ST_COUNT + 7, kSlotViNeg = bo::ST_COUNT + 8;   // row kernels
 struct ProfRec {
   int slot;
   hipEvent_t a, b;
@@ -367,7 +367,7 @@ static const char *const kStepNames[kProfSlots] = {
     "chunk_product", "fs_summary", "fs_replay", "f2_summary", "f2_replay", "b1_summary",
     "b1_replay", "b2_summary", "b2_replay", "asc_group_compose", "asc_group_sweep",
     "asc_chunk_sweep", "desc_group_compose", "desc_group_sweep", "desc_chunk_sweep",
-    "clear_partials", "finalize", "wide_f1", "wide_f2", "wide_b1", "wide_b2", "vi_pre", "vi_post"};
+    "clear_partials", "finalize", "wide_f1", "wide_f2", "wide_b1", "wide_b2", "vi_pre", "vi_post", "vi_neg"};
 
 extern "C" int bo_profile_slots(void) { return kProfSlots; }
 
@@ -740,7 +740,7 @@ extern "C" bo_status bo_plan_vi_kl(const bo_plan *plan, bo_prec prec, const bo_k
     if (count <= 0) return 0;
     const dim3 grid((unsigned)count);
     const size_t pre_lds = bo_vi::pre_lds_bytes(k + 1), post_lds = bo_vi::post_lds_bytes(k + 1);
-    const int slot = which == 0 ? kSlotViPre : which == 3 ? bo::ST_COUNT + 1 : kSlotViPost;
+    const int slot = which == 0 ? kSlotViPre : which == 1 ? kSlotViPost : which == 2 ? kSlotViNeg : bo::ST_COUNT + 1;
     return profiled(slot, stream, [&] {
       const bool f64 = prec == BO_F64;
       const dim3 rows(bo_vi::kRowBlock);

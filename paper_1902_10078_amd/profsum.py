@@ -61,7 +61,8 @@ _KERNEL_SLOTS = [
     (r"k_wide_b1", "wide_b1"),
     (r"k_wide_b2", "wide_b2"),
     (r"k_kl_pre", "vi_pre"),
-    (r"k_kl_post|k_kl_neg", "vi_post"),
+    (r"k_kl_post", "vi_post"),
+    (r"k_kl_neg", "vi_neg"),
     (r"k_kl_finalize|k_finalize", "finalize"),
     (r"ClearPart", "clear_partials"),
     (r"k_gbmm", "gbmm"),
@@ -80,7 +81,7 @@ def slot_of(kernel_name: str) -> str | None:
 
 # Sources of the row-streaming kernels, their scans and their schedule.
 _KERNEL_SOURCES = ("bandops_algo.hpp", "bandops_step.hpp", "bandops_items.hpp", "bandops_tile.hpp",
-                   "bandops_driver.hpp", "bandops_steps.hpp", "bandops_kern.hip")
+                   "bandops_driver.hpp", "bandops_steps.hpp", "bandops_kern.hip", "bandops_vi.hpp")
 
 
 def source_hash() -> str:
