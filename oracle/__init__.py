@@ -61,6 +61,7 @@ def _load():
         "or_gauss_loss": (i32, [i64, i32, i64, P, P, P, P, P, P, P, P, P, P]),
         "or_gauss_loss_batch": (i32, [i32, P, P, P, P, P, P, P, P, P, P, P]),
         "or_forward_batch": (i32, [i32, P, P, P, P, P, P, P, P, P, P, P, P]),
+        "or_solve_band_mat_bwd": (None, [i64, i32, i64, P, i32, i32, i64, P, P, i64, P, P]),
         "or_vi_kl": (None, [i64, i32, i64, P, P, P, P, P, P, P, P, P, P]),
         "or_vi_kl_batch": (i32, [i32, P, P, P, P, P, P, P, P, P, P, P, P, P]),
     }
@@ -181,6 +182,18 @@ def solve_band_mat(L, k, R, lr, ur):
     _load().or_solve_band_mat(n, k, L.shape[1], _p(L), lr, ur, R.shape[1], _p(R),
                               k + ur + 1, _p(O))
     return O
+
+
+def solve_band_mat_bwd(L, k, O, Obar, lr, ur):
+    """Reverse mode of Algorithm 5 (Table 1, solve matrix-matrix): returns
+    (Rbar on the (lr, ur) band of R, Lbar on the lower band of L)."""
+    L, O, Obar = _f64(L), _f64(O), _f64(Obar)
+    n = L.shape[0]
+    Rbar = np.zeros((n, lr + ur + 1))
+    Lbar = np.zeros_like(L)
+    _load().or_solve_band_mat_bwd(n, k, L.shape[1], _p(L), lr, ur, O.shape[1], _p(O), _p(Obar),
+                                  lr + ur + 1, _p(Rbar), _p(Lbar))
+    return Rbar, Lbar
 
 
 def gauss_loss(Q, k, y, S):

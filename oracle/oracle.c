@@ -337,6 +337,44 @@ void or_solve_band_mat(int64_t n, int k, int64_t ldl, const double *L, int lr,
 }
 
 /* --------------------------------------------------------------------------
+ * Reverse mode of Algorithm 5 (Table 1, solve matrix-matrix, with B = R and
+ * S = O): Rbar = S(L^T, Obar), Lbar^T = -P(O, S(L^T, Obar)^T).
+ * G = L^{-T} Obar column by column, rows descending (back substitution with
+ * L^T); column c of Obar lives on rows c-ur .. c+k, so G's column c is zero
+ * below row c+k and its band entries need only band entries above them.
+ * ------------------------------------------------------------------------ */
+void or_solve_band_mat_bwd(int64_t n, int k, int64_t ldl, const double *L, int lr,
+                           int ur, int64_t ldo, const double *O,
+                           const double *Obar, int64_t ldr, double *Rbar,
+                           double *Lbar) {
+  int lo = k, uo = ur;
+  int64_t ldg = lo + uo + 1;
+  double *G = (double *)calloc((size_t)(n * ldg + 1), sizeof(double));
+  for (int64_t c = 0; c < n; ++c)
+    for (int64_t i = imin64(n - 1, c + lo); i >= imax64(0, c - uo); --i) {
+      double acc = gen_get(Obar, ldo, lo, uo, i, c);
+      for (int64_t m = i + 1; m <= imin64(n - 1, i + k); ++m)
+        acc -= LOW(L, ldl, m, i) * gen_get(G, ldg, lo, uo, m, c);
+      GEN(G, ldg, uo, i, c) = acc / LOW(L, ldl, i, i);
+    }
+  for (int64_t c = 0; c < n; ++c)
+    for (int s = 0; s <= lr + ur; ++s) {
+      int64_t i = c - ur + s;
+      Rbar[c * ldr + s] = (i >= 0 && i < n) ? gen_get(G, ldg, lo, uo, i, c) : 0.0;
+    }
+  for (int64_t m = 0; m < n; ++m)
+    for (int d = 0; d <= k; ++d) {
+      int64_t i = m + d;
+      double acc = 0.0;
+      if (i < n)
+        for (int64_t c = imax64(0, i - lo); c <= imin64(n - 1, m + uo); ++c)
+          acc += gen_get(G, ldg, lo, uo, i, c) * gen_get(O, ldo, lo, uo, m, c);
+      Lbar[m * ldl + d] = -acc;
+    }
+  free(G);
+}
+
+/* --------------------------------------------------------------------------
  * loss = log det Q - y^T Q^{-1} y + tr(Q^{-1} S) and its gradients, composed
  * from C, S, I and their reverse modes (Table 1, Algorithms 1-4):
  *   L = C(Q); z = S(L, y); Sig = I(L)

@@ -88,6 +88,17 @@ void or_solve_band_mat(int64_t n, int k, int64_t ldl, const double *L, int lr,
                        int ur, int64_t ldr, const double *R, int64_t ldo,
                        double *O);
 
+/* Reverse mode of Algorithm 5 (Table 1, solve matrix-matrix): given the band
+ * O (k lower, ur upper) of L^{-1} R and its sensitivity Obar on that band,
+ *   G = S(L^T, Obar) = L^{-T} Obar, exact on the band (k, ur),
+ *   Rbar = G on the band (lr, ur) of R (zero where that band exceeds G's),
+ *   Lbar = -band_k(G O^T), which needs only band entries of O.
+ * Writes Rbar (stride ldr) and Lbar (stride ldl). */
+void or_solve_band_mat_bwd(int64_t n, int k, int64_t ldl, const double *L, int lr,
+                           int ur, int64_t ldo, const double *O,
+                           const double *Obar, int64_t ldr, double *Rbar,
+                           double *Lbar);
+
 /* The Gaussian loss of a banded precision and its gradients, composed from the
  * operators above (Table 1 and Algorithms 1-4):
  *   loss = log det Q - y^T Q^{-1} y + tr(Q^{-1} S)
