@@ -108,6 +108,15 @@ bo_status bo_gbmv(bo_prec prec, const bo_band *A, int tA, const void *x, void *y
 bo_status bo_outer_band(bo_prec prec, const void *m, const void *v, double alpha, int accumulate,
                         bo_band *O, hipStream_t stream);
 
+/* S with a banded right-hand side (Algorithm 5): O = the band (k lower, u
+ * upper) of L^{-1} R for L lower-banded with k sub-diagonals and R a general
+ * band with u upper diagonals (and any lower width).  O must have l = k and
+ * u = R's u; its entries are exact (a column of L^{-1} R is zero above row
+ * c - u, and the entries in the band need only band entries above them).
+ * k, u <= 12; returns BO_EUNSUPPORTED above.  One lane per column. */
+bo_status bo_solve_band_mat(bo_prec prec, const bo_band *L, const bo_band *R, bo_band *O,
+                            hipStream_t stream);
+
 /* ---------------------------------------------------------- reverse mode */
 
 /* Reverse mode of C (Algorithm 2): Qbar = d c/d Q (stored lower entries) from
@@ -129,6 +138,17 @@ bo_status bo_subset_inv_bwd(bo_prec prec, const bo_band *L, const bo_band *Sigma
 bo_status bo_trsv_bwd(bo_prec prec, const bo_band *L, int trans, const void *x, const void *xbar,
                       void *bbar, bo_band *Lbar, int accumulate, void *ws, size_t ws_bytes,
                       hipStream_t stream);
+
+/* Reverse mode of Algorithm 5 (Table 1, solve matrix-matrix): from O (the
+ * forward output, band (k, u)) and its sensitivity Obar on that band,
+ * Rbar = L^{-T} Obar on Rbar's band (Rbar has R's widths; u must equal O's)
+ * and Lbar = -band_k((L^{-T} Obar) O^T), both overwritten.  ws holds
+ * L^{-T} Obar on the band (k, u) in FP64: at least
+ * bo_solve_band_mat_workspace(n, k, u) bytes (BO_EWORKSPACE otherwise). */
+size_t bo_solve_band_mat_workspace(int64_t n, int32_t k, int32_t u);
+bo_status bo_solve_band_mat_bwd(bo_prec prec, const bo_band *L, const bo_band *O, const bo_band *Obar,
+                                bo_band *Rbar, bo_band *Lbar, void *ws, size_t ws_bytes,
+                                hipStream_t stream);
 
 /* Reverse mode of log det: Lbar_ii (=, +=) 2 gbar / L_ii; gbar is one device
  * double. */

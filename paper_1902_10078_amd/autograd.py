@@ -17,6 +17,7 @@ off-diagonal stored value stands for both Q_ij and Q_ji.
   outer_band(m, v)   -> band of m v^T              Table 1, outer-product row
   gauss_loss(plan, Q, y, S) -> per-problem logdet Q - y^T Q^{-1} y + tr(Q^{-1} S)
                                   (fused forward and backward over a batch)
+  solve_band_mat(L, R, lr, u) -> band (k, u) of L^{-1} R   Algorithm 5 / Table 1
   vi_kl(plan, Lq, Lp, mq, mp) -> per-problem KL(q || p) of the variational
                                   objective (Eq. (KL), Algorithm 7; batched)
 """
@@ -219,6 +220,28 @@ class GaussLoss(torch.autograd.Function):
         return None, gQ, gy, gS
 
 
+class SolveBandMat(torch.autograd.Function):
+    """Band (k, u) of L^{-1} R (Algorithm 5) and its reverse mode (Table 1,
+    solve matrix-matrix).  L: (n, k+1) lower band; R: (n, lr+u+1) band with lr
+    lower and u upper diagonals; output (n, k+u+1)."""
+
+    @staticmethod
+    def forward(ctx, L, R, lr: int, u: int):
+        k = L.shape[1] - 1
+        Lb, Rb = _band(L, k), _band(R, lr, u)
+        O = bo.bo_solve_band_mat(Lb, Rb)
+        ctx.save_for_backward(L, O.band)
+        ctx.lr, ctx.u = lr, u
+        return O.band
+
+    @staticmethod
+    def backward(ctx, gO):
+        L, O = ctx.saved_tensors
+        k = L.shape[1] - 1
+        Rbar, Lbar = bo.bo_solve_band_mat_bwd(_band(L, k), _band(O, k, ctx.u), _band(gO, k, ctx.u), ctx.lr)
+        return Lbar.band, Rbar.band, None, None
+
+
 class ViKL(torch.autograd.Function):
     """Per-problem KL(q_p || p_p) of the variational objective (Eq. (KL),
     Algorithm 7) over a plan's batch: q = N(m_q, (L_q L_q^T)^{-1}),
@@ -295,6 +318,10 @@ def gauss_loss_composed(Q, y, S):
     w = torch.full((k + 1,), 2.0, dtype=torch.float64, device=Q.device)
     w[0] = 1.0
     return logdet - (z * z).sum() + (Sig * S * w).sum()
+
+
+def solve_band_mat(L, R, lr: int, u: int):
+    return SolveBandMat.apply(L, R, lr, u)
 
 
 def vi_kl(plan, Lq, Lp, mq, mp):

@@ -70,6 +70,9 @@ def lib():
         "bo_gbmm": (_I32, [_I32, bp, _I32, bp, _I32, bp, _P]),
         "bo_gbmv": (_I32, [_I32, bp, _I32, _P, _P, _P]),
         "bo_outer_band": (_I32, [_I32, _P, _P, ctypes.c_double, _I32, bp, _P]),
+        "bo_solve_band_mat": (_I32, [_I32, bp, bp, bp, _P]),
+        "bo_solve_band_mat_workspace": (ctypes.c_size_t, [_I64, _I32, _I32]),
+        "bo_solve_band_mat_bwd": (_I32, [_I32, bp, bp, bp, bp, bp, _P, ctypes.c_size_t, _P]),
         "bo_chol_bwd": (_I32, [_I32, bp, bp, bp, _P, ctypes.c_size_t, _P]),
         "bo_subset_inv_bwd": (_I32, [_I32, bp, bp, bp, bp, _I32, _P, ctypes.c_size_t, _P]),
         "bo_trsv_bwd": (_I32, [_I32, bp, _I32, _P, _P, _P, bp, _I32, _P, ctypes.c_size_t, _P]),
@@ -102,7 +105,8 @@ def lib():
 
 
 EXPORTED = ("bo_workspace_size", "bo_chol", "bo_trsv", "bo_subset_inv", "bo_gbmm", "bo_gbmv",
-            "bo_outer_band", "bo_chol_bwd", "bo_subset_inv_bwd", "bo_trsv_bwd", "bo_logdet_bwd",
+            "bo_outer_band", "bo_solve_band_mat", "bo_solve_band_mat_workspace",
+            "bo_solve_band_mat_bwd", "bo_chol_bwd", "bo_subset_inv_bwd", "bo_trsv_bwd", "bo_logdet_bwd",
             "bo_plan_create", "bo_plan_workspace_size", "bo_plan_upload", "bo_plan_forward",
             "bo_plan_gauss_loss", "bo_plan_vi_kl", "bo_plan_stats", "bo_plan_destroy", "bo_wide_workspace_size",
             "bo_wide_upload", "bo_wide_forward", "bo_wide_gauss_loss", "bo_profile_enable",
@@ -259,7 +263,30 @@ def bo_outer_band(m: torch.Tensor, v: torch.Tensor, l: int, u: int = 0, alpha: f
     return O
 
 
+def bo_solve_band_mat(L: Band, R: Band):
+    """Algorithm 5: the band (L.l lower, R.u upper) of L^{-1} R."""
+    O = new_band(L.n, L.l, R.u, L.prec, L.band.device)
+    lc, rc, oc = L.c(), R.c(), O.c()
+    _check(lib().bo_solve_band_mat(L.prec, ctypes.byref(lc), ctypes.byref(rc), ctypes.byref(oc), _stream()),
+           "bo_solve_band_mat")
+    return O
+
+
 # ----------------------------------------------------------- reverse mode
+
+def bo_solve_band_mat_bwd(L: Band, O: Band, Obar: Band, lr: int):
+    """Reverse mode of Algorithm 5 (Table 1, solve matrix-matrix): (Rbar on
+    the band (lr, O.u), Lbar)."""
+    Rbar = new_band(L.n, lr, O.u, L.prec, L.band.device)
+    Lbar = new_band(L.n, L.l, 0, L.prec, L.band.device)
+    size = max(int(lib().bo_solve_band_mat_workspace(L.n, L.l, O.u)), 256)
+    ws = torch.empty(size, dtype=torch.uint8, device=L.band.device)
+    lc, oc, obc, rbc, lbc = L.c(), O.c(), Obar.c(), Rbar.c(), Lbar.c()
+    _check(lib().bo_solve_band_mat_bwd(L.prec, ctypes.byref(lc), ctypes.byref(oc), ctypes.byref(obc),
+                                       ctypes.byref(rbc), ctypes.byref(lbc), _ptr(ws), ws.numel(), _stream()),
+           "bo_solve_band_mat_bwd")
+    return Rbar, Lbar
+
 
 def bo_chol_bwd(L: Band, Lbar: Band):
     Qbar = new_band(L.n, L.l, 0, L.prec, L.band.device)

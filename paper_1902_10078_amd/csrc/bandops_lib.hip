@@ -357,6 +357,82 @@ __global__ void k_logdet_bwd(int64_t n, GB<T> L, const double *g, int acc, GB<T>
   if (s == 0 && Lb.diag) Lb.diag[j] = val;
 }
 
+// Algorithm 5: O = band (k, u) of L^{-1} R, one lane per column c of O.  The
+// column's entries, rows c-u .. c+k, follow by forward substitution down the
+// column; each needs only the column's entries above it (the column of L^{-1} R
+// is zero above row c-u because R has u upper diagonals).  Widths k, u <= 12.
+constexpr int kSolveCol = 25;
+template <typename T> __global__ void k_solve_mat(int64_t n, GB<T> L, GB<T> R, GB<T> O) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const int k = L.l, u = O.u;
+  double col[kSolveCol];
+  for (int s = 0; s <= k + u; ++s) {
+    const int64_t i = c - u + s;
+    double v = 0.0;
+    if (i >= 0 && i < n) {
+      double acc = R.get(i, c);
+      int64_t m0 = i - k > c - u ? i - k : c - u;
+      if (m0 < 0) m0 = 0;
+      for (int64_t m = m0; m < i; ++m) acc -= L.get(i, m) * col[m - (c - u)];
+      v = acc / L.get(i, i);
+    }
+    col[s] = v;
+    O.p[c * O.ld + s] = (T)v;
+    if (s == u && O.diag) O.diag[c] = v;
+  }
+}
+
+// Reverse mode of Algorithm 5 (Table 1, solve matrix-matrix), first step:
+// G = L^{-T} Obar on the band (k, u) (FP64, record c at G + c (k+u+1)), one
+// lane per column, rows c+k .. c-u descending (back substitution with L^T).
+template <typename T> __global__ void k_solve_mat_g(int64_t n, GB<T> L, GB<T> Ob, double *G) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const int k = L.l, u = Ob.u, w = k + u + 1;
+  double col[kSolveCol];
+  for (int s = k + u; s >= 0; --s) {
+    const int64_t i = c - u + s;
+    double v = 0.0;
+    if (i >= 0 && i < n) {
+      double acc = Ob.get(i, c);
+      int64_t m1 = i + k < c + k ? i + k : c + k;
+      if (m1 > n - 1) m1 = n - 1;
+      for (int64_t m = i + 1; m <= m1; ++m) acc -= L.get(m, i) * col[m - (c - u)];
+      v = acc / L.get(i, i);
+    }
+    col[s] = v;
+    G[c * w + s] = v;
+  }
+}
+
+// Second step, one lane per stored entry: Rbar = G on the band of R, and
+// Lbar(i, m) = -sum_c G(i, c) O(m, c) over c in [i-k, m+u] (both factors in
+// their bands there).
+template <typename T>
+__global__ void k_solve_mat_rbar(int64_t n, int k, int u, const double *G, GB<T> Rb) {
+  const int64_t w = Rb.l + Rb.u + 1, t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * w) return;
+  const int64_t c = t / w, s = t - c * w, i = c - Rb.u + s;
+  double v = 0.0;
+  if (i >= 0 && i < n && i - c <= k && c - i <= u) v = G[c * (k + u + 1) + u + (i - c)];
+  Rb.p[c * Rb.ld + s] = (T)v;
+  if (s == Rb.u && Rb.diag) Rb.diag[c] = v;
+}
+template <typename T>
+__global__ void k_solve_mat_lbar(int64_t n, int k, int u, const double *G, GB<T> O, GB<T> Lb) {
+  const int64_t w = k + 1, t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * w) return;
+  const int64_t m = t / w, d = t - m * w, i = m + d;
+  double acc = 0.0;
+  if (i < n) {
+    int64_t c0 = i - k > 0 ? i - k : 0, c1 = m + u < n - 1 ? m + u : n - 1;
+    for (int64_t c = c0; c <= c1; ++c) acc += G[c * (k + u + 1) + u + (i - c)] * O.get(m, c);
+  }
+  Lb.p[m * Lb.ld + d] = (T)(-acc);
+  if (d == 0 && Lb.diag) Lb.diag[m] = -acc;
+}
+
 unsigned blocks_for(int64_t count, int block) { return (unsigned)((count + block - 1) / block); }
 
 }  // namespace
@@ -480,6 +556,68 @@ extern "C" bo_status bo_gbmm(bo_prec prec, const bo_band *A, int tA, const bo_ba
     hipLaunchKernelGGL(k_gbmm<float>, dim3(blocks_for(n * w, 256)), dim3(256), 0, stream, n,
                        gb<float>(A), tA, gb<float>(B), tB, gb<float>(C));
   return dev_status(hipGetLastError() == hipSuccess ? 0 : -2, "bo_gbmm");
+}
+
+extern "C" bo_status bo_solve_band_mat(bo_prec prec, const bo_band *L, const bo_band *R, bo_band *O,
+                                       hipStream_t stream) {
+  if (bo_status e = check_band(L, prec, "L", true)) return e;
+  if (bo_status e = check_band(R, prec, "R", false)) return e;
+  if (bo_status e = check_band(O, prec, "O", false)) return e;
+  if (L->n != R->n || L->n != O->n) return fail(BO_EINVAL, "bo_solve_band_mat: matrix orders differ");
+  if (O->l != L->l || O->u != R->u)
+    return fail(BO_EINVAL, "bo_solve_band_mat: O must have L's lower and R's upper width");
+  if (L->l > 12 || R->u > 12) return fail(BO_EUNSUPPORTED, "bo_solve_band_mat: widths above 12");
+  const int64_t n = O->n;
+  if (n == 0) return BO_OK;
+  if (prec == BO_F64)
+    hipLaunchKernelGGL(k_solve_mat<double>, dim3(blocks_for(n, 256)), dim3(256), 0, stream, n, gb<double>(L),
+                       gb<double>(R), gb<double>(O));
+  else
+    hipLaunchKernelGGL(k_solve_mat<float>, dim3(blocks_for(n, 256)), dim3(256), 0, stream, n, gb<float>(L),
+                       gb<float>(R), gb<float>(O));
+  return dev_status(hipGetLastError() == hipSuccess ? 0 : -2, "bo_solve_band_mat");
+}
+
+extern "C" size_t bo_solve_band_mat_workspace(int64_t n, int32_t k, int32_t u) {
+  return n > 0 ? (size_t)n * (size_t)(k + u + 1) * sizeof(double) : 0;
+}
+
+extern "C" bo_status bo_solve_band_mat_bwd(bo_prec prec, const bo_band *L, const bo_band *O,
+                                           const bo_band *Obar, bo_band *Rbar, bo_band *Lbar, void *ws,
+                                           size_t ws_bytes, hipStream_t stream) {
+  if (bo_status e = check_band(L, prec, "L", true)) return e;
+  if (bo_status e = check_band(O, prec, "O", false)) return e;
+  if (bo_status e = check_band(Obar, prec, "Obar", false)) return e;
+  if (bo_status e = check_band(Rbar, prec, "Rbar", false)) return e;
+  if (bo_status e = check_band(Lbar, prec, "Lbar", true)) return e;
+  const int64_t n = O->n;
+  if (L->n != n || Obar->n != n || Rbar->n != n || Lbar->n != n)
+    return fail(BO_EINVAL, "bo_solve_band_mat_bwd: matrix orders differ");
+  if (O->l != L->l || Obar->l != O->l || Obar->u != O->u || Rbar->u != O->u || Lbar->l != L->l)
+    return fail(BO_EINVAL, "bo_solve_band_mat_bwd: band widths do not match the forward call");
+  if (L->l > 12 || O->u > 12) return fail(BO_EUNSUPPORTED, "bo_solve_band_mat_bwd: widths above 12");
+  if (n == 0) return BO_OK;
+  if (!ws || ws_bytes < bo_solve_band_mat_workspace(n, L->l, O->u))
+    return fail(BO_EWORKSPACE, "bo_solve_band_mat_bwd: workspace smaller than bo_solve_band_mat_workspace()");
+  double *G = (double *)ws;
+  const int k = L->l, u = O->u;
+  const int64_t wr = (int64_t)Rbar->l + Rbar->u + 1;
+  if (prec == BO_F64) {
+    hipLaunchKernelGGL(k_solve_mat_g<double>, dim3(blocks_for(n, 256)), dim3(256), 0, stream, n, gb<double>(L),
+                       gb<double>(Obar), G);
+    hipLaunchKernelGGL(k_solve_mat_rbar<double>, dim3(blocks_for(n * wr, 256)), dim3(256), 0, stream, n, k, u,
+                       (const double *)G, gb<double>(Rbar));
+    hipLaunchKernelGGL(k_solve_mat_lbar<double>, dim3(blocks_for(n * (k + 1), 256)), dim3(256), 0, stream, n, k,
+                       u, (const double *)G, gb<double>(O), gb<double>(Lbar));
+  } else {
+    hipLaunchKernelGGL(k_solve_mat_g<float>, dim3(blocks_for(n, 256)), dim3(256), 0, stream, n, gb<float>(L),
+                       gb<float>(Obar), G);
+    hipLaunchKernelGGL(k_solve_mat_rbar<float>, dim3(blocks_for(n * wr, 256)), dim3(256), 0, stream, n, k, u,
+                       (const double *)G, gb<float>(Rbar));
+    hipLaunchKernelGGL(k_solve_mat_lbar<float>, dim3(blocks_for(n * (k + 1), 256)), dim3(256), 0, stream, n, k, u,
+                       (const double *)G, gb<float>(O), gb<float>(Lbar));
+  }
+  return dev_status(hipGetLastError() == hipSuccess ? 0 : -2, "bo_solve_band_mat_bwd");
 }
 
 extern "C" bo_status bo_gbmv(bo_prec prec, const bo_band *A, int tA, const void *x, void *y,
