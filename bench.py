@@ -88,6 +88,16 @@ def vi_bytes_per_row(k: int, prec: int):
             "unit": 5 * wb + 4 * wv}                 # inputs L_q, L_p, m_q, m_p; outputs Sigma and the gradients
 
 
+def alg5_bytes_per_row(k: int, lr: int, u: int):
+    """Algorithmic bytes per row of the matrix solve with a banded right-hand
+    side (Algorithm 5) and its reverse mode, FP64."""
+    wl, wr, wo = 8 * (k + 1), 8 * (lr + u + 1), 8 * (k + u + 1)
+    return {"solve_mat": wl + wr + wo,          # L, R -> O
+            "solve_mat_g": wl + 2 * wo + wr,    # L, Obar -> G = L^{-T} Obar, Rbar
+            "solve_mat_out": 2 * wo + wl,       # G, O -> Lbar
+            "unit": wl + wr + 2 * wo + wr + wl}  # L, R, Obar in; O, Rbar, Lbar out
+
+
 def wide_bytes_per_row():
     """Algorithmic bytes per row of the wide passes (mixed storage, k = 64)."""
     wb, _ = record_bytes(64, 1)
@@ -331,6 +341,54 @@ def make_vi(args):
     return [args.n_vi] * args.batch, [5] * args.batch, (Lqs, Lps, mqs, mps)
 
 
+class Alg5Workload:
+    """One matrix: O = band of L^{-1} R (Algorithm 5) and the reverse mode
+    (Table 1, solve matrix-matrix) from a fixed Obar; every output and the
+    workspace allocated once, the step only launches."""
+
+    def __init__(self, bo, torch, dev, host_inputs, k, lr, u):
+        import ctypes
+        L, R, Ob = host_inputs
+        n = L.shape[0]
+        f = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+        self.bo, self.k, self.lr, self.u = bo, k, lr, u
+        self.t = dict(L=f(L), R=f(R), Obar=f(Ob))
+        self.bands = dict(L=bo.Band(self.t["L"], k), R=bo.Band(self.t["R"], lr, u), Obar=bo.Band(self.t["Obar"], k, u),
+                          O=bo.new_band(n, k, u, device=dev), Rbar=bo.new_band(n, lr, u, device=dev),
+                          Lbar=bo.new_band(n, k, 0, device=dev))
+        self.c = {nm: b.c() for nm, b in self.bands.items()}
+        self.ws = torch.empty(max(int(bo.lib().bo_solve_band_mat_workspace(n, k, u)), 256), dtype=torch.uint8,
+                              device=dev)
+        self.kw = dict(O=self.bands["O"].band)
+        self.ref = ctypes.byref
+
+    def step(self):
+        bo, c, r = self.bo, self.c, self.ref
+        bo._check(bo.lib().bo_solve_band_mat(bo.F64, r(c["L"]), r(c["R"]), r(c["O"]), bo._stream()),
+                  "bo_solve_band_mat")
+        bo._check(bo.lib().bo_solve_band_mat_bwd(bo.F64, r(c["L"]), r(c["O"]), r(c["Obar"]), r(c["Rbar"]),
+                                                 r(c["Lbar"]), bo._ptr(self.ws), self.ws.numel(), bo._stream()),
+                  "bo_solve_band_mat_bwd")
+
+
+def make_alg5(args):
+    """L a lower band (diagonal U[1,2], off-diagonals N(0, 0.3^2)), R and
+    Obar general bands with N(0,1) entries, seed 5."""
+    from paper_1902_10078_amd import inputs
+    n, k, lr, u = args.n_alg5, 5, 2, 5
+    rng = np.random.default_rng(5)
+    L = inputs.random_lower_band(n, k, rng)
+    R = rng.normal(size=(n, lr + u + 1))
+    Ob = rng.normal(size=(n, k + u + 1))
+    for s_ in range(lr + u + 1):   # slots past the matrix edges are zero
+        i = np.arange(n) - u + s_
+        R[(i < 0) | (i >= n), s_] = 0.0
+    for s_ in range(k + u + 1):
+        i = np.arange(n) - u + s_
+        Ob[(i < 0) | (i >= n), s_] = 0.0
+    return [n], [k], (L, R, Ob), (k, lr, u)
+
+
 class WideWorkload:
     """The wide block-banded batch on the device (mixed storage)."""
 
@@ -376,6 +434,26 @@ def make_wide(args, bo, torch, dev):
     return ns, [64] * len(ns), (Qs, ys, Ws)
 
 
+def cpu_baseline_alg5(host_inputs, widths, rows: int):
+    """The FP64 oracle (Algorithm 5 and its reverse mode, single-threaded:
+    one sequential sweep per column family) on the first `rows` rows."""
+    import oracle
+    L, R, Ob = host_inputs
+    k, lr, u = widths
+    Ls, Rs, Obs = L[:rows].copy(), R[:rows].copy(), Ob[:rows].copy()
+    for s_ in range(lr + u + 1):
+        Rs[np.arange(rows) - u + s_ >= rows, s_] = 0.0
+    for s_ in range(k + u + 1):
+        Obs[np.arange(rows) - u + s_ >= rows, s_] = 0.0
+    t0 = time.perf_counter()
+    O = oracle.solve_band_mat(Ls, k, Rs, lr, u)
+    oracle.solve_band_mat_bwd(Ls, k, O, Obs, lr, u)
+    dt = time.perf_counter() - t0
+    return dict(value=rows / dt, unit="band-rows/s", cores=1, kind="oracle",
+                sample=f"the first {rows} rows of the matrix, FP64 C oracle (forward and reverse), "
+                       f"one thread, {dt:.2f} s wall"), O
+
+
 def cpu_baseline(host_inputs, ns, ks, nsample: int, vi: bool = False):
     """The FP64 oracle as it stands, OpenMP across problems, on a bounded
     sample of the workload's problems."""
@@ -415,7 +493,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", choices=["matern52_loss", "uneven_forward", "matern32_forward", "wide_loss",
-                                           "vi_kl"], default="matern52_loss")
+                                           "vi_kl", "solve_band_mat"], default="matern52_loss")
     ap.add_argument("--prec", choices=["f64", "mixed"], default=None,
                     help="storage format (default: f64; mixed for uneven_forward)")
     ap.add_argument("--batch", type=int, default=16)
@@ -426,6 +504,7 @@ def main():
     ap.add_argument("--nwide", type=int, default=8)
     ap.add_argument("--n-wide", type=int, default=200_000)
     ap.add_argument("--n-vi", type=int, default=1_000_000, help="rows per problem of the KL batch")
+    ap.add_argument("--n-alg5", type=int, default=16_000_000, help="rows of the Algorithm 5 matrix")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="problems timed on the CPU oracle (default: 8 for the loss batch, "
                          "256 for the uneven batch, 1 otherwise)")
@@ -464,6 +543,7 @@ def main():
     forward_only = args.workload in ("uneven_forward", "matern32_forward")
     wide = args.workload == "wide_loss"
     vi = args.workload == "vi_kl"
+    alg5 = args.workload == "solve_band_mat"
     if args.workload == "matern52_loss":
         ns, ks, host_inputs = make_matern52(args)
         cfg = {"workload": f"matern52_ssm_batch{len(ns)}_rows{ns[0]}_k5_gauss_loss_fwd_bwd",
@@ -474,6 +554,11 @@ def main():
         cfg = {"workload": f"uneven_batch{len(ns)}_n256-65536_k1-3-5-11_forward",
                "batch": len(ns), "rows": sum(ns), "k": "1,3,5,11"}
         nsample = args.cpu_sample or 256
+    elif alg5:
+        ns, ks, host_inputs, widths = make_alg5(args)
+        cfg = {"workload": f"solve_band_mat_rows{ns[0]}_k5_R2-5_fwd_bwd", "batch": 1,
+               "rows_per_problem": ns[0], "k": 5, "R_lower": 2, "R_upper": 5}
+        nsample = 0
     elif vi:
         ns, ks, host_inputs = make_vi(args)
         cfg = {"workload": f"vi_kl_batch{len(ns)}_rows{ns[0]}_k5_fwd_bwd",
@@ -495,6 +580,8 @@ def main():
     if wide:
         W = WideWorkload(bo, torch, dev, ns, host_inputs)
         log(f"wide plan: {W.stats}, workspace {W.plan.ws.numel() / 2**20:.1f} MiB")
+    elif alg5:
+        W = Alg5Workload(bo, torch, dev, host_inputs, *widths)
     else:
         if vi:
             W = VIWorkload(bo, torch, dev, ns, ks, prec, host_inputs, args.target_chunks)
@@ -516,6 +603,8 @@ def main():
     torch.cuda.synchronize()
     if "info" in W.kw:
         assert int(W.kw["info"].max().item()) == 0, "Cholesky failed on the benchmark inputs"
+    elif alg5:
+        assert bool(torch.isfinite(W.kw["O"]).all()), "non-finite solve on the benchmark inputs"
     else:
         assert bool(torch.isfinite(W.kw["parts"]).all()), "non-finite KL on the benchmark inputs"
 
@@ -555,6 +644,8 @@ def main():
     bo.profile_enable(False)
     if wide:
         bb = {nm: b * rows for nm, b in wide_bytes_per_row().items()}
+    elif alg5:
+        bb = {nm: b * rows for nm, b in alg5_bytes_per_row(*widths).items()}
     else:
         bb = batch_bytes(ns, ks, prec, forward_only, vi)
     kern = {}
@@ -580,7 +671,7 @@ def main():
 
     # the plain FP64 one-matrix-per-launch form: per-problem plans, host loop, no graph
     vs_plain = None
-    if not args.no_plain and not wide:
+    if not args.no_plain and not wide and not alg5:
         if prec == bo.F64:
             W64 = W
         elif vi:
@@ -603,6 +694,8 @@ def main():
     cfg.update(storage=args.prec, graph=use_graph)
     if wide:
         cfg.update(blocks=W.stats["blocks"])
+    elif alg5:
+        pass
     else:
         cfg.update(chunks=W.plan.stats["nchunk"])
         if args.autotune:
@@ -626,7 +719,13 @@ def main():
         "unit_hbm_frac": round(unit_gbs / HBM_PEAK_GBS, 4),
         "vs_fp64_plain": vs_plain,
     }
-    if not args.no_cpu:
+    if not args.no_cpu and alg5:
+        cb, ref = cpu_baseline_alg5(host_inputs, widths, rows=min(2_000_000, rows))
+        got = W.kw["O"].cpu().numpy()[: ref.shape[0] - 12]   # rows whose band lies inside the sample
+        cb["max_rel_diff_vs_gpu"] = float(np.max(np.abs(got - ref[: got.shape[0]])) / np.max(np.abs(ref)))
+        out["cpu_baseline"] = cb
+        log(f"cpu baseline: {cb}")
+    elif not args.no_cpu:
         cb, ref = cpu_baseline(host_inputs, ns, ks, nsample, vi)
         src = W.kw["logdet"] if forward_only else W.kw["parts"]
         gp = src.cpu().numpy()[: len(ref)]

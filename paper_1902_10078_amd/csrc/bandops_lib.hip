@@ -132,8 +132,11 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const Args A) {
 // ------------------------------------------------------------ profiling
 // When enabled, every launch is bracketed by a pair of events on its stream;
 // bo_profile_read() waits for them and sums the durations per step kind.
-constexpr int kProfSlots = bo::ST_COUNT + 9;   // + clear, finalize, the four wide passes, the KL term's
-constexpr int kSlotViPre = bo::ST_COUNT + 6, kSlotViPost = bo::ST_COUNT + 7, kSlotViNeg = bo::ST_COUNT + 8;   // row kernels
+// + clear, finalize, the four wide passes, the KL term's row kernels, the
+// three launches of Algorithm 5 and its reverse mode
+constexpr int kProfSlots = bo::ST_COUNT + 12;
+constexpr int kSlotViPre = bo::ST_COUNT + 6, kSlotViPost = bo::ST_COUNT + 7, kSlotViNeg = bo::ST_COUNT + 8;
+constexpr int kSlotSolveMat = bo::ST_COUNT + 9, kSlotSolveMatG = bo::ST_COUNT + 10, kSlotSolveMatOut = bo::ST_COUNT + 11;
 struct ProfRec {
   int slot;
   hipEvent_t a, b;
@@ -360,77 +363,151 @@ __global__ void k_logdet_bwd(int64_t n, GB<T> L, const double *g, int acc, GB<T>
 // Algorithm 5: O = band (k, u) of L^{-1} R, one lane per column c of O.  The
 // column's entries, rows c-u .. c+k, follow by forward substitution down the
 // column; each needs only the column's entries above it (the column of L^{-1} R
-// is zero above row c-u because R has u upper diagonals).  Widths k, u <= 12.
-constexpr int kSolveCol = 25;
-template <typename T> __global__ void k_solve_mat(int64_t n, GB<T> L, GB<T> R, GB<T> O) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n) return;
-  const int k = L.l, u = O.u;
-  double col[kSolveCol];
-  for (int s = 0; s <= k + u; ++s) {
-    const int64_t i = c - u + s;
-    double v = 0.0;
-    if (i >= 0 && i < n) {
-      double acc = R.get(i, c);
-      int64_t m0 = i - k > c - u ? i - k : c - u;
-      if (m0 < 0) m0 = 0;
-      for (int64_t m = m0; m < i; ++m) acc -= L.get(i, m) * col[m - (c - u)];
-      v = acc / L.get(i, i);
-    }
-    col[s] = v;
-    O.p[c * O.ld + s] = (T)v;
-    if (s == u && O.diag) O.diag[c] = v;
+// is zero above row c-u because R has u upper diagonals).  A workgroup takes
+// TC consecutive columns: the L records they reach (columns c0-u .. c1+k-1),
+// their R records and the O records being built are staged in LDS as FP64
+// (consecutive lanes copy consecutive elements), and O goes back the same way.
+// Widths k, u <= 12.
+template <typename T>
+__device__ __forceinline__ void stage_rec(double *dst, const GB<T> &B, int64_t r0, int64_t r1, int64_t n, int W) {
+  const int64_t lo = r0 > 0 ? r0 : 0, hi = r1 < n ? r1 : n;
+  for (int64_t e = threadIdx.x; e < (hi - lo) * W; e += blockDim.x) {
+    const int64_t r = lo + e / W;
+    const int s = (int)(e - (r - lo) * W);
+    dst[(r - r0) * W + s] = (s == B.u && B.diag) ? B.diag[r] : (double)B.p[r * B.ld + s];
   }
+}
+template <typename T>
+__device__ __forceinline__ void store_rec(const GB<T> &B, const double *src, int64_t r0, int64_t r1, int W) {
+  for (int64_t e = threadIdx.x; e < (r1 - r0) * W; e += blockDim.x) {
+    const int64_t r = r0 + e / W;
+    const int s = (int)(e - (r - r0) * W);
+    B.p[r * B.ld + s] = (T)src[e];
+    if (s == B.u && B.diag) B.diag[r] = src[e];
+  }
+}
+
+// LDS of the two column kernels for TC columns.
+__host__ __device__ constexpr size_t solve_mat_lds(int TC, int k, int lr, int u) {
+  return (size_t)((TC + u + k) * (k + 1) + TC * (lr + u + 1) + TC * (k + u + 1)) * 8;
+}
+__host__ __device__ constexpr size_t solve_mat_g_lds(int TC, int k, int u) {
+  return (size_t)((TC + u + k) * (k + 1) + TC * (k + u + 1)) * 8;
+}
+
+template <typename T> __global__ void __launch_bounds__(256) k_solve_mat(int64_t n, GB<T> L, GB<T> R, GB<T> O) {
+  extern __shared__ double dyn[];
+  const int k = L.l, u = O.u, WL = k + 1, WR = R.l + R.u + 1, WO = k + u + 1, TC = (int)blockDim.x;
+  const int64_t c0 = (int64_t)blockIdx.x * TC, c1 = c0 + TC < n ? c0 + TC : n;
+  double *sL = dyn;                       // L records [c0 - u, c1 + k)
+  double *sR = sL + (TC + u + k) * WL;    // R records [c0, c1)
+  double *sO = sR + TC * WR;              // O records [c0, c1)
+  stage_rec(sL, L, c0 - u, c1 + k, n, WL);
+  stage_rec(sR, R, c0, c1, n, WR);
+  __syncthreads();
+  const int64_t c = c0 + threadIdx.x;
+  if (c < c1) {
+    double *col = sO + threadIdx.x * WO;                          // O(c-u+s, c) at col[s]
+    auto lv = [&](int64_t i, int64_t m) { return sL[(m - (c0 - u)) * WL + (i - m)]; };   // L(i, m)
+    for (int s = 0; s < WO; ++s) {
+      const int64_t i = c - u + s;
+      double v = 0.0;
+      if (i >= 0 && i < n) {
+        double acc = (i - c <= R.l) ? sR[threadIdx.x * WR + s] : 0.0;   // R(i, c): slot u + i - c = s
+        int64_t m0 = i - k > c - u ? i - k : c - u;
+        if (m0 < 0) m0 = 0;
+        for (int64_t m = m0; m < i; ++m) acc -= lv(i, m) * col[m - (c - u)];
+        v = acc / lv(i, i);
+      }
+      col[s] = v;
+    }
+  }
+  __syncthreads();
+  store_rec(O, sO, c0, c1, WO);
 }
 
 // Reverse mode of Algorithm 5 (Table 1, solve matrix-matrix), first step:
 // G = L^{-T} Obar on the band (k, u) (FP64, record c at G + c (k+u+1)), one
 // lane per column, rows c+k .. c-u descending (back substitution with L^T).
-template <typename T> __global__ void k_solve_mat_g(int64_t n, GB<T> L, GB<T> Ob, double *G) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n) return;
-  const int k = L.l, u = Ob.u, w = k + u + 1;
-  double col[kSolveCol];
-  for (int s = k + u; s >= 0; --s) {
-    const int64_t i = c - u + s;
-    double v = 0.0;
-    if (i >= 0 && i < n) {
-      double acc = Ob.get(i, c);
-      int64_t m1 = i + k < c + k ? i + k : c + k;
-      if (m1 > n - 1) m1 = n - 1;
-      for (int64_t m = i + 1; m <= m1; ++m) acc -= L.get(m, i) * col[m - (c - u)];
-      v = acc / L.get(i, i);
+// Staged like the forward kernel; a column's Obar record is overwritten in
+// LDS by G as the substitution goes (slot s is read before it is written, and
+// later slots only read G).
+template <typename T>
+__global__ void __launch_bounds__(256) k_solve_mat_g(int64_t n, GB<T> L, GB<T> Ob, double *G, GB<T> Rb) {
+  extern __shared__ double dyn[];
+  const int k = L.l, u = Ob.u, WL = k + 1, WO = k + u + 1, TC = (int)blockDim.x;
+  const int64_t c0 = (int64_t)blockIdx.x * TC, c1 = c0 + TC < n ? c0 + TC : n;
+  double *sL = dyn;                       // L records [c0 - u, c1 + k)
+  double *sG = sL + (TC + u + k) * WL;    // Obar, then G, records [c0, c1)
+  stage_rec(sL, L, c0 - u, c1 + k, n, WL);
+  stage_rec(sG, Ob, c0, c1, n, WO);
+  __syncthreads();
+  const int64_t c = c0 + threadIdx.x;
+  if (c < c1) {
+    double *col = sG + threadIdx.x * WO;
+    auto lv = [&](int64_t i, int64_t m) { return sL[(m - (c0 - u)) * WL + (i - m)]; };
+    for (int s = WO - 1; s >= 0; --s) {
+      const int64_t i = c - u + s;
+      double v = 0.0;
+      if (i >= 0 && i < n) {
+        double acc = col[s];
+        int64_t m1 = i + k < c + k ? i + k : c + k;
+        if (m1 > n - 1) m1 = n - 1;
+        for (int64_t m = i + 1; m <= m1; ++m) acc -= lv(m, i) * col[m - (c - u)];
+        v = acc / lv(i, i);
+      }
+      col[s] = v;
     }
-    col[s] = v;
-    G[c * w + s] = v;
+  }
+  __syncthreads();
+  for (int64_t e = threadIdx.x; e < (c1 - c0) * WO; e += blockDim.x) G[c0 * WO + e] = sG[e];
+  // Rbar = G on R's band (lr lower, u upper): slot u + (i - c) of both
+  const int WR = Rb.l + Rb.u + 1;
+  for (int64_t e = threadIdx.x; e < (c1 - c0) * WR; e += blockDim.x) {
+    const int64_t cc = e / WR;
+    const int sr = (int)(e - cc * WR);
+    const int64_t c = c0 + cc, i = c - Rb.u + sr;
+    const double v = (i >= 0 && i < n && sr < WO) ? sG[cc * WO + sr] : 0.0;
+    Rb.p[c * Rb.ld + sr] = (T)v;
+    if (sr == Rb.u && Rb.diag) Rb.diag[c] = v;
   }
 }
 
-// Second step, one lane per stored entry: Rbar = G on the band of R, and
-// Lbar(i, m) = -sum_c G(i, c) O(m, c) over c in [i-k, m+u] (both factors in
-// their bands there).
-template <typename T>
-__global__ void k_solve_mat_rbar(int64_t n, int k, int u, const double *G, GB<T> Rb) {
-  const int64_t w = Rb.l + Rb.u + 1, t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n * w) return;
-  const int64_t c = t / w, s = t - c * w, i = c - Rb.u + s;
-  double v = 0.0;
-  if (i >= 0 && i < n && i - c <= k && c - i <= u) v = G[c * (k + u + 1) + u + (i - c)];
-  Rb.p[c * Rb.ld + s] = (T)v;
-  if (s == Rb.u && Rb.diag) Rb.diag[c] = v;
+// Second step, one lane per record m of Lbar: Lbar(i, m) = -sum_c G(i, c)
+// O(m, c) over c in [i-k, m+u] (both factors in their bands there), i = m ..
+// m+k.  The G and O records of columns m0-k .. m1+u-1 are staged in LDS.
+__host__ __device__ constexpr size_t solve_mat_lbar_lds(int TC, int k, int u) {
+  return (size_t)(2 * (TC + k + u) * (k + u + 1) + TC * (k + 1)) * 8;
 }
 template <typename T>
-__global__ void k_solve_mat_lbar(int64_t n, int k, int u, const double *G, GB<T> O, GB<T> Lb) {
-  const int64_t w = k + 1, t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n * w) return;
-  const int64_t m = t / w, d = t - m * w, i = m + d;
-  double acc = 0.0;
-  if (i < n) {
-    int64_t c0 = i - k > 0 ? i - k : 0, c1 = m + u < n - 1 ? m + u : n - 1;
-    for (int64_t c = c0; c <= c1; ++c) acc += G[c * (k + u + 1) + u + (i - c)] * O.get(m, c);
+__global__ void __launch_bounds__(256) k_solve_mat_lbar(int64_t n, int k, int u, const double *G, GB<T> O, GB<T> Lb) {
+  extern __shared__ double dyn[];
+  const int WO = k + u + 1, WL = k + 1, TC = (int)blockDim.x;
+  const int64_t m0 = (int64_t)blockIdx.x * TC, m1 = m0 + TC < n ? m0 + TC : n;
+  const int64_t r0 = m0 - k, r1 = m1 + u;
+  double *sG = dyn;                        // G records [r0, r1)
+  double *sO = sG + (TC + k + u) * WO;     // O records [r0, r1)
+  double *sOut = sO + (TC + k + u) * WO;   // Lbar records [m0, m1)
+  {
+    const int64_t lo = r0 > 0 ? r0 : 0, hi = r1 < n ? r1 : n;
+    for (int64_t e = threadIdx.x; e < (hi - lo) * WO; e += blockDim.x) sG[(lo - r0) * WO + e] = G[lo * WO + e];
   }
-  Lb.p[m * Lb.ld + d] = (T)(-acc);
-  if (d == 0 && Lb.diag) Lb.diag[m] = -acc;
+  stage_rec(sO, O, r0, r1, n, WO);
+  __syncthreads();
+  const int64_t m = m0 + threadIdx.x;
+  if (m < m1) {
+    for (int d = 0; d < WL; ++d) {
+      const int64_t i = m + d;
+      double acc = 0.0;
+      if (i < n) {
+        int64_t ca = i - k > 0 ? i - k : 0, cb = m + u < n - 1 ? m + u : n - 1;
+        for (int64_t c = ca; c <= cb; ++c) acc += sG[(c - r0) * WO + u + (i - c)] * sO[(c - r0) * WO + u + (m - c)];
+      }
+      sOut[threadIdx.x * WL + d] = -acc;
+    }
+  }
+  __syncthreads();
+  store_rec(Lb, sOut, m0, m1, WL);
 }
 
 unsigned blocks_for(int64_t count, int block) { return (unsigned)((count + block - 1) / block); }
@@ -443,7 +520,7 @@ static const char *const kStepNames[kProfSlots] = {
     "chunk_product", "fs_summary", "fs_replay", "f2_summary", "f2_replay", "b1_summary",
     "b1_replay", "b2_summary", "b2_replay", "asc_group_compose", "asc_group_sweep",
     "asc_chunk_sweep", "desc_group_compose", "desc_group_sweep", "desc_chunk_sweep",
-    "clear_partials", "finalize", "wide_f1", "wide_f2", "wide_b1", "wide_b2", "vi_pre", "vi_post", "vi_neg"};
+    "clear_partials", "finalize", "wide_f1", "wide_f2", "wide_b1", "wide_b2", "vi_pre", "vi_post", "vi_neg", "solve_mat", "solve_mat_g", "solve_mat_out"};
 
 extern "C" int bo_profile_slots(void) { return kProfSlots; }
 
@@ -569,13 +646,19 @@ extern "C" bo_status bo_solve_band_mat(bo_prec prec, const bo_band *L, const bo_
   if (L->l > 12 || R->u > 12) return fail(BO_EUNSUPPORTED, "bo_solve_band_mat: widths above 12");
   const int64_t n = O->n;
   if (n == 0) return BO_OK;
-  if (prec == BO_F64)
-    hipLaunchKernelGGL(k_solve_mat<double>, dim3(blocks_for(n, 256)), dim3(256), 0, stream, n, gb<double>(L),
-                       gb<double>(R), gb<double>(O));
-  else
-    hipLaunchKernelGGL(k_solve_mat<float>, dim3(blocks_for(n, 256)), dim3(256), 0, stream, n, gb<float>(L),
-                       gb<float>(R), gb<float>(O));
-  return dev_status(hipGetLastError() == hipSuccess ? 0 : -2, "bo_solve_band_mat");
+  const int e = profiled(kSlotSolveMat, stream, [&] {
+    int TC = 256;
+    while (TC > 64 && solve_mat_lds(TC, L->l, R->l, R->u) > 48 * 1024) TC /= 2;
+    const size_t lds = solve_mat_lds(TC, L->l, R->l, R->u);
+    if (prec == BO_F64)
+      hipLaunchKernelGGL(k_solve_mat<double>, dim3(blocks_for(n, TC)), dim3(TC), lds, stream, n, gb<double>(L),
+                         gb<double>(R), gb<double>(O));
+    else
+      hipLaunchKernelGGL(k_solve_mat<float>, dim3(blocks_for(n, TC)), dim3(TC), lds, stream, n, gb<float>(L),
+                         gb<float>(R), gb<float>(O));
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+  });
+  return dev_status(e, "bo_solve_band_mat");
 }
 
 extern "C" size_t bo_solve_band_mat_workspace(int64_t n, int32_t k, int32_t u) {
@@ -601,23 +684,33 @@ extern "C" bo_status bo_solve_band_mat_bwd(bo_prec prec, const bo_band *L, const
     return fail(BO_EWORKSPACE, "bo_solve_band_mat_bwd: workspace smaller than bo_solve_band_mat_workspace()");
   double *G = (double *)ws;
   const int k = L->l, u = O->u;
-  const int64_t wr = (int64_t)Rbar->l + Rbar->u + 1;
-  if (prec == BO_F64) {
-    hipLaunchKernelGGL(k_solve_mat_g<double>, dim3(blocks_for(n, 256)), dim3(256), 0, stream, n, gb<double>(L),
-                       gb<double>(Obar), G);
-    hipLaunchKernelGGL(k_solve_mat_rbar<double>, dim3(blocks_for(n * wr, 256)), dim3(256), 0, stream, n, k, u,
-                       (const double *)G, gb<double>(Rbar));
-    hipLaunchKernelGGL(k_solve_mat_lbar<double>, dim3(blocks_for(n * (k + 1), 256)), dim3(256), 0, stream, n, k,
-                       u, (const double *)G, gb<double>(O), gb<double>(Lbar));
-  } else {
-    hipLaunchKernelGGL(k_solve_mat_g<float>, dim3(blocks_for(n, 256)), dim3(256), 0, stream, n, gb<float>(L),
-                       gb<float>(Obar), G);
-    hipLaunchKernelGGL(k_solve_mat_rbar<float>, dim3(blocks_for(n * wr, 256)), dim3(256), 0, stream, n, k, u,
-                       (const double *)G, gb<float>(Rbar));
-    hipLaunchKernelGGL(k_solve_mat_lbar<float>, dim3(blocks_for(n * (k + 1), 256)), dim3(256), 0, stream, n, k, u,
-                       (const double *)G, gb<float>(O), gb<float>(Lbar));
-  }
-  return dev_status(hipGetLastError() == hipSuccess ? 0 : -2, "bo_solve_band_mat_bwd");
+  const bool f64 = prec == BO_F64;
+  int e = profiled(kSlotSolveMatG, stream, [&] {
+    int TC = 256;
+    while (TC > 64 && solve_mat_g_lds(TC, k, u) > 48 * 1024) TC /= 2;
+    const size_t lds = solve_mat_g_lds(TC, k, u);
+    if (f64)
+      hipLaunchKernelGGL(k_solve_mat_g<double>, dim3(blocks_for(n, TC)), dim3(TC), lds, stream, n, gb<double>(L),
+                         gb<double>(Obar), G, gb<double>(Rbar));
+    else
+      hipLaunchKernelGGL(k_solve_mat_g<float>, dim3(blocks_for(n, TC)), dim3(TC), lds, stream, n, gb<float>(L),
+                         gb<float>(Obar), G, gb<float>(Rbar));
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+  });
+  if (e == 0)
+    e = profiled(kSlotSolveMatOut, stream, [&] {
+      int TC = 256;
+      while (TC > 64 && solve_mat_lbar_lds(TC, k, u) > 48 * 1024) TC /= 2;
+      const size_t lds = solve_mat_lbar_lds(TC, k, u);
+      if (f64)
+        hipLaunchKernelGGL(k_solve_mat_lbar<double>, dim3(blocks_for(n, TC)), dim3(TC), lds, stream, n, k, u,
+                           (const double *)G, gb<double>(O), gb<double>(Lbar));
+      else
+        hipLaunchKernelGGL(k_solve_mat_lbar<float>, dim3(blocks_for(n, TC)), dim3(TC), lds, stream, n, k, u,
+                           (const double *)G, gb<float>(O), gb<float>(Lbar));
+      return hipGetLastError() == hipSuccess ? 0 : -2;
+    });
+  return dev_status(e, "bo_solve_band_mat_bwd");
 }
 
 extern "C" bo_status bo_gbmv(bo_prec prec, const bo_band *A, int tA, const void *x, void *y,

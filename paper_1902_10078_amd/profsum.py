@@ -63,6 +63,9 @@ _KERNEL_SLOTS = [
     (r"k_kl_pre", "vi_pre"),
     (r"k_kl_post", "vi_post"),
     (r"k_kl_neg", "vi_neg"),
+    (r"k_solve_mat<", "solve_mat"),
+    (r"k_solve_mat_g<", "solve_mat_g"),
+    (r"k_solve_mat_lbar", "solve_mat_out"),
     (r"k_kl_finalize|k_finalize", "finalize"),
     (r"ClearPart", "clear_partials"),
     (r"k_gbmm", "gbmm"),
