@@ -130,7 +130,7 @@ def measured_traffic(slot: str, path: str, rows: int):
     workload, or the kernels have changed since it was taken."""
     from paper_1902_10078_amd import profsum
     tr, meta = profsum.read_traffic(path)
-    if slot not in tr or meta.get("source_hash") != profsum.source_hash():
+    if slot not in tr or meta.get("source_hash") != profsum.source_hash(meta.get("hash_sources")):
         return None
     if int(meta.get("rows_per_launch", -1)) != rows:
         return None

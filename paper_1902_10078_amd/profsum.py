@@ -82,19 +82,20 @@ def slot_of(kernel_name: str) -> str | None:
     return None
 
 
-# Sources of the row-streaming kernels, their scans and their schedule.
+# Sources of the row-streaming kernels, their scans and their schedule (the
+# default set a traffic summary is tied to); a summary can name others.
 _KERNEL_SOURCES = ("bandops_algo.hpp", "bandops_step.hpp", "bandops_items.hpp", "bandops_tile.hpp",
-                   "bandops_driver.hpp", "bandops_steps.hpp", "bandops_kern.hip", "bandops_vi.hpp")
+                   "bandops_driver.hpp", "bandops_steps.hpp", "bandops_kern.hip")
 
 
-def source_hash() -> str:
-    """Hash of the sources that decide what the row-streaming kernels execute
-    and how the batch is cut into chunks."""
+def source_hash(sources=None) -> str:
+    """Hash of the sources (file names under csrc/) that decide what the
+    measured kernels execute; default: the row-streaming kernels."""
     h = hashlib.sha256()
-    files = sorted(os.path.join(HERE, "csrc", f) for f in _KERNEL_SOURCES)
-    for f in files:
-        h.update(os.path.basename(f).encode())
-        with open(f, "rb") as fh:
+    names = sorted(sources.split(",") if isinstance(sources, str) else (sources or _KERNEL_SOURCES))
+    for f in names:
+        with open(os.path.join(HERE, "csrc", f), "rb") as fh:
+            h.update(f.encode())
             h.update(fh.read())
     return h.hexdigest()[:16]
 
@@ -138,7 +139,9 @@ def traffic(args):
     print(f"fetch_scale: {fscale:.4f}")
     print(f"write_scale: {wscale:.4f}")
     print(f"rows_per_launch: {args.rows}")
-    print(f"source_hash: {source_hash()}")
+    srcs = args.sources or ",".join(_KERNEL_SOURCES)
+    print(f"hash_sources: {srcs}")
+    print(f"source_hash: {source_hash(srcs)}")
     print(f"# {'slot':20s} {'fetch_GB':>10s} {'write_GB':>10s} {'traffic_GB':>11s} {'B/row':>8s}")
     seen = set()
     for k, (fv, n) in fe.items():
@@ -184,6 +187,7 @@ def main(argv=None):
     t.add_argument("--cmd", default="")
     t.add_argument("--cmd-fetch", default="")
     t.add_argument("--cmd-write", default="")
+    t.add_argument("--sources", default="", help="comma-separated csrc/ files the measured kernels come from")
     a = ap.parse_args(argv)
     (stats if a.cmd_name == "stats" else traffic)(a)
 
