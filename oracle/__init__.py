@@ -62,6 +62,7 @@ def _load():
         "or_gauss_loss_batch": (i32, [i32, P, P, P, P, P, P, P, P, P, P, P]),
         "or_forward_batch": (i32, [i32, P, P, P, P, P, P, P, P, P, P, P, P]),
         "or_solve_band_mat_bwd": (None, [i64, i32, i64, P, i32, i32, i64, P, P, i64, P, P]),
+        "or_marglik": (i32, [i64, i32, i64, P, P, P, dbl, P, P, P, P]),
         "or_vi_kl": (None, [i64, i32, i64, P, P, P, P, P, P, P, P, P, P]),
         "or_vi_kl_batch": (i32, [i32, P, P, P, P, P, P, P, P, P, P, P, P, P]),
     }
@@ -283,3 +284,18 @@ def vi_kl_batch(ns, ks, Lq, Lp, mq, mp):
     th = _load().or_vi_kl_batch(len(ns), _p(ns), _p(ks), _p(boff), _p(voff), _p(Lq), _p(Lp), _p(mq),
                                 _p(mp), _p(parts), _p(Lqbar), _p(Lpbar), _p(mqbar), _p(mpbar))
     return parts, Lqbar, Lpbar, mqbar, mpbar, int(th)
+
+
+def marglik(Q, k, mask, b, tau2):
+    """Log marginal likelihood of Eq. (marg_lik) / Algorithm 8 and its reverse
+    mode.  Returns dict with parts (4,) = (log p(Y), log|L|, log|L_Q|,
+    ||L^{-1} b||^2), Qbar, bbar, tau2bar, info."""
+    Q, mask, b = _f64(Q), _f64(mask), _f64(b)
+    n, ld = Q.shape
+    parts = np.zeros(4)
+    Qbar = np.zeros_like(Q)
+    bbar = np.zeros_like(b)
+    t2 = ctypes.c_double(0.0)
+    info = _load().or_marglik(n, k, ld, _p(Q), _p(mask), _p(b), float(tau2), _p(parts), _p(Qbar), _p(bbar),
+                              ctypes.byref(t2))
+    return dict(parts=parts, Qbar=Qbar, bbar=bbar, tau2bar=t2.value, info=int(info))

@@ -438,6 +438,80 @@ int or_gauss_loss(int64_t n, int k, int64_t ld, const double *Q,
 }
 
 /* --------------------------------------------------------------------------
+ * Marginal likelihood (Eq. (marg_lik), Algorithm 8) in the order of Algorithm
+ * 8: L = C(Q + tau^-2 E^T E), L' = C(Q), R = S(L, E^T Y), then the terms of
+ * Eq. (marg_lik) (Algorithm 8 as printed omits -(m/2) log tau2; the equation
+ * keeps it, and it is kept here).  Reverse mode through Table 1:
+ *   -log|L|:            Lbar  = logdet_bwd(L, -1/2)
+ *   R^T R / (2 tau^4):  Rbar = R / tau^4; (bbar, Lbar') = solve bwd
+ *   Qbar = chol_bwd(L, Lbar + Lbar') + chol_bwd(L', logdet_bwd(L', 1/2))
+ * (Q + tau^-2 E^T E and Q share their stored off-diagonal entries, and the
+ * diagonal shift is additive, so both factors' sensitivities add onto Q);
+ *   bbar += -b / tau2 (the Y^T Y term), restricted to the observed nodes;
+ *   tau2bar = -tau^-4 sum_i mask_i Qbar1_ii (Q1's dependence on tau2)
+ *             - m / (2 tau2) + Y^T Y / (2 tau2^2) - R^T R / tau2^3.
+ * ------------------------------------------------------------------------ */
+int or_marglik(int64_t n, int k, int64_t ld, const double *Q, const double *mask,
+               const double *b, double tau2, double *parts, double *Qbar,
+               double *bbar, double *tau2bar) {
+  size_t bsz = (size_t)(n * ld + 1) * sizeof(double);
+  size_t vsz = (size_t)(n + 1) * sizeof(double);
+  double *Q1 = (double *)malloc(bsz), *L = (double *)malloc(bsz), *Lp = (double *)malloc(bsz);
+  double *Lb = (double *)calloc((size_t)(n * ld + 1), sizeof(double));
+  double *Lb2 = (double *)calloc((size_t)(n * ld + 1), sizeof(double));
+  double *Lpb = (double *)calloc((size_t)(n * ld + 1), sizeof(double));
+  double *Qb1 = (double *)calloc((size_t)(n * ld + 1), sizeof(double));
+  double *Qb0 = (double *)calloc((size_t)(n * ld + 1), sizeof(double));
+  double *R = (double *)malloc(vsz), *Rb = (double *)malloc(vsz);
+  double m = 0.0, yy = 0.0;
+  for (int64_t t = 0; t < n * ld; ++t) Q1[t] = Q[t];
+  for (int64_t i = 0; i < n; ++i) {
+    LOW(Q1, ld, i, i) += mask[i] / tau2;
+    m += mask[i];
+    yy += b[i] * b[i];
+  }
+  int info = or_chol(n, k, ld, Q1, L);
+  int info0 = info ? 0 : or_chol(n, k, ld, Q, Lp);
+  if (info || info0) {
+    parts[0] = parts[1] = parts[2] = parts[3] = NAN;
+    *tau2bar = NAN;
+  } else {
+    double lL = 0.5 * or_logdet(n, k, ld, L), lLp = 0.5 * or_logdet(n, k, ld, Lp), rr = 0.0;
+    or_trsv(n, k, ld, L, 0, b, R);
+    for (int64_t i = 0; i < n; ++i) rr += R[i] * R[i];
+    parts[1] = lL;
+    parts[2] = lLp;
+    parts[3] = rr;
+    parts[0] = -0.5 * m * log(2.0 * 3.14159265358979323846) - lL + lLp - 0.5 * m * log(tau2) - yy / (2.0 * tau2) +
+               rr / (2.0 * tau2 * tau2);
+    /* reverse */
+    or_logdet_bwd(n, k, ld, L, -0.5, Lb);
+    for (int64_t i = 0; i < n; ++i) Rb[i] = R[i] / (tau2 * tau2);
+    or_trsv_bwd(n, k, ld, L, 0, R, Rb, bbar, Lb2);
+    for (int64_t t = 0; t < n * ld; ++t) Lb[t] += Lb2[t];
+    or_chol_bwd(n, k, ld, L, Lb, Qb1);
+    or_logdet_bwd(n, k, ld, Lp, 0.5, Lpb);
+    or_chol_bwd(n, k, ld, Lp, Lpb, Qb0);
+    double dq = 0.0;
+    for (int64_t i = 0; i < n; ++i) dq += mask[i] * LOW(Qb1, ld, i, i);
+    for (int64_t t = 0; t < n * ld; ++t) Qbar[t] = Qb1[t] + Qb0[t];
+    for (int64_t i = 0; i < n; ++i) bbar[i] = mask[i] != 0.0 ? bbar[i] - b[i] / tau2 : 0.0;
+    *tau2bar = -dq / (tau2 * tau2) - 0.5 * m / tau2 + yy / (2.0 * tau2 * tau2) - rr / (tau2 * tau2 * tau2);
+  }
+  free(Q1);
+  free(L);
+  free(Lp);
+  free(Lb);
+  free(Lb2);
+  free(Lpb);
+  free(Qb1);
+  free(Qb0);
+  free(R);
+  free(Rb);
+  return info ? info : (info0 ? (int)(info0 + n) : 0);
+}
+
+/* --------------------------------------------------------------------------
  * Variational KL term (Section 3.3, Eq. (KL), Algorithm 7), in the order of
  * Algorithm 7: the band of I(L_q), the product P(L_p, L_p^T), the trace as the
  * element-wise product over the band, the log-diagonals, P(L_p^T, m_p - m_q).

@@ -114,6 +114,23 @@ int or_gauss_loss(int64_t n, int k, int64_t ld, const double *Q,
                   double *Qbar, double *ybar, double *L, double *z,
                   double *Sig, double *Lbar);
 
+/* Log marginal likelihood of a conjugate GMRF with partial observations
+ * (Section 3.1, Eq. (marg_lik); Algorithm 8): prior precision Q (lower band,
+ * k sub-diagonals, stride ld) over n nodes, observation mask (1 at the
+ * observed nodes, 0 elsewhere: the diagonal of E^T E), b = E^T Y (observed
+ * values at their nodes, 0 elsewhere) and noise variance tau2:
+ *   log p(Y) = -(m/2) log 2 pi - log|L| + log|L_Q| - (m/2) log tau2
+ *              - Y^T Y / (2 tau2) + ||L^{-1} b||^2 / (2 tau2^2),
+ * L L^T = Q + E^T E / tau2, L_Q L_Q^T = Q, m = number of observed nodes.
+ * parts[0] = log p(Y), parts[1] = log|L|, parts[2] = log|L_Q|,
+ * parts[3] = ||L^{-1} b||^2.  Reverse mode (Table 1 compositions): Qbar
+ * (stored lower-band entries), bbar (d log p / d b at the observed nodes, 0
+ * elsewhere) and *tau2bar.  Returns 0, or the Cholesky info of the posterior
+ * (as is) or of the prior (+ n). */
+int or_marglik(int64_t n, int k, int64_t ld, const double *Q, const double *mask,
+               const double *b, double tau2, double *parts, double *Qbar,
+               double *bbar, double *tau2bar);
+
 /* Kullback-Leibler term of the variational objective (Section 3.3, Eq. (KL);
  * Algorithm 7): q = N(m_q, (L_q L_q^T)^{-1}), p = N(m_p, (L_p L_p^T)^{-1}), with
  * L_q and L_p lower bands of the same width k (stride ld), composed from I, P
