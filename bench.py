@@ -20,6 +20,15 @@ Other workloads (--workload):
   wide_loss        8 wide block-banded problems (n = 2e5, k = 64, Q = D +
                    band(B B^T)): loss = log det Q + tr(Q^{-1} W) forward and
                    backward on 64 x 64 blocks (FP32 MFMA products, FP64 pivots).
+  vi_kl            16 KL terms KL(q || p) of Algorithm 7 (n = 1e6, k = 5) with
+                   their gradients in L_q, L_p, m_q, m_p;
+  solve_band_mat   one matrix solve with a banded right-hand side (Algorithm
+                   5; n = 1.6e7, k = 5, R with 2 lower and 5 upper diagonals)
+                   and its reverse mode;
+  marglik          16 log marginal likelihoods with partial observations
+                   (Algorithm 8) on the Matérn-5/2 priors of the loss
+                   workload, 80% of the inputs' function values observed,
+                   with the gradients in Q, b and tau2.
 
 Prints ONE JSON line on stdout; diagnostics go to stderr.
 """
@@ -88,6 +97,20 @@ def vi_bytes_per_row(k: int, prec: int):
             "unit": 5 * wb + 4 * wv}                 # inputs L_q, L_p, m_q, m_p; outputs Sigma and the gradients
 
 
+def ml_bytes_per_row(k: int, prec: int):
+    """Algorithmic bytes per row of the marginal likelihood's kernels
+    (Algorithm 8 and its reverse mode): two forward lists (on Q without a
+    right-hand side, on Q1 with b) and the row kernels around them."""
+    wb, wv = record_bytes(k, prec)
+    return {"ml_pre": 2 * wb + wv,                  # Q, mask -> Q1
+            "chunk_product": 0,                      # chunk scans only (written by the F1 replays)
+            "f1_summary": 2 * wb + wv,               # Q; Q1, b
+            "f1_replay": 4 * wb + 2 * wv,            # Q -> L_Q; Q1, b -> L, z
+            "f2_replay": 4 * wb + 2 * wv,            # L_Q -> I(L_Q); L, z -> Sigma, x
+            "ml_post": 3 * wb + 4 * wv,              # Sigma, I(L_Q), x, mask, b -> Qbar, bbar
+            "unit": 4 * wb + 4 * wv}                 # Q, mask, b in; L, Sigma, x, Qbar, bbar out
+
+
 def alg5_bytes_per_row(k: int, lr: int, u: int):
     """Algorithmic bytes per row of the matrix solve with a banded right-hand
     side (Algorithm 5) and its reverse mode, FP64."""
@@ -108,11 +131,12 @@ def wide_bytes_per_row():
             "unit": 11 * wb}
 
 
-def batch_bytes(ns, ks, prec, forward_only, vi=False):
+def batch_bytes(ns, ks, prec, forward_only, vi=False, ml=False):
     """Algorithmic bytes of one step of each kernel kind over the batch."""
     tot = {}
     for n, k in zip(ns, ks):
-        per = vi_bytes_per_row(k, prec) if vi else bytes_per_row(k, prec, forward_only)
+        per = (vi_bytes_per_row(k, prec) if vi else ml_bytes_per_row(k, prec) if ml
+               else bytes_per_row(k, prec, forward_only))
         for nm, b in per.items():
             tot[nm] = tot.get(nm, 0) + b * n
     return tot
@@ -341,6 +365,79 @@ def make_vi(args):
     return [args.n_vi] * args.batch, [5] * args.batch, (Lqs, Lps, mqs, mps)
 
 
+class MLWorkload:
+    """The log marginal likelihood with partial observations over a batch
+    (inputs resident on the device): Q, mask, b, tau2 in; L, Sigma, x, Qbar,
+    bbar, tau2bar, the parts and info out."""
+
+    def __init__(self, bo, torch, dev, ns, ks, prec, host_inputs, target_chunks=0):
+        self.bo, self.torch, self.dev = bo, torch, dev
+        self.ns, self.ks, self.prec = ns, ks, prec
+        Qs, masks, bs, tau2 = host_inputs
+        vdt = torch.float64 if prec == bo.F64 else torch.float32
+        up = lambda arrs: torch.from_numpy(np.concatenate([a.ravel() for a in arrs])).to(dev, vdt)
+        kw = dict(Q=up(Qs), mask=up(masks), b=up(bs),
+                  tau2=torch.tensor(np.asarray(tau2, dtype=np.float64), device=dev))
+        E, N, P = kw["Q"].numel(), kw["b"].numel(), len(ns)
+        for nm in ("L", "Sig", "Qbar"):
+            kw[nm] = torch.zeros(E, dtype=vdt, device=dev)
+        for nm in ("x", "bbar"):
+            kw[nm] = torch.zeros(N, dtype=vdt, device=dev)
+        kw["tau2bar"] = torch.zeros(P, dtype=torch.float64, device=dev)
+        kw["parts"] = torch.zeros((P, 4), dtype=torch.float64, device=dev)
+        kw["info"] = torch.zeros(P, dtype=torch.int32, device=dev)
+        if prec == bo.MIXED:
+            kw["Qd"] = torch.from_numpy(np.concatenate([a[:, 0] for a in Qs])).to(dev)
+            for nm in ("Ld", "Sigd", "Qbard"):
+                kw[nm] = torch.zeros(N, dtype=torch.float64, device=dev)
+        self.kw = kw
+        self.set_schedule(target_chunks)
+
+    def set_schedule(self, target_chunks: int):
+        self.plan = self.bo.Plan(self.ns, self.ks, target_chunks=target_chunks, device=self.dev)
+        self.io = self.plan.ml_io(**self.kw)
+
+    def step(self):
+        self.plan.marglik(self.prec, self.io)
+
+    def plain_steps(self):
+        """The plain FP64 form: one plan per matrix, host loop, no graph."""
+        bo = self.bo
+        out = []
+        for p in range(len(self.ns)):
+            n, k = self.ns[p], self.ks[p]
+            pl = bo.Plan([n], [k], device=self.dev)
+            o, v, sz = self.plan.boff[p], self.plan.voff[p], n * (k + 1)
+            kw = {}
+            for nm, t in self.kw.items():
+                if nm in ("parts", "tau2", "tau2bar", "info"):
+                    kw[nm] = t[p:p + 1]
+                elif nm in ("mask", "b", "x", "bbar") or nm.endswith("d"):
+                    kw[nm] = t[v:v + n]
+                else:
+                    kw[nm] = t[o:o + sz]
+            out.append((pl, pl.ml_io(**kw)))
+
+        def run():
+            for pl, pio in out:
+                pl.marglik(bo.F64, pio)
+        return run
+
+
+def make_ml(args):
+    """The Matérn-5/2 prior precisions of the loss workload with each input's
+    function value observed with probability 0.8, noise variance 0.1."""
+    from paper_1902_10078_amd import inputs
+    Qs, masks, bs, t2 = [], [], [], []
+    for b in range(args.batch):
+        Q, mask, y, tau2 = inputs.config5_marglik(b, n_in=args.n_in, nbatch=16)
+        Qs.append(Q)
+        masks.append(mask)
+        bs.append(y)
+        t2.append(tau2)
+    return [q.shape[0] for q in Qs], [5] * args.batch, (Qs, masks, bs, t2)
+
+
 class Alg5Workload:
     """One matrix: O = band of L^{-1} R (Algorithm 5) and the reverse mode
     (Table 1, solve matrix-matrix) from a fixed Obar; every output and the
@@ -454,6 +551,21 @@ def cpu_baseline_alg5(host_inputs, widths, rows: int):
                        f"one thread, {dt:.2f} s wall"), O
 
 
+def cpu_baseline_ml(host_inputs, ns, ks, nsample: int):
+    """The FP64 oracle (Algorithm 8 and its reverse mode), one thread, problem
+    after problem, on the first `nsample` problems."""
+    import oracle
+    Qs, masks, bs, t2 = host_inputs
+    idx = list(range(min(nsample, len(ns))))
+    t0 = time.perf_counter()
+    ref = np.array([oracle.marglik(Qs[i], ks[i], masks[i], bs[i], t2[i])["parts"] for i in idx])
+    dt = time.perf_counter() - t0
+    rows = sum(ns[i] for i in idx)
+    return dict(value=rows / dt, unit="band-rows/s", cores=1, kind="oracle",
+                sample=f"{len(idx)} of the workload's {len(ns)} problems ({rows} rows), FP64 C oracle "
+                       f"(forward and reverse), one thread, {dt:.2f} s wall"), ref
+
+
 def cpu_baseline(host_inputs, ns, ks, nsample: int, vi: bool = False):
     """The FP64 oracle as it stands, OpenMP across problems, on a bounded
     sample of the workload's problems."""
@@ -493,7 +605,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", choices=["matern52_loss", "uneven_forward", "matern32_forward", "wide_loss",
-                                           "vi_kl", "solve_band_mat"], default="matern52_loss")
+                                           "vi_kl", "solve_band_mat", "marglik"], default="matern52_loss")
     ap.add_argument("--prec", choices=["f64", "mixed"], default=None,
                     help="storage format (default: f64; mixed for uneven_forward)")
     ap.add_argument("--batch", type=int, default=16)
@@ -506,8 +618,8 @@ def main():
     ap.add_argument("--n-vi", type=int, default=1_000_000, help="rows per problem of the KL batch")
     ap.add_argument("--n-alg5", type=int, default=16_000_000, help="rows of the Algorithm 5 matrix")
     ap.add_argument("--cpu-sample", type=int, default=0,
-                    help="problems timed on the CPU oracle (default: 8 for the loss batch, "
-                         "256 for the uneven batch, 1 otherwise)")
+                    help="problems timed on the CPU oracle (default: 8 for the loss, KL and "
+                         "marginal-likelihood batches, 256 for the uneven batch, 1 otherwise)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
@@ -543,6 +655,7 @@ def main():
     forward_only = args.workload in ("uneven_forward", "matern32_forward")
     wide = args.workload == "wide_loss"
     vi = args.workload == "vi_kl"
+    ml = args.workload == "marglik"
     alg5 = args.workload == "solve_band_mat"
     if args.workload == "matern52_loss":
         ns, ks, host_inputs = make_matern52(args)
@@ -559,6 +672,11 @@ def main():
         cfg = {"workload": f"solve_band_mat_rows{ns[0]}_k5_R2-5_fwd_bwd", "batch": 1,
                "rows_per_problem": ns[0], "k": 5, "R_lower": 2, "R_upper": 5}
         nsample = 0
+    elif ml:
+        ns, ks, host_inputs = make_ml(args)
+        cfg = {"workload": f"marglik_matern52_batch{len(ns)}_rows{ns[0]}_k5_obs0.8_fwd_bwd",
+               "batch": len(ns), "rows_per_problem": ns[0], "k": 5}
+        nsample = args.cpu_sample or 8
     elif vi:
         ns, ks, host_inputs = make_vi(args)
         cfg = {"workload": f"vi_kl_batch{len(ns)}_rows{ns[0]}_k5_fwd_bwd",
@@ -585,6 +703,8 @@ def main():
     else:
         if vi:
             W = VIWorkload(bo, torch, dev, ns, ks, prec, host_inputs, args.target_chunks)
+        elif ml:
+            W = MLWorkload(bo, torch, dev, ns, ks, prec, host_inputs, args.target_chunks)
         else:
             W = Workload(bo, torch, dev, ns, ks, prec, host_inputs, forward_only, args.target_chunks)
         if args.autotune:
@@ -647,7 +767,7 @@ def main():
     elif alg5:
         bb = {nm: b * rows for nm, b in alg5_bytes_per_row(*widths).items()}
     else:
-        bb = batch_bytes(ns, ks, prec, forward_only, vi)
+        bb = batch_bytes(ns, ks, prec, forward_only, vi, ml)
     kern = {}
     for name, (tms, cnt) in prof.items():
         entry = dict(avg_ms=tms / cnt, launches_per_step=cnt / nprof, ms_per_step=tms / nprof)
@@ -660,9 +780,11 @@ def main():
     dom = max((k_ for k_ in kern if "gbs" in kern[k_]), key=lambda k_: kern[k_]["ms_per_step"])
     d = kern[dom]
     path = traffic_profile_path(args.workload, args.prec, args.batch, args.n_in)
+    # per launch: every launch of the marginal likelihood's kernels covers all rows
+    whole = d["launches_per_step"] == 1 or ml
     roof = dict(bound="hbm", kernel=dom, achieved=round(d["gbs"], 2), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(d["gbs"] / HBM_PEAK_GBS, 4),
-                traffic=measured_traffic(dom, path, rows) if d["launches_per_step"] == 1 else None,
+                traffic=measured_traffic(dom, path, rows) if whole else None,
                 bytes_per_step=bb[dom], launches_per_step=d["launches_per_step"], rows=rows)
     unit_gbs = bb["unit"] / (ms / 1e3) / 1e9
     if args.kernels_json:
@@ -676,6 +798,8 @@ def main():
             W64 = W
         elif vi:
             W64 = VIWorkload(bo, torch, dev, ns, ks, bo.F64, host_inputs)
+        elif ml:
+            W64 = MLWorkload(bo, torch, dev, ns, ks, bo.F64, host_inputs)
         else:
             W64 = Workload(bo, torch, dev, ns, ks, bo.F64, host_inputs, forward_only)
         plain_step = W64.plain_steps()
@@ -723,6 +847,12 @@ def main():
         cb, ref = cpu_baseline_alg5(host_inputs, widths, rows=min(2_000_000, rows))
         got = W.kw["O"].cpu().numpy()[: ref.shape[0] - 12]   # rows whose band lies inside the sample
         cb["max_rel_diff_vs_gpu"] = float(np.max(np.abs(got - ref[: got.shape[0]])) / np.max(np.abs(ref)))
+        out["cpu_baseline"] = cb
+        log(f"cpu baseline: {cb}")
+    elif not args.no_cpu and ml:
+        cb, ref = cpu_baseline_ml(host_inputs, ns, ks, nsample)
+        gp = W.kw["parts"].cpu().numpy()[: len(ref)]
+        cb["max_rel_diff_vs_gpu"] = float(np.max(np.abs(gp - ref) / np.maximum(np.abs(ref), 1e-300)))
         out["cpu_baseline"] = cb
         log(f"cpu baseline: {cb}")
     elif not args.no_cpu:

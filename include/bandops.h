@@ -233,6 +233,42 @@ typedef struct {
 } bo_kl_io;
 bo_status bo_plan_vi_kl(const bo_plan *plan, bo_prec prec, const bo_kl_io *io, void *ws,
                         hipStream_t stream);
+/* Log marginal likelihood of a conjugate Gaussian Markov model with partial
+ * observations (Section 3.1, Eq. (marg_lik); Algorithm 8) for every problem of
+ * the plan: prior x ~ N(0, Q^{-1}), Y = E x + noise of variance tau2, m observed
+ * nodes, mask = diag(E^T E) (1 at an observed node, 0 elsewhere), b = E^T Y
+ * (the observed values at their nodes, 0 elsewhere), Q1 = Q + E^T E / tau2:
+ *   log p(Y) = -(m/2) log 2 pi - log|L| + log|L_Q| - (m/2) log tau2
+ *              - b^T b / (2 tau2) + ||L^{-1} b||^2 / (2 tau2^2),
+ * L = C(Q1), L_Q = C(Q), with its reverse mode with respect to the stored
+ * band of Q, b and tau2 (from forward quantities: I(L), I(L_Q), Q1^{-1} b).
+ * Records of Q, L, Sig, Qbar at boff and vectors at voff as for the other plan
+ * calls; every array is required (the diagonals only in BO_MIXED), all device
+ * arrays of the caller.  Outputs: L (posterior factor), Sig = I(L) (the
+ * posterior covariances on the band), x = Q1^{-1} b (the posterior mean is
+ * x / tau2), Qbar (stored lower entries; it also holds I(L_Q) during the call),
+ * bbar (0 at unobserved nodes; it holds L^{-1} b during the call), tau2bar[p],
+ * parts[4 p .. 4 p + 3] = (log p(Y), log|L|, log|L_Q|, ||L^{-1} b||^2) and
+ * info[p]: 0, else the first row at which C(Q1) fails (1-based), else n + the
+ * row at which C(Q) fails; then the parts and tau2bar are NaN and the other
+ * outputs unspecified.  tau2 must be positive (not checked on the device).
+ * The workspace is the plan's. */
+typedef struct {
+  const void *Q;   const double *Qd;     /* prior precision Q (lower band)       */
+  const void *mask;                       /* observation mask (vector)            */
+  const void *b;                          /* E^T Y (vector)                       */
+  const double *tau2;                     /* noise variance, one per problem      */
+  void *L;         double *Ld;           /* out: C(Q1)                           */
+  void *Sig;       double *Sigd;         /* out: I(C(Q1))                        */
+  void *x;                                /* out: Q1^{-1} b                       */
+  void *Qbar;      double *Qbard;        /* out: d log p / d Q                   */
+  void *bbar;                             /* out: d log p / d b                   */
+  double *tau2bar;                        /* out: d log p / d tau2, per problem   */
+  double *parts;                          /* out: 4 per problem                   */
+  int32_t *info;                          /* out: per problem                     */
+} bo_ml_io;
+bo_status bo_plan_marglik(const bo_plan *plan, bo_prec prec, const bo_ml_io *io, void *ws,
+                          hipStream_t stream);
 /* Plan statistics: out[0] problems, out[1] chunks, out[2] groups, out[3] rows,
  * out[4] largest k. */
 bo_status bo_plan_stats(const bo_plan *plan, int64_t out[5]);

@@ -44,6 +44,12 @@ class _BatchIO(ctypes.Structure):
         "Qbar", "Qbard", "logdet", "parts", "info")]
 
 
+class _MLIO(ctypes.Structure):
+    _fields_ = [(name, _P) for name in (
+        "Q", "Qd", "mask", "b", "tau2", "L", "Ld", "Sig", "Sigd", "x", "Qbar", "Qbard", "bbar", "tau2bar",
+        "parts", "info")]
+
+
 class _KLIO(ctypes.Structure):
     _fields_ = [(name, _P) for name in (
         "Lq", "Lqd", "Lp", "Lpd", "mq", "mp", "Sig", "Sigd", "Lqbar", "Lqbard", "Lpbar", "Lpbard",
@@ -83,6 +89,7 @@ def lib():
         "bo_plan_forward": (_I32, [_P, _I32, ctypes.POINTER(_BatchIO), _P, _P]),
         "bo_plan_gauss_loss": (_I32, [_P, _I32, ctypes.POINTER(_BatchIO), _P, _P]),
         "bo_plan_vi_kl": (_I32, [_P, _I32, ctypes.POINTER(_KLIO), _P, _P]),
+        "bo_plan_marglik": (_I32, [_P, _I32, ctypes.POINTER(_MLIO), _P, _P]),
         "bo_plan_stats": (_I32, [_P, ctypes.POINTER(_I64)]),
         "bo_plan_destroy": (_I32, [_P]),
         "bo_wide_workspace_size": (_I32, [ctypes.POINTER(_Problem), _I32, ctypes.POINTER(ctypes.c_size_t)]),
@@ -108,7 +115,7 @@ EXPORTED = ("bo_workspace_size", "bo_chol", "bo_trsv", "bo_subset_inv", "bo_gbmm
             "bo_outer_band", "bo_solve_band_mat", "bo_solve_band_mat_workspace",
             "bo_solve_band_mat_bwd", "bo_chol_bwd", "bo_subset_inv_bwd", "bo_trsv_bwd", "bo_logdet_bwd",
             "bo_plan_create", "bo_plan_workspace_size", "bo_plan_upload", "bo_plan_forward",
-            "bo_plan_gauss_loss", "bo_plan_vi_kl", "bo_plan_stats", "bo_plan_destroy", "bo_wide_workspace_size",
+            "bo_plan_gauss_loss", "bo_plan_vi_kl", "bo_plan_marglik", "bo_plan_stats", "bo_plan_destroy", "bo_wide_workspace_size",
             "bo_wide_upload", "bo_wide_forward", "bo_wide_gauss_loss", "bo_profile_enable",
             "bo_profile_read", "bo_profile_slots", "bo_profile_slot_name", "bo_status_string",
             "bo_last_error")
@@ -410,6 +417,19 @@ class Plan:
         bo_plan_vi_kl): fills io.Sig, the four gradients and io.parts."""
         _check(lib().bo_plan_vi_kl(self.h, prec, ctypes.byref(io), _ptr(self.ws), _stream()),
                "bo_plan_vi_kl")
+
+    def ml_io(self, **arrays) -> _MLIO:
+        io = _MLIO()
+        for k_, v in arrays.items():
+            setattr(io, k_, _ptr(v))
+        return io
+
+    def marglik(self, prec: int, io: _MLIO):
+        """Log marginal likelihood with partial observations and its reverse
+        mode for every problem (see bo_plan_marglik): fills io.L, io.Sig, io.x,
+        io.Qbar, io.bbar, io.tau2bar, io.parts and io.info."""
+        _check(lib().bo_plan_marglik(self.h, prec, ctypes.byref(io), _ptr(self.ws), _stream()),
+               "bo_plan_marglik")
 
 
 class WidePlan:

@@ -168,7 +168,8 @@ inline bool build_sched(const ProbIn *in, int nprob, int64_t target_chunks, int6
   s.off_lgmap = take((size_t)s.ngroup * s.sw_lin);
   s.off_lgst = take((size_t)s.ngroup * s.sw_lin);
   s.off_part = take((size_t)s.nchunk * 4);
-  s.off_out = take((size_t)nprob * 4);   // scratch per-problem outputs
+  // scratch per-problem results of a composite call (8 words per problem)
+  s.off_out = take((size_t)nprob * 8);
   s.bytes = o;
   return true;
 }

@@ -11,7 +11,7 @@
 
 #include "../../include/bandops.h"
 #include "bandops_driver.hpp"
-#include "bandops_vi.hpp"
+#include "bandops_ml.hpp"
 
 using bo::Args;
 using bo::Sched;
@@ -134,9 +134,10 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const Args A) {
 // bo_profile_read() waits for them and sums the durations per step kind.
 // + clear, finalize, the four wide passes, the KL term's row kernels, the
 // three launches of Algorithm 5 and its reverse mode
-constexpr int kProfSlots = bo::ST_COUNT + 12;
+constexpr int kProfSlots = bo::ST_COUNT + 15;
 constexpr int kSlotViPre = bo::ST_COUNT + 6, kSlotViPost = bo::ST_COUNT + 7, kSlotViNeg = bo::ST_COUNT + 8;
 constexpr int kSlotSolveMat = bo::ST_COUNT + 9, kSlotSolveMatG = bo::ST_COUNT + 10, kSlotSolveMatOut = bo::ST_COUNT + 11;
+constexpr int kSlotMlPre = bo::ST_COUNT + 12, kSlotMlPost = bo::ST_COUNT + 13, kSlotMlFinal = bo::ST_COUNT + 14;
 struct ProfRec {
   int slot;
   hipEvent_t a, b;
@@ -520,7 +521,8 @@ static const char *const kStepNames[kProfSlots] = {
     "chunk_product", "fs_summary", "fs_replay", "f2_summary", "f2_replay", "b1_summary",
     "b1_replay", "b2_summary", "b2_replay", "asc_group_compose", "asc_group_sweep",
     "asc_chunk_sweep", "desc_group_compose", "desc_group_sweep", "desc_chunk_sweep",
-    "clear_partials", "finalize", "wide_f1", "wide_f2", "wide_b1", "wide_b2", "vi_pre", "vi_post", "vi_neg", "solve_mat", "solve_mat_g", "solve_mat_out"};
+    "clear_partials", "finalize", "wide_f1", "wide_f2", "wide_b1", "wide_b2", "vi_pre", "vi_post", "vi_neg", "solve_mat", "solve_mat_g", "solve_mat_out",
+    "ml_pre", "ml_post", "ml_finalize"};
 
 extern "C" int bo_profile_slots(void) { return kProfSlots; }
 
@@ -995,6 +997,73 @@ extern "C" bo_status bo_plan_vi_kl(const bo_plan *plan, bo_prec prec, const bo_k
     });
   };
   return dev_status(bo_vi::pipe_vi_kl(be, plan->s, A, (int)prec, launch), "bo_plan_vi_kl");
+}
+
+extern "C" bo_status bo_plan_marglik(const bo_plan *plan, bo_prec prec, const bo_ml_io *io, void *ws,
+                                     hipStream_t stream) {
+  if (!plan || !io || !ws) return fail(BO_EINVAL, "bo_plan_marglik: null argument");
+  if (prec != BO_F64 && prec != BO_MIXED) return fail(BO_EINVAL, "unknown precision");
+  if (!io->Q || !io->mask || !io->b || !io->tau2 || !io->L || !io->Sig || !io->x || !io->Qbar || !io->bbar ||
+      !io->tau2bar || !io->parts || !io->info)
+    return fail(BO_EINVAL, "bo_plan_marglik: every array is required");
+  if (prec == BO_MIXED && (!io->Qd || !io->Ld || !io->Sigd || !io->Qbard))
+    return fail(BO_EINVAL, "bo_plan_marglik: BO_MIXED needs every FP64 diagonal");
+  if (prec == BO_F64 && (io->Qd || io->Ld || io->Sigd || io->Qbard))
+    return fail(BO_EINVAL, "bo_plan_marglik: FP64 diagonals are for BO_MIXED only");
+  const Sched &s = plan->s;
+  double *sc = (double *)((unsigned char *)ws + s.off_out);   // 8 words per problem
+  // first forward list: C(Q) into L, I(L_Q) into Qbar
+  Args prior = Args{};
+  bo::bind_sched(s, ws, false, prior);
+  prior.Q = io->Q;
+  prior.Qd = io->Qd;
+  prior.L = io->L;
+  prior.Ld = io->Ld;
+  prior.S = io->Qbar;
+  prior.Sd = io->Qbard;
+  prior.parts = sc;
+  prior.info = (int32_t *)(sc + 6 * (size_t)s.nprob);
+  // second forward list: Q1 (written into Sig by pre) with the right-hand side b
+  Args post = Args{};
+  bo::bind_sched(s, ws, false, post);
+  post.Q = io->Sig;
+  post.Qd = io->Sigd;
+  post.L = io->L;
+  post.Ld = io->Ld;
+  post.y = io->b;
+  post.z = io->bbar;
+  post.x = io->x;
+  post.S = io->Sig;
+  post.Sd = io->Sigd;
+  post.parts = sc + 3 * (size_t)s.nprob;
+  post.info = io->info;
+  const bo_ml::MLP P{io->Q,    io->Qd,   io->mask,   io->b,       io->tau2,  io->Sig,        io->Sigd,
+                     io->Sig,  io->Sigd, io->x,      io->Qbar,    io->Qbard, io->bbar,       io->tau2bar,
+                     io->parts, io->info, prior.parts, post.parts, prior.info};
+  GpuBE be{stream};
+  auto launch = [&](int which, int64_t count, const Args &a, int) -> int {
+    if (count <= 0) return 0;
+    const dim3 grid((unsigned)count);
+    const int slot = which == 0 ? kSlotMlPre : which == 1 ? kSlotMlPost : kSlotMlFinal;
+    return profiled(slot, stream, [&] {
+      const bool f64 = prec == BO_F64;
+      const dim3 rows(bo_ml::kRowBlock);
+      switch (which) {
+        case 0:
+          if (f64) hipLaunchKernelGGL(bo_ml::k_ml_pre<double>, grid, rows, 0, stream, a, P);
+          else hipLaunchKernelGGL(bo_ml::k_ml_pre<float>, grid, rows, 0, stream, a, P);
+          break;
+        case 1:
+          if (f64) hipLaunchKernelGGL(bo_ml::k_ml_post<double>, grid, rows, 0, stream, a, P);
+          else hipLaunchKernelGGL(bo_ml::k_ml_post<float>, grid, rows, 0, stream, a, P);
+          break;
+        default:
+          hipLaunchKernelGGL(bo_ml::k_ml_finalize, grid, dim3(64), 0, stream, a, P);
+      }
+      return hipGetLastError() == hipSuccess ? 0 : -2;
+    });
+  };
+  return dev_status(bo_ml::pipe_marglik(be, s, prior, post, (int)prec, launch), "bo_plan_marglik");
 }
 
 extern "C" bo_status bo_plan_stats(const bo_plan *plan, int64_t out[5]) {

@@ -252,6 +252,26 @@ def config3_problem(b: int, seed: int = 3, n_in: int = 1_000_000, h: float = 0.1
     return Q, y, S, m
 
 
+def config5_marglik(b: int, seed: int = 5, n_in: int = 1_000_000, h: float = 0.1, nbatch: int = 16,
+                    p_obs: float = 0.8, tau2: float = 0.1):
+    """Problem b of the marginal-likelihood workload: the Matérn-5/2 prior
+    precision of config3_problem (lengthscale 1 + b/nbatch, states (f, f', f'')
+    stacked per input); each input's function value observed with probability
+    p_obs (the derivative states are never observed), Y_t = sin(2 pi x_t / 5) +
+    N(0, tau2).  Returns (Q, mask, b = E^T Y, tau2)."""
+    ell = 1.0 + b / nbatch
+    m = matern52_grid_ssm(n_in, h, ell)
+    Q = grid_precision_band(m)
+    rng = np.random.default_rng(np.random.SeedSequence([seed, b]))
+    obs = rng.random(n_in) < p_obs
+    x = np.arange(n_in) * h
+    mask = np.zeros(Q.shape[0])
+    mask[0::3] = obs
+    y = np.zeros(Q.shape[0])
+    y[0::3] = (np.sin(2 * np.pi * x / 5.0) + rng.normal(scale=math.sqrt(tau2), size=n_in)) * obs
+    return Q, mask, y, tau2
+
+
 def config4_factors(b: int, seed: int = 4, n: int = 200_000, k: int = 64):
     """Problem b of the wide block-banded workload: B lower-banded with k+1
     diagonals (main included), entries N(0, 1/k); D diagonal U[1, 2].  The

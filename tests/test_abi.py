@@ -116,6 +116,15 @@ def test_vi_kl_errors(L):
     assert b"bo_plan_vi_kl" in L.bo_last_error()
 
 
+def test_marglik_errors(L):
+    """bo_plan_marglik refuses a missing plan, io or workspace before any launch."""
+    from paper_1902_10078_amd.bandops import _MLIO
+    io = _MLIO()
+    assert L.bo_plan_marglik(None, 0, ctypes.byref(io), ctypes.c_void_p(1), None) == -1
+    assert L.bo_plan_marglik(None, 0, None, ctypes.c_void_p(1), None) == -1
+    assert b"bo_plan_marglik" in L.bo_last_error()
+
+
 def test_wide_errors_and_workspace(L):
     """The wide (k = 64) entry points: argument errors before any launch, and
     the workspace size (problem table plus two FP32 64 x 64 blocks per block
