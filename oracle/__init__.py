@@ -63,6 +63,7 @@ def _load():
         "or_forward_batch": (i32, [i32, P, P, P, P, P, P, P, P, P, P, P, P]),
         "or_solve_band_mat_bwd": (None, [i64, i32, i64, P, i32, i32, i64, P, P, i64, P, P]),
         "or_marglik": (i32, [i64, i32, i64, P, P, P, dbl, P, P, P, P]),
+        "or_natgp": (i32, [i64, i32, i64, P, P, P, P, P, P, P, P, P]),
         "or_vi_kl": (None, [i64, i32, i64, P, P, P, P, P, P, P, P, P, P]),
         "or_vi_kl_batch": (i32, [i32, P, P, P, P, P, P, P, P, P, P, P, P, P]),
     }
@@ -299,3 +300,20 @@ def marglik(Q, k, mask, b, tau2):
     info = _load().or_marglik(n, k, ld, _p(Q), _p(mask), _p(b), float(tau2), _p(parts), _p(Qbar), _p(bbar),
                               ctypes.byref(t2))
     return dict(parts=parts, Qbar=Qbar, bbar=bbar, tau2bar=t2.value, info=int(info))
+
+
+def natgp(Lam_pr, eta_pr, Lam_lik, eta_lik, k):
+    """GP regression with banded natural parameters (Appendix C.5, Algorithm
+    10): value = a(eta_pr, Lam_pr) - a(eta_po, Lam_po) and its reverse mode.
+    Returns dict with parts (5,) = (value, sum log C_pr,ii, sum log C_po,ii,
+    ||C_pr^-1 eta_pr||^2, ||C_po^-1 eta_po||^2), Lprbar, Llikbar, etaprbar,
+    etalikbar, info."""
+    Lam_pr, Lam_lik = _f64(Lam_pr), _f64(Lam_lik)
+    eta_pr, eta_lik = _f64(eta_pr), _f64(eta_lik)
+    n, ld = Lam_pr.shape
+    out = dict(parts=np.zeros(5), Lprbar=np.zeros_like(Lam_pr), Llikbar=np.zeros_like(Lam_pr),
+               etaprbar=np.zeros(n), etalikbar=np.zeros(n))
+    info = _load().or_natgp(n, k, ld, _p(Lam_pr), _p(eta_pr), _p(Lam_lik), _p(eta_lik), _p(out["parts"]),
+                            _p(out["Lprbar"]), _p(out["Llikbar"]), _p(out["etaprbar"]), _p(out["etalikbar"]))
+    out["info"] = int(info)
+    return out

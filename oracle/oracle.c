@@ -512,6 +512,88 @@ int or_marglik(int64_t n, int k, int64_t ld, const double *Q, const double *mask
 }
 
 /* --------------------------------------------------------------------------
+ * Gaussian-process regression with banded natural parameters (Appendix C.5,
+ * Algorithm 10), in the algorithm's order: C of the prior precision, C of the
+ * posterior precision (prior + likelihood), then the log-determinants and the
+ * two squared norms ||C^{-1} eta||^2.  Reverse mode: each factor's value term
+ * s * (sum log C_ii) + t * ||C^{-1} eta||^2 (s = +1, t = -1/2 for the prior;
+ * s = -1, t = +1/2 for the posterior) goes back through the log-determinant
+ * and solve rows of Table 1 and Algorithm 2; the posterior's precision and
+ * natural mean are sums, so their gradients flow to both summands.
+ * ------------------------------------------------------------------------ */
+static void natgp_term(int64_t n, int k, int64_t ld, const double *L, const double *eta, double s,
+                       double t, double *Lambar, double *etabar) {
+  size_t bsz = (size_t)(n * ld + 1);
+  double *R = (double *)malloc((n + 1) * sizeof(double));
+  double *Rb = (double *)malloc((n + 1) * sizeof(double));
+  double *Lb = (double *)calloc(bsz, sizeof(double));
+  double *Lb2 = (double *)calloc(bsz, sizeof(double));
+  or_trsv(n, k, ld, L, 0, eta, R);
+  or_logdet_bwd(n, k, ld, L, 0.5 * s, Lb);   /* sum log C_ii = logdet / 2 */
+  for (int64_t i = 0; i < n; ++i) Rb[i] = 2.0 * t * R[i];
+  or_trsv_bwd(n, k, ld, L, 0, R, Rb, etabar, Lb2);
+  for (int64_t e = 0; e < n * ld; ++e) Lb[e] += Lb2[e];
+  or_chol_bwd(n, k, ld, L, Lb, Lambar);
+  free(R);
+  free(Rb);
+  free(Lb);
+  free(Lb2);
+}
+
+static double natgp_sqnorm(int64_t n, int k, int64_t ld, const double *L, const double *eta) {
+  double *R = (double *)malloc((n + 1) * sizeof(double)), q = 0.0;
+  or_trsv(n, k, ld, L, 0, eta, R);
+  for (int64_t i = 0; i < n; ++i) q += R[i] * R[i];
+  free(R);
+  return q;
+}
+
+int or_natgp(int64_t n, int k, int64_t ld, const double *Lam_pr, const double *eta_pr,
+             const double *Lam_lik, const double *eta_lik, double *parts, double *Lprbar,
+             double *Llikbar, double *etaprbar, double *etalikbar) {
+  size_t bsz = (size_t)(n * ld + 1);
+  double *Cpr = (double *)malloc(bsz * sizeof(double)), *Cpo = (double *)malloc(bsz * sizeof(double));
+  double *Lpo = (double *)malloc(bsz * sizeof(double));
+  double *eta_po = (double *)malloc((n + 1) * sizeof(double));
+  double *gpr = (double *)calloc(bsz, sizeof(double)), *gpo = (double *)calloc(bsz, sizeof(double));
+  double *epr = (double *)calloc(n + 1, sizeof(double)), *epo = (double *)calloc(n + 1, sizeof(double));
+  for (int64_t e = 0; e < n * ld; ++e) Lpo[e] = Lam_pr[e] + Lam_lik[e];
+  for (int64_t i = 0; i < n; ++i) eta_po[i] = eta_pr[i] + eta_lik[i];
+  int info = or_chol(n, k, ld, Lam_pr, Cpr);
+  int info1 = info ? 0 : or_chol(n, k, ld, Lpo, Cpo);
+  if (info || info1) {
+    for (int i = 0; i < 5; ++i) parts[i] = NAN;
+  } else {
+    double lpr = 0.5 * or_logdet(n, k, ld, Cpr), lpo = 0.5 * or_logdet(n, k, ld, Cpo);
+    double qpr = natgp_sqnorm(n, k, ld, Cpr, eta_pr), qpo = natgp_sqnorm(n, k, ld, Cpo, eta_po);
+    parts[0] = lpr - 0.5 * qpr - lpo + 0.5 * qpo;
+    parts[1] = lpr;
+    parts[2] = lpo;
+    parts[3] = qpr;
+    parts[4] = qpo;
+    natgp_term(n, k, ld, Cpr, eta_pr, 1.0, -0.5, gpr, epr);
+    natgp_term(n, k, ld, Cpo, eta_po, -1.0, 0.5, gpo, epo);
+    for (int64_t e = 0; e < n * ld; ++e) {
+      Lprbar[e] = gpr[e] + gpo[e];
+      Llikbar[e] = gpo[e];
+    }
+    for (int64_t i = 0; i < n; ++i) {
+      etaprbar[i] = epr[i] + epo[i];
+      etalikbar[i] = epo[i];
+    }
+  }
+  free(Cpr);
+  free(Cpo);
+  free(Lpo);
+  free(eta_po);
+  free(gpr);
+  free(gpo);
+  free(epr);
+  free(epo);
+  return info ? info : (info1 ? (int)(info1 + n) : 0);
+}
+
+/* --------------------------------------------------------------------------
  * Variational KL term (Section 3.3, Eq. (KL), Algorithm 7), in the order of
  * Algorithm 7: the band of I(L_q), the product P(L_p, L_p^T), the trace as the
  * element-wise product over the band, the log-diagonals, P(L_p^T, m_p - m_q).

@@ -131,6 +131,28 @@ int or_marglik(int64_t n, int k, int64_t ld, const double *Q, const double *mask
                const double *b, double tau2, double *parts, double *Qbar,
                double *bbar, double *tau2bar);
 
+/* Gaussian-process regression with banded natural parameters (Appendix C.5,
+ * Algorithm 10).  Prior N(F; eta_pr, Lam_pr) and Gaussian likelihood
+ * N(F; eta_lik, Lam_lik) in natural parameters (Lam_pr, Lam_lik symmetric, lower
+ * bands of width k, stride ld); posterior Lam_po = Lam_pr + Lam_lik,
+ * eta_po = eta_pr + eta_lik; C_pr = C(Lam_pr), C_po = C(Lam_po).  With
+ * a(eta, Lam) = 1/2 log|Lam| - 1/2 eta^T Lam^{-1} eta (the 2 pi terms of the
+ * prior and posterior cancel):
+ *   value = a(eta_pr, Lam_pr) - a(eta_po, Lam_po)
+ *         = sum_i log[C_pr]_ii - 1/2 ||C_pr^{-1} eta_pr||^2
+ *           - sum_i log[C_po]_ii + 1/2 ||C_po^{-1} eta_po||^2,
+ * and log p(Y) = value + the likelihood's own normaliser in data space
+ * (-(n_y/2) log 2 pi - 1/2 log|R| - 1/2 sum_t Y_t^T R^{-1} Y_t), which involves no
+ * banded matrix and is left to the caller.  parts[0] = value,
+ * parts[1] = sum log[C_pr]_ii, parts[2] = sum log[C_po]_ii,
+ * parts[3] = ||C_pr^{-1} eta_pr||^2, parts[4] = ||C_po^{-1} eta_po||^2.
+ * Reverse mode (Table 1 compositions through both Cholesky factors): Lprbar,
+ * Llikbar (stored lower-band entries), etaprbar, etalikbar.  Returns 0, the
+ * prior's Cholesky info (as is), or the posterior's (+ n). */
+int or_natgp(int64_t n, int k, int64_t ld, const double *Lam_pr, const double *eta_pr,
+             const double *Lam_lik, const double *eta_lik, double *parts, double *Lprbar,
+             double *Llikbar, double *etaprbar, double *etalikbar);
+
 /* Kullback-Leibler term of the variational objective (Section 3.3, Eq. (KL);
  * Algorithm 7): q = N(m_q, (L_q L_q^T)^{-1}), p = N(m_p, (L_p L_p^T)^{-1}), with
  * L_q and L_p lower bands of the same width k (stride ld), composed from I, P

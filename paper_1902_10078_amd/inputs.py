@@ -113,6 +113,79 @@ def matern32_ssm(x: np.ndarray, ell: float, sigma2: float = 1.0) -> SSM:
     return SSM(A=A, Qt=Qt, d=2)
 
 
+def quasi_periodic_ssm(x: np.ndarray, ell: float, sigma2: float, f0: float, J: int) -> SSM:
+    """k(tau) = sigma2 e^{-|tau|/ell} sum_{j=1..J} cos(2 pi j f0 tau): a
+    Matérn-1/2 envelope on J harmonics, two states per harmonic (d = 2J).  Per
+    harmonic: A = e^{-Delta/ell} R(2 pi j f0 Delta) (R a rotation), stationary
+    covariance sigma2 I, innovation sigma2 (1 - e^{-2 Delta/ell}) I."""
+    T = len(x)
+    dx = np.diff(x)
+    A = np.zeros((T, 2 * J, 2 * J))
+    Qt = np.zeros((T, 2 * J, 2 * J))
+    e = np.exp(-dx / ell)
+    q = -sigma2 * np.expm1(-2.0 * dx / ell)
+    for j in range(J):
+        w = 2.0 * math.pi * (j + 1) * f0 * dx
+        a = 2 * j
+        A[1:, a, a] = e * np.cos(w)
+        A[1:, a, a + 1] = -e * np.sin(w)
+        A[1:, a + 1, a] = e * np.sin(w)
+        A[1:, a + 1, a + 1] = e * np.cos(w)
+        Qt[0, a, a] = Qt[0, a + 1, a + 1] = sigma2
+        Qt[1:, a, a] = Qt[1:, a + 1, a + 1] = q
+    return SSM(A=A, Qt=Qt, d=2 * J)
+
+
+def sum_ssm(*ms: SSM) -> SSM:
+    """The state-space model of a sum of kernels: the components' states
+    stacked per input (block-diagonal transitions and covariances)."""
+    T = ms[0].A.shape[0]
+    d = sum(m.d for m in ms)
+    A = np.zeros((T, d, d))
+    Qt = np.zeros((T, d, d))
+    o = 0
+    for m in ms:
+        A[:, o:o + m.d, o:o + m.d] = m.A
+        Qt[:, o:o + m.d, o:o + m.d] = m.Qt
+        o += m.d
+    return SSM(A=A, Qt=Qt, d=d)
+
+
+def co2_natgp(T: int, seed: int = 6, J: int = 2, h: float = 1.0 / 52, ell_s: float = 2.0,
+              s2_s: float = 1.0, ell_q: float = 1.0, s2_q: float = 0.5, f0: float = 1.0,
+              tau2: float = 0.1, p_obs: float = 0.95):
+    """A CO2-shaped regression problem in banded natural parameters: weekly
+    inputs x_t = t h (years), a Matérn-3/2 trend plus the quasi-periodic kernel
+    of J harmonics (d = 2 + 2J states per input, bandwidth 2d - 1 = 4J + 3),
+    observation y_t = H s_t + N(0, tau2) with H summing the components' first
+    states, each week observed with probability p_obs.
+    Returns dict: Lam_pr (lower band of the prior precision), eta_pr (a prior
+    natural mean, N(0, 0.1^2) entries), Lam_lik (lower band of H^T H / tau2 per
+    observed input), eta_lik (H^T y_t / tau2 per observed input), k, d, H, y,
+    obs, tau2."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, T, J]))
+    x = np.arange(T) * h
+    m = sum_ssm(matern32_ssm(x, ell_s, s2_s), quasi_periodic_ssm(x, ell_q, s2_q, f0, J))
+    d = m.d
+    k = 2 * d - 1
+    Lam_pr = ssm_precision_band(m)
+    N = T * d
+    H = np.zeros(d)
+    H[0] = 1.0
+    H[2::2] = 1.0
+    obs = rng.random(T) < p_obs
+    y = (0.05 * x + np.sin(2 * math.pi * x) + rng.normal(scale=math.sqrt(tau2), size=T)) * obs
+    Lam_lik = np.zeros((N, k + 1))
+    Bl = Lam_lik.reshape(T, d, k + 1)
+    for a in range(d):
+        for b in range(a, d):
+            Bl[:, a, b - a] = obs * H[a] * H[b] / tau2
+    eta_lik = (obs[:, None] * y[:, None] * H[None, :] / tau2).reshape(N)
+    eta_pr = rng.normal(scale=0.1, size=N)
+    return dict(Lam_pr=Lam_pr, eta_pr=eta_pr, Lam_lik=_zero_pads(Lam_lik), eta_lik=eta_lik, k=k, d=d, H=H,
+                y=y, obs=obs, tau2=tau2)
+
+
 def matern52_stationary(ell: float, sigma2: float = 1.0) -> np.ndarray:
     lam = math.sqrt(5.0) / ell
     k = lam * lam / 3.0
