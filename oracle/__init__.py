@@ -64,6 +64,8 @@ def _load():
         "or_solve_band_mat_bwd": (None, [i64, i32, i64, P, i32, i32, i64, P, P, i64, P, P]),
         "or_marglik": (i32, [i64, i32, i64, P, P, P, dbl, P, P, P, P]),
         "or_natgp": (i32, [i64, i32, i64, P, P, P, P, P, P, P, P, P]),
+        "or_whiten": (i32, [i64, i32, i64, P, P, P, P]),
+        "or_whiten_bwd": (None, [i64, i32, i64, P, P, P, P, P]),
         "or_vi_kl": (None, [i64, i32, i64, P, P, P, P, P, P, P, P, P, P]),
         "or_vi_kl_batch": (i32, [i32, P, P, P, P, P, P, P, P, P, P, P, P, P]),
     }
@@ -317,3 +319,23 @@ def natgp(Lam_pr, eta_pr, Lam_lik, eta_lik, k):
                             _p(out["Lprbar"]), _p(out["Llikbar"]), _p(out["etaprbar"]), _p(out["etalikbar"]))
     out["info"] = int(info)
     return out
+
+
+def whiten(Q, k, v):
+    """Whitened sample (Section 3.2, Algorithm 6): (L, F = L^{-T} v, info)."""
+    Q, v = _f64(Q), _f64(v)
+    n, ld = Q.shape
+    L = np.zeros_like(Q)
+    F = np.zeros(n)
+    info = _load().or_whiten(n, k, ld, _p(Q), _p(v), _p(L), _p(F))
+    return L, F, int(info)
+
+
+def whiten_bwd(L, k, F, Fbar):
+    """Reverse mode of the whitened sample: (vbar, Qbar)."""
+    L, F, Fbar = _f64(L), _f64(F), _f64(Fbar)
+    n, ld = L.shape
+    vbar = np.zeros(n)
+    Qbar = np.zeros_like(L)
+    _load().or_whiten_bwd(n, k, ld, _p(L), _p(F), _p(Fbar), _p(vbar), _p(Qbar))
+    return vbar, Qbar

@@ -594,6 +594,29 @@ int or_natgp(int64_t n, int k, int64_t ld, const double *Lam_pr, const double *e
 }
 
 /* --------------------------------------------------------------------------
+ * Whitened GMRF sample (Section 3.2, Algorithm 6): C, then S with the
+ * transposed factor; the reverse mode composes the solve row of Table 1 (for
+ * the transposed factor) with Algorithm 2.
+ * ------------------------------------------------------------------------ */
+int or_whiten(int64_t n, int k, int64_t ld, const double *Q, const double *v, double *L, double *F) {
+  int info = or_chol(n, k, ld, Q, L);
+  if (info) {
+    for (int64_t i = 0; i < n; ++i) F[i] = NAN;
+    return info;
+  }
+  or_trsv(n, k, ld, L, 1, v, F);
+  return 0;
+}
+
+void or_whiten_bwd(int64_t n, int k, int64_t ld, const double *L, const double *F, const double *Fbar,
+                   double *vbar, double *Qbar) {
+  double *Lb = (double *)calloc((size_t)(n * ld + 1), sizeof(double));
+  or_trsv_bwd(n, k, ld, L, 1, F, Fbar, vbar, Lb);
+  or_chol_bwd(n, k, ld, L, Lb, Qbar);
+  free(Lb);
+}
+
+/* --------------------------------------------------------------------------
  * Variational KL term (Section 3.3, Eq. (KL), Algorithm 7), in the order of
  * Algorithm 7: the band of I(L_q), the product P(L_p, L_p^T), the trace as the
  * element-wise product over the band, the log-diagonals, P(L_p^T, m_p - m_q).

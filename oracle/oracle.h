@@ -153,6 +153,17 @@ int or_natgp(int64_t n, int k, int64_t ld, const double *Lam_pr, const double *e
              const double *Lam_lik, const double *eta_lik, double *parts, double *Lprbar,
              double *Llikbar, double *etaprbar, double *etalikbar);
 
+/* Whitened sample of the GMRF for gradient-based MCMC (Section 3.2,
+ * Algorithm 6): L = C(Q) and F = S(L^T, v) = L^{-T} v, so that F ~ N(0, Q^{-1})
+ * when v ~ N(0, I).  Returns the Cholesky info (0 when Q is positive
+ * definite). */
+int or_whiten(int64_t n, int k, int64_t ld, const double *Q, const double *v, double *L, double *F);
+/* Its reverse mode (Table 1, solve row with the transposed factor, then
+ * Algorithm 2): given Fbar, vbar = L^{-1} Fbar, Lbar = -band(F vbar^T) and Qbar
+ * from Algorithm 2 (stored lower-band entries). */
+void or_whiten_bwd(int64_t n, int k, int64_t ld, const double *L, const double *F, const double *Fbar,
+                   double *vbar, double *Qbar);
+
 /* Kullback-Leibler term of the variational objective (Section 3.3, Eq. (KL);
  * Algorithm 7): q = N(m_q, (L_q L_q^T)^{-1}), p = N(m_p, (L_p L_p^T)^{-1}), with
  * L_q and L_p lower bands of the same width k (stride ld), composed from I, P
