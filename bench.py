@@ -28,7 +28,17 @@ Other workloads (--workload):
   marglik          16 log marginal likelihoods with partial observations
                    (Algorithm 8) on the Matérn-5/2 priors of the loss
                    workload, 80% of the inputs' function values observed,
-                   with the gradients in Q, b and tau2.
+                   with the gradients in Q, b and tau2;
+  natgp_co2        1024 GP regressions in banded natural parameters
+                   (Algorithm 10) on CO2-shaped state-space priors (3082
+                   weekly inputs, Matérn-3/2 trend + two quasi-periodic
+                   harmonics: 18492 rows, k = 11), one per lengthscale
+                   setting of a grid, with the gradients in both precisions
+                   and the prior natural mean;
+  whiten_hmc       one gradient evaluation of a whitened HMC target
+                   (Algorithm 6) on the 16 Matérn-5/2 precisions of the loss
+                   workload: F = L^{-T} v, then vbar and Qbar from a given
+                   Fbar (the likelihood's gradient, synthetic).
 
 Prints ONE JSON line on stdout; diagnostics go to stderr.
 """
@@ -111,6 +121,37 @@ def ml_bytes_per_row(k: int, prec: int):
             "unit": 4 * wb + 4 * wv}                 # Q, mask, b in; L, Sigma, x, Qbar, bbar out
 
 
+def ng_bytes_per_row(k: int, prec: int):
+    """Algorithmic bytes per row of the natural-parameter GP regression's
+    kernels (Algorithm 10 and its reverse mode): two forward lists with a
+    right-hand side each and the row kernels around them."""
+    wb, wv = record_bytes(k, prec)
+    return {"ng_pre": 3 * wb + 3 * wv,               # Lam_pr, Lam_lik, eta_pr, eta_lik -> Lam_po, eta_po
+            "f1_summary": 2 * wb + 2 * wv,           # Lam_pr, eta_pr; Lam_po, eta_po
+            "f1_replay": 4 * wb + 4 * wv,            # -> C_pr, z_pr; C_po, z_po
+            "f2_summary": 2 * wb + 2 * wv,           # C, z of both lists
+            "f2_replay": 4 * wb + 4 * wv,            # C, z -> Sigma, mu of both lists
+            "ng_post": 4 * wb + 2 * wv,              # Sigma_po, Sigma_pr, mu_po, mu_pr -> Lprbar, Llikbar
+            "ng_neg": 3 * wv,                        # mu_po, mu_pr -> etaprbar
+            "unit": 6 * wb + 5 * wv}                 # 2 bands + 2 vectors in; L, Sigma, 2 band grads, x, etaprbar out
+
+
+def wh_bytes_per_row(k: int, prec: int):
+    """Algorithmic bytes per row of the whitened sample and its reverse mode
+    (Algorithm 6; Table 1, Algorithm 2): every summary is its own kernel."""
+    wb, wv = record_bytes(k, prec)
+    return {"f1_summary": wb,                       # Q
+            "f1_replay": 2 * wb,                    # Q -> L
+            "f2_summary": wb + wv,                  # L, v
+            "f2_replay": wb + 2 * wv,               # L, v -> F
+            "chunk_product": wb,                    # L
+            "fs_summary": wb + wv,                  # L, Fbar
+            "fs_replay": wb + 2 * wv,               # L, Fbar -> vbar
+            "b2_summary": wb + 2 * wv,              # L, F, vbar
+            "b2_replay": 2 * wb + 2 * wv,           # L, F, vbar -> Qbar
+            "unit": 3 * wb + 5 * wv}                # Q, v, Fbar in; L, F, vbar, Qbar out
+
+
 def alg5_bytes_per_row(k: int, lr: int, u: int):
     """Algorithmic bytes per row of the matrix solve with a banded right-hand
     side (Algorithm 5) and its reverse mode, FP64."""
@@ -131,11 +172,12 @@ def wide_bytes_per_row():
             "unit": 11 * wb}
 
 
-def batch_bytes(ns, ks, prec, forward_only, vi=False, ml=False):
+def batch_bytes(ns, ks, prec, forward_only, vi=False, ml=False, ng=False, wh=False):
     """Algorithmic bytes of one step of each kernel kind over the batch."""
     tot = {}
     for n, k in zip(ns, ks):
         per = (vi_bytes_per_row(k, prec) if vi else ml_bytes_per_row(k, prec) if ml
+               else ng_bytes_per_row(k, prec) if ng else wh_bytes_per_row(k, prec) if wh
                else bytes_per_row(k, prec, forward_only))
         for nm, b in per.items():
             tot[nm] = tot.get(nm, 0) + b * n
@@ -438,6 +480,150 @@ def make_ml(args):
     return [q.shape[0] for q in Qs], [5] * args.batch, (Qs, masks, bs, t2)
 
 
+class NGWorkload:
+    """GP regression with banded natural parameters over a batch (inputs
+    resident on the device): Lam_pr, eta_pr, Lam_lik, eta_lik in; L, Sigma, x,
+    the three gradients, the parts and info out."""
+
+    def __init__(self, bo, torch, dev, ns, ks, prec, host_inputs, target_chunks=0):
+        self.bo, self.torch, self.dev = bo, torch, dev
+        self.ns, self.ks, self.prec = ns, ks, prec
+        vdt = torch.float64 if prec == bo.F64 else torch.float32
+        up = lambda key: torch.from_numpy(np.concatenate([p[key].ravel() for p in host_inputs])).to(dev, vdt)
+        kw = dict(Lpr=up("Lam_pr"), etapr=up("eta_pr"), Llik=up("Lam_lik"), etalik=up("eta_lik"))
+        E, N, P = kw["Lpr"].numel(), kw["etapr"].numel(), len(ns)
+        for nm in ("L", "Sig", "Lprbar", "Llikbar"):
+            kw[nm] = torch.zeros(E, dtype=vdt, device=dev)
+        for nm in ("x", "etaprbar"):
+            kw[nm] = torch.zeros(N, dtype=vdt, device=dev)
+        kw["parts"] = torch.zeros((P, 5), dtype=torch.float64, device=dev)
+        kw["info"] = torch.zeros(P, dtype=torch.int32, device=dev)
+        if prec == bo.MIXED:
+            dg = lambda key: torch.from_numpy(np.concatenate([p[key][:, 0] for p in host_inputs])).to(dev)
+            kw["Lprd"], kw["Llikd"] = dg("Lam_pr"), dg("Lam_lik")
+            for nm in ("Ld", "Sigd", "Lprbard", "Llikbard"):
+                kw[nm] = torch.zeros(N, dtype=torch.float64, device=dev)
+        self.kw = kw
+        self.set_schedule(target_chunks)
+
+    def set_schedule(self, target_chunks: int):
+        self.plan = self.bo.Plan(self.ns, self.ks, target_chunks=target_chunks, device=self.dev)
+        self.io = self.plan.ng_io(**self.kw)
+
+    def step(self):
+        self.plan.natgp(self.prec, self.io)
+
+    def plain_steps(self):
+        """The plain FP64 form: one plan per matrix, host loop, no graph."""
+        bo = self.bo
+        out = []
+        for p in range(len(self.ns)):
+            n, k = self.ns[p], self.ks[p]
+            pl = bo.Plan([n], [k], device=self.dev)
+            o, v, sz = self.plan.boff[p], self.plan.voff[p], n * (k + 1)
+            kw = {}
+            for nm, t in self.kw.items():
+                if nm in ("parts", "info"):
+                    kw[nm] = t[p:p + 1]
+                elif nm in ("etapr", "etalik", "x", "etaprbar") or nm.endswith("d"):
+                    kw[nm] = t[v:v + n]
+                else:
+                    kw[nm] = t[o:o + sz]
+            out.append((pl, pl.ng_io(**kw)))
+
+        def run():
+            for pl, pio in out:
+                pl.natgp(bo.F64, pio)
+        return run
+
+
+def make_ng(args):
+    """CO2-shaped regression problems (weekly inputs, 3082 weeks, Matérn-3/2
+    trend plus two quasi-periodic harmonics: d = 6, k = 11), one per
+    hyper-parameter setting of a grid over the two lengthscales."""
+    from paper_1902_10078_amd import inputs
+    probs = []
+    for b in range(args.nng):
+        g = int(round(args.nng ** 0.5))
+        ell_s = 1.0 + 2.0 * (b % g) / g
+        ell_q = 0.5 + (b // g) / g
+        probs.append(inputs.co2_natgp(args.t_ng, seed=600 + b, J=2, ell_s=ell_s, ell_q=ell_q))
+    return [p["Lam_pr"].shape[0] for p in probs], [p["k"] for p in probs], probs
+
+
+class WHWorkload:
+    """One gradient evaluation of a whitened HMC target over a batch (inputs
+    resident on the device): F = L^{-T} v with L = C(Q), then the reverse mode
+    from a given Fbar (the likelihood's gradient, here synthetic)."""
+
+    def __init__(self, bo, torch, dev, ns, ks, prec, host_inputs, target_chunks=0):
+        self.bo, self.torch, self.dev = bo, torch, dev
+        self.ns, self.ks, self.prec = ns, ks, prec
+        Qs, vs, Fbs = host_inputs
+        vdt = torch.float64 if prec == bo.F64 else torch.float32
+        up = lambda arrs: torch.from_numpy(np.concatenate([a.ravel() for a in arrs])).to(dev, vdt)
+        kw = dict(Q=up(Qs), v=up(vs), Fbar=up(Fbs))
+        E, N, P = kw["Q"].numel(), kw["v"].numel(), len(ns)
+        for nm in ("L", "Qbar"):
+            kw[nm] = torch.zeros(E, dtype=vdt, device=dev)
+        for nm in ("F", "vbar"):
+            kw[nm] = torch.zeros(N, dtype=vdt, device=dev)
+        kw["logdet"] = torch.zeros(P, dtype=torch.float64, device=dev)
+        kw["info"] = torch.zeros(P, dtype=torch.int32, device=dev)
+        if prec == bo.MIXED:
+            kw["Qd"] = torch.from_numpy(np.concatenate([a[:, 0] for a in Qs])).to(dev)
+            for nm in ("Ld", "Qbard"):
+                kw[nm] = torch.zeros(N, dtype=torch.float64, device=dev)
+        self.kw = kw
+        self.set_schedule(target_chunks)
+
+    def set_schedule(self, target_chunks: int):
+        self.plan = self.bo.Plan(self.ns, self.ks, target_chunks=target_chunks, device=self.dev)
+        self.io = self.plan.wh_io(**self.kw)
+
+    def step(self):
+        self.plan.whiten(self.prec, self.io)
+        self.plan.whiten_bwd(self.prec, self.io)
+
+    def plain_steps(self):
+        """The plain FP64 form: one plan per matrix, host loop, no graph."""
+        bo = self.bo
+        out = []
+        for p in range(len(self.ns)):
+            n, k = self.ns[p], self.ks[p]
+            pl = bo.Plan([n], [k], device=self.dev)
+            o, v, sz = self.plan.boff[p], self.plan.voff[p], n * (k + 1)
+            kw = {}
+            for nm, t in self.kw.items():
+                if nm in ("logdet", "info"):
+                    kw[nm] = t[p:p + 1]
+                elif nm in ("v", "Fbar", "F", "vbar") or nm.endswith("d"):
+                    kw[nm] = t[v:v + n]
+                else:
+                    kw[nm] = t[o:o + sz]
+            out.append((pl, pl.wh_io(**kw)))
+
+        def run():
+            for pl, pio in out:
+                pl.whiten(bo.F64, pio)
+                pl.whiten_bwd(bo.F64, pio)
+        return run
+
+
+def make_wh(args):
+    """The Matérn-5/2 precisions of the loss workload with v, Fbar ~ N(0, I)
+    (per-problem substreams of seed 8)."""
+    from paper_1902_10078_amd import inputs
+    Qs, vs, Fbs = [], [], []
+    for b in range(args.batch):
+        Q, _, _, _ = inputs.config3_problem(b, n_in=args.n_in, nbatch=16)
+        rng = np.random.default_rng(np.random.SeedSequence([8, b]))
+        Qs.append(Q)
+        vs.append(rng.normal(size=Q.shape[0]))
+        Fbs.append(rng.normal(size=Q.shape[0]))
+    return [q.shape[0] for q in Qs], [5] * args.batch, (Qs, vs, Fbs)
+
+
 class Alg5Workload:
     """One matrix: O = band of L^{-1} R (Algorithm 5) and the reverse mode
     (Table 1, solve matrix-matrix) from a fixed Obar; every output and the
@@ -551,6 +737,40 @@ def cpu_baseline_alg5(host_inputs, widths, rows: int):
                        f"one thread, {dt:.2f} s wall"), O
 
 
+def cpu_baseline_ng(host_inputs, ns, nsample: int):
+    """The FP64 oracle (Algorithm 10 and its reverse mode), one thread, problem
+    after problem, on the first `nsample` problems."""
+    import oracle
+    idx = list(range(min(nsample, len(ns))))
+    t0 = time.perf_counter()
+    ref = np.array([oracle.natgp(host_inputs[i]["Lam_pr"], host_inputs[i]["eta_pr"], host_inputs[i]["Lam_lik"],
+                                 host_inputs[i]["eta_lik"], host_inputs[i]["k"])["parts"] for i in idx])
+    dt = time.perf_counter() - t0
+    rows = sum(ns[i] for i in idx)
+    return dict(value=rows / dt, unit="band-rows/s", cores=1, kind="oracle",
+                sample=f"{len(idx)} of the workload's {len(ns)} problems ({rows} rows), FP64 C oracle "
+                       f"(forward and reverse), one thread, {dt:.2f} s wall"), ref
+
+
+def cpu_baseline_wh(host_inputs, ns, ks, nsample: int):
+    """The FP64 oracle (Algorithm 6 and its reverse mode), one thread, problem
+    after problem, on the first `nsample` problems; returns the log-determinants."""
+    import oracle
+    Qs, vs, Fbs = host_inputs
+    idx = list(range(min(nsample, len(ns))))
+    t0 = time.perf_counter()
+    ref = []
+    for i in idx:
+        L, F, _ = oracle.whiten(Qs[i], ks[i], vs[i])
+        oracle.whiten_bwd(L, ks[i], F, Fbs[i])
+        ref.append(oracle.logdet(L, ks[i]))
+    dt = time.perf_counter() - t0
+    rows = sum(ns[i] for i in idx)
+    return dict(value=rows / dt, unit="band-rows/s", cores=1, kind="oracle",
+                sample=f"{len(idx)} of the workload's {len(ns)} problems ({rows} rows), FP64 C oracle "
+                       f"(forward and reverse), one thread, {dt:.2f} s wall"), np.array(ref)
+
+
 def cpu_baseline_ml(host_inputs, ns, ks, nsample: int):
     """The FP64 oracle (Algorithm 8 and its reverse mode), one thread, problem
     after problem, on the first `nsample` problems."""
@@ -605,7 +825,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", choices=["matern52_loss", "uneven_forward", "matern32_forward", "wide_loss",
-                                           "vi_kl", "solve_band_mat", "marglik"], default="matern52_loss")
+                                           "vi_kl", "solve_band_mat", "marglik", "natgp_co2", "whiten_hmc"],
+                    default="matern52_loss")
     ap.add_argument("--prec", choices=["f64", "mixed"], default=None,
                     help="storage format (default: f64; mixed for uneven_forward)")
     ap.add_argument("--batch", type=int, default=16)
@@ -616,6 +837,8 @@ def main():
     ap.add_argument("--nwide", type=int, default=8)
     ap.add_argument("--n-wide", type=int, default=200_000)
     ap.add_argument("--n-vi", type=int, default=1_000_000, help="rows per problem of the KL batch")
+    ap.add_argument("--nng", type=int, default=1024, help="problems of the natural-parameter GP batch")
+    ap.add_argument("--t-ng", type=int, default=3082, help="weeks (inputs) per natural-parameter GP problem")
     ap.add_argument("--n-alg5", type=int, default=16_000_000, help="rows of the Algorithm 5 matrix")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="problems timed on the CPU oracle (default: 8 for the loss, KL and "
@@ -656,6 +879,8 @@ def main():
     wide = args.workload == "wide_loss"
     vi = args.workload == "vi_kl"
     ml = args.workload == "marglik"
+    ng = args.workload == "natgp_co2"
+    wh = args.workload == "whiten_hmc"
     alg5 = args.workload == "solve_band_mat"
     if args.workload == "matern52_loss":
         ns, ks, host_inputs = make_matern52(args)
@@ -677,6 +902,21 @@ def main():
         cfg = {"workload": f"marglik_matern52_batch{len(ns)}_rows{ns[0]}_k5_obs0.8_fwd_bwd",
                "batch": len(ns), "rows_per_problem": ns[0], "k": 5}
         nsample = args.cpu_sample or 8
+    elif wh:
+        ns, ks, host_inputs = make_wh(args)
+        cfg = {"workload": f"whiten_hmc_matern52_batch{len(ns)}_rows{ns[0]}_k5_fwd_bwd",
+               "batch": len(ns), "rows_per_problem": ns[0], "k": 5}
+        nsample = args.cpu_sample or 16
+    elif ng:
+        ns, ks, host_inputs = make_ng(args)
+        cfg = {"workload": f"natgp_co2_batch{len(ns)}_weeks{args.t_ng}_rows{ns[0]}_k11_fwd_bwd",
+               "batch": len(ns), "rows_per_problem": ns[0], "k": 11}
+        nsample = args.cpu_sample or 512
+        # At k = 11 every chunk is one lane's serial work; 65536 chunks (64 per
+        # problem) fill one round of resident waves (4 per CU on 256 CUs)
+        # exactly, measured best against 32768, 72704 and 131072.
+        if not args.target_chunks and not args.autotune:
+            args.target_chunks = 65536
     elif vi:
         ns, ks, host_inputs = make_vi(args)
         cfg = {"workload": f"vi_kl_batch{len(ns)}_rows{ns[0]}_k5_fwd_bwd",
@@ -705,6 +945,10 @@ def main():
             W = VIWorkload(bo, torch, dev, ns, ks, prec, host_inputs, args.target_chunks)
         elif ml:
             W = MLWorkload(bo, torch, dev, ns, ks, prec, host_inputs, args.target_chunks)
+        elif ng:
+            W = NGWorkload(bo, torch, dev, ns, ks, prec, host_inputs, args.target_chunks)
+        elif wh:
+            W = WHWorkload(bo, torch, dev, ns, ks, prec, host_inputs, args.target_chunks)
         else:
             W = Workload(bo, torch, dev, ns, ks, prec, host_inputs, forward_only, args.target_chunks)
         if args.autotune:
@@ -767,7 +1011,7 @@ def main():
     elif alg5:
         bb = {nm: b * rows for nm, b in alg5_bytes_per_row(*widths).items()}
     else:
-        bb = batch_bytes(ns, ks, prec, forward_only, vi, ml)
+        bb = batch_bytes(ns, ks, prec, forward_only, vi, ml, ng, wh)
     kern = {}
     for name, (tms, cnt) in prof.items():
         entry = dict(avg_ms=tms / cnt, launches_per_step=cnt / nprof, ms_per_step=tms / nprof)
@@ -781,7 +1025,7 @@ def main():
     d = kern[dom]
     path = traffic_profile_path(args.workload, args.prec, args.batch, args.n_in)
     # per launch: every launch of the marginal likelihood's kernels covers all rows
-    whole = d["launches_per_step"] == 1 or ml
+    whole = d["launches_per_step"] == 1 or ml or ng
     roof = dict(bound="hbm", kernel=dom, achieved=round(d["gbs"], 2), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(d["gbs"] / HBM_PEAK_GBS, 4),
                 traffic=measured_traffic(dom, path, rows) if whole else None,
@@ -800,6 +1044,10 @@ def main():
             W64 = VIWorkload(bo, torch, dev, ns, ks, bo.F64, host_inputs)
         elif ml:
             W64 = MLWorkload(bo, torch, dev, ns, ks, bo.F64, host_inputs)
+        elif ng:
+            W64 = NGWorkload(bo, torch, dev, ns, ks, bo.F64, host_inputs)
+        elif wh:
+            W64 = WHWorkload(bo, torch, dev, ns, ks, bo.F64, host_inputs)
         else:
             W64 = Workload(bo, torch, dev, ns, ks, bo.F64, host_inputs, forward_only)
         plain_step = W64.plain_steps()
@@ -847,6 +1095,18 @@ def main():
         cb, ref = cpu_baseline_alg5(host_inputs, widths, rows=min(2_000_000, rows))
         got = W.kw["O"].cpu().numpy()[: ref.shape[0] - 12]   # rows whose band lies inside the sample
         cb["max_rel_diff_vs_gpu"] = float(np.max(np.abs(got - ref[: got.shape[0]])) / np.max(np.abs(ref)))
+        out["cpu_baseline"] = cb
+        log(f"cpu baseline: {cb}")
+    elif not args.no_cpu and wh:
+        cb, ref = cpu_baseline_wh(host_inputs, ns, ks, nsample)
+        gp = W.kw["logdet"].cpu().numpy()[: len(ref)]
+        cb["max_rel_diff_vs_gpu"] = float(np.max(np.abs(gp - ref) / np.maximum(np.abs(ref), 1e-300)))
+        out["cpu_baseline"] = cb
+        log(f"cpu baseline: {cb}")
+    elif not args.no_cpu and ng:
+        cb, ref = cpu_baseline_ng(host_inputs, ns, nsample)
+        gp = W.kw["parts"].cpu().numpy()[: len(ref)]
+        cb["max_rel_diff_vs_gpu"] = float(np.max(np.abs(gp - ref) / np.maximum(np.abs(ref), 1e-300)))
         out["cpu_baseline"] = cb
         log(f"cpu baseline: {cb}")
     elif not args.no_cpu and ml:

@@ -269,6 +269,71 @@ typedef struct {
 } bo_ml_io;
 bo_status bo_plan_marglik(const bo_plan *plan, bo_prec prec, const bo_ml_io *io, void *ws,
                           hipStream_t stream);
+/* Gaussian-process regression with banded natural parameters (Appendix C.5,
+ * Algorithm 10) for every problem of the plan: prior N(F; eta_pr, Lam_pr) and
+ * likelihood N(F; eta_lik, Lam_lik) in natural parameters (Lam_pr, Lam_lik
+ * symmetric, stored as lower bands of the plan's widths), posterior
+ * Lam_po = Lam_pr + Lam_lik, eta_po = eta_pr + eta_lik, C_pr = C(Lam_pr),
+ * C_po = C(Lam_po):
+ *   value = sum_i log[C_pr]_ii - 1/2 ||C_pr^{-1} eta_pr||^2
+ *           - sum_i log[C_po]_ii + 1/2 ||C_po^{-1} eta_po||^2,
+ * which is log p(Y) up to the likelihood's normaliser in data space
+ * (-(n_y/2) log 2 pi - 1/2 log|R| - 1/2 sum_t Y_t^T R^{-1} Y_t, no banded matrix
+ * in it: the caller's).  Reverse mode from forward quantities (the posterior
+ * mean mu = Lam^{-1} eta and I(C) of both factors).  Records at boff, vectors at
+ * voff as for the other plan calls; every array is required (the diagonals only
+ * in BO_MIXED), all device arrays of the caller.  Outputs: L = C_po, Sig =
+ * I(C_po) (posterior covariances on the band), x = the posterior mean
+ * Lam_po^{-1} eta_po, which is also d value / d eta_lik, Lprbar, Llikbar (stored
+ * lower entries), etaprbar, parts[5 p .. 5 p + 4] = (value, sum log[C_pr]_ii,
+ * sum log[C_po]_ii, ||C_pr^{-1} eta_pr||^2, ||C_po^{-1} eta_po||^2) and info[p]:
+ * 0, else the first row at which C(Lam_pr) fails (1-based), else n + the row at
+ * which C(Lam_po) fails; then the parts are NaN and the other outputs
+ * unspecified.  During the call L, x, Lprbar, Llikbar and etaprbar also hold
+ * intermediates.  The workspace is the plan's. */
+typedef struct {
+  const void *Lpr;   const double *Lprd;   /* prior precision Lam_pr             */
+  const void *etapr;                        /* prior natural mean eta_pr          */
+  const void *Llik;  const double *Llikd;  /* likelihood precision Lam_lik       */
+  const void *etalik;                       /* likelihood natural mean eta_lik    */
+  void *L;           double *Ld;           /* out: C(Lam_po)                     */
+  void *Sig;         double *Sigd;         /* out: I(C(Lam_po))                  */
+  void *x;                                  /* out: Lam_po^{-1} eta_po            */
+  void *Lprbar;      double *Lprbard;      /* out: d value / d Lam_pr            */
+  void *Llikbar;     double *Llikbard;     /* out: d value / d Lam_lik           */
+  void *etaprbar;                           /* out: d value / d eta_pr            */
+  double *parts;                            /* out: 5 per problem                 */
+  int32_t *info;                            /* out: per problem                   */
+} bo_natgp_io;
+bo_status bo_plan_natgp(const bo_plan *plan, bo_prec prec, const bo_natgp_io *io, void *ws,
+                        hipStream_t stream);
+/* Whitened GMRF sample for gradient-based MCMC (Section 3.2, Algorithm 6) for
+ * every problem of the plan: L = C(Q) and F = S(L^T, v) = L^{-T} v, so that
+ * F ~ N(0, Q^{-1}) when v ~ N(0, I).  bo_plan_whiten reads Q (Qd), v and writes
+ * L (Ld), F, logdet[p] = log det Q (may be NULL) and info[p] (may be NULL: 0,
+ * or the first failing row of C(Q), 1-based; F is then unspecified).
+ * bo_plan_whiten_bwd is its reverse mode (Table 1, solve row; Algorithm 2): it
+ * reads L (Ld), F and Fbar = d f / d F for a scalar f (the likelihood's
+ * gradient: model-specific, the caller's) and writes vbar = L^{-1} Fbar and
+ * Qbar (stored lower-band entries, Qbard in BO_MIXED).  The log density of v
+ * itself, -1/2 v^T v - n/2 log 2 pi, holds no banded matrix and is the caller's
+ * too.  Records at boff and vectors at voff as for the other plan calls; all
+ * arrays are device arrays of the caller; the workspace is the plan's. */
+typedef struct {
+  const void *Q;     const double *Qd;     /* in (forward): precision Q         */
+  const void *v;                            /* in (forward): white noise v       */
+  void *L;           double *Ld;           /* out (forward), in (backward)      */
+  void *F;                                  /* out (forward), in (backward)      */
+  const void *Fbar;                         /* in (backward)                     */
+  void *vbar;                               /* out (backward)                    */
+  void *Qbar;        double *Qbard;        /* out (backward)                    */
+  double *logdet;                           /* out (forward), per problem        */
+  int32_t *info;                            /* out (forward), per problem        */
+} bo_whiten_io;
+bo_status bo_plan_whiten(const bo_plan *plan, bo_prec prec, const bo_whiten_io *io, void *ws,
+                         hipStream_t stream);
+bo_status bo_plan_whiten_bwd(const bo_plan *plan, bo_prec prec, const bo_whiten_io *io, void *ws,
+                             hipStream_t stream);
 /* Plan statistics: out[0] problems, out[1] chunks, out[2] groups, out[3] rows,
  * out[4] largest k. */
 bo_status bo_plan_stats(const bo_plan *plan, int64_t out[5]);

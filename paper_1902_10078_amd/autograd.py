@@ -275,6 +275,37 @@ class ViKL(torch.autograd.Function):
                 mpbar * gr if ctx.needs_input_grad[4] else None)
 
 
+class Whiten(torch.autograd.Function):
+    """Whitened GMRF samples F = L^{-T} v, L = C(Q) (Section 3.2, Algorithm
+    6), over a plan's batch, FP64: Q packed lower bands, v packed vectors.
+    Backward runs the library's reverse mode (Table 1, Algorithm 2)."""
+
+    @staticmethod
+    def forward(ctx, plan, Q, v):
+        Q, v = _vec(Q), _vec(v)
+        L = torch.empty_like(Q)
+        F = torch.empty_like(v)
+        info = torch.zeros(plan.nprob, dtype=torch.int32, device=Q.device)
+        plan.whiten(bo.F64, plan.wh_io(Q=Q, v=v, L=L, F=F, info=info))
+        _check_info(info)
+        ctx.save_for_backward(L, F)
+        ctx.plan = plan
+        return F
+
+    @staticmethod
+    def backward(ctx, Fbar):
+        L, F = ctx.saved_tensors
+        plan = ctx.plan
+        vbar = torch.empty_like(F)
+        Qbar = torch.empty_like(L)
+        plan.whiten_bwd(bo.F64, plan.wh_io(L=L, F=F, Fbar=_vec(Fbar), vbar=vbar, Qbar=Qbar))
+        return None, Qbar if ctx.needs_input_grad[1] else None, vbar if ctx.needs_input_grad[2] else None
+
+
+def whiten(plan, Q, v):
+    return Whiten.apply(plan, Q, v)
+
+
 def chol(Q):
     return Chol.apply(Q)
 

@@ -50,6 +50,17 @@ class _MLIO(ctypes.Structure):
         "parts", "info")]
 
 
+class _NGIO(ctypes.Structure):
+    _fields_ = [(name, _P) for name in (
+        "Lpr", "Lprd", "etapr", "Llik", "Llikd", "etalik", "L", "Ld", "Sig", "Sigd", "x", "Lprbar", "Lprbard",
+        "Llikbar", "Llikbard", "etaprbar", "parts", "info")]
+
+
+class _WHIO(ctypes.Structure):
+    _fields_ = [(name, _P) for name in (
+        "Q", "Qd", "v", "L", "Ld", "F", "Fbar", "vbar", "Qbar", "Qbard", "logdet", "info")]
+
+
 class _KLIO(ctypes.Structure):
     _fields_ = [(name, _P) for name in (
         "Lq", "Lqd", "Lp", "Lpd", "mq", "mp", "Sig", "Sigd", "Lqbar", "Lqbard", "Lpbar", "Lpbard",
@@ -90,6 +101,9 @@ def lib():
         "bo_plan_gauss_loss": (_I32, [_P, _I32, ctypes.POINTER(_BatchIO), _P, _P]),
         "bo_plan_vi_kl": (_I32, [_P, _I32, ctypes.POINTER(_KLIO), _P, _P]),
         "bo_plan_marglik": (_I32, [_P, _I32, ctypes.POINTER(_MLIO), _P, _P]),
+        "bo_plan_natgp": (_I32, [_P, _I32, ctypes.POINTER(_NGIO), _P, _P]),
+        "bo_plan_whiten": (_I32, [_P, _I32, ctypes.POINTER(_WHIO), _P, _P]),
+        "bo_plan_whiten_bwd": (_I32, [_P, _I32, ctypes.POINTER(_WHIO), _P, _P]),
         "bo_plan_stats": (_I32, [_P, ctypes.POINTER(_I64)]),
         "bo_plan_destroy": (_I32, [_P]),
         "bo_wide_workspace_size": (_I32, [ctypes.POINTER(_Problem), _I32, ctypes.POINTER(ctypes.c_size_t)]),
@@ -115,7 +129,7 @@ EXPORTED = ("bo_workspace_size", "bo_chol", "bo_trsv", "bo_subset_inv", "bo_gbmm
             "bo_outer_band", "bo_solve_band_mat", "bo_solve_band_mat_workspace",
             "bo_solve_band_mat_bwd", "bo_chol_bwd", "bo_subset_inv_bwd", "bo_trsv_bwd", "bo_logdet_bwd",
             "bo_plan_create", "bo_plan_workspace_size", "bo_plan_upload", "bo_plan_forward",
-            "bo_plan_gauss_loss", "bo_plan_vi_kl", "bo_plan_marglik", "bo_plan_stats", "bo_plan_destroy", "bo_wide_workspace_size",
+            "bo_plan_gauss_loss", "bo_plan_vi_kl", "bo_plan_marglik", "bo_plan_natgp", "bo_plan_whiten", "bo_plan_whiten_bwd", "bo_plan_stats", "bo_plan_destroy", "bo_wide_workspace_size",
             "bo_wide_upload", "bo_wide_forward", "bo_wide_gauss_loss", "bo_profile_enable",
             "bo_profile_read", "bo_profile_slots", "bo_profile_slot_name", "bo_status_string",
             "bo_last_error")
@@ -430,6 +444,36 @@ class Plan:
         io.Qbar, io.bbar, io.tau2bar, io.parts and io.info."""
         _check(lib().bo_plan_marglik(self.h, prec, ctypes.byref(io), _ptr(self.ws), _stream()),
                "bo_plan_marglik")
+
+    def ng_io(self, **arrays) -> _NGIO:
+        io = _NGIO()
+        for k_, v in arrays.items():
+            setattr(io, k_, _ptr(v))
+        return io
+
+    def natgp(self, prec: int, io: _NGIO):
+        """GP regression with banded natural parameters and its reverse mode
+        for every problem (see bo_plan_natgp): fills io.L, io.Sig, io.x (the
+        posterior mean, also the gradient in eta_lik), io.Lprbar, io.Llikbar,
+        io.etaprbar, io.parts and io.info."""
+        _check(lib().bo_plan_natgp(self.h, prec, ctypes.byref(io), _ptr(self.ws), _stream()), "bo_plan_natgp")
+
+    def wh_io(self, **arrays) -> _WHIO:
+        io = _WHIO()
+        for k_, v in arrays.items():
+            setattr(io, k_, _ptr(v))
+        return io
+
+    def whiten(self, prec: int, io: _WHIO):
+        """Whitened sample F = L^{-T} v with L = C(Q) for every problem (see
+        bo_plan_whiten): fills io.L, io.F and, when given, io.logdet, io.info."""
+        _check(lib().bo_plan_whiten(self.h, prec, ctypes.byref(io), _ptr(self.ws), _stream()), "bo_plan_whiten")
+
+    def whiten_bwd(self, prec: int, io: _WHIO):
+        """Reverse mode of the whitened sample from io.Fbar (see
+        bo_plan_whiten_bwd): fills io.vbar and io.Qbar."""
+        _check(lib().bo_plan_whiten_bwd(self.h, prec, ctypes.byref(io), _ptr(self.ws), _stream()),
+               "bo_plan_whiten_bwd")
 
 
 class WidePlan:

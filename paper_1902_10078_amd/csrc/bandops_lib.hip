@@ -12,6 +12,8 @@
 #include "../../include/bandops.h"
 #include "bandops_driver.hpp"
 #include "bandops_ml.hpp"
+#include "bandops_ng.hpp"
+#include "bandops_wh.hpp"
 
 using bo::Args;
 using bo::Sched;
@@ -134,10 +136,12 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const Args A) {
 // bo_profile_read() waits for them and sums the durations per step kind.
 // + clear, finalize, the four wide passes, the KL term's row kernels, the
 // three launches of Algorithm 5 and its reverse mode
-constexpr int kProfSlots = bo::ST_COUNT + 15;
+constexpr int kProfSlots = bo::ST_COUNT + 19;
 constexpr int kSlotViPre = bo::ST_COUNT + 6, kSlotViPost = bo::ST_COUNT + 7, kSlotViNeg = bo::ST_COUNT + 8;
 constexpr int kSlotSolveMat = bo::ST_COUNT + 9, kSlotSolveMatG = bo::ST_COUNT + 10, kSlotSolveMatOut = bo::ST_COUNT + 11;
 constexpr int kSlotMlPre = bo::ST_COUNT + 12, kSlotMlPost = bo::ST_COUNT + 13, kSlotMlFinal = bo::ST_COUNT + 14;
+constexpr int kSlotNgPre = bo::ST_COUNT + 15, kSlotNgPost = bo::ST_COUNT + 16, kSlotNgNeg = bo::ST_COUNT + 17,
+              kSlotNgFinal = bo::ST_COUNT + 18;
 struct ProfRec {
   int slot;
   hipEvent_t a, b;
@@ -522,7 +526,7 @@ static const char *const kStepNames[kProfSlots] = {
     "b1_replay", "b2_summary", "b2_replay", "asc_group_compose", "asc_group_sweep",
     "asc_chunk_sweep", "desc_group_compose", "desc_group_sweep", "desc_chunk_sweep",
     "clear_partials", "finalize", "wide_f1", "wide_f2", "wide_b1", "wide_b2", "vi_pre", "vi_post", "vi_neg", "solve_mat", "solve_mat_g", "solve_mat_out",
-    "ml_pre", "ml_post", "ml_finalize"};
+    "ml_pre", "ml_post", "ml_finalize", "ng_pre", "ng_post", "ng_neg", "ng_finalize"};
 
 extern "C" int bo_profile_slots(void) { return kProfSlots; }
 
@@ -1064,6 +1068,127 @@ extern "C" bo_status bo_plan_marglik(const bo_plan *plan, bo_prec prec, const bo
     });
   };
   return dev_status(bo_ml::pipe_marglik(be, s, prior, post, (int)prec, launch), "bo_plan_marglik");
+}
+
+extern "C" bo_status bo_plan_natgp(const bo_plan *plan, bo_prec prec, const bo_natgp_io *io, void *ws,
+                                   hipStream_t stream) {
+  if (!plan || !io || !ws) return fail(BO_EINVAL, "bo_plan_natgp: null argument");
+  if (prec != BO_F64 && prec != BO_MIXED) return fail(BO_EINVAL, "unknown precision");
+  if (!io->Lpr || !io->etapr || !io->Llik || !io->etalik || !io->L || !io->Sig || !io->x || !io->Lprbar ||
+      !io->Llikbar || !io->etaprbar || !io->parts || !io->info)
+    return fail(BO_EINVAL, "bo_plan_natgp: every array is required");
+  const bool mixed = prec == BO_MIXED;
+  const bool any_d = io->Lprd || io->Llikd || io->Ld || io->Sigd || io->Lprbard || io->Llikbard;
+  const bool all_d = io->Lprd && io->Llikd && io->Ld && io->Sigd && io->Lprbard && io->Llikbard;
+  if (mixed && !all_d) return fail(BO_EINVAL, "bo_plan_natgp: BO_MIXED needs every FP64 diagonal");
+  if (!mixed && any_d) return fail(BO_EINVAL, "bo_plan_natgp: FP64 diagonals are for BO_MIXED only");
+  const Sched &s = plan->s;
+  double *sc = (double *)((unsigned char *)ws + s.off_out);   // 8 words per problem
+  // first forward list: Lam_pr with eta_pr
+  Args prior = Args{};
+  bo::bind_sched(s, ws, false, prior);
+  prior.Q = io->Lpr;
+  prior.Qd = io->Lprd;
+  prior.L = io->L;
+  prior.Ld = io->Ld;
+  prior.y = io->etapr;
+  prior.z = io->x;
+  prior.x = io->etaprbar;
+  prior.S = io->Lprbar;
+  prior.Sd = io->Lprbard;
+  prior.parts = sc;
+  prior.info = io->info;
+  // second forward list: Lam_po (written into Sig by pre) with eta_po (in x)
+  Args post = Args{};
+  bo::bind_sched(s, ws, false, post);
+  post.Q = io->Sig;
+  post.Qd = io->Sigd;
+  post.L = io->L;
+  post.Ld = io->Ld;
+  post.y = io->x;
+  post.z = io->Llikbar;
+  post.x = io->x;
+  post.S = io->Sig;
+  post.Sd = io->Sigd;
+  post.parts = sc + 3 * (size_t)s.nprob;
+  post.info = (int32_t *)(sc + 6 * (size_t)s.nprob);
+  const bo_ng::NGP P{io->Lpr,     io->Lprd,     io->etapr,    io->Llik,    io->Llikd,  io->etalik, io->Sig,
+                     io->Sigd,    io->x,        io->Sig,      io->Sigd,    io->Lprbar, io->Lprbard, io->Llikbar,
+                     io->Llikbard, io->etaprbar, io->parts,   io->info,    prior.parts, post.parts, post.info};
+  GpuBE be{stream};
+  auto launch = [&](int which, int64_t count, const Args &a) -> int {
+    if (count <= 0) return 0;
+    static const int slots[4] = {kSlotNgPre, kSlotNgPost, kSlotNgNeg, kSlotNgFinal};
+    return profiled(slots[which], stream, [&] {
+      const bool f64 = prec == BO_F64;
+      const dim3 grid((unsigned)count), rows(bo_ng::kRowBlock);
+      switch (which) {
+        case 0:
+          if (f64) hipLaunchKernelGGL(bo_ng::k_ng_pre<double>, grid, rows, 0, stream, a, P);
+          else hipLaunchKernelGGL(bo_ng::k_ng_pre<float>, grid, rows, 0, stream, a, P);
+          break;
+        case 1:
+          if (f64) hipLaunchKernelGGL(bo_ng::k_ng_post<double>, grid, rows, 0, stream, a, P);
+          else hipLaunchKernelGGL(bo_ng::k_ng_post<float>, grid, rows, 0, stream, a, P);
+          break;
+        case 2:
+          if (f64) hipLaunchKernelGGL(bo_ng::k_ng_neg<double>, grid, rows, 0, stream, a, P);
+          else hipLaunchKernelGGL(bo_ng::k_ng_neg<float>, grid, rows, 0, stream, a, P);
+          break;
+        default:
+          hipLaunchKernelGGL(bo_ng::k_ng_finalize, dim3((unsigned)((count + 63) / 64)), dim3(64), 0, stream, a, P,
+                             (int32_t)count);
+      }
+      return hipGetLastError() == hipSuccess ? 0 : -2;
+    });
+  };
+  return dev_status(bo_ng::pipe_natgp(be, s, prior, post, (int)prec, launch), "bo_plan_natgp");
+}
+
+extern "C" bo_status bo_plan_whiten(const bo_plan *plan, bo_prec prec, const bo_whiten_io *io, void *ws,
+                                    hipStream_t stream) {
+  if (!plan || !io || !ws) return fail(BO_EINVAL, "bo_plan_whiten: null argument");
+  if (prec != BO_F64 && prec != BO_MIXED) return fail(BO_EINVAL, "unknown precision");
+  if (!io->Q || !io->v || !io->L || !io->F) return fail(BO_EINVAL, "bo_plan_whiten: Q, v, L and F are required");
+  if (prec == BO_MIXED && (!io->Qd || !io->Ld))
+    return fail(BO_EINVAL, "bo_plan_whiten: BO_MIXED needs FP64 diagonals of Q and L");
+  if (prec == BO_F64 && (io->Qd || io->Ld)) return fail(BO_EINVAL, "bo_plan_whiten: FP64 diagonals are for BO_MIXED only");
+  Args A = Args{};
+  bo::bind_sched(plan->s, ws, false, A);
+  A.Q = io->Q;
+  A.Qd = io->Qd;
+  A.L = io->L;
+  A.Ld = io->Ld;
+  A.bx = io->v;
+  A.x = io->F;
+  A.logdet = io->logdet;
+  A.info = io->info;
+  GpuBE be{stream};
+  return dev_status(bo_wh::pipe_whiten(be, plan->s, A, (int)prec), "bo_plan_whiten");
+}
+
+extern "C" bo_status bo_plan_whiten_bwd(const bo_plan *plan, bo_prec prec, const bo_whiten_io *io, void *ws,
+                                        hipStream_t stream) {
+  if (!plan || !io || !ws) return fail(BO_EINVAL, "bo_plan_whiten_bwd: null argument");
+  if (prec != BO_F64 && prec != BO_MIXED) return fail(BO_EINVAL, "unknown precision");
+  if (!io->L || !io->F || !io->Fbar || !io->vbar || !io->Qbar)
+    return fail(BO_EINVAL, "bo_plan_whiten_bwd: L, F, Fbar, vbar and Qbar are required");
+  if (prec == BO_MIXED && (!io->Ld || !io->Qbard))
+    return fail(BO_EINVAL, "bo_plan_whiten_bwd: BO_MIXED needs FP64 diagonals of L and Qbar");
+  if (prec == BO_F64 && (io->Ld || io->Qbard))
+    return fail(BO_EINVAL, "bo_plan_whiten_bwd: FP64 diagonals are for BO_MIXED only");
+  Args A = Args{};
+  bo::bind_sched(plan->s, ws, false, A);
+  A.L = io->L;
+  A.Ld = io->Ld;
+  A.bx = io->Fbar;
+  A.x = io->vbar;
+  A.yb = io->F;
+  A.zf = io->vbar;
+  A.Qb = io->Qbar;
+  A.Qbd = io->Qbard;
+  GpuBE be{stream};
+  return dev_status(bo_wh::pipe_whiten_bwd(be, plan->s, A, (int)prec), "bo_plan_whiten_bwd");
 }
 
 extern "C" bo_status bo_plan_stats(const bo_plan *plan, int64_t out[5]) {

@@ -125,6 +125,26 @@ def test_marglik_errors(L):
     assert b"bo_plan_marglik" in L.bo_last_error()
 
 
+def test_natgp_errors(L):
+    """bo_plan_natgp refuses a missing plan, io or workspace before any launch."""
+    from paper_1902_10078_amd.bandops import _NGIO
+    io = _NGIO()
+    assert L.bo_plan_natgp(None, 0, ctypes.byref(io), ctypes.c_void_p(1), None) == -1
+    assert L.bo_plan_natgp(None, 0, None, ctypes.c_void_p(1), None) == -1
+    assert b"bo_plan_natgp" in L.bo_last_error()
+
+
+def test_whiten_errors(L):
+    """bo_plan_whiten and its reverse refuse a missing plan, io or workspace
+    before any launch."""
+    from paper_1902_10078_amd.bandops import _WHIO
+    io = _WHIO()
+    assert L.bo_plan_whiten(None, 0, ctypes.byref(io), ctypes.c_void_p(1), None) == -1
+    assert b"bo_plan_whiten" in L.bo_last_error()
+    assert L.bo_plan_whiten_bwd(None, 0, ctypes.byref(io), ctypes.c_void_p(1), None) == -1
+    assert b"bo_plan_whiten_bwd" in L.bo_last_error()
+
+
 def test_wide_errors_and_workspace(L):
     """The wide (k = 64) entry points: argument errors before any launch, and
     the workspace size (problem table plus two FP32 64 x 64 blocks per block
