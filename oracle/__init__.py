@@ -339,3 +339,67 @@ def whiten_bwd(L, k, F, Fbar):
     Qbar = np.zeros_like(L)
     _load().or_whiten_bwd(n, k, ld, _p(L), _p(F), _p(Fbar), _p(vbar), _p(Qbar))
     return vbar, Qbar
+
+
+# ---------------------------------------------------------------------------
+# Bandwidth-reducing node ordering for GMRFs on graphs (Section 2: the
+# ordering heuristics the paper points to for graph precisions; Section 5 uses
+# reverse Cuthill-McKee).  Integer work: plain Python loops.
+
+def rcm(n, indptr, indices):
+    """Reverse Cuthill-McKee ordering of a symmetric sparsity pattern (CSR,
+    self-loops ignored).  Cuthill-McKee: every connected component is
+    traversed breadth-first from its node of lowest degree (ties: lowest
+    index); the unvisited neighbours of each visited node join the order by
+    ascending degree (ties: lowest index).  The reverse of that order is
+    returned: perm[new] = old."""
+    indptr = [int(v) for v in indptr]
+    indices = [int(v) for v in indices]
+    adj = [[j for j in indices[indptr[i]:indptr[i + 1]] if j != i] for i in range(n)]
+    deg = [len(set(a)) for a in adj]
+    seen = [False] * n
+    order = []
+    by_degree = sorted(range(n), key=lambda i: (deg[i], i))
+    for s in by_degree:
+        if seen[s]:
+            continue
+        seen[s] = True
+        order.append(s)
+        head = len(order) - 1
+        while head < len(order):
+            i = order[head]
+            head += 1
+            new = sorted({j for j in adj[i] if not seen[j]}, key=lambda j: (deg[j], j))
+            for j in new:
+                seen[j] = True
+                order.append(j)
+    return np.array(order[::-1], dtype=np.int64)
+
+
+def bandwidth(n, indptr, indices, perm=None):
+    """Lower bandwidth max |inv[i] - inv[j]| over the pattern's entries under
+    the ordering perm (perm[new] = old; identity when None)."""
+    inv = np.arange(n) if perm is None else np.argsort(perm)
+    rows = np.repeat(np.arange(n), np.diff(np.asarray(indptr)))
+    cols = np.asarray(indices)
+    return int(np.max(np.abs(inv[rows] - inv[cols]), initial=0))
+
+
+def csr_to_band(n, indptr, indices, vals, perm, k):
+    """Lower band (k sub-diagonals, n x (k+1) records) of P Q P^T for a
+    symmetric CSR matrix Q and the ordering perm (perm[new] = old): entry
+    (i, j) of Q lands at (inv[i], inv[j]).  Entries outside the band are
+    counted and dropped.  Returns (band, dropped)."""
+    inv = np.argsort(perm)
+    B = np.zeros((n, k + 1))
+    dropped = 0
+    for i in range(n):
+        for e in range(int(indptr[i]), int(indptr[i + 1])):
+            a, b = int(inv[i]), int(inv[int(indices[e])])
+            if a < b:
+                continue
+            if a - b > k:
+                dropped += 1
+                continue
+            B[b, a - b] = vals[e]
+    return B, dropped
