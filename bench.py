@@ -38,7 +38,12 @@ Other workloads (--workload):
   whiten_hmc       one gradient evaluation of a whitened HMC target
                    (Algorithm 6) on the 16 Matérn-5/2 precisions of the loss
                    workload: F = L^{-T} v, then vbar and Qbar from a given
-                   Fbar (the likelihood's gradient, synthetic).
+                   Fbar (the likelihood's gradient, synthetic);
+  graph_whiten     the same gradient evaluation on graph GMRFs: a 3 x 333334
+                   road strip in its reverse Cuthill-McKee order (host,
+                   once), 16 edge-precision settings assembled into bands from
+                   CSR each step, and the band gradients gathered back to the
+                   CSR values.
 
 Prints ONE JSON line on stdout; diagnostics go to stderr.
 """
@@ -624,6 +629,86 @@ def make_wh(args):
     return [q.shape[0] for q in Qs], [5] * args.batch, (Qs, vs, Fbs)
 
 
+class GraphWorkload:
+    """Gradient evaluations of a whitened HMC target on graph GMRFs: one road
+    graph in its reverse Cuthill-McKee order (computed once, on the host), one
+    precision per lengthscale setting.  A step assembles every band from the
+    CSR values, runs the whitened sample and its reverse mode over the batch,
+    and gathers the band gradients back to the CSR values."""
+
+    def __init__(self, bo, torch, dev, host_inputs, prec):
+        self.bo, self.prec = bo, prec
+        g = host_inputs
+        n, k, nb = g["n"], g["k"], len(g["vals"])
+        self.n, self.k, self.nb = n, k, nb
+        i64 = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.int64)).to(dev)
+        self.ip, self.ix, self.iperm = i64(g["indptr"]), i64(g["indices"]), i64(g["iperm"])
+        self.vals = [torch.from_numpy(v).to(dev) for v in g["vals"]]
+        vdt = torch.float64 if prec == bo.F64 else torch.float32
+        E, N = nb * n * (k + 1), nb * n
+        kw = dict(Q=torch.zeros(E, dtype=vdt, device=dev), L=torch.zeros(E, dtype=vdt, device=dev),
+                  Qbar=torch.zeros(E, dtype=vdt, device=dev),
+                  v=torch.from_numpy(np.concatenate(g["v"])).to(dev, vdt),
+                  Fbar=torch.from_numpy(np.concatenate(g["Fbar"])).to(dev, vdt),
+                  F=torch.zeros(N, dtype=vdt, device=dev), vbar=torch.zeros(N, dtype=vdt, device=dev),
+                  logdet=torch.zeros(nb, dtype=torch.float64, device=dev),
+                  info=torch.zeros(nb, dtype=torch.int32, device=dev))
+        if prec == bo.MIXED:
+            for nm in ("Qd", "Ld", "Qbard"):
+                kw[nm] = torch.zeros(N, dtype=torch.float64, device=dev)
+        self.kw = kw
+        self.gvals = [torch.zeros_like(v) for v in self.vals]
+        self.dropped = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.plan = bo.Plan([n] * nb, [k] * nb, device=dev)
+        self.io = self.plan.wh_io(**kw)
+        W = n * (k + 1)
+        self.views = [(kw["Q"][b * W:(b + 1) * W], kw["Qbar"][b * W:(b + 1) * W],
+                       kw["Qd"][b * n:(b + 1) * n] if prec == bo.MIXED else None,
+                       kw["Qbard"][b * n:(b + 1) * n] if prec == bo.MIXED else None) for b in range(nb)]
+
+    def step(self):
+        bo, p = self.bo, self.prec
+        for b in range(self.nb):
+            Qv, _, Qd, _ = self.views[b]
+            bo.csr_to_band(p, self.ip, self.ix, self.vals[b], self.iperm, self.k, Qv, Qd, self.dropped)
+        self.plan.whiten(p, self.io)
+        self.plan.whiten_bwd(p, self.io)
+        for b in range(self.nb):
+            _, Gv, _, Gd = self.views[b]
+            bo.band_to_csr_grad(p, self.ip, self.ix, self.iperm, self.k, Gv, Gd, self.gvals[b])
+
+
+def make_graph(args, bo):
+    """A W = 3 by L road strip (10^6 junctions by default) in its reverse
+    Cuthill-McKee order (the library's host ordering, timed), Matérn-1/2 edge
+    precisions for 16 lengthscales ell_b = 2 + b/8, v and Fbar ~ N(0, I) in the
+    new order."""
+    from paper_1902_10078_amd import inputs
+    n, ip, ix, ln = inputs.road_graph(3, args.graph_len, seed=9)
+    qip, qix, vals = inputs.graph_gmrf_csr(n, ip, ix, ln, ell=[2.0 + b / 8.0 for b in range(16)])
+    t0 = time.perf_counter()
+    perm, iperm, bw = bo.rcm(qip, qix)
+    rcm_ms = (time.perf_counter() - t0) * 1e3
+    vs, Fbs = [], []
+    for b in range(16):
+        rng = np.random.default_rng(np.random.SeedSequence([10, b]))
+        vs.append(rng.normal(size=n))
+        Fbs.append(rng.normal(size=n))
+    return dict(n=n, k=bw, indptr=qip, indices=qix, perm=perm, iperm=iperm, vals=vals, v=vs, Fbar=Fbs,
+                rcm_ms=rcm_ms, nnz=int(qip[-1]))
+
+
+def graph_bytes_per_row(k: int, prec: int, nnz_per_row: float):
+    """Algorithmic bytes per row of the graph workload's kernels."""
+    wb, wv = record_bytes(k, prec)
+    csr = 8 + 16 * nnz_per_row          # indptr, column indices and values
+    per = wh_bytes_per_row(k, prec)
+    per["csr_to_band"] = csr + 8 + wb                  # CSR, iperm -> band
+    per["band_to_csr"] = 8 + 16 * nnz_per_row + 8 + wb  # indptr, indices, iperm, band gradient -> CSR gradient
+    per["unit"] = per["unit"] + 2 * csr
+    return per
+
+
 class Alg5Workload:
     """One matrix: O = band of L^{-1} R (Algorithm 5) and the reverse mode
     (Table 1, solve matrix-matrix) from a fixed Obar; every output and the
@@ -825,7 +910,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", choices=["matern52_loss", "uneven_forward", "matern32_forward", "wide_loss",
-                                           "vi_kl", "solve_band_mat", "marglik", "natgp_co2", "whiten_hmc"],
+                                           "vi_kl", "solve_band_mat", "marglik", "natgp_co2", "whiten_hmc", "graph_whiten"],
                     default="matern52_loss")
     ap.add_argument("--prec", choices=["f64", "mixed"], default=None,
                     help="storage format (default: f64; mixed for uneven_forward)")
@@ -839,6 +924,7 @@ def main():
     ap.add_argument("--n-vi", type=int, default=1_000_000, help="rows per problem of the KL batch")
     ap.add_argument("--nng", type=int, default=1024, help="problems of the natural-parameter GP batch")
     ap.add_argument("--t-ng", type=int, default=3082, help="weeks (inputs) per natural-parameter GP problem")
+    ap.add_argument("--graph-len", type=int, default=333_334, help="length of the road strip (3 x len junctions)")
     ap.add_argument("--n-alg5", type=int, default=16_000_000, help="rows of the Algorithm 5 matrix")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="problems timed on the CPU oracle (default: 8 for the loss, KL and "
@@ -881,6 +967,7 @@ def main():
     ml = args.workload == "marglik"
     ng = args.workload == "natgp_co2"
     wh = args.workload == "whiten_hmc"
+    gr = args.workload == "graph_whiten"
     alg5 = args.workload == "solve_band_mat"
     if args.workload == "matern52_loss":
         ns, ks, host_inputs = make_matern52(args)
@@ -902,6 +989,15 @@ def main():
         cfg = {"workload": f"marglik_matern52_batch{len(ns)}_rows{ns[0]}_k5_obs0.8_fwd_bwd",
                "batch": len(ns), "rows_per_problem": ns[0], "k": 5}
         nsample = args.cpu_sample or 8
+    elif gr:
+        host_inputs = make_graph(args, bo)
+        ns, ks = [host_inputs["n"]] * 16, [host_inputs["k"]] * 16
+        if host_inputs["k"] > 12:
+            sys.exit(f"graph bandwidth {host_inputs['k']} after ordering exceeds the compiled widths")
+        cfg = {"workload": f"graph_whiten_road3x{args.graph_len}_rcm_batch16_k{host_inputs['k']}_fwd_bwd",
+               "batch": 16, "rows_per_problem": host_inputs["n"], "k": host_inputs["k"],
+               "nnz": host_inputs["nnz"], "rcm_host_ms": round(host_inputs["rcm_ms"], 1)}
+        nsample = args.cpu_sample or 4
     elif wh:
         ns, ks, host_inputs = make_wh(args)
         cfg = {"workload": f"whiten_hmc_matern52_batch{len(ns)}_rows{ns[0]}_k5_fwd_bwd",
@@ -935,7 +1031,9 @@ def main():
     rows = sum(ns)
     log(f"inputs: {len(ns)} problems, {rows} rows ({time.perf_counter() - t0:.1f} s)")
 
-    if wide:
+    if gr:
+        W = GraphWorkload(bo, torch, dev, host_inputs, prec)
+    elif wide:
         W = WideWorkload(bo, torch, dev, ns, host_inputs)
         log(f"wide plan: {W.stats}, workspace {W.plan.ws.numel() / 2**20:.1f} MiB")
     elif alg5:
@@ -1010,6 +1108,8 @@ def main():
         bb = {nm: b * rows for nm, b in wide_bytes_per_row().items()}
     elif alg5:
         bb = {nm: b * rows for nm, b in alg5_bytes_per_row(*widths).items()}
+    elif gr:
+        bb = {nm: b * rows for nm, b in graph_bytes_per_row(ks[0], prec, host_inputs["nnz"] / ns[0]).items()}
     else:
         bb = batch_bytes(ns, ks, prec, forward_only, vi, ml, ng, wh)
     kern = {}
@@ -1037,7 +1137,7 @@ def main():
 
     # the plain FP64 one-matrix-per-launch form: per-problem plans, host loop, no graph
     vs_plain = None
-    if not args.no_plain and not wide and not alg5:
+    if not args.no_plain and not wide and not alg5 and not gr:
         if prec == bo.F64:
             W64 = W
         elif vi:
@@ -1066,7 +1166,7 @@ def main():
     cfg.update(storage=args.prec, graph=use_graph)
     if wide:
         cfg.update(blocks=W.stats["blocks"])
-    elif alg5:
+    elif alg5 or gr:
         pass
     else:
         cfg.update(chunks=W.plan.stats["nchunk"])
@@ -1095,6 +1195,26 @@ def main():
         cb, ref = cpu_baseline_alg5(host_inputs, widths, rows=min(2_000_000, rows))
         got = W.kw["O"].cpu().numpy()[: ref.shape[0] - 12]   # rows whose band lies inside the sample
         cb["max_rel_diff_vs_gpu"] = float(np.max(np.abs(got - ref[: got.shape[0]])) / np.max(np.abs(ref)))
+        out["cpu_baseline"] = cb
+        log(f"cpu baseline: {cb}")
+    elif not args.no_cpu and gr:
+        import oracle
+        g = host_inputs
+        idx = list(range(min(nsample, 16)))
+        t0 = time.perf_counter()
+        ref = []
+        for b in idx:
+            B, _ = oracle.csr_to_band(g["n"], g["indptr"], g["indices"], g["vals"][b], g["perm"], g["k"])
+            L, F, _ = oracle.whiten(B, g["k"], g["v"][b])
+            oracle.whiten_bwd(L, g["k"], F, g["Fbar"][b])
+            ref.append(oracle.logdet(L, g["k"]))
+        dt = time.perf_counter() - t0
+        rws = len(idx) * g["n"]
+        cb = dict(value=rws / dt, unit="band-rows/s", cores=1, kind="oracle",
+                  sample=f"{len(idx)} of the workload's 16 problems ({rws} rows), FP64 oracle (band assembly, "
+                         f"whitened sample and its reverse mode), one thread, {dt:.2f} s wall")
+        gp = W.kw["logdet"].cpu().numpy()[: len(ref)]
+        cb["max_rel_diff_vs_gpu"] = float(np.max(np.abs(gp - np.array(ref)) / np.abs(np.array(ref))))
         out["cpu_baseline"] = cb
         log(f"cpu baseline: {cb}")
     elif not args.no_cpu and wh:

@@ -334,6 +334,41 @@ bo_status bo_plan_whiten(const bo_plan *plan, bo_prec prec, const bo_whiten_io *
                          hipStream_t stream);
 bo_status bo_plan_whiten_bwd(const bo_plan *plan, bo_prec prec, const bo_whiten_io *io, void *ws,
                              hipStream_t stream);
+/* ------------------------------------------------- GMRF precisions on graphs */
+/* A GMRF on a graph has Q_ij = 0 off the edges, and the bandwidth of Q
+ * depends on the node ordering (Section 2); Section 5 orders a road network
+ * with reverse Cuthill-McKee before using the banded operators.
+ *
+ * bo_rcm (host; every pointer is a host pointer): the reverse Cuthill-McKee
+ * ordering of the symmetric pattern (indptr[n+1], indices[indptr[n]], CSR,
+ * self-loops and repeated entries ignored).  Cuthill-McKee traverses every
+ * connected component breadth-first from its node of lowest degree (ties: lower
+ * index) and appends a visited node's unvisited neighbours by ascending degree
+ * (ties: lower index); the reverse of that order is returned as perm[new] =
+ * old, with iperm[old] = new (iperm may be NULL) and *bandwidth =
+ * max |iperm[i] - iperm[j]| over the entries (may be NULL).  Malformed CSR
+ * (indptr[0] != 0, decreasing indptr, an index outside [0, n)) is BO_EINVAL. */
+bo_status bo_rcm(int64_t n, const int64_t *indptr, const int64_t *indices, int64_t *perm, int64_t *iperm,
+                 int64_t *bandwidth);
+/* bo_csr_to_band (device arrays, stream-ordered): the lower band (k
+ * sub-diagonals, records of ld >= k+1 elements, pads 0) of P Q P^T for the
+ * symmetric CSR matrix Q (values vals, FP64) and the ordering iperm[old] = new:
+ * the entry (i, j) with iperm[i] >= iperm[j] is stored at record iperm[j], slot
+ * iperm[i] - iperm[j]; entries above the diagonal of P Q P^T are not read (Q is
+ * symmetric); entries below the band are dropped and counted in *dropped (a
+ * device int64).  band is FP64 (BO_F64) or FP32 with the FP64 diagonal in diag
+ * (BO_MIXED; diag must be NULL in BO_F64).  Repeated CSR entries race. */
+bo_status bo_csr_to_band(bo_prec prec, int64_t n, const int64_t *indptr, const int64_t *indices,
+                         const double *vals, const int64_t *iperm, int32_t k, int64_t ld, void *band,
+                         double *diag, int64_t *dropped, hipStream_t stream);
+/* bo_band_to_csr_grad: the reverse of bo_csr_to_band: gvals[e] = the band
+ * gradient at the element entry e was stored to, 0 for the entries it did not
+ * read (above the diagonal of P Q P^T or below the band).  Device arrays,
+ * stream-ordered; gdiag is the FP64 diagonal in BO_MIXED (NULL in BO_F64). */
+bo_status bo_band_to_csr_grad(bo_prec prec, int64_t n, const int64_t *indptr, const int64_t *indices,
+                              const int64_t *iperm, int32_t k, int64_t ld, const void *gband, const double *gdiag,
+                              double *gvals, hipStream_t stream);
+
 /* Plan statistics: out[0] problems, out[1] chunks, out[2] groups, out[3] rows,
  * out[4] largest k. */
 bo_status bo_plan_stats(const bo_plan *plan, int64_t out[5]);

@@ -391,15 +391,10 @@ def csr_to_band(n, indptr, indices, vals, perm, k):
     (i, j) of Q lands at (inv[i], inv[j]).  Entries outside the band are
     counted and dropped.  Returns (band, dropped)."""
     inv = np.argsort(perm)
+    rows = np.repeat(np.arange(n), np.diff(np.asarray(indptr)))
+    a, b = inv[rows], inv[np.asarray(indices)]
+    low = a >= b
+    inside = low & (a - b <= k)
     B = np.zeros((n, k + 1))
-    dropped = 0
-    for i in range(n):
-        for e in range(int(indptr[i]), int(indptr[i + 1])):
-            a, b = int(inv[i]), int(inv[int(indices[e])])
-            if a < b:
-                continue
-            if a - b > k:
-                dropped += 1
-                continue
-            B[b, a - b] = vals[e]
-    return B, dropped
+    B[b[inside], (a - b)[inside]] = np.asarray(vals, dtype=np.float64)[inside]
+    return B, int(np.sum(low & ~inside))

@@ -44,6 +44,7 @@ def build(jobs: int | None = None, verbose: bool = True) -> str:
                       os.path.join(BUILD, f"kern_k{k}.o"), [f"-DBO_K={k}"]))
     units.append((os.path.join(CSRC, "bandops_lib.hip"), os.path.join(BUILD, "lib.o"), []))
     units.append((os.path.join(CSRC, "bandops_wide.hip"), os.path.join(BUILD, "wide.o"), []))
+    units.append((os.path.join(CSRC, "bandops_graph.hip"), os.path.join(BUILD, "graph.o"), []))
     jobs = jobs or min(len(units), max(1, (os.cpu_count() or 4)))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, units))

@@ -136,7 +136,7 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const Args A) {
 // bo_profile_read() waits for them and sums the durations per step kind.
 // + clear, finalize, the four wide passes, the KL term's row kernels, the
 // three launches of Algorithm 5 and its reverse mode
-constexpr int kProfSlots = bo::ST_COUNT + 19;
+constexpr int kProfSlots = bo::ST_COUNT + 21;
 constexpr int kSlotViPre = bo::ST_COUNT + 6, kSlotViPost = bo::ST_COUNT + 7, kSlotViNeg = bo::ST_COUNT + 8;
 constexpr int kSlotSolveMat = bo::ST_COUNT + 9, kSlotSolveMatG = bo::ST_COUNT + 10, kSlotSolveMatOut = bo::ST_COUNT + 11;
 constexpr int kSlotMlPre = bo::ST_COUNT + 12, kSlotMlPost = bo::ST_COUNT + 13, kSlotMlFinal = bo::ST_COUNT + 14;
@@ -174,6 +174,12 @@ template <class F> int profiled(int slot, hipStream_t s, F &&launch) {
 }
 
 }  // namespace
+
+// Launch timing of the graph kernels (the band assembly and its gradient's
+// gather): slots ST_COUNT + 19 + which, which = 0..1.
+int bo_profile_graph(int which, hipStream_t s, const std::function<int()> &launch) {
+  return profiled(bo::ST_COUNT + 19 + which, s, launch);
+}
 
 // Launch timing for the other translation units of the library (C++ linkage):
 // the wide passes use slots ST_COUNT + 2 + which, which = 0..3.
@@ -526,7 +532,8 @@ static const char *const kStepNames[kProfSlots] = {
     "b1_replay", "b2_summary", "b2_replay", "asc_group_compose", "asc_group_sweep",
     "asc_chunk_sweep", "desc_group_compose", "desc_group_sweep", "desc_chunk_sweep",
     "clear_partials", "finalize", "wide_f1", "wide_f2", "wide_b1", "wide_b2", "vi_pre", "vi_post", "vi_neg", "solve_mat", "solve_mat_g", "solve_mat_out",
-    "ml_pre", "ml_post", "ml_finalize", "ng_pre", "ng_post", "ng_neg", "ng_finalize"};
+    "ml_pre", "ml_post", "ml_finalize", "ng_pre", "ng_post", "ng_neg", "ng_finalize", "csr_to_band",
+    "band_to_csr"};
 
 extern "C" int bo_profile_slots(void) { return kProfSlots; }
 

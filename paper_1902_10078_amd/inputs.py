@@ -348,7 +348,7 @@ def config5_marglik(b: int, seed: int = 5, n_in: int = 1_000_000, h: float = 0.1
 def road_graph(W: int, L: int, seed: int = 9, p_drop: float = 0.15, p_diag: float = 0.1):
     """A synthetic road network on a long strip: a W x L grid of junctions with
     jittered positions (unit spacing), each grid edge dropped with probability
-    p_drop (kept when it is the only link along the strip, so the graph stays
+    p_drop (except the links along the strip's first row, so the graph stays
     connected), plus random diagonal shortcuts with probability p_diag; nodes
     are numbered in a random order.  Returns (n, indptr, indices, lengths):
     a symmetric CSR pattern without self-loops and the edge lengths in the
@@ -357,18 +357,19 @@ def road_graph(W: int, L: int, seed: int = 9, p_drop: float = 0.15, p_diag: floa
     n = W * L
     pos = np.stack(np.meshgrid(np.arange(L), np.arange(W), indexing="ij"), -1).reshape(n, 2).astype(float)
     pos += rng.uniform(-0.3, 0.3, size=pos.shape)
-    idx = lambda x, y: x * W + y
-    edges = []
-    for x in range(L):
-        for y in range(W):
-            if x + 1 < L and (y == 0 or rng.random() >= p_drop):
-                edges.append((idx(x, y), idx(x + 1, y)))
-            if y + 1 < W and rng.random() >= p_drop:
-                edges.append((idx(x, y), idx(x, y + 1)))
-            if x + 1 < L and y + 1 < W and rng.random() < p_diag:
-                edges.append((idx(x, y), idx(x + 1, y + 1)))
+    grid = np.arange(n).reshape(L, W)
+    # along the strip (x -> x+1): kept unless dropped; row y = 0 is never dropped
+    ax, bx = grid[:-1, :].ravel(), grid[1:, :].ravel()
+    keep_x = (np.tile(np.arange(W), L - 1) == 0) | (rng.random(ax.size) >= p_drop)
+    # across the strip (y -> y+1)
+    ay, by = grid[:, :-1].ravel(), grid[:, 1:].ravel()
+    keep_y = rng.random(ay.size) >= p_drop
+    # diagonal shortcuts (x, y) -> (x+1, y+1)
+    ad, bd = grid[:-1, :-1].ravel(), grid[1:, 1:].ravel()
+    keep_d = rng.random(ad.size) < p_diag
+    e = np.stack([np.concatenate([ax[keep_x], ay[keep_y], ad[keep_d]]),
+                  np.concatenate([bx[keep_x], by[keep_y], bd[keep_d]])], 1).astype(np.int64)
     relabel = rng.permutation(n)
-    e = np.array(edges)
     a, b = relabel[e[:, 0]], relabel[e[:, 1]]
     length = np.linalg.norm(pos[e[:, 0]] - pos[e[:, 1]], axis=1)
     rows = np.concatenate([a, b])
@@ -381,28 +382,30 @@ def road_graph(W: int, L: int, seed: int = 9, p_drop: float = 0.15, p_diag: floa
     return n, np.cumsum(indptr), cols.astype(np.int64), lens
 
 
-def graph_gmrf_csr(n, indptr, indices, lengths, sigma2: float = 1.0, ell: float = 3.0):
+def graph_gmrf_csr(n, indptr, indices, lengths, sigma2: float = 1.0, ell=3.0):
     """Precision of a GMRF on a graph from Matérn-1/2 inner products over the
     edges: each edge (i, j) with correlation lam = exp(-d_ij / ell) adds
     (1/sigma2) [[c, -lam c], [-lam c, c]] - (1/(2 sigma2)) I, c = 1/(1 - lam^2),
     on nodes (i, j); every 2 x 2 term is positive definite.  Returns the CSR
-    values of Q on the pattern with the diagonal inserted (indptr, indices,
-    vals)."""
+    of Q on the pattern with the diagonal inserted (indptr, indices, vals);
+    for a sequence of lengthscales, vals is a list with one array per value."""
     n = int(n)
     rows = np.repeat(np.arange(n), np.diff(indptr))
-    lam = np.exp(-lengths / ell)
-    c = 1.0 / (1.0 - lam * lam)
-    off = -lam * c / sigma2
-    diag = np.zeros(n)
-    np.add.at(diag, rows, c / sigma2 - 0.5 / sigma2)
     all_r = np.concatenate([rows, np.arange(n)])
     all_c = np.concatenate([indices, np.arange(n)])
-    all_v = np.concatenate([off, diag])
     order = np.lexsort((all_c, all_r))
-    all_r, all_c, all_v = all_r[order], all_c[order], all_v[order]
     ip = np.zeros(n + 1, dtype=np.int64)
-    np.add.at(ip, all_r + 1, 1)
-    return np.cumsum(ip), all_c.astype(np.int64), all_v
+    np.add.at(ip, all_r[order] + 1, 1)
+
+    def vals_for(el):
+        lam = np.exp(-lengths / el)
+        c = 1.0 / (1.0 - lam * lam)
+        diag = np.zeros(n)
+        np.add.at(diag, rows, c / sigma2 - 0.5 / sigma2)
+        return np.concatenate([-lam * c / sigma2, diag])[order]
+    many = isinstance(ell, (list, tuple, np.ndarray))
+    vals = [vals_for(el) for el in ell] if many else vals_for(ell)
+    return np.cumsum(ip), all_c[order].astype(np.int64), vals
 
 
 def config4_factors(b: int, seed: int = 4, n: int = 200_000, k: int = 64):
