@@ -642,8 +642,8 @@ class GraphWorkload:
         n, k, nb = g["n"], g["k"], len(g["vals"])
         self.n, self.k, self.nb = n, k, nb
         i64 = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.int64)).to(dev)
-        self.ip, self.ix, self.iperm = i64(g["indptr"]), i64(g["indices"]), i64(g["iperm"])
-        self.vals = [torch.from_numpy(v).to(dev) for v in g["vals"]]
+        self.ip, self.ix = i64(g["pindptr"]), i64(g["pindices"])
+        self.vals = torch.from_numpy(np.concatenate([v[g["map"]] for v in g["vals"]])).to(dev)
         vdt = torch.float64 if prec == bo.F64 else torch.float32
         E, N = nb * n * (k + 1), nb * n
         kw = dict(Q=torch.zeros(E, dtype=vdt, device=dev), L=torch.zeros(E, dtype=vdt, device=dev),
@@ -657,30 +657,23 @@ class GraphWorkload:
             for nm in ("Qd", "Ld", "Qbard"):
                 kw[nm] = torch.zeros(N, dtype=torch.float64, device=dev)
         self.kw = kw
-        self.gvals = [torch.zeros_like(v) for v in self.vals]
+        self.gvals = torch.zeros_like(self.vals)
         self.dropped = torch.zeros(1, dtype=torch.int64, device=dev)
         self.plan = bo.Plan([n] * nb, [k] * nb, device=dev)
         self.io = self.plan.wh_io(**kw)
-        W = n * (k + 1)
-        self.views = [(kw["Q"][b * W:(b + 1) * W], kw["Qbar"][b * W:(b + 1) * W],
-                       kw["Qd"][b * n:(b + 1) * n] if prec == bo.MIXED else None,
-                       kw["Qbard"][b * n:(b + 1) * n] if prec == bo.MIXED else None) for b in range(nb)]
 
     def step(self):
-        bo, p = self.bo, self.prec
-        for b in range(self.nb):
-            Qv, _, Qd, _ = self.views[b]
-            bo.csr_to_band(p, self.ip, self.ix, self.vals[b], self.iperm, self.k, Qv, Qd, self.dropped)
+        bo, p, kw = self.bo, self.prec, self.kw
+        bo.csr_to_band(p, self.ip, self.ix, self.vals, self.k, kw["Q"], kw.get("Qd"), self.dropped, nsets=self.nb)
         self.plan.whiten(p, self.io)
         self.plan.whiten_bwd(p, self.io)
-        for b in range(self.nb):
-            _, Gv, _, Gd = self.views[b]
-            bo.band_to_csr_grad(p, self.ip, self.ix, self.iperm, self.k, Gv, Gd, self.gvals[b])
+        bo.band_to_csr_grad(p, self.ip, self.ix, self.k, kw["Qbar"], kw.get("Qbard"), self.gvals, nsets=self.nb)
 
 
 def make_graph(args, bo):
     """A W = 3 by L road strip (10^6 junctions by default) in its reverse
-    Cuthill-McKee order (the library's host ordering, timed), Matérn-1/2 edge
+    Cuthill-McKee order (the library's host ordering and permuted pattern,
+    timed together; the values are then laid out in the new order), Matérn-1/2 edge
     precisions for 16 lengthscales ell_b = 2 + b/8, v and Fbar ~ N(0, I) in the
     new order."""
     from paper_1902_10078_amd import inputs
@@ -688,6 +681,7 @@ def make_graph(args, bo):
     qip, qix, vals = inputs.graph_gmrf_csr(n, ip, ix, ln, ell=[2.0 + b / 8.0 for b in range(16)])
     t0 = time.perf_counter()
     perm, iperm, bw = bo.rcm(qip, qix)
+    pip, pix, mp = bo.csr_permute(qip, qix, perm, iperm)
     rcm_ms = (time.perf_counter() - t0) * 1e3
     vs, Fbs = [], []
     for b in range(16):
@@ -695,7 +689,7 @@ def make_graph(args, bo):
         vs.append(rng.normal(size=n))
         Fbs.append(rng.normal(size=n))
     return dict(n=n, k=bw, indptr=qip, indices=qix, perm=perm, iperm=iperm, vals=vals, v=vs, Fbar=Fbs,
-                rcm_ms=rcm_ms, nnz=int(qip[-1]))
+                pindptr=pip, pindices=pix, map=mp, rcm_ms=rcm_ms, nnz=int(qip[-1]))
 
 
 def graph_bytes_per_row(k: int, prec: int, nnz_per_row: float):
@@ -703,8 +697,8 @@ def graph_bytes_per_row(k: int, prec: int, nnz_per_row: float):
     wb, wv = record_bytes(k, prec)
     csr = 8 + 16 * nnz_per_row          # indptr, column indices and values
     per = wh_bytes_per_row(k, prec)
-    per["csr_to_band"] = csr + 8 + wb                  # CSR, iperm -> band
-    per["band_to_csr"] = 8 + 16 * nnz_per_row + 8 + wb  # indptr, indices, iperm, band gradient -> CSR gradient
+    per["csr_to_band"] = csr + wb                       # CSR in band order -> band
+    per["band_to_csr"] = 8 + 16 * nnz_per_row + wb      # indptr, indices, band gradient -> CSR gradient
     per["unit"] = per["unit"] + 2 * csr
     return per
 

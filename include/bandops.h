@@ -350,24 +350,35 @@ bo_status bo_plan_whiten_bwd(const bo_plan *plan, bo_prec prec, const bo_whiten_
  * (indptr[0] != 0, decreasing indptr, an index outside [0, n)) is BO_EINVAL. */
 bo_status bo_rcm(int64_t n, const int64_t *indptr, const int64_t *indices, int64_t *perm, int64_t *iperm,
                  int64_t *bandwidth);
-/* bo_csr_to_band (device arrays, stream-ordered): the lower band (k
- * sub-diagonals, records of ld >= k+1 elements, pads 0) of P Q P^T for the
- * symmetric CSR matrix Q (values vals, FP64) and the ordering iperm[old] = new:
- * the entry (i, j) with iperm[i] >= iperm[j] is stored at record iperm[j], slot
- * iperm[i] - iperm[j]; entries above the diagonal of P Q P^T are not read (Q is
- * symmetric); entries below the band are dropped and counted in *dropped (a
- * device int64).  band is FP64 (BO_F64) or FP32 with the FP64 diagonal in diag
- * (BO_MIXED; diag must be NULL in BO_F64).  Repeated CSR entries race. */
-bo_status bo_csr_to_band(bo_prec prec, int64_t n, const int64_t *indptr, const int64_t *indices,
-                         const double *vals, const int64_t *iperm, int32_t k, int64_t ld, void *band,
-                         double *diag, int64_t *dropped, hipStream_t stream);
-/* bo_band_to_csr_grad: the reverse of bo_csr_to_band: gvals[e] = the band
- * gradient at the element entry e was stored to, 0 for the entries it did not
- * read (above the diagonal of P Q P^T or below the band).  Device arrays,
- * stream-ordered; gdiag is the FP64 diagonal in BO_MIXED (NULL in BO_F64). */
-bo_status bo_band_to_csr_grad(bo_prec prec, int64_t n, const int64_t *indptr, const int64_t *indices,
-                              const int64_t *iperm, int32_t k, int64_t ld, const void *gband, const double *gdiag,
-                              double *gvals, hipStream_t stream);
+/* bo_csr_permute (host): the pattern of P Q P^T for the ordering perm[new] =
+ * old, iperm[old] = new: row j is row perm[j] of Q with its columns renamed
+ * by iperm and sorted; map[e'] is the position in Q's CSR of the new entry e'
+ * (so a value set in Q's layout goes to the new layout as vals[map]).
+ * out_indptr has n+1 entries, out_indices and map indptr[n].  BO_EINVAL for
+ * malformed CSR or when perm and iperm are not inverse permutations. */
+bo_status bo_csr_permute(int64_t n, const int64_t *indptr, const int64_t *indices, const int64_t *perm,
+                         const int64_t *iperm, int64_t *out_indptr, int64_t *out_indices, int64_t *map);
+/* bo_csr_to_band (device arrays, stream-ordered): for nsets value sets on one
+ * symmetric CSR pattern whose rows are in band order (indptr[n+1],
+ * indices[nnz], sorted or not; set s's values at vals + s nnz, FP64), the
+ * lower band (k <= 64 sub-diagonals, records of ld >= k+1 elements, pads 0;
+ * set s's records at band + s n ld).  Record j, column j of the matrix, is
+ * read as row j from the diagonal rightwards: the entries (j, c), c >= j, at
+ * slot c - j (the matrix is symmetric); entries past slot k are dropped and
+ * counted in *dropped (a device int64, cleared by the call).  band is FP64
+ * (BO_F64) or FP32 with the FP64 diagonal in diag (at diag + s n; BO_MIXED;
+ * diag must be NULL in BO_F64).  Repeated CSR entries are not allowed. */
+bo_status bo_csr_to_band(bo_prec prec, int64_t n, int32_t nsets, const int64_t *indptr, const int64_t *indices,
+                         int64_t nnz, const double *vals, int32_t k, int64_t ld, void *band, double *diag,
+                         int64_t *dropped, hipStream_t stream);
+/* bo_band_to_csr_grad: the reverse of bo_csr_to_band: gvals[s nnz + e] = the
+ * band gradient of set s at the slot entry e was read into, 0 for the entries
+ * the assembly did not read (left of the diagonal, or past the band).  Device
+ * arrays, stream-ordered; gdiag is the FP64 diagonal in BO_MIXED (NULL in
+ * BO_F64). */
+bo_status bo_band_to_csr_grad(bo_prec prec, int64_t n, int32_t nsets, const int64_t *indptr,
+                              const int64_t *indices, int64_t nnz, int32_t k, int64_t ld, const void *gband,
+                              const double *gdiag, double *gvals, hipStream_t stream);
 
 /* Plan statistics: out[0] problems, out[1] chunks, out[2] groups, out[3] rows,
  * out[4] largest k. */

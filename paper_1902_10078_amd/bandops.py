@@ -104,8 +104,9 @@ def lib():
         "bo_plan_natgp": (_I32, [_P, _I32, ctypes.POINTER(_NGIO), _P, _P]),
         "bo_plan_whiten": (_I32, [_P, _I32, ctypes.POINTER(_WHIO), _P, _P]),
         "bo_rcm": (_I32, [_I64, _P, _P, _P, _P, _P]),
-        "bo_csr_to_band": (_I32, [_I32, _I64, _P, _P, _P, _P, _I32, _I64, _P, _P, _P, _P]),
-        "bo_band_to_csr_grad": (_I32, [_I32, _I64, _P, _P, _P, _I32, _I64, _P, _P, _P, _P]),
+        "bo_csr_permute": (_I32, [_I64, _P, _P, _P, _P, _P, _P, _P]),
+        "bo_csr_to_band": (_I32, [_I32, _I64, _I32, _P, _P, _I64, _P, _I32, _I64, _P, _P, _P, _P]),
+        "bo_band_to_csr_grad": (_I32, [_I32, _I64, _I32, _P, _P, _I64, _I32, _I64, _P, _P, _P, _P]),
         "bo_plan_whiten_bwd": (_I32, [_P, _I32, ctypes.POINTER(_WHIO), _P, _P]),
         "bo_plan_stats": (_I32, [_P, ctypes.POINTER(_I64)]),
         "bo_plan_destroy": (_I32, [_P]),
@@ -132,7 +133,7 @@ EXPORTED = ("bo_workspace_size", "bo_chol", "bo_trsv", "bo_subset_inv", "bo_gbmm
             "bo_outer_band", "bo_solve_band_mat", "bo_solve_band_mat_workspace",
             "bo_solve_band_mat_bwd", "bo_chol_bwd", "bo_subset_inv_bwd", "bo_trsv_bwd", "bo_logdet_bwd",
             "bo_plan_create", "bo_plan_workspace_size", "bo_plan_upload", "bo_plan_forward",
-            "bo_plan_gauss_loss", "bo_plan_vi_kl", "bo_plan_marglik", "bo_plan_natgp", "bo_plan_whiten", "bo_plan_whiten_bwd", "bo_rcm", "bo_csr_to_band", "bo_band_to_csr_grad", "bo_plan_stats", "bo_plan_destroy", "bo_wide_workspace_size",
+            "bo_plan_gauss_loss", "bo_plan_vi_kl", "bo_plan_marglik", "bo_plan_natgp", "bo_plan_whiten", "bo_plan_whiten_bwd", "bo_rcm", "bo_csr_permute", "bo_csr_to_band", "bo_band_to_csr_grad", "bo_plan_stats", "bo_plan_destroy", "bo_wide_workspace_size",
             "bo_wide_upload", "bo_wide_forward", "bo_wide_gauss_loss", "bo_profile_enable",
             "bo_profile_read", "bo_profile_slots", "bo_profile_slot_name", "bo_status_string",
             "bo_last_error")
@@ -535,20 +536,38 @@ def rcm(indptr, indices):
     return perm[:n], iperm[:n], int(bw.value)
 
 
-def csr_to_band(prec: int, indptr, indices, vals, iperm, k: int, band, diag=None, dropped=None):
-    """Lower band of P Q P^T from Q's CSR entries (device tensors, see
-    bo_csr_to_band).  Returns the device int64 count of dropped entries."""
+def csr_permute(indptr, indices, perm, iperm):
+    """The pattern of P Q P^T (host, see bo_csr_permute): (indptr, indices,
+    map) with new entry e' taken from Q's entry map[e']."""
+    import numpy as np
+    ip = np.ascontiguousarray(indptr, dtype=np.int64)
+    ix = np.ascontiguousarray(indices, dtype=np.int64)
+    pm = np.ascontiguousarray(perm, dtype=np.int64)
+    ipm = np.ascontiguousarray(iperm, dtype=np.int64)
+    n = ip.size - 1
+    oip = np.zeros(n + 1, dtype=np.int64)
+    oix = np.zeros(max(ix.size, 1), dtype=np.int64)
+    mp = np.zeros(max(ix.size, 1), dtype=np.int64)
+    hp = lambda a: ctypes.c_void_p(a.ctypes.data)
+    _check(lib().bo_csr_permute(n, hp(ip), hp(ix), hp(pm), hp(ipm), hp(oip), hp(oix), hp(mp)), "bo_csr_permute")
+    return oip, oix[:ix.size], mp[:ix.size]
+
+
+def csr_to_band(prec: int, indptr, indices, vals, k: int, band, diag=None, dropped=None, nsets: int = 1):
+    """Lower bands of a symmetric CSR matrix whose rows are in band order, for
+    nsets value sets (device tensors, see bo_csr_to_band).  Returns the device
+    int64 count of dropped entries."""
     n = indptr.numel() - 1
     if dropped is None:
         dropped = torch.zeros(1, dtype=torch.int64, device=indptr.device)
-    _check(lib().bo_csr_to_band(prec, n, _ptr(indptr), _ptr(indices), _ptr(vals), _ptr(iperm), k, k + 1, _ptr(band),
-                                _ptr(diag), _ptr(dropped), _stream()), "bo_csr_to_band")
+    _check(lib().bo_csr_to_band(prec, n, nsets, _ptr(indptr), _ptr(indices), indices.numel(), _ptr(vals), k, k + 1,
+                                _ptr(band), _ptr(diag), _ptr(dropped), _stream()), "bo_csr_to_band")
     return dropped
 
 
-def band_to_csr_grad(prec: int, indptr, indices, iperm, k: int, gband, gdiag, gvals):
-    """Gradient with respect to Q's CSR entries from the band gradient (device
-    tensors, see bo_band_to_csr_grad)."""
+def band_to_csr_grad(prec: int, indptr, indices, k: int, gband, gdiag, gvals, nsets: int = 1):
+    """Gradient with respect to the CSR entries from the band gradient for
+    nsets value sets (device tensors, see bo_band_to_csr_grad)."""
     n = indptr.numel() - 1
-    _check(lib().bo_band_to_csr_grad(prec, n, _ptr(indptr), _ptr(indices), _ptr(iperm), k, k + 1, _ptr(gband),
-                                     _ptr(gdiag), _ptr(gvals), _stream()), "bo_band_to_csr_grad")
+    _check(lib().bo_band_to_csr_grad(prec, n, nsets, _ptr(indptr), _ptr(indices), indices.numel(), k, k + 1,
+                                     _ptr(gband), _ptr(gdiag), _ptr(gvals), _stream()), "bo_band_to_csr_grad")

@@ -4,7 +4,10 @@
 // before using the banded operators).
 //   bo_rcm               host: the reverse Cuthill-McKee ordering of a CSR
 //                        pattern;
-//   bo_csr_to_band       GPU: the lower band of P Q P^T from Q's CSR entries;
+//   bo_csr_permute       host: the pattern of P Q P^T (rows in the new order,
+//                        columns sorted) and where each of its entries was;
+//   bo_csr_to_band       GPU: the lower band of a symmetric CSR matrix whose
+//                        rows are in band order, for several value sets;
 //   bo_band_to_csr_grad  GPU: the gradient with respect to Q's CSR entries
 //                        from the gradient with respect to the band.
 #include <hip/hip_runtime.h>
@@ -39,54 +42,63 @@ bool csr_ok(int64_t n, const int64_t *indptr, const int64_t *indices) {
 
 constexpr int kRows = 256;
 
-template <typename T> __global__ void __launch_bounds__(kRows) k_fill_band(int64_t count, T *p, double *d, int64_t n) {
-  const int64_t t = (int64_t)blockIdx.x * kRows + threadIdx.x;
-  if (t < count) p[t] = (T)0;
-  if (d && t < n) d[t] = 0.0;
-}
-
 __global__ void __launch_bounds__(kRows) k_zero_counter(int64_t *c) {
   if (threadIdx.x == 0) c[0] = 0;
 }
 
-// One thread per row of Q: its entries (i, j) with inv[i] >= inv[j] land at
-// record inv[j], slot inv[i] - inv[j] of the band; entries below the band are
-// counted.
-template <typename T>
+// One thread per (value set, band record) of a CSR matrix whose rows are
+// already in band order: record j is row j from the diagonal rightwards,
+// the entries (j, c), c >= j, at slot c - j (the matrix is symmetric).  The
+// record is built in registers and written whole (pads 0); entries past the
+// band are counted.
+template <typename T, int W>
 __global__ void __launch_bounds__(kRows)
-    k_csr_to_band(int64_t n, const int64_t *indptr, const int64_t *indices, const double *vals, const int64_t *iperm,
-                  int32_t k, int64_t ld, T *band, double *diag, int64_t *dropped) {
-  const int64_t i = (int64_t)blockIdx.x * kRows + threadIdx.x;
-  if (i >= n) return;
-  const int64_t a = iperm[i];
+    k_csr_to_band(int64_t n, int32_t nsets, const int64_t *indptr, const int64_t *indices, const double *vals,
+                  int64_t nnz, int32_t k, int64_t ld, T *band, double *diag, int64_t *dropped) {
+  const int64_t t = (int64_t)blockIdx.x * kRows + threadIdx.x;
+  if (t >= n * nsets) return;
+  const int64_t set = t / n, j = t - set * n;
+  const double *v = vals + set * nnz;
+  double rec[W];
+#pragma unroll
+  for (int s = 0; s < W; ++s) rec[s] = 0.0;
   int64_t lost = 0;
-  for (int64_t e = indptr[i]; e < indptr[i + 1]; ++e) {
-    const int64_t b = iperm[indices[e]];
-    if (a < b) continue;
-    if (a - b > k) {
+  for (int64_t e = indptr[j]; e < indptr[j + 1]; ++e) {
+    const int64_t d = indices[e] - j;
+    if (d < 0) continue;
+    if (d > k) {
       ++lost;
       continue;
     }
-    band[b * ld + (a - b)] = (T)vals[e];
-    if (a == b && diag) diag[b] = vals[e];
+#pragma unroll
+    for (int s = 0; s < W; ++s)
+      if (s == d) rec[s] = v[e];
   }
+  T *out = band + set * n * ld + j * ld;
+#pragma unroll
+  for (int s = 0; s < W; ++s)
+    if (s < ld) out[s] = (T)rec[s];
+  for (int64_t s = W; s < ld; ++s) out[s] = (T)0;
+  if (diag) diag[set * n + j] = rec[0];
   if (lost) atomicAdd((unsigned long long *)dropped, (unsigned long long)lost);
 }
 
-// One thread per row of Q: the entry (i, j) that the band assembly placed
-// gets the band's gradient there; the entries it did not read get 0.
+// The reverse: the entries of row j that record j read get the band's
+// gradient there, the row's other entries 0.
 template <typename T>
 __global__ void __launch_bounds__(kRows)
-    k_band_to_csr(int64_t n, const int64_t *indptr, const int64_t *indices, const int64_t *iperm, int32_t k,
+    k_band_to_csr(int64_t n, int32_t nsets, const int64_t *indptr, const int64_t *indices, int64_t nnz, int32_t k,
                   int64_t ld, const T *gband, const double *gdiag, double *gvals) {
-  const int64_t i = (int64_t)blockIdx.x * kRows + threadIdx.x;
-  if (i >= n) return;
-  const int64_t a = iperm[i];
-  for (int64_t e = indptr[i]; e < indptr[i + 1]; ++e) {
-    const int64_t b = iperm[indices[e]];
-    double g = 0.0;
-    if (a >= b && a - b <= k) g = (a == b && gdiag) ? gdiag[b] : (double)gband[b * ld + (a - b)];
-    gvals[e] = g;
+  const int64_t t = (int64_t)blockIdx.x * kRows + threadIdx.x;
+  if (t >= n * nsets) return;
+  const int64_t set = t / n, j = t - set * n;
+  const T *g = gband + set * n * ld + j * ld;
+  double *gv = gvals + set * nnz;
+  for (int64_t e = indptr[j]; e < indptr[j + 1]; ++e) {
+    const int64_t d = indices[e] - j;
+    double x = 0.0;
+    if (d >= 0 && d <= k) x = (d == 0 && gdiag) ? gdiag[set * n + j] : (double)g[d];
+    gv[e] = x;
   }
 }
 
@@ -149,51 +161,88 @@ extern "C" bo_status bo_rcm(int64_t n, const int64_t *indptr, const int64_t *ind
   return BO_OK;
 }
 
-extern "C" bo_status bo_csr_to_band(bo_prec prec, int64_t n, const int64_t *indptr, const int64_t *indices,
-                                    const double *vals, const int64_t *iperm, int32_t k, int64_t ld, void *band,
-                                    double *diag, int64_t *dropped, hipStream_t stream) {
+extern "C" bo_status bo_csr_permute(int64_t n, const int64_t *indptr, const int64_t *indices, const int64_t *perm,
+                                    const int64_t *iperm, int64_t *out_indptr, int64_t *out_indices, int64_t *map) {
+  if (n < 0 || !indptr || !out_indptr || (n > 0 && (!indices || !perm || !iperm || !out_indices || !map)))
+    return gfail(BO_EINVAL, "bo_csr_permute: bad argument");
+  if (!csr_ok(n, indptr, indices)) return gfail(BO_EINVAL, "bo_csr_permute: malformed CSR pattern");
+  for (int64_t t = 0; t < n; ++t)
+    if (perm[t] < 0 || perm[t] >= n || iperm[perm[t]] != t)
+      return gfail(BO_EINVAL, "bo_csr_permute: perm and iperm are not inverse permutations");
+  std::vector<std::pair<int64_t, int64_t>> row;
+  out_indptr[0] = 0;
+  int64_t o = 0;
+  for (int64_t j = 0; j < n; ++j) {
+    const int64_t i = perm[j];
+    row.clear();
+    for (int64_t e = indptr[i]; e < indptr[i + 1]; ++e) row.emplace_back(iperm[indices[e]], e);
+    std::sort(row.begin(), row.end());
+    for (const auto &ce : row) {
+      out_indices[o] = ce.first;
+      map[o] = ce.second;
+      ++o;
+    }
+    out_indptr[j + 1] = o;
+  }
+  return BO_OK;
+}
+
+template <typename T>
+int launch_csr_to_band(int64_t n, int32_t nsets, const int64_t *indptr, const int64_t *indices, const double *vals,
+                       int64_t nnz, int32_t k, int64_t ld, T *band, double *diag, int64_t *dropped,
+                       hipStream_t stream) {
+  const dim3 grid(grid_for(n * nsets)), blk(kRows);
+#define BO_CSR_W(WW)                                                                                          \
+  hipLaunchKernelGGL((k_csr_to_band<T, WW>), grid, blk, 0, stream, n, nsets, indptr, indices, vals, nnz, k, ld, \
+                     band, diag, dropped)
+  if (k < 4) BO_CSR_W(4);
+  else if (k < 8) BO_CSR_W(8);
+  else if (k < 13) BO_CSR_W(13);
+  else if (k < 32) BO_CSR_W(32);
+  else BO_CSR_W(65);
+#undef BO_CSR_W
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+extern "C" bo_status bo_csr_to_band(bo_prec prec, int64_t n, int32_t nsets, const int64_t *indptr,
+                                    const int64_t *indices, int64_t nnz, const double *vals, int32_t k, int64_t ld,
+                                    void *band, double *diag, int64_t *dropped, hipStream_t stream) {
   if (prec != BO_F64 && prec != BO_MIXED) return gfail(BO_EINVAL, "unknown precision");
-  if (n < 0 || k < 0 || ld < k + 1) return gfail(BO_EINVAL, "bo_csr_to_band: bad sizes");
-  if (n > 0 && (!indptr || !indices || !vals || !iperm || !band || !dropped))
+  if (n < 0 || nsets < 0 || nnz < 0 || k < 0 || k > 64 || ld < k + 1)
+    return gfail(BO_EINVAL, "bo_csr_to_band: bad sizes");
+  if (n > 0 && nsets > 0 && (!indptr || !indices || !vals || !band || !dropped))
     return gfail(BO_EINVAL, "bo_csr_to_band: null array");
   if ((prec == BO_MIXED) != (diag != nullptr))
     return gfail(BO_EINVAL, "bo_csr_to_band: the FP64 diagonal is for BO_MIXED only, and required there");
-  if (n == 0) return BO_OK;
-  const bool f64 = prec == BO_F64;
-  const int64_t cnt = n * ld;
+  if (n == 0 || nsets == 0) return BO_OK;
   int e = bo_profile_graph(0, stream, [&] {
     hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(kRows), 0, stream, dropped);
-    if (f64) {
-      hipLaunchKernelGGL(k_fill_band<double>, dim3(grid_for(cnt)), dim3(kRows), 0, stream, cnt, (double *)band, diag, n);
-      hipLaunchKernelGGL(k_csr_to_band<double>, dim3(grid_for(n)), dim3(kRows), 0, stream, n, indptr, indices, vals,
-                         iperm, k, ld, (double *)band, diag, dropped);
-    } else {
-      hipLaunchKernelGGL(k_fill_band<float>, dim3(grid_for(cnt)), dim3(kRows), 0, stream, cnt, (float *)band, diag, n);
-      hipLaunchKernelGGL(k_csr_to_band<float>, dim3(grid_for(n)), dim3(kRows), 0, stream, n, indptr, indices, vals,
-                         iperm, k, ld, (float *)band, diag, dropped);
-    }
-    return hipGetLastError() == hipSuccess ? 0 : -2;
+    return prec == BO_F64 ? launch_csr_to_band<double>(n, nsets, indptr, indices, vals, nnz, k, ld, (double *)band,
+                                                      diag, dropped, stream)
+                          : launch_csr_to_band<float>(n, nsets, indptr, indices, vals, nnz, k, ld, (float *)band, diag,
+                                                     dropped, stream);
   });
   return e ? gfail(BO_EDEVICE, "bo_csr_to_band: kernel launch failed") : BO_OK;
 }
 
-extern "C" bo_status bo_band_to_csr_grad(bo_prec prec, int64_t n, const int64_t *indptr, const int64_t *indices,
-                                         const int64_t *iperm, int32_t k, int64_t ld, const void *gband,
-                                         const double *gdiag, double *gvals, hipStream_t stream) {
+extern "C" bo_status bo_band_to_csr_grad(bo_prec prec, int64_t n, int32_t nsets, const int64_t *indptr,
+                                         const int64_t *indices, int64_t nnz, int32_t k, int64_t ld,
+                                         const void *gband, const double *gdiag, double *gvals, hipStream_t stream) {
   if (prec != BO_F64 && prec != BO_MIXED) return gfail(BO_EINVAL, "unknown precision");
-  if (n < 0 || k < 0 || ld < k + 1) return gfail(BO_EINVAL, "bo_band_to_csr_grad: bad sizes");
-  if (n > 0 && (!indptr || !indices || !iperm || !gband || !gvals))
+  if (n < 0 || nsets < 0 || nnz < 0 || k < 0 || ld < k + 1) return gfail(BO_EINVAL, "bo_band_to_csr_grad: bad sizes");
+  if (n > 0 && nsets > 0 && (!indptr || !indices || !gband || !gvals))
     return gfail(BO_EINVAL, "bo_band_to_csr_grad: null array");
   if ((prec == BO_MIXED) != (gdiag != nullptr))
     return gfail(BO_EINVAL, "bo_band_to_csr_grad: the FP64 diagonal is for BO_MIXED only, and required there");
-  if (n == 0) return BO_OK;
+  if (n == 0 || nsets == 0) return BO_OK;
   int e = bo_profile_graph(1, stream, [&] {
+    const dim3 grid(grid_for(n * nsets)), blk(kRows);
     if (prec == BO_F64)
-      hipLaunchKernelGGL(k_band_to_csr<double>, dim3(grid_for(n)), dim3(kRows), 0, stream, n, indptr, indices, iperm,
-                         k, ld, (const double *)gband, gdiag, gvals);
+      hipLaunchKernelGGL(k_band_to_csr<double>, grid, blk, 0, stream, n, nsets, indptr, indices, nnz, k, ld,
+                         (const double *)gband, gdiag, gvals);
     else
-      hipLaunchKernelGGL(k_band_to_csr<float>, dim3(grid_for(n)), dim3(kRows), 0, stream, n, indptr, indices, iperm,
-                         k, ld, (const float *)gband, gdiag, gvals);
+      hipLaunchKernelGGL(k_band_to_csr<float>, grid, blk, 0, stream, n, nsets, indptr, indices, nnz, k, ld,
+                         (const float *)gband, gdiag, gvals);
     return hipGetLastError() == hipSuccess ? 0 : -2;
   });
   return e ? gfail(BO_EDEVICE, "bo_band_to_csr_grad: kernel launch failed") : BO_OK;

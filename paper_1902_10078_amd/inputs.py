@@ -347,9 +347,10 @@ def config5_marglik(b: int, seed: int = 5, n_in: int = 1_000_000, h: float = 0.1
 
 def road_graph(W: int, L: int, seed: int = 9, p_drop: float = 0.15, p_diag: float = 0.1):
     """A synthetic road network on a long strip: a W x L grid of junctions with
-    jittered positions (unit spacing), each grid edge dropped with probability
-    p_drop (except the links along the strip's first row, so the graph stays
-    connected), plus random diagonal shortcuts with probability p_diag; nodes
+    jittered positions (unit spacing); each link along the strip dropped with
+    probability p_drop, except in the strip's first row; every link across
+    the strip kept (so every junction connects to the first row and the graph
+    is connected); random diagonal shortcuts with probability p_diag; nodes
     are numbered in a random order.  Returns (n, indptr, indices, lengths):
     a symmetric CSR pattern without self-loops and the edge lengths in the
     same layout."""
@@ -361,9 +362,9 @@ def road_graph(W: int, L: int, seed: int = 9, p_drop: float = 0.15, p_diag: floa
     # along the strip (x -> x+1): kept unless dropped; row y = 0 is never dropped
     ax, bx = grid[:-1, :].ravel(), grid[1:, :].ravel()
     keep_x = (np.tile(np.arange(W), L - 1) == 0) | (rng.random(ax.size) >= p_drop)
-    # across the strip (y -> y+1)
+    # across the strip (y -> y+1): always kept
     ay, by = grid[:, :-1].ravel(), grid[:, 1:].ravel()
-    keep_y = rng.random(ay.size) >= p_drop
+    keep_y = np.ones(ay.size, dtype=bool)
     # diagonal shortcuts (x, y) -> (x+1, y+1)
     ad, bd = grid[:-1, :-1].ravel(), grid[1:, 1:].ravel()
     keep_d = rng.random(ad.size) < p_diag

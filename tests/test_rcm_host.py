@@ -1,7 +1,9 @@
 """The library's host reverse Cuthill-McKee ordering (bo_rcm, through the C
 ABI; no GPU needed) against the oracle, bit for bit: road graphs of several
 widths, a path, a star, several components, isolated nodes, self-loops and
-repeated entries, n = 0 and n = 1; and its argument errors."""
+repeated entries, n = 0 and n = 1; and its argument errors.  The permuted
+pattern (bo_csr_permute) against SciPy's symmetric permutation of the sparse
+matrix."""
 import os
 
 import numpy as np
@@ -74,3 +76,25 @@ def test_rcm_empty_and_errors():
     out = np.array([0, 1, 2], dtype=np.int64)
     ix2 = np.array([5, 0], dtype=np.int64)      # index outside [0, n)
     assert L.bo_rcm(2, hp(out), hp(ix2), hp(perm), None, None) == -1
+
+
+@pytest.mark.parametrize("W,L", [(4, 300), (3, 1000), (6, 50)])
+def test_csr_permute_matches_scipy(W, L):
+    import scipy.sparse as sp
+    from paper_1902_10078_amd import bandops
+    n, ip, ix, ln = inputs.road_graph(W, L, seed=W)
+    qip, qix, qv = inputs.graph_gmrf_csr(n, ip, ix, ln)
+    perm, iperm, _ = bandops.rcm(qip, qix)
+    pip, pix, mp = bandops.csr_permute(qip, qix, perm, iperm)
+    A = sp.csr_matrix((qv, qix, qip), shape=(n, n))[perm][:, perm].tocsr()
+    A.sort_indices()
+    assert np.array_equal(pip, A.indptr) and np.array_equal(pix, A.indices)
+    assert np.array_equal(qv[mp], A.data)
+    # an ordering that is not a permutation is refused
+    import ctypes
+    hp = lambda a: ctypes.c_void_p(a.ctypes.data)
+    bad = perm.copy()
+    bad[0] = bad[1]
+    out = np.zeros(n + 1, dtype=np.int64)
+    o2 = np.zeros(qix.size, dtype=np.int64)
+    assert bandops.lib().bo_csr_permute(n, hp(qip), hp(qix), hp(bad), hp(iperm), hp(out), hp(o2), hp(o2)) == -1
