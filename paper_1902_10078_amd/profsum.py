@@ -70,6 +70,12 @@ _KERNEL_SLOTS = [
     (r"k_ml_post<", "ml_post"),
     (r"k_ml_finalize", "ml_finalize"),
     (r"k_kl_finalize|k_finalize", "finalize"),
+    (r"k_csr_to_band", "csr_to_band"),
+    (r"k_band_to_csr", "band_to_csr"),
+    (r"k_ng_pre<", "ng_pre"),
+    (r"k_ng_post<", "ng_post"),
+    (r"k_ng_neg<", "ng_neg"),
+    (r"k_ng_finalize", "ng_finalize"),
     (r"ClearPart", "clear_partials"),
     (r"k_gbmm", "gbmm"),
     (r"k_gbmv", "gbmv"),
