@@ -486,9 +486,11 @@ template <typename T> int run_step(int step, const Args &a, int64_t count, hipSt
   const bool packed = a.probs != nullptr || a.one.ld == K + 1;
   // Scans: one wavefront per group or problem (groups hold at most 64 chunks,
   // problems at most 64 groups, when the plan's group size is at most 64).
-  // Wider maps (K > 6) are too large to trade between lanes cheaply: their
-  // scans stay with the serial work items.
-  if (K <= 6 && a.G <= kBlock) {
+  // Above K = 6 the maps spill in both forms; measured on gfx950 the
+  // wavefront scans still win at K = 9 (a 16-problem batch of 10^6 rows:
+  // 12 ms of scans down to 4.5) and lose at K = 11 (5 KB of scratch per
+  // lane), so K = 10 and up stay with the serial work items.
+  if (K <= 9 && a.G <= kBlock) {
     const dim3 wg((unsigned)count);
     switch (step) {
       case ST_F1_GCOMP: hipLaunchKernelGGL((k_f1_gscan<K>), wg, block, 0, s, a, count); return hip_ok();
