@@ -306,6 +306,86 @@ def whiten(plan, Q, v):
     return Whiten.apply(plan, Q, v)
 
 
+def _per_band(plan, g):
+    return torch.repeat_interleave(g, torch.tensor([n * (k + 1) for n, k in zip(plan.ns, plan.ks)], device=g.device))
+
+
+def _per_row(plan, g):
+    return torch.repeat_interleave(g, torch.tensor(plan.ns, device=g.device))
+
+
+class MargLik(torch.autograd.Function):
+    """Per-problem log marginal likelihood with partial observations (Eq.
+    (marg_lik), Algorithm 8) over a plan's batch, FP64: Q packed lower bands,
+    mask and b = E^T Y packed vectors, tau2 one per problem.  The forward pass
+    runs the library's call once and keeps the gradients in Q, b and tau2."""
+
+    @staticmethod
+    def forward(ctx, plan, Q, mask, b, tau2):
+        Q, mask, b, tau2 = _vec(Q), _vec(mask), _vec(b), _vec(tau2)
+        dev = Q.device
+        E, N, P = Q.numel(), b.numel(), plan.nprob
+        bufs = {nm: torch.empty(E, dtype=torch.float64, device=dev) for nm in ("L", "Sig", "Qbar")}
+        bufs.update({nm: torch.empty(N, dtype=torch.float64, device=dev) for nm in ("x", "bbar")})
+        tau2bar = torch.empty(P, dtype=torch.float64, device=dev)
+        parts = torch.empty((P, 4), dtype=torch.float64, device=dev)
+        info = torch.zeros(P, dtype=torch.int32, device=dev)
+        plan.marglik(bo.F64, plan.ml_io(Q=Q, mask=mask, b=b, tau2=tau2, tau2bar=tau2bar, parts=parts, info=info,
+                                         **bufs))
+        _check_info(info)
+        ctx.save_for_backward(bufs["Qbar"], bufs["bbar"], tau2bar)
+        ctx.plan = plan
+        return parts[:, 0]
+
+    @staticmethod
+    def backward(ctx, g):
+        Qbar, bbar, tau2bar = ctx.saved_tensors
+        plan = ctx.plan
+        return (None, Qbar * _per_band(plan, g) if ctx.needs_input_grad[1] else None, None,
+                bbar * _per_row(plan, g) if ctx.needs_input_grad[3] else None,
+                tau2bar * g if ctx.needs_input_grad[4] else None)
+
+
+def marglik(plan, Q, mask, b, tau2):
+    return MargLik.apply(plan, Q, mask, b, tau2)
+
+
+class NatGP(torch.autograd.Function):
+    """Per-problem GP regression value a(eta_pr, Lam_pr) - a(eta_po, Lam_po)
+    in banded natural parameters (Appendix C.5, Algorithm 10) over a plan's
+    batch, FP64: Lpr, Llik packed lower bands, etapr, etalik packed vectors.
+    The forward pass keeps the four gradients."""
+
+    @staticmethod
+    def forward(ctx, plan, Lpr, etapr, Llik, etalik):
+        Lpr, etapr, Llik, etalik = _vec(Lpr), _vec(etapr), _vec(Llik), _vec(etalik)
+        dev = Lpr.device
+        E, N, P = Lpr.numel(), etapr.numel(), plan.nprob
+        bufs = {nm: torch.empty(E, dtype=torch.float64, device=dev) for nm in ("L", "Sig", "Lprbar", "Llikbar")}
+        bufs.update({nm: torch.empty(N, dtype=torch.float64, device=dev) for nm in ("x", "etaprbar")})
+        parts = torch.empty((P, 5), dtype=torch.float64, device=dev)
+        info = torch.zeros(P, dtype=torch.int32, device=dev)
+        plan.natgp(bo.F64, plan.ng_io(Lpr=Lpr, etapr=etapr, Llik=Llik, etalik=etalik, parts=parts, info=info, **bufs))
+        _check_info(info)
+        ctx.save_for_backward(bufs["Lprbar"], bufs["etaprbar"], bufs["Llikbar"], bufs["x"])
+        ctx.plan = plan
+        return parts[:, 0]
+
+    @staticmethod
+    def backward(ctx, g):
+        Lprbar, etaprbar, Llikbar, x = ctx.saved_tensors
+        plan = ctx.plan
+        gb, gr = _per_band(plan, g), _per_row(plan, g)
+        return (None, Lprbar * gb if ctx.needs_input_grad[1] else None,
+                etaprbar * gr if ctx.needs_input_grad[2] else None,
+                Llikbar * gb if ctx.needs_input_grad[3] else None,
+                x * gr if ctx.needs_input_grad[4] else None)
+
+
+def natgp(plan, Lpr, etapr, Llik, etalik):
+    return NatGP.apply(plan, Lpr, etapr, Llik, etalik)
+
+
 def chol(Q):
     return Chol.apply(Q)
 

@@ -187,3 +187,44 @@ def test_marglik_info_codes(bo):
     r = oracle.marglik(Q[p], ks[p], mask[p], b[p], tau2[p])
     assert res["info"][p] == 0
     assert abs(res["parts"][p, 0] - r["parts"][0]) <= 1e-12 * max(1.0, abs(r["parts"][1]) + abs(r["parts"][2]))
+
+
+def test_marglik_autograd_vs_dense(bo):
+    """The autograd Function against dense torch autograd (CPU, FP64) of
+    log N(Y; 0, E Q^{-1} E^T + tau2 I) in the stored band of Q, in b at the
+    observed nodes and in tau2, with per-problem output weights."""
+    from paper_1902_10078_amd import autograd as ag
+    ns, ks, fracs = [9, 23, 4], [2, 3, 1], [0.6, 0.5, 1.0]
+    Q, mask, b, tau2 = draw(ns, ks, fracs, 91)
+    plan = bo.Plan(ns, ks)
+    cu = lambda a, rg=True: torch.tensor(np.concatenate([x.ravel() for x in a]) if isinstance(a, list) else a,
+                                         dtype=torch.float64, device="cuda", requires_grad=rg)
+    tQ, tb, tt = cu(Q), cu(b), cu(tau2)
+    w = torch.tensor([1.0, -0.5, 2.0], dtype=torch.float64, device="cuda")
+    lp = ag.marglik(plan, tQ, cu(mask, False), tb, tt)
+    (lp * w).sum().backward()
+    gQ, gb, gt = tQ.grad.cpu().numpy(), tb.grad.cpu().numpy(), tt.grad.cpu().numpy()
+    for p, (n, k) in enumerate(zip(ns, ks)):
+        obs = np.nonzero(mask[p])[0]
+        Qt = torch.tensor(Q[p], requires_grad=True)
+        bt = torch.tensor(b[p], requires_grad=True)
+        t2 = torch.tensor(tau2[p], dtype=torch.float64, requires_grad=True)
+        M = torch.zeros((n, n), dtype=torch.float64)
+        for d in range(min(k, n - 1) + 1):
+            idx = torch.arange(n - d)
+            M = M.index_put((idx + d, idx), Qt[: n - d, d])
+            if d:
+                M = M.index_put((idx, idx + d), Qt[: n - d, d])
+        E = torch.eye(n, dtype=torch.float64)[torch.tensor(obs)]
+        C = E @ torch.linalg.inv(M) @ E.T + t2 * torch.eye(len(obs), dtype=torch.float64)
+        Y = bt[torch.tensor(obs)]
+        ref = -0.5 * len(obs) * np.log(2 * np.pi) - 0.5 * torch.logdet(C) - 0.5 * Y @ torch.linalg.solve(C, Y)
+        assert abs(lp[p].item() - ref.item()) <= 1e-11 * max(1.0, abs(ref.item()))
+        (ref * float(w[p])).backward()
+        o, v = plan.boff[p], plan.voff[p]
+        m = band_mask(n, k)
+        g = Qt.grad.numpy() * m
+        assert np.max(np.abs(gQ[o:o + n * (k + 1)].reshape(n, k + 1) * m - g)) <= 1e-10 * max(1.0, np.abs(g).max())
+        gbr = bt.grad.numpy() * mask[p]
+        assert np.max(np.abs(gb[v:v + n] * mask[p] - gbr)) <= 1e-10 * max(1.0, np.abs(gbr).max())
+        assert abs(gt[p] - t2.grad.item()) <= 1e-10 * max(1.0, abs(t2.grad.item()))

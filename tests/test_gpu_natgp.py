@@ -208,3 +208,43 @@ def test_natgp_info_codes(bo):
     r = oracle_all(probs[2])
     assert res["info"][2] == 0
     assert abs(res["parts"][2, 0] - r["parts"][0]) <= 1e-12 * max(1.0, abs(r["parts"][1]) + abs(r["parts"][2]))
+
+
+def test_natgp_autograd_vs_dense(bo):
+    """The autograd Function against dense torch autograd (CPU, FP64) of
+    a(eta_pr, Lam_pr) - a(eta_po, Lam_po) in all four inputs, with per-problem
+    output weights."""
+    from paper_1902_10078_amd import autograd as ag
+    ns, ks = [9, 23, 4], [2, 3, 1]
+    probs = random_problems(ns, ks, 93)
+    plan = bo.Plan(ns, ks)
+    cu = lambda key: torch.tensor(np.concatenate([p[key].ravel() for p in probs]), dtype=torch.float64,
+                                  device="cuda", requires_grad=True)
+    ts = [cu("Lam_pr"), cu("eta_pr"), cu("Lam_lik"), cu("eta_lik")]
+    w = torch.tensor([0.5, 2.0, -1.0], dtype=torch.float64, device="cuda")
+    val = ag.natgp(plan, *ts)
+    (val * w).sum().backward()
+    grads = [t.grad.cpu().numpy() for t in ts]
+    for p, (n, k) in enumerate(zip(ns, ks)):
+        c = [torch.tensor(probs[p][key], requires_grad=True) for key in ("Lam_pr", "eta_pr", "Lam_lik", "eta_lik")]
+
+        def sym(B):
+            M = torch.zeros((n, n), dtype=torch.float64)
+            for d in range(min(k, n - 1) + 1):
+                idx = torch.arange(n - d)
+                M = M.index_put((idx + d, idx), B[: n - d, d])
+                if d:
+                    M = M.index_put((idx, idx + d), B[: n - d, d])
+            return M
+        a = lambda e, P: 0.5 * torch.logdet(P) - 0.5 * e @ torch.linalg.solve(P, e)
+        ref = a(c[1], sym(c[0])) - a(c[1] + c[3], sym(c[0]) + sym(c[2]))
+        assert abs(val[p].item() - ref.item()) <= 1e-11 * max(1.0, abs(ref.item()))
+        (ref * float(w[p])).backward()
+        o, v = plan.boff[p], plan.voff[p]
+        m = band_mask(n, k)
+        for i, (ct, band) in enumerate(zip(c, (True, False, True, False))):
+            if band:
+                got, want = grads[i][o:o + n * (k + 1)].reshape(n, k + 1) * m, ct.grad.numpy() * m
+            else:
+                got, want = grads[i][v:v + n], ct.grad.numpy()
+            assert np.max(np.abs(got - want)) <= 1e-10 * max(1.0, np.abs(want).max()), i
