@@ -41,6 +41,7 @@ bool csr_ok(int64_t n, const int64_t *indptr, const int64_t *indices) {
 }
 
 constexpr int kRows = 256;
+constexpr int kStageLd = 16;   // records of at most 16 elements are staged in LDS (32 KB in FP64)
 
 __global__ void __launch_bounds__(kRows) k_zero_counter(int64_t *c) {
   if (threadIdx.x == 0) c[0] = 0;
@@ -55,49 +56,82 @@ template <typename T, int W>
 __global__ void __launch_bounds__(kRows)
     k_csr_to_band(int64_t n, int32_t nsets, const int64_t *indptr, const int64_t *indices, const double *vals,
                   int64_t nnz, int32_t k, int64_t ld, T *band, double *diag, int64_t *dropped) {
-  const int64_t t = (int64_t)blockIdx.x * kRows + threadIdx.x;
-  if (t >= n * nsets) return;
-  const int64_t set = t / n, j = t - set * n;
-  const double *v = vals + set * nnz;
+  const int64_t total = n * nsets;
+  const int64_t t0 = (int64_t)blockIdx.x * kRows, t = t0 + threadIdx.x;
+  const bool valid = t < total;
   double rec[W];
 #pragma unroll
   for (int s = 0; s < W; ++s) rec[s] = 0.0;
-  int64_t lost = 0;
-  for (int64_t e = indptr[j]; e < indptr[j + 1]; ++e) {
-    const int64_t d = indices[e] - j;
-    if (d < 0) continue;
-    if (d > k) {
-      ++lost;
-      continue;
-    }
+  if (valid) {
+    const int64_t set = t / n, j = t - set * n;
+    const double *v = vals + set * nnz;
+    int64_t lost = 0;
+    for (int64_t e = indptr[j]; e < indptr[j + 1]; ++e) {
+      const int64_t d = indices[e] - j;
+      if (d < 0) continue;
+      if (d > k) {
+        ++lost;
+        continue;
+      }
 #pragma unroll
-    for (int s = 0; s < W; ++s)
-      if (s == d) rec[s] = v[e];
+      for (int s = 0; s < W; ++s)
+        if (s == d) rec[s] = v[e];
+    }
+    if (diag) diag[t] = rec[0];
+    if (lost) atomicAdd((unsigned long long *)dropped, (unsigned long long)lost);
   }
-  T *out = band + set * n * ld + j * ld;
+  // Record t of the launch lives at band + t ld (t = set n + j), so a
+  // block's records form one contiguous range.  Narrow records go through LDS
+  // and out with consecutive threads on consecutive elements (every thread of
+  // the block reaches the barrier); wide ones are stored directly.
+  if (ld <= kStageLd) {
+    __shared__ T stage[kRows * kStageLd];
+    const int64_t cnt = total - t0 < kRows ? total - t0 : kRows;
+    if (valid) {
+#pragma unroll
+      for (int s = 0; s < W; ++s)
+        if (s < ld) stage[threadIdx.x * ld + s] = (T)rec[s];
+      for (int64_t s = W; s < ld; ++s) stage[threadIdx.x * ld + s] = (T)0;
+    }
+    __syncthreads();
+    T *dst = band + t0 * ld;
+    for (int64_t e = threadIdx.x; e < cnt * ld; e += kRows) dst[e] = stage[e];
+    return;
+  }
+  if (!valid) return;
+  T *out = band + t * ld;
 #pragma unroll
   for (int s = 0; s < W; ++s)
     if (s < ld) out[s] = (T)rec[s];
   for (int64_t s = W; s < ld; ++s) out[s] = (T)0;
-  if (diag) diag[set * n + j] = rec[0];
-  if (lost) atomicAdd((unsigned long long *)dropped, (unsigned long long)lost);
 }
 
 // The reverse: the entries of row j that record j read get the band's
-// gradient there, the row's other entries 0.
+// gradient there, the row's other entries 0.  Narrow records come in through
+// LDS like the assembly's go out (every thread of the block reaches the
+// barrier).
 template <typename T>
 __global__ void __launch_bounds__(kRows)
     k_band_to_csr(int64_t n, int32_t nsets, const int64_t *indptr, const int64_t *indices, int64_t nnz, int32_t k,
                   int64_t ld, const T *gband, const double *gdiag, double *gvals) {
-  const int64_t t = (int64_t)blockIdx.x * kRows + threadIdx.x;
-  if (t >= n * nsets) return;
+  const int64_t total = n * nsets;
+  const int64_t t0 = (int64_t)blockIdx.x * kRows, t = t0 + threadIdx.x;
+  const T *g = gband + t * ld;
+  if (ld <= kStageLd) {
+    __shared__ T stage[kRows * kStageLd];
+    const int64_t cnt = total - t0 < kRows ? total - t0 : kRows;
+    const T *src = gband + t0 * ld;
+    for (int64_t e = threadIdx.x; e < cnt * ld; e += kRows) stage[e] = src[e];
+    __syncthreads();
+    g = stage + threadIdx.x * ld;
+  }
+  if (t >= total) return;
   const int64_t set = t / n, j = t - set * n;
-  const T *g = gband + set * n * ld + j * ld;
   double *gv = gvals + set * nnz;
   for (int64_t e = indptr[j]; e < indptr[j + 1]; ++e) {
     const int64_t d = indices[e] - j;
     double x = 0.0;
-    if (d >= 0 && d <= k) x = (d == 0 && gdiag) ? gdiag[set * n + j] : (double)g[d];
+    if (d >= 0 && d <= k) x = (d == 0 && gdiag) ? gdiag[t] : (double)g[d];
     gv[e] = x;
   }
 }
