@@ -936,8 +936,8 @@ def main():
                          "that calibrates HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        log("bench.py measures one GPU: this build has no multi-GPU path (the batch shards "
-            "by whole problems across GPUs with no exchange; see the design notes). Use --gpus 1.")
+        log("bench.py measures one GPU: the library has no multi-GPU path (a batch would shard by whole "
+            "problems across GPUs, with no exchange between them). Use --gpus 1.")
         sys.exit(2)
 
     import torch
