@@ -9,7 +9,7 @@
  * accessors below (the appendix on algorithms writes them the same way).  No
  * blocking, fusion or reordering beyond what the algorithm states.
  *
- * Readings of the paper taken here (all listed in the design notes):
+ * Readings of the paper taken here:
  *  - band storage index: B[i,j] is slot u+i-j of record j (Section 4.3; the
  *    printed index formula has its sign garbled);
  *  - Algorithms 3 and 4 use the band *height* in their ranges; here every range
@@ -18,7 +18,13 @@
  *    triangle and zeros in its strict upper triangle, which gives the gradient
  *    with respect to the stored lower-band entries of S;
  *  - the solve gradient follows Table 1 (the appendix derivation drops a sign);
- *  - Algorithm 1 has no positivity check; a LAPACK-style info is added.
+ *  - Algorithm 1 has no positivity check; a LAPACK-style info is added;
+ *  - Algorithm 8's last line lacks the -(m/2) log tau2 term of Eq. (marg_lik);
+ *    the equation is followed;
+ *  - Appendix C.5's log-likelihood and Algorithm 10's last line are garbled in
+ *    their signs; the natural-parameter identity the appendix states,
+ *    a(eta_pr, Lam_pr) - a(eta_po, Lam_po) plus the data-space normaliser, is
+ *    followed.
  */
 #include "oracle.h"
 
