@@ -252,7 +252,8 @@ bo_status bo_plan_vi_kl(const bo_plan *plan, bo_prec prec, const bo_kl_io *io, v
  * info[p]: 0, else the first row at which C(Q1) fails (1-based), else n + the
  * row at which C(Q) fails; then the parts and tau2bar are NaN and the other
  * outputs unspecified.  tau2 must be positive (not checked on the device).
- * The workspace is the plan's. */
+ * No output array may overlap an input or another output (intermediates are
+ * kept in the outputs during the call).  The workspace is the plan's. */
 typedef struct {
   const void *Q;   const double *Qd;     /* prior precision Q (lower band)       */
   const void *mask;                       /* observation mask (vector)            */
@@ -290,7 +291,8 @@ bo_status bo_plan_marglik(const bo_plan *plan, bo_prec prec, const bo_ml_io *io,
  * 0, else the first row at which C(Lam_pr) fails (1-based), else n + the row at
  * which C(Lam_po) fails; then the parts are NaN and the other outputs
  * unspecified.  During the call L, x, Lprbar, Llikbar and etaprbar also hold
- * intermediates.  The workspace is the plan's. */
+ * intermediates, so no output array may overlap an input or another output.
+ * The workspace is the plan's. */
 typedef struct {
   const void *Lpr;   const double *Lprd;   /* prior precision Lam_pr             */
   const void *etapr;                        /* prior natural mean eta_pr          */
