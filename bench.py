@@ -921,8 +921,9 @@ def main():
     ap.add_argument("--graph-len", type=int, default=333_334, help="length of the road strip (3 x len junctions)")
     ap.add_argument("--n-alg5", type=int, default=16_000_000, help="rows of the Algorithm 5 matrix")
     ap.add_argument("--cpu-sample", type=int, default=0,
-                    help="problems timed on the CPU oracle (default: 8 for the loss, KL and "
-                         "marginal-likelihood batches, 256 for the uneven batch, 1 otherwise)")
+                    help="problems timed on the CPU oracle (default: 8 for the loss and KL batches, "
+                         "256 for the uneven batch, the whole batch for the marginal-likelihood, "
+                         "natural-parameter, whitened and graph batches, 1 otherwise)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
@@ -982,7 +983,7 @@ def main():
         ns, ks, host_inputs = make_ml(args)
         cfg = {"workload": f"marglik_matern52_batch{len(ns)}_rows{ns[0]}_k5_obs0.8_fwd_bwd",
                "batch": len(ns), "rows_per_problem": ns[0], "k": 5}
-        nsample = args.cpu_sample or 8
+        nsample = args.cpu_sample or len(ns)   # the whole batch: about 10 s of one core
     elif gr:
         host_inputs = make_graph(args, bo)
         ns, ks = [host_inputs["n"]] * 16, [host_inputs["k"]] * 16
@@ -991,7 +992,7 @@ def main():
         cfg = {"workload": f"graph_whiten_road3x{args.graph_len}_rcm_batch16_k{host_inputs['k']}_fwd_bwd",
                "batch": 16, "rows_per_problem": host_inputs["n"], "k": host_inputs["k"],
                "nnz": host_inputs["nnz"], "rcm_host_ms": round(host_inputs["rcm_ms"], 1)}
-        nsample = args.cpu_sample or 4
+        nsample = args.cpu_sample or 16   # the whole batch: a few seconds of one core
     elif wh:
         ns, ks, host_inputs = make_wh(args)
         cfg = {"workload": f"whiten_hmc_matern52_batch{len(ns)}_rows{ns[0]}_k5_fwd_bwd",
@@ -1001,7 +1002,7 @@ def main():
         ns, ks, host_inputs = make_ng(args)
         cfg = {"workload": f"natgp_co2_batch{len(ns)}_weeks{args.t_ng}_rows{ns[0]}_k11_fwd_bwd",
                "batch": len(ns), "rows_per_problem": ns[0], "k": 11}
-        nsample = args.cpu_sample or 512
+        nsample = args.cpu_sample or len(ns)   # the whole batch: a few seconds of one core
         # At k = 11 every chunk is one lane's serial work; 65536 chunks (64 per
         # problem) fill one round of resident waves (4 per CU on 256 CUs)
         # exactly, measured best against 32768, 72704 and 131072.
