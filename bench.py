@@ -149,7 +149,7 @@ def wh_bytes_per_row(k: int, prec: int):
             "f1_replay": 2 * wb,                    # Q -> L
             "f2_summary": wb + wv,                  # L, v
             "f2_replay": wb + 2 * wv,               # L, v -> F
-            "chunk_product": wb,                    # L
+            "chunk_product": wb,                    # L (only when the backward does not reuse them)
             "fs_summary": wb + wv,                  # L, Fbar
             "fs_replay": wb + 2 * wv,               # L, Fbar -> vbar
             "b2_summary": wb + 2 * wv,              # L, F, vbar
@@ -584,7 +584,7 @@ class WHWorkload:
 
     def set_schedule(self, target_chunks: int):
         self.plan = self.bo.Plan(self.ns, self.ks, target_chunks=target_chunks, device=self.dev)
-        self.io = self.plan.wh_io(**self.kw)
+        self.io = self.plan.wh_io(reuse=True, **self.kw)   # backward right after forward
 
     def step(self):
         self.plan.whiten(self.prec, self.io)
@@ -660,7 +660,7 @@ class GraphWorkload:
         self.gvals = torch.zeros_like(self.vals)
         self.dropped = torch.zeros(1, dtype=torch.int64, device=dev)
         self.plan = bo.Plan([n] * nb, [k] * nb, device=dev)
-        self.io = self.plan.wh_io(**kw)
+        self.io = self.plan.wh_io(reuse=True, **kw)   # backward right after forward
 
     def step(self):
         bo, p, kw = self.bo, self.prec, self.kw

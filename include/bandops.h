@@ -331,6 +331,10 @@ typedef struct {
   void *Qbar;        double *Qbard;        /* out (backward)                    */
   double *logdet;                           /* out (forward), per problem        */
   int32_t *info;                            /* out (forward), per problem        */
+  int32_t reuse;   /* backward: nonzero reuses the chunk products of L that the
+                      preceding bo_plan_whiten on this plan left in ws (L and ws
+                      unchanged since, no other call on ws in between); 0
+                      recomputes them */
 } bo_whiten_io;
 bo_status bo_plan_whiten(const bo_plan *plan, bo_prec prec, const bo_whiten_io *io, void *ws,
                          hipStream_t stream);

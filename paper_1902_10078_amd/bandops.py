@@ -58,7 +58,7 @@ class _NGIO(ctypes.Structure):
 
 class _WHIO(ctypes.Structure):
     _fields_ = [(name, _P) for name in (
-        "Q", "Qd", "v", "L", "Ld", "F", "Fbar", "vbar", "Qbar", "Qbard", "logdet", "info")]
+        "Q", "Qd", "v", "L", "Ld", "F", "Fbar", "vbar", "Qbar", "Qbard", "logdet", "info")] + [("reuse", _I32)]
 
 
 class _KLIO(ctypes.Structure):
@@ -462,10 +462,13 @@ class Plan:
         io.etaprbar, io.parts and io.info."""
         _check(lib().bo_plan_natgp(self.h, prec, ctypes.byref(io), _ptr(self.ws), _stream()), "bo_plan_natgp")
 
-    def wh_io(self, **arrays) -> _WHIO:
+    def wh_io(self, reuse: bool = False, **arrays) -> _WHIO:
+        """reuse: the backward call takes the chunk products of L that the
+        preceding whiten call on this plan left in the workspace."""
         io = _WHIO()
         for k_, v in arrays.items():
             setattr(io, k_, _ptr(v))
+        io.reuse = 1 if reuse else 0
         return io
 
     def whiten(self, prec: int, io: _WHIO):

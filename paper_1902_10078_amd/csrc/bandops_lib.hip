@@ -959,7 +959,7 @@ extern "C" bo_status bo_plan_whiten_bwd(const bo_plan *plan, bo_prec prec, const
   A.Qb = io->Qbar;
   A.Qbd = io->Qbard;
   GpuBE be{stream};
-  return dev_status(bo_wh::pipe_whiten_bwd(be, plan->s, A, (int)prec), "bo_plan_whiten_bwd");
+  return dev_status(bo_wh::pipe_whiten_bwd(be, plan->s, A, (int)prec, io->reuse != 0), "bo_plan_whiten_bwd");
 }
 
 extern "C" bo_status bo_plan_stats(const bo_plan *plan, int64_t out[5]) {

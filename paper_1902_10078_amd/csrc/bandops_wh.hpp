@@ -36,14 +36,17 @@ template <class BE> int pipe_whiten(BE &be, const bo::Sched &s, bo::Args A, int 
 }
 
 // A.L: the factor; A.bx = Fbar, A.x = vbar; A.yb = F, A.zf = vbar; A.Qb = Qbar.
-template <class BE> int pipe_whiten_bwd(BE &be, const bo::Sched &s, bo::Args A, int prec) {
+// With reuse, the chunk products of L are the ones the forward call's F1
+// replay left in the workspace (the linear passes' scans only read them).
+template <class BE> int pipe_whiten_bwd(BE &be, const bo::Sched &s, bo::Args A, int prec, bool reuse) {
   A.lmap_out = nullptr;
   A.Lb = nullptr;
   A.Lbd = nullptr;
   A.gl = 0.0;
   A.xscale = 1.0;
   if (int e = bo::seq_clear(be, s, A)) return e;
-  if (int e = bo::seq_pc(be, s, A, prec)) return e;
+  if (!reuse)
+    if (int e = bo::seq_pc(be, s, A, prec)) return e;
   if (int e = bo::seq_lin(be, s, A, prec, bo::PASS_FS, false)) return e;
   return bo::seq_lin(be, s, A, prec, bo::PASS_B2, false);
 }

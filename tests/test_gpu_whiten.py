@@ -51,7 +51,7 @@ def rounded(B):
     return R
 
 
-def run_wh(bo, plan, Qs, vs, Fbs, prec=0):
+def run_wh(bo, plan, Qs, vs, Fbs, prec=0, reuse=False):
     cat = lambda a: np.concatenate([x.ravel() for x in a])
     dt = torch.float64 if prec == 0 else torch.float32
     dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
@@ -67,7 +67,7 @@ def run_wh(bo, plan, Qs, vs, Fbs, prec=0):
         t["Qd"] = torch.tensor(np.concatenate([a[:, 0] for a in Qs]), dtype=torch.float64, device="cuda")
         for nm in ("Ld", "Qbard"):
             t[nm] = torch.full((N,), float("nan"), dtype=torch.float64, device="cuda")
-    io = plan.wh_io(**t)
+    io = plan.wh_io(reuse=reuse, **t)
     plan.whiten(prec, io)
     plan.whiten_bwd(prec, io)
     torch.cuda.synchronize()
@@ -125,6 +125,22 @@ def test_whiten_mixed(bo, ns, ks):
     res = run_wh(bo, plan, Qs, vs, Fbs, prec=1)
     r32 = lambda a: a.astype(np.float32).astype(np.float64)
     check(plan, [rounded(a) for a in Qs], [r32(a) for a in vs], [r32(a) for a in Fbs], res, TOL_MIXED)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_whiten_bwd_reusing_chunk_products(bo, prec):
+    """The backward call taking the chunk products the forward call left in
+    the workspace (reuse) meets the same bar against the oracle."""
+    ns, ks = BATCHES[0]
+    print(f"case whiten reuse prec={prec}", flush=True)
+    Qs, vs, Fbs = draw(ns, ks, 71 + prec)
+    plan = bo.Plan(ns, ks, target_chunks=300)
+    res = run_wh(bo, plan, Qs, vs, Fbs, prec=prec, reuse=True)
+    if prec == 0:
+        check(plan, Qs, vs, Fbs, res, TOL)
+    else:
+        r32 = lambda a: a.astype(np.float32).astype(np.float64)
+        check(plan, [rounded(a) for a in Qs], [r32(a) for a in vs], [r32(a) for a in Fbs], res, TOL_MIXED)
 
 
 def test_whiten_full_size_rows(bo):
