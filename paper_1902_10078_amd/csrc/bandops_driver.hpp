@@ -228,8 +228,11 @@ template <class BE> int seq_clear(BE &be, const Sched &s, Args A) {
 }
 
 // F1: Cholesky + log-determinant (+ forward solve when A.y is set); with
-// want_P the chunk products of L for the linear passes that follow.
-template <class BE> int seq_f1(BE &be, const Sched &s, Args A, int prec, bool want_P) {
+// want_P the chunk products of L for the linear passes that follow.  rep_y,
+// when given with A.y and A.z null, is read by the replay alone as the
+// right-hand side of the F2 chunk maps it accumulates (A.lmap_out).
+template <class BE> int seq_f1(BE &be, const Sched &s, Args A, int prec, bool want_P,
+                               const void *rep_y = nullptr) {
   for (const KRange &r : s.ranges) {
     set_range(A, r);
     if (r.K > 0 && r.max_nchunk > 1) {
@@ -244,6 +247,7 @@ template <class BE> int seq_f1(BE &be, const Sched &s, Args A, int prec, bool wa
       B.lmap_out = nullptr;
     }
     if (r.K > KMAX_FUSED) B.lmap_out = nullptr;
+    if (rep_y && B.lmap_out && !A.y && !A.z) B.y = rep_y;
     if (int e = be.step(ST_F1_REP, r.K, prec, B, r.c_cnt)) return e;
   }
   return 0;

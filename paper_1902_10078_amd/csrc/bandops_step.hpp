@@ -104,9 +104,11 @@ template <int K, typename T> struct F1RepStep {
   T *z;
 
   // wantF2 (needs wantP): also accumulate the chunk map of the descending F2
-  // pass, M = sum_j R_j^T c_j e0 e0^T R_j and v = sum_j R_j^T e0 z_j / L_jj
+  // pass, M = sum_j R_j^T c_j e0 e0^T R_j and v = sum_j R_j^T e0 b_j / L_jj
   // with R_j = Kt_{j-1} ... Kt_a -- the zero-state run of F2 over the chunk,
-  // summed in ascending order.
+  // summed in ascending order.  The back solve's right-hand side b is the
+  // forward solve's z when the replay writes z, else the replay's y input
+  // itself (a back solve L^{-T} y with no forward solve).
   BO_HD void begin(const F1State<K> &st, BandP<T> L_, T *z_, bool wantP, bool wantF2 = false) {
     L = L_;
     z = z_;
@@ -169,7 +171,7 @@ template <int K, typename T> struct F1RepStep {
     if (want_P) {
       if (want_f2) {
         // row 0 of R_j = Pm before this row's update
-        const double cj = inv * inv, xj = zj * inv;
+        const double cj = inv * inv, xj = (z ? zj : yj) * inv;
 #pragma unroll
         for (int p = 0; p < K; ++p) {
           v2[p] += Pm[0][p] * xj;

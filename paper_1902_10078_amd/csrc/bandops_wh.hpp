@@ -11,8 +11,10 @@
 //   backward: the chunk products of L, the FS pass (vbar), then the B2 pass
 //             with no incoming Lbar, no log-determinant term and the solve
 //             term -F[j+d] vbar[j] folded into each column of Lbar.
-// Every summary runs as its own kernel: the F1 replay only sees Q, not the
-// right-hand side of the back solve.  Included by the host library.
+// The F1 replay also reads v and accumulates the F2 chunk maps, so the back
+// solve has no summary kernel of its own (up to the fused bandwidth limit);
+// the backward passes run their summaries as kernels of their own.
+// Included by the host library.
 #pragma once
 #include "bandops_driver.hpp"
 
@@ -23,15 +25,15 @@ template <class BE> int pipe_whiten(BE &be, const bo::Sched &s, bo::Args A, int 
   bo::Args F1 = A;
   F1.y = nullptr;
   F1.z = nullptr;
-  F1.lmap_out = nullptr;
-  if (int e = bo::seq_f1(be, s, F1, prec, true)) return e;
+  F1.lmap_out = A.lmap;
+  if (int e = bo::seq_f1(be, s, F1, prec, true, A.bx)) return e;
   bo::Args F2 = A;   // A.bx = v, A.x = F
   F2.S = nullptr;
   F2.Sd = nullptr;
   F2.Sb = nullptr;
   F2.xscale = 1.0;
   F2.lmap_out = nullptr;
-  if (int e = bo::seq_lin(be, s, F2, prec, bo::PASS_F2, false)) return e;
+  if (int e = bo::seq_lin(be, s, F2, prec, bo::PASS_F2, true)) return e;
   return bo::seq_finalize(be, s, A);
 }
 
