@@ -209,7 +209,7 @@ BO_HD void run_pass(const Args &A, const ProbDesc &pd, int64_t a, int64_t b, Lin
   aux = 0.0;
   if (PASS == PASS_FS) {
     fs_chunk<K, T, REPLAY>(a, b, pd.n, cband<T>(A.L, A.Ld, pd), cvec<T>(A.bx, pd), vec<T>(A.x, pd),
-                           A.xscale, st);
+                           A.xscale, st, cvec<T>(A.yb, pd), A.gl, next);
   } else if (PASS == PASS_F2) {
     f2_chunk<K, T, REPLAY>(a, b, pd.n, cband<T>(A.L, A.Ld, pd), band<T>(A.S, A.Sd, pd),
                            cvec<T>(A.bx, pd), vec<T>(A.x, pd), A.xscale, st,
@@ -252,7 +252,7 @@ template <int K, typename T, int PASS> struct LinReplay {
       lin_zero<K>(st);
     double aux;
     LinMap<K> nm;
-    const bool fuse = A.lmap_out && (PASS == PASS_F2 || PASS == PASS_B1);
+    const bool fuse = A.lmap_out && (PASS == PASS_FS || PASS == PASS_F2 || PASS == PASS_B1);
     run_pass<K, T, PASS, true>(A, pd, a, b, st, aux, fuse ? &nm : nullptr);
     if (fuse) lin_store<K>(A.lmap_out + (int64_t)c * A.sw_lin, nm);
     if (PASS == PASS_B1) A.part[4 * (int64_t)c + 2] = aux;

@@ -132,7 +132,10 @@ template <int K> __device__ __forceinline__ void lin_in(const Args &A, const Lan
     lin_zero<K>(st);
 }
 
-template <int K, typename T, bool REPLAY>
+// FUSE (replay only): the forward solve also accumulates the chunk maps of a
+// B2 pass whose z is this solve's output and which has no Lbar record (needs
+// ybar, staged K+1 rows ahead).
+template <int K, typename T, bool REPLAY, bool FUSE>
 __global__ void __launch_bounds__(kBlock) k_fs(const Args A, int64_t count) {
   const LaneChunk C = lane_chunk(A, count);
   const ProbDesc &pd = C.pd;
@@ -143,11 +146,29 @@ __global__ void __launch_bounds__(kBlock) k_fs(const Args A, int64_t count) {
   FsStep<K, T, REPLAY> s;
   s.begin(st, vec<T>(A.x, pd), A.xscale);
   BandIn<T> bands[1] = {{on ? L.p : nullptr, on ? L.diag : nullptr, 0}};
-  VecIn<T> vecs[1] = {{on ? cvec<T>(A.bx, pd) : nullptr, 0}};
-  stream_rows<K, T, 1, 1, false>(bands, vecs, on ? C.a : 0, on ? C.b : 0, pd.n, pd.ld,
-                                 [&](int64_t j, const double (&rec)[1][K + 1], const double (&val)[1]) {
-                                   s.row(j, rec[0], val[0]);
-                                 });
+  if constexpr (FUSE) {
+    const T *yb = cvec<T>(A.yb, pd);
+    B2MapAcc<K> m2;
+    if (on) m2.begin(C.a, pd.n, yb, A.gl);
+    const double zero[K + 1] = {};
+    VecIn<T> vecs[2] = {{on ? cvec<T>(A.bx, pd) : nullptr, 0}, {on ? yb : nullptr, K + 1}};
+    stream_rows<K, T, 1, 2, false>(bands, vecs, on ? C.a : 0, on ? C.b : 0, pd.n, pd.ld,
+                                   [&](int64_t j, const double (&rec)[1][K + 1], const double (&val)[2]) {
+                                     const double xj = s.row(j, rec[0], val[0]);
+                                     m2.row(rec[0], 1.0 / rec[0][0], zero, xj, val[1]);
+                                   });
+    if (on) {
+      LinMap<K> m;
+      m2.end(m);
+      lin_store<K>(A.lmap_out + (int64_t)C.c * A.sw_lin, m);
+    }
+  } else {
+    VecIn<T> vecs[1] = {{on ? cvec<T>(A.bx, pd) : nullptr, 0}};
+    stream_rows<K, T, 1, 1, false>(bands, vecs, on ? C.a : 0, on ? C.b : 0, pd.n, pd.ld,
+                                   [&](int64_t j, const double (&rec)[1][K + 1], const double (&val)[1]) {
+                                     s.row(j, rec[0], val[0]);
+                                   });
+  }
   if (on && !REPLAY) {
     s.end(st);
     lin_store<K>(A.lmap + (int64_t)C.c * A.sw_lin, st);
@@ -513,8 +534,13 @@ template <typename T> int run_step(int step, const Args &a, int64_t count, hipSt
     case ST_F1_SUM: hipLaunchKernelGGL((k_f1_sum<K, T>), grid, block, 0, s, a, count); break;
     case ST_F1_REP: hipLaunchKernelGGL((k_f1_rep<K, T>), grid, block, 0, s, a, count); break;
     case ST_PC: hipLaunchKernelGGL((k_pc<K, T>), grid, block, 0, s, a, count); break;
-    case ST_FS_SUM: hipLaunchKernelGGL((k_fs<K, T, false>), grid, block, 0, s, a, count); break;
-    case ST_FS_REP: hipLaunchKernelGGL((k_fs<K, T, true>), grid, block, 0, s, a, count); break;
+    case ST_FS_SUM: hipLaunchKernelGGL((k_fs<K, T, false, false>), grid, block, 0, s, a, count); break;
+    case ST_FS_REP:
+      if (a.lmap_out)
+        hipLaunchKernelGGL((k_fs<K, T, true, true>), grid, block, 0, s, a, count);
+      else
+        hipLaunchKernelGGL((k_fs<K, T, true, false>), grid, block, 0, s, a, count);
+      break;
     case ST_F2_SUM: hipLaunchKernelGGL((k_f2<K, T, false, false>), grid, block, 0, s, a, count); break;
     case ST_F2_REP:
       if (a.lmap_out && a.Sb)

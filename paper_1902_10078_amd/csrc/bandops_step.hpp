@@ -239,12 +239,15 @@ template <int K, typename T, bool REPLAY> struct FsStep {
 #pragma unroll
     for (int p = 0; p < K1; ++p) g[p] = REPLAY ? st.v[p] : 0.0;
   }
-  BO_HD void row(int64_t j, const double (&r)[K + 1], double yj) {
+  // Returns the value stored at x[j] (xscale z_j, rounded to T).
+  BO_HD double row(int64_t j, const double (&r)[K + 1], double yj) {
     double inv = 1.0 / r[0];
     double zj = (yj - (K > 0 ? g[0] : 0.0)) * inv;
-    if (REPLAY) x[j] = (T)(xscale * zj);
+    const T xj = (T)(xscale * zj);
+    if (REPLAY) x[j] = xj;
 #pragma unroll
     for (int p = 0; p < K; ++p) g[p] = ((p + 1 < K) ? g[p + 1] : 0.0) + r[p + 1] * zj;
+    return (double)xj;
   }
   BO_HD void end(LinMap<K> &st) const {
 #pragma unroll
@@ -387,37 +390,18 @@ template <int K, typename T, bool REPLAY> struct F2Step {
   }
 };
 
-// ================================================================== B1
-// Ascending: reverse mode of the subset inverse (Algorithm 4).  The state
-// entering row j is Wb, the sensitivity of the window W_j (symmetric, both
-// halves counted).  With sb = Sigmabar record j (stored lower entries):
-//   Sbjj  = sb_0 + Wb[0][0]
-//   vb_p  = sb_{1+p} + 2 Wb[0][1+p]            (vb_{K-1} = sb_K)
-//   ub    = -2 Sbjj v - X vb                   (X = Sigma window below j,
-//                                               v = Sigma[j+1.., j])
-//   Lbar[j+1+p, j] = ub_p / L_jj
-//   Lbar_jj        = -2 Sbjj c_j / L_jj - (ub . u) / L_jj
-//   Wb'  = shift(Wb) + Sbjj u u^T - (vb u^T + u vb^T)/2   (= Kt Wb Kt^T + ...)
-// The replay keeps the K+1 Sigma records j .. j+K in registers (Sg[i] =
-// record j+i) and takes record j+K+1 with each row.  With sb_is_S the
-// sensitivity is (S_jj, 2 S_{j+1,j}, ...) from the band S of tr(Q^{-1} S), and
-// sum_j Sigma_jj S_jj + 2 sum Sigma_ij S_ij is accumulated.
-template <int K, typename T, bool REPLAY> struct B1Step {
+// Ascending accumulation of the chunk map of the descending B2 pass: the
+// zero-state run of B2 over a chunk is M = sum_j R_j^T inj2_j R_j with
+// R_j = Kt_{j-1} ... Kt_a and inj2_j the B2 injection of the total
+// sensitivity of column j (a given Lbar record, the log-determinant term
+// 2 gl / L_jj and the solve term -ybar[j+d] z[j]); yw = ybar[j .. j+K].  A
+// replay that visits rows upwards and produces either the Lbar record (B1) or
+// z (the forward solve) feeds it one row at a time.
+template <int K> struct B2MapAcc {
   static constexpr int K1 = Dim<K>::K1, NS = Dim<K>::NS;
-  double Wb[NS];
-  double Sg[K + 1][K + 1];
-  double tr;
-  bool sb_is_S, accumulate;
-  BandP<T> Lb;
-  // fused summary of the descending B2 pass: M = sum_j R_j^T inj2_j R_j with
-  // R_j = Kt_{j-1} ... Kt_a and inj2_j the B2 injection of the total
-  // sensitivity of column j (this pass's Lbar record, the log-determinant term
-  // and the solve term); yw = ybar[j .. j+K].
-  bool want_b2;
   double Rf[K1][K1], Mf[NS], yw[K + 1], glf;
 
-  BO_HD void begin_b2(int64_t a, int64_t n, const T *ybar, double gl) {
-    want_b2 = true;
+  template <typename T> BO_HD void begin(int64_t a, int64_t n, const T *ybar, double gl) {
     glf = gl;
 #pragma unroll
     for (int p = 0; p < K1; ++p)
@@ -429,7 +413,7 @@ template <int K, typename T, bool REPLAY> struct B1Step {
     for (int d = 0; d <= K; ++d) yw[d] = (ybar && a + d < n) ? (double)ybar[a + d] : 0.0;
   }
 
-  BO_HD void end_b2(LinMap<K> &m) const {
+  BO_HD void end(LinMap<K> &m) const {
 #pragma unroll
     for (int p = 0; p < K1; ++p) {
       m.v[p] = 0.0;
@@ -438,9 +422,9 @@ template <int K, typename T, bool REPLAY> struct B1Step {
     }
   }
 
-  // o = Lbar record j just produced, r = L record j (inv = 1 / L_jj), zj =
-  // z[j], yahead = ybar[j+K+1] (0 past the end).
-  BO_HD void row_b2(const double (&r)[K + 1], double inv, const double (&o)[K + 1], double zj, double yahead) {
+  // o = Lbar record j (zeros when there is none), r = L record j (inv =
+  // 1 / L_jj), zj = z[j], yahead = ybar[j+K+1] (0 past the end).
+  BO_HD void row(const double (&r)[K + 1], double inv, const double (&o)[K + 1], double zj, double yahead) {
     double Lt[K + 1];
 #pragma unroll
     for (int d = 0; d <= K; ++d) Lt[d] = o[d] - yw[d] * zj;
@@ -479,6 +463,41 @@ template <int K, typename T, bool REPLAY> struct B1Step {
     for (int d = 0; d < K; ++d) yw[d] = yw[d + 1];
     yw[K] = yahead;
   }
+};
+
+// ================================================================== B1
+// Ascending: reverse mode of the subset inverse (Algorithm 4).  The state
+// entering row j is Wb, the sensitivity of the window W_j (symmetric, both
+// halves counted).  With sb = Sigmabar record j (stored lower entries):
+//   Sbjj  = sb_0 + Wb[0][0]
+//   vb_p  = sb_{1+p} + 2 Wb[0][1+p]            (vb_{K-1} = sb_K)
+//   ub    = -2 Sbjj v - X vb                   (X = Sigma window below j,
+//                                               v = Sigma[j+1.., j])
+//   Lbar[j+1+p, j] = ub_p / L_jj
+//   Lbar_jj        = -2 Sbjj c_j / L_jj - (ub . u) / L_jj
+//   Wb'  = shift(Wb) + Sbjj u u^T - (vb u^T + u vb^T)/2   (= Kt Wb Kt^T + ...)
+// The replay keeps the K+1 Sigma records j .. j+K in registers (Sg[i] =
+// record j+i) and takes record j+K+1 with each row.  With sb_is_S the
+// sensitivity is (S_jj, 2 S_{j+1,j}, ...) from the band S of tr(Q^{-1} S), and
+// sum_j Sigma_jj S_jj + 2 sum Sigma_ij S_ij is accumulated.
+template <int K, typename T, bool REPLAY> struct B1Step {
+  static constexpr int K1 = Dim<K>::K1, NS = Dim<K>::NS;
+  double Wb[NS];
+  double Sg[K + 1][K + 1];
+  double tr;
+  bool sb_is_S, accumulate;
+  BandP<T> Lb;
+  // fused summary of the descending B2 pass (B2MapAcc), fed with this pass's
+  // Lbar record of each row.
+  bool want_b2;
+  B2MapAcc<K> b2;
+
+  BO_HD void begin_b2(int64_t a, int64_t n, const T *ybar, double gl) {
+    want_b2 = true;
+    b2.begin(a, n, ybar, gl);
+  }
+
+  BO_HD void end_b2(LinMap<K> &m) const { b2.end(m); }
 
   // Sigma records a .. a+K are read directly (once per chunk).
   BO_HD void begin(const LinMap<K> &st, int64_t a, int64_t n, BandP<const T> Sig, bool sbS,
@@ -551,7 +570,7 @@ template <int K, typename T, bool REPLAY> struct B1Step {
         for (int d = 0; d <= K; ++d) o[d] += old[d];
       }
       store_rec<K, T>(Lb.p, Lb.diag, Lb.ld, j, o);
-      if (want_b2) row_b2(r, inv, o, zj, yahead);
+      if (want_b2) b2.row(r, inv, o, zj, yahead);
 #pragma unroll
       for (int i = 0; i < K; ++i)
 #pragma unroll
@@ -718,17 +737,27 @@ BO_HD void pc_chunk(int64_t a, int64_t b, int64_t n, BandP<const T> L, double *P
   s.end(P);
 }
 
+// With b2map (replay only): also the chunk map of a B2 pass that takes this
+// solve's output as its z, no Lbar record, ybar and the log-determinant
+// weight gl.
 template <int K, typename T, bool REPLAY>
 BO_HD void fs_chunk(int64_t a, int64_t b, int64_t n, BandP<const T> L, const T *y, T *z,
-                    double xscale, LinMap<K> &st) {
+                    double xscale, LinMap<K> &st, const T *ybar = nullptr, double gl = 0.0,
+                    LinMap<K> *b2map = nullptr) {
   FsStep<K, T, REPLAY> s;
   s.begin(st, z, xscale);
+  B2MapAcc<K> m2;
+  if (REPLAY && b2map) m2.begin(a, n, ybar, gl);
+  const double zero[K + 1] = {};
   for (int64_t j = a; j < b; ++j) {
     double r[K + 1];
     load_rec<K, T>(L.p, L.diag, L.ld, j, n, r);
-    s.row(j, r, (double)y[j]);
+    const double xj = s.row(j, r, (double)y[j]);
+    if (REPLAY && b2map)
+      m2.row(r, 1.0 / r[0], zero, xj, (ybar && j + K + 1 < n) ? (double)ybar[j + K + 1] : 0.0);
   }
   s.end(st);
+  if (REPLAY && b2map) m2.end(*b2map);
 }
 
 template <int K, typename T, bool REPLAY>

@@ -11,10 +11,10 @@
 //   backward: the chunk products of L, the FS pass (vbar), then the B2 pass
 //             with no incoming Lbar, no log-determinant term and the solve
 //             term -F[j+d] vbar[j] folded into each column of Lbar.
-// The F1 replay also reads v and accumulates the F2 chunk maps, so the back
-// solve has no summary kernel of its own (up to the fused bandwidth limit);
-// the backward passes run their summaries as kernels of their own.
-// Included by the host library.
+// Summaries are fused into the replay before them (up to the fused bandwidth
+// limit): the F1 replay also reads v and accumulates the F2 chunk maps, and
+// the FS replay accumulates the B2 chunk maps from each vbar[j] it produces
+// and F staged k+1 rows ahead.  Included by the host library.
 #pragma once
 #include "bandops_driver.hpp"
 
@@ -49,8 +49,12 @@ template <class BE> int pipe_whiten_bwd(BE &be, const bo::Sched &s, bo::Args A, 
   if (int e = bo::seq_clear(be, s, A)) return e;
   if (!reuse)
     if (int e = bo::seq_pc(be, s, A, prec)) return e;
-  if (int e = bo::seq_lin(be, s, A, prec, bo::PASS_FS, false)) return e;
-  return bo::seq_lin(be, s, A, prec, bo::PASS_B2, false);
+  bo::Args FS = A;   // the FS replay also accumulates the B2 chunk maps
+  FS.lmap_out = A.lmap2;
+  if (int e = bo::seq_lin(be, s, FS, prec, bo::PASS_FS, false)) return e;
+  bo::Args B2 = A;
+  B2.lmap = A.lmap2;
+  return bo::seq_lin(be, s, B2, prec, bo::PASS_B2, true);
 }
 
 }  // namespace bo_wh
