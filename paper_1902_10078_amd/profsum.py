@@ -30,8 +30,8 @@ _KERNEL_SLOTS = [
     (r"k_f1_sum<", "f1_summary"),
     (r"k_f1_rep<", "f1_replay"),
     (r"k_pc<", "chunk_product"),
-    (r"k_fs<\d+, \w+, false>", "fs_summary"),
-    (r"k_fs<\d+, \w+, true>", "fs_replay"),
+    (r"k_fs<\d+, \w+, false", "fs_summary"),
+    (r"k_fs<\d+, \w+, true", "fs_replay"),
     (r"k_f2<\d+, \w+, false", "f2_summary"),
     (r"k_f2<\d+, \w+, true", "f2_replay"),
     (r"k_b1<\d+, \w+, false", "b1_summary"),
