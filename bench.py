@@ -117,10 +117,9 @@ def ml_bytes_per_row(k: int, prec: int):
     (Algorithm 8 and its reverse mode): two forward lists (on Q without a
     right-hand side, on Q1 with b) and the row kernels around them."""
     wb, wv = record_bytes(k, prec)
-    return {"ml_pre": 2 * wb + wv,                  # Q, mask -> Q1
-            "chunk_product": 0,                      # chunk scans only (written by the F1 replays)
-            "f1_summary": 2 * wb + wv,               # Q; Q1, b
-            "f1_replay": 4 * wb + 2 * wv,            # Q -> L_Q; Q1, b -> L, z
+    return {"chunk_product": 0,                      # chunk scans only (written by the F1 replays)
+            "f1_summary": 2 * wb + 2 * wv,           # Q; Q, mask, b (Q1 = Q + mask / tau2 as read)
+            "f1_replay": 4 * wb + 3 * wv,            # Q -> L_Q; Q, mask, b -> L, z
             "f2_replay": 4 * wb + 2 * wv,            # L_Q -> I(L_Q); L, z -> Sigma, x
             "ml_post": 3 * wb + 4 * wv,              # Sigma, I(L_Q), x, mask, b -> Qbar, bbar
             "unit": 4 * wb + 4 * wv}                 # Q, mask, b in; L, Sigma, x, Qbar, bbar out

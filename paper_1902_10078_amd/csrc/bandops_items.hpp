@@ -40,6 +40,7 @@ struct Args {
   int32_t sw_f1map, sw_f1st, sw_mat, sw_lin;
   // ---- data (typed by the item's storage type T)
   const void *Q;  const double *Qd;   // input precision (lower band)
+  const void *qdn; const double *qdd; // F1 only: Q_jj + qdn[j] / qdd[problem] (qdn null: none)
   void *L;        double *Ld;         // Cholesky factor (output of F1, input after)
   const void *y;  void *z;            // rhs, forward solve
   const void *bx; void *x;            // back-solve rhs and result
@@ -92,6 +93,10 @@ template <typename T> BO_HD const T *cvec(const void *p, const ProbDesc &pd) {
   return p ? (const T *)p + pd.voff : nullptr;
 }
 template <typename T> BO_HD T *vec(void *p, const ProbDesc &pd) { return p ? (T *)p + pd.voff : nullptr; }
+// Scale of F1's diagonal addend for a problem: 1 / qdd[problem] (0 without one).
+BO_HD double qdiag_scale(const Args &A, const ProbDesc &pd) {
+  return (A.qdn && A.qdd) ? 1.0 / A.qdd[pd.orig] : 0.0;
+}
 
 // ============================================================== F1 items
 template <int K, typename T> struct F1Summary {
@@ -102,7 +107,8 @@ template <int K, typename T> struct F1Summary {
     int64_t a, b;
     chunk_rows(pd, c, a, b);
     F1Map<K> m;
-    f1_summary_chunk<K, T>(a, b, pd.n, cband<T>(A.Q, A.Qd, pd), cvec<T>(A.y, pd), m);
+    f1_summary_chunk<K, T>(a, b, pd.n, cband<T>(A.Q, A.Qd, pd), cvec<T>(A.y, pd), m, cvec<T>(A.qdn, pd),
+                           qdiag_scale(A, pd));
     f1_store_map<K>(A.f1map + (int64_t)c * A.sw_f1map, m);
   }
 };
@@ -180,7 +186,7 @@ template <int K, typename T> struct F1Replay {
     int64_t fail = f1_replay_chunk<K, T>(a, b, pd.n, cband<T>(A.Q, A.Qd, pd), band<T>(A.L, A.Ld, pd),
                                          cvec<T>(A.y, pd), vec<T>(A.z, pd), s,
                                          A.Pc ? A.Pc + (int64_t)c * A.sw_mat : nullptr, ls, qs,
-                                         fuse ? &f2m : nullptr);
+                                         fuse ? &f2m : nullptr, cvec<T>(A.qdn, pd), qdiag_scale(A, pd));
     if (fuse) lin_store<K>(A.lmap_out + (int64_t)c * A.sw_lin, f2m);
     double *pt = A.part + 4 * (int64_t)c;
     pt[0] = ls;

@@ -49,35 +49,60 @@ __device__ __forceinline__ LaneChunk lane_chunk(const Args &A, int64_t count) {
 }
 
 // ------------------------------------------------------------------- F1
-template <int K, typename T>
+// DIAG: the factored matrix is Q + diag(qdn / qdd[problem]); the addend is
+// staged as a second vector (val[1]) and added to each diagonal entry as it is
+// read.
+template <int K>
+__device__ __forceinline__ void with_diag(const double (&rec)[K + 1], const double (&val)[2], double ds,
+                                          double (&q)[K + 1]) {
+#pragma unroll
+  for (int d = 0; d <= K; ++d) q[d] = rec[d];
+  q[0] += val[1] * ds;
+}
+
+template <int K, typename T, bool DIAG>
 __global__ void __launch_bounds__(kBlock) k_f1_sum(const Args A, int64_t count) {
+  constexpr int NV = DIAG ? 2 : 1;
   const LaneChunk C = lane_chunk(A, count);
   const ProbDesc &pd = C.pd;
   const bool on = C.active && C.c != pd.chunk0 + pd.nchunk - 1;
   BandP<const T> Q = cband<T>(A.Q, A.Qd, pd);
   const T *y = cvec<T>(A.y, pd);
+  const T *dn = DIAG ? cvec<T>(A.qdn, pd) : nullptr;
+  const double ds = DIAG ? qdiag_scale(A, pd) : 0.0;
   F1Map<K> m;
   F1SumStep<K, T> st;
-  if (on) st.begin(C.a, pd.n, Q, y, m);
+  if (on) st.begin(C.a, pd.n, Q, y, m, dn, ds);
   BandIn<T> bands[1] = {{on ? Q.p : nullptr, on ? Q.diag : nullptr, 0}};
-  VecIn<T> vecs[1] = {{on ? y : nullptr, 0}};
-  stream_rows<K, T, 1, 1, false>(bands, vecs, on ? C.a + K : 0, on ? C.b : 0, pd.n, pd.ld,
-                                 [&](int64_t, const double (&rec)[1][K + 1], const double (&val)[1]) {
-                                   st.row(rec[0], val[0]);
-                                 });
+  VecIn<T> vecs[NV];
+  vecs[0] = {on ? y : nullptr, 0};
+  if constexpr (DIAG) vecs[NV - 1] = {on ? dn : nullptr, 0};
+  stream_rows<K, T, 1, NV, false>(bands, vecs, on ? C.a + K : 0, on ? C.b : 0, pd.n, pd.ld,
+                                  [&](int64_t, const double (&rec)[1][K + 1], const double (&val)[NV]) {
+                                    if constexpr (DIAG) {
+                                      double q[K + 1];
+                                      with_diag<K>(rec[0], val, ds, q);
+                                      st.row(q, val[0]);
+                                    } else {
+                                      st.row(rec[0], val[0]);
+                                    }
+                                  });
   if (on) {
     st.end(m);
     f1_store_map<K>(A.f1map + (int64_t)C.c * A.sw_f1map, m);
   }
 }
 
-template <int K, typename T>
+template <int K, typename T, bool DIAG>
 __global__ void __launch_bounds__(kBlock) k_f1_rep(const Args A, int64_t count) {
+  constexpr int NV = DIAG ? 2 : 1;
   const LaneChunk C = lane_chunk(A, count);
   const ProbDesc &pd = C.pd;
   const bool on = C.active;
   BandP<const T> Q = cband<T>(A.Q, A.Qd, pd);
   const T *y = cvec<T>(A.y, pd);
+  const T *dn = DIAG ? cvec<T>(A.qdn, pd) : nullptr;
+  const double ds = DIAG ? qdiag_scale(A, pd) : 0.0;
   F1State<K> s0;
   if (on && pd.nchunk > 1)
     f1_load_state<K>(A.f1st + (int64_t)C.c * A.sw_f1st, s0);
@@ -87,11 +112,19 @@ __global__ void __launch_bounds__(kBlock) k_f1_rep(const Args A, int64_t count) 
   const bool fuse = A.lmap_out && A.Pc;
   st.begin(s0, band<T>(A.L, A.Ld, pd), y ? vec<T>(A.z, pd) : nullptr, A.Pc != nullptr, fuse);
   BandIn<T> bands[1] = {{on ? Q.p : nullptr, on ? Q.diag : nullptr, 0}};
-  VecIn<T> vecs[1] = {{on ? y : nullptr, 0}};
-  stream_rows<K, T, 1, 1, false>(bands, vecs, on ? C.a : 0, on ? C.b : 0, pd.n, pd.ld,
-                                 [&](int64_t j, const double (&rec)[1][K + 1], const double (&val)[1]) {
-                                   st.row(j, rec[0], val[0]);
-                                 });
+  VecIn<T> vecs[NV];
+  vecs[0] = {on ? y : nullptr, 0};
+  if constexpr (DIAG) vecs[NV - 1] = {on ? dn : nullptr, 0};
+  stream_rows<K, T, 1, NV, false>(bands, vecs, on ? C.a : 0, on ? C.b : 0, pd.n, pd.ld,
+                                  [&](int64_t j, const double (&rec)[1][K + 1], const double (&val)[NV]) {
+                                    if constexpr (DIAG) {
+                                      double q[K + 1];
+                                      with_diag<K>(rec[0], val, ds, q);
+                                      st.row(j, q, val[0]);
+                                    } else {
+                                      st.row(j, rec[0], val[0]);
+                                    }
+                                  });
   if (on) {
     st.end(A.Pc ? A.Pc + (int64_t)C.c * A.sw_mat : nullptr);
     if (fuse) {
@@ -531,8 +564,18 @@ template <typename T> int run_step(int step, const Args &a, int64_t count, hipSt
     return with_item<K, T>(step, l);
   }
   switch (step) {
-    case ST_F1_SUM: hipLaunchKernelGGL((k_f1_sum<K, T>), grid, block, 0, s, a, count); break;
-    case ST_F1_REP: hipLaunchKernelGGL((k_f1_rep<K, T>), grid, block, 0, s, a, count); break;
+    case ST_F1_SUM:
+      if (a.qdn)
+        hipLaunchKernelGGL((k_f1_sum<K, T, true>), grid, block, 0, s, a, count);
+      else
+        hipLaunchKernelGGL((k_f1_sum<K, T, false>), grid, block, 0, s, a, count);
+      break;
+    case ST_F1_REP:
+      if (a.qdn)
+        hipLaunchKernelGGL((k_f1_rep<K, T, true>), grid, block, 0, s, a, count);
+      else
+        hipLaunchKernelGGL((k_f1_rep<K, T, false>), grid, block, 0, s, a, count);
+      break;
     case ST_PC: hipLaunchKernelGGL((k_pc<K, T>), grid, block, 0, s, a, count); break;
     case ST_FS_SUM: hipLaunchKernelGGL((k_fs<K, T, false, false>), grid, block, 0, s, a, count); break;
     case ST_FS_REP:

@@ -139,7 +139,7 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const Args A) {
 constexpr int kProfSlots = bo::ST_COUNT + 21;
 constexpr int kSlotViPre = bo::ST_COUNT + 6, kSlotViPost = bo::ST_COUNT + 7, kSlotViNeg = bo::ST_COUNT + 8;
 constexpr int kSlotSolveMat = bo::ST_COUNT + 9, kSlotSolveMatG = bo::ST_COUNT + 10, kSlotSolveMatOut = bo::ST_COUNT + 11;
-constexpr int kSlotMlPre = bo::ST_COUNT + 12, kSlotMlPost = bo::ST_COUNT + 13, kSlotMlFinal = bo::ST_COUNT + 14;
+constexpr int kSlotMlPost = bo::ST_COUNT + 13, kSlotMlFinal = bo::ST_COUNT + 14;   // + 12: unused
 constexpr int kSlotNgPre = bo::ST_COUNT + 15, kSlotNgPost = bo::ST_COUNT + 16, kSlotNgNeg = bo::ST_COUNT + 17,
               kSlotNgFinal = bo::ST_COUNT + 18;
 struct ProfRec {
@@ -296,7 +296,7 @@ static const char *const kStepNames[kProfSlots] = {
     "b1_replay", "b2_summary", "b2_replay", "asc_group_compose", "asc_group_sweep",
     "asc_chunk_sweep", "desc_group_compose", "desc_group_sweep", "desc_chunk_sweep",
     "clear_partials", "finalize", "wide_f1", "wide_f2", "wide_b1", "wide_b2", "vi_pre", "vi_post", "vi_neg", "solve_mat", "solve_mat_g", "solve_mat_out",
-    "ml_pre", "ml_post", "ml_finalize", "ng_pre", "ng_post", "ng_neg", "ng_finalize", "csr_to_band",
+    "reserved", "ml_post", "ml_finalize", "ng_pre", "ng_post", "ng_neg", "ng_finalize", "csr_to_band",
     "band_to_csr"};
 
 extern "C" int bo_profile_slots(void) { return kProfSlots; }
@@ -798,11 +798,14 @@ extern "C" bo_status bo_plan_marglik(const bo_plan *plan, bo_prec prec, const bo
   prior.Sd = io->Qbard;
   prior.parts = sc;
   prior.info = (int32_t *)(sc + 6 * (size_t)s.nprob);
-  // second forward list: Q1 (written into Sig by pre) with the right-hand side b
+  // second forward list: Q1 = Q + mask / tau2 (added to the diagonal as F1
+  // reads Q) with the right-hand side b
   Args post = Args{};
   bo::bind_sched(s, ws, false, post);
-  post.Q = io->Sig;
-  post.Qd = io->Sigd;
+  post.Q = io->Q;
+  post.Qd = io->Qd;
+  post.qdn = io->mask;
+  post.qdd = io->tau2;
   post.L = io->L;
   post.Ld = io->Ld;
   post.y = io->b;
@@ -812,22 +815,18 @@ extern "C" bo_status bo_plan_marglik(const bo_plan *plan, bo_prec prec, const bo
   post.Sd = io->Sigd;
   post.parts = sc + 3 * (size_t)s.nprob;
   post.info = io->info;
-  const bo_ml::MLP P{io->Q,    io->Qd,   io->mask,   io->b,       io->tau2,  io->Sig,        io->Sigd,
-                     io->Sig,  io->Sigd, io->x,      io->Qbar,    io->Qbard, io->bbar,       io->tau2bar,
-                     io->parts, io->info, prior.parts, post.parts, prior.info};
+  const bo_ml::MLP P{io->Q,     io->Qd,   io->mask,    io->b,      io->tau2,   io->Sig,  io->Sigd,
+                     io->x,     io->Qbar, io->Qbard,   io->bbar,   io->tau2bar, io->parts, io->info,
+                     prior.parts, post.parts, prior.info};
   GpuBE be{stream};
   auto launch = [&](int which, int64_t count, const Args &a, int) -> int {
     if (count <= 0) return 0;
     const dim3 grid((unsigned)count);
-    const int slot = which == 0 ? kSlotMlPre : which == 1 ? kSlotMlPost : kSlotMlFinal;
+    const int slot = which == 1 ? kSlotMlPost : kSlotMlFinal;
     return profiled(slot, stream, [&] {
       const bool f64 = prec == BO_F64;
       const dim3 rows(bo_ml::kRowBlock);
       switch (which) {
-        case 0:
-          if (f64) hipLaunchKernelGGL(bo_ml::k_ml_pre<double>, grid, rows, 0, stream, a, P);
-          else hipLaunchKernelGGL(bo_ml::k_ml_pre<float>, grid, rows, 0, stream, a, P);
-          break;
         case 1:
           if (f64) hipLaunchKernelGGL(bo_ml::k_ml_post<double>, grid, rows, 0, stream, a, P);
           else hipLaunchKernelGGL(bo_ml::k_ml_post<float>, grid, rows, 0, stream, a, P);

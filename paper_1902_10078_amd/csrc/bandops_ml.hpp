@@ -16,10 +16,9 @@
 // (tau2 enters log p through Q1 and through the explicit terms).  A call runs
 // the library's forward list twice, each ending in the per-problem finalize:
 //   1. on Q: L_Q into the L arrays, Sigma0 into the Qbar arrays;
-//   pre:  Q1 = Q + mask / tau2 on the diagonal into the Sigma1 arrays (the
-//         second forward list reads Q1 there before its F2 pass overwrites it);
 //   2. on Q1 with the right-hand side b: L, z = L^{-1} b (kept in the bbar
-//         arrays), Sigma1, x = L^{-T} z;
+//         arrays), Sigma1, x = L^{-T} z.  Q1 is never stored: the F1 pass reads
+//         Q and adds mask_j / tau2 to each diagonal entry as it reads it;
 //   post: Qbar (over Sigma0, element by element), bbar, and per chunk the sums
 //         of mask_i Q1bar_ii, mask_i and b_i^2;
 //   finalize: per problem, log p(Y), its parts and tau2bar from the two forward
@@ -40,8 +39,6 @@ struct MLP {
   const double *Qd;
   const void *mask, *b;   // observation mask and E^T Y (vectors)
   const double *tau2;     // per problem
-  void *Q1;               // Q + mask / tau2, written by pre (the Sigma1 arrays)
-  double *Q1d;
   const void *Sig1;       // I(L) after the second forward list
   const double *Sig1d;
   const void *x;          // Q1^{-1} b
@@ -53,28 +50,6 @@ struct MLP {
   const double *prior_parts, *post_parts;   // the forward lists' finalize parts (3 per problem)
   const int32_t *prior_info;
 };
-
-template <typename T> __global__ void __launch_bounds__(kRowBlock) k_ml_pre(const bo::Args A, const MLP P) {
-  const ChunkRows C = chunk_of_block(A);
-  const bo::ProbDesc &pd = *C.pd;
-  const int64_t ld = pd.ld;
-  const T *q = (const T *)P.Q + pd.boff;
-  const double *qd = P.Qd ? P.Qd + pd.voff : nullptr;
-  const T *mask = (const T *)P.mask + pd.voff;
-  T *q1 = (T *)P.Q1 + pd.boff;
-  double *q1d = P.Q1d ? P.Q1d + pd.voff : nullptr;
-  const double it2 = 1.0 / P.tau2[pd.orig];
-  for (int64_t e = C.a * ld + threadIdx.x; e < C.b * ld; e += kRowBlock) {
-    const int64_t j = e / ld;
-    if (e != j * ld) {
-      q1[e] = q[e];
-      continue;
-    }
-    const double d = (qd ? qd[j] : (double)q[e]) + (double)mask[j] * it2;
-    q1[e] = (T)d;
-    if (q1d) q1d[j] = d;
-  }
-}
 
 template <typename T> __global__ void __launch_bounds__(kRowBlock) k_ml_post(const bo::Args A, const MLP P) {
   __shared__ double sh[kRowBlock];
@@ -170,18 +145,14 @@ __global__ void __launch_bounds__(64) k_ml_finalize(const bo::Args A, const MLP 
 
 // The call's sequence.  `prior` and `post` are the two forward lists' arguments
 // (their parts / info pointing at the plan's per-problem scratch and at the
-// caller's info); `launch(which, count, args, K)` runs 0 = pre, 1 = post,
-// 2 = finalize.
+// caller's info; post carries the diagonal addend mask / tau2);
+// `launch(which, count, args, K)` runs 1 = post, 2 = finalize.
 template <class BE, class Launch>
 int pipe_marglik(BE &be, const bo::Sched &s, const bo::Args &prior, const bo::Args &post, int prec,
                  Launch &&launch) {
   if (int e = bo::pipe_forward(be, s, prior, prec)) return e;
-  bo::Args A = post;
-  for (const bo::KRange &r : s.ranges) {
-    bo::set_range(A, r);
-    if (int e = launch(0, r.c_cnt, A, r.K)) return e;
-  }
   if (int e = bo::pipe_forward(be, s, post, prec)) return e;
+  bo::Args A = post;
   for (const bo::KRange &r : s.ranges) {
     bo::set_range(A, r);
     if (int e = launch(1, r.c_cnt, A, r.K)) return e;

@@ -23,8 +23,10 @@ template <int K, typename T> struct F1SumStep {
   static constexpr int K1 = Dim<K>::K1, NS = Dim<K>::NS;
   double C[NS], Z[NS], X[K1][K1], g[K1], e[K1];
 
-  // Boundary rows a..a+K-1: Q_FF, the coupling of rows a+K.. to F, y_F.
-  BO_HD void begin(int64_t a, int64_t n, BandP<const T> Q, const T *y, F1Map<K> &m) {
+  // Boundary rows a..a+K-1: Q_FF, the coupling of rows a+K.. to F, y_F.  With
+  // dn, dn[j] * ds is added to each Q_jj.
+  BO_HD void begin(int64_t a, int64_t n, BandP<const T> Q, const T *y, F1Map<K> &m,
+                   const T *dn = nullptr, double ds = 0.0) {
 #pragma unroll
     for (int i = 0; i < NS; ++i) C[i] = Z[i] = 0.0;
 #pragma unroll
@@ -37,6 +39,7 @@ template <int K, typename T> struct F1SumStep {
     for (int f = 0; f < K; ++f) {
       double rec[K + 1];
       load_rec<K, T>(Q.p, Q.diag, Q.ld, a + f, n, rec);
+      if (dn) rec[0] += (double)dn[a + f] * ds;
 #pragma unroll
       for (int p = f; p < K; ++p) m.A[p][f] = m.A[f][p] = rec[p - f];
 #pragma unroll
@@ -696,12 +699,13 @@ BO_HD void load_rec_or_zero(BandP<const T> B, int64_t j, int64_t n, double (&r)[
 
 template <int K, typename T>
 BO_HD void f1_summary_chunk(int64_t a, int64_t b, int64_t n, BandP<const T> Q, const T *y,
-                            F1Map<K> &m) {
+                            F1Map<K> &m, const T *dn = nullptr, double ds = 0.0) {
   F1SumStep<K, T> s;
-  s.begin(a, n, Q, y, m);
+  s.begin(a, n, Q, y, m, dn, ds);
   for (int64_t i = a + K; i < b; ++i) {
     double q[K + 1];
     load_rec<K, T>(Q.p, Q.diag, Q.ld, i, n, q);
+    if (dn) q[0] += (double)dn[i] * ds;
     s.row(q, y ? (double)y[i] : 0.0);
   }
   s.end(m);
@@ -710,12 +714,14 @@ BO_HD void f1_summary_chunk(int64_t a, int64_t b, int64_t n, BandP<const T> Q, c
 template <int K, typename T>
 BO_HD int64_t f1_replay_chunk(int64_t a, int64_t b, int64_t n, BandP<const T> Q, BandP<T> L,
                               const T *y, T *z, const F1State<K> &st, double *P,
-                              double &logsum, double &quad, LinMap<K> *f2map = nullptr) {
+                              double &logsum, double &quad, LinMap<K> *f2map = nullptr,
+                              const T *dn = nullptr, double ds = 0.0) {
   F1RepStep<K, T> s;
   s.begin(st, L, y ? z : nullptr, P != nullptr, f2map != nullptr);
   for (int64_t j = a; j < b && s.fail < 0; ++j) {
     double q[K + 1];
     load_rec<K, T>(Q.p, Q.diag, Q.ld, j, n, q);
+    if (dn) q[0] += (double)dn[j] * ds;
     s.row(j, q, y ? (double)y[j] : 0.0);
   }
   s.end(P);

@@ -66,7 +66,6 @@ _KERNEL_SLOTS = [
     (r"k_solve_mat<", "solve_mat"),
     (r"k_solve_mat_g<", "solve_mat_g"),
     (r"k_solve_mat_lbar", "solve_mat_out"),
-    (r"k_ml_pre<", "ml_pre"),
     (r"k_ml_post<", "ml_post"),
     (r"k_ml_finalize", "ml_finalize"),
     (r"k_kl_finalize|k_finalize", "finalize"),
