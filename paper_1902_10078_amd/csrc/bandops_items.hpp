@@ -51,6 +51,7 @@ struct Args {
   const void *yb; const void *zf;     // ybar window and z for the solve term of B2
   double xscale;                      // x <- xscale * L^{-T} b
   double gl;                          // log-determinant sensitivity
+  double gl1;                         // B1: gl1 / L_jj added to each Lbar_jj it writes
   int32_t sb_is_S;                    // B1: Sb holds S of tr(Q^{-1} S)
   int32_t accumulate;                 // B1: add into Lb
   // ---- workspace
@@ -224,7 +225,7 @@ BO_HD void run_pass(const Args &A, const ProbDesc &pd, int64_t a, int64_t b, Lin
     b1_chunk<K, T, REPLAY>(a, b, pd.n, cband<T>(A.L, A.Ld, pd), cband<T>(A.S, A.Sd, pd),
                            cband<T>(A.Sb, A.Sbd, pd), A.sb_is_S != 0, band<T>(A.Lb, A.Lbd, pd),
                            A.accumulate != 0, aux, st, cvec<T>(A.yb, pd), cvec<T>(A.zf, pd), A.gl,
-                           next);
+                           next, A.gl1);
   } else {
     b2_chunk<K, T, REPLAY>(a, b, pd.n, cband<T>(A.L, A.Ld, pd), cband<T>(A.Lb, A.Lbd, pd), A.gl,
                            cvec<T>(A.yb, pd), cvec<T>(A.zf, pd), band<T>(A.Qb, A.Qbd, pd), st);

@@ -263,7 +263,7 @@ __global__ void __launch_bounds__(kBlock) k_b1(const Args A, int64_t count) {
   LinMap<K> st;
   lin_in<K>(A, C, REPLAY, st);
   B1Step<K, T, REPLAY> s;
-  if (on) s.begin(st, C.a, pd.n, Sig, A.sb_is_S != 0, band<T>(A.Lb, A.Lbd, pd), A.accumulate != 0);
+  if (on) s.begin(st, C.a, pd.n, Sig, A.sb_is_S != 0, band<T>(A.Lb, A.Lbd, pd), A.accumulate != 0, A.gl1);
   if constexpr (REPLAY) {
     BandIn<T> bands[3] = {{on ? L.p : nullptr, on ? L.diag : nullptr, 0},
                           {on ? Sb.p : nullptr, on ? Sb.diag : nullptr, 0},

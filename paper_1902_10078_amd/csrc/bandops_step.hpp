@@ -488,6 +488,7 @@ template <int K, typename T, bool REPLAY> struct B1Step {
   double Wb[NS];
   double Sg[K + 1][K + 1];
   double tr;
+  double dgl;   // log-determinant term dgl / L_jj added to each Lbar_jj
   bool sb_is_S, accumulate;
   BandP<T> Lb;
   // fused summary of the descending B2 pass (B2MapAcc), fed with this pass's
@@ -504,10 +505,11 @@ template <int K, typename T, bool REPLAY> struct B1Step {
 
   // Sigma records a .. a+K are read directly (once per chunk).
   BO_HD void begin(const LinMap<K> &st, int64_t a, int64_t n, BandP<const T> Sig, bool sbS,
-                   BandP<T> Lb_, bool acc) {
+                   BandP<T> Lb_, bool acc, double gl1 = 0.0) {
     want_b2 = false;
     sb_is_S = sbS;
     accumulate = acc;
+    dgl = gl1;
     Lb = Lb_;
     tr = 0.0;
 #pragma unroll
@@ -566,6 +568,7 @@ template <int K, typename T, bool REPLAY> struct B1Step {
         o[p + 1] = (j + 1 + p < n) ? acc * inv : 0.0;
       }
       o[0] = -2.0 * Sbjj * inv * inv * inv - dot * inv;
+      o[0] += dgl * inv;
       if (accumulate) {
         double old[K + 1];
         load_rec<K, T>((const T *)Lb.p, Lb.diag, Lb.ld, j, n, old);
@@ -791,9 +794,9 @@ template <int K, typename T, bool REPLAY>
 BO_HD void b1_chunk(int64_t a, int64_t b, int64_t n, BandP<const T> L, BandP<const T> Sig,
                     BandP<const T> Sb, bool sb_is_S, BandP<T> Lb, bool accumulate,
                     double &trace, LinMap<K> &st, const T *ybar = nullptr, const T *z = nullptr,
-                    double gl = 0.0, LinMap<K> *b2map = nullptr) {
+                    double gl = 0.0, LinMap<K> *b2map = nullptr, double gl1 = 0.0) {
   B1Step<K, T, REPLAY> s;
-  s.begin(st, a, n, Sig, sb_is_S, Lb, accumulate);
+  s.begin(st, a, n, Sig, sb_is_S, Lb, accumulate, gl1);
   if (REPLAY && b2map) s.begin_b2(a, n, ybar, gl);
   for (int64_t j = a; j < b; ++j) {
     double r[K + 1], sb[K + 1], ah[K + 1];

@@ -12,7 +12,8 @@
 //         B1 pass weighs a stored off-diagonal entry twice, as it stands for
 //         two entries), v = L_p^T (m_p - m_q), and per chunk the sums of
 //         log[L_q]_jj - log[L_p]_jj and of v_j^2;
-//   post: Lqbar_jj += 1/[L_q]_jj (log term); Lpbar = band(I(L_q) L_p) (the
+//   (B1 adds the log term 1/[L_q]_jj to each Lqbar_jj as it writes it)
+//   post: Lpbar = band(I(L_q) L_p) (the
 //         trace term: the symmetric band of I(L_q) suffices on the band of
 //         L_p) + d v^T on the band (d = m_p - m_q) - 1/[L_p]_jj on the
 //         diagonal; mpbar = L_p v;
@@ -172,15 +173,12 @@ template <typename T> __global__ void __launch_bounds__(kRowBlock) k_kl_post(con
   double *sd = sS + TL * W;            // d on [t0, t1 + k)
   double *sv = sd + TL;                // v on [t0 - k, t1)
   const int64_t n = pd.n, ld = pd.ld;
-  const LB<T> Lq{(const T *)A.L + pd.boff, A.Ld ? A.Ld + pd.voff : nullptr, ld};
   const T *Lp = (const T *)P.Lp + pd.boff;
   const double *Lpd = P.Lpd ? P.Lpd + pd.voff : nullptr;
   const T *Sg = (const T *)A.S + pd.boff;
   const double *Sgd = A.Sd ? A.Sd + pd.voff : nullptr;
   const T *mq = (const T *)P.mq + pd.voff, *mp = (const T *)P.mp + pd.voff;
   const T *v = (const T *)P.mqbar + pd.voff;
-  T *lqb = (T *)A.Lb + pd.boff;
-  double *lqbd = A.Lbd ? A.Lbd + pd.voff : nullptr;
   T *lpb = (T *)P.Lpbar + pd.boff;
   double *lpbd = P.Lpbard ? P.Lpbard + pd.voff : nullptr;
   T *mpb = (T *)P.mpbar + pd.voff;
@@ -200,10 +198,6 @@ template <typename T> __global__ void __launch_bounds__(kRowBlock) k_kl_post(con
       auto sg = [&](int64_t r, int64_t m) {   // symmetric: element (r, m) from the stored lower band
         return r >= m ? sS[(m - t0) * W + (r - m)] : sS[(r - t0) * W + (m - r)];
       };
-      // log-determinant term of L_q
-      const double g0 = (lqbd ? lqbd[j] : (double)lqb[j * ld]) + 1.0 / Lq.at(j, j);
-      lqb[j * ld] = (T)g0;
-      if (lqbd) lqbd[j] = g0;
       // L_p: trace, squared-norm and log terms
       const double vj = sv[j - (t0 - K)];
       const int64_t m1 = (j + K < n - 1) ? j + K : n - 1;
@@ -277,7 +271,7 @@ __global__ void __launch_bounds__(64) k_kl_finalize(const bo::Args A, double *pa
 
 // The whole term: clear, pre, chunk products of L_q, F2 (I(L_q), with the B1
 // chunk maps fused in for k <= KMAX_FUSED), B1 (Algorithm 4 with Sigmabar =
-// Q_p / 2 and its trace), post, neg, finalize.  A carries the schedule, L =
+// Q_p / 2 and its trace, plus the log term of L_q), post, neg, finalize.  A carries the schedule, L =
 // L_q, S = Sig, Sb = Lpbar (Q_p / 2), Lb = Lqbar; `launch(which, grid,
 // range, k)` runs pre (0), post (1), neg (2) or finalize (3).
 template <class BE, class Launch>
@@ -300,6 +294,7 @@ int pipe_vi_kl(BE &be, const bo::Sched &s, bo::Args A, int prec, Launch &&launch
   bo::Args B1 = A;
   B1.lmap = A.lmap2;
   B1.lmap_out = nullptr;
+  B1.gl1 = 1.0;   // the log term of L_q, added as B1 writes Lqbar
   if (int e = bo::seq_lin(be, s, B1, prec, bo::PASS_B1, true)) return e;
   for (int which = 1; which <= 2; ++which)
     for (const bo::KRange &r : s.ranges) {
