@@ -107,7 +107,7 @@ def vi_bytes_per_row(k: int, prec: int):
             "f2_replay": 3 * wb,                     # L_q, Q_p / 2 -> Sigma
             "b1_summary": 2 * wb,                    # L_q, Q_p / 2
             "b1_replay": 4 * wb,                     # L_q, Sigma, Q_p / 2 -> Lqbar
-            "vi_post": 4 * wb + 24 + 4 * wv,         # L_p, Sigma, diags, m_q, m_p, v -> Lpbar, mpbar
+            "vi_post": 3 * wb + 4 * wv,              # L_p, Sigma, m_q, m_p, v -> Lpbar, mpbar
             "vi_neg": 2 * wv,                        # mpbar -> mqbar
             "unit": 5 * wb + 4 * wv}                 # inputs L_q, L_p, m_q, m_p; outputs Sigma and the gradients
 
