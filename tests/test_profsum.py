@@ -14,8 +14,10 @@ KERN = os.path.join(HERE, "..", "paper_1902_10078_amd", "csrc", "bandops_kern.hi
 
 # template name and its boolean arguments -> slot
 EXPECTED = {
-    ("k_f1_sum", ()): "f1_summary",
-    ("k_f1_rep", ()): "f1_replay",
+    ("k_f1_sum", ("false",)): "f1_summary",
+    ("k_f1_sum", ("true",)): "f1_summary",
+    ("k_f1_rep", ("false",)): "f1_replay",
+    ("k_f1_rep", ("true",)): "f1_replay",
     ("k_pc", ()): "chunk_product",
     ("k_fs", ("false", "false")): "fs_summary",
     ("k_fs", ("true", "false")): "fs_replay",
