@@ -635,7 +635,7 @@ class GraphWorkload:
     CSR values, runs the whitened sample and its reverse mode over the batch,
     and gathers the band gradients back to the CSR values."""
 
-    def __init__(self, bo, torch, dev, host_inputs, prec):
+    def __init__(self, bo, torch, dev, host_inputs, prec, target_chunks=0):
         self.bo, self.prec = bo, prec
         g = host_inputs
         n, k, nb = g["n"], g["k"], len(g["vals"])
@@ -658,7 +658,7 @@ class GraphWorkload:
         self.kw = kw
         self.gvals = torch.zeros_like(self.vals)
         self.dropped = torch.zeros(1, dtype=torch.int64, device=dev)
-        self.plan = bo.Plan([n] * nb, [k] * nb, device=dev)
+        self.plan = bo.Plan([n] * nb, [k] * nb, target_chunks=target_chunks, device=dev)
         self.io = self.plan.wh_io(reuse=True, **kw)   # backward right after forward
 
     def step(self):
@@ -1026,7 +1026,7 @@ def main():
     log(f"inputs: {len(ns)} problems, {rows} rows ({time.perf_counter() - t0:.1f} s)")
 
     if gr:
-        W = GraphWorkload(bo, torch, dev, host_inputs, prec)
+        W = GraphWorkload(bo, torch, dev, host_inputs, prec, args.target_chunks)
     elif wide:
         W = WideWorkload(bo, torch, dev, ns, host_inputs)
         log(f"wide plan: {W.stats}, workspace {W.plan.ws.numel() / 2**20:.1f} MiB")
