@@ -393,6 +393,7 @@ template <int K, typename T, bool REPLAY> struct F2Step {
   }
 };
 
+// ============================================ B2 chunk maps, accumulated upwards
 // Ascending accumulation of the chunk map of the descending B2 pass: the
 // zero-state run of B2 over a chunk is M = sum_j R_j^T inj2_j R_j with
 // R_j = Kt_{j-1} ... Kt_a and inj2_j the B2 injection of the total
@@ -482,7 +483,8 @@ template <int K> struct B2MapAcc {
 // The replay keeps the K+1 Sigma records j .. j+K in registers (Sg[i] =
 // record j+i) and takes record j+K+1 with each row.  With sb_is_S the
 // sensitivity is (S_jj, 2 S_{j+1,j}, ...) from the band S of tr(Q^{-1} S), and
-// sum_j Sigma_jj S_jj + 2 sum Sigma_ij S_ij is accumulated.
+// sum_j Sigma_jj S_jj + 2 sum Sigma_ij S_ij is accumulated.  A log-determinant
+// term dgl / L_jj can be added to each Lbar_jj as it is written.
 template <int K, typename T, bool REPLAY> struct B1Step {
   static constexpr int K1 = Dim<K>::K1, NS = Dim<K>::NS;
   double Wb[NS];
