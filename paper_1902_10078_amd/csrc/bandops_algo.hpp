@@ -30,6 +30,13 @@
 
 namespace bo {
 
+// Largest bandwidth whose replays also produce the next pass's chunk maps.
+// Above it the fused replay kernels no longer fit in registers (they spill)
+// and gave wrong next-pass maps on gfx950 while the same code is exact on the
+// host; those bandwidths run separate summary kernels instead, and their
+// steppers and kernels are compiled without the fused accumulations.
+constexpr int KMAX_FUSED = 5;
+
 template <int K> struct Dim {
   static constexpr int K1 = K > 0 ? K : 1;                 // array extent
   static constexpr int NS = K > 0 ? K * (K + 1) / 2 : 1;   // packed symmetric

@@ -26,11 +26,6 @@ enum Step : int {
 
 // Bandwidths with compiled kernels.
 constexpr int KMAX_SUPPORTED = 12;
-// Largest bandwidth whose replays also produce the next pass's chunk maps.
-// Above it the fused replay kernels no longer fit in registers (they spill)
-// and gave wrong next-pass maps on gfx950 while the same code is exact on the
-// host; those bandwidths run separate summary kernels instead.
-constexpr int KMAX_FUSED = 5;
 
 struct KRange {
   int K;

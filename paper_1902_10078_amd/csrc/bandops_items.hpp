@@ -183,7 +183,7 @@ template <int K, typename T> struct F1Replay {
       f1_zero_state<K>(s);
     double ls = 0.0, qs = 0.0;
     LinMap<K> f2m;
-    const bool fuse = A.lmap_out && A.Pc;
+    const bool fuse = K <= KMAX_FUSED && A.lmap_out && A.Pc;
     int64_t fail = f1_replay_chunk<K, T>(a, b, pd.n, cband<T>(A.Q, A.Qd, pd), band<T>(A.L, A.Ld, pd),
                                          cvec<T>(A.y, pd), vec<T>(A.z, pd), s,
                                          A.Pc ? A.Pc + (int64_t)c * A.sw_mat : nullptr, ls, qs,
@@ -259,7 +259,7 @@ template <int K, typename T, int PASS> struct LinReplay {
       lin_zero<K>(st);
     double aux;
     LinMap<K> nm;
-    const bool fuse = A.lmap_out && (PASS == PASS_FS || PASS == PASS_F2 || PASS == PASS_B1);
+    const bool fuse = K <= KMAX_FUSED && A.lmap_out && (PASS == PASS_FS || PASS == PASS_F2 || PASS == PASS_B1);
     run_pass<K, T, PASS, true>(A, pd, a, b, st, aux, fuse ? &nm : nullptr);
     if (fuse) lin_store<K>(A.lmap_out + (int64_t)c * A.sw_lin, nm);
     if (PASS == PASS_B1) A.part[4 * (int64_t)c + 2] = aux;

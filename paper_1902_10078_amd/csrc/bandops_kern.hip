@@ -109,7 +109,7 @@ __global__ void __launch_bounds__(kBlock) k_f1_rep(const Args A, int64_t count) 
   else
     f1_zero_state<K>(s0);
   F1RepStep<K, T> st;
-  const bool fuse = A.lmap_out && A.Pc;
+  const bool fuse = K <= KMAX_FUSED && A.lmap_out && A.Pc;
   st.begin(s0, band<T>(A.L, A.Ld, pd), y ? vec<T>(A.z, pd) : nullptr, A.Pc != nullptr, fuse);
   BandIn<T> bands[1] = {{on ? Q.p : nullptr, on ? Q.diag : nullptr, 0}};
   VecIn<T> vecs[NV];
@@ -262,7 +262,7 @@ __global__ void __launch_bounds__(kBlock) k_b1(const Args A, int64_t count) {
   BandP<const T> Sb = cband<T>(A.Sb, A.Sbd, pd);
   LinMap<K> st;
   lin_in<K>(A, C, REPLAY, st);
-  B1Step<K, T, REPLAY> s;
+  B1Step<K, T, REPLAY, FUSE> s;
   if (on) s.begin(st, C.a, pd.n, Sig, A.sb_is_S != 0, band<T>(A.Lb, A.Lbd, pd), A.accumulate != 0, A.gl1);
   if constexpr (REPLAY) {
     BandIn<T> bands[3] = {{on ? L.p : nullptr, on ? L.diag : nullptr, 0},
@@ -579,24 +579,30 @@ template <typename T> int run_step(int step, const Args &a, int64_t count, hipSt
     case ST_PC: hipLaunchKernelGGL((k_pc<K, T>), grid, block, 0, s, a, count); break;
     case ST_FS_SUM: hipLaunchKernelGGL((k_fs<K, T, false, false>), grid, block, 0, s, a, count); break;
     case ST_FS_REP:
-      if (a.lmap_out)
-        hipLaunchKernelGGL((k_fs<K, T, true, true>), grid, block, 0, s, a, count);
-      else
-        hipLaunchKernelGGL((k_fs<K, T, true, false>), grid, block, 0, s, a, count);
+      if constexpr (K <= KMAX_FUSED)
+        if (a.lmap_out) {
+          hipLaunchKernelGGL((k_fs<K, T, true, true>), grid, block, 0, s, a, count);
+          break;
+        }
+      hipLaunchKernelGGL((k_fs<K, T, true, false>), grid, block, 0, s, a, count);
       break;
     case ST_F2_SUM: hipLaunchKernelGGL((k_f2<K, T, false, false>), grid, block, 0, s, a, count); break;
     case ST_F2_REP:
-      if (a.lmap_out && a.Sb)
-        hipLaunchKernelGGL((k_f2<K, T, true, true>), grid, block, 0, s, a, count);
-      else
-        hipLaunchKernelGGL((k_f2<K, T, true, false>), grid, block, 0, s, a, count);
+      if constexpr (K <= KMAX_FUSED)
+        if (a.lmap_out && a.Sb) {
+          hipLaunchKernelGGL((k_f2<K, T, true, true>), grid, block, 0, s, a, count);
+          break;
+        }
+      hipLaunchKernelGGL((k_f2<K, T, true, false>), grid, block, 0, s, a, count);
       break;
     case ST_B1_SUM: hipLaunchKernelGGL((k_b1<K, T, false, false>), grid, block, 0, s, a, count); break;
     case ST_B1_REP:
-      if (a.lmap_out)
-        hipLaunchKernelGGL((k_b1<K, T, true, true>), grid, block, 0, s, a, count);
-      else
-        hipLaunchKernelGGL((k_b1<K, T, true, false>), grid, block, 0, s, a, count);
+      if constexpr (K <= KMAX_FUSED)
+        if (a.lmap_out) {
+          hipLaunchKernelGGL((k_b1<K, T, true, true>), grid, block, 0, s, a, count);
+          break;
+        }
+      hipLaunchKernelGGL((k_b1<K, T, true, false>), grid, block, 0, s, a, count);
       break;
     case ST_B2_SUM: hipLaunchKernelGGL((k_b2<K, T, false>), grid, block, 0, s, a, count); break;
     case ST_B2_REP: hipLaunchKernelGGL((k_b2<K, T, true>), grid, block, 0, s, a, count); break;

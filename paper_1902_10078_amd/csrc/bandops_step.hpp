@@ -116,7 +116,7 @@ template <int K, typename T> struct F1RepStep {
     L = L_;
     z = z_;
     want_P = wantP;
-    want_f2 = wantP && wantF2;
+    want_f2 = K <= KMAX_FUSED && wantP && wantF2;
     ls = qs = 0.0;
     fail = -1;
 #pragma unroll
@@ -172,7 +172,7 @@ template <int K, typename T> struct F1RepStep {
       for (int h = 0; h <= p; ++h)
         C[six(p, h)] = ((p + 1 < K) ? C[six(p + 1, h + 1)] : 0.0) + l[p] * l[h];
     if (want_P) {
-      if (want_f2) {
+      if (K <= KMAX_FUSED && want_f2) {
         // row 0 of R_j = Pm before this row's update
         const double cj = inv * inv, xj = (z ? zj : yj) * inv;
 #pragma unroll
@@ -485,7 +485,7 @@ template <int K> struct B2MapAcc {
 // sensitivity is (S_jj, 2 S_{j+1,j}, ...) from the band S of tr(Q^{-1} S), and
 // sum_j Sigma_jj S_jj + 2 sum Sigma_ij S_ij is accumulated.  A log-determinant
 // term dgl / L_jj can be added to each Lbar_jj as it is written.
-template <int K, typename T, bool REPLAY> struct B1Step {
+template <int K, typename T, bool REPLAY, bool B2MAP = true> struct B1Step {
   static constexpr int K1 = Dim<K>::K1, NS = Dim<K>::NS;
   double Wb[NS];
   double Sg[K + 1][K + 1];
@@ -494,7 +494,7 @@ template <int K, typename T, bool REPLAY> struct B1Step {
   bool sb_is_S, accumulate;
   BandP<T> Lb;
   // fused summary of the descending B2 pass (B2MapAcc), fed with this pass's
-  // Lbar record of each row.
+  // Lbar record of each row (compiled in with B2MAP, for K <= KMAX_FUSED).
   bool want_b2;
   B2MapAcc<K> b2;
 
@@ -578,7 +578,7 @@ template <int K, typename T, bool REPLAY> struct B1Step {
         for (int d = 0; d <= K; ++d) o[d] += old[d];
       }
       store_rec<K, T>(Lb.p, Lb.diag, Lb.ld, j, o);
-      if (want_b2) b2.row(r, inv, o, zj, yahead);
+      if (B2MAP && K <= KMAX_FUSED && want_b2) b2.row(r, inv, o, zj, yahead);
 #pragma unroll
       for (int i = 0; i < K; ++i)
 #pragma unroll
