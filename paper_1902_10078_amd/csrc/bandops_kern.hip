@@ -304,8 +304,12 @@ __global__ void __launch_bounds__(kBlock) k_b1(const Args A, int64_t count) {
   }
 }
 
-template <int K, typename T, bool REPLAY>
+// WITH_LB: an incoming Lbar band is staged next to L.  Without one (the
+// whitened sample's reverse mode) only L is staged, so its tiles hold twice
+// the rows.
+template <int K, typename T, bool REPLAY, bool WITH_LB>
 __global__ void __launch_bounds__(kBlock) k_b2(const Args A, int64_t count) {
+  constexpr int NB = WITH_LB ? 2 : 1;
   const LaneChunk C = lane_chunk(A, count);
   const ProbDesc &pd = C.pd;
   const bool on = C.active && (REPLAY || pd.nchunk > 1);
@@ -317,13 +321,19 @@ __global__ void __launch_bounds__(kBlock) k_b2(const Args A, int64_t count) {
   lin_in<K>(A, C, REPLAY, st);
   B2Step<K, T, REPLAY> s;
   s.begin(st, C.b, pd.n, on ? yb : nullptr, A.gl, band<T>(A.Qb, A.Qbd, pd));
-  BandIn<T> bands[2] = {{on ? L.p : nullptr, on ? L.diag : nullptr, 0},
-                        {on ? Lb.p : nullptr, on ? Lb.diag : nullptr, 0}};
+  BandIn<T> bands[NB];
+  bands[0] = {on ? L.p : nullptr, on ? L.diag : nullptr, 0};
+  if constexpr (WITH_LB) bands[NB - 1] = {on ? Lb.p : nullptr, on ? Lb.diag : nullptr, 0};
   VecIn<T> vecs[2] = {{on ? yb : nullptr, 0}, {on ? zf : nullptr, 0}};
-  stream_rows<K, T, 2, 2, true>(bands, vecs, on ? C.a : 0, on ? C.b : 0, pd.n, pd.ld,
-                                [&](int64_t j, const double (&rec)[2][K + 1], const double (&val)[2]) {
-                                  s.row(j, pd.n, rec[0], rec[1], val[0], val[1]);
-                                });
+  stream_rows<K, T, NB, 2, true>(bands, vecs, on ? C.a : 0, on ? C.b : 0, pd.n, pd.ld,
+                                 [&](int64_t j, const double (&rec)[NB][K + 1], const double (&val)[2]) {
+                                   if constexpr (WITH_LB) {
+                                     s.row(j, pd.n, rec[0], rec[NB - 1], val[0], val[1]);
+                                   } else {
+                                     const double none[K + 1] = {};
+                                     s.row(j, pd.n, rec[0], none, val[0], val[1]);
+                                   }
+                                 });
   if (on && !REPLAY) {
     s.end(st);
     lin_store<K>(A.lmap + (int64_t)C.c * A.sw_lin, st);
@@ -604,8 +614,18 @@ template <typename T> int run_step(int step, const Args &a, int64_t count, hipSt
         }
       hipLaunchKernelGGL((k_b1<K, T, true, false>), grid, block, 0, s, a, count);
       break;
-    case ST_B2_SUM: hipLaunchKernelGGL((k_b2<K, T, false>), grid, block, 0, s, a, count); break;
-    case ST_B2_REP: hipLaunchKernelGGL((k_b2<K, T, true>), grid, block, 0, s, a, count); break;
+    case ST_B2_SUM:
+      if (a.Lb)
+        hipLaunchKernelGGL((k_b2<K, T, false, true>), grid, block, 0, s, a, count);
+      else
+        hipLaunchKernelGGL((k_b2<K, T, false, false>), grid, block, 0, s, a, count);
+      break;
+    case ST_B2_REP:
+      if (a.Lb)
+        hipLaunchKernelGGL((k_b2<K, T, true, true>), grid, block, 0, s, a, count);
+      else
+        hipLaunchKernelGGL((k_b2<K, T, true, false>), grid, block, 0, s, a, count);
+      break;
     default: {
       Launch<T> l{a, count, s};
       return with_item<K, T>(step, l);

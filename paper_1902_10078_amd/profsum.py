@@ -36,8 +36,8 @@ _KERNEL_SLOTS = [
     (r"k_f2<\d+, \w+, true", "f2_replay"),
     (r"k_b1<\d+, \w+, false", "b1_summary"),
     (r"k_b1<\d+, \w+, true", "b1_replay"),
-    (r"k_b2<\d+, \w+, false>", "b2_summary"),
-    (r"k_b2<\d+, \w+, true>", "b2_replay"),
+    (r"k_b2<\d+, \w+, false", "b2_summary"),
+    (r"k_b2<\d+, \w+, true", "b2_replay"),
     (r"k_f1_gscan", "f1_group_compose"),
     (r"k_f1_pscan", "f1_group_sweep"),
     (r"k_f1_capply", "f1_chunk_sweep"),

@@ -28,8 +28,10 @@ EXPECTED = {
     ("k_b1", ("false", "false")): "b1_summary",
     ("k_b1", ("true", "false")): "b1_replay",
     ("k_b1", ("true", "true")): "b1_replay",
-    ("k_b2", ("false",)): "b2_summary",
-    ("k_b2", ("true",)): "b2_replay",
+    ("k_b2", ("false", "false")): "b2_summary",
+    ("k_b2", ("false", "true")): "b2_summary",
+    ("k_b2", ("true", "false")): "b2_replay",
+    ("k_b2", ("true", "true")): "b2_replay",
     ("k_f1_gscan", ()): "f1_group_compose",
     ("k_f1_pscan", ()): "f1_group_sweep",
     ("k_f1_capply", ()): "f1_chunk_sweep",
