@@ -86,22 +86,28 @@ __device__ __forceinline__ ChunkRows chunk_of_block(const bo::Args &A) {
 constexpr int kMaxW = 13;   // record length at the widest compiled k
 
 // Records [r0, r1) of a band (clipped to [0, n)) into dst[(r - r0) * W + s].
+// A tile spans at most kRowBlock + k records, so offsets inside it are 32-bit.
 template <typename T>
 __device__ __forceinline__ void stage_band(double *dst, const T *rec, const double *diag, int64_t r0, int64_t r1,
                                            int64_t n, int W) {
   const int64_t lo = r0 > 0 ? r0 : 0, hi = r1 < n ? r1 : n;
-  const int skip = (int)(lo - r0);
-  for (int64_t e = threadIdx.x; e < (hi - lo) * W; e += kRowBlock)
-    if (!(diag && e % W == 0)) dst[skip * W + e] = (double)rec[lo * W + e];
+  if (hi <= lo) return;
+  const int skip = (int)(lo - r0), rows = (int)(hi - lo), cnt = rows * W;
+  const T *src = rec + lo * W;
+  double *d = dst + skip * W;
+  for (int e = threadIdx.x; e < cnt; e += kRowBlock)
+    if (!(diag && e % W == 0)) d[e] = (double)src[e];
   if (diag)
-    for (int64_t r = lo + threadIdx.x; r < hi; r += kRowBlock) dst[(r - r0) * W] = diag[r];
+    for (int r = threadIdx.x; r < rows; r += kRowBlock) d[r * W] = diag[lo + r];
 }
 // src[(r - r0) * W + s] into records [r0, r1) of a band (and its FP64 diagonal).
 template <typename T>
 __device__ __forceinline__ void store_band(T *rec, double *diag, const double *src, int64_t r0, int64_t r1, int W) {
-  for (int64_t e = threadIdx.x; e < (r1 - r0) * W; e += kRowBlock) rec[r0 * W + e] = (T)src[e];
+  const int rows = (int)(r1 - r0), cnt = rows * W;
+  T *dst = rec + r0 * W;
+  for (int e = threadIdx.x; e < cnt; e += kRowBlock) dst[e] = (T)src[e];
   if (diag)
-    for (int64_t r = r0 + threadIdx.x; r < r1; r += kRowBlock) diag[r] = src[(r - r0) * W];
+    for (int r = threadIdx.x; r < rows; r += kRowBlock) diag[r0 + r] = src[r * W];
 }
 
 // LDS of the row kernels for records of W elements (launch size, bytes).
@@ -135,22 +141,25 @@ template <typename T> __global__ void __launch_bounds__(kRowBlock) k_kl_pre(cons
     for (int64_t r = t0 + threadIdx.x; r < t1 + K; r += kRowBlock)
       sd[r - t0] = r < n ? (double)mp[r] - (double)mq[r] : 0.0;
     __syncthreads();
-    const int64_t j = t0 + threadIdx.x;
+    const int jl = threadIdx.x;   // rows and columns below are offsets from t0
+    const int64_t j = t0 + jl;
     if (j < t1) {
-      // element (r, m) of L_p, m in [t0 - k, t1)
-      auto lp = [&](int64_t r, int64_t m) { return sLp[(m - (t0 - K)) * W + (r - m)]; };
+      const int nl = (int)(n - t0 < 2 * kRowBlock ? n - t0 : 2 * kRowBlock);   // rows at or past nl are beyond n
+      const int ml0 = -(int)(t0 < K ? t0 : K);                                // first column offset >= row 0
+      // element (r, m) of L_p, m - t0 in [-k, t1 - t0)
+      auto lp = [&](int r, int m) { return sLp[(m + K) * W + (r - m)]; };
       for (int s = 0; s < W; ++s) {
-        const int64_t i = j + s;
+        const int il = jl + s;
         double q = 0.0;   // (L_p L_p^T)_ij over the columns both rows reach
-        if (i < n)
-          for (int64_t m = (i - K > 0 ? i - K : 0); m <= j; ++m) q += lp(i, m) * lp(j, m);
-        sQ[threadIdx.x * W + s] = 0.5 * q;
+        if (il < nl)
+          for (int m = (il - K > ml0 ? il - K : ml0); m <= jl; ++m) q += lp(il, m) * lp(jl, m);
+        sQ[jl * W + s] = 0.5 * q;
       }
       double vj = 0.0;
-      for (int s = 0; s < W && j + s < n; ++s) vj += lp(j + s, j) * sd[j + s - t0];
+      for (int s = 0; s < W && jl + s < nl; ++s) vj += lp(jl + s, jl) * sd[jl + s];
       v[j] = (T)vj;
       vsum += vj * vj;
-      lsum += log(Lq.at(j, j)) - log(lp(j, j));
+      lsum += log(Lq.at(j, j)) - log(lp(jl, jl));
     }
     __syncthreads();
     store_band(sb, sbd, sQ, t0, t1, W);
@@ -172,7 +181,7 @@ template <typename T> __global__ void __launch_bounds__(kRowBlock) k_kl_post(con
   double *sS = sLp + TL * W;           // Sigma records [t0, t1 + k); reused for the Lpbar output
   double *sd = sS + TL * W;            // d on [t0, t1 + k)
   double *sv = sd + TL;                // v on [t0 - k, t1)
-  const int64_t n = pd.n, ld = pd.ld;
+  const int64_t n = pd.n;
   const T *Lp = (const T *)P.Lp + pd.boff;
   const double *Lpd = P.Lpd ? P.Lpd + pd.voff : nullptr;
   const T *Sg = (const T *)A.S + pd.boff;
@@ -191,34 +200,37 @@ template <typename T> __global__ void __launch_bounds__(kRowBlock) k_kl_post(con
       sd[r - t0] = r < n ? (double)mp[r] - (double)mq[r] : 0.0;
     for (int64_t r = t0 - K + threadIdx.x; r < t1; r += kRowBlock) sv[r - (t0 - K)] = r >= 0 ? (double)v[r] : 0.0;
     __syncthreads();
-    const int64_t j = t0 + threadIdx.x;
+    const int jl = threadIdx.x;   // rows and columns below are offsets from t0
+    const int64_t j = t0 + jl;
     double g[kMaxW];
     if (j < t1) {
-      auto lp = [&](int64_t r, int64_t m) { return sLp[(m - (t0 - K)) * W + (r - m)]; };
-      auto sg = [&](int64_t r, int64_t m) {   // symmetric: element (r, m) from the stored lower band
-        return r >= m ? sS[(m - t0) * W + (r - m)] : sS[(r - t0) * W + (m - r)];
+      const int nl = (int)(n - t0 < 2 * kRowBlock ? n - t0 : 2 * kRowBlock);   // rows at or past nl are beyond n
+      const int ml0 = -(int)(t0 < K ? t0 : K);                                // first column offset >= row 0
+      auto lp = [&](int r, int m) { return sLp[(m + K) * W + (r - m)]; };
+      auto sg = [&](int r, int m) {   // symmetric: element (r, m) from the stored lower band
+        return r >= m ? sS[m * W + (r - m)] : sS[r * W + (m - r)];
       };
       // L_p: trace, squared-norm and log terms
-      const double vj = sv[j - (t0 - K)];
-      const int64_t m1 = (j + K < n - 1) ? j + K : n - 1;
+      const double vj = sv[jl + K];
+      const int m1 = (jl + K < nl - 1) ? jl + K : nl - 1;
       for (int s = 0; s < W; ++s) {
-        const int64_t i = j + s;
+        const int il = jl + s;
         double a = 0.0;
-        if (i < n) {
-          for (int64_t m = j; m <= m1; ++m) a += sg(i, m) * lp(m, j);
-          a += sd[i - t0] * vj;
-          if (s == 0) a -= 1.0 / lp(j, j);
+        if (il < nl) {
+          for (int m = jl; m <= m1; ++m) a += sg(il, m) * lp(m, jl);
+          a += sd[il] * vj;
+          if (s == 0) a -= 1.0 / lp(jl, jl);
         }
         g[s] = a;
       }
       // means: L_p v
       double mb = 0.0;
-      for (int64_t m = (j - K > 0 ? j - K : 0); m <= j; ++m) mb += lp(j, m) * sv[m - (t0 - K)];
+      for (int m = (jl - K > ml0 ? jl - K : ml0); m <= jl; ++m) mb += lp(jl, m) * sv[m + K];
       mpb[j] = (T)mb;
     }
     __syncthreads();   // every read of sS is done: reuse it for the output records
     if (j < t1)
-      for (int s = 0; s < W; ++s) sS[threadIdx.x * W + s] = g[s];
+      for (int s = 0; s < W; ++s) sS[jl * W + s] = g[s];
     __syncthreads();
     store_band(lpb, lpbd, sS, t0, t1, W);
   }
