@@ -67,9 +67,12 @@ template <typename T> __global__ void __launch_bounds__(kRowBlock) k_ml_post(con
   const double it2 = 1.0 / P.tau2[pd.orig], it4 = it2 * it2;
   // Qbar record entries: consecutive threads take consecutive entries; each
   // entry of I(L_Q) is read and replaced by the same thread
-  for (int64_t e = C.a * ld + threadIdx.x; e < C.b * ld; e += kRowBlock) {
-    const int64_t j = e / ld;
-    const int s = (int)(e - j * ld);
+  // element e = j * ld + s: (j, s) advance with e, so no element is divided by ld
+  const int ldi = (int)ld, dj = kRowBlock / ldi, ds = kRowBlock % ldi;
+  int64_t j = C.a + (int)threadIdx.x / ldi;
+  int s = (int)threadIdx.x % ldi;
+  for (int64_t e = C.a * ld + threadIdx.x; e < C.b * ld; e += kRowBlock, j += dj, s += ds) {
+    if (s >= ldi) { s -= ldi; ++j; }
     const int64_t i = j + s;
     double g = 0.0;
     if (s <= K && i < n) {

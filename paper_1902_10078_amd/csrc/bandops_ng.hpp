@@ -67,15 +67,21 @@ template <typename T> __global__ void __launch_bounds__(kRowBlock) k_ng_pre(cons
   const double *prd = P.Lprd ? P.Lprd + pd.voff : nullptr, *lkd = P.Llikd ? P.Llikd + pd.voff : nullptr;
   T *po = (T *)P.Lpo + pd.boff;
   double *pod = P.Lpod ? P.Lpod + pd.voff : nullptr;
+  // element e = j * ld + s: (j, s) advance with e, so no element is divided by ld
+  const int ldi = (int)ld, dj = kRowBlock / ldi, ds = kRowBlock % ldi;
+  int64_t j = C.a + (int)threadIdx.x / ldi;
+  int s = (int)threadIdx.x % ldi;
   for (int64_t e = C.a * ld + threadIdx.x; e < C.b * ld; e += kRowBlock) {
-    const int64_t j = e / ld;
-    if (e != j * ld || !pod) {
+    if (s != 0 || !pod) {
       po[e] = (T)((double)pr[e] + (double)lk[e]);
-      continue;
+    } else {
+      const double d = prd[j] + lkd[j];
+      po[e] = (T)d;
+      pod[j] = d;
     }
-    const double d = prd[j] + lkd[j];
-    po[e] = (T)d;
-    pod[j] = d;
+    j += dj;
+    s += ds;
+    if (s >= ldi) { s -= ldi; ++j; }
   }
   const T *ep = (const T *)P.etapr + pd.voff, *el = (const T *)P.etalik + pd.voff;
   T *eo = (T *)P.x + pd.voff;
@@ -92,9 +98,12 @@ template <typename T> __global__ void __launch_bounds__(kRowBlock) k_ng_post(con
   const T *mo = (const T *)P.x + pd.voff, *mp = (const T *)P.etaprbar + pd.voff;
   T *gp = (T *)P.Lprbar + pd.boff, *gl = (T *)P.Llikbar + pd.boff;
   double *gpd = P.Lprbard ? P.Lprbard + pd.voff : nullptr, *gld = P.Llikbard ? P.Llikbard + pd.voff : nullptr;
-  for (int64_t e = C.a * ld + threadIdx.x; e < C.b * ld; e += kRowBlock) {
-    const int64_t j = e / ld;
-    const int s = (int)(e - j * ld);
+  // element e = j * ld + s: (j, s) advance with e, so no element is divided by ld
+  const int ldi = (int)ld, dj = kRowBlock / ldi, ds = kRowBlock % ldi;
+  int64_t j = C.a + (int)threadIdx.x / ldi;
+  int s = (int)threadIdx.x % ldi;
+  for (int64_t e = C.a * ld + threadIdx.x; e < C.b * ld; e += kRowBlock, j += dj, s += ds) {
+    if (s >= ldi) { s -= ldi; ++j; }
     const int64_t i = j + s;
     double g_pr = 0.0, g_lk = 0.0;
     if (s <= K && i < n) {
