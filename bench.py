@@ -198,13 +198,55 @@ def measured_traffic(slot: str, path: str, rows: int):
     """HBM bytes per launch of `slot` from the committed rocprofv3 counter
     summary of this workload, or None when there is none, it covers another
     workload, or the kernels have changed since it was taken."""
-    from paper_1902_10078_amd import profsum
+    import profsum
     tr, meta = profsum.read_traffic(path)
     if slot not in tr or meta.get("source_hash") != profsum.source_hash(meta.get("hash_sources")):
         return None
     if int(meta.get("rows_per_launch", -1)) != rows:
         return None
     return round(tr[slot])
+
+
+def copy_gbs(torch, mib: int):
+    """Measured rate of a plain device copy of mib MiB (read + write bytes per
+    second, GB/s): the bandwidth these streaming kernels can actually reach,
+    reported beside the 8 TB/s peak."""
+    dev = torch.device("cuda", 0)
+    nbytes = mib << 20
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    reps = 10
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2 * nbytes / (ms / 1e3) / 1e9
+
+
+def host_info(threads_used: int):
+    """Host CPU facts for the CPU baseline: logical CPUs the process may run
+    on, the OpenMP threads the oracle used, and the CPU model."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return dict(cores=int(threads_used), host_cpus_available=avail, host_cpus_total=os.cpu_count(),
+                omp_num_threads=os.environ.get("OMP_NUM_THREADS"), cpu_model=model)
 
 
 def copy_probe(torch, mib: int):
@@ -810,7 +852,7 @@ def cpu_baseline_alg5(host_inputs, widths, rows: int):
     O = oracle.solve_band_mat(Ls, k, Rs, lr, u)
     oracle.solve_band_mat_bwd(Ls, k, O, Obs, lr, u)
     dt = time.perf_counter() - t0
-    return dict(value=rows / dt, unit="band-rows/s", cores=1, kind="oracle",
+    return dict(value=rows / dt, unit="band-rows/s", kind="oracle", **host_info(1),
                 sample=f"the first {rows} rows of the matrix, FP64 C oracle (forward and reverse), "
                        f"one thread, {dt:.2f} s wall"), O
 
@@ -825,7 +867,7 @@ def cpu_baseline_ng(host_inputs, ns, nsample: int):
                                  host_inputs[i]["eta_lik"], host_inputs[i]["k"])["parts"] for i in idx])
     dt = time.perf_counter() - t0
     rows = sum(ns[i] for i in idx)
-    return dict(value=rows / dt, unit="band-rows/s", cores=1, kind="oracle",
+    return dict(value=rows / dt, unit="band-rows/s", kind="oracle", **host_info(1),
                 sample=f"{len(idx)} of the workload's {len(ns)} problems ({rows} rows), FP64 C oracle "
                        f"(forward and reverse), one thread, {dt:.2f} s wall"), ref
 
@@ -844,7 +886,7 @@ def cpu_baseline_wh(host_inputs, ns, ks, nsample: int):
         ref.append(oracle.logdet(L, ks[i]))
     dt = time.perf_counter() - t0
     rows = sum(ns[i] for i in idx)
-    return dict(value=rows / dt, unit="band-rows/s", cores=1, kind="oracle",
+    return dict(value=rows / dt, unit="band-rows/s", kind="oracle", **host_info(1),
                 sample=f"{len(idx)} of the workload's {len(ns)} problems ({rows} rows), FP64 C oracle "
                        f"(forward and reverse), one thread, {dt:.2f} s wall"), np.array(ref)
 
@@ -859,7 +901,7 @@ def cpu_baseline_ml(host_inputs, ns, ks, nsample: int):
     ref = np.array([oracle.marglik(Qs[i], ks[i], masks[i], bs[i], t2[i])["parts"] for i in idx])
     dt = time.perf_counter() - t0
     rows = sum(ns[i] for i in idx)
-    return dict(value=rows / dt, unit="band-rows/s", cores=1, kind="oracle",
+    return dict(value=rows / dt, unit="band-rows/s", kind="oracle", **host_info(1),
                 sample=f"{len(idx)} of the workload's {len(ns)} problems ({rows} rows), FP64 C oracle "
                        f"(forward and reverse), one thread, {dt:.2f} s wall"), ref
 
@@ -877,9 +919,10 @@ def cpu_baseline(host_inputs, ns, ks, nsample: int, vi: bool = False):
         parts, _, _, _, _, threads = oracle.vi_kl_batch(sn, sk, cat(Lqs), cat(Lps), cat(mqs), cat(mps))
         dt = time.perf_counter() - t0
         rows = sum(sn)
-        return dict(value=rows / dt, unit="band-rows/s", cores=int(min(threads, len(idx))), kind="oracle",
+        used = min(threads, len(idx))
+        return dict(value=rows / dt, unit="band-rows/s", kind="oracle", **host_info(used),
                     sample=f"{len(idx)} of the workload's {len(ns)} problems ({rows} rows), FP64 C oracle, "
-                           f"OpenMP across problems, {dt:.2f} s wall"), parts
+                           f"OpenMP across problems ({threads} threads, {used} busy), {dt:.2f} s wall"), parts
     Qs, ys, Ss = host_inputs
     Qf = np.concatenate([Qs[i].ravel() for i in idx])
     yf = np.concatenate([ys[i] for i in idx])
@@ -892,9 +935,10 @@ def cpu_baseline(host_inputs, ns, ks, nsample: int, vi: bool = False):
     dt = time.perf_counter() - t0
     rows = sum(sn)
     # OpenMP runs one problem per thread: the threads in use are at most the problems
-    return dict(value=rows / dt, unit="band-rows/s", cores=int(min(threads, len(idx))), kind="oracle",
+    used = min(threads, len(idx))
+    return dict(value=rows / dt, unit="band-rows/s", kind="oracle", **host_info(used),
                 sample=f"{len(idx)} of the workload's {len(ns)} problems ({rows} rows), FP64 C oracle, "
-                       f"OpenMP across problems, {dt:.2f} s wall"), ref
+                       f"OpenMP across problems ({threads} threads, {used} busy), {dt:.2f} s wall"), ref
 
 
 def main():
@@ -920,7 +964,7 @@ def main():
     ap.add_argument("--graph-len", type=int, default=333_334, help="length of the road strip (3 x len junctions)")
     ap.add_argument("--n-alg5", type=int, default=16_000_000, help="rows of the Algorithm 5 matrix")
     ap.add_argument("--cpu-sample", type=int, default=0,
-                    help="problems timed on the CPU oracle (default: 8 for the loss and KL batches, "
+                    help="problems timed on the CPU oracle (default: the whole batch for the loss workload, 8 for the KL batch, "
                          "256 for the uneven batch, the whole batch for the marginal-likelihood, "
                          "natural-parameter, whitened and graph batches, 1 otherwise)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -967,7 +1011,7 @@ def main():
         ns, ks, host_inputs = make_matern52(args)
         cfg = {"workload": f"matern52_ssm_batch{len(ns)}_rows{ns[0]}_k5_gauss_loss_fwd_bwd",
                "batch": len(ns), "rows_per_problem": ns[0], "k": 5}
-        nsample = args.cpu_sample or 8
+        nsample = args.cpu_sample or len(ns)   # the whole batch, one problem per OpenMP thread
     elif args.workload == "uneven_forward":
         ns, ks, host_inputs = make_uneven(args, bo, torch, dev)
         cfg = {"workload": f"uneven_batch{len(ns)}_n256-65536_k1-3-5-11_forward",
@@ -1125,6 +1169,8 @@ def main():
                 traffic=measured_traffic(dom, path, rows) if whole else None,
                 bytes_per_step=bb[dom], launches_per_step=d["launches_per_step"], rows=rows)
     unit_gbs = bb["unit"] / (ms / 1e3) / 1e9
+    copy_rate = copy_gbs(torch, 1024)
+    log(f"plain 1 GiB device copy: {copy_rate:.1f} GB/s (read + write)")
     if args.kernels_json:
         with open(args.kernels_json, "w") as f:
             json.dump(dict(kernels=kern, ms_per_step=ms, rows=rows), f, indent=1)
@@ -1183,6 +1229,9 @@ def main():
         "config": cfg,
         "roofline": roof,
         "unit_hbm_frac": round(unit_gbs / HBM_PEAK_GBS, 4),
+        "copy_gbs": round(copy_rate, 1),
+        "unit_frac_of_copy": round(unit_gbs / copy_rate, 4),
+        "dominant_frac_of_copy": round(d["gbs"] / copy_rate, 4),
         "vs_fp64_plain": vs_plain,
     }
     if not args.no_cpu and alg5:
@@ -1204,7 +1253,7 @@ def main():
             ref.append(oracle.logdet(L, g["k"]))
         dt = time.perf_counter() - t0
         rws = len(idx) * g["n"]
-        cb = dict(value=rws / dt, unit="band-rows/s", cores=1, kind="oracle",
+        cb = dict(value=rws / dt, unit="band-rows/s", kind="oracle", **host_info(1),
                   sample=f"{len(idx)} of the workload's 16 problems ({rws} rows), FP64 oracle (band assembly, "
                          f"whitened sample and its reverse mode), one thread, {dt:.2f} s wall")
         gp = W.kw["logdet"].cpu().numpy()[: len(ref)]

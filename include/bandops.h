@@ -48,6 +48,12 @@
 extern "C" {
 #endif
 
+/* Storage formats.  There is no pure-FP32 format: every pass is bound by HBM
+ * traffic (0.1 - 1 flop per byte), so FP32 arithmetic would save no time,
+ * while FP32 pivots break down on the paper's state-space precisions (an
+ * FP32-rounded Matern-3/2 precision at lengthscale 10 is already
+ * indefinite).  BO_MIXED halves the off-diagonal traffic and keeps every
+ * pivot, log-determinant and diagonal in FP64. */
 typedef enum { BO_F64 = 0, BO_MIXED = 1 } bo_prec;
 
 typedef enum {
@@ -85,12 +91,23 @@ size_t bo_workspace_size(int64_t n, int32_t k);
 bo_status bo_chol(bo_prec prec, const bo_band *Q, bo_band *L, const void *y, void *z,
                   double *logdet, int32_t *info, void *ws, size_t ws_bytes, hipStream_t stream);
 
-/* S (Section 4.1): x = L^{-1} b (trans = 0) or x = L^{-T} b (trans = 1, the
- * upper-banded variant the gradients need, Section 4.1 "transposes"). */
-bo_status bo_trsv(bo_prec prec, const bo_band *L, int trans, const void *b, void *x, void *ws,
-                  size_t ws_bytes, hipStream_t stream);
+/* S (Section 4.1): X = L^{-1} B (trans = 0) or X = L^{-T} B (trans = 1, the
+ * upper-banded variant the gradients need, Section 4.1 "transposes") for nrhs
+ * right-hand sides: column c of B and of X starts at element c * ldx (ldx >=
+ * n; ignored when nrhs = 1), in double (BO_F64) or float (BO_MIXED).  The
+ * columns are solved one after another on the stream with the same
+ * workspace (bo_workspace_size(n, k)).  nrhs = 0 does nothing; B and X may
+ * not overlap. */
+bo_status bo_trsv(bo_prec prec, const bo_band *L, int trans, const void *b, void *x, int64_t nrhs,
+                  int64_t ldx, void *ws, size_t ws_bytes, hipStream_t stream);
 
-/* I (Algorithm 3, Takahashi): Sigma = lower band (width k) of (L L^T)^{-1}. */
+/* I (Algorithm 3, Takahashi): Sigma = lower band of (L L^T)^{-1} of width
+ * kout = Sigma->l >= L->l (Algorithm 3's recursion read on kout sub-diagonals;
+ * the entries beyond L's band follow from the same sums).  With kout = L->l,
+ * Sigma has L's stride.  With kout > L->l (kout <= BO_KMAX), Sigma must be
+ * packed (ld = kout + 1), and ws holds a copy of L widened to kout with zero
+ * slots: at least bo_subset_inv_workspace_size(n, L->l, kout) bytes. */
+size_t bo_subset_inv_workspace_size(int64_t n, int32_t k, int32_t kout);
 bo_status bo_subset_inv(bo_prec prec, const bo_band *L, bo_band *Sigma, void *ws, size_t ws_bytes,
                         hipStream_t stream);
 
@@ -185,6 +202,8 @@ typedef struct {
   double *logdet;                         /* per problem                       */
   double *parts;                          /* per problem: logdet, yQ^-1y, trace */
   int32_t *info;                          /* per problem                       */
+  double *loss;                           /* loss: per problem (may be NULL)   */
+  void *Sbar;      double *Sbard;         /* loss: d loss / d S (may be NULL)  */
 } bo_batch_io;
 
 /* Build a plan (host object): chunking of every problem into about
@@ -204,7 +223,9 @@ bo_status bo_plan_forward(const bo_plan *plan, bo_prec prec, const bo_batch_io *
  * mode: forward (C, log det, S, I), then Algorithm 4 with Sigmabar = S, the
  * solve sensitivity of Table 1 with zbar = -2z, the log-determinant
  * sensitivity and Algorithm 2.  Writes L, z, Sig, Lbar, x (= ybar), Qbar,
- * parts and info. */
+ * parts and info; when given, loss[p] (the sum of the parts) and Sbar =
+ * d loss / d S on S's stored entries (Sigma_ii on the diagonal, 2 Sigma_ij off
+ * it: an off-diagonal stored entry of S stands for S_ij and S_ji). */
 bo_status bo_plan_gauss_loss(const bo_plan *plan, bo_prec prec, const bo_batch_io *io, void *ws,
                              hipStream_t stream);
 /* Kullback-Leibler term of the variational objective (Section 3.3, Eq. (KL);
@@ -385,6 +406,25 @@ bo_status bo_csr_to_band(bo_prec prec, int64_t n, int32_t nsets, const int64_t *
 bo_status bo_band_to_csr_grad(bo_prec prec, int64_t n, int32_t nsets, const int64_t *indptr,
                               const int64_t *indices, int64_t nnz, int32_t k, int64_t ld, const void *gband,
                               const double *gdiag, double *gvals, hipStream_t stream);
+
+/* The chain rule over a plan's batch (the step a reverse-mode caller takes
+ * with the upstream sensitivity g of each problem's scalar output):
+ *   kind BO_SCALE_BAND:      out = g[p] * in on every stored entry of problem
+ *                            p's records (boff, stride k+1);
+ *   kind BO_SCALE_BAND_SYM:  as BO_SCALE_BAND with an extra factor 2 off the
+ *                            diagonal (the stored-entry gradient of a trace
+ *                            tr(Sigma S) with respect to a symmetric S);
+ *   kind BO_SCALE_VEC:       out = g[p] * in on problem p's n entries (voff);
+ *   kind BO_SCALE_PROBLEM:   out[p] = g[p] * in[p], one FP64 value per problem
+ *                            (a per-problem scalar input such as tau2).
+ * g: nprob device doubles in the caller's problem order, or NULL for 1.
+ * BO_MIXED: records and vectors are float and the band diagonals are the FP64
+ * arrays ind / outd (used for the band kinds only).  out may equal in.  The
+ * workspace is the plan's (its problem tables).  Slots past a matrix's end
+ * are written 0. */
+enum { BO_SCALE_BAND = 0, BO_SCALE_BAND_SYM = 1, BO_SCALE_VEC = 2, BO_SCALE_PROBLEM = 3 };
+bo_status bo_plan_scale(const bo_plan *plan, bo_prec prec, int32_t kind, const double *g, const void *in,
+                        const double *ind, void *out, double *outd, void *ws, hipStream_t stream);
 
 /* Plan statistics: out[0] problems, out[1] chunks, out[2] groups, out[3] rows,
  * out[4] largest k. */

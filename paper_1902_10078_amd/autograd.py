@@ -177,46 +177,44 @@ class OuterBand(torch.autograd.Function):
         return gm, gv, None, None
 
 
+def _scale(plan, kind, g, t):
+    """g[p] * t on every problem p's records or entries, in the library."""
+    return plan.scale(bo.F64, kind, g.contiguous(), t, torch.empty_like(t))
+
+
 class GaussLoss(torch.autograd.Function):
     """Per-problem loss_p = log det Q_p - y_p^T Q_p^{-1} y_p + tr(Q_p^{-1} S_p)
     over a plan's batch.  Q, S: packed lower bands (all problems' records back
-    to back); y: packed vectors.  The forward pass runs the fused forward and
-    backward passes once and keeps dloss/dQ and dloss/dy for backward."""
+    to back); y: packed vectors.  The forward pass runs the library's fused
+    forward and backward passes once: it writes the losses and d loss / dQ,
+    dy, dS, which backward scales by the upstream sensitivities (the library's
+    per-problem scaling)."""
 
     @staticmethod
     def forward(ctx, plan, Q, y, S):
         Q, y, S = _vec(Q), _vec(y), _vec(S)
         dev = Q.device
         E, N = Q.numel(), y.numel()
-        bufs = {nm: torch.empty(E, dtype=torch.float64, device=dev) for nm in ("L", "Sig", "Lbar", "Qbar")}
+        bufs = {nm: torch.empty(E, dtype=torch.float64, device=dev) for nm in ("L", "Sig", "Lbar", "Qbar", "Sbar")}
         z = torch.empty(N, dtype=torch.float64, device=dev)
         ybar = torch.empty(N, dtype=torch.float64, device=dev)
-        parts = torch.zeros((plan.nprob, 3), dtype=torch.float64, device=dev)
+        parts = torch.empty((plan.nprob, 3), dtype=torch.float64, device=dev)
+        loss = torch.empty(plan.nprob, dtype=torch.float64, device=dev)
         info = torch.zeros(plan.nprob, dtype=torch.int32, device=dev)
-        io = plan.io(Q=Q, y=y, S=S, z=z, x=ybar, parts=parts, info=info, **bufs)
+        io = plan.io(Q=Q, y=y, S=S, z=z, x=ybar, parts=parts, info=info, loss=loss, **bufs)
         plan.gauss_loss(bo.F64, io)
         _check_info(info)
-        ctx.save_for_backward(bufs["Qbar"], ybar, bufs["Sig"])
+        ctx.save_for_backward(bufs["Qbar"], ybar, bufs["Sbar"])
         ctx.plan = plan
-        return parts[:, 0] - parts[:, 1] + parts[:, 2]
+        return loss
 
     @staticmethod
     def backward(ctx, g):
-        Qbar, ybar, Sig = ctx.saved_tensors
+        Qbar, ybar, Sbar = ctx.saved_tensors
         plan = ctx.plan
-        band_sizes = torch.tensor([n * (k + 1) for n, k in zip(plan.ns, plan.ks)], device=g.device)
-        rows = torch.tensor(plan.ns, device=g.device)
-        gb = torch.repeat_interleave(g, band_sizes)
-        gQ = Qbar * gb if ctx.needs_input_grad[1] else None
-        gy = ybar * torch.repeat_interleave(g, rows) if ctx.needs_input_grad[2] else None
-        gS = None
-        if ctx.needs_input_grad[3]:
-            # d tr(Q^{-1} S) / d S on the stored lower band: Sigma_ii, 2 Sigma_ij
-            w = torch.cat([torch.ones(1, dtype=torch.float64, device=g.device),
-                           torch.full((1,), 2.0, dtype=torch.float64, device=g.device)])
-            slot_w = torch.cat([torch.where(torch.arange(k + 1, device=g.device) == 0, w[0], w[1]).repeat(n)
-                                for n, k in zip(plan.ns, plan.ks)])
-            gS = Sig * slot_w * gb
+        gQ = _scale(plan, bo.SCALE_BAND, g, Qbar) if ctx.needs_input_grad[1] else None
+        gy = _scale(plan, bo.SCALE_VEC, g, ybar) if ctx.needs_input_grad[2] else None
+        gS = _scale(plan, bo.SCALE_BAND, g, Sbar) if ctx.needs_input_grad[3] else None
         return None, gQ, gy, gS
 
 
@@ -266,13 +264,10 @@ class ViKL(torch.autograd.Function):
     def backward(ctx, g):
         Lqbar, Lpbar, mqbar, mpbar = ctx.saved_tensors
         plan = ctx.plan
-        gb = torch.repeat_interleave(g, torch.tensor([n * (k + 1) for n, k in zip(plan.ns, plan.ks)],
-                                                     device=g.device))
-        gr = torch.repeat_interleave(g, torch.tensor(plan.ns, device=g.device))
-        return (None, Lqbar * gb if ctx.needs_input_grad[1] else None,
-                Lpbar * gb if ctx.needs_input_grad[2] else None,
-                mqbar * gr if ctx.needs_input_grad[3] else None,
-                mpbar * gr if ctx.needs_input_grad[4] else None)
+        return (None, _scale(plan, bo.SCALE_BAND, g, Lqbar) if ctx.needs_input_grad[1] else None,
+                _scale(plan, bo.SCALE_BAND, g, Lpbar) if ctx.needs_input_grad[2] else None,
+                _scale(plan, bo.SCALE_VEC, g, mqbar) if ctx.needs_input_grad[3] else None,
+                _scale(plan, bo.SCALE_VEC, g, mpbar) if ctx.needs_input_grad[4] else None)
 
 
 class Whiten(torch.autograd.Function):
@@ -306,14 +301,6 @@ def whiten(plan, Q, v):
     return Whiten.apply(plan, Q, v)
 
 
-def _per_band(plan, g):
-    return torch.repeat_interleave(g, torch.tensor([n * (k + 1) for n, k in zip(plan.ns, plan.ks)], device=g.device))
-
-
-def _per_row(plan, g):
-    return torch.repeat_interleave(g, torch.tensor(plan.ns, device=g.device))
-
-
 class MargLik(torch.autograd.Function):
     """Per-problem log marginal likelihood with partial observations (Eq.
     (marg_lik), Algorithm 8) over a plan's batch, FP64: Q packed lower bands,
@@ -341,9 +328,9 @@ class MargLik(torch.autograd.Function):
     def backward(ctx, g):
         Qbar, bbar, tau2bar = ctx.saved_tensors
         plan = ctx.plan
-        return (None, Qbar * _per_band(plan, g) if ctx.needs_input_grad[1] else None, None,
-                bbar * _per_row(plan, g) if ctx.needs_input_grad[3] else None,
-                tau2bar * g if ctx.needs_input_grad[4] else None)
+        return (None, _scale(plan, bo.SCALE_BAND, g, Qbar) if ctx.needs_input_grad[1] else None, None,
+                _scale(plan, bo.SCALE_VEC, g, bbar) if ctx.needs_input_grad[3] else None,
+                _scale(plan, bo.SCALE_PROBLEM, g, tau2bar) if ctx.needs_input_grad[4] else None)
 
 
 def marglik(plan, Q, mask, b, tau2):
@@ -375,11 +362,10 @@ class NatGP(torch.autograd.Function):
     def backward(ctx, g):
         Lprbar, etaprbar, Llikbar, x = ctx.saved_tensors
         plan = ctx.plan
-        gb, gr = _per_band(plan, g), _per_row(plan, g)
-        return (None, Lprbar * gb if ctx.needs_input_grad[1] else None,
-                etaprbar * gr if ctx.needs_input_grad[2] else None,
-                Llikbar * gb if ctx.needs_input_grad[3] else None,
-                x * gr if ctx.needs_input_grad[4] else None)
+        return (None, _scale(plan, bo.SCALE_BAND, g, Lprbar) if ctx.needs_input_grad[1] else None,
+                _scale(plan, bo.SCALE_VEC, g, etaprbar) if ctx.needs_input_grad[2] else None,
+                _scale(plan, bo.SCALE_BAND, g, Llikbar) if ctx.needs_input_grad[3] else None,
+                _scale(plan, bo.SCALE_VEC, g, x) if ctx.needs_input_grad[4] else None)
 
 
 def natgp(plan, Lpr, etapr, Llik, etalik):
@@ -418,37 +404,9 @@ def gauss_loss(plan, Q, y, S):
     return GaussLoss.apply(plan, Q, y, S)
 
 
-def gauss_loss_composed(Q, y, S):
-    """The same loss for one problem composed from the separate operators
-    (Table 1 compositions through autograd): logdet from C, the quadratic
-    term from S twice, the trace from I."""
-    k = Q.shape[1] - 1
-    L, logdet = chol(Q)
-    z = trsv(L, y, 0)
-    Sig = subset_inv(L)
-    w = torch.full((k + 1,), 2.0, dtype=torch.float64, device=Q.device)
-    w[0] = 1.0
-    return logdet - (z * z).sum() + (Sig * S * w).sum()
-
-
 def solve_band_mat(L, R, lr: int, u: int):
     return SolveBandMat.apply(L, R, lr, u)
 
 
 def vi_kl(plan, Lq, Lp, mq, mp):
     return ViKL.apply(plan, Lq, Lp, mq, mp)
-
-
-def vi_kl_composed(Lq, Lp, mq, mp):
-    """KL(q || p) for one problem composed from the separate operators as
-    Algorithm 7 writes it: tr(I(L_q) P(L_p, L_p^T)) as the weighted sum over
-    the band, the log-diagonals, ||P(L_p^T, m_p - m_q)||^2."""
-    k = Lq.shape[1] - 1
-    n = Lq.shape[0]
-    Sig = subset_inv(Lq)
-    Qp = gbmm(Lp, Lp, k, 0, k, 0, 0, 1, k, 0)
-    w = torch.full((k + 1,), 2.0, dtype=torch.float64, device=Lq.device)
-    w[0] = 1.0
-    tr = (Sig * Qp * w).sum()
-    v = gbmv(Lp, mp - mq, k, 0, 1)
-    return 0.5 * (tr + 2.0 * (torch.log(Lq[:, 0]).sum() - torch.log(Lp[:, 0]).sum()) + (v * v).sum() - n)

@@ -23,6 +23,7 @@ LIB_PATH = os.environ.get("BANDOPS_LIB") or os.path.join(_HERE, "libbandops.so")
 
 F64, MIXED = 0, 1
 KMAX = 12
+SCALE_BAND, SCALE_BAND_SYM, SCALE_VEC, SCALE_PROBLEM = 0, 1, 2, 3
 
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64
@@ -41,7 +42,7 @@ class _Problem(ctypes.Structure):
 class _BatchIO(ctypes.Structure):
     _fields_ = [(name, _P) for name in (
         "Q", "Qd", "y", "S", "Sd", "L", "Ld", "z", "x", "Sig", "Sigd", "Lbar", "Lbard",
-        "Qbar", "Qbard", "logdet", "parts", "info")]
+        "Qbar", "Qbard", "logdet", "parts", "info", "loss", "Sbar", "Sbard")]
 
 
 class _MLIO(ctypes.Structure):
@@ -82,7 +83,8 @@ def lib():
     sigs = {
         "bo_workspace_size": (ctypes.c_size_t, [_I64, _I32]),
         "bo_chol": (_I32, [_I32, bp, bp, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
-        "bo_trsv": (_I32, [_I32, bp, _I32, _P, _P, _P, ctypes.c_size_t, _P]),
+        "bo_trsv": (_I32, [_I32, bp, _I32, _P, _P, _I64, _I64, _P, ctypes.c_size_t, _P]),
+        "bo_subset_inv_workspace_size": (ctypes.c_size_t, [_I64, _I32, _I32]),
         "bo_subset_inv": (_I32, [_I32, bp, bp, _P, ctypes.c_size_t, _P]),
         "bo_gbmm": (_I32, [_I32, bp, _I32, bp, _I32, bp, _P]),
         "bo_gbmv": (_I32, [_I32, bp, _I32, _P, _P, _P]),
@@ -108,6 +110,7 @@ def lib():
         "bo_csr_to_band": (_I32, [_I32, _I64, _I32, _P, _P, _I64, _P, _I32, _I64, _P, _P, _P, _P]),
         "bo_band_to_csr_grad": (_I32, [_I32, _I64, _I32, _P, _P, _I64, _I32, _I64, _P, _P, _P, _P]),
         "bo_plan_whiten_bwd": (_I32, [_P, _I32, ctypes.POINTER(_WHIO), _P, _P]),
+        "bo_plan_scale": (_I32, [_P, _I32, _I32, _P, _P, _P, _P, _P, _P, _P]),
         "bo_plan_stats": (_I32, [_P, ctypes.POINTER(_I64)]),
         "bo_plan_destroy": (_I32, [_P]),
         "bo_wide_workspace_size": (_I32, [ctypes.POINTER(_Problem), _I32, ctypes.POINTER(ctypes.c_size_t)]),
@@ -129,11 +132,11 @@ def lib():
     return L
 
 
-EXPORTED = ("bo_workspace_size", "bo_chol", "bo_trsv", "bo_subset_inv", "bo_gbmm", "bo_gbmv",
+EXPORTED = ("bo_workspace_size", "bo_chol", "bo_trsv", "bo_subset_inv_workspace_size", "bo_subset_inv", "bo_gbmm", "bo_gbmv",
             "bo_outer_band", "bo_solve_band_mat", "bo_solve_band_mat_workspace",
             "bo_solve_band_mat_bwd", "bo_chol_bwd", "bo_subset_inv_bwd", "bo_trsv_bwd", "bo_logdet_bwd",
             "bo_plan_create", "bo_plan_workspace_size", "bo_plan_upload", "bo_plan_forward",
-            "bo_plan_gauss_loss", "bo_plan_vi_kl", "bo_plan_marglik", "bo_plan_natgp", "bo_plan_whiten", "bo_plan_whiten_bwd", "bo_rcm", "bo_csr_permute", "bo_csr_to_band", "bo_band_to_csr_grad", "bo_plan_stats", "bo_plan_destroy", "bo_wide_workspace_size",
+            "bo_plan_gauss_loss", "bo_plan_vi_kl", "bo_plan_marglik", "bo_plan_natgp", "bo_plan_whiten", "bo_plan_whiten_bwd", "bo_rcm", "bo_csr_permute", "bo_csr_to_band", "bo_band_to_csr_grad", "bo_plan_scale", "bo_plan_stats", "bo_plan_destroy", "bo_wide_workspace_size",
             "bo_wide_upload", "bo_wide_forward", "bo_wide_gauss_loss", "bo_profile_enable",
             "bo_profile_read", "bo_profile_slots", "bo_profile_slot_name", "bo_status_string",
             "bo_last_error")
@@ -241,17 +244,27 @@ def bo_chol(Q: Band, y: Optional[torch.Tensor] = None):
 
 
 def bo_trsv(L: Band, b: torch.Tensor, trans: int = 0):
+    """X = L^{-1} B or L^{-T} B; b is one vector (n,) or nrhs columns stored
+    as rows of a (nrhs, n) tensor (column c at element c * n)."""
+    b = b.contiguous()
     x = torch.empty_like(b)
+    nrhs, ldx = (1, L.n) if b.dim() == 1 else (b.shape[0], b.shape[1])
     ws = workspace(L.n, L.l)
     lc = L.c()
-    _check(lib().bo_trsv(L.prec, ctypes.byref(lc), int(trans), _ptr(b), _ptr(x), _ptr(ws), ws.numel(),
-                         _stream()), "bo_trsv")
+    _check(lib().bo_trsv(L.prec, ctypes.byref(lc), int(trans), _ptr(b), _ptr(x), int(nrhs), int(ldx), _ptr(ws),
+                         ws.numel(), _stream()), "bo_trsv")
     return x
 
 
-def bo_subset_inv(L: Band):
-    S = new_band(L.n, L.l, 0, L.prec, L.band.device)
-    ws = workspace(L.n, L.l)
+def bo_subset_inv(L: Band, kout: Optional[int] = None):
+    """Lower band of (L L^T)^{-1} of width kout (default: L's own width)."""
+    kout = L.l if kout is None else int(kout)
+    S = new_band(L.n, kout, 0, L.prec, L.band.device)
+    if kout == L.l:
+        ws = workspace(L.n, L.l)
+    else:
+        size = max(int(lib().bo_subset_inv_workspace_size(L.n, L.l, kout)), 256)
+        ws = torch.empty(size, dtype=torch.uint8, device=L.band.device)
     lc, sc = L.c(), S.c()
     _check(lib().bo_subset_inv(L.prec, ctypes.byref(lc), ctypes.byref(sc), _ptr(ws), ws.numel(),
                                _stream()), "bo_subset_inv")
@@ -423,6 +436,16 @@ class Plan:
     def gauss_loss(self, prec: int, io: _BatchIO):
         _check(lib().bo_plan_gauss_loss(self.h, prec, ctypes.byref(io), _ptr(self.ws), _stream()),
                "bo_plan_gauss_loss")
+
+    def scale(self, prec: int, kind: int, g: Optional[torch.Tensor], inp: torch.Tensor,
+              out: torch.Tensor, ind: Optional[torch.Tensor] = None, outd: Optional[torch.Tensor] = None):
+        """out = g[p] * inp over every problem p (bo_plan_scale): kind
+        SCALE_BAND / SCALE_BAND_SYM on packed records, SCALE_VEC on packed
+        vectors, SCALE_PROBLEM on one FP64 value per problem; g None scales by
+        1.  out may be inp."""
+        _check(lib().bo_plan_scale(self.h, prec, int(kind), _ptr(g), _ptr(inp), _ptr(ind), _ptr(out), _ptr(outd),
+                                   _ptr(self.ws), _stream()), "bo_plan_scale")
+        return out
 
     def kl_io(self, **arrays) -> _KLIO:
         io = _KLIO()

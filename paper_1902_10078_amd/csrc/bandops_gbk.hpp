@@ -243,3 +243,58 @@ __global__ void __launch_bounds__(256) k_solve_mat_lbar(int64_t n, int k, int u,
 }
 
 unsigned blocks_for(int64_t count, int block) { return (unsigned)((count + block - 1) / block); }
+
+// ------------------------------------------ widened factor (subset inverse)
+// dst = src widened from k to K sub-diagonals (K > k), packed (stride K+1):
+// slot d of record j is src's slot d for d <= k inside the matrix, else 0.
+// Algorithm 3 on the widened factor gives the band of width K of Q^{-1}:
+// the sums over m only ever meet L's own k sub-diagonals.  One lane per
+// stored element of dst.
+template <typename T>
+__global__ void k_widen_lower(int64_t n, const T *src, int64_t lds, int k, T *dst, int K) {
+  const int64_t w = K + 1;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * w) return;
+  const int64_t j = t / w;
+  const int d = (int)(t - j * w);
+  dst[t] = (d <= k && j + d < n) ? src[j * lds + d] : (T)0;
+}
+
+// -------------------------------------------- per-problem scaling of a plan
+// One workgroup per chunk of the plan's schedule, over that chunk's rows of
+// its problem: out = s_p * in (s_p = g[problem] or 1), with the factor 2 off
+// the diagonal for BO_SCALE_BAND_SYM; band pads (slots past the matrix end)
+// are written 0.  Mixed format: records are float and the diagonal is the
+// FP64 side array (ind -> outd).
+template <typename T>
+__global__ void __launch_bounds__(256) k_plan_scale(const bo::ProbDesc *probs, const int32_t *chunk_prob,
+                                                    int kind, const double *g, const T *in, const double *ind,
+                                                    T *out, double *outd) {
+  const int32_t c = (int32_t)blockIdx.x;
+  const bo::ProbDesc &pd = probs[chunk_prob[c]];
+  int64_t a, b;
+  bo::chunk_rows(pd, c, a, b);
+  const double s = g ? g[pd.orig] : 1.0;
+  if (kind == BO_SCALE_VEC) {
+    for (int64_t j = a + threadIdx.x; j < b; j += blockDim.x) out[pd.voff + j] = (T)(s * (double)in[pd.voff + j]);
+    return;
+  }
+  const int64_t w = pd.ld;
+  const T *src = in + pd.boff;
+  T *dst = out + pd.boff;
+  for (int64_t e = a * w + threadIdx.x; e < b * w; e += blockDim.x) {
+    const int64_t j = e / w;
+    const int d = (int)(e - j * w);
+    double v = (d <= pd.k && j + d < pd.n) ? s * (double)src[e] : 0.0;
+    if (kind == BO_SCALE_BAND_SYM && d > 0) v *= 2.0;
+    dst[e] = (T)v;
+  }
+  if (outd)
+    for (int64_t j = a + threadIdx.x; j < b; j += blockDim.x) outd[pd.voff + j] = s * ind[pd.voff + j];
+}
+
+// out[p] = g[p] * in[p] for the nprob per-problem values (BO_SCALE_PROBLEM).
+__global__ void k_problem_scale(int64_t nprob, const double *g, const double *in, double *out) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < nprob) out[p] = (g ? g[p] : 1.0) * in[p];
+}

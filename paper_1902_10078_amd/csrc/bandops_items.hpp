@@ -66,6 +66,7 @@ struct Args {
   double *logdet;   // per problem
   double *parts;    // 3 per problem: logdet, y^T Q^{-1} y, tr(Q^{-1} S)
   int32_t *info;    // per problem
+  double *loss;     // per problem: logdet - y^T Q^{-1} y + tr(Q^{-1} S) (or null)
 };
 
 BO_HD const ProbDesc &prob_at(const Args &a, int32_t p) { return a.probs ? a.probs[p] : a.one; }

@@ -129,6 +129,7 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const Args A) {
     A.parts[3 * (int64_t)o + 2] = tr;
   }
   if (A.info) A.info[o] = fail >= 0 ? (int32_t)(fail + 1) : 0;
+  if (A.loss) A.loss[o] = fail >= 0 ? NAN : ld - q + tr;
 }
 
 // ------------------------------------------------------------ profiling
@@ -364,30 +365,79 @@ extern "C" bo_status bo_chol(bo_prec prec, const bo_band *Q, bo_band *L, const v
 }
 
 extern "C" bo_status bo_trsv(bo_prec prec, const bo_band *L, int trans, const void *b, void *x,
-                             void *ws, size_t ws_bytes, hipStream_t stream) {
+                             int64_t nrhs, int64_t ldx, void *ws, size_t ws_bytes, hipStream_t stream) {
   if (bo_status e = check_band(L, prec, "L", true)) return e;
-  if (L->n > 0 && (!b || !x)) return fail(BO_EINVAL, "bo_trsv: null vector");
+  if (nrhs < 0) return fail(BO_EINVAL, "bo_trsv: negative nrhs");
+  if (nrhs > 1 && ldx < L->n) return fail(BO_EINVAL, "bo_trsv: ldx < n");
+  if (L->n > 0 && nrhs > 0 && (!b || !x)) return fail(BO_EINVAL, "bo_trsv: null vector");
   Sched s;
   Args A;
   if (bo_status e = single_sched(L->n, L->l, L->ld, ws, ws_bytes, s, A)) return e;
+  if (nrhs == 0 || L->n == 0) return BO_OK;
   A.L = L->band;
   A.Ld = L->diag64;
-  A.bx = b;
-  A.x = x;
   A.xscale = 1.0;
+  const size_t esz = prec == BO_F64 ? sizeof(double) : sizeof(float);
   GpuBE be{stream};
-  return dev_status(bo::pipe_linear(be, s, A, (int)prec, trans ? bo::PASS_F2 : bo::PASS_FS), "bo_trsv");
+  const int pass = trans ? bo::PASS_F2 : bo::PASS_FS;
+  for (int64_t c = 0; c < nrhs; ++c) {
+    A.bx = (const char *)b + (size_t)(c * ldx) * esz;
+    A.x = (char *)x + (size_t)(c * ldx) * esz;
+    // the chunk products of L stay in ws from the first column's pipeline
+    const int e = c == 0 ? bo::pipe_linear(be, s, A, (int)prec, pass) : bo::seq_lin(be, s, A, (int)prec, pass);
+    if (e) return dev_status(e, "bo_trsv");
+  }
+  return BO_OK;
+}
+
+extern "C" size_t bo_subset_inv_workspace_size(int64_t n, int32_t k, int32_t kout) {
+  if (n < 0 || k < 0 || kout < k || kout > bo::KMAX_SUPPORTED) return 0;
+  if (kout == k) return bo_workspace_size(n, k);
+  const size_t base = bo_workspace_size(n, kout);
+  return base ? bo::align_up((size_t)n * (size_t)(kout + 1) * sizeof(double)) + base : 0;
 }
 
 extern "C" bo_status bo_subset_inv(bo_prec prec, const bo_band *L, bo_band *Sig, void *ws,
                                    size_t ws_bytes, hipStream_t stream) {
   if (bo_status e = check_band(L, prec, "L", true)) return e;
   if (bo_status e = check_band(Sig, prec, "Sigma", true)) return e;
-  if (bo_status e = check_same(L, Sig, "bo_subset_inv")) return e;
+  if (Sig->l < L->l) return fail(BO_EINVAL, "bo_subset_inv: Sigma narrower than L");
+  if (Sig->l == L->l) {
+    if (bo_status e = check_same(L, Sig, "bo_subset_inv")) return e;
+    Sched s;
+    Args A;
+    if (bo_status e = single_sched(L->n, L->l, L->ld, ws, ws_bytes, s, A)) return e;
+    A.L = L->band;
+    A.Ld = L->diag64;
+    A.S = Sig->band;
+    A.Sd = Sig->diag64;
+    GpuBE be{stream};
+    return dev_status(bo::pipe_linear(be, s, A, (int)prec, bo::PASS_F2), "bo_subset_inv");
+  }
+  // a wider output: Algorithm 3 on L widened to kout sub-diagonals with zeros
+  const int32_t kout = Sig->l;
+  const int64_t n = L->n;
+  if (Sig->n != n) return fail(BO_EINVAL, "bo_subset_inv: matrix orders differ");
+  if (kout > bo::KMAX_SUPPORTED)
+    return fail(BO_EUNSUPPORTED, "bo_subset_inv: output width k_out = " + std::to_string(kout) + " exceeds BO_KMAX");
+  if (Sig->ld != kout + 1) return fail(BO_EINVAL, "bo_subset_inv: a wider Sigma must be packed (ld = k_out + 1)");
+  const size_t need = bo_subset_inv_workspace_size(n, L->l, kout);
+  if (!ws || ws_bytes < need)
+    return fail(BO_EWORKSPACE, "bo_subset_inv: workspace needs " + std::to_string(need) + " bytes");
+  const size_t pad = bo::align_up((size_t)n * (size_t)(kout + 1) * sizeof(double));
   Sched s;
   Args A;
-  if (bo_status e = single_sched(L->n, L->l, L->ld, ws, ws_bytes, s, A)) return e;
-  A.L = L->band;
+  if (bo_status e = single_sched(n, kout, kout + 1, (char *)ws + pad, ws_bytes - pad, s, A)) return e;
+  if (n == 0) return BO_OK;
+  const int64_t el = n * (int64_t)(kout + 1);
+  if (prec == BO_F64)
+    hipLaunchKernelGGL(k_widen_lower<double>, dim3(blocks_for(el, 256)), dim3(256), 0, stream, n,
+                       (const double *)L->band, (int64_t)L->ld, L->l, (double *)ws, kout);
+  else
+    hipLaunchKernelGGL(k_widen_lower<float>, dim3(blocks_for(el, 256)), dim3(256), 0, stream, n,
+                       (const float *)L->band, (int64_t)L->ld, L->l, (float *)ws, kout);
+  if (hipGetLastError() != hipSuccess) return dev_status(-2, "bo_subset_inv");
+  A.L = ws;
   A.Ld = L->diag64;
   A.S = Sig->band;
   A.Sd = Sig->diag64;
@@ -692,7 +742,31 @@ static bo_status plan_args(const bo_plan *plan, bo_prec prec, const bo_batch_io 
   A.logdet = io->logdet;
   A.parts = io->parts;
   A.info = io->info;
+  A.loss = io->loss;
   return BO_OK;
+}
+
+// out = s_p * in over every problem of a plan (bo_plan_scale's kinds).
+static bo_status plan_scale_launch(const bo_plan *plan, bo_prec prec, int32_t kind, const double *g,
+                                   const void *in, const double *ind, void *out, double *outd, void *ws,
+                                   hipStream_t stream) {
+  const Sched &s = plan->s;
+  if (kind == BO_SCALE_PROBLEM) {
+    hipLaunchKernelGGL(k_problem_scale, dim3(blocks_for(s.nprob, 256)), dim3(256), 0, stream, (int64_t)s.nprob, g,
+                       (const double *)in, (double *)out);
+    return hipGetLastError() == hipSuccess ? BO_OK : dev_status(-2, "bo_plan_scale");
+  }
+  if (s.nchunk == 0) return BO_OK;
+  Args A{};
+  bo::bind_sched(s, ws, false, A);
+  if (prec == BO_F64)
+    hipLaunchKernelGGL(k_plan_scale<double>, dim3((unsigned)s.nchunk), dim3(256), 0, stream, A.probs, A.chunk_prob,
+                       (int)kind, g, (const double *)in, (const double *)nullptr, (double *)out, (double *)nullptr);
+  else
+    hipLaunchKernelGGL(k_plan_scale<float>, dim3((unsigned)s.nchunk), dim3(256), 0, stream, A.probs, A.chunk_prob,
+                       (int)kind, g, (const float *)in, kind == BO_SCALE_VEC ? nullptr : ind, (float *)out,
+                       kind == BO_SCALE_VEC ? nullptr : outd);
+  return hipGetLastError() == hipSuccess ? BO_OK : dev_status(-2, "bo_plan_scale");
 }
 
 extern "C" bo_status bo_plan_forward(const bo_plan *plan, bo_prec prec, const bo_batch_io *io,
@@ -716,9 +790,30 @@ extern "C" bo_status bo_plan_gauss_loss(const bo_plan *plan, bo_prec prec, const
     return fail(BO_EINVAL, "bo_plan_gauss_loss: y, S, z, x, Sig, Lbar, Qbar, parts, info required");
   if (prec == BO_MIXED && (!io->Sd || !io->Sigd || !io->Lbard || !io->Qbard))
     return fail(BO_EINVAL, "bo_plan_gauss_loss: BO_MIXED needs every FP64 diagonal");
+  if (io->Sbar && prec == BO_MIXED && !io->Sbard)
+    return fail(BO_EINVAL, "bo_plan_gauss_loss: BO_MIXED needs Sbard with Sbar");
   GpuBE be{stream};
-  return dev_status(bo::pipe_gauss_loss(be, plan->s, A, (int)prec, fuse_summaries()),
-                    "bo_plan_gauss_loss");
+  if (bo_status e = dev_status(bo::pipe_gauss_loss(be, plan->s, A, (int)prec, fuse_summaries()),
+                               "bo_plan_gauss_loss"))
+    return e;
+  if (!io->Sbar) return BO_OK;
+  // d tr(Q^{-1} S) / dS on S's stored entries: Sigma_ii, 2 Sigma_ij
+  return plan_scale_launch(plan, prec, BO_SCALE_BAND_SYM, nullptr, io->Sig, io->Sigd, io->Sbar, io->Sbard, ws,
+                           stream);
+}
+
+extern "C" bo_status bo_plan_scale(const bo_plan *plan, bo_prec prec, int32_t kind, const double *g, const void *in,
+                                   const double *ind, void *out, double *outd, void *ws, hipStream_t stream) {
+  if (!plan || !ws) return fail(BO_EINVAL, "bo_plan_scale: null plan or workspace");
+  if (prec != BO_F64 && prec != BO_MIXED) return fail(BO_EINVAL, "unknown precision");
+  if (kind != BO_SCALE_BAND && kind != BO_SCALE_BAND_SYM && kind != BO_SCALE_VEC && kind != BO_SCALE_PROBLEM)
+    return fail(BO_EINVAL, "bo_plan_scale: unknown kind");
+  if ((plan->s.rows > 0 || kind == BO_SCALE_PROBLEM) && (!in || !out))
+    return fail(BO_EINVAL, "bo_plan_scale: null array");
+  if ((kind == BO_SCALE_BAND || kind == BO_SCALE_BAND_SYM) && prec == BO_MIXED && plan->s.rows > 0 && (!ind || !outd))
+    return fail(BO_EINVAL, "bo_plan_scale: BO_MIXED bands need their FP64 diagonals");
+  if (prec == BO_F64 && (ind || outd)) return fail(BO_EINVAL, "bo_plan_scale: diagonals must be NULL for BO_F64");
+  return plan_scale_launch(plan, prec, kind, g, in, ind, out, outd, ws, stream);
 }
 
 extern "C" bo_status bo_plan_vi_kl(const bo_plan *plan, bo_prec prec, const bo_kl_io *io, void *ws,

@@ -294,7 +294,8 @@ __global__ void __launch_bounds__(NT) k_wide_f1(const Args A) {
     const int64_t o = blockIdx.x;
     if (A.parts) {
       A.parts[3 * o + 0] = fail_s ? NAN : 2.0 * lsum;
-      A.parts[3 * o + 1] = 0.0;
+      A.parts[3 * o + 1] = fail_s ? NAN : 0.0;
+      A.parts[3 * o + 2] = NAN;   // the trace, written by the F2 pass when it runs
     }
     A.info[o] = fail_s;
   }
@@ -306,7 +307,10 @@ __global__ void __launch_bounds__(NT) k_wide_f2(const Args A) {
   __shared__ MatF Xf, Pf, Wf, Ef, Tf;
   __shared__ double red[4];
   const Prob p = A.probs[blockIdx.x];
-  if (A.info[blockIdx.x] != 0) return;
+  if (A.info[blockIdx.x] != 0) {   // a failed factorisation: every part is NaN
+    if (threadIdx.x == 0 && A.parts) A.parts[3 * blockIdx.x + 2] = NAN;
+    return;
+  }
   const int64_t nb = nblocks(p.n);
   double tr = 0.0;
   for (int64_t b = nb - 1; b >= 0; --b) {

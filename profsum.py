@@ -1,8 +1,8 @@
 """Summaries of rocprofv3 output for the banded kernels.
 
-  python -m paper_1902_10078_amd.profsum stats KERNEL_STATS_CSV --cmd "..."
+  python profsum.py stats KERNEL_STATS_CSV --cmd "..."
       per-kernel call counts and durations (rocprofv3 --kernel-trace --stats)
-  python -m paper_1902_10078_amd.profsum traffic --fetch CSV --write CSV \\
+  python profsum.py traffic --fetch CSV --write CSV \\
       --copy-fetch CSV --copy-write CSV --copy-bytes B --rows R --cmd "..."
       HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counters (KiB per
       dispatch), each scaled by what the same counter reads for a plain copy of
@@ -24,6 +24,7 @@ import sys
 from collections import defaultdict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "paper_1902_10078_amd", "csrc")
 
 # rocprofv3 kernel name -> the library's profiling slot name
 _KERNEL_SLOTS = [
@@ -102,7 +103,7 @@ def source_hash(sources=None) -> str:
     h = hashlib.sha256()
     names = sorted(sources.split(",") if isinstance(sources, str) else (sources or _KERNEL_SOURCES))
     for f in names:
-        with open(os.path.join(HERE, "csrc", f), "rb") as fh:
+        with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(f.encode())
             h.update(fh.read())
     return h.hexdigest()[:16]

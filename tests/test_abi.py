@@ -91,9 +91,24 @@ def test_argument_errors_return_before_launch(L):
     # workspace too small
     assert L.bo_chol(0, bp(Q), bp(Lb), None, None, None, info, ctypes.c_void_p(4096), 16, None) == -3
     # unknown precision
-    assert L.bo_trsv(7, bp(Q), 0, ctypes.c_void_p(8), ctypes.c_void_p(8), None, 0, None) == -1
+    assert L.bo_trsv(7, bp(Q), 0, ctypes.c_void_p(8), ctypes.c_void_p(8), 1, 100, None, 0, None) == -1
     # null vectors
-    assert L.bo_trsv(0, bp(Q), 0, None, None, None, 0, None) == -1
+    assert L.bo_trsv(0, bp(Q), 0, None, None, 1, 100, None, 0, None) == -1
+    # several right-hand sides with ldx < n; a negative count
+    assert L.bo_trsv(0, bp(Q), 0, ctypes.c_void_p(8), ctypes.c_void_p(8), 2, 99, None, 0, None) == -1
+    assert L.bo_trsv(0, bp(Q), 0, ctypes.c_void_p(8), ctypes.c_void_p(8), -1, 100, None, 0, None) == -1
+    # subset inverse: output narrower than L, too wide, or wider and not packed
+    S2 = _band(100, 2, 0, 3)
+    assert L.bo_subset_inv(0, bp(Q), bp(S2), None, 0, None) == -1
+    S13 = _band(100, 13, 0, 14)
+    assert L.bo_subset_inv(0, bp(Q), bp(S13), ctypes.c_void_p(4096), 1 << 30, None) == -4
+    S7 = _band(100, 7, 0, 9)
+    assert L.bo_subset_inv(0, bp(Q), bp(S7), ctypes.c_void_p(4096), 1 << 30, None) == -1
+    S7p = _band(100, 7, 0, 8)
+    assert L.bo_subset_inv(0, bp(Q), bp(S7p), ctypes.c_void_p(4096), 16, None) == -3
+    assert L.bo_subset_inv_workspace_size(100, 3, 7) > L.bo_workspace_size(100, 7)
+    assert L.bo_subset_inv_workspace_size(100, 3, 3) == L.bo_workspace_size(100, 3)
+    assert L.bo_subset_inv_workspace_size(100, 3, 2) == 0
 
 
 def test_plan_errors_and_stats(L):

@@ -12,6 +12,7 @@ import pytest
 import torch
 
 import oracle
+import composed
 from bandutil import band_mask
 from paper_1902_10078_amd import inputs
 
@@ -229,7 +230,7 @@ def test_gauss_loss_batch_vs_dense_autograd_and_composed(ag):
             assert np.max(np.abs(got - ref)) <= 1e-10 * max(1.0, np.max(np.abs(ref)))
         # the same loss composed from separate operators through autograd
         Qp = cuda(Qs[p], True)
-        lc = ag.gauss_loss_composed(Qp, cuda(ys[p]), cuda(Ss[p]))
+        lc = composed.gauss_loss_composed(Qp, cuda(ys[p]), cuda(Ss[p]))
         lc.backward()
         assert abs(lc.item() - loss[p].item()) <= 1e-11 * max(1.0, abs(lr.item()))
         ref = gQ[bo_:bo_ + n * (k + 1)].reshape(n, k + 1) / float(g[p])

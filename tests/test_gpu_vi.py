@@ -12,6 +12,7 @@ import pytest
 import torch
 
 import oracle
+import composed
 from bandutil import band_mask, rel_err
 from paper_1902_10078_amd import inputs
 
@@ -188,7 +189,7 @@ def test_vi_kl_autograd_vs_dense_and_composed(bo):
             assert np.max(np.abs(got - rt)) <= 1e-10 * max(1.0, np.max(np.abs(rt)))
         # composed from the operators' own Functions
         cq, cp = cu(Lq[p]), cu(Lp[p])
-        lc = ag.vi_kl_composed(cq, cp, cu(mq[p]), cu(mp[p]))
+        lc = composed.vi_kl_composed(cq, cp, cu(mq[p]), cu(mp[p]))
         lc.backward()
         assert abs(lc.item() - kl[p].item()) <= 1e-11 * max(1.0, abs(ref.item()))
         refq = grads[0][o:o + sz].reshape(n, k + 1) / float(g[p])

@@ -122,5 +122,32 @@ def test_wide_non_spd_isolated(bo):
     out = run_wide(bo, ns, Qbad, None, loss=False)
     assert out["info"][0] == 301
     assert out["info"][1] == 0
+    assert np.all(np.isnan(out["parts"][0])), out["parts"][0]   # every part of the failed problem
+    assert np.all(np.isfinite(out["parts"][1]))
     good = run_wide(bo, ns, Qs, None, loss=False)
     assert np.array_equal(out["L"][1], good["L"][1])
+
+
+def test_wide_loss_full_size_sampled(bo):
+    """The wide workload at its full size, in the launch configuration the
+    benchmark times (one call over 8 problems of n = 2e5, k = 64): problems 0
+    and 7 against the FP64 oracle's scalar recurrences on the same stored
+    inputs, every output at 1e-4; every problem's info is 0."""
+    nb, n = 8, 200_000
+    Qs = [wide_matrix(b, 4, n) for b in range(nb)]
+    Ws = [wide_matrix(b, 5, n) for b in range(nb)]
+    out = run_wide(bo, [n] * nb, Qs, Ws)
+    assert np.all(out["info"] == 0)
+    m = band_mask(n, K)
+    for p in (0, nb - 1):
+        r = oracle.gauss_loss(Qs[p], K, np.zeros(n), Ws[p])
+        assert r["info"] == 0
+        Lb = out["Lbar"][p].copy()
+        Lb[:, 0] += 2.0 / r["L"][:, 0]
+        errs = dict(L=rel_err(out["L"][p] * m, r["L"]), Sig=rel_err(out["Sig"][p] * m, r["Sig"]),
+                    Qbar=rel_err(out["Qbar"][p] * m, r["Qbar"]), Lbar=rel_err(Lb * m, r["Lbar"]))
+        for i, nm in ((0, "logdet"), (2, "trace")):
+            errs[nm] = abs(out["parts"][p, i] - r["parts"][i]) / max(abs(r["parts"][i]), 1e-300)
+        print(f"wide full size, problem {p}: per-output relative errors {errs}")
+        for nm, e in errs.items():
+            assert e <= TOL, (p, nm, e)

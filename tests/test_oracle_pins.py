@@ -498,3 +498,70 @@ def test_batch_matches_single():
         assert np.array_equal(ybar[voff: voff + n], o["ybar"])
         off += n * (k + 1)
         voff += n
+
+
+def _pack(mats):
+    return np.concatenate([m.ravel() for m in mats])
+
+
+def test_forward_batch_matches_dense_per_problem():
+    """or_forward_batch (the uneven batch's forward list, Algorithms 1 and 3
+    with both solves of Section 4.1) against dense numpy on every problem of a
+    small uneven batch, including k = 0, k >= n and a one-row problem: a wrong
+    record or vector offset in the batch wrapper lands one problem's output in
+    another's slot and fails here."""
+    ns, ks = [9, 1, 31, 4, 17, 23], [2, 0, 5, 11, 0, 3]
+    Ls, ys = inputs.config2_factors(77, ns, ks)
+    Qs = [dense_to_lower(lower_to_dense(L) @ lower_to_dense(L).T, k) for L, k in zip(Ls, ks)]
+    L, z, x, Sig, logdet, info, th = oracle.forward_batch(ns, ks, _pack(Qs), np.concatenate(ys))
+    assert th >= 1 and np.all(info == 0)
+    off = voff = 0
+    for p, (n, k) in enumerate(zip(ns, ks)):
+        Qd = sym_to_dense(Qs[p], k)
+        Lref = np.linalg.cholesky(Qd)
+        Lp = L[off: off + n * (k + 1)].reshape(n, k + 1)
+        assert rel_err(lower_to_dense(Lp, k), Lref) < 1e-13, p
+        assert np.all(Lp[band_mask(n, k) == 0] == 0), p
+        sign, ld = np.linalg.slogdet(Qd)
+        assert sign > 0 and abs(logdet[p] - ld) <= 1e-12 * max(1.0, abs(ld)), p
+        zref = sla.solve_triangular(Lref, ys[p], lower=True)
+        assert rel_err(z[voff: voff + n], zref) < 1e-13, p
+        assert rel_err(x[voff: voff + n], np.linalg.solve(Qd, ys[p])) < 1e-12, p
+        Sp = Sig[off: off + n * (k + 1)].reshape(n, k + 1)
+        assert rel_err(Sp, dense_to_lower(np.linalg.inv(Qd), k)) < 1e-12, p
+        off += n * (k + 1)
+        voff += n
+
+
+def test_forward_batch_equals_single_calls_and_isolates_failures():
+    """A larger uneven batch equals the single-problem oracle calls bit for bit
+    (each of them pinned above to dense and LAPACK references), and a problem
+    whose Cholesky breaks down reports its LAPACK info without touching its
+    neighbours."""
+    ns, ks = [300, 2000, 5, 777, 1024, 64], [3, 11, 1, 5, 0, 7]
+    Ls, ys = inputs.config2_factors(78, ns, ks)
+    Qs = [oracle.gbmm(L, k, 0, L, k, 0, tB=1, lc=k, uc=0) for L, k in zip(Ls, ks)]
+    bad = 3
+    Qs[bad] = Qs[bad].copy()
+    Qs[bad][500, 0] = -1.0                # leading minor of order 501 fails
+    L, z, x, Sig, logdet, info, th = oracle.forward_batch(ns, ks, _pack(Qs), np.concatenate(ys))
+    Qd_bad = sym_to_dense(Qs[bad], ks[bad])
+    np.linalg.cholesky(Qd_bad[:500, :500])              # order 500 is still SPD
+    with pytest.raises(np.linalg.LinAlgError):
+        np.linalg.cholesky(Qd_bad[:501, :501])
+    off = voff = 0
+    for p, (n, k) in enumerate(zip(ns, ks)):
+        if p == bad:
+            assert info[p] == 501 and np.isnan(logdet[p])
+        else:
+            assert info[p] == 0
+            Lp, i1 = oracle.chol(Qs[p], k)
+            assert i1 == 0
+            assert np.array_equal(L[off: off + n * (k + 1)].reshape(n, k + 1), Lp)
+            assert logdet[p] == oracle.logdet(Lp, k)
+            zp = oracle.trsv(Lp, k, ys[p], trans=0)
+            assert np.array_equal(z[voff: voff + n], zp)
+            assert np.array_equal(x[voff: voff + n], oracle.trsv(Lp, k, zp, trans=1))
+            assert np.array_equal(Sig[off: off + n * (k + 1)].reshape(n, k + 1), oracle.subset_inv(Lp, k))
+        off += n * (k + 1)
+        voff += n

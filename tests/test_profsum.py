@@ -7,7 +7,7 @@ import re
 
 import pytest
 
-from paper_1902_10078_amd import profsum
+import profsum
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERN = os.path.join(HERE, "..", "paper_1902_10078_amd", "csrc", "bandops_kern.hip")
