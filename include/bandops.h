@@ -91,6 +91,22 @@ size_t bo_workspace_size(int64_t n, int32_t k);
 bo_status bo_chol(bo_prec prec, const bo_band *Q, bo_band *L, const void *y, void *z,
                   double *logdet, int32_t *info, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* bo_chol without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the same operation, arguments and results as
+ * bo_chol, with the workspace in a fixed device array of the library of
+ * BO_NOALLOC_SCRATCH_MB MiB per GPU (bo_chol_noalloc_scratch_bytes()), held
+ * until the process ends.  When bo_chol's schedule would need more, fewer
+ * chunks are used (same results up to rounding order); a problem whose
+ * smallest schedule still does not fit returns BO_EWORKSPACE.  The call
+ * allocates nothing.  Every call on one GPU shares that GPU's array: calls
+ * that overlap in time on one GPU (different streams, or host threads
+ * without ordering) race and must not be issued. */
+#define BO_NOALLOC_SCRATCH_MB 64
+size_t bo_chol_noalloc_scratch_bytes(void);
+bo_status bo_chol_noalloc(bo_prec prec, const bo_band *Q, bo_band *L, const void *y, void *z, double *logdet,
+                          int32_t *info, hipStream_t stream);
+
 /* S (Section 4.1): X = L^{-1} B (trans = 0) or X = L^{-T} B (trans = 1, the
  * upper-banded variant the gradients need, Section 4.1 "transposes") for nrhs
  * right-hand sides: column c of B and of X starts at element c * ldx (ldx >=

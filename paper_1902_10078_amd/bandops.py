@@ -83,6 +83,8 @@ def lib():
     sigs = {
         "bo_workspace_size": (ctypes.c_size_t, [_I64, _I32]),
         "bo_chol": (_I32, [_I32, bp, bp, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
+        "bo_chol_noalloc_scratch_bytes": (ctypes.c_size_t, []),
+        "bo_chol_noalloc": (_I32, [_I32, bp, bp, _P, _P, _P, _P, _P]),
         "bo_trsv": (_I32, [_I32, bp, _I32, _P, _P, _I64, _I64, _P, ctypes.c_size_t, _P]),
         "bo_subset_inv_workspace_size": (ctypes.c_size_t, [_I64, _I32, _I32]),
         "bo_subset_inv": (_I32, [_I32, bp, bp, _P, ctypes.c_size_t, _P]),
@@ -132,7 +134,7 @@ def lib():
     return L
 
 
-EXPORTED = ("bo_workspace_size", "bo_chol", "bo_trsv", "bo_subset_inv_workspace_size", "bo_subset_inv", "bo_gbmm", "bo_gbmv",
+EXPORTED = ("bo_workspace_size", "bo_chol", "bo_chol_noalloc_scratch_bytes", "bo_chol_noalloc", "bo_trsv", "bo_subset_inv_workspace_size", "bo_subset_inv", "bo_gbmm", "bo_gbmv",
             "bo_outer_band", "bo_solve_band_mat", "bo_solve_band_mat_workspace",
             "bo_solve_band_mat_bwd", "bo_chol_bwd", "bo_subset_inv_bwd", "bo_trsv_bwd", "bo_logdet_bwd",
             "bo_plan_create", "bo_plan_workspace_size", "bo_plan_upload", "bo_plan_forward",
@@ -240,6 +242,25 @@ def bo_chol(Q: Band, y: Optional[torch.Tensor] = None):
     qc, lc = Q.c(), L.c()
     _check(lib().bo_chol(prec, ctypes.byref(qc), ctypes.byref(lc), _ptr(y), _ptr(z), _ptr(logdet),
                          _ptr(info), _ptr(ws), ws.numel(), _stream()), "bo_chol")
+    return L, z, logdet, info
+
+
+def bo_chol_noalloc(Q: Band, y: Optional[torch.Tensor] = None, out=None):
+    """bo_chol with the library's fixed scratch array as its workspace (no
+    workspace argument, no allocation inside the call).  out: optional (L, z,
+    logdet, info) tensors to write into (the caller allocates them once);
+    returns them."""
+    prec = Q.prec
+    if out is None:
+        L = new_band(Q.n, Q.l, 0, prec, Q.band.device)
+        z = torch.empty_like(y) if y is not None else None
+        logdet = torch.zeros(1, dtype=torch.float64, device=Q.band.device)
+        info = torch.zeros(1, dtype=torch.int32, device=Q.band.device)
+    else:
+        L, z, logdet, info = out
+    qc, lc = Q.c(), L.c()
+    _check(lib().bo_chol_noalloc(prec, ctypes.byref(qc), ctypes.byref(lc), _ptr(y), _ptr(z), _ptr(logdet),
+                                 _ptr(info), _stream()), "bo_chol_noalloc")
     return L, z, logdet, info
 
 

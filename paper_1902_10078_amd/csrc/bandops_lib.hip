@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <functional>
+#include <mutex>
 #include <string>
 
 #include "../../include/bandops.h"
@@ -362,6 +363,77 @@ extern "C" bo_status bo_chol(bo_prec prec, const bo_band *Q, bo_band *L, const v
   A.info = info;
   GpuBE be{stream};
   return dev_status(bo::pipe_forward(be, s, A, (int)prec), "bo_chol");
+}
+
+// ------------------------------------------ Cholesky without allocation
+// The workspace of bo_chol_noalloc lives in this file-scope device array; each
+// GPU the library runs on holds its own copy until the process ends.  Host
+// code never passes the array's name to a kernel (on the host it is only a
+// stand-in): the entry point looks up the array's device address once per
+// device with hipGetSymbolAddress and uses that pointer.
+constexpr size_t kScratchBytes = (size_t)BO_NOALLOC_SCRATCH_MB << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];
+
+// Device address of the scratch array on the current device (looked up on the
+// first call there).
+static bo_status scratch_on_current_device(void **out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+    return fail(BO_EDEVICE, "bo_chol_noalloc: no current HIP device");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(BO_EDEVICE, std::string("bo_chol_noalloc: scratch address lookup failed: ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return BO_OK;
+}
+
+extern "C" size_t bo_chol_noalloc_scratch_bytes(void) { return kScratchBytes; }
+
+extern "C" bo_status bo_chol_noalloc(bo_prec prec, const bo_band *Q, bo_band *L, const void *y, void *z,
+                                     double *logdet, int32_t *info, hipStream_t stream) {
+  if (bo_status e = check_band(Q, prec, "Q", true)) return e;
+  if (bo_status e = check_band(L, prec, "L", true)) return e;
+  if (bo_status e = check_same(Q, L, "bo_chol_noalloc")) return e;
+  if ((y == nullptr) != (z == nullptr)) return fail(BO_EINVAL, "bo_chol_noalloc: y and z go together");
+  if (!info) return fail(BO_EINVAL, "bo_chol_noalloc: info is required");
+  if (Q->l > bo::KMAX_SUPPORTED)
+    return fail(BO_EUNSUPPORTED, "bo_chol_noalloc: bandwidth k = " + std::to_string(Q->l) + " exceeds BO_KMAX");
+  // The schedule of bo_chol, with fewer chunks when its workspace would not fit.
+  bo::ProbIn pi{Q->n, Q->l, Q->ld, 0, 0};
+  Sched s;
+  int64_t target = default_target_chunks();
+  for (;;) {
+    if (!bo::build_sched(&pi, 1, target, default_min_len(), group_size(), s))
+      return fail(BO_EINVAL, "bo_chol_noalloc: bad problem shape");
+    if (s.bytes <= kScratchBytes) break;
+    if (target <= 1)
+      return fail(BO_EWORKSPACE, "bo_chol_noalloc: the workspace (" + std::to_string(s.bytes) +
+                                     " bytes) exceeds the scratch array (" + std::to_string(kScratchBytes) + " bytes)");
+    target /= 2;
+  }
+  void *ws = nullptr;
+  if (bo_status e = scratch_on_current_device(&ws)) return e;
+  Args A{};
+  bo::bind_sched(s, ws, true, A);
+  A.Q = Q->band;
+  A.Qd = Q->diag64;
+  A.L = L->band;
+  A.Ld = L->diag64;
+  A.y = y;
+  A.z = z;
+  A.logdet = logdet;
+  A.info = info;
+  GpuBE be{stream};
+  return dev_status(bo::pipe_forward(be, s, A, (int)prec), "bo_chol_noalloc");
 }
 
 extern "C" bo_status bo_trsv(bo_prec prec, const bo_band *L, int trans, const void *b, void *x,
