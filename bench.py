@@ -167,13 +167,21 @@ def alg5_bytes_per_row(k: int, lr: int, u: int):
 
 
 def wide_bytes_per_row():
-    """Algorithmic bytes per row of the wide passes (mixed storage, k = 64)."""
+    """Algorithmic bytes per row of the wide passes' replays (mixed storage,
+    k = 64); the chunk summaries re-read inputs and are not counted."""
     wb, _ = record_bytes(64, 1)
     return {"wide_f1": 2 * wb,      # Q -> L
             "wide_f2": 2 * wb,      # W -> Sigma (trace term)
             "wide_b1": 4 * wb,      # L, Sigma, W -> Lbar
             "wide_b2": 3 * wb,      # L, Lbar -> Qbar
             "unit": 11 * wb}
+
+
+# Algorithmic flops per row of the wide loss unit: 9 k (k + 1) (Cholesky
+# k(k+1)/2 multiply-adds, Takahashi k(k+1), Algorithm 4 2k(k+1), Algorithm 2
+# k(k+1), two flops each), k = 64.
+WIDE_FLOP_PER_ROW = 9 * 64 * 65
+FP32_MFMA_PEAK_TFLOPS = 157.3
 
 
 def batch_bytes(ns, ks, prec, forward_only, vi=False, ml=False, ng=False, wh=False):
@@ -1171,6 +1179,11 @@ def main():
     unit_gbs = bb["unit"] / (ms / 1e3) / 1e9
     copy_rate = copy_gbs(torch, 1024)
     log(f"plain 1 GiB device copy: {copy_rate:.1f} GB/s (read + write)")
+    if wide:
+        tf = WIDE_FLOP_PER_ROW * rows / (ms / 1e3) / 1e12
+        roof["mfma"] = dict(bound="mfma", achieved=round(tf, 3), peak=FP32_MFMA_PEAK_TFLOPS, unit="TFLOP/s",
+                            frac=round(tf / FP32_MFMA_PEAK_TFLOPS, 5), flop_per_step=WIDE_FLOP_PER_ROW * rows,
+                            note="algorithmic flops of the whole unit over the step time")
     if args.kernels_json:
         with open(args.kernels_json, "w") as f:
             json.dump(dict(kernels=kern, ms_per_step=ms, rows=rows), f, indent=1)

@@ -454,22 +454,28 @@ bo_status bo_plan_destroy(bo_plan *plan);
  * tiles).  Dense block products run on the matrix cores in FP32 (MFMA); the
  * diagonal-block Cholesky, its inverse, the pivots and the log-determinant
  * are FP64.  Storage is BO_MIXED only: FP32 records of 65 elements (ld = 65)
- * plus FP64 diagonals.  probs[p].k must be 64; boff / voff as for plans.  One
- * workgroup walks the blocks of each problem in order.  The workspace holds
- * the problem table and two FP32 64 x 64 blocks per block row. */
+ * plus FP64 diagonals.  probs[p].k must be 64; boff / voff as for plans.
+ * Each problem's blocks are cut into chunks spread over the compute units and
+ * every pass is an exact chunked scan (chunk maps, an in-order combination per
+ * problem, replays from the exact entering states).  The workspace holds the
+ * problem and chunk tables, two FP32 64 x 64 blocks per block row and eleven
+ * per chunk; every call takes the same probs. */
 bo_status bo_wide_workspace_size(const bo_problem *probs, int32_t nprob, size_t *bytes);
-/* Copy the problem table into ws (synchronous).  Call it before any call that
- * uses ws, and before graph capture. */
+/* Copy the problem and chunk tables into ws (synchronous).  Call it before
+ * any call that uses ws, and before graph capture. */
 bo_status bo_wide_upload(const bo_problem *probs, int32_t nprob, void *ws, size_t ws_bytes);
 /* Forward: L (with Ld), Sig (with Sigd), parts[3p] = log det Q_p (parts may
  * be NULL) and info; io->Q and io->Qd are the input. */
-bo_status bo_wide_forward(int32_t nprob, const bo_batch_io *io, void *ws, hipStream_t stream);
+bo_status bo_wide_forward(const bo_problem *probs, int32_t nprob, const bo_batch_io *io, void *ws, size_t ws_bytes,
+                          hipStream_t stream);
 /* loss_p = log det Q_p + tr(Q_p^{-1} W_p), W_p given in io->S / io->Sd, and
  * its reverse mode: Algorithm 4 by blocks with Sigmabar = (W_ii, 2 W_ij), the
  * log-determinant sensitivity and Algorithm 2 by blocks.  Writes L, Sig,
  * Lbar (the subset-inverse part), Qbar (stored entries), parts (log det, 0,
- * trace) and info. */
-bo_status bo_wide_gauss_loss(int32_t nprob, const bo_batch_io *io, void *ws, hipStream_t stream);
+ * trace) and info; a problem whose factorisation fails gets info > 0 and NaN
+ * parts, its other outputs unspecified. */
+bo_status bo_wide_gauss_loss(const bo_problem *probs, int32_t nprob, const bo_batch_io *io, void *ws,
+                             size_t ws_bytes, hipStream_t stream);
 
 /* ------------------------------------------------------------- profiling */
 /* Kernel timing on the launch stream (a tracing aid).  While enabled, every

@@ -117,8 +117,10 @@ def lib():
         "bo_plan_destroy": (_I32, [_P]),
         "bo_wide_workspace_size": (_I32, [ctypes.POINTER(_Problem), _I32, ctypes.POINTER(ctypes.c_size_t)]),
         "bo_wide_upload": (_I32, [ctypes.POINTER(_Problem), _I32, _P, ctypes.c_size_t]),
-        "bo_wide_forward": (_I32, [_I32, ctypes.POINTER(_BatchIO), _P, _P]),
-        "bo_wide_gauss_loss": (_I32, [_I32, ctypes.POINTER(_BatchIO), _P, _P]),
+        "bo_wide_forward": (_I32, [ctypes.POINTER(_Problem), _I32, ctypes.POINTER(_BatchIO), _P, ctypes.c_size_t,
+                                    _P]),
+        "bo_wide_gauss_loss": (_I32, [ctypes.POINTER(_Problem), _I32, ctypes.POINTER(_BatchIO), _P,
+                                       ctypes.c_size_t, _P]),
         "bo_profile_enable": (_I32, [_I32]),
         "bo_profile_read": (_I32, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64), _I32]),
         "bo_profile_slots": (_I32, []),
@@ -547,6 +549,7 @@ class WidePlan:
             boff += n * (self.K + 1)
             voff += n
         self.band_elems, self.rows = boff, voff
+        self.probs = probs
         sz = ctypes.c_size_t()
         _check(lib().bo_wide_workspace_size(probs, self.nprob, ctypes.byref(sz)), "bo_wide_workspace_size")
         self.ws = torch.empty(max(sz.value, 256), dtype=torch.uint8, device=device)
@@ -559,11 +562,12 @@ class WidePlan:
         return io
 
     def forward(self, io: _BatchIO):
-        _check(lib().bo_wide_forward(self.nprob, ctypes.byref(io), _ptr(self.ws), _stream()), "bo_wide_forward")
+        _check(lib().bo_wide_forward(self.probs, self.nprob, ctypes.byref(io), _ptr(self.ws), self.ws.numel(),
+                                     _stream()), "bo_wide_forward")
 
     def gauss_loss(self, io: _BatchIO):
-        _check(lib().bo_wide_gauss_loss(self.nprob, ctypes.byref(io), _ptr(self.ws), _stream()),
-               "bo_wide_gauss_loss")
+        _check(lib().bo_wide_gauss_loss(self.probs, self.nprob, ctypes.byref(io), _ptr(self.ws), self.ws.numel(),
+                                        _stream()), "bo_wide_gauss_loss")
 
 
 # ------------------------------------------------------------- graph GMRFs

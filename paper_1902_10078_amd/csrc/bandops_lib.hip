@@ -138,7 +138,7 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const Args A) {
 // bo_profile_read() waits for them and sums the durations per step kind.
 // + clear, finalize, the four wide passes, the KL term's row kernels, the
 // three launches of Algorithm 5 and its reverse mode
-constexpr int kProfSlots = bo::ST_COUNT + 21;
+constexpr int kProfSlots = bo::ST_COUNT + 27;
 constexpr int kSlotViPre = bo::ST_COUNT + 6, kSlotViPost = bo::ST_COUNT + 7, kSlotViNeg = bo::ST_COUNT + 8;
 constexpr int kSlotSolveMat = bo::ST_COUNT + 9, kSlotSolveMatG = bo::ST_COUNT + 10, kSlotSolveMatOut = bo::ST_COUNT + 11;
 constexpr int kSlotMlPost = bo::ST_COUNT + 13, kSlotMlFinal = bo::ST_COUNT + 14;   // + 12: unused
@@ -184,9 +184,10 @@ int bo_profile_graph(int which, hipStream_t s, const std::function<int()> &launc
 }
 
 // Launch timing for the other translation units of the library (C++ linkage):
-// the wide passes use slots ST_COUNT + 2 + which, which = 0..3.
+// the wide passes' replays use slots ST_COUNT + 2 + which, which = 0..3, their
+// summaries, scans and finalisation ST_COUNT + 21 + (which - 4), which = 4..9.
 int bo_profile_wide(int which, hipStream_t s, const std::function<int()> &launch) {
-  return profiled(bo::ST_COUNT + 2 + which, s, launch);
+  return profiled(which < 4 ? bo::ST_COUNT + 2 + which : bo::ST_COUNT + 21 + (which - 4), s, launch);
 }
 
 namespace {
@@ -299,7 +300,7 @@ static const char *const kStepNames[kProfSlots] = {
     "asc_chunk_sweep", "desc_group_compose", "desc_group_sweep", "desc_chunk_sweep",
     "clear_partials", "finalize", "wide_f1", "wide_f2", "wide_b1", "wide_b2", "vi_pre", "vi_post", "vi_neg", "solve_mat", "solve_mat_g", "solve_mat_out",
     "reserved", "ml_post", "ml_finalize", "ng_pre", "ng_post", "ng_neg", "ng_finalize", "csr_to_band",
-    "band_to_csr"};
+    "band_to_csr", "wide_f1_sum", "wide_f1_scan", "wide_lin_sum", "wide_lin_scan", "wide_b2_sum", "wide_finalize"};
 
 extern "C" int bo_profile_slots(void) { return kProfSlots; }
 

@@ -9,6 +9,8 @@
 // then each lane's stepper consumes its rows from LDS.  One workgroup is one
 // wavefront.  Records must be packed (stride K+1).
 #pragma once
+#include <type_traits>
+
 #include "bandops_step.hpp"
 
 namespace bo {
@@ -21,6 +23,16 @@ constexpr int kWave = 64;
 #define BO_TILE_BYTES 40960
 #endif
 constexpr int kTileBytes = BO_TILE_BYTES;
+// Tile buffers per array.  With 2, the loads of a wave's next tile are issued
+// before it steps through the current one (each buffer gets half the budget).
+// The wait at the next tile then also covers the stores the row work has just
+// issued (one counter tracks loads and stores), and halving the tiles doubles
+// those waits: measured slower on every kernel that writes, so 1 is the
+// default.
+#ifndef BO_TILE_BUFS
+#define BO_TILE_BUFS 1
+#endif
+constexpr int kTileBufs = BO_TILE_BUFS;
 
 // Maximum over the wavefront (one workgroup = one wavefront).
 __device__ __forceinline__ int64_t wave_max(int64_t v) {
@@ -51,12 +63,13 @@ template <int K, typename T, int NB, int NV, int TR> constexpr int tile_lds_byte
   return NB * Geom<T, K + 1, TR>::WORDS * 4 + (sizeof(T) == 4 ? NB * Geom<double, 1, TR>::WORDS * 4 : 0) +
          NV * Geom<T, 1, TR>::WORDS * 4;
 }
-// Rows per tile: the most (up to 32) whose tiles fit the budget, at least 2.
+// Rows per tile: the most (up to 32) whose tiles (kTileBufs sets) fit the
+// budget, at least 2.
 template <int K, typename T, int NB, int NV, int TR = 32> constexpr int tile_rows() {
   if constexpr (TR <= 2) {
     return 2;
   } else {
-    if constexpr (tile_lds_bytes<K, T, NB, NV, TR>() <= kTileBytes) return TR;
+    if constexpr (kTileBufs * tile_lds_bytes<K, T, NB, NV, TR>() <= kTileBytes) return TR;
     else return tile_rows<K, T, NB, NV, TR - 1>();
   }
 }
@@ -70,7 +83,7 @@ template <int K, typename T, int NB, int NV, int TR, int VM = 8> constexpr int v
     return 1;
   } else {
     constexpr int bands = NB * Geom<T, K + 1, TR>::WORDS * 4 + (sizeof(T) == 4 ? NB * Geom<double, 1, TR>::WORDS * 4 : 0);
-    if constexpr (bands + NV * Geom<T, 1, TR * VM>::WORDS * 4 <= kTileBytes - 2048) return VM;
+    if constexpr (kTileBufs * (bands + NV * Geom<T, 1, TR * VM>::WORDS * 4) <= kTileBytes - 2048) return VM;
     else return vec_mult<K, T, NB, NV, TR, VM - 1>();
   }
 }
@@ -160,6 +173,12 @@ template <typename T> struct VecIn {
 // Streams rows [lo, hi) of each lane (ascending, or descending when DESC) and
 // calls body(j, rec, val) per row with rec[b] = record j(+shift_b) of band b
 // (slots past the matrix end zeroed) and val[v] = vector v at row j.
+//
+// Tile i of every array goes to buffer i % kTileBufs.  With two buffers the
+// order per tile is: wait for tile i's loads, barrier, issue tile i+1's loads
+// into the other buffer (whose tile i-1 every lane has finished with at the
+// barrier), step through tile i.  A vector tile spans VM band tiles and
+// alternates between its own two buffers the same way.
 template <int K, typename T, int NB, int NV, bool DESC, class Body>
 __device__ __forceinline__ void stream_rows(const BandIn<T> (&bands)[NB > 0 ? NB : 1],
                                             const VecIn<T> (&vecs)[NV > 0 ? NV : 1], int64_t lo,
@@ -170,49 +189,75 @@ __device__ __forceinline__ void stream_rows(const BandIn<T> (&bands)[NB > 0 ? NB
   constexpr int VR = TR * VM;   // rows per vector tile
   constexpr bool MIXED = sizeof(T) == 4;
   constexpr int NB1 = NB > 0 ? NB : 1, NV1 = NV > 0 ? NV : 1;
+  constexpr int NBUF = kTileBufs;
+  static_assert(NBUF == 1 || NBUF == 2, "one or two tile buffers");
   using GB = Geom<T, W, TR>;
   using GD = Geom<double, 1, TR>;
   using GV = Geom<T, 1, VR>;
-  __shared__ __attribute__((aligned(16))) uint32_t sb[NB1][GB::WORDS];
-  __shared__ __attribute__((aligned(16))) uint32_t sd[MIXED ? NB1 : 1][MIXED ? GD::WORDS : 1];
-  __shared__ __attribute__((aligned(16))) uint32_t sv[NV1][NV > 0 ? GV::WORDS : 1];
+  __shared__ __attribute__((aligned(16))) uint32_t sb[NBUF][NB1][GB::WORDS];
+  __shared__ __attribute__((aligned(16))) uint32_t sd[NBUF][MIXED ? NB1 : 1][MIXED ? GD::WORDS : 1];
+  __shared__ __attribute__((aligned(16))) uint32_t sv[NBUF][NV1][NV > 0 ? GV::WORDS : 1];
 
   const int lane = threadIdx.x;
   const int64_t len = hi > lo ? hi - lo : 0;
   const int64_t maxlen = wave_max(len);
-  int pitch_v[NV1];
-  int64_t vbase = 0;   // first processed row of the current vector tile
+  // Segment pitches and vector-tile origins per buffer.  Band buffers are
+  // indexed by compile-time constants (the tile loop is unrolled by NBUF);
+  // the vector buffer of a tile is a run-time choice between two, made with
+  // selects so that nothing here is indexed dynamically.
+  int pitch_b[NBUF][NB1], pitch_d[NBUF][NB1];
+  int pv0[NV1], pv1[NV1];
+  int64_t vb0 = 0, vb1 = 0;
 #pragma unroll
-  for (int vi = 0; vi < NV1; ++vi) pitch_v[vi] = 0;
-  for (int64_t t0 = 0; t0 < maxlen; t0 += TR) {
+  for (int vi = 0; vi < NV1; ++vi) pv0[vi] = pv1[vi] = 0;
+#pragma unroll
+  for (int u = 0; u < NBUF; ++u)
+#pragma unroll
+    for (int bi = 0; bi < NB1; ++bi) pitch_b[u][bi] = pitch_d[u][bi] = 0;
+  // Issue the loads of tile `it` (rows from it * TR) into band buffer U.
+  auto fill = [&](int64_t it, auto Uc) {
+    constexpr int U = decltype(Uc)::value;
+    const int64_t t0 = it * TR;
     const int cnt = (int)(len - t0 < TR ? (len - t0 > 0 ? len - t0 : 0) : TR);
-    const int64_t r0 = DESC ? hi - t0 - cnt : lo + t0;   // first row of this tile
-    int pitch_b[NB1], pitch_d[NB1];
+    const int64_t r0 = DESC ? hi - t0 - cnt : lo + t0;
 #pragma unroll
     for (int bi = 0; bi < NB; ++bi) {
       int64_t s0 = r0 + bands[bi].shift;
       int c = cnt;
       if (s0 + c > n) c = (int)(n - s0 > 0 ? n - s0 : 0);
       const bool on = bands[bi].p && c > 0;
-      pitch_b[bi] = lds_fill<T, W, TR>(sb[bi], on ? bands[bi].p + s0 * ld : nullptr, c, lane);
-      pitch_d[bi] = 0;
+      pitch_b[U][bi] = lds_fill<T, W, TR>(sb[U][bi], on ? bands[bi].p + s0 * ld : nullptr, c, lane);
       if (MIXED)
-        pitch_d[bi] = lds_fill<double, 1, TR>(sd[MIXED ? bi : 0],
-                                              (on && bands[bi].diag) ? bands[bi].diag + s0 : nullptr, c, lane);
+        pitch_d[U][bi] = lds_fill<double, 1, TR>(sd[U][MIXED ? bi : 0],
+                                                 (on && bands[bi].diag) ? bands[bi].diag + s0 : nullptr, c, lane);
     }
-    if ((t0 / TR) % VM == 0) {   // next vector tile: rows of the following VM band tiles
+    if (NV > 0 && it % VM == 0) {   // next vector tile: rows of the following VM band tiles
+      const bool v1 = NBUF > 1 && ((it / VM) & 1);
       const int vcnt = (int)(len - t0 < VR ? (len - t0 > 0 ? len - t0 : 0) : VR);
-      vbase = DESC ? hi - t0 - vcnt : lo + t0;
+      const int64_t vb = DESC ? hi - t0 - vcnt : lo + t0;
+      if (v1) vb1 = vb;
+      else vb0 = vb;
 #pragma unroll
       for (int vi = 0; vi < NV; ++vi) {
-        int64_t s0 = vbase + vecs[vi].shift;
+        int64_t s0 = vb + vecs[vi].shift;
         int c = vcnt;
         if (s0 + c > n) c = (int)(n - s0 > 0 ? n - s0 : 0);
-        pitch_v[vi] = lds_fill<T, 1, VR>(sv[vi], (vecs[vi].p && c > 0) ? vecs[vi].p + s0 : nullptr, c, lane);
+        const T *src = (vecs[vi].p && c > 0) ? vecs[vi].p + s0 : nullptr;
+        // buffer 1 of vector vi lies NV1 * GV::WORDS words past buffer 0
+        const int pv = lds_fill<T, 1, VR>(&sv[0][vi][0] + (v1 ? (NBUF - 1) * NV1 * GV::WORDS : 0), src, c, lane);
+        if (v1) pv1[vi] = pv;
+        else pv0[vi] = pv;
       }
     }
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
+  };
+  // Step through the rows of tile `it`, staged in band buffer U.
+  auto consume = [&](int64_t it, auto Uc) {
+    constexpr int U = decltype(Uc)::value;
+    const bool v1 = NBUF > 1 && ((it / VM) & 1);
+    const int64_t vbase = v1 ? vb1 : vb0;
+    const int64_t t0 = it * TR;
+    const int cnt = (int)(len - t0 < TR ? (len - t0 > 0 ? len - t0 : 0) : TR);
+    const int64_t r0 = DESC ? hi - t0 - cnt : lo + t0;
 #pragma unroll 1
     for (int t = 0; t < TR; ++t) {
       if (t < cnt) {
@@ -223,25 +268,56 @@ __device__ __forceinline__ void stream_rows(const BandIn<T> (&bands)[NB > 0 ? NB
 #pragma unroll
         for (int bi = 0; bi < NB; ++bi) {
           const int64_t js = j + bands[bi].shift;
-          lds_cptr<T> row = (lds_cptr<T>)((lds_cptr<char>)(lds_ptr_t)sb[bi] + lane * pitch_b[bi]) + r * W;
+          lds_cptr<T> row = (lds_cptr<T>)((lds_cptr<char>)(lds_ptr_t)sb[U][bi] + lane * pitch_b[U][bi]) + r * W;
 #pragma unroll
           for (int d = 0; d <= K; ++d) {
             double x = (double)row[d];
             if (d == 0 && MIXED && bands[bi].diag)
-              x = ((lds_cptr<double>)((lds_cptr<char>)(lds_ptr_t)sd[MIXED ? bi : 0] + lane * pitch_d[bi]))[r];
+              x = ((lds_cptr<double>)((lds_cptr<char>)(lds_ptr_t)sd[U][MIXED ? bi : 0] + lane * pitch_d[U][bi]))[r];
             rec[bi][d] = (bands[bi].p && js + d < n) ? x : 0.0;
           }
         }
         const int rv = (int)(j - vbase);
 #pragma unroll
-        for (int vi = 0; vi < NV; ++vi)
-          val[vi] = (vecs[vi].p && j + vecs[vi].shift < n)
-                        ? (double)((lds_cptr<T>)((lds_cptr<char>)(lds_ptr_t)sv[vi] + lane * pitch_v[vi]))[rv]
-                        : 0.0;
+        for (int vi = 0; vi < NV; ++vi) {
+          // buffer 1 of vector vi lies NV1 * GV::WORDS words past buffer 0
+          const int voff = v1 ? (NBUF - 1) * NV1 * GV::WORDS * 4 + lane * pv1[vi] : lane * pv0[vi];
+          lds_cptr<char> vrow = (lds_cptr<char>)(lds_ptr_t)sv[0][vi] + voff;
+          val[vi] = (vecs[vi].p && j + vecs[vi].shift < n) ? (double)((lds_cptr<T>)vrow)[rv] : 0.0;
+        }
         body(j, rec, val);
       }
     }
-    __syncthreads();
+  };
+  using C0 = std::integral_constant<int, 0>;
+  using CL = std::integral_constant<int, NBUF - 1>;
+  const int64_t ntile = (maxlen + TR - 1) / TR;
+  if constexpr (NBUF == 1) {
+#pragma unroll 1
+    for (int64_t it = 0; it < ntile; ++it) {
+      fill(it, C0{});
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      consume(it, C0{});
+      __syncthreads();
+    }
+  } else {
+    // wait for tile it, barrier (every lane is done with the other buffer),
+    // issue tile it+1 into the other buffer, step through tile it
+    if (ntile > 0) fill(0, C0{});
+#pragma unroll 1
+    for (int64_t it = 0; it < ntile; it += 2) {
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      if (it + 1 < ntile) fill(it + 1, CL{});
+      consume(it, C0{});
+      if (it + 1 < ntile) {
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (it + 2 < ntile) fill(it + 2, C0{});
+        consume(it + 1, CL{});
+      }
+    }
   }
 }
 

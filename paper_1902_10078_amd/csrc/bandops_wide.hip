@@ -22,14 +22,34 @@
 // (FP64 pivots and log-determinant); every dense block product runs on the
 // matrix cores as FP32 MFMA (v_mfma_f32_16x16x4_f32).
 //
-// Parallelism: one workgroup (four wavefronts) per problem walks its blocks in
-// order; each block step is a handful of 64 x 64 MFMA products plus the FP64
-// factorisation of one diagonal block.  The factor's inverse X_b and P_b are
-// kept in the workspace between passes.
+// Parallelism: each problem's blocks are cut into chunks of consecutive
+// blocks, one workgroup (four wavefronts) per chunk, and every pass is an exact
+// chunked scan:
+//   * the subset inverse and both reverse passes are block congruences with
+//     the same P_b: Sigma_bb = P_b^T Sigma_{b+1,b+1} P_b + X_b^T X_b, the
+//     adjoint of Sigma_bb carried upwards as C_{b+1} = P_b sym(C_b) P_b^T + ...,
+//     and the adjoint of S_b (dS_{b+1} = P_b dS_b P_b^T, as S_{b+1} = Q -
+//     C_b S_b^{-1} C_b^T) carried downwards as Sbar_b = P_b^T Sbar_{b+1} P_b
+//     + ...; a chunk [a, e) maps its entering state affinely through
+//     R = P_{e-1} ... P_a and its zero-state run M;
+//   * the Cholesky's Schur-complement recurrence is not linear: a chunk maps
+//     the correction E_a subtracted from its first diagonal block to the one
+//     it leaves on the next block, E_e = D + B (A - E_a)^{-1} B^T, where
+//     eliminating the chunk's interior blocks gives A (the Schur complement on
+//     its first block), B (the coupling of the next block to the first) and D
+//     (the correction on the next block) -- Algorithm 1's elimination order
+//     within the chunk, the block form of the scalar passes' chunk maps.
+// Per pass: zero-state summaries of every chunk, one workgroup per problem
+// applying the chunk maps in order (a few 64 x 64 products per chunk), and a
+// replay of every chunk from its exact entering state that writes the outputs.
+// Nothing is reordered, so the results are the sequential block recurrences'
+// up to rounding.  X_b and P_b are kept in the workspace between passes.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
 
+#include <algorithm>
+#include <cstdlib>
 #include <functional>
 #include <string>
 #include <vector>
@@ -51,7 +71,17 @@ typedef float float4_ __attribute__((ext_vector_type(4)));
 
 struct Prob {
   int64_t n, boff, voff, wsoff;   // wsoff: first block of this problem in the workspace
+  int32_t chunk0, nchunk;         // its chunks: consecutive ids [chunk0, chunk0 + nchunk)
 };
+struct Chunk {
+  int32_t prob, pad;
+  int64_t b0, b1;                 // blocks [b0, b1) of its problem
+};
+// Per-chunk workspace, in 64 x 64 FP32 matrices: the Cholesky map (A, B, D),
+// the entering states of the four passes, the block product R of the linear
+// passes and their zero-state maps.
+enum CwSlot { CW_A = 0, CW_B, CW_D, CW_E, CW_R, CW_MF2, CW_MB1, CW_MB2, CW_SF2, CW_SB1, CW_SB2, CW_N };
+constexpr int64_t kMat = (int64_t)NB * NB;
 
 struct Args {
   const Prob *probs;
@@ -62,6 +92,9 @@ struct Args {
   float *Lb; double *Lbd;
   float *Qb; double *Qbd;
   float *ws;                            // X_b, P_b per block
+  const Chunk *chunks;
+  float *cws;                           // CW_N matrices per chunk
+  double *cpart;                        // per chunk: log-sum, failing row (1-based, 0: none), trace
   double *parts;                        // per problem: logdet, 0, trace
   int32_t *info;
 };
@@ -256,64 +289,270 @@ __device__ double block_sum(double v, double *red) {
   return red[0] + red[1] + red[2] + red[3];
 }
 
-// ============================================================= F1 (forward)
-// Cholesky by blocks: L, log det, X_b and P_b = M_b X_b for the later passes.
-__global__ void __launch_bounds__(NT) k_wide_f1(const Args A) {
+// ------------------------------------------------------ chunk workspace
+__device__ __forceinline__ float *cw(const Args &A, int32_t c, int slot) {
+  return A.cws + ((int64_t)c * CW_N + slot) * kMat;
+}
+__device__ __forceinline__ void set_zero(MatF &M) {
+  for (int e = threadIdx.x; e < NB * NB; e += NT) M[e / NB][e % NB] = 0.f;
+}
+__device__ __forceinline__ void set_identity(MatF &M) {
+  for (int e = threadIdx.x; e < NB * NB; e += NT) M[e / NB][e % NB] = (e / NB == e % NB) ? 1.f : 0.f;
+}
+__device__ __forceinline__ void set_nan(MatF &M) {
+  for (int e = threadIdx.x; e < NB * NB; e += NT) M[e / NB][e % NB] = NAN;
+}
+
+// ============================================== F1 (Algorithm 1 by blocks)
+// Chunk summary: eliminate the chunk's interior blocks a+1 .. e-1 with
+// Algorithm 1's block steps, carrying V (the coupling of the next block to
+// the first block a), Z (the correction on block a) and Pc (the correction on
+// the next diagonal block):
+//   S_i = Q_ii - Pc,  X = chol(S_i)^{-1},  Y = X V,  Z += Y^T Y,
+//   W = X C_i^T,  Pc = W^T W,  V = -W^T Y        (V starts as C_a)
+// giving the map A = Q_aa - Z, B = V, D = Pc of E_a -> E_e.  A problem's last
+// chunk has no successor and no map.
+__global__ void __launch_bounds__(NT) k_wf1_sum(const Args A) {
+  __shared__ MatD S, X;   // X also holds Y and W once its FP32 copy is taken
+  __shared__ MatF Xf, V, Z, Pc, Cf;
+  __shared__ double dg[NB], rdg[NB];
+  const int32_t c = blockIdx.x;
+  const Chunk ch = A.chunks[c];
+  const Prob p = A.probs[ch.prob];
+  if (ch.b1 >= nblocks(p.n)) return;
+  MatF &Y = *reinterpret_cast<MatF *>(&X[0][0]);
+  MatF &Wt = *reinterpret_cast<MatF *>(reinterpret_cast<char *>(&X[0][0]) + sizeof(MatF));
+  float *Am = cw(A, c, CW_A), *Bm = cw(A, c, CW_B), *Dm = cw(A, c, CW_D);
+  load_blocks(A.Q, A.Qd, p, ch.b0, S, &V);
+  for (int e = threadIdx.x; e < NB * NB; e += NT) {
+    Am[e] = (float)S[e / NB][e % NB];
+    Z[e / NB][e % NB] = 0.f;
+    Pc[e / NB][e % NB] = 0.f;
+  }
+  __syncthreads();
+  double unused = 0.0;
+  bool bad = false;
+  for (int64_t i = ch.b0 + 1; i < ch.b1; ++i) {
+    load_blocks(A.Q, A.Qd, p, i, S, &Cf);
+    for (int e = threadIdx.x; e < NB * NB; e += NT) S[e / NB][e % NB] -= (double)Pc[e / NB][e % NB];
+    __syncthreads();
+    if (potrf64(S, dg, rdg, unused)) {
+      bad = true;
+      break;
+    }
+    trtri64(S, rdg, X);
+    for (int e = threadIdx.x; e < NB * NB; e += NT) Xf[e / NB][e % NB] = (float)X[e / NB][e % NB];
+    gemm64<false, false>(Xf, V, 1.f, [&](int r, int q, float v) { Y[r][q] = v; });
+    gemm64<true, false>(Y, Y, 1.f, [&](int r, int q, float v) { Z[r][q] += v; });
+    gemm64<false, true>(Xf, Cf, 1.f, [&](int r, int q, float v) { Wt[r][q] = v; });
+    gemm64<true, false>(Wt, Wt, 1.f, [&](int r, int q, float v) { Pc[r][q] = v; });
+    gemm64<true, false>(Wt, Y, -1.f, [&](int r, int q, float v) { V[r][q] = v; });
+  }
+  __syncthreads();
+  // an interior block that is not positive definite: the leading part of Q is
+  // not either, and the replay of this chunk reports where; the map is NaN
+  for (int e = threadIdx.x; e < NB * NB; e += NT) {
+    const int r = e / NB, q = e % NB;
+    Am[e] = bad ? NAN : Am[e] - Z[r][q];
+    Bm[e] = bad ? NAN : V[r][q];
+    Dm[e] = bad ? NAN : Pc[r][q];
+  }
+}
+
+// The chunk maps of each problem in order, one workgroup per problem: the
+// correction entering chunk c+1 is E_{c+1} = D_c + (X B_c^T)^T (X B_c^T),
+// X = chol(A_c - E_c)^{-1}; E_0 = 0.
+__global__ void __launch_bounds__(NT) k_wf1_scan(const Args A) {
+  __shared__ MatD S, X;
+  __shared__ MatF Xf, Bf, Ef, Y;
+  __shared__ double dg[NB], rdg[NB];
+  const Prob p = A.probs[blockIdx.x];
+  set_zero(Ef);
+  double unused = 0.0;
+  for (int32_t c = p.chunk0; c < p.chunk0 + p.nchunk; ++c) {
+    ws_store(cw(A, c, CW_E), Ef);
+    if (c == p.chunk0 + p.nchunk - 1) break;
+    const float *Am = cw(A, c, CW_A);
+    __syncthreads();
+    for (int e = threadIdx.x; e < NB * NB; e += NT) S[e / NB][e % NB] = (double)Am[e] - (double)Ef[e / NB][e % NB];
+    ws_load(cw(A, c, CW_B), Bf);
+    if (potrf64(S, dg, rdg, unused)) {   // reported by this chunk's replay
+      __syncthreads();
+      set_nan(Ef);
+      __syncthreads();
+      continue;
+    }
+    trtri64(S, rdg, X);
+    for (int e = threadIdx.x; e < NB * NB; e += NT) Xf[e / NB][e % NB] = (float)X[e / NB][e % NB];
+    gemm64<false, true>(Xf, Bf, 1.f, [&](int r, int q, float v) { Y[r][q] = v; });
+    ws_load(cw(A, c, CW_D), Ef);
+    gemm64<true, false>(Y, Y, 1.f, [&](int r, int q, float v) { Ef[r][q] += v; });
+  }
+}
+
+// Chunk replay: Algorithm 1 by blocks from the exact correction entering the
+// chunk: L, the log-determinant partial, X_b and P_b = M_b X_b for the later
+// passes; the first failing row (1-based) of the chunk, if any.
+__global__ void __launch_bounds__(NT) k_wf1_rep(const Args A) {
   __shared__ MatD S, X;
   __shared__ MatF Cf, Mf, Xf;
   __shared__ double dg[NB], rdg[NB];
-  __shared__ int fail_s;
-  const Prob p = A.probs[blockIdx.x];
-  const int64_t nb = nblocks(p.n);
+  const int32_t c = blockIdx.x;
+  const Chunk ch = A.chunks[c];
+  const Prob p = A.probs[ch.prob];
   double lsum = 0.0;
-  int fail = 0;
-  for (int64_t b = 0; b < nb && !fail; ++b) {
+  int64_t fail = 0;
+  for (int64_t b = ch.b0; b < ch.b1; ++b) {
     load_blocks(A.Q, A.Qd, p, b, S, &Cf);
-    if (b > 0)   // S_b = Q_bb - M_{b-1} M_{b-1}^T
+    if (b > ch.b0) {   // S_b = Q_bb - M_{b-1} M_{b-1}^T
       gemm64<false, true>(Mf, Mf, 1.f, [&](int i, int j, float v) { S[i][j] -= (double)v; });
+    } else if (b > 0) {   // the correction entering the chunk
+      const float *E = cw(A, c, CW_E);
+      for (int e = threadIdx.x; e < NB * NB; e += NT) S[e / NB][e % NB] -= (double)E[e];
+      __syncthreads();
+    }
     const int r = potrf64(S, dg, rdg, lsum);
     if (r) {
-      fail = (int)(NB * b + r);
+      fail = NB * b + r;
       break;
     }
     trtri64(S, rdg, X);
     for (int e = threadIdx.x; e < NB * NB; e += NT) Xf[e / NB][e % NB] = (float)X[e / NB][e % NB];
     // M_b = C_b X_b^T (upper triangular)
     gemm64<false, true>(Cf, Xf, 1.f, [&](int i, int j, float v) { Mf[i][j] = v; });
-    store_blocks(A.L, A.Ld, p, b, [&](int c) { return dg[c]; }, [&](int i, int c) { return S[i][c]; },
-                 [&](int rr, int c) { return (double)Mf[rr][c]; });
+    store_blocks(A.L, A.Ld, p, b, [&](int cc) { return dg[cc]; }, [&](int i, int cc) { return S[i][cc]; },
+                 [&](int rr, int cc) { return (double)Mf[rr][cc]; });
     float *wsb = A.ws + (p.wsoff + b) * kBlockWs;
     ws_store(wsb, Xf);
     // P_b = M_b X_b (into Cf, which is free now)
     gemm64<false, false>(Mf, Xf, 1.f, [&](int i, int j, float v) { Cf[i][j] = v; });
     ws_store(wsb + NB * NB, Cf);
   }
-  if (threadIdx.x == 0) fail_s = fail;
-  __syncthreads();
   if (threadIdx.x == 0) {
-    const int64_t o = blockIdx.x;
-    if (A.parts) {
-      A.parts[3 * o + 0] = fail_s ? NAN : 2.0 * lsum;
-      A.parts[3 * o + 1] = fail_s ? NAN : 0.0;
-      A.parts[3 * o + 2] = NAN;   // the trace, written by the F2 pass when it runs
+    A.cpart[3 * (int64_t)c + 0] = lsum;
+    A.cpart[3 * (int64_t)c + 1] = (double)fail;
+  }
+}
+
+// Per problem: log det Q from the chunks' log-sums, info = the first failing
+// row over the chunks in order.
+__global__ void k_wfin1(const Args A, int32_t nprob) {
+  const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nprob) return;
+  const Prob p = A.probs[q];
+  double ls = 0.0;
+  int64_t fail = 0;
+  for (int32_t c = p.chunk0; c < p.chunk0 + p.nchunk; ++c) {
+    ls += A.cpart[3 * (int64_t)c];
+    const int64_t f = (int64_t)A.cpart[3 * (int64_t)c + 1];
+    if (f > 0 && fail == 0) fail = f;
+  }
+  if (A.parts) {
+    A.parts[3 * (int64_t)q + 0] = fail ? NAN : 2.0 * ls;
+    A.parts[3 * (int64_t)q + 1] = fail ? NAN : 0.0;
+    A.parts[3 * (int64_t)q + 2] = NAN;   // the trace, written after the F2 pass
+  }
+  A.info[q] = (int32_t)fail;
+}
+
+// ======================================== linear passes: chunk summaries
+// One ascending walk over the chunk's blocks gives
+//   R = P_{e-1} ... P_a,
+//   the subset inverse's zero-state map (descending, written ascending):
+//     M_F2 = sum_i R_i^T X_i^T X_i R_i,   R_i = P_{i-1} ... P_a,
+//   and, with B1, the zero-state carry of Algorithm 4 by blocks over the chunk
+//   (ascending): C <- P (W_ii + sym C) P^T - 2 W_{i+1,i} P^T.
+// A problem's first chunk needs no F2 map and its last chunk no B1 map.
+__global__ void __launch_bounds__(NT) k_wlin_sum(const Args A, int32_t want_b1) {
+  __shared__ MatF Xf, Pf, Rf, Mf2, Cb, Sf, EMf, Tf;
+  const int32_t c = blockIdx.x;
+  const Chunk ch = A.chunks[c];
+  const Prob p = A.probs[ch.prob];
+  if (A.info[ch.prob] != 0) return;
+  const bool f2 = c != p.chunk0;
+  const bool b1 = want_b1 && ch.b1 < nblocks(p.n);
+  set_identity(Rf);
+  set_zero(Mf2);
+  set_zero(Cb);
+  for (int64_t b = ch.b0; b < ch.b1; ++b) {
+    const float *wsb = A.ws + (p.wsoff + b) * kBlockWs;
+    ws_load(wsb, Xf);
+    ws_load(wsb + NB * NB, Pf);
+    if (f2) {
+      gemm64<false, false>(Xf, Rf, 1.f, [&](int i, int j, float v) { Tf[i][j] = v; });
+      gemm64<true, false>(Tf, Tf, 1.f, [&](int i, int j, float v) { Mf2[i][j] += v; });
     }
-    A.info[o] = fail_s;
+    if (b1) {
+      load_blocks(A.Wm, A.Wmd, p, b, Sf, &EMf);
+      for (int e = threadIdx.x; e < NB * NB; e += NT) {
+        const int i = e / NB, j = e % NB;
+        Sf[i][j] += 0.5f * (Cb[i][j] + Cb[j][i]);
+        EMf[i][j] *= 2.f;
+      }
+      gemm64<false, false>(Pf, Sf, 1.f, [&](int i, int j, float v) { Tf[i][j] = v; });
+      gemm64<false, true>(Tf, Pf, 1.f, [&](int i, int j, float v) { Cb[i][j] = v; });
+      gemm64<false, true>(EMf, Pf, -1.f, [&](int i, int j, float v) { Cb[i][j] += v; });
+    }
+    gemm64<false, false>(Pf, Rf, 1.f, [&](int i, int j, float v) { Rf[i][j] = v; });
+  }
+  ws_store(cw(A, c, CW_R), Rf);
+  if (f2) ws_store(cw(A, c, CW_MF2), Mf2);
+  if (b1) ws_store(cw(A, c, CW_MB1), Cb);
+}
+
+// The linear passes' chunk maps of each problem in order (one workgroup per
+// problem):  PASS 0, the subset inverse (descending): S <- R^T S R + M_F2;
+// PASS 1, Algorithm 4 (ascending): S <- R sym(S) R^T + M_B1;  PASS 2,
+// Algorithm 2 (descending): S <- R^T S R + M_B2.  Zero state at the start;
+// every chunk's entering state is stored.
+template <int PASS> __global__ void __launch_bounds__(NT) k_wlin_scan(const Args A) {
+  __shared__ MatF Sf, Rf, Mf, Tf;
+  const Prob p = A.probs[blockIdx.x];
+  if (A.info[blockIdx.x] != 0) return;
+  constexpr bool DESC = PASS != 1;
+  constexpr int MSLOT = PASS == 0 ? CW_MF2 : PASS == 1 ? CW_MB1 : CW_MB2;
+  constexpr int SSLOT = PASS == 0 ? CW_SF2 : PASS == 1 ? CW_SB1 : CW_SB2;
+  set_zero(Sf);
+  for (int32_t t = 0; t < p.nchunk; ++t) {
+    const int32_t c = DESC ? p.chunk0 + p.nchunk - 1 - t : p.chunk0 + t;
+    ws_store(cw(A, c, SSLOT), Sf);
+    if (t == p.nchunk - 1) break;
+    ws_load(cw(A, c, CW_R), Rf);
+    ws_load(cw(A, c, MSLOT), Mf);
+    if (DESC) {
+      gemm64<false, false>(Sf, Rf, 1.f, [&](int i, int j, float v) { Tf[i][j] = v; });
+      gemm64<true, false>(Rf, Tf, 1.f, [&](int i, int j, float v) { Sf[i][j] = v + Mf[i][j]; });
+    } else {
+      for (int e = threadIdx.x; e < NB * NB; e += NT) {
+        const int i = e / NB, j = e % NB;
+        Tf[i][j] = 0.5f * (Sf[i][j] + Sf[j][i]);
+      }
+      gemm64<false, false>(Rf, Tf, 1.f, [&](int i, int j, float v) { Sf[i][j] = v; });
+      gemm64<false, true>(Sf, Rf, 1.f, [&](int i, int j, float v) { Tf[i][j] = v; });
+      for (int e = threadIdx.x; e < NB * NB; e += NT) {
+        const int i = e / NB, j = e % NB;
+        Sf[i][j] = Tf[i][j] + Mf[i][j];
+      }
+      __syncthreads();
+    }
   }
 }
 
 // ========================================================== F2 (forward)
-// Subset inverse by blocks, descending; with Wm given, also tr(Q^{-1} W).
-__global__ void __launch_bounds__(NT) k_wide_f2(const Args A) {
+// Chunk replay of the subset inverse by blocks (descending) from Sigma of the
+// block above the chunk; with Wm given, the chunk's part of tr(Q^{-1} W).
+__global__ void __launch_bounds__(NT) k_wf2_rep(const Args A) {
   __shared__ MatF Xf, Pf, Wf, Ef, Tf;
   __shared__ double red[4];
-  const Prob p = A.probs[blockIdx.x];
-  if (A.info[blockIdx.x] != 0) {   // a failed factorisation: every part is NaN
-    if (threadIdx.x == 0 && A.parts) A.parts[3 * blockIdx.x + 2] = NAN;
-    return;
-  }
+  __shared__ double sdg[NB];
+  const int32_t c = blockIdx.x;
+  const Chunk ch = A.chunks[c];
+  const Prob p = A.probs[ch.prob];
+  if (A.info[ch.prob] != 0) return;
   const int64_t nb = nblocks(p.n);
+  ws_load(cw(A, c, CW_SF2), Wf);
   double tr = 0.0;
-  for (int64_t b = nb - 1; b >= 0; --b) {
+  for (int64_t b = ch.b1 - 1; b >= ch.b0; --b) {
     const float *wsb = A.ws + (p.wsoff + b) * kBlockWs;
     ws_load(wsb, Xf);
     ws_load(wsb + NB * NB, Pf);
@@ -324,7 +563,6 @@ __global__ void __launch_bounds__(NT) k_wide_f2(const Args A) {
     gemm64<true, false>(Xf, Xf, 1.f, [&](int i, int j, float v) { Tf[i][j] = v; });
     if (!last) gemm64<true, false>(Pf, Ef, -1.f, [&](int i, int j, float v) { Tf[i][j] += v; });
     // FP64 diagonal: sum_k X_ki^2 - sum_k P_ki E_ki
-    __shared__ double sdg[NB];
     if (threadIdx.x < NB) {
       const int i = threadIdx.x;
       double s = 0.0;
@@ -334,15 +572,15 @@ __global__ void __launch_bounds__(NT) k_wide_f2(const Args A) {
       sdg[i] = s;
     }
     __syncthreads();
-    store_blocks(A.Sig, A.Sigd, p, b, [&](int c) { return sdg[c]; },
-                 [&](int i, int c) { return (double)Tf[i][c]; },
-                 [&](int rr, int c) { return last ? 0.0 : (double)Ef[rr][c]; });
+    store_blocks(A.Sig, A.Sigd, p, b, [&](int cc) { return sdg[cc]; },
+                 [&](int i, int cc) { return (double)Tf[i][cc]; },
+                 [&](int rr, int cc) { return last ? 0.0 : (double)Ef[rr][cc]; });
     if (A.Wm) {   // tr(Sigma W) over the stored entries (off-diagonal ones twice)
       double wv[kSlotIters];
       read_block(A.Wm, A.Wmd, p, b, wv);
-      for_block_slots(b, p.n, [&](int it, int c, int d, int64_t, bool valid) {
+      for_block_slots(b, p.n, [&](int it, int cc, int d, int64_t, bool valid) {
         if (!valid) return;
-        const double sv = d == 0 ? sdg[c] : (d <= NB - 1 - c ? (double)Tf[c + d][c] : (double)Ef[d - NB + c][c]);
+        const double sv = d == 0 ? sdg[cc] : (d <= NB - 1 - cc ? (double)Tf[cc + d][cc] : (double)Ef[d - NB + cc][cc]);
         tr += (d == 0 ? 1.0 : 2.0) * wv[it] * sv;
       });
     }
@@ -355,20 +593,37 @@ __global__ void __launch_bounds__(NT) k_wide_f2(const Args A) {
     __syncthreads();
   }
   const double t = block_sum(tr, red);
-  if (threadIdx.x == 0 && A.parts) A.parts[3 * blockIdx.x + 2] = t;
+  if (threadIdx.x == 0) A.cpart[3 * (int64_t)c + 2] = t;
+}
+
+// Per problem: tr(Q^{-1} W) from the chunks (NaN for a failed factorisation).
+__global__ void k_wfin2(const Args A, int32_t nprob) {
+  const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nprob || !A.parts) return;
+  const Prob p = A.probs[q];
+  if (A.info[q] != 0) {
+    A.parts[3 * (int64_t)q + 2] = NAN;
+    return;
+  }
+  double t = 0.0;
+  for (int32_t c = p.chunk0; c < p.chunk0 + p.nchunk; ++c) t += A.cpart[3 * (int64_t)c + 2];
+  A.parts[3 * (int64_t)q + 2] = A.Wm ? t : 0.0;
 }
 
 // =================================================== B1 (Algorithm 4, blocks)
-// Ascending reverse of F2 with Sigmabar from W (S_ii on the diagonal, 2 S_ij
-// off it, on the stored entries): writes Lbar (diagonal-block lower triangle
-// and coupling-block upper triangle).  Carried: the adjoint of Sigma_bb.
-__global__ void __launch_bounds__(NT) k_wide_b1(const Args A) {
+// Chunk replay, ascending, from the carry entering the chunk, with Sigmabar
+// from W (S_ii on the diagonal, 2 S_ij off it, on the stored entries): writes
+// Lbar (diagonal-block lower triangle and coupling-block upper triangle).
+// Carried: the adjoint of Sigma_bb (only its symmetric part is used).
+__global__ void __launch_bounds__(NT) k_wb1_rep(const Args A) {
   __shared__ MatF Xf, Pf, Wf, EMf, Sf, Cf, A1, A2;
-  const Prob p = A.probs[blockIdx.x];
-  if (A.info[blockIdx.x] != 0) return;
+  const int32_t c = blockIdx.x;
+  const Chunk ch = A.chunks[c];
+  const Prob p = A.probs[ch.prob];
+  if (A.info[ch.prob] != 0) return;
   const int64_t nb = nblocks(p.n);
-  for (int e = threadIdx.x; e < NB * NB; e += NT) Cf[e / NB][e % NB] = 0.f;
-  for (int64_t b = 0; b < nb; ++b) {
+  ws_load(cw(A, c, CW_SB1), Cf);
+  for (int64_t b = ch.b0; b < ch.b1; ++b) {
     const float *wsb = A.ws + (p.wsoff + b) * kBlockWs;
     ws_load(wsb, Xf);
     ws_load(wsb + NB * NB, Pf);
@@ -407,25 +662,32 @@ __global__ void __launch_bounds__(NT) k_wide_b1(const Args A) {
     // Lbar_bb = -X^T Xbar X^T (lower triangle kept)
     gemm64<true, false>(Xf, Wf, 1.f, [&](int i, int j, float v) { Sf[i][j] = v; });
     gemm64<false, true>(Sf, Xf, -1.f, [&](int i, int j, float v) { A2[i][j] = v; });
-    store_blocks(A.Lb, A.Lbd, p, b, [&](int c) { return (double)A2[c][c]; },
-                 [&](int i, int c) { return (double)A2[i][c]; },
-                 [&](int rr, int c) { return last ? 0.0 : (double)A1[rr][c]; });
+    store_blocks(A.Lb, A.Lbd, p, b, [&](int cc) { return (double)A2[cc][cc]; },
+                 [&](int i, int cc) { return (double)A2[i][cc]; },
+                 [&](int rr, int cc) { return last ? 0.0 : (double)A1[rr][cc]; });
     __syncthreads();
   }
 }
 
 // =================================================== B2 (Algorithm 2, blocks)
-// Descending reverse of F1: Qbar from L, Lbar and the log-determinant
-// sensitivity gl (per unit loss weight).  Carried: the adjoint of S_{b+1}.
-__global__ void __launch_bounds__(NT) k_wide_b2(const Args A, double gl) {
+// Descending reverse of F1 over a chunk: Qbar from L, Lbar and the
+// log-determinant sensitivity gl.  Carried: the adjoint of S_{b+1}.  REPLAY:
+// from the carry entering the chunk, writing Qbar; otherwise the zero-state
+// run of a chunk, whose final carry is its map M_B2 (a problem's first chunk
+// needs none).
+template <bool REPLAY> __global__ void __launch_bounds__(NT) k_wb2(const Args A, double gl) {
   __shared__ MatF Lf, Xf, Mf, MBf, LBf, Sc, A1, A2;
   __shared__ double dg[NB], lbd[NB];
-  const Prob p = A.probs[blockIdx.x];
-  if (A.info[blockIdx.x] != 0) return;
+  const int32_t c = blockIdx.x;
+  const Chunk ch = A.chunks[c];
+  const Prob p = A.probs[ch.prob];
+  if (A.info[ch.prob] != 0) return;
+  if (!REPLAY && c == p.chunk0) return;
   const int64_t nb = nblocks(p.n);
-  for (int e = threadIdx.x; e < NB * NB; e += NT) Sc[e / NB][e % NB] = 0.f;
+  if (REPLAY) ws_load(cw(A, c, CW_SB2), Sc);
+  else set_zero(Sc);
   __syncthreads();
-  for (int64_t b = nb - 1; b >= 0; --b) {
+  for (int64_t b = ch.b1 - 1; b >= ch.b0; --b) {
     const bool last = b == nb - 1;
     ws_load(A.ws + (p.wsoff + b) * kBlockWs, Xf);
     // L_bb (lower) and M_b (upper) from L, the FP64 pivots from Ld
@@ -455,7 +717,7 @@ __global__ void __launch_bounds__(NT) k_wide_b2(const Args A, double gl) {
       // Mbar -= 2 Sc M   (Sc: adjoint of S_{b+1}, symmetric)
       gemm64<false, false>(Sc, Mf, -2.f, [&](int i, int j, float v) { MBf[i][j] += v; });
       // Cbar = Mbar X (upper triangle kept) -> Qbar's coupling block (A2)
-      gemm64<false, false>(MBf, Xf, 1.f, [&](int i, int j, float v) { A2[i][j] = v; });
+      if (REPLAY) gemm64<false, false>(MBf, Xf, 1.f, [&](int i, int j, float v) { A2[i][j] = v; });
       // Lbar_bb -= X^T (Mbar^T M)
       gemm64<true, false>(MBf, Mf, 1.f, [&](int i, int j, float v) { A1[i][j] = v; });
       gemm64<true, false>(Xf, A1, -1.f, [&](int i, int j, float v) { LBf[i][j] += v; });
@@ -475,11 +737,13 @@ __global__ void __launch_bounds__(NT) k_wide_b2(const Args A, double gl) {
     gemm64<true, false>(Xf, Mf, 1.f, [&](int i, int j, float v) { A1[i][j] = v; });
     gemm64<false, false>(A1, Xf, 0.5f, [&](int i, int j, float v) { Sc[i][j] = v; });
     // Qbar: diagonal block from Sbar (stored entries: S_ii, 2 S_ij), coupling from Cbar
-    store_blocks(A.Qb, A.Qbd, p, b, [&](int c) { return (double)Sc[c][c]; },
-                 [&](int i, int c) { return (double)(Sc[i][c] + Sc[c][i]); },
-                 [&](int rr, int c) { return last ? 0.0 : (double)A2[rr][c]; });
+    if (REPLAY)
+      store_blocks(A.Qb, A.Qbd, p, b, [&](int cc) { return (double)Sc[cc][cc]; },
+                   [&](int i, int cc) { return (double)(Sc[i][cc] + Sc[cc][i]); },
+                   [&](int rr, int cc) { return last ? 0.0 : (double)A2[rr][cc]; });
     __syncthreads();
   }
+  if (!REPLAY) ws_store(cw(A, c, CW_MB2), Sc);
 }
 
 }  // namespace wide
@@ -487,52 +751,103 @@ __global__ void __launch_bounds__(NT) k_wide_b2(const Args A, double gl) {
 // ====================================================================== C ABI
 // The library's thread-local error message (defined with the other entry points).
 bo_status bo_set_error(bo_status s, const std::string &msg);
-// Launch timing hook of the library (slot per wide pass, which = 0..3).
+// Launch timing hook of the library (slot per wide kernel kind, which = 0..9).
 int bo_profile_wide(int which, hipStream_t s, const std::function<int()> &launch);
 
 namespace {
 bo_status wfail(bo_status s, const std::string &m) { return bo_set_error(s, m); }
-size_t table_bytes(int32_t nprob) { return ((size_t)nprob * sizeof(wide::Prob) + 255) / 256 * 256; }
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+// Chunks per call: about one workgroup per compute unit (the passes' LDS use,
+// up to ~150 KB, allows one per CU), spread over the problems by their block
+// counts.  BANDOPS_WIDE_CHUNKS overrides the target.
+int64_t wide_target_chunks() {
+  static int64_t v = [] {
+    const char *e = std::getenv("BANDOPS_WIDE_CHUNKS");
+    long long t = e ? std::atoll(e) : 0;
+    return (int64_t)(t > 0 ? t : 256);
+  }();
+  return v;
+}
+
+// Host image of a call's tables and its workspace layout.
+struct WideLayout {
+  std::vector<wide::Prob> probs;
+  std::vector<wide::Chunk> chunks;
+  size_t off_chunks = 0, off_blockws = 0, off_cws = 0, off_cpart = 0, bytes = 0;
+  int64_t blocks = 0;
+};
 }  // namespace
 
-static bo_status wide_table(const bo_problem *probs, int32_t nprob, std::vector<wide::Prob> &t,
-                            size_t &bytes) {
+static bo_status wide_layout(const bo_problem *probs, int32_t nprob, WideLayout &L) {
   if (!probs || nprob <= 0) return wfail(BO_EINVAL, "bo_wide: no problems");
-  t.resize(nprob);
+  L = WideLayout{};
+  L.probs.resize(nprob);
   int64_t blocks = 0;
   for (int32_t i = 0; i < nprob; ++i) {
     if (probs[i].k != wide::NB) return wfail(BO_EUNSUPPORTED, "bo_wide: every problem must have k = 64");
     if (probs[i].n < 0 || probs[i].boff < 0 || probs[i].voff < 0) return wfail(BO_EINVAL, "bo_wide: bad problem");
-    t[i] = wide::Prob{probs[i].n, probs[i].boff, probs[i].voff, blocks};
     blocks += (probs[i].n + wide::NB - 1) / wide::NB;
   }
-  bytes = table_bytes(nprob) + (size_t)blocks * wide::kBlockWs * sizeof(float);
+  const int64_t target = wide_target_chunks();
+  int64_t wsoff = 0;
+  for (int32_t i = 0; i < nprob; ++i) {
+    const int64_t nb = (probs[i].n + wide::NB - 1) / wide::NB;
+    wide::Prob p{probs[i].n, probs[i].boff, probs[i].voff, wsoff, (int32_t)L.chunks.size(), 0};
+    if (nb > 0) {
+      int64_t nc = blocks > 0 ? (target * nb + blocks / 2) / blocks : 1;
+      nc = std::max<int64_t>(1, std::min<int64_t>(nc, nb));
+      const int64_t cb = (nb + nc - 1) / nc;
+      for (int64_t b0 = 0; b0 < nb; b0 += cb) L.chunks.push_back(wide::Chunk{i, 0, b0, std::min(nb, b0 + cb)});
+      p.nchunk = (int32_t)L.chunks.size() - p.chunk0;
+    }
+    L.probs[i] = p;
+    wsoff += nb;
+  }
+  L.blocks = blocks;
+  const size_t nch = L.chunks.size();
+  L.off_chunks = align256((size_t)nprob * sizeof(wide::Prob));
+  L.off_blockws = L.off_chunks + align256(nch * sizeof(wide::Chunk));
+  L.off_cws = L.off_blockws + align256((size_t)blocks * wide::kBlockWs * sizeof(float));
+  L.off_cpart = L.off_cws + align256(nch * wide::CW_N * wide::kMat * sizeof(float));
+  L.bytes = L.off_cpart + align256(nch * 3 * sizeof(double));
   return BO_OK;
 }
 
 extern "C" bo_status bo_wide_workspace_size(const bo_problem *probs, int32_t nprob, size_t *bytes) {
-  std::vector<wide::Prob> t;
   if (!bytes) return wfail(BO_EINVAL, "bo_wide_workspace_size: null bytes");
-  return wide_table(probs, nprob, t, *bytes);
+  WideLayout L;
+  if (bo_status e = wide_layout(probs, nprob, L)) return e;
+  *bytes = L.bytes;
+  return BO_OK;
 }
 
 extern "C" bo_status bo_wide_upload(const bo_problem *probs, int32_t nprob, void *ws, size_t ws_bytes) {
-  std::vector<wide::Prob> t;
-  size_t need = 0;
-  if (bo_status e = wide_table(probs, nprob, t, need)) return e;
-  if (!ws || ws_bytes < need) return wfail(BO_EWORKSPACE, "bo_wide_upload: workspace too small");
-  if (hipMemcpy(ws, t.data(), t.size() * sizeof(wide::Prob), hipMemcpyHostToDevice) != hipSuccess)
+  WideLayout L;
+  if (bo_status e = wide_layout(probs, nprob, L)) return e;
+  if (!ws || ws_bytes < L.bytes) return wfail(BO_EWORKSPACE, "bo_wide_upload: workspace too small");
+  if (hipMemcpy(ws, L.probs.data(), L.probs.size() * sizeof(wide::Prob), hipMemcpyHostToDevice) != hipSuccess ||
+      (!L.chunks.empty() && hipMemcpy((char *)ws + L.off_chunks, L.chunks.data(), L.chunks.size() * sizeof(wide::Chunk),
+                                      hipMemcpyHostToDevice) != hipSuccess))
     return wfail(BO_EDEVICE, "bo_wide_upload: copy failed");
   return BO_OK;
 }
 
-static bo_status wide_args(int32_t nprob, const bo_batch_io *io, void *ws, wide::Args &A) {
+static bo_status wide_args(const bo_problem *probs, int32_t nprob, const bo_batch_io *io, void *ws, size_t ws_bytes,
+                           WideLayout &L, wide::Args &A) {
   if (nprob <= 0 || !io || !ws) return wfail(BO_EINVAL, "bo_wide: null argument");
   if (!io->Q || !io->Qd || !io->L || !io->Ld || !io->info)
     return wfail(BO_EINVAL, "bo_wide: Q, Qd, L, Ld and info are required");
+  if (bo_status e = wide_layout(probs, nprob, L)) return e;
+  if (ws_bytes < L.bytes)
+    return wfail(BO_EWORKSPACE, "bo_wide: workspace needs " + std::to_string(L.bytes) + " bytes");
   A = wide::Args{};
-  A.probs = (const wide::Prob *)ws;
-  A.ws = (float *)((char *)ws + table_bytes(nprob));
+  char *w = (char *)ws;
+  A.probs = (const wide::Prob *)w;
+  A.chunks = (const wide::Chunk *)(w + L.off_chunks);
+  A.ws = (float *)(w + L.off_blockws);
+  A.cws = (float *)(w + L.off_cws);
+  A.cpart = (double *)(w + L.off_cpart);
   A.Q = (const float *)io->Q; A.Qd = io->Qd;
   A.Wm = (const float *)io->S; A.Wmd = io->Sd;
   A.L = (float *)io->L; A.Ld = io->Ld;
@@ -544,16 +859,37 @@ static bo_status wide_args(int32_t nprob, const bo_batch_io *io, void *ws, wide:
   return BO_OK;
 }
 
-static void launch_f1_f2(int32_t nprob, const wide::Args &A, hipStream_t stream) {
-  bo_profile_wide(0, stream, [&] {
-    hipLaunchKernelGGL(wide::k_wide_f1, dim3(nprob), dim3(wide::NT), 0, stream, A);
-    return 0;
-  });
-  bo_profile_wide(1, stream, [&] {
-    hipLaunchKernelGGL(wide::k_wide_f2, dim3(nprob), dim3(wide::NT), 0, stream, A);
+namespace {
+// One launch on the stream, timed under the given slot when profiling is on.
+template <class K, class... Ts> void wlaunch(int which, K kern, unsigned grid, hipStream_t s, Ts... args) {
+  if (grid == 0) return;
+  bo_profile_wide(which, s, [&] {
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(wide::NT), 0, s, args...);
     return 0;
   });
 }
+enum { WS_F1 = 0, WS_F2, WS_B1, WS_B2, WS_F1SUM, WS_F1SCAN, WS_LINSUM, WS_LINSCAN, WS_B2SUM, WS_FIN };
+
+// Cholesky, log det, subset inverse (and the trace when W is given), and with
+// want_b1 the linear-pass maps Algorithm 4 needs.
+void launch_forward(const WideLayout &L, int32_t nprob, const wide::Args &A, bool want_b1, hipStream_t s) {
+  const unsigned nch = (unsigned)L.chunks.size(), np = (unsigned)nprob, npb = (unsigned)((nprob + 63) / 64);
+  wlaunch(WS_F1SUM, wide::k_wf1_sum, nch, s, A);
+  wlaunch(WS_F1SCAN, wide::k_wf1_scan, np, s, A);
+  wlaunch(WS_F1, wide::k_wf1_rep, nch, s, A);
+  bo_profile_wide(WS_FIN, s, [&] {
+    hipLaunchKernelGGL(wide::k_wfin1, dim3(npb), dim3(64), 0, s, A, nprob);
+    return 0;
+  });
+  wlaunch(WS_LINSUM, wide::k_wlin_sum, nch, s, A, (int32_t)(want_b1 ? 1 : 0));
+  wlaunch(WS_LINSCAN, wide::k_wlin_scan<0>, np, s, A);
+  wlaunch(WS_F2, wide::k_wf2_rep, nch, s, A);
+  bo_profile_wide(WS_FIN, s, [&] {
+    hipLaunchKernelGGL(wide::k_wfin2, dim3(npb), dim3(64), 0, s, A, nprob);
+    return 0;
+  });
+}
+}  // namespace
 
 static bo_status wide_launch_status(const char *what) {
   hipError_t e = hipGetLastError();
@@ -561,30 +897,32 @@ static bo_status wide_launch_status(const char *what) {
   return BO_OK;
 }
 
-extern "C" bo_status bo_wide_forward(int32_t nprob, const bo_batch_io *io, void *ws, hipStream_t stream) {
+extern "C" bo_status bo_wide_forward(const bo_problem *probs, int32_t nprob, const bo_batch_io *io, void *ws,
+                                     size_t ws_bytes, hipStream_t stream) {
+  WideLayout L;
   wide::Args A;
-  if (bo_status e = wide_args(nprob, io, ws, A)) return e;
+  if (bo_status e = wide_args(probs, nprob, io, ws, ws_bytes, L, A)) return e;
   if (!io->Sig || !io->Sigd) return wfail(BO_EINVAL, "bo_wide_forward: Sig and Sigd are required");
   A.Wm = nullptr;
   A.Wmd = nullptr;
-  launch_f1_f2(nprob, A, stream);
+  launch_forward(L, nprob, A, false, stream);
   return wide_launch_status("bo_wide_forward");
 }
 
-extern "C" bo_status bo_wide_gauss_loss(int32_t nprob, const bo_batch_io *io, void *ws, hipStream_t stream) {
+extern "C" bo_status bo_wide_gauss_loss(const bo_problem *probs, int32_t nprob, const bo_batch_io *io, void *ws,
+                                        size_t ws_bytes, hipStream_t stream) {
+  WideLayout L;
   wide::Args A;
-  if (bo_status e = wide_args(nprob, io, ws, A)) return e;
+  if (bo_status e = wide_args(probs, nprob, io, ws, ws_bytes, L, A)) return e;
   if (!io->S || !io->Sd || !io->Sig || !io->Sigd || !io->Lbar || !io->Lbard || !io->Qbar || !io->Qbard ||
       !io->parts)
     return wfail(BO_EINVAL, "bo_wide_gauss_loss: S, Sig, Lbar, Qbar (with diagonals) and parts are required");
-  launch_f1_f2(nprob, A, stream);
-  bo_profile_wide(2, stream, [&] {
-    hipLaunchKernelGGL(wide::k_wide_b1, dim3(nprob), dim3(wide::NT), 0, stream, A);
-    return 0;
-  });
-  bo_profile_wide(3, stream, [&] {
-    hipLaunchKernelGGL(wide::k_wide_b2, dim3(nprob), dim3(wide::NT), 0, stream, A, 1.0);
-    return 0;
-  });
+  launch_forward(L, nprob, A, true, stream);
+  const unsigned nch = (unsigned)L.chunks.size(), np = (unsigned)nprob;
+  wlaunch(WS_LINSCAN, wide::k_wlin_scan<1>, np, stream, A);
+  wlaunch(WS_B1, wide::k_wb1_rep, nch, stream, A);
+  wlaunch(WS_B2SUM, wide::k_wb2<false>, nch, stream, A, 1.0);
+  wlaunch(WS_LINSCAN, wide::k_wlin_scan<2>, np, stream, A);
+  wlaunch(WS_B2, wide::k_wb2<true>, nch, stream, A, 1.0);
   return wide_launch_status("bo_wide_gauss_loss");
 }

@@ -57,10 +57,16 @@ _KERNEL_SLOTS = [
     (r"LinGroupCompose<\d+, false>", "asc_group_compose"),
     (r"LinGroupSweep<\d+, false>", "asc_group_sweep"),
     (r"LinChunkSweep<\d+, false>", "asc_chunk_sweep"),
-    (r"k_wide_f1", "wide_f1"),
-    (r"k_wide_f2", "wide_f2"),
-    (r"k_wide_b1", "wide_b1"),
-    (r"k_wide_b2", "wide_b2"),
+    (r"k_wf1_sum", "wide_f1_sum"),
+    (r"k_wf1_scan", "wide_f1_scan"),
+    (r"k_wf1_rep", "wide_f1"),
+    (r"k_wfin", "wide_finalize"),
+    (r"k_wlin_sum", "wide_lin_sum"),
+    (r"k_wlin_scan", "wide_lin_scan"),
+    (r"k_wf2_rep", "wide_f2"),
+    (r"k_wb1_rep", "wide_b1"),
+    (r"k_wb2<false>", "wide_b2_sum"),
+    (r"k_wb2<true>", "wide_b2"),
     (r"k_kl_pre", "vi_pre"),
     (r"k_kl_post", "vi_post"),
     (r"k_kl_neg", "vi_neg"),

@@ -162,14 +162,17 @@ def test_whiten_errors(L):
 
 def test_wide_errors_and_workspace(L):
     """The wide (k = 64) entry points: argument errors before any launch, and
-    the workspace size (problem table plus two FP32 64 x 64 blocks per block
-    row)."""
+    the workspace size (problem and chunk tables, two FP32 64 x 64 blocks per
+    block row, eleven per chunk and three doubles per chunk; here every block
+    is a chunk of its own)."""
     from paper_1902_10078_amd.bandops import _BatchIO, _Problem
     sz = ctypes.c_size_t()
     probs = (_Problem * 2)(_Problem(130, 64, 0, 0, 0), _Problem(64, 64, 0, 130 * 65, 130))
     assert L.bo_wide_workspace_size(probs, 2, ctypes.byref(sz)) == 0
-    blocks = 3 + 1
-    assert sz.value == 256 + blocks * 2 * 64 * 64 * 4
+    blocks = chunks = 3 + 1
+    al = lambda x: (x + 255) // 256 * 256
+    assert sz.value == (al(2 * 40) + al(chunks * 24) + al(blocks * 2 * 64 * 64 * 4) + al(chunks * 11 * 64 * 64 * 4)
+                        + al(chunks * 3 * 8))
     bad = (_Problem * 1)(_Problem(100, 5, 0, 0, 0))
     assert L.bo_wide_workspace_size(bad, 1, ctypes.byref(sz)) == -4
     assert b"k = 64" in L.bo_last_error()
@@ -180,6 +183,6 @@ def test_wide_errors_and_workspace(L):
     assert L.bo_wide_upload(probs, 2, ctypes.c_void_p(1), 16) == -3
     io = _BatchIO()
     # missing required arrays: refused before any launch
-    assert L.bo_wide_forward(1, ctypes.byref(io), ctypes.c_void_p(1), None) == -1
-    assert L.bo_wide_gauss_loss(1, ctypes.byref(io), ctypes.c_void_p(1), None) == -1
-    assert L.bo_wide_forward(0, ctypes.byref(io), ctypes.c_void_p(1), None) == -1
+    assert L.bo_wide_forward(probs, 1, ctypes.byref(io), ctypes.c_void_p(1), 1 << 30, None) == -1
+    assert L.bo_wide_gauss_loss(probs, 1, ctypes.byref(io), ctypes.c_void_p(1), 1 << 30, None) == -1
+    assert L.bo_wide_forward(probs, 0, ctypes.byref(io), ctypes.c_void_p(1), 1 << 30, None) == -1
