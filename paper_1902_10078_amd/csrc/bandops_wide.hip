@@ -19,8 +19,9 @@
 //
 // Precision: blocks are stored in the mixed format (FP32 records, FP64
 // diagonal).  The diagonal-block Cholesky and triangular inverse run in FP64
-// (FP64 pivots and log-determinant); every dense block product runs on the
-// matrix cores as FP32 MFMA (v_mfma_f32_16x16x4_f32).
+// (FP64 pivots and log-determinant; one wavefront with the block in
+// registers); every dense block product runs on the matrix cores as FP32 MFMA
+// (v_mfma_f32_16x16x4_f32).
 //
 // Parallelism: each problem's blocks are cut into chunks of consecutive
 // blocks, one workgroup (four wavefronts) per chunk, and every pass is an exact
@@ -215,51 +216,80 @@ __device__ __forceinline__ void gemm64(const MatF &A, const MatF &B, float alpha
 }
 
 
-// FP64 Cholesky of the symmetric block S in place: the strict lower triangle
-// of S becomes L's, the diagonal goes to dg and its reciprocal to rdg (S's
-// diagonal is left as is).  Returns 0, or 1 + the first column whose pivot is
-// not positive.  Thread 0 adds the log-determinant of L to lsum.
-__device__ int potrf64(MatD &S, double *dg, double *rdg, double &lsum) {
-  const int tid = threadIdx.x;
-  for (int j = 0; j < NB; ++j) {
-    const double piv = S[j][j];
-    if (!(piv > 0.0)) return j + 1;
-    const double d = sqrt(piv), r = 1.0 / d;
-    if (tid == 0) { dg[j] = d; rdg[j] = r; }
-    if (tid > j && tid < NB) S[tid][j] *= r;
-    __syncthreads();
-    const int c = tid & 63, q = tid >> 6;
-    const int k = j + 1 + c;
-    if (k < NB) {
-      const double lk = S[k][j];
-      for (int i = k + q; i < NB; i += 4) S[i][k] -= S[i][j] * lk;
-    }
-    __syncthreads();
-  }
-  if (tid < NB) {
-    double lg = log(dg[tid]);
-    for (int off = 32; off >= 1; off >>= 1) lg += __shfl_xor(lg, off, 64);
-    if (tid == 0) lsum += lg;
-  }
-  __syncthreads();
-  return 0;
+// Value of v in lane src of the wavefront (src a compile-time constant after
+// unrolling), for every lane.
+__device__ __forceinline__ double bcast_lane(double v, int src) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+  return __hiloint2double(hi, lo);
 }
 
-// X = L^{-1} for L = (strict lower triangle of S, reciprocal diagonal rdg),
-// in FP64.  Four lanes per column j: lane q sums the terms k = j + q (mod 4)
-// and keeps (writes, then reads back) exactly those entries of column j.
-__device__ void trtri64(const MatD &S, const double *rdg, MatD &X) {
-  const int tid = threadIdx.x, j = tid >> 2, q = tid & 3;
-  for (int i = q; i < j; i += 4) X[i][j] = 0.0;
-  for (int i = j; i < NB; ++i) {
-    double s = 0.0;
-    for (int k = j + q; k < i; k += 4) s += S[i][k] * X[k][j];
-    s += __shfl_xor(s, 1, 64);
-    s += __shfl_xor(s, 2, 64);
-    const double x = ((i == j ? 1.0 : 0.0) - s) * rdg[i];
-    if (((i - j) & 3) == q) X[i][j] = x;
+// FP64 Cholesky S = L L^T of the symmetric block S (held full) and X = L^{-1},
+// each by one wavefront with its matrix in registers (lane j holds column j).
+// Cholesky, right-looking: at column c every lane j > c takes its
+// l_j = L[j, c] from its own copy of S[c, j] (the update keeps both
+// triangles), l_i is broadcast from lane i, and lane j applies
+// S[i, j] -= l_i l_j (i > c).  Then X by forward substitution on the columns
+// of the identity, X[i, j] = (delta_ij - sum_{k<i} L[i, k] X[k, j]) / L_ii,
+// every lane reading row i of L from LDS.  Writes the strict lower triangle of
+// L into S, L's diagonal into dg and its reciprocal into rdg, X (full, zero
+// above the diagonal) into X; thread 0 adds the log-determinant of L to lsum.
+// Returns 0, or 1 + the first column whose pivot is not positive (then S, X,
+// dg are unspecified).  Every thread of the workgroup calls it.
+__device__ int potrf_inv64(MatD &S, double *dg, double *rdg, MatD &X, double &lsum) {
+  __shared__ int fail_s;
+  const int tid = threadIdx.x;
+  if (tid < NB) {
+    const int j = tid;
+    double a[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) a[i] = S[i][j];
+    double dmine = 1.0;
+    int fail = 0;
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      const double piv = bcast_lane(a[c], c);
+      if (!(piv > 0.0)) {
+        fail = c + 1;
+        break;
+      }
+      const double d = sqrt(piv), r = 1.0 / d;
+      if (j == c) dmine = d;
+      // lane c keeps S's column c unscaled (l = 0 leaves it as is); L's
+      // column c is that column over d, taken when L is written out
+      const double lj = j > c ? a[c] * r : 0.0;
+#pragma unroll
+      for (int i = c + 1; i < NB; ++i) a[i] -= bcast_lane(lj, i) * lj;
+    }
+    if (j == 0) fail_s = fail;
+    if (!fail) {
+      const double rj = 1.0 / dmine;
+#pragma unroll
+      for (int i = 0; i < NB; ++i)
+        if (i > j) S[i][j] = a[i] * rj;
+      dg[j] = dmine;
+      rdg[j] = rj;
+      double lg = log(dmine);
+      for (int off = 32; off >= 1; off >>= 1) lg += __shfl_xor(lg, off, 64);
+      if (j == 0) lsum += lg;
+    }
   }
   __syncthreads();
+  const int fail = fail_s;
+  if (!fail && tid < NB) {
+    const int j = tid;
+    double x[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      double s = i == j ? 1.0 : 0.0;
+#pragma unroll
+      for (int k = 0; k < i; ++k) s -= S[i][k] * x[k];
+      x[i] = s * rdg[i];
+      X[i][j] = x[i];
+    }
+  }
+  __syncthreads();
+  return fail;
 }
 
 __device__ __forceinline__ void ws_load(const float *src, MatF &M) {
@@ -336,11 +366,10 @@ __global__ void __launch_bounds__(NT) k_wf1_sum(const Args A) {
     load_blocks(A.Q, A.Qd, p, i, S, &Cf);
     for (int e = threadIdx.x; e < NB * NB; e += NT) S[e / NB][e % NB] -= (double)Pc[e / NB][e % NB];
     __syncthreads();
-    if (potrf64(S, dg, rdg, unused)) {
+    if (potrf_inv64(S, dg, rdg, X, unused)) {
       bad = true;
       break;
     }
-    trtri64(S, rdg, X);
     for (int e = threadIdx.x; e < NB * NB; e += NT) Xf[e / NB][e % NB] = (float)X[e / NB][e % NB];
     gemm64<false, false>(Xf, V, 1.f, [&](int r, int q, float v) { Y[r][q] = v; });
     gemm64<true, false>(Y, Y, 1.f, [&](int r, int q, float v) { Z[r][q] += v; });
@@ -376,13 +405,11 @@ __global__ void __launch_bounds__(NT) k_wf1_scan(const Args A) {
     __syncthreads();
     for (int e = threadIdx.x; e < NB * NB; e += NT) S[e / NB][e % NB] = (double)Am[e] - (double)Ef[e / NB][e % NB];
     ws_load(cw(A, c, CW_B), Bf);
-    if (potrf64(S, dg, rdg, unused)) {   // reported by this chunk's replay
-      __syncthreads();
+    if (potrf_inv64(S, dg, rdg, X, unused)) {   // reported by this chunk's replay
       set_nan(Ef);
       __syncthreads();
       continue;
     }
-    trtri64(S, rdg, X);
     for (int e = threadIdx.x; e < NB * NB; e += NT) Xf[e / NB][e % NB] = (float)X[e / NB][e % NB];
     gemm64<false, true>(Xf, Bf, 1.f, [&](int r, int q, float v) { Y[r][q] = v; });
     ws_load(cw(A, c, CW_D), Ef);
@@ -411,12 +438,11 @@ __global__ void __launch_bounds__(NT) k_wf1_rep(const Args A) {
       for (int e = threadIdx.x; e < NB * NB; e += NT) S[e / NB][e % NB] -= (double)E[e];
       __syncthreads();
     }
-    const int r = potrf64(S, dg, rdg, lsum);
+    const int r = potrf_inv64(S, dg, rdg, X, lsum);
     if (r) {
       fail = NB * b + r;
       break;
     }
-    trtri64(S, rdg, X);
     for (int e = threadIdx.x; e < NB * NB; e += NT) Xf[e / NB][e % NB] = (float)X[e / NB][e % NB];
     // M_b = C_b X_b^T (upper triangular)
     gemm64<false, true>(Cf, Xf, 1.f, [&](int i, int j, float v) { Mf[i][j] = v; });
