@@ -35,7 +35,10 @@ namespace bo {
 // and gave wrong next-pass maps on gfx950 while the same code is exact on the
 // host; those bandwidths run separate summary kernels instead, and their
 // steppers and kernels are compiled without the fused accumulations.
-constexpr int KMAX_FUSED = 5;
+#ifndef BO_KMAX_FUSED
+#define BO_KMAX_FUSED 5
+#endif
+constexpr int KMAX_FUSED = BO_KMAX_FUSED;
 
 template <int K> struct Dim {
   static constexpr int K1 = K > 0 ? K : 1;                 // array extent
