@@ -228,16 +228,19 @@ __device__ __forceinline__ double bcast_lane(double v, int src) {
 // each by one wavefront with its matrix in registers (lane j holds column j).
 // Cholesky, right-looking: at column c every lane j > c takes its
 // l_j = L[j, c] from its own copy of S[c, j] (the update keeps both
-// triangles), l_i is broadcast from lane i, and lane j applies
-// S[i, j] -= l_i l_j (i > c).  Then X by forward substitution on the columns
-// of the identity, X[i, j] = (delta_ij - sum_{k<i} L[i, k] X[k, j]) / L_ii,
-// every lane reading row i of L from LDS.  Writes the strict lower triangle of
-// L into S, L's diagonal into dg and its reciprocal into rdg, X (full, zero
-// above the diagonal) into X; thread 0 adds the log-determinant of L to lsum.
-// Returns 0, or 1 + the first column whose pivot is not positive (then S, X,
-// dg are unspecified).  Every thread of the workgroup calls it.
-__device__ int potrf_inv64(MatD &S, double *dg, double *rdg, MatD &X, double &lsum) {
+// triangles), publishes it in LDS, reads every l_i (i > c) back (the same
+// address for all lanes: a broadcast) and applies S[i, j] -= l_i l_j.  The
+// factor goes to S (strict lower triangle) and, transposed, to Lt (row j =
+// column j of L), so that the inverse reads contiguous rows: X by the same
+// right-looking order on the columns of the identity,
+//   X[k, j] /= L_kk,  X[i, j] -= L[i, k] X[k, j]  (i > k),
+// written in FP32 to Xf (zero above the diagonal).  dg / rdg receive L's
+// diagonal and its reciprocal; thread 0 adds the log-determinant of L to
+// lsum.  Returns 0, or 1 + the first column whose pivot is not positive (then
+// S, Xf, dg are unspecified).  Every thread of the workgroup calls it.
+__device__ int potrf_inv64(MatD &S, double *dg, double *rdg, MatD &Lt, MatF &Xf, double &lsum) {
   __shared__ int fail_s;
+  __shared__ double lb[NB];
   const int tid = threadIdx.x;
   if (tid < NB) {
     const int j = tid;
@@ -258,15 +261,20 @@ __device__ int potrf_inv64(MatD &S, double *dg, double *rdg, MatD &X, double &ls
       // lane c keeps S's column c unscaled (l = 0 leaves it as is); L's
       // column c is that column over d, taken when L is written out
       const double lj = j > c ? a[c] * r : 0.0;
+      lb[j] = lj;   // one wavefront: its LDS accesses complete in order
+      __builtin_amdgcn_wave_barrier();
 #pragma unroll
-      for (int i = c + 1; i < NB; ++i) a[i] -= bcast_lane(lj, i) * lj;
+      for (int i = c + 1; i < NB; ++i) a[i] -= lb[i] * lj;
     }
     if (j == 0) fail_s = fail;
     if (!fail) {
       const double rj = 1.0 / dmine;
 #pragma unroll
-      for (int i = 0; i < NB; ++i)
-        if (i > j) S[i][j] = a[i] * rj;
+      for (int i = 0; i < NB; ++i) {
+        const double l = i > j ? a[i] * rj : 0.0;
+        if (i > j) S[i][j] = l;
+        Lt[j][i] = l;
+      }
       dg[j] = dmine;
       rdg[j] = rj;
       double lg = log(dmine);
@@ -280,13 +288,15 @@ __device__ int potrf_inv64(MatD &S, double *dg, double *rdg, MatD &X, double &ls
     const int j = tid;
     double x[NB];
 #pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      double s = i == j ? 1.0 : 0.0;
+    for (int i = 0; i < NB; ++i) x[i] = i == j ? 1.0 : 0.0;
 #pragma unroll
-      for (int k = 0; k < i; ++k) s -= S[i][k] * x[k];
-      x[i] = s * rdg[i];
-      X[i][j] = x[i];
+    for (int k = 0; k < NB; ++k) {
+      x[k] *= rdg[k];
+#pragma unroll
+      for (int i = k + 1; i < NB; ++i) x[i] -= Lt[k][i] * x[k];
     }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) Xf[i][j] = (float)x[i];
   }
   __syncthreads();
   return fail;
@@ -343,7 +353,7 @@ __device__ __forceinline__ void set_nan(MatF &M) {
 // giving the map A = Q_aa - Z, B = V, D = Pc of E_a -> E_e.  A problem's last
 // chunk has no successor and no map.
 __global__ void __launch_bounds__(NT) k_wf1_sum(const Args A) {
-  __shared__ MatD S, X;   // X also holds Y and W once its FP32 copy is taken
+  __shared__ MatD S, X;   // X: the factor transposed, then Y and W
   __shared__ MatF Xf, V, Z, Pc, Cf;
   __shared__ double dg[NB], rdg[NB];
   const int32_t c = blockIdx.x;
@@ -366,11 +376,10 @@ __global__ void __launch_bounds__(NT) k_wf1_sum(const Args A) {
     load_blocks(A.Q, A.Qd, p, i, S, &Cf);
     for (int e = threadIdx.x; e < NB * NB; e += NT) S[e / NB][e % NB] -= (double)Pc[e / NB][e % NB];
     __syncthreads();
-    if (potrf_inv64(S, dg, rdg, X, unused)) {
+    if (potrf_inv64(S, dg, rdg, X, Xf, unused)) {
       bad = true;
       break;
     }
-    for (int e = threadIdx.x; e < NB * NB; e += NT) Xf[e / NB][e % NB] = (float)X[e / NB][e % NB];
     gemm64<false, false>(Xf, V, 1.f, [&](int r, int q, float v) { Y[r][q] = v; });
     gemm64<true, false>(Y, Y, 1.f, [&](int r, int q, float v) { Z[r][q] += v; });
     gemm64<false, true>(Xf, Cf, 1.f, [&](int r, int q, float v) { Wt[r][q] = v; });
@@ -405,12 +414,11 @@ __global__ void __launch_bounds__(NT) k_wf1_scan(const Args A) {
     __syncthreads();
     for (int e = threadIdx.x; e < NB * NB; e += NT) S[e / NB][e % NB] = (double)Am[e] - (double)Ef[e / NB][e % NB];
     ws_load(cw(A, c, CW_B), Bf);
-    if (potrf_inv64(S, dg, rdg, X, unused)) {   // reported by this chunk's replay
+    if (potrf_inv64(S, dg, rdg, X, Xf, unused)) {   // reported by this chunk's replay
       set_nan(Ef);
       __syncthreads();
       continue;
     }
-    for (int e = threadIdx.x; e < NB * NB; e += NT) Xf[e / NB][e % NB] = (float)X[e / NB][e % NB];
     gemm64<false, true>(Xf, Bf, 1.f, [&](int r, int q, float v) { Y[r][q] = v; });
     ws_load(cw(A, c, CW_D), Ef);
     gemm64<true, false>(Y, Y, 1.f, [&](int r, int q, float v) { Ef[r][q] += v; });
@@ -438,12 +446,11 @@ __global__ void __launch_bounds__(NT) k_wf1_rep(const Args A) {
       for (int e = threadIdx.x; e < NB * NB; e += NT) S[e / NB][e % NB] -= (double)E[e];
       __syncthreads();
     }
-    const int r = potrf_inv64(S, dg, rdg, X, lsum);
+    const int r = potrf_inv64(S, dg, rdg, X, Xf, lsum);
     if (r) {
       fail = NB * b + r;
       break;
     }
-    for (int e = threadIdx.x; e < NB * NB; e += NT) Xf[e / NB][e % NB] = (float)X[e / NB][e % NB];
     // M_b = C_b X_b^T (upper triangular)
     gemm64<false, true>(Cf, Xf, 1.f, [&](int i, int j, float v) { Mf[i][j] = v; });
     store_blocks(A.L, A.Ld, p, b, [&](int cc) { return dg[cc]; }, [&](int i, int cc) { return S[i][cc]; },
@@ -570,7 +577,7 @@ template <int PASS> __global__ void __launch_bounds__(NT) k_wlin_scan(const Args
 __global__ void __launch_bounds__(NT) k_wf2_rep(const Args A) {
   __shared__ MatF Xf, Pf, Wf, Ef, Tf;
   __shared__ double red[4];
-  __shared__ double sdg[NB];
+  __shared__ double sdg[NB], red4[4][NB];
   const int32_t c = blockIdx.x;
   const Chunk ch = A.chunks[c];
   const Prob p = A.probs[ch.prob];
@@ -583,27 +590,36 @@ __global__ void __launch_bounds__(NT) k_wf2_rep(const Args A) {
     ws_load(wsb, Xf);
     ws_load(wsb + NB * NB, Pf);
     const bool last = b == nb - 1;
+    // W's block for the trace, loaded before the products so that its latency
+    // overlaps them
+    double wv[kSlotIters];
+    if (A.Wm) read_block(A.Wm, A.Wmd, p, b, wv);
     if (!last)   // E = Sigma_{b+1,b} = -W P
       gemm64<false, false>(Wf, Pf, -1.f, [&](int i, int j, float v) { Ef[i][j] = v; });
     // Sigma_bb = X^T X - P^T E
     gemm64<true, false>(Xf, Xf, 1.f, [&](int i, int j, float v) { Tf[i][j] = v; });
     if (!last) gemm64<true, false>(Pf, Ef, -1.f, [&](int i, int j, float v) { Tf[i][j] += v; });
-    // FP64 diagonal: sum_k X_ki^2 - sum_k P_ki E_ki
+    // FP64 diagonal: sum_k X_ki^2 - sum_k P_ki E_ki, four threads per entry
+    {
+      const int i = threadIdx.x & 63, q = threadIdx.x >> 6;
+      double s = 0.0;
+#pragma unroll
+      for (int k = 16 * q; k < 16 * q + 16; ++k) {
+        s += (double)Xf[k][i] * (double)Xf[k][i];
+        if (!last) s -= (double)Pf[k][i] * (double)Ef[k][i];
+      }
+      red4[q][i] = s;
+    }
+    __syncthreads();
     if (threadIdx.x < NB) {
       const int i = threadIdx.x;
-      double s = 0.0;
-      for (int k = 0; k < NB; ++k) s += (double)Xf[k][i] * (double)Xf[k][i];
-      if (!last)
-        for (int k = 0; k < NB; ++k) s -= (double)Pf[k][i] * (double)Ef[k][i];
-      sdg[i] = s;
+      sdg[i] = (red4[0][i] + red4[1][i]) + (red4[2][i] + red4[3][i]);
     }
     __syncthreads();
     store_blocks(A.Sig, A.Sigd, p, b, [&](int cc) { return sdg[cc]; },
                  [&](int i, int cc) { return (double)Tf[i][cc]; },
                  [&](int rr, int cc) { return last ? 0.0 : (double)Ef[rr][cc]; });
     if (A.Wm) {   // tr(Sigma W) over the stored entries (off-diagonal ones twice)
-      double wv[kSlotIters];
-      read_block(A.Wm, A.Wmd, p, b, wv);
       for_block_slots(b, p.n, [&](int it, int cc, int d, int64_t, bool valid) {
         if (!valid) return;
         const double sv = d == 0 ? sdg[cc] : (d <= NB - 1 - cc ? (double)Tf[cc + d][cc] : (double)Ef[d - NB + cc][cc]);
