@@ -224,7 +224,12 @@ typedef struct {
 
 /* Build a plan (host object): chunking of every problem into about
  * target_chunks lanes (0: library default), bandwidth ranges, workspace
- * layout.  Problems may have any n >= 0 and k in [0, BO_KMAX]. */
+ * layout.  Problems may have any n >= 0 and k in [0, BO_KMAX].  A plan with
+ * problems of several bandwidths also creates one HIP stream per extra
+ * bandwidth range (default priority) and the events that fork them from the
+ * caller's stream and join them back within bo_plan_forward and
+ * bo_plan_gauss_loss, so create it with the device current that runs it; one
+ * plan serves one call at a time. */
 bo_status bo_plan_create(const bo_problem *probs, int32_t nprob, int64_t target_chunks,
                          bo_plan **out);
 bo_status bo_plan_workspace_size(const bo_plan *plan, size_t *bytes);

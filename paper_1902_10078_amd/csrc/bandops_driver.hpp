@@ -212,10 +212,14 @@ inline void set_range(Args &A, const KRange &r) {
 }
 
 // ---------------------------------------------------------------- sequences
-// Return codes: 0 ok, otherwise the backend's error.
+// Return codes: 0 ok, otherwise the backend's error.  A backend may restrict
+// a sequence to one bandwidth range (be.range_on): the ranges touch disjoint
+// problems, chunks and workspace slots, so they can run on separate streams.
 
 template <class BE> int seq_clear(BE &be, const Sched &s, Args A) {
-  for (const KRange &r : s.ranges) {
+  for (size_t ri = 0; ri < s.ranges.size(); ++ri) {
+    const KRange &r = s.ranges[ri];
+    if (!be.range_on((int)ri)) continue;
     set_range(A, r);
     if (int e = be.clear(A, r.c_cnt)) return e;
   }
@@ -228,7 +232,9 @@ template <class BE> int seq_clear(BE &be, const Sched &s, Args A) {
 // right-hand side of the F2 chunk maps it accumulates (A.lmap_out).
 template <class BE> int seq_f1(BE &be, const Sched &s, Args A, int prec, bool want_P,
                                const void *rep_y = nullptr) {
-  for (const KRange &r : s.ranges) {
+  for (size_t ri = 0; ri < s.ranges.size(); ++ri) {
+    const KRange &r = s.ranges[ri];
+    if (!be.range_on((int)ri)) continue;
     set_range(A, r);
     if (r.K > 0 && r.max_nchunk > 1) {
       if (int e = be.step(ST_F1_SUM, r.K, prec, A, r.c_cnt)) return e;
@@ -249,7 +255,9 @@ template <class BE> int seq_f1(BE &be, const Sched &s, Args A, int prec, bool wa
 }
 
 template <class BE> int seq_pc(BE &be, const Sched &s, Args A, int prec) {
-  for (const KRange &r : s.ranges) {
+  for (size_t ri = 0; ri < s.ranges.size(); ++ri) {
+    const KRange &r = s.ranges[ri];
+    if (!be.range_on((int)ri)) continue;
     set_range(A, r);
     if (r.K > 0 && r.max_nchunk > 1)
       if (int e = be.step(ST_PC, r.K, prec, A, r.c_cnt)) return e;
@@ -263,7 +271,9 @@ template <class BE> int seq_lin(BE &be, const Sched &s, Args A, int prec, int pa
   static const int sum_step[4] = {ST_FS_SUM, ST_F2_SUM, ST_B1_SUM, ST_B2_SUM};
   static const int rep_step[4] = {ST_FS_REP, ST_F2_REP, ST_B1_REP, ST_B2_REP};
   const bool desc = (pass == PASS_F2 || pass == PASS_B2);
-  for (const KRange &r : s.ranges) {
+  for (size_t ri = 0; ri < s.ranges.size(); ++ri) {
+    const KRange &r = s.ranges[ri];
+    if (!be.range_on((int)ri)) continue;
     set_range(A, r);
     if (r.K > 0 && r.max_nchunk > 1) {
       if (!have_maps || r.K > KMAX_FUSED)

@@ -9,6 +9,7 @@
 #include <functional>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "../../include/bandops.h"
 #include "bandops_driver.hpp"
@@ -194,6 +195,8 @@ namespace {
 
 struct GpuBE {
   hipStream_t s;
+  int only = -1;   // >= 0: run the sequences of this bandwidth range alone, no finalisation
+  bool range_on(int r) const { return only < 0 || only == r; }
   int step(int st, int K, int prec, const Args &a, int64_t count) {
     if (K < 0 || K > bo::KMAX_SUPPORTED) return -4;
     if (count <= 0) return 0;
@@ -204,7 +207,7 @@ struct GpuBE {
     return profiled(bo::ST_COUNT, s, [&] { return launch_items<bo::ClearPart>(a, count, s); });
   }
   int finalize(const Args &a, int64_t count) {
-    if (count <= 0) return 0;
+    if (count <= 0 || only >= 0) return 0;
     return profiled(bo::ST_COUNT + 1, s, [&] {
       hipLaunchKernelGGL(k_finalize, dim3((unsigned)count), dim3(kBlock), 0, s, a);
       return hipGetLastError() == hipSuccess ? 0 : -2;
@@ -740,7 +743,42 @@ extern "C" bo_status bo_logdet_bwd(bo_prec prec, const bo_band *L, const double 
 struct bo_plan {
   Sched s;
   void *pinned = nullptr;   // host copy of the device tables (pinned)
+  // One stream per bandwidth range after the first (default priority) and the
+  // events that fork them from the caller's stream and join them back.
+  std::vector<hipStream_t> aux;
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> join;
 };
+
+// Run `pipe` (a pass sequence that takes a GpuBE) once per bandwidth range,
+// each range on its own stream forked from `stream` and joined back to it
+// before the per-problem finalisation: the ranges share no problem, chunk or
+// workspace slot, so their scans (serial, narrow launches at the wide
+// bandwidths) overlap the other ranges' streaming passes.  Event records and
+// waits are stream-ordered and graph-capturable (the captured graph holds the
+// ranges as parallel branches).  Plans with one range, or without streams,
+// run on `stream` alone.
+template <class F>
+static int run_ranges(const bo_plan *plan, hipStream_t stream, const Args &A, F &&pipe) {
+  const int nr = (int)plan->s.ranges.size();
+  if (nr <= 1 || (int)plan->aux.size() + 1 < nr || !plan->fork) {
+    GpuBE be{stream};
+    return pipe(be);
+  }
+  if (hipEventRecord(plan->fork, stream) != hipSuccess) return -2;
+  for (int r = 0; r < nr; ++r) {
+    hipStream_t st = r == 0 ? stream : plan->aux[r - 1];
+    if (r > 0 && hipStreamWaitEvent(st, plan->fork, 0) != hipSuccess) return -2;
+    GpuBE be{st};
+    be.only = r;
+    if (int e = pipe(be)) return e;
+    if (r > 0 && (hipEventRecord(plan->join[r - 1], st) != hipSuccess ||
+                  hipStreamWaitEvent(stream, plan->join[r - 1], 0) != hipSuccess))
+      return -2;
+  }
+  GpuBE be{stream};
+  return bo::seq_finalize(be, plan->s, A);
+}
 
 extern "C" bo_status bo_plan_create(const bo_problem *probs, int32_t nprob, int64_t target_chunks,
                                     bo_plan **out) {
@@ -768,6 +806,22 @@ extern "C" bo_status bo_plan_create(const bo_problem *probs, int32_t nprob, int6
     return fail(BO_EDEVICE, "bo_plan_create: pinned host allocation failed");
   }
   if (tb) std::memcpy(pl->pinned, pl->s.table_blob.data(), tb);
+  const int nr = (int)pl->s.ranges.size();
+  if (nr > 1) {
+    bool ok = hipEventCreateWithFlags(&pl->fork, hipEventDisableTiming) == hipSuccess;
+    for (int r = 1; r < nr && ok; ++r) {
+      hipStream_t st = nullptr;
+      hipEvent_t ev = nullptr;
+      ok = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
+      if (ok) pl->aux.push_back(st);
+      ok = ok && hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess;
+      if (ok) pl->join.push_back(ev);
+    }
+    if (!ok) {
+      bo_plan_destroy(pl);
+      return fail(BO_EDEVICE, "bo_plan_create: stream or event creation failed");
+    }
+  }
   *out = pl;
   return BO_OK;
 }
@@ -850,8 +904,8 @@ extern "C" bo_status bo_plan_forward(const bo_plan *plan, bo_prec prec, const bo
   if (io->x && !io->z) return fail(BO_EINVAL, "bo_plan_forward: x needs z");
   if (io->Sig && prec == BO_MIXED && !io->Sigd) return fail(BO_EINVAL, "bo_plan_forward: Sigd needed");
   A.Sb = nullptr;
-  GpuBE be{stream};
-  return dev_status(bo::pipe_forward(be, plan->s, A, (int)prec), "bo_plan_forward");
+  return dev_status(run_ranges(plan, stream, A, [&](GpuBE &be) { return bo::pipe_forward(be, plan->s, A, (int)prec); }),
+                    "bo_plan_forward");
 }
 
 extern "C" bo_status bo_plan_gauss_loss(const bo_plan *plan, bo_prec prec, const bo_batch_io *io,
@@ -865,8 +919,10 @@ extern "C" bo_status bo_plan_gauss_loss(const bo_plan *plan, bo_prec prec, const
     return fail(BO_EINVAL, "bo_plan_gauss_loss: BO_MIXED needs every FP64 diagonal");
   if (io->Sbar && prec == BO_MIXED && !io->Sbard)
     return fail(BO_EINVAL, "bo_plan_gauss_loss: BO_MIXED needs Sbard with Sbar");
-  GpuBE be{stream};
-  if (bo_status e = dev_status(bo::pipe_gauss_loss(be, plan->s, A, (int)prec, fuse_summaries()),
+  if (bo_status e = dev_status(run_ranges(plan, stream, A,
+                                          [&](GpuBE &be) {
+                                            return bo::pipe_gauss_loss(be, plan->s, A, (int)prec, fuse_summaries());
+                                          }),
                                "bo_plan_gauss_loss"))
     return e;
   if (!io->Sbar) return BO_OK;
@@ -1142,6 +1198,9 @@ extern "C" bo_status bo_plan_stats(const bo_plan *plan, int64_t out[5]) {
 extern "C" bo_status bo_plan_destroy(bo_plan *plan) {
   if (!plan) return BO_OK;
   if (plan->pinned) (void)hipHostFree(plan->pinned);
+  for (hipStream_t st : plan->aux) (void)hipStreamDestroy(st);
+  for (hipEvent_t ev : plan->join) (void)hipEventDestroy(ev);
+  if (plan->fork) (void)hipEventDestroy(plan->fork);
   delete plan;
   return BO_OK;
 }

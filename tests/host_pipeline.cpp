@@ -36,6 +36,7 @@ template <int K> int host_step(int st, const Args &a, int64_t count) {
 constexpr int kKs[] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12};
 
 struct HostBE {
+  bool range_on(int) const { return true; }
   int step(int st, int K, int, const Args &a, int64_t count) {
     switch (K) {
       case 0: return host_step<0>(st, a, count);

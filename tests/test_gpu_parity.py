@@ -426,3 +426,58 @@ def test_padded_record_stride(bo, n, k):
     assert rel_err(host(z), oracle.trsv(Lref, k, y, 0)) <= TOL
     assert abs(logdet.item() - oracle.logdet(Lref, k)) <= TOL * abs(oracle.logdet(Lref, k))
     assert bands_close(Sg[:, :k + 1], oracle.subset_inv(Lref, k), n, k, TOL)
+
+
+def test_graph_capture_forward_four_ranges_mixed(bo):
+    """The forward list over problems of four bandwidths in the mixed format
+    (each bandwidth range on its own stream, forked from and joined to the
+    caller's stream) captured into a HIP graph: every replay, with eager
+    library work on the same buffers in between, equals the eager call bit for
+    bit."""
+    ns, ks = [4000, 1300, 2500, 3100, 700, 5000], [11, 1, 5, 3, 11, 1]
+    Qs, ys, _ = packed_batch(ns, ks, 21)
+    plan = bo.Plan(ns, ks, target_chunks=240)
+    Qf = np.concatenate([q.ravel() for q in Qs])
+    N = sum(ns)
+    kw = dict(Q=dev(Qf, torch.float32), Qd=dev(np.concatenate([q[:, 0] for q in Qs])),
+              y=dev(np.concatenate(ys), torch.float32))
+    for nm in ("L", "Sig"):
+        kw[nm] = torch.zeros(Qf.size, dtype=torch.float32, device="cuda")
+        kw[nm + "d"] = torch.zeros(N, dtype=torch.float64, device="cuda")
+    for nm in ("z", "x"):
+        kw[nm] = torch.zeros(N, dtype=torch.float32, device="cuda")
+    kw["logdet"] = torch.zeros(len(ns), dtype=torch.float64, device="cuda")
+    kw["info"] = torch.zeros(len(ns), dtype=torch.int32, device="cuda")
+    io = plan.io(**kw)
+    plan.forward(1, io)
+    torch.cuda.synchronize()
+    eager = {nm: t.clone() for nm, t in kw.items()}
+    assert int(eager["info"].abs().max().item()) == 0
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            plan.forward(1, io)
+    torch.cuda.current_stream().wait_stream(s)
+    for rep in range(3):
+        for nm in ("L", "Sig", "Ld", "Sigd", "z", "x", "logdet"):
+            kw[nm].fill_(float("nan"))
+        plan.forward(1, io)          # eager work between the replays
+        for nm in ("L", "Sig", "x"):
+            kw[nm].fill_(float("nan"))
+        g.replay()
+        torch.cuda.synchronize()
+        for nm in ("L", "Sig", "Ld", "Sigd", "z", "x", "logdet", "info"):
+            assert torch.equal(kw[nm], eager[nm]), (rep, nm)
+    # the eager result itself against the oracle on the stored inputs
+    Lh = host(eager["L"])
+    Ldh = host(eager["Ld"])
+    for p, (n, k) in enumerate(zip(ns, ks)):
+        Qr = Qs[p].astype(np.float32).astype(np.float64)
+        Qr[:, 0] = Qs[p][:, 0]
+        Lr, _ = oracle.chol(Qr, k)
+        o, v = plan.boff[p], plan.voff[p]
+        Lg = Lh[o:o + n * (k + 1)].reshape(n, k + 1).copy()
+        Lg[:, 0] = Ldh[v:v + n]
+        assert rel_err(Lg * band_mask(n, k), Lr) <= TOL_MIXED, p
