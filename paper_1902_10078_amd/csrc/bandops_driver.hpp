@@ -69,8 +69,12 @@ inline int64_t chunk_len_for(int64_t n, int k, int64_t rows, int64_t target_chun
 
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
+// kscale (optional, KMAX_SUPPORTED + 1 entries >= 1): the chunks of the
+// problems of bandwidth k are kscale[k] times as long, so that bandwidths
+// whose chunk maps are expensive to combine (the scans compose K x K maps
+// serially above K = 9) get fewer of them.
 inline bool build_sched(const ProbIn *in, int nprob, int64_t target_chunks, int64_t min_len, int32_t G,
-                        Sched &s) {
+                        Sched &s, const int32_t *kscale = nullptr) {
   s = Sched();
   s.G = G;
   s.nprob = nprob;
@@ -91,6 +95,11 @@ inline bool build_sched(const ProbIn *in, int nprob, int64_t target_chunks, int6
     d.voff = p.voff;
     d.orig = ord[ii];
     d.clen = p.n > 0 ? chunk_len_for(p.n, p.k, s.rows, target_chunks, min_len, G) : 1;
+    if (p.n > 0 && kscale && kscale[p.k] > 1) {
+      d.clen *= kscale[p.k];
+      const int64_t cap = (int64_t)G * G;   // keep the two-level scan's bound
+      if ((p.n + d.clen - 1) / d.clen > cap) d.clen = (p.n + cap - 1) / cap;
+    }
     d.nchunk = p.n > 0 ? (int32_t)((p.n + d.clen - 1) / d.clen) : 0;
     d.chunk0 = c;
     // Two-level scan: about sqrt(nchunk) chunks per group balances the serial

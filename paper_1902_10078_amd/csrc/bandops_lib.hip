@@ -6,6 +6,7 @@
 
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <functional>
 #include <mutex>
 #include <string>
@@ -230,6 +231,27 @@ int64_t default_min_len() {
     return (int64_t)(t > 0 ? t : 32);
   }();
   return v;
+}
+// Per-bandwidth chunk-length factors "k:f,k:f" from BANDOPS_KSCALE, a switch
+// for schedule experiments (unset: every factor 1, the measured best).
+const int32_t *env_kscale() {
+  static int32_t v[bo::KMAX_SUPPORTED + 1];
+  static bool any = [] {
+    for (int k = 0; k <= bo::KMAX_SUPPORTED; ++k) v[k] = 1;
+    const char *e = std::getenv("BANDOPS_KSCALE");
+    bool set = false;
+    while (e && *e) {
+      int k = 0, f = 0;
+      if (std::sscanf(e, "%d:%d", &k, &f) == 2 && k >= 0 && k <= bo::KMAX_SUPPORTED && f >= 1) {
+        v[k] = f;
+        set = true;
+      }
+      const char *c = std::strchr(e, ',');
+      e = c ? c + 1 : nullptr;
+    }
+    return set;
+  }();
+  return any ? v : nullptr;
 }
 bool fuse_summaries() {
   static bool v = [] {
@@ -796,7 +818,7 @@ extern "C" bo_status bo_plan_create(const bo_problem *probs, int32_t nprob, int6
   }
   bo_plan *pl = new bo_plan();
   if (!bo::build_sched(in.data(), nprob, target_chunks > 0 ? target_chunks : default_target_chunks(),
-                       default_min_len(), group_size(), pl->s)) {
+                       default_min_len(), group_size(), pl->s, env_kscale())) {
     delete pl;
     return fail(BO_EINVAL, "bo_plan_create: bad problem table");
   }
