@@ -102,6 +102,27 @@ struct Args {
 
 __device__ __forceinline__ int64_t nblocks(int64_t n) { return (n + NB - 1) / NB; }
 
+// Workgroup barrier for LDS traffic: waits for this wavefront's LDS accesses
+// only (lgkmcnt(0); its global loads may stay in flight across it, so the next
+// block's loads overlap the current block's work) and joins the workgroup.
+// The empty asm statements keep the compiler from moving memory accesses
+// across it.  Threads of a workgroup here exchange data only through LDS.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0xc07f);
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+// The thread index passed through an empty asm statement: address arithmetic
+// derived from it is then recomputed where it is used, instead of being
+// hoisted out of the block loops and held (spilled) across them.
+__device__ __forceinline__ int opaque_tid() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
 // ----------------------------------------------------------- block I/O
 constexpr int kSlotIters = (NB * W + NT - 1) / NT;   // slots of a block per thread
 
@@ -110,7 +131,7 @@ constexpr int kSlotIters = (NB * W + NT - 1) / NT;   // slots of a block per thr
 template <class F> __device__ __forceinline__ void for_block_slots(int64_t b, int64_t n, F &&f) {
 #pragma unroll
   for (int it = 0; it < kSlotIters; ++it) {
-    const int idx = threadIdx.x + it * NT;
+    const int idx = opaque_tid() + it * NT;
     if (idx < NB * W) {
       const int c = idx / W, d = idx - c * W;
       const int64_t j = NB * b + c;
@@ -121,27 +142,29 @@ template <class F> __device__ __forceinline__ void for_block_slots(int64_t b, in
 
 // Every slot of block b of band Bp/Bd into registers (all loads issued before
 // any is used); slots past the matrix end read 1 on the diagonal, else 0.
+// R = float keeps a block that only goes into FP32 tiles in half the
+// registers (the FP64 diagonal rounded).
+template <typename R>
 __device__ __forceinline__ void read_block(const float *Bp, const double *Bd, const Prob &p, int64_t b,
-                                           double (&v)[kSlotIters]) {
+                                           R (&v)[kSlotIters]) {
 #pragma unroll
-  for (int it = 0; it < kSlotIters; ++it) v[it] = 0.0;
+  for (int it = 0; it < kSlotIters; ++it) v[it] = 0;
   for_block_slots(b, p.n, [&](int it, int c, int d, int64_t j, bool valid) {
-    if (valid) v[it] = d == 0 ? Bd[p.voff + j] : (double)Bp[(p.boff + j * W) + d];
-    else if (d == 0) v[it] = 1.0;   // identity past the matrix end
+    if (valid) v[it] = d == 0 ? (R)Bd[p.voff + j] : (R)Bp[(p.boff + j * W) + d];
+    else if (d == 0) v[it] = 1;   // identity past the matrix end
   });
 }
 
 // Diagonal block (symmetric, full; E = double or float) and coupling block
 // (upper triangular, FP32) of band Bp/Bd at block b; rows past n read as the
 // identity on the diagonal and zero elsewhere.
-template <typename E>
-__device__ void load_blocks(const float *Bp, const double *Bd, const Prob &p, int64_t b, E (&S)[NB][LDF],
-                            MatF *Cf) {
-  double v[kSlotIters];
-  read_block(Bp, Bd, p, b, v);
+// (put_blocks: from the registers read_block filled, so that the loads of
+// the next block can be issued while the current one is worked on.)
+template <typename R, typename E>
+__device__ __forceinline__ void put_blocks(const R (&v)[kSlotIters], const Prob &p, int64_t b, E (&S)[NB][LDF], MatF *Cf) {
   if (Cf)
     for (int e = threadIdx.x; e < NB * NB; e += NT) (*Cf)[e / NB][e % NB] = 0.f;
-  __syncthreads();
+  lds_barrier();
   for_block_slots(b, p.n, [&](int it, int c, int d, int64_t, bool) {
     if (d <= NB - 1 - c) {
       S[c + d][c] = (E)v[it];
@@ -150,26 +173,32 @@ __device__ void load_blocks(const float *Bp, const double *Bd, const Prob &p, in
       (*Cf)[d - NB + c][c] = (float)v[it];
     }
   });
-  __syncthreads();
+  lds_barrier();
 }
-
-// The coupling block alone (upper triangular, zero below).
-__device__ void load_coupling(const float *Bp, const double *Bd, const Prob &p, int64_t b, MatF &Cf) {
+template <typename E>
+__device__ __forceinline__ void load_blocks(const float *Bp, const double *Bd, const Prob &p, int64_t b, E (&S)[NB][LDF],
+                            MatF *Cf) {
   double v[kSlotIters];
   read_block(Bp, Bd, p, b, v);
+  put_blocks(v, p, b, S, Cf);
+}
+
+// The coupling block alone (upper triangular, zero below), from registers.
+template <typename R>
+__device__ __forceinline__ void put_coupling(const R (&v)[kSlotIters], const Prob &p, int64_t b, MatF &Cf) {
   for (int e = threadIdx.x; e < NB * NB; e += NT) Cf[e / NB][e % NB] = 0.f;
-  __syncthreads();
+  lds_barrier();
   for_block_slots(b, p.n, [&](int it, int c, int d, int64_t, bool) {
     if (d > NB - 1 - c) Cf[d - NB + c][c] = (float)v[it];
   });
-  __syncthreads();
+  lds_barrier();
 }
 
 // Store a block pair into band Bp/Bd: the lower triangle of Dg (diagonal
 // values from dg when given, else Dg's own) and the upper triangle of Cf
 // (when given; the coupling slots are written 0 when it is not).
 template <class DiagF, class LowF, class CoupF>
-__device__ void store_blocks(float *Bp, double *Bd, const Prob &p, int64_t b, DiagF &&diag, LowF &&low,
+__device__ __forceinline__ void store_blocks(float *Bp, double *Bd, const Prob &p, int64_t b, DiagF &&diag, LowF &&low,
                              CoupF &&coup) {
   for_block_slots(b, p.n, [&](int, int c, int d, int64_t j, bool valid) {
     if (j >= p.n) return;
@@ -190,7 +219,7 @@ __device__ void store_blocks(float *Bp, double *Bd, const Prob &p, int64_t b, Di
 // component r.
 template <bool TA, bool TB, class Out>
 __device__ __forceinline__ void gemm64(const MatF &A, const MatF &B, float alpha, Out &&out) {
-  __syncthreads();
+  lds_barrier();
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int jl = 16 * w + (l & 15), kq = l >> 4;
   float4_ acc[4];
@@ -207,12 +236,12 @@ __device__ __forceinline__ void gemm64(const MatF &A, const MatF &B, float alpha
       acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[t], 0, 0, 0);
     }
   }
-  __syncthreads();   // every read of A and B is done before any output is written
+  lds_barrier();   // every read of A and B is done before any output is written
 #pragma unroll
   for (int t = 0; t < 4; ++t)
 #pragma unroll
     for (int r = 0; r < 4; ++r) out(16 * t + 4 * kq + r, jl, alpha * acc[t][r]);
-  __syncthreads();
+  lds_barrier();
 }
 
 
@@ -224,108 +253,189 @@ __device__ __forceinline__ double bcast_lane(double v, int src) {
   return __hiloint2double(hi, lo);
 }
 
-// FP64 Cholesky S = L L^T of the symmetric block S (held full) and X = L^{-1},
-// each by one wavefront with its matrix in registers (lane j holds column j).
-// Cholesky, right-looking: at column c every lane j > c takes its
-// l_j = L[j, c] from its own copy of S[c, j] (the update keeps both
-// triangles), publishes it in LDS, reads every l_i (i > c) back (the same
-// address for all lanes: a broadcast) and applies S[i, j] -= l_i l_j.  The
-// factor goes to S (strict lower triangle) and, transposed, to Lt (row j =
-// column j of L), so that the inverse reads contiguous rows: X by the same
-// right-looking order on the columns of the identity,
-//   X[k, j] /= L_kk,  X[i, j] -= L[i, k] X[k, j]  (i > k),
-// written in FP32 to Xf (zero above the diagonal).  dg / rdg receive L's
-// diagonal and its reciprocal; thread 0 adds the log-determinant of L to
-// lsum.  Returns 0, or 1 + the first column whose pivot is not positive (then
-// S, Xf, dg are unspecified).  Every thread of the workgroup calls it.
-__device__ int potrf_inv64(MatD &S, double *dg, double *rdg, MatD &Lt, MatF &Xf, double &lsum) {
-  __shared__ int fail_s;
-  __shared__ double lb[NB];
-  const int tid = threadIdx.x;
-  if (tid < NB) {
-    const int j = tid;
-    double a[NB];
+// Reciprocal square root of x > 0 in FP64: the hardware estimate refined by
+// two Newton steps y <- y + y (1/2 - (x/2) y^2), each of which roughly doubles
+// the number of correct bits.
+__device__ __forceinline__ double rsqrt64(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
 #pragma unroll
-    for (int i = 0; i < NB; ++i) a[i] = S[i][j];
-    double dmine = 1.0;
-    int fail = 0;
-#pragma unroll
-    for (int c = 0; c < NB; ++c) {
-      const double piv = bcast_lane(a[c], c);
-      if (!(piv > 0.0)) {
-        fail = c + 1;
-        break;
-      }
-      const double d = sqrt(piv), r = 1.0 / d;
-      if (j == c) dmine = d;
-      // lane c keeps S's column c unscaled (l = 0 leaves it as is); L's
-      // column c is that column over d, taken when L is written out
-      const double lj = j > c ? a[c] * r : 0.0;
-      lb[j] = lj;   // one wavefront: its LDS accesses complete in order
-      __builtin_amdgcn_wave_barrier();
-#pragma unroll
-      for (int i = c + 1; i < NB; ++i) a[i] -= lb[i] * lj;
-    }
-    if (j == 0) fail_s = fail;
-    if (!fail) {
-      const double rj = 1.0 / dmine;
-#pragma unroll
-      for (int i = 0; i < NB; ++i) {
-        const double l = i > j ? a[i] * rj : 0.0;
-        if (i > j) S[i][j] = l;
-        Lt[j][i] = l;
-      }
-      dg[j] = dmine;
-      rdg[j] = rj;
-      double lg = log(dmine);
-      for (int off = 32; off >= 1; off >>= 1) lg += __shfl_xor(lg, off, 64);
-      if (j == 0) lsum += lg;
-    }
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-h * y, y, 0.5);
+    y = fma(y, e, y);
   }
-  __syncthreads();
-  const int fail = fail_s;
-  if (!fail && tid < NB) {
-    const int j = tid;
-    double x[NB];
-#pragma unroll
-    for (int i = 0; i < NB; ++i) x[i] = i == j ? 1.0 : 0.0;
-#pragma unroll
-    for (int k = 0; k < NB; ++k) {
-      x[k] *= rdg[k];
-#pragma unroll
-      for (int i = k + 1; i < NB; ++i) x[i] -= Lt[k][i] * x[k];
-    }
-#pragma unroll
-    for (int i = 0; i < NB; ++i) Xf[i][j] = (float)x[i];
-  }
-  __syncthreads();
-  return fail;
+  return y;
 }
 
-__device__ __forceinline__ void ws_load(const float *src, MatF &M) {
-  float4 v[NB * NB / (4 * NT)];
+// FP64 Cholesky S = L L^T of the symmetric block S (held full) and X = L^{-1}
+// by the workgroup's four wavefronts, wavefront w holding rows [16w, 16w + 16)
+// of every column in registers (lane j = column j).
+//
+// Cholesky, right-looking: at column c the wavefront owning row c takes
+// l_j = L[j, c] = S[c, j] / sqrt(S[c, c]) (the trailing update keeps both
+// triangles, so row c holds column c), publishes the l_j in LDS (two buffers
+// alternate, so one barrier per column suffices), and every wavefront applies
+// S[i, j] -= l_i l_j to its rows (l_i = 0 for i <= c leaves those as they
+// are).  Lane c's column is never touched after step c, so L[i, c] is that
+// column over the pivot's square root.  L's strict lower triangle goes to S.
+//
+// Inverse by row blocks of 16, L_qq X_q = E_q - sum_{m<q} L_qm X_m (E the
+// identity's rows): in round m wavefront m solves its rows with L_mm and
+// publishes them (transposed into S's upper triangle, which the Cholesky no
+// longer needs, and in FP32 to Xf); after the round's barrier every later
+// wavefront subtracts L_qm X_m from its rows.  X is exactly zero above the
+// diagonal.  dg / rdg receive L's diagonal and its reciprocal; lsum gains
+// log det L.  Returns 0, or 1 + the first column whose pivot is not positive
+// (then S, Xf, dg are unspecified).  Every thread of the workgroup calls it.
+__device__ int potrf_inv64(MatD &S, double *dg, double *rdg, MatF &Xf, double &lsum) {
+  __shared__ int fail_s;
+  __shared__ double lb[2][NB];
+  const int tid = threadIdx.x, j = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wavefront index (uniform)
+  const int r0 = 16 * w;
+  double a[16];
 #pragma unroll
-  for (int it = 0; it < NB * NB / (4 * NT); ++it) v[it] = reinterpret_cast<const float4 *>(src)[threadIdx.x + it * NT];
+  for (int t = 0; t < 16; ++t) a[t] = S[r0 + t][j];
+  if (tid == 0) fail_s = 0;
+#pragma unroll 1
+  for (int cb = 0; cb < 4; ++cb) {
 #pragma unroll
-  for (int it = 0; it < NB * NB / (4 * NT); ++it) {
+    for (int tc = 0; tc < 16; ++tc) {
+      const int c = 16 * cb + tc;
+      if (w == cb) {
+        const double piv = bcast_lane(a[tc], c);
+        const bool ok = piv > 0.0;
+        const double r = rsqrt64(ok ? piv : 1.0);
+        lb[tc & 1][j] = j > c ? a[tc] * r : 0.0;
+        if (j == c) {
+          dg[c] = piv * r;
+          rdg[c] = r;
+          if (!ok && fail_s == 0) fail_s = c + 1;
+        }
+      }
+      lds_barrier();
+      const double lj = lb[tc & 1][j];
+      double li[16];
+#pragma unroll
+      for (int t = 0; t < 16; ++t) li[t] = lb[tc & 1][r0 + t];
+#pragma unroll
+      for (int t = 0; t < 16; ++t) a[t] = fma(-li[t], lj, a[t]);
+      // the update is applied here, not deferred to the end of the loop with
+      // every step's l values held in registers meanwhile
+#pragma unroll
+      for (int t = 0; t < 16; ++t) asm volatile("" : "+v"(a[t]));
+    }
+  }
+  lds_barrier();
+  const int fail = fail_s;
+  if (fail) return fail;
+  {
+    const double rj = rdg[j];
+#pragma unroll
+    for (int t = 0; t < 16; ++t)
+      if (r0 + t > j) S[r0 + t][j] = a[t] * rj;
+  }
+  if (w == 0) {
+    double lg = log(dg[j]);
+    for (int off = 32; off >= 1; off >>= 1) lg += __shfl_xor(lg, off, 64);
+    if (j == 0) lsum += lg;
+  }
+  lds_barrier();
+  double x[16];
+#pragma unroll
+  for (int t = 0; t < 16; ++t) x[t] = r0 + t == j ? 1.0 : 0.0;
+#pragma unroll 1
+  for (int m = 0; m < 4; ++m) {
+    // L's entries are read a column ahead of their use; the empty asm
+    // statements with a memory clobber keep the compiler from hoisting every
+    // column's loads to the top (rows and columns are indexed through m, not
+    // r0, so that nothing is invariant across the rounds either)
+    const int m0 = 16 * m;
+    if (w == m) {   // forward substitution with L_mm, then publish X_m
+      double cur[16], nxt[16], rd = rdg[m0], rdn = 0.0;
+#pragma unroll
+      for (int t = 1; t < 16; ++t) cur[t] = S[m0 + t][m0];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        if (k < 15) {
+#pragma unroll
+          for (int t = k + 2; t < 16; ++t) nxt[t] = S[m0 + t][m0 + k + 1];
+          rdn = rdg[m0 + k + 1];
+        }
+        asm volatile("" ::: "memory");
+        x[k] *= rd;
+#pragma unroll
+        for (int t = k + 1; t < 16; ++t) x[t] = fma(-cur[t], x[k], x[t]);
+#pragma unroll
+        for (int t = k + 2; t < 16; ++t) cur[t] = nxt[t];
+        rd = rdn;
+      }
+#pragma unroll
+      for (int t = 0; t < 16; ++t) {
+        if (m0 + t >= j) S[j][m0 + t] = x[t];
+        Xf[m0 + t][j] = (float)x[t];
+      }
+    }
+    lds_barrier();
+    if (w > m) {   // subtract L_wm X_m (X_m read back from S's upper triangle)
+      double lc[16], ln[16], xc = S[j][m0], xn = 0.0;
+#pragma unroll
+      for (int t = 0; t < 16; ++t) lc[t] = S[r0 + t][m0];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        if (k < 15) {
+#pragma unroll
+          for (int t = 0; t < 16; ++t) ln[t] = S[r0 + t][m0 + k + 1];
+          xn = S[j][m0 + k + 1];
+        }
+        asm volatile("" ::: "memory");
+        const double xm = m0 + k >= j ? xc : 0.0;   // X is zero above the diagonal
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+          x[t] = fma(-lc[t], xm, x[t]);
+          lc[t] = ln[t];
+        }
+        xc = xn;
+      }
+    }
+  }
+  return 0;
+}
+
+// A 64 x 64 FP32 workspace matrix (row-major) into registers, and from them
+// into LDS; ws_load does both.
+constexpr int kWsIters = NB * NB / (4 * NT);
+typedef float4 WsReg[kWsIters];
+__device__ __forceinline__ void ws_read(const float *src, WsReg &v) {
+#pragma unroll
+  for (int it = 0; it < kWsIters; ++it) v[it] = reinterpret_cast<const float4 *>(src)[threadIdx.x + it * NT];
+}
+__device__ __forceinline__ void ws_put(const WsReg &v, MatF &M) {
+#pragma unroll
+  for (int it = 0; it < kWsIters; ++it) {
     const int e = 4 * (threadIdx.x + it * NT), r = e / NB, c = e % NB;
     M[r][c] = v[it].x;
     M[r][c + 1] = v[it].y;
     M[r][c + 2] = v[it].z;
     M[r][c + 3] = v[it].w;
   }
-  __syncthreads();
+  lds_barrier();
+}
+__device__ __forceinline__ void ws_load(const float *src, MatF &M) {
+  WsReg v;
+  ws_read(src, v);
+  ws_put(v, M);
 }
 __device__ __forceinline__ void ws_store(float *dst, const MatF &M) {
-  __syncthreads();
+  lds_barrier();
   for (int e = threadIdx.x; e < NB * NB; e += NT) dst[e] = M[e / NB][e % NB];
 }
 
 __device__ double block_sum(double v, double *red) {
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-  __syncthreads();
+  lds_barrier();
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
+  lds_barrier();
   return red[0] + red[1] + red[2] + red[3];
 }
 
@@ -369,14 +479,18 @@ __global__ void __launch_bounds__(NT) k_wf1_sum(const Args A) {
     Z[e / NB][e % NB] = 0.f;
     Pc[e / NB][e % NB] = 0.f;
   }
-  __syncthreads();
+  lds_barrier();
   double unused = 0.0;
   bool bad = false;
+  // each block's loads are issued while the block before it is worked on
+  double q[kSlotIters];
+  if (ch.b0 + 1 < ch.b1) read_block(A.Q, A.Qd, p, ch.b0 + 1, q);
   for (int64_t i = ch.b0 + 1; i < ch.b1; ++i) {
-    load_blocks(A.Q, A.Qd, p, i, S, &Cf);
+    put_blocks(q, p, i, S, &Cf);
+    if (i + 1 < ch.b1) read_block(A.Q, A.Qd, p, i + 1, q);
     for (int e = threadIdx.x; e < NB * NB; e += NT) S[e / NB][e % NB] -= (double)Pc[e / NB][e % NB];
-    __syncthreads();
-    if (potrf_inv64(S, dg, rdg, X, Xf, unused)) {
+    lds_barrier();
+    if (potrf_inv64(S, dg, rdg, Xf, unused)) {
       bad = true;
       break;
     }
@@ -386,7 +500,7 @@ __global__ void __launch_bounds__(NT) k_wf1_sum(const Args A) {
     gemm64<true, false>(Wt, Wt, 1.f, [&](int r, int q, float v) { Pc[r][q] = v; });
     gemm64<true, false>(Wt, Y, -1.f, [&](int r, int q, float v) { V[r][q] = v; });
   }
-  __syncthreads();
+  lds_barrier();
   // an interior block that is not positive definite: the leading part of Q is
   // not either, and the replay of this chunk reports where; the map is NaN
   for (int e = threadIdx.x; e < NB * NB; e += NT) {
@@ -411,12 +525,12 @@ __global__ void __launch_bounds__(NT) k_wf1_scan(const Args A) {
     ws_store(cw(A, c, CW_E), Ef);
     if (c == p.chunk0 + p.nchunk - 1) break;
     const float *Am = cw(A, c, CW_A);
-    __syncthreads();
+    lds_barrier();
     for (int e = threadIdx.x; e < NB * NB; e += NT) S[e / NB][e % NB] = (double)Am[e] - (double)Ef[e / NB][e % NB];
     ws_load(cw(A, c, CW_B), Bf);
-    if (potrf_inv64(S, dg, rdg, X, Xf, unused)) {   // reported by this chunk's replay
+    if (potrf_inv64(S, dg, rdg, Xf, unused)) {   // reported by this chunk's replay
       set_nan(Ef);
-      __syncthreads();
+      lds_barrier();
       continue;
     }
     gemm64<false, true>(Xf, Bf, 1.f, [&](int r, int q, float v) { Y[r][q] = v; });
@@ -437,16 +551,19 @@ __global__ void __launch_bounds__(NT) k_wf1_rep(const Args A) {
   const Prob p = A.probs[ch.prob];
   double lsum = 0.0;
   int64_t fail = 0;
+  double q[kSlotIters];   // the next block's records, loaded behind this block's work
+  read_block(A.Q, A.Qd, p, ch.b0, q);
   for (int64_t b = ch.b0; b < ch.b1; ++b) {
-    load_blocks(A.Q, A.Qd, p, b, S, &Cf);
+    put_blocks(q, p, b, S, &Cf);
+    if (b + 1 < ch.b1) read_block(A.Q, A.Qd, p, b + 1, q);
     if (b > ch.b0) {   // S_b = Q_bb - M_{b-1} M_{b-1}^T
       gemm64<false, true>(Mf, Mf, 1.f, [&](int i, int j, float v) { S[i][j] -= (double)v; });
     } else if (b > 0) {   // the correction entering the chunk
       const float *E = cw(A, c, CW_E);
       for (int e = threadIdx.x; e < NB * NB; e += NT) S[e / NB][e % NB] -= (double)E[e];
-      __syncthreads();
+      lds_barrier();
     }
-    const int r = potrf_inv64(S, dg, rdg, X, Xf, lsum);
+    const int r = potrf_inv64(S, dg, rdg, Xf, lsum);
     if (r) {
       fail = NB * b + r;
       break;
@@ -507,16 +624,25 @@ __global__ void __launch_bounds__(NT) k_wlin_sum(const Args A, int32_t want_b1) 
   set_identity(Rf);
   set_zero(Mf2);
   set_zero(Cb);
-  for (int64_t b = ch.b0; b < ch.b1; ++b) {
+  WsReg px, pp;   // the next block's X, P and W, loaded behind this block's work
+  float pw[kSlotIters];
+  auto fetch = [&](int64_t b) __attribute__((always_inline)) {
     const float *wsb = A.ws + (p.wsoff + b) * kBlockWs;
-    ws_load(wsb, Xf);
-    ws_load(wsb + NB * NB, Pf);
+    ws_read(wsb, px);
+    ws_read(wsb + NB * NB, pp);
+    if (b1) read_block(A.Wm, A.Wmd, p, b, pw);
+  };
+  fetch(ch.b0);
+  for (int64_t b = ch.b0; b < ch.b1; ++b) {
+    ws_put(px, Xf);
+    ws_put(pp, Pf);
+    if (b1) put_blocks(pw, p, b, Sf, &EMf);
+    if (b + 1 < ch.b1) fetch(b + 1);
     if (f2) {
       gemm64<false, false>(Xf, Rf, 1.f, [&](int i, int j, float v) { Tf[i][j] = v; });
       gemm64<true, false>(Tf, Tf, 1.f, [&](int i, int j, float v) { Mf2[i][j] += v; });
     }
     if (b1) {
-      load_blocks(A.Wm, A.Wmd, p, b, Sf, &EMf);
       for (int e = threadIdx.x; e < NB * NB; e += NT) {
         const int i = e / NB, j = e % NB;
         Sf[i][j] += 0.5f * (Cb[i][j] + Cb[j][i]);
@@ -566,7 +692,7 @@ template <int PASS> __global__ void __launch_bounds__(NT) k_wlin_scan(const Args
         const int i = e / NB, j = e % NB;
         Sf[i][j] = Tf[i][j] + Mf[i][j];
       }
-      __syncthreads();
+      lds_barrier();
     }
   }
 }
@@ -585,15 +711,23 @@ __global__ void __launch_bounds__(NT) k_wf2_rep(const Args A) {
   const int64_t nb = nblocks(p.n);
   ws_load(cw(A, c, CW_SF2), Wf);
   double tr = 0.0;
-  for (int64_t b = ch.b1 - 1; b >= ch.b0; --b) {
+  WsReg px, pp;   // the next block's X, P and W, loaded behind this block's work
+  double pw[kSlotIters];
+  auto fetch = [&](int64_t b) __attribute__((always_inline)) {
     const float *wsb = A.ws + (p.wsoff + b) * kBlockWs;
-    ws_load(wsb, Xf);
-    ws_load(wsb + NB * NB, Pf);
+    ws_read(wsb, px);
+    ws_read(wsb + NB * NB, pp);
+    if (A.Wm) read_block(A.Wm, A.Wmd, p, b, pw);
+  };
+  fetch(ch.b1 - 1);
+  for (int64_t b = ch.b1 - 1; b >= ch.b0; --b) {
+    ws_put(px, Xf);
+    ws_put(pp, Pf);
     const bool last = b == nb - 1;
-    // W's block for the trace, loaded before the products so that its latency
-    // overlaps them
-    double wv[kSlotIters];
-    if (A.Wm) read_block(A.Wm, A.Wmd, p, b, wv);
+    double wv[kSlotIters];   // W's block for the trace
+#pragma unroll
+    for (int it = 0; it < kSlotIters; ++it) wv[it] = pw[it];
+    if (b - 1 >= ch.b0) fetch(b - 1);
     if (!last)   // E = Sigma_{b+1,b} = -W P
       gemm64<false, false>(Wf, Pf, -1.f, [&](int i, int j, float v) { Ef[i][j] = v; });
     // Sigma_bb = X^T X - P^T E
@@ -610,12 +744,12 @@ __global__ void __launch_bounds__(NT) k_wf2_rep(const Args A) {
       }
       red4[q][i] = s;
     }
-    __syncthreads();
+    lds_barrier();
     if (threadIdx.x < NB) {
       const int i = threadIdx.x;
       sdg[i] = (red4[0][i] + red4[1][i]) + (red4[2][i] + red4[3][i]);
     }
-    __syncthreads();
+    lds_barrier();
     store_blocks(A.Sig, A.Sigd, p, b, [&](int cc) { return sdg[cc]; },
                  [&](int i, int cc) { return (double)Tf[i][cc]; },
                  [&](int rr, int cc) { return last ? 0.0 : (double)Ef[rr][cc]; });
@@ -626,13 +760,13 @@ __global__ void __launch_bounds__(NT) k_wf2_rep(const Args A) {
         tr += (d == 0 ? 1.0 : 2.0) * wv[it] * sv;
       });
     }
-    __syncthreads();
+    lds_barrier();
     // carry Sigma_bb (full, symmetric) to the block above
     for (int e = threadIdx.x; e < NB * NB; e += NT) {
       const int i = e / NB, j = e % NB;
       Wf[i][j] = i == j ? (float)sdg[i] : (i > j ? Tf[i][j] : Tf[j][i]);
     }
-    __syncthreads();
+    lds_barrier();
   }
   const double t = block_sum(tr, red);
   if (threadIdx.x == 0) A.cpart[3 * (int64_t)c + 2] = t;
@@ -658,31 +792,49 @@ __global__ void k_wfin2(const Args A, int32_t nprob) {
 // Lbar (diagonal-block lower triangle and coupling-block upper triangle).
 // Carried: the adjoint of Sigma_bb (only its symmetric part is used).
 __global__ void __launch_bounds__(NT) k_wb1_rep(const Args A) {
-  __shared__ MatF Xf, Pf, Wf, EMf, Sf, Cf, A1, A2;
+  __shared__ MatF Xf, Pf, Wf, EMf, Sf, Cf, A1, A2, Mc;
   const int32_t c = blockIdx.x;
   const Chunk ch = A.chunks[c];
   const Prob p = A.probs[ch.prob];
   if (A.info[ch.prob] != 0) return;
   const int64_t nb = nblocks(p.n);
   ws_load(cw(A, c, CW_SB1), Cf);
-  for (int64_t b = ch.b0; b < ch.b1; ++b) {
+  // The next block's X, P, W, Sigma_{b+2,b+2} and L coupling block are
+  // loaded behind this block's products (every wait for them comes at the
+  // top of the next iteration).
+  WsReg px, pp;
+  float pw[kSlotIters], ps[kSlotIters], pl[kSlotIters];
+  auto fetch = [&](int64_t b) __attribute__((always_inline)) {
     const float *wsb = A.ws + (p.wsoff + b) * kBlockWs;
-    ws_load(wsb, Xf);
-    ws_load(wsb + NB * NB, Pf);
+    ws_read(wsb, px);
+    ws_read(wsb + NB * NB, pp);
+    read_block(A.Wm, A.Wmd, p, b, pw);
+    if (b != nb - 1) {
+      read_block(A.Sig, A.Sigd, p, b + 1, ps);
+      read_block(A.L, A.Ld, p, b, pl);
+    }
+  };
+  fetch(ch.b0);
+  for (int64_t b = ch.b0; b < ch.b1; ++b) {
+    ws_put(px, Xf);
+    ws_put(pp, Pf);
     const bool last = b == nb - 1;
     // Sbar = sym(user's adjoint of Sigma_bb) + sym(carry) = W_bb + sym(C);
     // Ebar = user's adjoint of Sigma_{b+1,b} = 2 W_{b+1,b} (upper triangle)
-    load_blocks(A.Wm, A.Wmd, p, b, Sf, &EMf);
+    put_blocks(pw, p, b, Sf, &EMf);
+    if (!last) {
+      put_blocks(ps, p, b + 1, Wf, nullptr);   // W = Sigma_{b+1,b+1}
+      put_coupling(pl, p, b, Mc);              // M_b from L's coupling slots
+    }
+    if (b + 1 < ch.b1) fetch(b + 1);
     for (int e = threadIdx.x; e < NB * NB; e += NT) {
       const int i = e / NB, j = e % NB;
       const bool pad = NB * b + i >= p.n || NB * b + j >= p.n;
       Sf[i][j] = pad ? 0.f : Sf[i][j] + 0.5f * (Cf[i][j] + Cf[j][i]);
       EMf[i][j] *= 2.f;
     }
-    __syncthreads();
+    lds_barrier();
     if (!last) {
-      // W = Sigma_{b+1,b+1} from the Sigma band
-      load_blocks(A.Sig, A.Sigd, p, b + 1, Wf, nullptr);
       // Pbar = 2 W P Sbar - W Ebar   (A2)
       gemm64<false, false>(Wf, Pf, 1.f, [&](int i, int j, float v) { A1[i][j] = v; });
       gemm64<false, false>(A1, Sf, 2.f, [&](int i, int j, float v) { A2[i][j] = v; });
@@ -693,11 +845,9 @@ __global__ void __launch_bounds__(NT) k_wb1_rep(const Args A) {
       gemm64<false, true>(EMf, Pf, -1.f, [&](int i, int j, float v) { Cf[i][j] += v; });
       // Mbar = Pbar X^T: Lbar's coupling block (upper triangle kept), in A1
       gemm64<false, true>(A2, Xf, 1.f, [&](int i, int j, float v) { A1[i][j] = v; });
-      // M_b from L's coupling slots (into EMf, free now)
-      load_coupling(A.L, A.Ld, p, b, EMf);
       // Xbar = 2 X Sbar + M^T Pbar   (Wf)
       gemm64<false, false>(Xf, Sf, 2.f, [&](int i, int j, float v) { Wf[i][j] = v; });
-      gemm64<true, false>(EMf, A2, 1.f, [&](int i, int j, float v) { Wf[i][j] += v; });
+      gemm64<true, false>(Mc, A2, 1.f, [&](int i, int j, float v) { Wf[i][j] += v; });
     } else {
       gemm64<false, false>(Xf, Sf, 2.f, [&](int i, int j, float v) { Wf[i][j] = v; });
     }
@@ -707,7 +857,7 @@ __global__ void __launch_bounds__(NT) k_wb1_rep(const Args A) {
     store_blocks(A.Lb, A.Lbd, p, b, [&](int cc) { return (double)A2[cc][cc]; },
                  [&](int i, int cc) { return (double)A2[i][cc]; },
                  [&](int rr, int cc) { return last ? 0.0 : (double)A1[rr][cc]; });
-    __syncthreads();
+    lds_barrier();
   }
 }
 
@@ -728,33 +878,47 @@ template <bool REPLAY> __global__ void __launch_bounds__(NT) k_wb2(const Args A,
   const int64_t nb = nblocks(p.n);
   if (REPLAY) ws_load(cw(A, c, CW_SB2), Sc);
   else set_zero(Sc);
-  __syncthreads();
+  lds_barrier();
+  // the next block's X, L and Lbar (and the pivots and Lbar's diagonal) are
+  // loaded behind this block's products
+  WsReg px;
+  float pl[kSlotIters], plb[kSlotIters];
+  double pdg = 1.0, plbd = 0.0;
+  auto fetch = [&](int64_t b) __attribute__((always_inline)) {
+    ws_read(A.ws + (p.wsoff + b) * kBlockWs, px);
+    read_block(A.L, A.Ld, p, b, pl);
+    read_block(A.Lb, A.Lbd, p, b, plb);
+    if (threadIdx.x < NB) {
+      const int64_t j = NB * b + threadIdx.x;
+      pdg = j < p.n ? A.Ld[p.voff + j] : 1.0;
+      plbd = j < p.n ? A.Lbd[p.voff + j] : 0.0;
+    }
+  };
+  fetch(ch.b1 - 1);
   for (int64_t b = ch.b1 - 1; b >= ch.b0; --b) {
     const bool last = b == nb - 1;
-    ws_load(A.ws + (p.wsoff + b) * kBlockWs, Xf);
+    ws_put(px, Xf);
     // L_bb (lower) and M_b (upper) from L, the FP64 pivots from Ld
-    load_blocks(A.L, A.Ld, p, b, Lf, &Mf);
+    put_blocks(pl, p, b, Lf, &Mf);
     for (int e = threadIdx.x; e < NB * NB; e += NT) {
       const int i = e / NB, j = e % NB;
       if (i < j) Lf[i][j] = 0.f;
     }
     if (threadIdx.x < NB) {
       const int64_t j = NB * b + threadIdx.x;
-      dg[threadIdx.x] = j < p.n ? A.Ld[p.voff + j] : 1.0;
+      dg[threadIdx.x] = pdg;
+      // Lbar_bb's diagonal with the log-determinant term
+      lbd[threadIdx.x] = j < p.n ? plbd + 2.0 * gl / pdg : 0.0;
     }
-    __syncthreads();
-    // Lbar_bb (lower, with the log-determinant term) and Mbar_b (upper)
-    if (threadIdx.x < NB) {
-      const int64_t j = NB * b + threadIdx.x;
-      lbd[threadIdx.x] = j < p.n ? A.Lbd[p.voff + j] + 2.0 * gl / dg[threadIdx.x] : 0.0;
-    }
-    load_blocks(A.Lb, A.Lbd, p, b, LBf, &MBf);
+    // Lbar_bb (lower) and Mbar_b (upper)
+    put_blocks(plb, p, b, LBf, &MBf);
+    if (b - 1 >= ch.b0) fetch(b - 1);
     for (int e = threadIdx.x; e < NB * NB; e += NT) {
       const int i = e / NB, j = e % NB;
       const bool pad = NB * b + i >= p.n;
       LBf[i][j] = i == j ? (float)lbd[i] : (i > j && !pad ? LBf[i][j] : 0.f);
     }
-    __syncthreads();
+    lds_barrier();
     if (!last) {
       // Mbar -= 2 Sc M   (Sc: adjoint of S_{b+1}, symmetric)
       gemm64<false, false>(Sc, Mf, -2.f, [&](int i, int j, float v) { MBf[i][j] += v; });
@@ -783,7 +947,7 @@ template <bool REPLAY> __global__ void __launch_bounds__(NT) k_wb2(const Args A,
       store_blocks(A.Qb, A.Qbd, p, b, [&](int cc) { return (double)Sc[cc][cc]; },
                    [&](int i, int cc) { return (double)(Sc[i][cc] + Sc[cc][i]); },
                    [&](int rr, int cc) { return last ? 0.0 : (double)A2[rr][cc]; });
-    __syncthreads();
+    lds_barrier();
   }
   if (!REPLAY) ws_store(cw(A, c, CW_MB2), Sc);
 }
