@@ -140,56 +140,67 @@ template <class F> __device__ __forceinline__ void for_block_slots(int64_t b, in
   }
 }
 
-// Every slot of block b of band Bp/Bd into registers (all loads issued before
-// any is used); slots past the matrix end read 1 on the diagonal, else 0.
-// R = float keeps a block that only goes into FP32 tiles in half the
-// registers (the FP64 diagonal rounded).
-template <typename R>
+// The raw slots of one block in registers: the FP32 record values and the
+// thread's one FP64 diagonal value (a thread's slots idx = tid + 256 it hold
+// the diagonal, idx = 0 mod 65, for at most one it).  read_block issues every
+// load from an in-bounds address (a slot past the matrix end reads the
+// problem's first record) and converts nothing, so that no wait for the loads
+// comes before the values are put into LDS; put_blocks then applies the
+// identity past the matrix end (1 on the diagonal, else 0).
+struct BlockRegs {
+  float v[kSlotIters];
+  double dv;
+};
 __device__ __forceinline__ void read_block(const float *Bp, const double *Bd, const Prob &p, int64_t b,
-                                           R (&v)[kSlotIters]) {
-#pragma unroll
-  for (int it = 0; it < kSlotIters; ++it) v[it] = 0;
+                                           BlockRegs &r) {
+  int64_t dj = 0;   // the diagonal slot's row: one load after the loop, not one per slot
   for_block_slots(b, p.n, [&](int it, int c, int d, int64_t j, bool valid) {
-    if (valid) v[it] = d == 0 ? (R)Bd[p.voff + j] : (R)Bp[(p.boff + j * W) + d];
-    else if (d == 0) v[it] = 1;   // identity past the matrix end
+    const int64_t jj = valid ? j : 0;
+    if (d == 0) dj = jj;
+    r.v[it] = Bp[(p.boff + jj * W) + (valid ? d : 0)];
   });
+  r.dv = Bd[p.voff + dj];
+}
+__device__ __forceinline__ double slot_value(const BlockRegs &r, int it, int d, bool valid) {
+  return valid ? (d == 0 ? r.dv : (double)r.v[it]) : (d == 0 ? 1.0 : 0.0);
 }
 
 // Diagonal block (symmetric, full; E = double or float) and coupling block
-// (upper triangular, FP32) of band Bp/Bd at block b; rows past n read as the
-// identity on the diagonal and zero elsewhere.
-// (put_blocks: from the registers read_block filled, so that the loads of
-// the next block can be issued while the current one is worked on.)
-template <typename R, typename E>
-__device__ __forceinline__ void put_blocks(const R (&v)[kSlotIters], const Prob &p, int64_t b, E (&S)[NB][LDF], MatF *Cf) {
+// (upper triangular, FP32) of band Bp/Bd at block b, from the registers
+// read_block filled (so that the loads of the next block can be issued while
+// the current one is worked on); rows past n read as the identity on the
+// diagonal and zero elsewhere.
+template <typename E>
+__device__ __forceinline__ void put_blocks(const BlockRegs &r, const Prob &p, int64_t b, E (&S)[NB][LDF],
+                                           MatF *Cf) {
   if (Cf)
     for (int e = threadIdx.x; e < NB * NB; e += NT) (*Cf)[e / NB][e % NB] = 0.f;
   lds_barrier();
-  for_block_slots(b, p.n, [&](int it, int c, int d, int64_t, bool) {
+  for_block_slots(b, p.n, [&](int it, int c, int d, int64_t, bool valid) {
+    const double x = slot_value(r, it, d, valid);
     if (d <= NB - 1 - c) {
-      S[c + d][c] = (E)v[it];
-      S[c][c + d] = (E)v[it];
+      S[c + d][c] = (E)x;
+      S[c][c + d] = (E)x;
     } else if (Cf) {
-      (*Cf)[d - NB + c][c] = (float)v[it];
+      (*Cf)[d - NB + c][c] = (float)x;
     }
   });
   lds_barrier();
 }
 template <typename E>
-__device__ __forceinline__ void load_blocks(const float *Bp, const double *Bd, const Prob &p, int64_t b, E (&S)[NB][LDF],
-                            MatF *Cf) {
-  double v[kSlotIters];
-  read_block(Bp, Bd, p, b, v);
-  put_blocks(v, p, b, S, Cf);
+__device__ __forceinline__ void load_blocks(const float *Bp, const double *Bd, const Prob &p, int64_t b,
+                                            E (&S)[NB][LDF], MatF *Cf) {
+  BlockRegs r;
+  read_block(Bp, Bd, p, b, r);
+  put_blocks(r, p, b, S, Cf);
 }
 
 // The coupling block alone (upper triangular, zero below), from registers.
-template <typename R>
-__device__ __forceinline__ void put_coupling(const R (&v)[kSlotIters], const Prob &p, int64_t b, MatF &Cf) {
+__device__ __forceinline__ void put_coupling(const BlockRegs &r, const Prob &p, int64_t b, MatF &Cf) {
   for (int e = threadIdx.x; e < NB * NB; e += NT) Cf[e / NB][e % NB] = 0.f;
   lds_barrier();
-  for_block_slots(b, p.n, [&](int it, int c, int d, int64_t, bool) {
-    if (d > NB - 1 - c) Cf[d - NB + c][c] = (float)v[it];
+  for_block_slots(b, p.n, [&](int it, int c, int d, int64_t, bool valid) {
+    if (d > NB - 1 - c) Cf[d - NB + c][c] = (float)slot_value(r, it, d, valid);
   });
   lds_barrier();
 }
@@ -483,7 +494,7 @@ __global__ void __launch_bounds__(NT) k_wf1_sum(const Args A) {
   double unused = 0.0;
   bool bad = false;
   // each block's loads are issued while the block before it is worked on
-  double q[kSlotIters];
+  BlockRegs q;
   if (ch.b0 + 1 < ch.b1) read_block(A.Q, A.Qd, p, ch.b0 + 1, q);
   for (int64_t i = ch.b0 + 1; i < ch.b1; ++i) {
     put_blocks(q, p, i, S, &Cf);
@@ -551,7 +562,7 @@ __global__ void __launch_bounds__(NT) k_wf1_rep(const Args A) {
   const Prob p = A.probs[ch.prob];
   double lsum = 0.0;
   int64_t fail = 0;
-  double q[kSlotIters];   // the next block's records, loaded behind this block's work
+  BlockRegs q;   // the next block's records, loaded behind this block's work
   read_block(A.Q, A.Qd, p, ch.b0, q);
   for (int64_t b = ch.b0; b < ch.b1; ++b) {
     put_blocks(q, p, b, S, &Cf);
@@ -625,7 +636,7 @@ __global__ void __launch_bounds__(NT) k_wlin_sum(const Args A, int32_t want_b1) 
   set_zero(Mf2);
   set_zero(Cb);
   WsReg px, pp;   // the next block's X, P and W, loaded behind this block's work
-  float pw[kSlotIters];
+  BlockRegs pw;
   auto fetch = [&](int64_t b) __attribute__((always_inline)) {
     const float *wsb = A.ws + (p.wsoff + b) * kBlockWs;
     ws_read(wsb, px);
@@ -712,7 +723,7 @@ __global__ void __launch_bounds__(NT) k_wf2_rep(const Args A) {
   ws_load(cw(A, c, CW_SF2), Wf);
   double tr = 0.0;
   WsReg px, pp;   // the next block's X, P and W, loaded behind this block's work
-  double pw[kSlotIters];
+  BlockRegs pw;
   auto fetch = [&](int64_t b) __attribute__((always_inline)) {
     const float *wsb = A.ws + (p.wsoff + b) * kBlockWs;
     ws_read(wsb, px);
@@ -724,9 +735,7 @@ __global__ void __launch_bounds__(NT) k_wf2_rep(const Args A) {
     ws_put(px, Xf);
     ws_put(pp, Pf);
     const bool last = b == nb - 1;
-    double wv[kSlotIters];   // W's block for the trace
-#pragma unroll
-    for (int it = 0; it < kSlotIters; ++it) wv[it] = pw[it];
+    const BlockRegs wv = pw;   // W's block for the trace
     if (b - 1 >= ch.b0) fetch(b - 1);
     if (!last)   // E = Sigma_{b+1,b} = -W P
       gemm64<false, false>(Wf, Pf, -1.f, [&](int i, int j, float v) { Ef[i][j] = v; });
@@ -757,7 +766,7 @@ __global__ void __launch_bounds__(NT) k_wf2_rep(const Args A) {
       for_block_slots(b, p.n, [&](int it, int cc, int d, int64_t, bool valid) {
         if (!valid) return;
         const double sv = d == 0 ? sdg[cc] : (d <= NB - 1 - cc ? (double)Tf[cc + d][cc] : (double)Ef[d - NB + cc][cc]);
-        tr += (d == 0 ? 1.0 : 2.0) * wv[it] * sv;
+        tr += (d == 0 ? 1.0 : 2.0) * slot_value(wv, it, d, true) * sv;
       });
     }
     lds_barrier();
@@ -803,7 +812,7 @@ __global__ void __launch_bounds__(NT) k_wb1_rep(const Args A) {
   // loaded behind this block's products (every wait for them comes at the
   // top of the next iteration).
   WsReg px, pp;
-  float pw[kSlotIters], ps[kSlotIters], pl[kSlotIters];
+  BlockRegs pw, ps, pl;
   auto fetch = [&](int64_t b) __attribute__((always_inline)) {
     const float *wsb = A.ws + (p.wsoff + b) * kBlockWs;
     ws_read(wsb, px);
@@ -882,16 +891,16 @@ template <bool REPLAY> __global__ void __launch_bounds__(NT) k_wb2(const Args A,
   // the next block's X, L and Lbar (and the pivots and Lbar's diagonal) are
   // loaded behind this block's products
   WsReg px;
-  float pl[kSlotIters], plb[kSlotIters];
-  double pdg = 1.0, plbd = 0.0;
+  BlockRegs pl, plb;
+  double pdg = 1.0, plbd = 0.0;   // (read in bounds; rows past n are masked where used)
   auto fetch = [&](int64_t b) __attribute__((always_inline)) {
     ws_read(A.ws + (p.wsoff + b) * kBlockWs, px);
     read_block(A.L, A.Ld, p, b, pl);
     read_block(A.Lb, A.Lbd, p, b, plb);
     if (threadIdx.x < NB) {
       const int64_t j = NB * b + threadIdx.x;
-      pdg = j < p.n ? A.Ld[p.voff + j] : 1.0;
-      plbd = j < p.n ? A.Lbd[p.voff + j] : 0.0;
+      pdg = A.Ld[p.voff + (j < p.n ? j : 0)];
+      plbd = A.Lbd[p.voff + (j < p.n ? j : 0)];
     }
   };
   fetch(ch.b1 - 1);
@@ -906,9 +915,10 @@ template <bool REPLAY> __global__ void __launch_bounds__(NT) k_wb2(const Args A,
     }
     if (threadIdx.x < NB) {
       const int64_t j = NB * b + threadIdx.x;
-      dg[threadIdx.x] = pdg;
+      const double d = j < p.n ? pdg : 1.0;
+      dg[threadIdx.x] = d;
       // Lbar_bb's diagonal with the log-determinant term
-      lbd[threadIdx.x] = j < p.n ? plbd + 2.0 * gl / pdg : 0.0;
+      lbd[threadIdx.x] = j < p.n ? plbd + 2.0 * gl / d : 0.0;
     }
     // Lbar_bb (lower) and Mbar_b (upper)
     put_blocks(plb, p, b, LBf, &MBf);
