@@ -283,7 +283,9 @@ def copy_probe(torch, mib: int):
 class Workload:
     """Inputs resident on the device, a plan over the batch, and the step."""
 
-    def __init__(self, bo, torch, dev, ns, ks, prec, host_inputs, forward_only, target_chunks=0):
+    def __init__(self, bo, torch, dev, ns, ks, prec, host_inputs, forward_only, target_chunks=0, keep=False):
+        """keep: the loss unit keeps L, Sigma and Lbar in the plan's workspace
+        (interleaved by chunk) instead of writing them to caller arrays."""
         self.bo, self.torch, self.dev = bo, torch, dev
         self.ns, self.ks, self.prec = ns, ks, prec
         self.forward_only = forward_only
@@ -301,7 +303,7 @@ class Workload:
         nprob = len(ns)
         kw = dict(Q=Qt, y=yt, z=torch.zeros(N, dtype=vdt, device=dev), x=torch.zeros(N, dtype=vdt, device=dev),
                   info=torch.zeros(nprob, dtype=torch.int32, device=dev))
-        names = ("L", "Sig") if forward_only else ("L", "Sig", "Lbar", "Qbar")
+        names = ("L", "Sig") if forward_only else (("Qbar",) if keep else ("L", "Sig", "Lbar", "Qbar"))
         for nm in names:
             kw[nm] = torch.zeros(E, dtype=vdt, device=dev)
         if forward_only:
@@ -978,6 +980,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--caller-arrays", action="store_true",
+                    help="loss unit: write L, Sigma and Lbar to caller arrays (default: keep them in the workspace)")
     ap.add_argument("--kernels-json", default="")
     ap.add_argument("--target-chunks", type=int, default=0, help="plan chunk target (0: library default)")
     ap.add_argument("--autotune", action="store_true",
@@ -1094,7 +1098,10 @@ def main():
         elif wh:
             W = WHWorkload(bo, torch, dev, ns, ks, prec, host_inputs, args.target_chunks)
         else:
-            W = Workload(bo, torch, dev, ns, ks, prec, host_inputs, forward_only, args.target_chunks)
+            keep = not forward_only and prec == bo.F64 and not args.caller_arrays
+            W = Workload(bo, torch, dev, ns, ks, prec, host_inputs, forward_only, args.target_chunks, keep=keep)
+            if not forward_only:
+                cfg.update(intermediates="workspace, interleaved by chunk" if keep else "caller arrays")
         if args.autotune:
             from paper_1902_10078_amd import autotune
 
@@ -1237,7 +1244,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if wide else "f64",
+        "dtype": "f32+f64" if (wide or prec != bo.F64) else "f64",
         "data": "synthetic",
         "config": cfg,
         "roofline": roof,

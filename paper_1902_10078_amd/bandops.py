@@ -100,6 +100,7 @@ def lib():
         "bo_logdet_bwd": (_I32, [_I32, bp, _P, bp, _I32, _P]),
         "bo_plan_create": (_I32, [ctypes.POINTER(_Problem), _I32, _I64, ctypes.POINTER(_P)]),
         "bo_plan_workspace_size": (_I32, [_P, ctypes.POINTER(ctypes.c_size_t)]),
+        "bo_plan_loss_workspace_size": (_I32, [_P, ctypes.POINTER(ctypes.c_size_t)]),
         "bo_plan_upload": (_I32, [_P, _P, _P]),
         "bo_plan_forward": (_I32, [_P, _I32, ctypes.POINTER(_BatchIO), _P, _P]),
         "bo_plan_gauss_loss": (_I32, [_P, _I32, ctypes.POINTER(_BatchIO), _P, _P]),
@@ -139,7 +140,7 @@ def lib():
 EXPORTED = ("bo_workspace_size", "bo_chol", "bo_chol_noalloc_scratch_bytes", "bo_chol_noalloc", "bo_trsv", "bo_subset_inv_workspace_size", "bo_subset_inv", "bo_gbmm", "bo_gbmv",
             "bo_outer_band", "bo_solve_band_mat", "bo_solve_band_mat_workspace",
             "bo_solve_band_mat_bwd", "bo_chol_bwd", "bo_subset_inv_bwd", "bo_trsv_bwd", "bo_logdet_bwd",
-            "bo_plan_create", "bo_plan_workspace_size", "bo_plan_upload", "bo_plan_forward",
+            "bo_plan_create", "bo_plan_workspace_size", "bo_plan_loss_workspace_size", "bo_plan_upload", "bo_plan_forward",
             "bo_plan_gauss_loss", "bo_plan_vi_kl", "bo_plan_marglik", "bo_plan_natgp", "bo_plan_whiten", "bo_plan_whiten_bwd", "bo_rcm", "bo_csr_permute", "bo_csr_to_band", "bo_band_to_csr_grad", "bo_plan_scale", "bo_plan_stats", "bo_plan_destroy", "bo_wide_workspace_size",
             "bo_wide_upload", "bo_wide_forward", "bo_wide_gauss_loss", "bo_profile_enable",
             "bo_profile_read", "bo_profile_slots", "bo_profile_slot_name", "bo_status_string",
@@ -456,7 +457,21 @@ class Plan:
         _check(lib().bo_plan_forward(self.h, prec, ctypes.byref(io), _ptr(self.ws), _stream()),
                "bo_plan_forward")
 
+    def ensure_loss_workspace(self):
+        """Grow the workspace to what bo_plan_gauss_loss needs when it keeps L,
+        Sig and Lbar in it (io without L, Sig and Lbar); call before graph
+        capture."""
+        sz = ctypes.c_size_t()
+        _check(lib().bo_plan_loss_workspace_size(self.h, ctypes.byref(sz)), "bo_plan_loss_workspace_size")
+        if self.ws.numel() < sz.value:
+            self.ws = torch.empty(sz.value, dtype=torch.uint8, device=self.ws.device)
+            _check(lib().bo_plan_upload(self.h, _ptr(self.ws), _stream()), "bo_plan_upload")
+
     def gauss_loss(self, prec: int, io: _BatchIO):
+        """The loss unit over the batch (bo_plan_gauss_loss).  An io without L,
+        Sig and Lbar keeps them in the workspace (grown on first use)."""
+        if not io.L and not io.Sig and not io.Lbar:
+            self.ensure_loss_workspace()
         _check(lib().bo_plan_gauss_loss(self.h, prec, ctypes.byref(io), _ptr(self.ws), _stream()),
                "bo_plan_gauss_loss")
 

@@ -31,6 +31,8 @@ struct KRange {
   int K;
   int32_t c_beg, c_cnt, g_beg, g_cnt, p_beg, p_cnt;
   int32_t max_nchunk;   // largest chunk count of a problem in the range
+  int32_t il_rows;      // interleaved slot rows per lane: longest chunk + K + 1
+  int64_t il_off;       // element offset of the range in each interleaved array
 };
 
 struct Sched {
@@ -40,10 +42,13 @@ struct Sched {
   std::vector<KRange> ranges;
   int32_t nchunk = 0, ngroup = 0, nprob = 0, G = 64, Kmax = 0;
   int64_t rows = 0;
+  // interleaved intermediates (FP64 elements per array; the arrays follow
+  // the workspace proper when a call keeps L, Sigma and Lbar there)
+  int64_t il_elems = 0;
   // workspace layout (bytes offsets from the workspace base)
   size_t off_tables = 0, off_f1map = 0, off_f1st = 0, off_f1gmap = 0, off_f1gst = 0, off_Pc = 0,
          off_Pg = 0, off_Pex = 0, off_lmap = 0, off_lmap2 = 0, off_lst = 0, off_lgmap = 0, off_lgst = 0, off_part = 0,
-         off_out = 0, bytes = 0;
+         off_out = 0, bytes = 0, off_il = 0, bytes_il = 0;
   int32_t sw_f1map = 1, sw_f1st = 1, sw_mat = 1, sw_lin = 1;
   std::vector<unsigned char> table_blob;   // probs | chunk_prob | group_prob (device image)
 };
@@ -127,14 +132,19 @@ inline bool build_sched(const ProbIn *in, int nprob, int64_t target_chunks, int6
     r.c_beg = s.probs[ii].chunk0;
     r.g_beg = s.probs[ii].group0;
     r.max_nchunk = 0;
+    int64_t maxclen = 0;
     while (jj < nprob && s.probs[jj].k == K) {
       r.max_nchunk = std::max(r.max_nchunk, s.probs[jj].nchunk);
+      if (s.probs[jj].n > 0) maxclen = std::max<int64_t>(maxclen, std::min<int64_t>(s.probs[jj].clen, s.probs[jj].n));
       ++jj;
     }
     r.p_cnt = jj - ii;
     const ProbDesc &last = s.probs[jj - 1];
     r.c_cnt = last.chunk0 + last.nchunk - r.c_beg;
     r.g_cnt = last.group0 + last.ngroup - r.g_beg;
+    r.il_rows = (int32_t)(maxclen + K + 1);
+    r.il_off = s.il_elems;
+    s.il_elems += (int64_t)((r.c_cnt + 63) / 64) * r.il_rows * 64 * (K + 1);
     s.ranges.push_back(r);
     ii = jj;
   }
@@ -175,6 +185,8 @@ inline bool build_sched(const ProbIn *in, int nprob, int64_t target_chunks, int6
   // scratch per-problem results of a composite call (8 words per problem)
   s.off_out = take((size_t)nprob * 8);
   s.bytes = o;
+  s.off_il = o;
+  s.bytes_il = o + 3 * align_up((size_t)s.il_elems * sizeof(double));
   return true;
 }
 
@@ -218,6 +230,22 @@ inline void set_range(Args &A, const KRange &r) {
   A.c_beg = r.c_beg;
   A.g_beg = r.g_beg;
   A.p_beg = r.p_beg;
+  A.il_rows = r.il_rows;
+  A.il_off = r.il_off;
+}
+
+// Point L, S and Lb at the interleaved arrays that follow the workspace
+// proper (a workspace of s.bytes_il bytes).
+inline void bind_il(const Sched &s, void *ws, Args &A) {
+  unsigned char *w = (unsigned char *)ws + s.off_il;
+  const size_t one = align_up((size_t)s.il_elems * sizeof(double));
+  A.il = 1;
+  A.L = w;
+  A.Ld = nullptr;
+  A.S = w + one;
+  A.Sd = nullptr;
+  A.Lb = w + 2 * one;
+  A.Lbd = nullptr;
 }
 
 // ---------------------------------------------------------------- sequences

@@ -67,6 +67,16 @@ struct Args {
   double *parts;    // 3 per problem: logdet, y^T Q^{-1} y, tr(Q^{-1} S)
   int32_t *info;    // per problem
   double *loss;     // per problem: logdet - y^T Q^{-1} y + tr(Q^{-1} S) (or null)
+  // ---- interleaved intermediates (FP64 tiled kernels only): L, S and Lb
+  // point at workspace arrays in which row r of the chunk of lane l of
+  // wavefront w of a launch is the record at element
+  // il_off + ((w * il_rows + r) * 64 + l) * (K + 1); il_rows is the range's
+  // longest chunk + K + 1, the extra rows a halo that holds the next chunk's
+  // first K + 1 records of S.
+  int32_t il;
+  int32_t il_rows;
+  void *sbar_out;   // F2 replay with il: also writes (Sigma_jj, 2 Sigma_ij) here (or null)
+  int64_t il_off;   // element offset of the launch's bandwidth range
 };
 
 BO_HD const ProbDesc &prob_at(const Args &a, int32_t p) { return a.probs ? a.probs[p] : a.one; }

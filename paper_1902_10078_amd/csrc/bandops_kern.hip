@@ -48,6 +48,33 @@ __device__ __forceinline__ LaneChunk lane_chunk(const Args &A, int64_t count) {
   return L;
 }
 
+// Interleaved intermediates (Args::il, FP64): the block of wavefront w of an
+// array, and a lane's view of its chunk as a band of stride 64 (K + 1) whose
+// record j is row j - a of the lane's slot (only records of the chunk and its
+// halo are ever addressed through it; the base is formed in unsigned
+// arithmetic and may lie before the array).
+template <int K, typename T> __device__ __forceinline__ T *il_wave(void *base, const Args &A, int64_t w) {
+  return (T *)base + A.il_off + w * (int64_t)A.il_rows * kBlock * (K + 1);
+}
+template <int K, typename T>
+__device__ __forceinline__ BandP<T> il_view(void *base, const Args &A, int64_t w, int l, int64_t a) {
+  constexpr int64_t W = K + 1;
+  const uint64_t p = (uint64_t)(il_wave<K, T>(base, A, w) + l * W) - (uint64_t)(a * kBlock * W * (int64_t)sizeof(T));
+  return BandP<T>{(T *)p, nullptr, kBlock * W};
+}
+template <int K, typename T> __device__ __forceinline__ BandP<T> lane_view(void *base, const Args &A, const LaneChunk &C) {
+  return il_view<K, T>(base, A, blockIdx.x, threadIdx.x, C.a);
+}
+template <typename T> __device__ __forceinline__ BandP<const T> const_view(BandP<T> b) {
+  return BandP<const T>{b.p, b.diag, b.ld};
+}
+// A staged band input: the wave's interleaved block, or the lane's records.
+template <int K, typename T>
+__device__ __forceinline__ BandIn<T> staged(bool il, void *base, const Args &A, BandP<const T> b, bool on, int shift = 0) {
+  if (il) return BandIn<T>{il_wave<K, T>(base, A, blockIdx.x), nullptr, shift, true};
+  return BandIn<T>{on ? b.p : nullptr, on ? b.diag : nullptr, shift, false};
+}
+
 // ------------------------------------------------------------------- F1
 // DIAG: the factored matrix is Q + diag(qdn / qdd[problem]); the addend is
 // staged as a second vector (val[1]) and added to each diagonal entry as it is
@@ -110,7 +137,9 @@ __global__ void __launch_bounds__(kBlock) k_f1_rep(const Args A, int64_t count) 
     f1_zero_state<K>(s0);
   F1RepStep<K, T> st;
   const bool fuse = K <= KMAX_FUSED && A.lmap_out && A.Pc;
-  st.begin(s0, band<T>(A.L, A.Ld, pd), y ? vec<T>(A.z, pd) : nullptr, A.Pc != nullptr, fuse);
+  const bool il = sizeof(T) == 8 && A.il != 0;
+  st.begin(s0, il ? lane_view<K, T>(A.L, A, C) : band<T>(A.L, A.Ld, pd), y ? vec<T>(A.z, pd) : nullptr,
+           A.Pc != nullptr, fuse);
   BandIn<T> bands[1] = {{on ? Q.p : nullptr, on ? Q.diag : nullptr, 0}};
   VecIn<T> vecs[NV];
   vecs[0] = {on ? y : nullptr, 0};
@@ -220,12 +249,21 @@ __global__ void __launch_bounds__(kBlock) k_f2(const Args A, int64_t count) {
   LinMap<K> st;
   lin_in<K>(A, C, REPLAY, st);
   F2Step<K, T, REPLAY> s;
-  s.begin(st, band<T>(A.S, A.Sd, pd), vec<T>(A.x, pd), A.xscale, A.S != nullptr, bx != nullptr, FUSE,
-          A.sb_is_S != 0);
+  const bool il = sizeof(T) == 8 && A.il != 0;
+  s.begin(st, il ? lane_view<K, T>(A.S, A, C) : band<T>(A.S, A.Sd, pd), vec<T>(A.x, pd), A.xscale,
+          A.S != nullptr, bx != nullptr, FUSE, A.sb_is_S != 0);
+  if (REPLAY && il && on && C.c > pd.chunk0) {
+    // rows a .. a+K are also the halo of the previous chunk of the problem
+    const int l = threadIdx.x;
+    s.set_halo(il_view<K, T>(A.S, A, l > 0 ? (int64_t)blockIdx.x : (int64_t)blockIdx.x - 1, l > 0 ? l - 1 : kBlock - 1,
+                             C.a - pd.clen),
+               C.a + K + 1);
+  }
+  if (REPLAY && il && A.sbar_out) s.set_sym_out(band<T>(A.sbar_out, nullptr, pd));
   VecIn<T> vecs[1] = {{on ? bx : nullptr, 0}};
   if constexpr (FUSE) {
     BandP<const T> Sb = cband<T>(A.Sb, A.Sbd, pd);
-    BandIn<T> bands[2] = {{on ? L.p : nullptr, on ? L.diag : nullptr, 0},
+    BandIn<T> bands[2] = {staged<K, T>(il, A.L, A, L, on),
                           {on ? Sb.p : nullptr, on ? Sb.diag : nullptr, 0}};
     stream_rows<K, T, 2, 1, true>(bands, vecs, on ? C.a : 0, on ? C.b : 0, pd.n, pd.ld,
                                   [&](int64_t j, const double (&rec)[2][K + 1], const double (&val)[1]) {
@@ -238,7 +276,7 @@ __global__ void __launch_bounds__(kBlock) k_f2(const Args A, int64_t count) {
       lin_store<K>(A.lmap_out + (int64_t)C.c * A.sw_lin, m);
     }
   } else {
-    BandIn<T> bands[1] = {{on ? L.p : nullptr, on ? L.diag : nullptr, 0}};
+    BandIn<T> bands[1] = {staged<K, T>(il, A.L, A, L, on)};
     stream_rows<K, T, 1, 1, true>(bands, vecs, on ? C.a : 0, on ? C.b : 0, pd.n, pd.ld,
                                   [&](int64_t j, const double (&rec)[1][K + 1], const double (&val)[1]) {
                                     s.row(j, rec[0], val[0]);
@@ -263,11 +301,14 @@ __global__ void __launch_bounds__(kBlock) k_b1(const Args A, int64_t count) {
   LinMap<K> st;
   lin_in<K>(A, C, REPLAY, st);
   B1Step<K, T, REPLAY, FUSE> s;
-  if (on) s.begin(st, C.a, pd.n, Sig, A.sb_is_S != 0, band<T>(A.Lb, A.Lbd, pd), A.accumulate != 0, A.gl1);
+  const bool il = sizeof(T) == 8 && A.il != 0;
+  if (on)
+    s.begin(st, C.a, pd.n, il ? const_view(lane_view<K, T>(A.S, A, C)) : Sig, A.sb_is_S != 0,
+            il ? lane_view<K, T>(A.Lb, A, C) : band<T>(A.Lb, A.Lbd, pd), A.accumulate != 0, A.gl1);
   if constexpr (REPLAY) {
-    BandIn<T> bands[3] = {{on ? L.p : nullptr, on ? L.diag : nullptr, 0},
+    BandIn<T> bands[3] = {staged<K, T>(il, A.L, A, L, on),
                           {on ? Sb.p : nullptr, on ? Sb.diag : nullptr, 0},
-                          {on ? Sig.p : nullptr, on ? Sig.diag : nullptr, K + 1}};
+                          staged<K, T>(il, A.S, A, Sig, on, K + 1)};
     if constexpr (FUSE) {
       const T *yb = cvec<T>(A.yb, pd);
       if (on) s.begin_b2(C.a, pd.n, yb, A.gl);
@@ -290,7 +331,7 @@ __global__ void __launch_bounds__(kBlock) k_b1(const Args A, int64_t count) {
     }
     if (on) A.part[4 * (int64_t)C.c + 2] = s.tr;
   } else {
-    BandIn<T> bands[2] = {{on ? L.p : nullptr, on ? L.diag : nullptr, 0},
+    BandIn<T> bands[2] = {staged<K, T>(il, A.L, A, L, on),
                           {on ? Sb.p : nullptr, on ? Sb.diag : nullptr, 0}};
     VecIn<T> vecs[1] = {{nullptr, 0}};
     stream_rows<K, T, 2, 0, false>(bands, vecs, on ? C.a : 0, on ? C.b : 0, pd.n, pd.ld,
@@ -321,9 +362,10 @@ __global__ void __launch_bounds__(kBlock) k_b2(const Args A, int64_t count) {
   lin_in<K>(A, C, REPLAY, st);
   B2Step<K, T, REPLAY> s;
   s.begin(st, C.b, pd.n, on ? yb : nullptr, A.gl, band<T>(A.Qb, A.Qbd, pd));
+  const bool il = sizeof(T) == 8 && A.il != 0;
   BandIn<T> bands[NB];
-  bands[0] = {on ? L.p : nullptr, on ? L.diag : nullptr, 0};
-  if constexpr (WITH_LB) bands[NB - 1] = {on ? Lb.p : nullptr, on ? Lb.diag : nullptr, 0};
+  bands[0] = staged<K, T>(il, A.L, A, L, on);
+  if constexpr (WITH_LB) bands[NB - 1] = staged<K, T>(il, A.Lb, A, Lb, on);
   VecIn<T> vecs[2] = {{on ? yb : nullptr, 0}, {on ? zf : nullptr, 0}};
   stream_rows<K, T, NB, 2, true>(bands, vecs, on ? C.a : 0, on ? C.b : 0, pd.n, pd.ld,
                                  [&](int64_t j, const double (&rec)[NB][K + 1], const double (&val)[2]) {

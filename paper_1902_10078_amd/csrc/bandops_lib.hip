@@ -854,6 +854,12 @@ extern "C" bo_status bo_plan_workspace_size(const bo_plan *plan, size_t *bytes) 
   return BO_OK;
 }
 
+extern "C" bo_status bo_plan_loss_workspace_size(const bo_plan *plan, size_t *bytes) {
+  if (!plan || !bytes) return fail(BO_EINVAL, "bo_plan_loss_workspace_size: null argument");
+  *bytes = plan->s.bytes_il;
+  return BO_OK;
+}
+
 extern "C" bo_status bo_plan_upload(const bo_plan *plan, void *ws, hipStream_t stream) {
   if (!plan || !ws) return fail(BO_EINVAL, "bo_plan_upload: null argument");
   size_t tb = plan->s.table_blob.size();
@@ -865,10 +871,10 @@ extern "C" bo_status bo_plan_upload(const bo_plan *plan, void *ws, hipStream_t s
 }
 
 static bo_status plan_args(const bo_plan *plan, bo_prec prec, const bo_batch_io *io, void *ws,
-                           Args &A) {
+                           Args &A, bool need_L = true) {
   if (!plan || !io || !ws) return fail(BO_EINVAL, "plan call: null argument");
   if (prec != BO_F64 && prec != BO_MIXED) return fail(BO_EINVAL, "unknown precision");
-  if (!io->Q || !io->L) return fail(BO_EINVAL, "plan call: Q and L are required");
+  if (!io->Q || (need_L && !io->L)) return fail(BO_EINVAL, "plan call: Q and L are required");
   if (prec == BO_MIXED && (!io->Qd || !io->Ld))
     return fail(BO_EINVAL, "plan call: BO_MIXED needs FP64 diagonals of Q and L");
   A = Args{};
@@ -933,10 +939,19 @@ extern "C" bo_status bo_plan_forward(const bo_plan *plan, bo_prec prec, const bo
 extern "C" bo_status bo_plan_gauss_loss(const bo_plan *plan, bo_prec prec, const bo_batch_io *io,
                                         void *ws, hipStream_t stream) {
   Args A;
-  if (bo_status e = plan_args(plan, prec, io, ws, A)) return e;
-  if (!io->y || !io->S || !io->z || !io->x || !io->Sig || !io->Lbar || !io->Qbar || !io->parts ||
+  // L, Sig and Lbar all NULL: the intermediates stay in the workspace,
+  // interleaved by chunk (FP64; ws of bo_plan_loss_workspace_size bytes)
+  const bool keep = io && !io->L && !io->Sig && !io->Lbar;
+  if (bo_status e = plan_args(plan, prec, io, ws, A, !keep)) return e;
+  if (keep && prec != BO_F64)
+    return fail(BO_EINVAL, "bo_plan_gauss_loss: intermediates in the workspace need BO_F64");
+  if (!io->y || !io->S || !io->z || !io->x || (!keep && (!io->Sig || !io->Lbar)) || !io->Qbar || !io->parts ||
       !io->info)
     return fail(BO_EINVAL, "bo_plan_gauss_loss: y, S, z, x, Sig, Lbar, Qbar, parts, info required");
+  if (keep) {
+    bo::bind_il(plan->s, ws, A);
+    A.sbar_out = io->Sbar;
+  }
   if (prec == BO_MIXED && (!io->Sd || !io->Sigd || !io->Lbard || !io->Qbard))
     return fail(BO_EINVAL, "bo_plan_gauss_loss: BO_MIXED needs every FP64 diagonal");
   if (io->Sbar && prec == BO_MIXED && !io->Sbard)
@@ -947,7 +962,7 @@ extern "C" bo_status bo_plan_gauss_loss(const bo_plan *plan, bo_prec prec, const
                                           }),
                                "bo_plan_gauss_loss"))
     return e;
-  if (!io->Sbar) return BO_OK;
+  if (!io->Sbar || keep) return BO_OK;
   // d tr(Q^{-1} S) / dS on S's stored entries: Sigma_ii, 2 Sigma_ij
   return plan_scale_launch(plan, prec, BO_SCALE_BAND_SYM, nullptr, io->Sig, io->Sigd, io->Sbar, io->Sbard, ws,
                            stream);

@@ -275,6 +275,19 @@ template <int K, typename T, bool REPLAY> struct F2Step {
   T *x;
   double xscale;
   bool want_s, want_x, want_b1, sb_is_S;
+  // Replays that keep Sigma interleaved also write rows j < jh to Sh, the
+  // halo of the previous chunk (the B1 replay reads K + 1 records ahead).
+  BandP<T> Sh{nullptr, nullptr, 0};
+  int64_t jh = 0;
+  // Optional copy of each Sigma record with doubled off-diagonal entries (the
+  // sensitivity of tr(Q^{-1} S) with respect to S's stored entries).
+  BandP<T> So{nullptr, nullptr, 0};
+
+  BO_HD void set_halo(BandP<T> h, int64_t j_end) {
+    Sh = h;
+    jh = j_end;
+  }
+  BO_HD void set_sym_out(BandP<T> o) { So = o; }
 
   // wantB1: also accumulate the chunk map of the ascending B1 pass,
   // M = sum_j R'_j inj_j R'_j^T with R'_j = Kt_{b-1} ... Kt_{j+1} and inj_j
@@ -363,6 +376,14 @@ template <int K, typename T, bool REPLAY> struct F2Step {
 #pragma unroll
         for (int p = 0; p < K; ++p) o[p + 1] = v[p];
         store_rec<K, T>(S.p, S.diag, S.ld, j, o);
+        if (Sh.p && j < jh) store_rec<K, T>(Sh.p, Sh.diag, Sh.ld, j, o);
+        if (So.p) {
+          double o2[K + 1];
+          o2[0] = o[0];
+#pragma unroll
+          for (int p = 1; p <= K; ++p) o2[p] = 2.0 * o[p];
+          store_rec<K, T>(So.p, So.diag, So.ld, j, o2);
+        }
       }
 #pragma unroll
       for (int p = K - 1; p >= 1; --p)

@@ -157,13 +157,31 @@ __device__ __forceinline__ int lds_fill(uint32_t *dst, const E *my_src, int my_c
   return G::PPI4 * 4;
 }
 
+// Fill an LDS tile from an interleaved band: `bytes` contiguous bytes (a
+// multiple of 16, 16-byte aligned source) copied in 16-byte pieces, piece q
+// by lane q % 64 of instruction q / 64; LDS receives the block unchanged.
+__device__ __forceinline__ void il_fill(uint32_t *dst, const void *src, int bytes, int lane) {
+  __attribute__((address_space(3))) char *d = (__attribute__((address_space(3))) char *)(lds_ptr_t)dst;
+  const char *sp = (const char *)src;
+  const int np = bytes >> 4;
+#pragma unroll 4
+  for (int i = 0; i < np; i += kWave)
+    if (i + lane < np) load_piece<16>((uint64_t)(sp + (int64_t)(i + lane) * 16), d + i * 16);
+}
+
 // A staged band input: records of the lane's problem (null when absent) and,
 // in the mixed format, its FP64 diagonal.  `shift` offsets the staged rows
 // from the processed rows (the B1 replay reads Sigma K+1 rows ahead).
+//
+// An interleaved band (il) holds the chunks of one wavefront row by row: row r
+// of the chunk of lane l (global row lo_l + r) is record r * 64 + l of the
+// array that p points at, so one tile of every lane is one contiguous block.
+// Interleaved bands are FP64 only (no diag).
 template <typename T> struct BandIn {
   const T *p;
   const double *diag;
   int shift;
+  bool il = false;
 };
 template <typename T> struct VecIn {
   const T *p;
@@ -173,6 +191,12 @@ template <typename T> struct VecIn {
 // Streams rows [lo, hi) of each lane (ascending, or descending when DESC) and
 // calls body(j, rec, val) per row with rec[b] = record j(+shift_b) of band b
 // (slots past the matrix end zeroed) and val[v] = vector v at row j.
+//
+// Tiles are laid out in chunk-relative rows r = j - lo, common to the wave:
+// ascending, tile i covers r in [i TR, (i+1) TR); descending, tile i covers
+// r in [top - (i+1) TR, top - i TR) with top the wave's longest chunk, so a
+// lane with a shorter chunk starts later.  Each lane takes the rows of a tile
+// that lie in [0, hi - lo).
 //
 // Tile i of every array goes to buffer i % kTileBufs.  With two buffers the
 // order per tile is: wait for tile i's loads, barrier, issue tile i+1's loads
@@ -194,6 +218,7 @@ __device__ __forceinline__ void stream_rows(const BandIn<T> (&bands)[NB > 0 ? NB
   using GB = Geom<T, W, TR>;
   using GD = Geom<double, 1, TR>;
   using GV = Geom<T, 1, VR>;
+  static_assert(kWave * TR * W * (int)sizeof(T) <= GB::WORDS * 4, "an interleaved tile fits the band buffer");
   __shared__ __attribute__((aligned(16))) uint32_t sb[NBUF][NB1][GB::WORDS];
   __shared__ __attribute__((aligned(16))) uint32_t sd[NBUF][MIXED ? NB1 : 1][MIXED ? GD::WORDS : 1];
   __shared__ __attribute__((aligned(16))) uint32_t sv[NBUF][NV1][NV > 0 ? GV::WORDS : 1];
@@ -201,40 +226,70 @@ __device__ __forceinline__ void stream_rows(const BandIn<T> (&bands)[NB > 0 ? NB
   const int lane = threadIdx.x;
   const int64_t len = hi > lo ? hi - lo : 0;
   const int64_t maxlen = wave_max(len);
-  // Segment pitches and vector-tile origins per buffer.  Band buffers are
-  // indexed by compile-time constants (the tile loop is unrolled by NBUF);
-  // the vector buffer of a tile is a run-time choice between two, made with
-  // selects so that nothing here is indexed dynamically.
-  int pitch_b[NBUF][NB1], pitch_d[NBUF][NB1];
+  const int64_t top = maxlen;   // descending tiles count down from here
+  // Per band: where the lane's rows of the current tile start in LDS (bytes)
+  // and the LDS distance between consecutive rows.  A segment band keeps the
+  // lane's rows together (pitch per lane); an interleaved band keeps the
+  // block as loaded (64 records per row).
+  int rbase[NBUF][NB1], dbase[NBUF][NB1], rstride[NB1];
   int pv0[NV1], pv1[NV1];
   int64_t vb0 = 0, vb1 = 0;
 #pragma unroll
   for (int vi = 0; vi < NV1; ++vi) pv0[vi] = pv1[vi] = 0;
 #pragma unroll
-  for (int u = 0; u < NBUF; ++u)
+  for (int bi = 0; bi < NB1; ++bi) {
+    rstride[bi] = (NB > 0 && bands[bi].il ? kWave * W : W) * (int)sizeof(T);
 #pragma unroll
-    for (int bi = 0; bi < NB1; ++bi) pitch_b[u][bi] = pitch_d[u][bi] = 0;
-  // Issue the loads of tile `it` (rows from it * TR) into band buffer U.
+    for (int u = 0; u < NBUF; ++u) rbase[u][bi] = dbase[u][bi] = 0;
+  }
+  // chunk-relative rows [r_lo, r_hi) of tile `it` (the wave's block) and the
+  // lane's share [r_lo, min(r_hi, len)) of it
+  auto tile_span = [&](int64_t it, int rows, int64_t &r_lo, int64_t &r_hi) {
+    const int64_t t0 = it * TR;
+    if (DESC) {
+      r_hi = top - t0;
+      r_lo = r_hi - rows > 0 ? r_hi - rows : 0;
+    } else {
+      r_lo = t0;
+      r_hi = t0 + rows < maxlen ? t0 + rows : maxlen;
+    }
+  };
+  // Issue the loads of tile `it` into band buffer U.
   auto fill = [&](int64_t it, auto Uc) {
     constexpr int U = decltype(Uc)::value;
-    const int64_t t0 = it * TR;
-    const int cnt = (int)(len - t0 < TR ? (len - t0 > 0 ? len - t0 : 0) : TR);
-    const int64_t r0 = DESC ? hi - t0 - cnt : lo + t0;
+    int64_t r_lo, r_hi;
+    tile_span(it, TR, r_lo, r_hi);
+    const int64_t mine = (r_hi < len ? r_hi : len) - r_lo;
+    const int cnt = (int)(mine > 0 ? mine : 0);
+    const int64_t r0 = lo + r_lo;
 #pragma unroll
     for (int bi = 0; bi < NB; ++bi) {
-      int64_t s0 = r0 + bands[bi].shift;
-      int c = cnt;
-      if (s0 + c > n) c = (int)(n - s0 > 0 ? n - s0 : 0);
-      const bool on = bands[bi].p && c > 0;
-      pitch_b[U][bi] = lds_fill<T, W, TR>(sb[U][bi], on ? bands[bi].p + s0 * ld : nullptr, c, lane);
-      if (MIXED)
-        pitch_d[U][bi] = lds_fill<double, 1, TR>(sd[U][MIXED ? bi : 0],
-                                                 (on && bands[bi].diag) ? bands[bi].diag + s0 : nullptr, c, lane);
+      if (!MIXED && bands[bi].il) {
+        // the wave's block of rows [r_lo, r_hi) (shifted), every lane's slot
+        const int64_t b0 = r_lo + bands[bi].shift;
+        const int rows = (int)(r_hi - r_lo);
+        if (bands[bi].p && rows > 0)
+          il_fill(sb[U][bi], bands[bi].p + b0 * kWave * W, rows * kWave * W * (int)sizeof(T), lane);
+        rbase[U][bi] = lane * W * (int)sizeof(T);
+      } else {
+        int64_t s0 = r0 + bands[bi].shift;
+        int c = cnt;
+        if (s0 + c > n) c = (int)(n - s0 > 0 ? n - s0 : 0);
+        const bool on = bands[bi].p && c > 0;
+        rbase[U][bi] = lane * lds_fill<T, W, TR>(sb[U][bi], on ? bands[bi].p + s0 * ld : nullptr, c, lane);
+        if (MIXED)
+          dbase[U][bi] = lane * lds_fill<double, 1, TR>(sd[U][MIXED ? bi : 0],
+                                                        (on && bands[bi].diag) ? bands[bi].diag + s0 : nullptr, c,
+                                                        lane);
+      }
     }
     if (NV > 0 && it % VM == 0) {   // next vector tile: rows of the following VM band tiles
       const bool v1 = NBUF > 1 && ((it / VM) & 1);
-      const int vcnt = (int)(len - t0 < VR ? (len - t0 > 0 ? len - t0 : 0) : VR);
-      const int64_t vb = DESC ? hi - t0 - vcnt : lo + t0;
+      int64_t v_lo, v_hi;
+      tile_span(it, VR, v_lo, v_hi);
+      const int64_t vmine = (v_hi < len ? v_hi : len) - v_lo;
+      const int vcnt = (int)(vmine > 0 ? vmine : 0);
+      const int64_t vb = lo + v_lo;
       if (v1) vb1 = vb;
       else vb0 = vb;
 #pragma unroll
@@ -255,25 +310,25 @@ __device__ __forceinline__ void stream_rows(const BandIn<T> (&bands)[NB > 0 ? NB
     constexpr int U = decltype(Uc)::value;
     const bool v1 = NBUF > 1 && ((it / VM) & 1);
     const int64_t vbase = v1 ? vb1 : vb0;
-    const int64_t t0 = it * TR;
-    const int cnt = (int)(len - t0 < TR ? (len - t0 > 0 ? len - t0 : 0) : TR);
-    const int64_t r0 = DESC ? hi - t0 - cnt : lo + t0;
+    int64_t r_lo, r_hi;
+    tile_span(it, TR, r_lo, r_hi);
 #pragma unroll 1
     for (int t = 0; t < TR; ++t) {
-      if (t < cnt) {
-        const int r = DESC ? cnt - 1 - t : t;
-        const int64_t j = r0 + r;
+      const int64_t r = DESC ? r_hi - 1 - t : r_lo + t;
+      if (r >= r_lo && r < r_hi && r < len) {
+        const int lr = (int)(r - r_lo);   // row within the tile
+        const int64_t j = lo + r;
         double rec[NB1][K + 1];
         double val[NV1];
 #pragma unroll
         for (int bi = 0; bi < NB; ++bi) {
           const int64_t js = j + bands[bi].shift;
-          lds_cptr<T> row = (lds_cptr<T>)((lds_cptr<char>)(lds_ptr_t)sb[U][bi] + lane * pitch_b[U][bi]) + r * W;
+          lds_cptr<T> row = (lds_cptr<T>)((lds_cptr<char>)(lds_ptr_t)sb[U][bi] + rbase[U][bi] + lr * rstride[bi]);
 #pragma unroll
           for (int d = 0; d <= K; ++d) {
             double x = (double)row[d];
             if (d == 0 && MIXED && bands[bi].diag)
-              x = ((lds_cptr<double>)((lds_cptr<char>)(lds_ptr_t)sd[U][MIXED ? bi : 0] + lane * pitch_d[U][bi]))[r];
+              x = ((lds_cptr<double>)((lds_cptr<char>)(lds_ptr_t)sd[U][MIXED ? bi : 0] + dbase[U][bi]))[lr];
             rec[bi][d] = (bands[bi].p && js + d < n) ? x : 0.0;
           }
         }

@@ -1,0 +1,220 @@
+"""The loss unit with its intermediates kept in the workspace.
+
+bo_plan_gauss_loss with L, Sig and Lbar all NULL keeps the three bands in the
+plan's workspace, interleaved by chunk (row r of the chunk of lane l of a
+wavefront at record r * 64 + l of the wavefront's block), with a halo of the
+next chunk's first K + 1 records of Sigma for the Algorithm 4 pass.  The
+arithmetic is the same as with the caller's arrays, so every output (Qbar,
+ybar, z, the per-problem parts and info) must agree bit for bit; Sbar, which
+this mode writes from the subset-inverse pass itself, must equal
+(Sigma_ii, 2 Sigma_ij) of the caller-array run.  The oracle check of the
+caller-array mode (test_gpu_parity.py) then carries over; one batch is also
+checked against the oracle directly."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from bandutil import band_mask, rel_err
+from paper_1902_10078_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def bo():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1902_10078_amd import bandops
+    bandops.lib()
+    return bandops
+
+
+def dev(a, dtype=torch.float64):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def packed_batch(ns, ks, seed):
+    Ls, ys = inputs.config2_factors(seed, ns, ks)
+    rng = np.random.default_rng(seed + 1)
+    Qs = [oracle.gbmm(L, k, 0, L, k, 0, tB=1, lc=k, uc=0) for L, k in zip(Ls, ks)]
+    Ss = [inputs.random_sym_band_dd(n, k, rng) for n, k in zip(ns, ks)]
+    return Qs, ys, Ss
+
+
+def run_loss(bo, plan, Qs, ys, Ss, keep: bool):
+    cat = lambda arrs: np.concatenate([a.ravel() for a in arrs]) if arrs else np.zeros(0)
+    Qf, yf, Sf = cat(Qs), cat(ys), cat(Ss)
+    E, N = Qf.size, yf.size
+    nan = lambda m: torch.full((m,), float("nan"), dtype=torch.float64, device="cuda")
+    kw = dict(Q=dev(Qf), y=dev(yf), S=dev(Sf), z=nan(N), x=nan(N), Qbar=nan(E), Sbar=nan(E),
+              parts=torch.zeros((len(Qs), 3), dtype=torch.float64, device="cuda"),
+              loss=torch.zeros(len(Qs), dtype=torch.float64, device="cuda"),
+              info=torch.zeros(len(Qs), dtype=torch.int32, device="cuda"))
+    if not keep:
+        kw.update(L=nan(E), Sig=nan(E), Lbar=nan(E))
+    io = plan.io(**kw)
+    plan.gauss_loss(0, io)
+    torch.cuda.synchronize()
+    return {nm: t.cpu().numpy() for nm, t in kw.items()}
+
+
+def same(a, b):
+    """Bit-for-bit equality, NaN where both are NaN (pads of never-written
+    slots are not compared)."""
+    return np.array_equal(a, b, equal_nan=True)
+
+
+def check_pair(plan, ns, ks, a, b):
+    """a: caller arrays, b: kept in the workspace."""
+    for nm in ("Qbar", "x", "z", "parts", "loss", "info"):
+        if nm in ("Qbar",):
+            for p, (n, k) in enumerate(zip(ns, ks)):
+                o, sz = plan.boff[p], n * (k + 1)
+                m = band_mask(n, k).astype(bool)
+                ga, gb = a[nm][o:o + sz].reshape(n, k + 1), b[nm][o:o + sz].reshape(n, k + 1)
+                assert same(ga[m], gb[m]), (nm, p)
+        else:
+            assert same(a[nm], b[nm]), nm
+    # Sbar from the subset-inverse pass against (Sigma_ii, 2 Sigma_ij) of the caller run
+    for p, (n, k) in enumerate(zip(ns, ks)):
+        o, sz = plan.boff[p], n * (k + 1)
+        m = band_mask(n, k).astype(bool)
+        sig = a["Sig"][o:o + sz].reshape(n, k + 1).copy()
+        sig[:, 1:] *= 2.0
+        got = b["Sbar"][o:o + sz].reshape(n, k + 1)
+        assert same(sig[m], got[m]), ("Sbar", p)
+
+
+CASES = [
+    # an uneven batch: empty, one-row and tiny problems, every chunk shape
+    ([700, 1, 33, 5000, 0, 257, 12000, 64, 3, 2500], [3, 0, 1, 5, 2, 11, 3, 12, 1, 5], 600),
+    # bandwidths above the fused limit (separate summary passes)
+    ([3001, 2222, 1777], [4, 6, 7], 180),
+    ([3001, 2222, 1777, 999, 1500], [1, 2, 8, 9, 10], 180),
+    # one long problem over many wavefronts, ragged last chunk
+    ([200001], [5], 4096),
+]
+
+
+@pytest.mark.parametrize("ns,ks,tc", CASES)
+def test_kept_intermediates_equal_caller_arrays(bo, ns, ks, tc):
+    Qs, ys, Ss = packed_batch(ns, ks, 31 + len(ns))
+    plan = bo.Plan(ns, ks, target_chunks=tc)
+    a = run_loss(bo, plan, Qs, ys, Ss, keep=False)
+    b = run_loss(bo, plan, Qs, ys, Ss, keep=True)
+    assert np.all(a["info"] == 0)
+    check_pair(plan, ns, ks, a, b)
+
+
+def test_kept_intermediates_many_problems(bo):
+    """Forty problems of every compiled bandwidth with chunks of different
+    lengths in one wavefront (problems end inside wavefronts)."""
+    rng = np.random.default_rng(77)
+    ns = [int(v) for v in rng.integers(40, 3000, size=40)]
+    ks = [int(v) for v in rng.integers(0, 13, size=40)]
+    Qs, ys, Ss = packed_batch(ns, ks, 78)
+    plan = bo.Plan(ns, ks, target_chunks=900)
+    a = run_loss(bo, plan, Qs, ys, Ss, keep=False)
+    b = run_loss(bo, plan, Qs, ys, Ss, keep=True)
+    assert np.all(a["info"] == 0)
+    check_pair(plan, ns, ks, a, b)
+
+
+def test_kept_intermediates_against_oracle(bo):
+    ns, ks = [5000, 1777, 33, 20011], [5, 3, 1, 5]
+    Qs, ys, Ss = packed_batch(ns, ks, 90)
+    plan = bo.Plan(ns, ks, target_chunks=300)
+    b = run_loss(bo, plan, Qs, ys, Ss, keep=True)
+    assert np.all(b["info"] == 0)
+    for p, (n, k) in enumerate(zip(ns, ks)):
+        r = oracle.gauss_loss(Qs[p], k, ys[p], Ss[p])
+        o, v, sz = plan.boff[p], plan.voff[p], n * (k + 1)
+        m = band_mask(n, k)
+        for i in range(3):
+            assert abs(b["parts"][p, i] - r["parts"][i]) <= TOL * max(1, abs(r["parts"][i])), (p, i)
+        assert rel_err(b["Qbar"][o:o + sz].reshape(n, k + 1) * m, r["Qbar"] * m) <= TOL, p
+        assert rel_err(b["x"][v:v + n], r["ybar"]) <= TOL, p
+        sig = r["Sig"].copy()
+        sig[:, 1:] *= 2.0
+        assert rel_err(b["Sbar"][o:o + sz].reshape(n, k + 1) * m, sig * m) <= TOL, p
+
+
+def test_kept_intermediates_failing_problem(bo):
+    """A non-SPD problem reports the same info as with caller arrays and leaves
+    its neighbours' outputs unchanged."""
+    ns, ks = [3000, 2500, 4000], [5, 5, 3]
+    Qs, ys, Ss = packed_batch(ns, ks, 91)
+    Qs[1] = Qs[1].copy()
+    Qs[1][1234, 0] = -1.0
+    plan = bo.Plan(ns, ks, target_chunks=200)
+    a = run_loss(bo, plan, Qs, ys, Ss, keep=False)
+    b = run_loss(bo, plan, Qs, ys, Ss, keep=True)
+    assert a["info"][1] > 0 and a["info"][0] == 0 and a["info"][2] == 0
+    assert np.array_equal(a["info"], b["info"])
+    for p in (0, 2):
+        o, v, sz = plan.boff[p], plan.voff[p], ns[p] * (ks[p] + 1)
+        m = band_mask(ns[p], ks[p]).astype(bool)
+        assert same(a["Qbar"][o:o + sz].reshape(ns[p], -1)[m], b["Qbar"][o:o + sz].reshape(ns[p], -1)[m])
+        assert same(a["x"][v:v + ns[p]], b["x"][v:v + ns[p]])
+        assert same(a["parts"][p], b["parts"][p])
+
+
+def test_kept_intermediates_graph_replays(bo):
+    """Captured in a HIP graph and replayed three times with eager work in
+    between: every replay equals the eager call bit for bit."""
+    ns, ks = [6000, 4096, 777], [5, 3, 11]
+    Qs, ys, Ss = packed_batch(ns, ks, 92)
+    plan = bo.Plan(ns, ks, target_chunks=256)
+    ref = run_loss(bo, plan, Qs, ys, Ss, keep=True)
+    cat = lambda arrs: np.concatenate([a.ravel() for a in arrs])
+    Qf, yf, Sf = cat(Qs), cat(ys), cat(Ss)
+    E, N = Qf.size, yf.size
+    kw = dict(Q=dev(Qf), y=dev(yf), S=dev(Sf), z=torch.zeros(N, dtype=torch.float64, device="cuda"),
+              x=torch.zeros(N, dtype=torch.float64, device="cuda"),
+              Qbar=torch.zeros(E, dtype=torch.float64, device="cuda"),
+              parts=torch.zeros((3, 3), dtype=torch.float64, device="cuda"),
+              info=torch.zeros(3, dtype=torch.int32, device="cuda"))
+    io = plan.io(**kw)
+    plan.ensure_loss_workspace()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.gauss_loss(0, io)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.gauss_loss(0, io)
+    for rep in range(3):
+        for t in (kw["Qbar"], kw["x"], kw["z"], kw["parts"]):
+            t.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for nm in ("x", "z", "parts", "info"):
+            assert np.array_equal(kw[nm].cpu().numpy(), ref[nm]), (rep, nm)
+        qb = kw["Qbar"].cpu().numpy()
+        for p, (n, k) in enumerate(zip(ns, ks)):
+            o, sz = plan.boff[p], n * (k + 1)
+            m = band_mask(n, k).astype(bool)
+            assert same(qb[o:o + sz].reshape(n, -1)[m], ref["Qbar"][o:o + sz].reshape(n, -1)[m]), (rep, p)
+        # eager work on the same plan between replays
+        run_loss(bo, plan, Qs, ys, Ss, keep=False)
+
+
+def test_kept_intermediates_need_f64(bo):
+    plan = bo.Plan([100], [3])
+    Q = torch.zeros(400, dtype=torch.float32, device="cuda")
+    y = torch.zeros(100, dtype=torch.float32, device="cuda")
+    d = torch.zeros(100, dtype=torch.float64, device="cuda")
+    io = plan.io(Q=Q, Qd=d, y=y, S=Q, Sd=d, z=y, x=y, Qbar=Q, Qbard=d,
+                 parts=torch.zeros(3, dtype=torch.float64, device="cuda"),
+                 info=torch.zeros(1, dtype=torch.int32, device="cuda"))
+    with pytest.raises(bo.BandOpsError):
+        plan.gauss_loss(bo.MIXED, io)
