@@ -304,6 +304,8 @@ class Workload:
         kw = dict(Q=Qt, y=yt, z=torch.zeros(N, dtype=vdt, device=dev), x=torch.zeros(N, dtype=vdt, device=dev),
                   info=torch.zeros(nprob, dtype=torch.int32, device=dev))
         names = ("L", "Sig") if forward_only else (("Qbar",) if keep else ("L", "Sig", "Lbar", "Qbar"))
+        if keep:
+            del kw["z"]   # an intermediate of the loss unit: kept in the workspace
         for nm in names:
             kw[nm] = torch.zeros(E, dtype=vdt, device=dev)
         if forward_only:

@@ -235,9 +235,9 @@ bo_status bo_plan_create(const bo_problem *probs, int32_t nprob, int64_t target_
 bo_status bo_plan_workspace_size(const bo_plan *plan, size_t *bytes);
 /* Workspace bytes for bo_plan_gauss_loss when it keeps L, Sig and Lbar in the
  * workspace (io->L, io->Sig and io->Lbar all NULL, BO_F64): the workspace
- * proper followed by three FP64 arrays in which the chunks of every
- * wavefront lie interleaved row by row, so that the passes read and write
- * them in whole contiguous blocks. */
+ * proper followed by three FP64 band arrays and two FP64 vectors (z and a
+ * copy of ybar) in which the chunks of every wavefront lie interleaved row by
+ * row, so that the passes read and write them in whole contiguous blocks. */
 bo_status bo_plan_loss_workspace_size(const bo_plan *plan, size_t *bytes);
 /* Copy the plan's device tables into ws (stream-ordered; do this once, before
  * capture, and again whenever ws is a new buffer). */
@@ -253,9 +253,10 @@ bo_status bo_plan_forward(const bo_plan *plan, bo_prec prec, const bo_batch_io *
  * parts and info; when given, loss[p] (the sum of the parts) and Sbar =
  * d loss / d S on S's stored entries (Sigma_ii on the diagonal, 2 Sigma_ij off
  * it: an off-diagonal stored entry of S stands for S_ij and S_ji).  With L,
- * Sig and Lbar all NULL (BO_F64 only) the three intermediates are kept in ws,
- * which must then hold bo_plan_loss_workspace_size bytes; the other outputs
- * are the same, bit for bit. */
+ * Sig and Lbar all NULL (BO_F64 only) the intermediates L, Sig, Lbar and z
+ * are kept in ws, which must then hold bo_plan_loss_workspace_size bytes; z
+ * may then be NULL (written when given), and the other outputs are the same,
+ * bit for bit. */
 bo_status bo_plan_gauss_loss(const bo_plan *plan, bo_prec prec, const bo_batch_io *io, void *ws,
                              hipStream_t stream);
 /* Kullback-Leibler term of the variational objective (Section 3.3, Eq. (KL);

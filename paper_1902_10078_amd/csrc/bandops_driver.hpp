@@ -32,7 +32,8 @@ struct KRange {
   int32_t c_beg, c_cnt, g_beg, g_cnt, p_beg, p_cnt;
   int32_t max_nchunk;   // largest chunk count of a problem in the range
   int32_t il_rows;      // interleaved slot rows per lane: longest chunk + K + 1
-  int64_t il_off;       // element offset of the range in each interleaved array
+  int64_t il_off;       // element offset of the range in each interleaved band
+  int64_t il_voff;      // element offset of the range in each interleaved vector
 };
 
 struct Sched {
@@ -44,7 +45,7 @@ struct Sched {
   int64_t rows = 0;
   // interleaved intermediates (FP64 elements per array; the arrays follow
   // the workspace proper when a call keeps L, Sigma and Lbar there)
-  int64_t il_elems = 0;
+  int64_t il_elems = 0, il_velems = 0;
   // workspace layout (bytes offsets from the workspace base)
   size_t off_tables = 0, off_f1map = 0, off_f1st = 0, off_f1gmap = 0, off_f1gst = 0, off_Pc = 0,
          off_Pg = 0, off_Pex = 0, off_lmap = 0, off_lmap2 = 0, off_lst = 0, off_lgmap = 0, off_lgst = 0, off_part = 0,
@@ -144,7 +145,9 @@ inline bool build_sched(const ProbIn *in, int nprob, int64_t target_chunks, int6
     r.g_cnt = last.group0 + last.ngroup - r.g_beg;
     r.il_rows = (int32_t)(maxclen + K + 1);
     r.il_off = s.il_elems;
+    r.il_voff = s.il_velems;
     s.il_elems += (int64_t)((r.c_cnt + 63) / 64) * r.il_rows * 64 * (K + 1);
+    s.il_velems += (int64_t)((r.c_cnt + 63) / 64) * r.il_rows * 64;
     s.ranges.push_back(r);
     ii = jj;
   }
@@ -186,7 +189,8 @@ inline bool build_sched(const ProbIn *in, int nprob, int64_t target_chunks, int6
   s.off_out = take((size_t)nprob * 8);
   s.bytes = o;
   s.off_il = o;
-  s.bytes_il = o + 3 * align_up((size_t)s.il_elems * sizeof(double));
+  s.bytes_il = o + 3 * align_up((size_t)s.il_elems * sizeof(double)) +
+               2 * align_up((size_t)s.il_velems * sizeof(double));
   return true;
 }
 
@@ -232,13 +236,16 @@ inline void set_range(Args &A, const KRange &r) {
   A.p_beg = r.p_beg;
   A.il_rows = r.il_rows;
   A.il_off = r.il_off;
+  A.il_voff = r.il_voff;
 }
 
-// Point L, S and Lb at the interleaved arrays that follow the workspace
-// proper (a workspace of s.bytes_il bytes).
+// Point L, S, Lb, z and the copy of x at the interleaved arrays that follow
+// the workspace proper (a workspace of s.bytes_il bytes); a caller's z
+// becomes the optional second copy of z.
 inline void bind_il(const Sched &s, void *ws, Args &A) {
   unsigned char *w = (unsigned char *)ws + s.off_il;
   const size_t one = align_up((size_t)s.il_elems * sizeof(double));
+  const size_t vone = align_up((size_t)s.il_velems * sizeof(double));
   A.il = 1;
   A.L = w;
   A.Ld = nullptr;
@@ -246,6 +253,9 @@ inline void bind_il(const Sched &s, void *ws, Args &A) {
   A.Sd = nullptr;
   A.Lb = w + 2 * one;
   A.Lbd = nullptr;
+  A.zcopy = A.z;
+  A.z = w + 3 * one;
+  A.xil = w + 3 * one + vone;
 }
 
 // ---------------------------------------------------------------- sequences

@@ -73,10 +73,16 @@ struct Args {
   // il_off + ((w * il_rows + r) * 64 + l) * (K + 1); il_rows is the range's
   // longest chunk + K + 1, the extra rows a halo that holds the next chunk's
   // first K + 1 records of S.
+  // With il the vectors z (so also bx and zf) are interleaved the same way
+  // (one element per record), and the kernels read ybar from xil, an
+  // interleaved copy of x (= ybar) with the same halo, instead of yb.
   int32_t il;
   int32_t il_rows;
   void *sbar_out;   // F2 replay with il: also writes (Sigma_jj, 2 Sigma_ij) here (or null)
-  int64_t il_off;   // element offset of the launch's bandwidth range
+  void *xil;        // F2 replay with il: the interleaved copy of x
+  void *zcopy;      // F1 replay with il: also writes z here (a caller's vector, or null)
+  int64_t il_off;   // element offset of the launch's bandwidth range (bands)
+  int64_t il_voff;  // element offset of the launch's bandwidth range (vectors)
 };
 
 BO_HD const ProbDesc &prob_at(const Args &a, int32_t p) { return a.probs ? a.probs[p] : a.one; }

@@ -65,6 +65,31 @@ __device__ __forceinline__ BandP<T> il_view(void *base, const Args &A, int64_t w
 template <int K, typename T> __device__ __forceinline__ BandP<T> lane_view(void *base, const Args &A, const LaneChunk &C) {
   return il_view<K, T>(base, A, blockIdx.x, threadIdx.x, C.a);
 }
+// Interleaved vectors (one element per record): the same rows and lanes.
+template <typename T> __device__ __forceinline__ T *il_vwave(const void *base, const Args &A, int64_t w) {
+  return (T *)base + A.il_voff + w * (int64_t)A.il_rows * kBlock;
+}
+template <typename T>
+__device__ __forceinline__ VecP<T> il_vview(const void *base, const Args &A, int64_t w, int l, int64_t a) {
+  const uint64_t p = (uint64_t)(il_vwave<T>(base, A, w) + l) - (uint64_t)(a * kBlock * (int64_t)sizeof(T));
+  return VecP<T>((T *)p, kBlock);
+}
+template <typename T> __device__ __forceinline__ VecP<T> lane_vview(const void *base, const Args &A, const LaneChunk &C) {
+  return il_vview<T>(base, A, blockIdx.x, threadIdx.x, C.a);
+}
+// The same view of the previous chunk of the lane's problem (its halo rows
+// follow its own rows).
+template <typename T> __device__ __forceinline__ VecP<T> prev_vview(const void *base, const Args &A, const LaneChunk &C) {
+  const int l = threadIdx.x;
+  return il_vview<T>(base, A, l > 0 ? (int64_t)blockIdx.x : (int64_t)blockIdx.x - 1, l > 0 ? l - 1 : kBlock - 1,
+                     C.a - C.pd.clen);
+}
+template <typename T>
+__device__ __forceinline__ VecIn<T> vstaged(bool il, const void *base, const Args &A, const T *rm, bool on,
+                                            int shift = 0) {
+  if (il) return VecIn<T>{il_vwave<T>(base, A, blockIdx.x), shift, true};
+  return VecIn<T>{on ? rm : nullptr, shift, false};
+}
 template <typename T> __device__ __forceinline__ BandP<const T> const_view(BandP<T> b) {
   return BandP<const T>{b.p, b.diag, b.ld};
 }
@@ -138,8 +163,10 @@ __global__ void __launch_bounds__(kBlock) k_f1_rep(const Args A, int64_t count) 
   F1RepStep<K, T> st;
   const bool fuse = K <= KMAX_FUSED && A.lmap_out && A.Pc;
   const bool il = sizeof(T) == 8 && A.il != 0;
-  st.begin(s0, il ? lane_view<K, T>(A.L, A, C) : band<T>(A.L, A.Ld, pd), y ? vec<T>(A.z, pd) : nullptr,
-           A.Pc != nullptr, fuse);
+  VecP<T> zout;
+  if (y) zout = il ? lane_vview<T>(A.z, A, C) : VecP<T>(vec<T>(A.z, pd));
+  st.begin(s0, il ? lane_view<K, T>(A.L, A, C) : band<T>(A.L, A.Ld, pd), zout, A.Pc != nullptr, fuse);
+  if (il && y && A.zcopy) st.z2 = VecP<T>(vec<T>(A.zcopy, pd));
   BandIn<T> bands[1] = {{on ? Q.p : nullptr, on ? Q.diag : nullptr, 0}};
   VecIn<T> vecs[NV];
   vecs[0] = {on ? y : nullptr, 0};
@@ -260,7 +287,9 @@ __global__ void __launch_bounds__(kBlock) k_f2(const Args A, int64_t count) {
                C.a + K + 1);
   }
   if (REPLAY && il && A.sbar_out) s.set_sym_out(band<T>(A.sbar_out, nullptr, pd));
-  VecIn<T> vecs[1] = {{on ? bx : nullptr, 0}};
+  if (REPLAY && il && A.xil && on)
+    s.set_x_copy(lane_vview<T>(A.xil, A, C), C.c > pd.chunk0 ? prev_vview<T>(A.xil, A, C) : VecP<T>(), C.a + K + 1);
+  VecIn<T> vecs[1] = {vstaged<T>(il, A.bx, A, bx, on)};
   if constexpr (FUSE) {
     BandP<const T> Sb = cband<T>(A.Sb, A.Sbd, pd);
     BandIn<T> bands[2] = {staged<K, T>(il, A.L, A, L, on),
@@ -311,8 +340,8 @@ __global__ void __launch_bounds__(kBlock) k_b1(const Args A, int64_t count) {
                           staged<K, T>(il, A.S, A, Sig, on, K + 1)};
     if constexpr (FUSE) {
       const T *yb = cvec<T>(A.yb, pd);
-      if (on) s.begin_b2(C.a, pd.n, yb, A.gl);
-      VecIn<T> vecs[2] = {{on ? yb : nullptr, K + 1}, {on ? cvec<T>(A.zf, pd) : nullptr, 0}};
+      if (on) s.begin_b2(C.a, pd.n, il ? lane_vview<const T>(A.xil, A, C) : VecP<const T>(yb), A.gl);
+      VecIn<T> vecs[2] = {vstaged<T>(il, A.xil, A, yb, on, K + 1), vstaged<T>(il, A.zf, A, cvec<T>(A.zf, pd), on)};
       stream_rows<K, T, 3, 2, false>(bands, vecs, on ? C.a : 0, on ? C.b : 0, pd.n, pd.ld,
                                      [&](int64_t j, const double (&rec)[3][K + 1], const double (&val)[2]) {
                                        s.row(j, pd.n, rec[0], rec[1], rec[2], val[1], val[0]);
@@ -361,12 +390,14 @@ __global__ void __launch_bounds__(kBlock) k_b2(const Args A, int64_t count) {
   LinMap<K> st;
   lin_in<K>(A, C, REPLAY, st);
   B2Step<K, T, REPLAY> s;
-  s.begin(st, C.b, pd.n, on ? yb : nullptr, A.gl, band<T>(A.Qb, A.Qbd, pd));
   const bool il = sizeof(T) == 8 && A.il != 0;
+  VecP<const T> ybv;
+  if (on && yb) ybv = il ? lane_vview<const T>(A.xil, A, C) : VecP<const T>(yb);
+  s.begin(st, C.b, pd.n, ybv, A.gl, band<T>(A.Qb, A.Qbd, pd));
   BandIn<T> bands[NB];
   bands[0] = staged<K, T>(il, A.L, A, L, on);
   if constexpr (WITH_LB) bands[NB - 1] = staged<K, T>(il, A.Lb, A, Lb, on);
-  VecIn<T> vecs[2] = {{on ? yb : nullptr, 0}, {on ? zf : nullptr, 0}};
+  VecIn<T> vecs[2] = {vstaged<T>(il && yb, A.xil, A, yb, on), vstaged<T>(il && zf, A.zf, A, zf, on)};
   stream_rows<K, T, NB, 2, true>(bands, vecs, on ? C.a : 0, on ? C.b : 0, pd.n, pd.ld,
                                  [&](int64_t j, const double (&rec)[NB][K + 1], const double (&val)[2]) {
                                    if constexpr (WITH_LB) {

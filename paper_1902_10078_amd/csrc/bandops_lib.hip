@@ -945,7 +945,7 @@ extern "C" bo_status bo_plan_gauss_loss(const bo_plan *plan, bo_prec prec, const
   if (bo_status e = plan_args(plan, prec, io, ws, A, !keep)) return e;
   if (keep && prec != BO_F64)
     return fail(BO_EINVAL, "bo_plan_gauss_loss: intermediates in the workspace need BO_F64");
-  if (!io->y || !io->S || !io->z || !io->x || (!keep && (!io->Sig || !io->Lbar)) || !io->Qbar || !io->parts ||
+  if (!io->y || !io->S || (!keep && (!io->z || !io->Sig || !io->Lbar)) || !io->x || !io->Qbar || !io->parts ||
       !io->info)
     return fail(BO_EINVAL, "bo_plan_gauss_loss: y, S, z, x, Sig, Lbar, Qbar, parts, info required");
   if (keep) {

@@ -104,7 +104,7 @@ template <int K, typename T> struct F1RepStep {
   int64_t fail;
   bool want_P, want_f2;
   BandP<T> L;
-  T *z;
+  VecP<T> z, z2;   // z, and an optional second copy of it
 
   // wantF2 (needs wantP): also accumulate the chunk map of the descending F2
   // pass, M = sum_j R_j^T c_j e0 e0^T R_j and v = sum_j R_j^T e0 b_j / L_jj
@@ -112,9 +112,10 @@ template <int K, typename T> struct F1RepStep {
   // summed in ascending order.  The back solve's right-hand side b is the
   // forward solve's z when the replay writes z, else the replay's y input
   // itself (a back solve L^{-T} y with no forward solve).
-  BO_HD void begin(const F1State<K> &st, BandP<T> L_, T *z_, bool wantP, bool wantF2 = false) {
+  BO_HD void begin(const F1State<K> &st, BandP<T> L_, VecP<T> z_, bool wantP, bool wantF2 = false) {
     L = L_;
     z = z_;
+    z2 = VecP<T>();
     want_P = wantP;
     want_f2 = K <= KMAX_FUSED && wantP && wantF2;
     ls = qs = 0.0;
@@ -162,6 +163,7 @@ template <int K, typename T> struct F1RepStep {
     if (z) {
       zj = (yj - (K > 0 ? g[0] : 0.0)) * inv;
       z[j] = (T)zj;
+      if (z2) z2[j] = (T)zj;
       qs += zj * zj;
     }
 #pragma unroll
@@ -272,7 +274,7 @@ template <int K, typename T, bool REPLAY> struct F2Step {
   double Rb[K1][K1], Mb[NS];   // fused summary of the B1 pass (see row_b1())
   double u_[K1];               // u_j of the last row() (row_b1() reuses it)
   BandP<T> S;
-  T *x;
+  VecP<T> x;
   double xscale;
   bool want_s, want_x, want_b1, sb_is_S;
   // Replays that keep Sigma interleaved also write rows j < jh to Sh, the
@@ -282,18 +284,25 @@ template <int K, typename T, bool REPLAY> struct F2Step {
   // Optional copy of each Sigma record with doubled off-diagonal entries (the
   // sensitivity of tr(Q^{-1} S) with respect to S's stored entries).
   BandP<T> So{nullptr, nullptr, 0};
+  // Optional second copy of x (x2) with its own halo view (xh, rows j < jh).
+  VecP<T> x2, xh;
 
   BO_HD void set_halo(BandP<T> h, int64_t j_end) {
     Sh = h;
     jh = j_end;
   }
   BO_HD void set_sym_out(BandP<T> o) { So = o; }
+  BO_HD void set_x_copy(VecP<T> c, VecP<T> h, int64_t j_end) {
+    x2 = c;
+    xh = h;
+    jh = j_end;
+  }
 
   // wantB1: also accumulate the chunk map of the ascending B1 pass,
   // M = sum_j R'_j inj_j R'_j^T with R'_j = Kt_{b-1} ... Kt_{j+1} and inj_j
   // the injection of Sigmabar record j (B1Step) -- the zero-state run of B1
   // over the chunk, summed in descending order.
-  BO_HD void begin(const LinMap<K> &st, BandP<T> S_, T *x_, double xs, bool ws, bool wx,
+  BO_HD void begin(const LinMap<K> &st, BandP<T> S_, VecP<T> x_, double xs, bool ws, bool wx,
                    bool wantB1 = false, bool sbS = false) {
     S = S_;
     x = x_;
@@ -397,7 +406,14 @@ template <int K, typename T, bool REPLAY> struct F2Step {
       double xj = bj * inv;
 #pragma unroll
       for (int p = 0; p < K; ++p) xj -= u[p] * xw[p];
-      if (REPLAY) x[j] = (T)(xscale * xj);
+      if (REPLAY) {
+        const T xv = (T)(xscale * xj);
+        x[j] = xv;
+        if (x2) {
+          x2[j] = xv;
+          if (xh && j < jh) xh[j] = xv;
+        }
+      }
 #pragma unroll
       for (int p = K - 1; p >= 1; --p) xw[p] = xw[p - 1];
       if (K > 0) xw[0] = xj;
@@ -427,6 +443,9 @@ template <int K> struct B2MapAcc {
   double Rf[K1][K1], Mf[NS], yw[K + 1], glf;
 
   template <typename T> BO_HD void begin(int64_t a, int64_t n, const T *ybar, double gl) {
+    begin_v<T>(a, n, VecP<const T>(ybar), gl);
+  }
+  template <typename T> BO_HD void begin_v(int64_t a, int64_t n, VecP<const T> ybar, double gl) {
     glf = gl;
 #pragma unroll
     for (int p = 0; p < K1; ++p)
@@ -519,9 +538,9 @@ template <int K, typename T, bool REPLAY, bool B2MAP = true> struct B1Step {
   bool want_b2;
   B2MapAcc<K> b2;
 
-  BO_HD void begin_b2(int64_t a, int64_t n, const T *ybar, double gl) {
+  BO_HD void begin_b2(int64_t a, int64_t n, VecP<const T> ybar, double gl) {
     want_b2 = true;
-    b2.begin(a, n, ybar, gl);
+    b2.template begin_v<T>(a, n, ybar, gl);
   }
 
   BO_HD void end_b2(LinMap<K> &m) const { b2.end(m); }
@@ -646,10 +665,10 @@ template <int K, typename T, bool REPLAY> struct B2Step {
   BandP<T> Qb;
 
   // ybar[b .. b+K-1] is read directly (once per chunk).
-  BO_HD void begin(const LinMap<K> &st, int64_t b, int64_t n, const T *ybar, double gl_,
+  BO_HD void begin(const LinMap<K> &st, int64_t b, int64_t n, VecP<const T> ybar, double gl_,
                    BandP<T> Qb_) {
     gl = gl_;
-    with_y = ybar != nullptr;
+    with_y = ybar.p != nullptr;
     Qb = Qb_;
 #pragma unroll
     for (int p = 0; p < K1; ++p) {

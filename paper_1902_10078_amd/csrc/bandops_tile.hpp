@@ -186,6 +186,7 @@ template <typename T> struct BandIn {
 template <typename T> struct VecIn {
   const T *p;
   int shift;   // staged rows = processed rows + shift (values past n read 0)
+  bool il = false;   // interleaved like a band (element r * 64 + l), FP64 only
 };
 
 // Streams rows [lo, hi) of each lane (ascending, or descending when DESC) and
@@ -219,6 +220,7 @@ __device__ __forceinline__ void stream_rows(const BandIn<T> (&bands)[NB > 0 ? NB
   using GD = Geom<double, 1, TR>;
   using GV = Geom<T, 1, VR>;
   static_assert(kWave * TR * W * (int)sizeof(T) <= GB::WORDS * 4, "an interleaved tile fits the band buffer");
+  static_assert(kWave * VR * (int)sizeof(T) <= GV::WORDS * 4, "an interleaved vector tile fits its buffer");
   __shared__ __attribute__((aligned(16))) uint32_t sb[NBUF][NB1][GB::WORDS];
   __shared__ __attribute__((aligned(16))) uint32_t sd[NBUF][MIXED ? NB1 : 1][MIXED ? GD::WORDS : 1];
   __shared__ __attribute__((aligned(16))) uint32_t sv[NBUF][NV1][NV > 0 ? GV::WORDS : 1];
@@ -232,10 +234,13 @@ __device__ __forceinline__ void stream_rows(const BandIn<T> (&bands)[NB > 0 ? NB
   // lane's rows together (pitch per lane); an interleaved band keeps the
   // block as loaded (64 records per row).
   int rbase[NBUF][NB1], dbase[NBUF][NB1], rstride[NB1];
-  int pv0[NV1], pv1[NV1];
+  int pv0[NV1], pv1[NV1], vstride[NV1];   // vector: lane's start (bytes) per buffer, row stride
   int64_t vb0 = 0, vb1 = 0;
 #pragma unroll
-  for (int vi = 0; vi < NV1; ++vi) pv0[vi] = pv1[vi] = 0;
+  for (int vi = 0; vi < NV1; ++vi) {
+    pv0[vi] = pv1[vi] = 0;
+    vstride[vi] = (NV > 0 && !MIXED && vecs[vi].il ? kWave : 1) * (int)sizeof(T);
+  }
 #pragma unroll
   for (int bi = 0; bi < NB1; ++bi) {
     rstride[bi] = (NB > 0 && bands[bi].il ? kWave * W : W) * (int)sizeof(T);
@@ -294,12 +299,21 @@ __device__ __forceinline__ void stream_rows(const BandIn<T> (&bands)[NB > 0 ? NB
       else vb0 = vb;
 #pragma unroll
       for (int vi = 0; vi < NV; ++vi) {
-        int64_t s0 = vb + vecs[vi].shift;
-        int c = vcnt;
-        if (s0 + c > n) c = (int)(n - s0 > 0 ? n - s0 : 0);
-        const T *src = (vecs[vi].p && c > 0) ? vecs[vi].p + s0 : nullptr;
         // buffer 1 of vector vi lies NV1 * GV::WORDS words past buffer 0
-        const int pv = lds_fill<T, 1, VR>(&sv[0][vi][0] + (v1 ? (NBUF - 1) * NV1 * GV::WORDS : 0), src, c, lane);
+        uint32_t *vdst = &sv[0][vi][0] + (v1 ? (NBUF - 1) * NV1 * GV::WORDS : 0);
+        int pv;
+        if (!MIXED && vecs[vi].il) {
+          const int rows = (int)(v_hi - v_lo);
+          if (vecs[vi].p && rows > 0)
+            il_fill(vdst, vecs[vi].p + (v_lo + vecs[vi].shift) * kWave, rows * kWave * (int)sizeof(T), lane);
+          pv = lane * (int)sizeof(T);
+        } else {
+          int64_t s0 = vb + vecs[vi].shift;
+          int c = vcnt;
+          if (s0 + c > n) c = (int)(n - s0 > 0 ? n - s0 : 0);
+          const T *src = (vecs[vi].p && c > 0) ? vecs[vi].p + s0 : nullptr;
+          pv = lane * lds_fill<T, 1, VR>(vdst, src, c, lane);
+        }
         if (v1) pv1[vi] = pv;
         else pv0[vi] = pv;
       }
@@ -336,9 +350,9 @@ __device__ __forceinline__ void stream_rows(const BandIn<T> (&bands)[NB > 0 ? NB
 #pragma unroll
         for (int vi = 0; vi < NV; ++vi) {
           // buffer 1 of vector vi lies NV1 * GV::WORDS words past buffer 0
-          const int voff = v1 ? (NBUF - 1) * NV1 * GV::WORDS * 4 + lane * pv1[vi] : lane * pv0[vi];
-          lds_cptr<char> vrow = (lds_cptr<char>)(lds_ptr_t)sv[0][vi] + voff;
-          val[vi] = (vecs[vi].p && j + vecs[vi].shift < n) ? (double)((lds_cptr<T>)vrow)[rv] : 0.0;
+          const int voff = v1 ? (NBUF - 1) * NV1 * GV::WORDS * 4 + pv1[vi] : pv0[vi];
+          lds_cptr<char> vrow = (lds_cptr<char>)(lds_ptr_t)sv[0][vi] + voff + rv * vstride[vi];
+          val[vi] = (vecs[vi].p && j + vecs[vi].shift < n) ? (double)*(lds_cptr<T>)vrow : 0.0;
         }
         body(j, rec, val);
       }

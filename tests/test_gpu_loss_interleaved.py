@@ -1,9 +1,10 @@
 """The loss unit with its intermediates kept in the workspace.
 
-bo_plan_gauss_loss with L, Sig and Lbar all NULL keeps the three bands in the
-plan's workspace, interleaved by chunk (row r of the chunk of lane l of a
-wavefront at record r * 64 + l of the wavefront's block), with a halo of the
-next chunk's first K + 1 records of Sigma for the Algorithm 4 pass.  The
+bo_plan_gauss_loss with L, Sig and Lbar all NULL keeps the three bands, z and
+a copy of ybar in the plan's workspace, interleaved by chunk (row r of the
+chunk of lane l of a wavefront at record r * 64 + l of the wavefront's block),
+with a halo of the next chunk's first K + 1 records of Sigma and ybar for the
+passes that read ahead.  The
 arithmetic is the same as with the caller's arrays, so every output (Qbar,
 ybar, z, the per-problem parts and info) must agree bit for bit; Sbar, which
 this mode writes from the subset-inverse pass itself, must equal
@@ -47,7 +48,7 @@ def packed_batch(ns, ks, seed):
     return Qs, ys, Ss
 
 
-def run_loss(bo, plan, Qs, ys, Ss, keep: bool):
+def run_loss(bo, plan, Qs, ys, Ss, keep: bool, with_z: bool = True):
     cat = lambda arrs: np.concatenate([a.ravel() for a in arrs]) if arrs else np.zeros(0)
     Qf, yf, Sf = cat(Qs), cat(ys), cat(Ss)
     E, N = Qf.size, yf.size
@@ -58,6 +59,8 @@ def run_loss(bo, plan, Qs, ys, Ss, keep: bool):
               info=torch.zeros(len(Qs), dtype=torch.int32, device="cuda"))
     if not keep:
         kw.update(L=nan(E), Sig=nan(E), Lbar=nan(E))
+    if not with_z:
+        del kw["z"]
     io = plan.io(**kw)
     plan.gauss_loss(0, io)
     torch.cuda.synchronize()
@@ -73,6 +76,8 @@ def same(a, b):
 def check_pair(plan, ns, ks, a, b):
     """a: caller arrays, b: kept in the workspace."""
     for nm in ("Qbar", "x", "z", "parts", "loss", "info"):
+        if nm not in b:
+            continue
         if nm in ("Qbar",):
             for p, (n, k) in enumerate(zip(ns, ks)):
                 o, sz = plan.boff[p], n * (k + 1)
@@ -109,6 +114,18 @@ def test_kept_intermediates_equal_caller_arrays(bo, ns, ks, tc):
     a = run_loss(bo, plan, Qs, ys, Ss, keep=False)
     b = run_loss(bo, plan, Qs, ys, Ss, keep=True)
     assert np.all(a["info"] == 0)
+    check_pair(plan, ns, ks, a, b)
+
+
+def test_kept_intermediates_without_z(bo):
+    """z is an intermediate of the loss: without a caller's vector it stays in
+    the workspace and every other output is unchanged."""
+    ns, ks = [700, 1, 33, 5000, 0, 257, 12000, 64, 3, 2500], [3, 0, 1, 5, 2, 11, 3, 12, 1, 5]
+    Qs, ys, Ss = packed_batch(ns, ks, 41)
+    plan = bo.Plan(ns, ks, target_chunks=600)
+    a = run_loss(bo, plan, Qs, ys, Ss, keep=False)
+    b = run_loss(bo, plan, Qs, ys, Ss, keep=True, with_z=False)
+    assert "z" not in b
     check_pair(plan, ns, ks, a, b)
 
 
