@@ -2,6 +2,9 @@
 
   python profsum.py stats KERNEL_STATS_CSV --cmd "..."
       per-kernel call counts and durations (rocprofv3 --kernel-trace --stats)
+  python profsum.py mfma COUNTERS_CSV --stats KERNEL_STATS_CSV --cmd "..." --cmd-stats "..."
+      MFMA flops, busy cycles and utilisation per kernel (rocprofv3 --pmc
+      SQ_INSTS_VALU_MFMA_MOPS_F32 SQ_VALU_MFMA_BUSY_CYCLES GRBM_GUI_ACTIVE)
   python profsum.py traffic --fetch CSV --write CSV \\
       --copy-fetch CSV --copy-write CSV --copy-bytes B --rows R --cmd "..."
       HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counters (KiB per
@@ -170,6 +173,41 @@ def traffic(args):
               f"{(fb + wb) / args.rows:8.1f}")
 
 
+def mfma(args):
+    """MFMA work and busy cycles per kernel slot from one rocprofv3 --pmc run
+    of SQ_INSTS_VALU_MFMA_MOPS_F32 SQ_VALU_MFMA_BUSY_CYCLES GRBM_GUI_ACTIVE,
+    with the average durations of a kernel-trace summary."""
+    mops = _counter_means(args.csv, "SQ_INSTS_VALU_MFMA_MOPS_F32")
+    busy = _counter_means(args.csv, "SQ_VALU_MFMA_BUSY_CYCLES")
+    gui = _counter_means(args.csv, "GRBM_GUI_ACTIVE")
+    dur = {}
+    for r in csv.DictReader(open(args.stats)):
+        dur[r["Name"]] = float(r["AverageNs"]) / 1e9
+    print("# MFMA use per dispatch from rocprofv3 --pmc SQ_INSTS_VALU_MFMA_MOPS_F32 SQ_VALU_MFMA_BUSY_CYCLES "
+          "GRBM_GUI_ACTIVE")
+    print(f"# command: {args.cmd}")
+    print(f"# durations: {args.cmd_stats}")
+    print(f"# FP32 MFMA flops = MOPS_F32 * 512 (executed, zeros of the dense blocks included);")
+    print(f"# util = MFMA busy cycles (summed over SIMDs) / (average kernel duration * {args.clock_ghz} GHz * "
+          f"{args.simds} SIMDs)")
+    print(f"# (GRBM_GUI_ACTIVE, shown for reference, spans the profiler's serialised dispatch, not the kernel alone);")
+    print(f"# TFLOP/s = flops / average kernel duration; peak FP32 MFMA {args.peak} TFLOP/s")
+    print(f"# {'slot':16s} {'GFLOP':>9s} {'busy_Mcyc':>10s} {'gui_Mcyc':>9s} {'util_%':>7s} {'avg_ms':>8s} {'TFLOP/s':>8s} "
+          f"{'of_peak':>7s}")
+    seen = set()
+    for k, (mv, n) in mops.items():
+        slot = slot_of(k)
+        if slot is None or (slot, k) in seen or k not in busy or k not in gui:
+            continue
+        seen.add((slot, k))
+        fl = mv * 512
+        d = dur.get(k)
+        util = 100.0 * busy[k][0] / (d * args.clock_ghz * 1e9 * args.simds) if d else float("nan")
+        tf = fl / d / 1e12 if d else float("nan")
+        print(f"mfma {slot:16s} {fl / 1e9:9.3f} {busy[k][0] / 1e6:10.2f} {gui[k][0] / 1e6:9.3f} {util:7.2f} "
+              f"{(d or float('nan')) * 1e3:8.3f} {tf:8.3f} {tf / args.peak:7.4f}")
+
+
 def read_traffic(path: str):
     """Parse a traffic summary: {slot: bytes per launch}, plus its source hash."""
     out, meta = {}, {}
@@ -203,8 +241,16 @@ def main(argv=None):
     t.add_argument("--cmd-fetch", default="")
     t.add_argument("--cmd-write", default="")
     t.add_argument("--sources", default="", help="comma-separated csrc/ files the measured kernels come from")
+    m = sub.add_parser("mfma")
+    m.add_argument("csv")
+    m.add_argument("--stats", required=True, help="kernel_stats.csv of a kernel-trace run of the same workload")
+    m.add_argument("--cmd", required=True)
+    m.add_argument("--cmd-stats", required=True)
+    m.add_argument("--simds", type=int, default=1024)
+    m.add_argument("--peak", type=float, default=157.3)
+    m.add_argument("--clock-ghz", type=float, default=2.4)
     a = ap.parse_args(argv)
-    (stats if a.cmd_name == "stats" else traffic)(a)
+    {"stats": stats, "traffic": traffic, "mfma": mfma}[a.cmd_name](a)
 
 
 if __name__ == "__main__":
