@@ -70,16 +70,14 @@ BO_HD void store_rec(T *__restrict__ band, double *__restrict__ diag, int64_t ld
   if (diag) diag[j] = r[0];
 }
 
-// A vector argument: element j at p[j * s] (s = 1 for a caller's vector; a
-// chunk-interleaved workspace vector has s = 64).
-template <typename T> struct VecP {
+// A vector argument: element j at p[j * S] (S = 1 for a caller's vector; a
+// chunk-interleaved workspace vector has S = 64).
+template <typename T, int S = 1> struct VecP {
   T *p = nullptr;
-  int64_t s = 1;
   BO_HD VecP() {}
   BO_HD VecP(T *q) : p(q) {}
-  BO_HD VecP(T *q, int64_t st) : p(q), s(st) {}
   BO_HD explicit operator bool() const { return p != nullptr; }
-  BO_HD T &operator[](int64_t j) const { return p[j * s]; }
+  BO_HD T &operator[](int64_t j) const { return p[j * S]; }
 };
 
 // A band argument as the kernels see it.

@@ -42,6 +42,10 @@ struct Sched {
   std::vector<int32_t> chunk_prob, group_prob;
   std::vector<KRange> ranges;
   int32_t nchunk = 0, ngroup = 0, nprob = 0, G = 64, Kmax = 0;
+  // From this bandwidth up, the chunk products of L are a pass of their own
+  // after the F1 replay instead of accumulated in it (the replay's state then
+  // fits in registers); above the compiled bandwidths: never.
+  int32_t kpc_sep = KMAX_SUPPORTED + 1;
   int64_t rows = 0;
   // interleaved intermediates (FP64 elements per array; the arrays follow
   // the workspace proper when a call keeps L, Sigma and Lbar there)
@@ -295,8 +299,12 @@ template <class BE> int seq_f1(BE &be, const Sched &s, Args A, int prec, bool wa
       B.lmap_out = nullptr;
     }
     if (r.K > KMAX_FUSED) B.lmap_out = nullptr;
+    const bool pc_pass = B.Pc && r.K >= s.kpc_sep;
+    if (pc_pass) B.Pc = nullptr;
     if (rep_y && B.lmap_out && !A.y && !A.z) B.y = rep_y;
     if (int e = be.step(ST_F1_REP, r.K, prec, B, r.c_cnt)) return e;
+    if (pc_pass)
+      if (int e = be.step(ST_PC, r.K, prec, A, r.c_cnt)) return e;
   }
   return 0;
 }

@@ -70,35 +70,39 @@ template <typename T> __device__ __forceinline__ T *il_vwave(const void *base, c
   return (T *)base + A.il_voff + w * (int64_t)A.il_rows * kBlock;
 }
 template <typename T>
-__device__ __forceinline__ VecP<T> il_vview(const void *base, const Args &A, int64_t w, int l, int64_t a) {
+__device__ __forceinline__ VecP<T, kBlock> il_vview(const void *base, const Args &A, int64_t w, int l, int64_t a) {
   const uint64_t p = (uint64_t)(il_vwave<T>(base, A, w) + l) - (uint64_t)(a * kBlock * (int64_t)sizeof(T));
-  return VecP<T>((T *)p, kBlock);
+  return VecP<T, kBlock>((T *)p);
 }
-template <typename T> __device__ __forceinline__ VecP<T> lane_vview(const void *base, const Args &A, const LaneChunk &C) {
+template <typename T>
+__device__ __forceinline__ VecP<T, kBlock> lane_vview(const void *base, const Args &A, const LaneChunk &C) {
   return il_vview<T>(base, A, blockIdx.x, threadIdx.x, C.a);
 }
 // The same view of the previous chunk of the lane's problem (its halo rows
 // follow its own rows).
-template <typename T> __device__ __forceinline__ VecP<T> prev_vview(const void *base, const Args &A, const LaneChunk &C) {
+template <typename T>
+__device__ __forceinline__ VecP<T, kBlock> prev_vview(const void *base, const Args &A, const LaneChunk &C) {
   const int l = threadIdx.x;
   return il_vview<T>(base, A, l > 0 ? (int64_t)blockIdx.x : (int64_t)blockIdx.x - 1, l > 0 ? l - 1 : kBlock - 1,
                      C.a - C.pd.clen);
 }
-template <typename T>
-__device__ __forceinline__ VecIn<T> vstaged(bool il, const void *base, const Args &A, const T *rm, bool on,
-                                            int shift = 0) {
-  if (il) return VecIn<T>{il_vwave<T>(base, A, blockIdx.x), shift, true};
-  return VecIn<T>{on ? rm : nullptr, shift, false};
+// A staged vector input: the wave's interleaved block, or the lane's values.
+template <bool IL, typename T>
+__device__ __forceinline__ VecIn<T> vstaged(const void *base, const Args &A, const T *rm, bool on, int shift = 0) {
+  if constexpr (IL) return VecIn<T>{il_vwave<T>(base, A, blockIdx.x), shift};
+  else return VecIn<T>{on ? rm : nullptr, shift};
 }
 template <typename T> __device__ __forceinline__ BandP<const T> const_view(BandP<T> b) {
   return BandP<const T>{b.p, b.diag, b.ld};
 }
 // A staged band input: the wave's interleaved block, or the lane's records.
-template <int K, typename T>
-__device__ __forceinline__ BandIn<T> staged(bool il, void *base, const Args &A, BandP<const T> b, bool on, int shift = 0) {
-  if (il) return BandIn<T>{il_wave<K, T>(base, A, blockIdx.x), nullptr, shift, true};
-  return BandIn<T>{on ? b.p : nullptr, on ? b.diag : nullptr, shift, false};
+template <bool IL, int K, typename T>
+__device__ __forceinline__ BandIn<T> staged(void *base, const Args &A, BandP<const T> b, bool on, int shift = 0) {
+  if constexpr (IL) return BandIn<T>{il_wave<K, T>(base, A, blockIdx.x), nullptr, shift};
+  else return BandIn<T>{on ? b.p : nullptr, on ? b.diag : nullptr, shift};
 }
+// Kernels with IL = true read and write L, S (Sigma), Lb, z (bx, zf) and the
+// copy of ybar (xil) interleaved (Args::il); FP64 only.
 
 // ------------------------------------------------------------------- F1
 // DIAG: the factored matrix is Q + diag(qdn / qdd[problem]); the addend is
@@ -122,9 +126,9 @@ __global__ void __launch_bounds__(kBlock) k_f1_sum(const Args A, int64_t count) 
   const T *y = cvec<T>(A.y, pd);
   const T *dn = DIAG ? cvec<T>(A.qdn, pd) : nullptr;
   const double ds = DIAG ? qdiag_scale(A, pd) : 0.0;
-  F1Map<K> m;
   F1SumStep<K, T> st;
-  if (on) st.begin(C.a, pd.n, Q, y, m, dn, ds);
+  double *mw = A.f1map + (int64_t)C.c * A.sw_f1map;   // the map is completed in place
+  if (on) st.begin_w(C.a, pd.n, Q, y, mw, dn, ds);
   BandIn<T> bands[1] = {{on ? Q.p : nullptr, on ? Q.diag : nullptr, 0}};
   VecIn<T> vecs[NV];
   vecs[0] = {on ? y : nullptr, 0};
@@ -139,13 +143,12 @@ __global__ void __launch_bounds__(kBlock) k_f1_sum(const Args A, int64_t count) 
                                       st.row(rec[0], val[0]);
                                     }
                                   });
-  if (on) {
-    st.end(m);
-    f1_store_map<K>(A.f1map + (int64_t)C.c * A.sw_f1map, m);
-  }
+  if (on) st.end_w(mw);
 }
 
-template <int K, typename T, bool DIAG>
+// PC: accumulates the chunk products (A.Pc); launched without it when A.Pc
+// is null.
+template <int K, typename T, bool DIAG, bool PC, bool IL>
 __global__ void __launch_bounds__(kBlock) k_f1_rep(const Args A, int64_t count) {
   constexpr int NV = DIAG ? 2 : 1;
   const LaneChunk C = lane_chunk(A, count);
@@ -160,13 +163,14 @@ __global__ void __launch_bounds__(kBlock) k_f1_rep(const Args A, int64_t count) 
     f1_load_state<K>(A.f1st + (int64_t)C.c * A.sw_f1st, s0);
   else
     f1_zero_state<K>(s0);
-  F1RepStep<K, T> st;
+  F1RepStep<K, T, PC, IL ? kBlock : 1> st;
   const bool fuse = K <= KMAX_FUSED && A.lmap_out && A.Pc;
-  const bool il = sizeof(T) == 8 && A.il != 0;
-  VecP<T> zout;
-  if (y) zout = il ? lane_vview<T>(A.z, A, C) : VecP<T>(vec<T>(A.z, pd));
-  st.begin(s0, il ? lane_view<K, T>(A.L, A, C) : band<T>(A.L, A.Ld, pd), zout, A.Pc != nullptr, fuse);
-  if (il && y && A.zcopy) st.z2 = VecP<T>(vec<T>(A.zcopy, pd));
+  if constexpr (IL) {
+    st.begin(s0, lane_view<K, T>(A.L, A, C), y ? lane_vview<T>(A.z, A, C) : VecP<T, kBlock>(), A.Pc != nullptr, fuse);
+    if (y && A.zcopy) st.z2 = VecP<T>(vec<T>(A.zcopy, pd));
+  } else {
+    st.begin(s0, band<T>(A.L, A.Ld, pd), y ? vec<T>(A.z, pd) : nullptr, A.Pc != nullptr, fuse);
+  }
   BandIn<T> bands[1] = {{on ? Q.p : nullptr, on ? Q.diag : nullptr, 0}};
   VecIn<T> vecs[NV];
   vecs[0] = {on ? y : nullptr, 0};
@@ -195,7 +199,7 @@ __global__ void __launch_bounds__(kBlock) k_f1_rep(const Args A, int64_t count) 
   }
 }
 
-template <int K, typename T>
+template <int K, typename T, bool IL>
 __global__ void __launch_bounds__(kBlock) k_pc(const Args A, int64_t count) {
   const LaneChunk C = lane_chunk(A, count);
   const ProbDesc &pd = C.pd;
@@ -203,9 +207,9 @@ __global__ void __launch_bounds__(kBlock) k_pc(const Args A, int64_t count) {
   BandP<const T> L = cband<T>(A.L, A.Ld, pd);
   PcStep<K> st;
   st.begin();
-  BandIn<T> bands[1] = {{on ? L.p : nullptr, on ? L.diag : nullptr, 0}};
+  BandIn<T> bands[1] = {staged<IL, K, T>(A.L, A, L, on)};
   VecIn<T> vecs[1] = {{nullptr, 0}};
-  stream_rows<K, T, 1, 0, false>(bands, vecs, on ? C.a : 0, on ? C.b : 0, pd.n, pd.ld,
+  stream_rows<K, T, 1, 0, false, IL ? 1u : 0u>(bands, vecs, on ? C.a : 0, on ? C.b : 0, pd.n, pd.ld,
                                  [&](int64_t, const double (&rec)[1][K + 1], const double (&)[1]) {
                                    st.row(rec[0]);
                                  });
@@ -266,7 +270,7 @@ __global__ void __launch_bounds__(kBlock) k_fs(const Args A, int64_t count) {
 
 // FUSE: the replay also accumulates the B1 pass's chunk maps (needs the
 // Sigmabar / S band as a second staged input).
-template <int K, typename T, bool REPLAY, bool FUSE>
+template <int K, typename T, bool REPLAY, bool FUSE, bool IL>
 __global__ void __launch_bounds__(kBlock) k_f2(const Args A, int64_t count) {
   const LaneChunk C = lane_chunk(A, count);
   const ProbDesc &pd = C.pd;
@@ -275,26 +279,28 @@ __global__ void __launch_bounds__(kBlock) k_f2(const Args A, int64_t count) {
   const T *bx = cvec<T>(A.bx, pd);
   LinMap<K> st;
   lin_in<K>(A, C, REPLAY, st);
-  F2Step<K, T, REPLAY> s;
-  const bool il = sizeof(T) == 8 && A.il != 0;
-  s.begin(st, il ? lane_view<K, T>(A.S, A, C) : band<T>(A.S, A.Sd, pd), vec<T>(A.x, pd), A.xscale,
+  F2Step<K, T, REPLAY, IL> s;
+  s.begin(st, IL ? lane_view<K, T>(A.S, A, C) : band<T>(A.S, A.Sd, pd), vec<T>(A.x, pd), A.xscale,
           A.S != nullptr, bx != nullptr, FUSE, A.sb_is_S != 0);
-  if (REPLAY && il && on && C.c > pd.chunk0) {
-    // rows a .. a+K are also the halo of the previous chunk of the problem
-    const int l = threadIdx.x;
-    s.set_halo(il_view<K, T>(A.S, A, l > 0 ? (int64_t)blockIdx.x : (int64_t)blockIdx.x - 1, l > 0 ? l - 1 : kBlock - 1,
-                             C.a - pd.clen),
-               C.a + K + 1);
+  if constexpr (IL && REPLAY) {
+    if (on && C.c > pd.chunk0) {
+      // rows a .. a+K are also the halo of the previous chunk of the problem
+      const int l = threadIdx.x;
+      s.set_halo(il_view<K, T>(A.S, A, l > 0 ? (int64_t)blockIdx.x : (int64_t)blockIdx.x - 1,
+                               l > 0 ? l - 1 : kBlock - 1, C.a - pd.clen),
+                 C.a + K + 1);
+    }
+    if (A.sbar_out) s.set_sym_out(band<T>(A.sbar_out, nullptr, pd));
+    if (A.xil && on)
+      s.set_x_copy(lane_vview<T>(A.xil, A, C), C.c > pd.chunk0 ? prev_vview<T>(A.xil, A, C) : VecP<T, kBlock>(),
+                   C.a + K + 1);
   }
-  if (REPLAY && il && A.sbar_out) s.set_sym_out(band<T>(A.sbar_out, nullptr, pd));
-  if (REPLAY && il && A.xil && on)
-    s.set_x_copy(lane_vview<T>(A.xil, A, C), C.c > pd.chunk0 ? prev_vview<T>(A.xil, A, C) : VecP<T>(), C.a + K + 1);
-  VecIn<T> vecs[1] = {vstaged<T>(il, A.bx, A, bx, on)};
+  VecIn<T> vecs[1] = {vstaged<IL>(A.bx, A, bx, on)};
   if constexpr (FUSE) {
     BandP<const T> Sb = cband<T>(A.Sb, A.Sbd, pd);
-    BandIn<T> bands[2] = {staged<K, T>(il, A.L, A, L, on),
+    BandIn<T> bands[2] = {staged<IL, K, T>(A.L, A, L, on),
                           {on ? Sb.p : nullptr, on ? Sb.diag : nullptr, 0}};
-    stream_rows<K, T, 2, 1, true>(bands, vecs, on ? C.a : 0, on ? C.b : 0, pd.n, pd.ld,
+    stream_rows<K, T, 2, 1, true, IL ? 1u : 0u, IL ? 1u : 0u>(bands, vecs, on ? C.a : 0, on ? C.b : 0, pd.n, pd.ld,
                                   [&](int64_t j, const double (&rec)[2][K + 1], const double (&val)[1]) {
                                     s.row(j, rec[0], val[0]);
                                     s.row_b1(rec[0], rec[1]);
@@ -305,8 +311,8 @@ __global__ void __launch_bounds__(kBlock) k_f2(const Args A, int64_t count) {
       lin_store<K>(A.lmap_out + (int64_t)C.c * A.sw_lin, m);
     }
   } else {
-    BandIn<T> bands[1] = {staged<K, T>(il, A.L, A, L, on)};
-    stream_rows<K, T, 1, 1, true>(bands, vecs, on ? C.a : 0, on ? C.b : 0, pd.n, pd.ld,
+    BandIn<T> bands[1] = {staged<IL, K, T>(A.L, A, L, on)};
+    stream_rows<K, T, 1, 1, true, IL ? 1u : 0u, IL ? 1u : 0u>(bands, vecs, on ? C.a : 0, on ? C.b : 0, pd.n, pd.ld,
                                   [&](int64_t j, const double (&rec)[1][K + 1], const double (&val)[1]) {
                                     s.row(j, rec[0], val[0]);
                                   });
@@ -319,7 +325,7 @@ __global__ void __launch_bounds__(kBlock) k_f2(const Args A, int64_t count) {
 
 // FUSE: the replay also accumulates the B2 pass's chunk maps (needs ybar,
 // staged K+1 rows ahead, and z).
-template <int K, typename T, bool REPLAY, bool FUSE>
+template <int K, typename T, bool REPLAY, bool FUSE, bool IL>
 __global__ void __launch_bounds__(kBlock) k_b1(const Args A, int64_t count) {
   const LaneChunk C = lane_chunk(A, count);
   const ProbDesc &pd = C.pd;
@@ -330,19 +336,22 @@ __global__ void __launch_bounds__(kBlock) k_b1(const Args A, int64_t count) {
   LinMap<K> st;
   lin_in<K>(A, C, REPLAY, st);
   B1Step<K, T, REPLAY, FUSE> s;
-  const bool il = sizeof(T) == 8 && A.il != 0;
   if (on)
-    s.begin(st, C.a, pd.n, il ? const_view(lane_view<K, T>(A.S, A, C)) : Sig, A.sb_is_S != 0,
-            il ? lane_view<K, T>(A.Lb, A, C) : band<T>(A.Lb, A.Lbd, pd), A.accumulate != 0, A.gl1);
+    s.begin(st, C.a, pd.n, IL ? const_view(lane_view<K, T>(A.S, A, C)) : Sig, A.sb_is_S != 0,
+            IL ? lane_view<K, T>(A.Lb, A, C) : band<T>(A.Lb, A.Lbd, pd), A.accumulate != 0, A.gl1);
   if constexpr (REPLAY) {
-    BandIn<T> bands[3] = {staged<K, T>(il, A.L, A, L, on),
+    BandIn<T> bands[3] = {staged<IL, K, T>(A.L, A, L, on),
                           {on ? Sb.p : nullptr, on ? Sb.diag : nullptr, 0},
-                          staged<K, T>(il, A.S, A, Sig, on, K + 1)};
+                          staged<IL, K, T>(A.S, A, Sig, on, K + 1)};
     if constexpr (FUSE) {
       const T *yb = cvec<T>(A.yb, pd);
-      if (on) s.begin_b2(C.a, pd.n, il ? lane_vview<const T>(A.xil, A, C) : VecP<const T>(yb), A.gl);
-      VecIn<T> vecs[2] = {vstaged<T>(il, A.xil, A, yb, on, K + 1), vstaged<T>(il, A.zf, A, cvec<T>(A.zf, pd), on)};
-      stream_rows<K, T, 3, 2, false>(bands, vecs, on ? C.a : 0, on ? C.b : 0, pd.n, pd.ld,
+      if constexpr (IL) {
+        if (on) s.begin_b2(C.a, pd.n, lane_vview<const T>(A.xil, A, C), A.gl);
+      } else {
+        if (on) s.begin_b2(C.a, pd.n, yb, A.gl);
+      }
+      VecIn<T> vecs[2] = {vstaged<IL>(A.xil, A, yb, on, K + 1), vstaged<IL>(A.zf, A, cvec<T>(A.zf, pd), on)};
+      stream_rows<K, T, 3, 2, false, IL ? 5u : 0u, IL ? 3u : 0u>(bands, vecs, on ? C.a : 0, on ? C.b : 0, pd.n, pd.ld,
                                      [&](int64_t j, const double (&rec)[3][K + 1], const double (&val)[2]) {
                                        s.row(j, pd.n, rec[0], rec[1], rec[2], val[1], val[0]);
                                      });
@@ -353,17 +362,17 @@ __global__ void __launch_bounds__(kBlock) k_b1(const Args A, int64_t count) {
       }
     } else {
       VecIn<T> vecs[1] = {{nullptr, 0}};
-      stream_rows<K, T, 3, 0, false>(bands, vecs, on ? C.a : 0, on ? C.b : 0, pd.n, pd.ld,
+      stream_rows<K, T, 3, 0, false, IL ? 5u : 0u>(bands, vecs, on ? C.a : 0, on ? C.b : 0, pd.n, pd.ld,
                                      [&](int64_t j, const double (&rec)[3][K + 1], const double (&)[1]) {
                                        s.row(j, pd.n, rec[0], rec[1], rec[2]);
                                      });
     }
     if (on) A.part[4 * (int64_t)C.c + 2] = s.tr;
   } else {
-    BandIn<T> bands[2] = {staged<K, T>(il, A.L, A, L, on),
+    BandIn<T> bands[2] = {staged<IL, K, T>(A.L, A, L, on),
                           {on ? Sb.p : nullptr, on ? Sb.diag : nullptr, 0}};
     VecIn<T> vecs[1] = {{nullptr, 0}};
-    stream_rows<K, T, 2, 0, false>(bands, vecs, on ? C.a : 0, on ? C.b : 0, pd.n, pd.ld,
+    stream_rows<K, T, 2, 0, false, IL ? 1u : 0u>(bands, vecs, on ? C.a : 0, on ? C.b : 0, pd.n, pd.ld,
                                    [&](int64_t j, const double (&rec)[2][K + 1], const double (&)[1]) {
                                      s.row(j, pd.n, rec[0], rec[1], rec[1]);
                                    });
@@ -377,7 +386,7 @@ __global__ void __launch_bounds__(kBlock) k_b1(const Args A, int64_t count) {
 // WITH_LB: an incoming Lbar band is staged next to L.  Without one (the
 // whitened sample's reverse mode) only L is staged, so its tiles hold twice
 // the rows.
-template <int K, typename T, bool REPLAY, bool WITH_LB>
+template <int K, typename T, bool REPLAY, bool WITH_LB, bool IL>
 __global__ void __launch_bounds__(kBlock) k_b2(const Args A, int64_t count) {
   constexpr int NB = WITH_LB ? 2 : 1;
   const LaneChunk C = lane_chunk(A, count);
@@ -390,15 +399,14 @@ __global__ void __launch_bounds__(kBlock) k_b2(const Args A, int64_t count) {
   LinMap<K> st;
   lin_in<K>(A, C, REPLAY, st);
   B2Step<K, T, REPLAY> s;
-  const bool il = sizeof(T) == 8 && A.il != 0;
-  VecP<const T> ybv;
-  if (on && yb) ybv = il ? lane_vview<const T>(A.xil, A, C) : VecP<const T>(yb);
-  s.begin(st, C.b, pd.n, ybv, A.gl, band<T>(A.Qb, A.Qbd, pd));
+  if constexpr (IL) s.begin_v(st, C.b, pd.n, on ? lane_vview<const T>(A.xil, A, C) : VecP<const T, kBlock>(), A.gl,
+                              band<T>(A.Qb, A.Qbd, pd));
+  else s.begin(st, C.b, pd.n, on ? yb : nullptr, A.gl, band<T>(A.Qb, A.Qbd, pd));
   BandIn<T> bands[NB];
-  bands[0] = staged<K, T>(il, A.L, A, L, on);
-  if constexpr (WITH_LB) bands[NB - 1] = staged<K, T>(il, A.Lb, A, Lb, on);
-  VecIn<T> vecs[2] = {vstaged<T>(il && yb, A.xil, A, yb, on), vstaged<T>(il && zf, A.zf, A, zf, on)};
-  stream_rows<K, T, NB, 2, true>(bands, vecs, on ? C.a : 0, on ? C.b : 0, pd.n, pd.ld,
+  bands[0] = staged<IL, K, T>(A.L, A, L, on);
+  if constexpr (WITH_LB) bands[NB - 1] = staged<IL, K, T>(A.Lb, A, Lb, on);
+  VecIn<T> vecs[2] = {vstaged<IL>(A.xil, A, yb, on), vstaged<IL>(A.zf, A, zf, on)};
+  stream_rows<K, T, NB, 2, true, IL ? (WITH_LB ? 3u : 1u) : 0u, IL ? 3u : 0u>(bands, vecs, on ? C.a : 0, on ? C.b : 0, pd.n, pd.ld,
                                  [&](int64_t j, const double (&rec)[NB][K + 1], const double (&val)[2]) {
                                    if constexpr (WITH_LB) {
                                      s.row(j, pd.n, rec[0], rec[NB - 1], val[0], val[1]);
@@ -614,6 +622,83 @@ template <typename T> struct Launch {
 
 inline int hip_ok() { return hipGetLastError() == hipSuccess ? 0 : -2; }
 
+// The LDS-tiled kernels of one step; IL: the variants that keep L, Sigma,
+// Lbar, z and the copy of ybar interleaved (Args::il, FP64).
+template <typename T, bool IL>
+int run_tiled(int step, const Args &a, int64_t count, hipStream_t s, dim3 grid, dim3 block) {
+  constexpr int K = BO_K;
+  switch (step) {
+    case ST_F1_SUM:
+      if (a.qdn)
+        hipLaunchKernelGGL((k_f1_sum<K, T, true>), grid, block, 0, s, a, count);
+      else
+        hipLaunchKernelGGL((k_f1_sum<K, T, false>), grid, block, 0, s, a, count);
+      break;
+    case ST_F1_REP:
+      if (a.qdn) {
+        if constexpr (IL) return -4;   // kept intermediates come with no diagonal addend
+        else if (a.Pc) hipLaunchKernelGGL((k_f1_rep<K, T, true, true, false>), grid, block, 0, s, a, count);
+        else hipLaunchKernelGGL((k_f1_rep<K, T, true, false, false>), grid, block, 0, s, a, count);
+      } else {
+        if (a.Pc) hipLaunchKernelGGL((k_f1_rep<K, T, false, true, IL>), grid, block, 0, s, a, count);
+        else hipLaunchKernelGGL((k_f1_rep<K, T, false, false, IL>), grid, block, 0, s, a, count);
+      }
+      break;
+    case ST_PC: hipLaunchKernelGGL((k_pc<K, T, IL>), grid, block, 0, s, a, count); break;
+    case ST_FS_SUM:
+      if constexpr (IL) return -4;
+      else hipLaunchKernelGGL((k_fs<K, T, false, false>), grid, block, 0, s, a, count);
+      break;
+    case ST_FS_REP:
+      if constexpr (IL) {
+        return -4;
+      } else {
+        if constexpr (K <= KMAX_FUSED)
+          if (a.lmap_out) {
+            hipLaunchKernelGGL((k_fs<K, T, true, true>), grid, block, 0, s, a, count);
+            break;
+          }
+        hipLaunchKernelGGL((k_fs<K, T, true, false>), grid, block, 0, s, a, count);
+      }
+      break;
+    case ST_F2_SUM: hipLaunchKernelGGL((k_f2<K, T, false, false, IL>), grid, block, 0, s, a, count); break;
+    case ST_F2_REP:
+      if constexpr (K <= KMAX_FUSED)
+        if (a.lmap_out && a.Sb) {
+          hipLaunchKernelGGL((k_f2<K, T, true, true, IL>), grid, block, 0, s, a, count);
+          break;
+        }
+      hipLaunchKernelGGL((k_f2<K, T, true, false, IL>), grid, block, 0, s, a, count);
+      break;
+    case ST_B1_SUM: hipLaunchKernelGGL((k_b1<K, T, false, false, IL>), grid, block, 0, s, a, count); break;
+    case ST_B1_REP:
+      if constexpr (K <= KMAX_FUSED)
+        if (a.lmap_out) {
+          hipLaunchKernelGGL((k_b1<K, T, true, true, IL>), grid, block, 0, s, a, count);
+          break;
+        }
+      hipLaunchKernelGGL((k_b1<K, T, true, false, IL>), grid, block, 0, s, a, count);
+      break;
+    case ST_B2_SUM:
+      if (a.Lb)
+        hipLaunchKernelGGL((k_b2<K, T, false, true, IL>), grid, block, 0, s, a, count);
+      else
+        hipLaunchKernelGGL((k_b2<K, T, false, false, IL>), grid, block, 0, s, a, count);
+      break;
+    case ST_B2_REP:
+      if (a.Lb)
+        hipLaunchKernelGGL((k_b2<K, T, true, true, IL>), grid, block, 0, s, a, count);
+      else
+        hipLaunchKernelGGL((k_b2<K, T, true, false, IL>), grid, block, 0, s, a, count);
+      break;
+    default: {   // the serial scan items (they read no band or vector)
+      Launch<T> l{a, count, s};
+      return with_item<K, T>(step, l);
+    }
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
 template <typename T> int run_step(int step, const Args &a, int64_t count, hipStream_t s) {
   if (count <= 0) return 0;
   const dim3 grid((unsigned)((count + kBlock - 1) / kBlock)), block(kBlock);
@@ -646,65 +731,9 @@ template <typename T> int run_step(int step, const Args &a, int64_t count, hipSt
     Launch<T> l{a, count, s};
     return with_item<K, T>(step, l);
   }
-  switch (step) {
-    case ST_F1_SUM:
-      if (a.qdn)
-        hipLaunchKernelGGL((k_f1_sum<K, T, true>), grid, block, 0, s, a, count);
-      else
-        hipLaunchKernelGGL((k_f1_sum<K, T, false>), grid, block, 0, s, a, count);
-      break;
-    case ST_F1_REP:
-      if (a.qdn)
-        hipLaunchKernelGGL((k_f1_rep<K, T, true>), grid, block, 0, s, a, count);
-      else
-        hipLaunchKernelGGL((k_f1_rep<K, T, false>), grid, block, 0, s, a, count);
-      break;
-    case ST_PC: hipLaunchKernelGGL((k_pc<K, T>), grid, block, 0, s, a, count); break;
-    case ST_FS_SUM: hipLaunchKernelGGL((k_fs<K, T, false, false>), grid, block, 0, s, a, count); break;
-    case ST_FS_REP:
-      if constexpr (K <= KMAX_FUSED)
-        if (a.lmap_out) {
-          hipLaunchKernelGGL((k_fs<K, T, true, true>), grid, block, 0, s, a, count);
-          break;
-        }
-      hipLaunchKernelGGL((k_fs<K, T, true, false>), grid, block, 0, s, a, count);
-      break;
-    case ST_F2_SUM: hipLaunchKernelGGL((k_f2<K, T, false, false>), grid, block, 0, s, a, count); break;
-    case ST_F2_REP:
-      if constexpr (K <= KMAX_FUSED)
-        if (a.lmap_out && a.Sb) {
-          hipLaunchKernelGGL((k_f2<K, T, true, true>), grid, block, 0, s, a, count);
-          break;
-        }
-      hipLaunchKernelGGL((k_f2<K, T, true, false>), grid, block, 0, s, a, count);
-      break;
-    case ST_B1_SUM: hipLaunchKernelGGL((k_b1<K, T, false, false>), grid, block, 0, s, a, count); break;
-    case ST_B1_REP:
-      if constexpr (K <= KMAX_FUSED)
-        if (a.lmap_out) {
-          hipLaunchKernelGGL((k_b1<K, T, true, true>), grid, block, 0, s, a, count);
-          break;
-        }
-      hipLaunchKernelGGL((k_b1<K, T, true, false>), grid, block, 0, s, a, count);
-      break;
-    case ST_B2_SUM:
-      if (a.Lb)
-        hipLaunchKernelGGL((k_b2<K, T, false, true>), grid, block, 0, s, a, count);
-      else
-        hipLaunchKernelGGL((k_b2<K, T, false, false>), grid, block, 0, s, a, count);
-      break;
-    case ST_B2_REP:
-      if (a.Lb)
-        hipLaunchKernelGGL((k_b2<K, T, true, true>), grid, block, 0, s, a, count);
-      else
-        hipLaunchKernelGGL((k_b2<K, T, true, false>), grid, block, 0, s, a, count);
-      break;
-    default: {
-      Launch<T> l{a, count, s};
-      return with_item<K, T>(step, l);
-    }
-  }
-  return hipGetLastError() == hipSuccess ? 0 : -2;
+  if constexpr (sizeof(T) == 8)
+    if (a.il) return run_tiled<T, true>(step, a, count, s, grid, block);
+  return run_tiled<T, false>(step, a, count, s, grid, block);
 }
 
 }  // namespace

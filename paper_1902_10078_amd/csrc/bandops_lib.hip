@@ -253,6 +253,16 @@ const int32_t *env_kscale() {
   }();
   return any ? v : nullptr;
 }
+// First bandwidth whose chunk products get a pass of their own after the F1
+// replay (BANDOPS_PC_SEPARATE, a switch for schedule experiments; 13: never).
+int32_t pc_separate_from() {
+  static int32_t v = [] {
+    const char *e = std::getenv("BANDOPS_PC_SEPARATE");
+    int t = e ? std::atoi(e) : 11;
+    return (int32_t)(t >= 1 ? t : 11);
+  }();
+  return v;
+}
 bool fuse_summaries() {
   static bool v = [] {
     const char *e = std::getenv("BANDOPS_FUSE");
@@ -822,6 +832,7 @@ extern "C" bo_status bo_plan_create(const bo_problem *probs, int32_t nprob, int6
     delete pl;
     return fail(BO_EINVAL, "bo_plan_create: bad problem table");
   }
+  pl->s.kpc_sep = pc_separate_from();
   size_t tb = pl->s.table_blob.size();
   if (hipHostMalloc(&pl->pinned, tb ? tb : 1, hipHostMallocDefault) != hipSuccess) {
     delete pl;

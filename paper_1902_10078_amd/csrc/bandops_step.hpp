@@ -90,21 +90,69 @@ template <int K, typename T> struct F1SumStep {
       m.d[p] = g[p];
     }
   }
+
+  // The same with the map in memory (the layout of f1_store_map): begin_w
+  // writes A = Q_FF and r = y_F there at once, so that they are not held
+  // across the rows; end_w completes the map in place.
+  BO_HD void begin_w(int64_t a, int64_t n, BandP<const T> Q, const T *y, double *w, const T *dn = nullptr,
+                     double ds = 0.0) {
+    constexpr int KK = K1 * K1;
+#pragma unroll
+    for (int i = 0; i < NS; ++i) C[i] = Z[i] = 0.0;
+#pragma unroll
+    for (int p = 0; p < K1; ++p) {
+      g[p] = e[p] = 0.0;
+#pragma unroll
+      for (int f = 0; f < K1; ++f) X[p][f] = 0.0;
+    }
+#pragma unroll
+    for (int f = 0; f < K; ++f) {
+      double rec[K + 1];
+      load_rec<K, T>(Q.p, Q.diag, Q.ld, a + f, n, rec);
+      if (dn) rec[0] += (double)dn[a + f] * ds;
+#pragma unroll
+      for (int p = f; p < K; ++p) w[p * K1 + f] = w[f * K1 + p] = rec[p - f];
+#pragma unroll
+      for (int p = 0; p <= f; ++p) X[p][f] = rec[K + p - f];   // Q[a+K+p, a+f]
+      w[3 * KK + f] = y ? (double)y[a + f] : 0.0;
+    }
+  }
+
+  BO_HD void end_w(double *w) const {
+    constexpr int KK = K1 * K1;
+#pragma unroll
+    for (int p = 0; p < K1; ++p) {
+#pragma unroll
+      for (int f = 0; f < K1; ++f) {
+        const bool in = p < K && f < K;
+        w[p * K1 + f] = in ? w[p * K1 + f] - Z[six(p, f)] : 0.0;
+        w[KK + p * K1 + f] = in ? -X[p][f] : 0.0;
+        w[2 * KK + p * K1 + f] = in ? C[six(p, f)] : 0.0;
+      }
+      w[3 * KK + p] = p < K ? w[3 * KK + p] - e[p] : 0.0;
+      w[3 * KK + K1 + p] = p < K ? g[p] : 0.0;
+    }
+  }
 };
 
 // ============================================================= F1 replay
 // Rows of the chunk from the exact entering state (C, g): writes L (and z),
 // sums log L_jj and z_j^2, records the first non-positive pivot, and (when
 // asked) accumulates the chunk product P = Kt_{b-1} ... Kt_a.
-template <int K, typename T> struct F1RepStep {
+// PC: compiled with the chunk-product accumulation (without it the replay
+// keeps only C and g in registers; the product then comes from PcStep).
+// ZS: the stride of z (64 when it is interleaved in a workspace; then a
+// caller's copy z2 may be written too).
+template <int K, typename T, bool PC = true, int ZS = 1> struct F1RepStep {
   static constexpr int K1 = Dim<K>::K1, NS = Dim<K>::NS;
-  double C[NS], g[K1], Pm[K1][K1];
+  double C[NS], g[K1], Pm[PC ? K1 : 1][PC ? K1 : 1];
   double M2[NS], v2[K1];   // fused summary of the F2 pass (see row())
   double ls, qs;
   int64_t fail;
   bool want_P, want_f2;
   BandP<T> L;
-  VecP<T> z, z2;   // z, and an optional second copy of it
+  VecP<T, ZS> z;
+  VecP<T> z2;   // optional second copy of z (ZS = 64 only)
 
   // wantF2 (needs wantP): also accumulate the chunk map of the descending F2
   // pass, M = sum_j R_j^T c_j e0 e0^T R_j and v = sum_j R_j^T e0 b_j / L_jj
@@ -112,12 +160,12 @@ template <int K, typename T> struct F1RepStep {
   // summed in ascending order.  The back solve's right-hand side b is the
   // forward solve's z when the replay writes z, else the replay's y input
   // itself (a back solve L^{-T} y with no forward solve).
-  BO_HD void begin(const F1State<K> &st, BandP<T> L_, VecP<T> z_, bool wantP, bool wantF2 = false) {
+  BO_HD void begin(const F1State<K> &st, BandP<T> L_, VecP<T, ZS> z_, bool wantP, bool wantF2 = false) {
     L = L_;
     z = z_;
     z2 = VecP<T>();
-    want_P = wantP;
-    want_f2 = K <= KMAX_FUSED && wantP && wantF2;
+    want_P = PC && wantP;
+    want_f2 = K <= KMAX_FUSED && want_P && wantF2;
     ls = qs = 0.0;
     fail = -1;
 #pragma unroll
@@ -126,8 +174,10 @@ template <int K, typename T> struct F1RepStep {
       v2[p] = 0.0;
 #pragma unroll
       for (int q = 0; q <= p; ++q) C[six(p, q)] = st.C[p][q];
+      if constexpr (PC) {
 #pragma unroll
-      for (int q = 0; q < K1; ++q) Pm[p][q] = (p == q) ? 1.0 : 0.0;
+        for (int q = 0; q < K1; ++q) Pm[p][q] = (p == q) ? 1.0 : 0.0;
+      }
     }
 #pragma unroll
     for (int i = 0; i < NS; ++i) M2[i] = 0.0;
@@ -163,7 +213,8 @@ template <int K, typename T> struct F1RepStep {
     if (z) {
       zj = (yj - (K > 0 ? g[0] : 0.0)) * inv;
       z[j] = (T)zj;
-      if (z2) z2[j] = (T)zj;
+      if constexpr (ZS != 1)
+        if (z2) z2[j] = (T)zj;
       qs += zj * zj;
     }
 #pragma unroll
@@ -173,7 +224,7 @@ template <int K, typename T> struct F1RepStep {
 #pragma unroll
       for (int h = 0; h <= p; ++h)
         C[six(p, h)] = ((p + 1 < K) ? C[six(p + 1, h + 1)] : 0.0) + l[p] * l[h];
-    if (want_P) {
+    if (PC && want_P) {
       if (K <= KMAX_FUSED && want_f2) {
         // row 0 of R_j = Pm before this row's update
         const double cj = inv * inv, xj = (z ? zj : yj) * inv;
@@ -195,11 +246,13 @@ template <int K, typename T> struct F1RepStep {
   }
 
   BO_HD void end(double *P) const {
-    if (!P) return;
+    if constexpr (PC) {
+      if (!P) return;
 #pragma unroll
-    for (int p = 0; p < K1; ++p)
+      for (int p = 0; p < K1; ++p)
 #pragma unroll
-      for (int q = 0; q < K1; ++q) P[p * K1 + q] = Pm[p][q];
+        for (int q = 0; q < K1; ++q) P[p * K1 + q] = Pm[p][q];
+    }
   }
 };
 
@@ -268,7 +321,10 @@ template <int K, typename T, bool REPLAY> struct FsStep {
 //   Sigma_jj = c_j - u_j^T v
 //   W' = [[Sigma_jj, v'^T], [v', W[0:K-1,0:K-1]]]   (= Kt^T W Kt + c e0 e0^T)
 //   x_j = b_j / L_jj - u_j^T xw,   xw' = (x_j, xw[0:K-1])
-template <int K, typename T, bool REPLAY> struct F2Step {
+// IL: Sigma is kept interleaved in a workspace; the replay then also writes
+// the halo of the previous chunk, optionally (Sigma_jj, 2 Sigma_ij) to a
+// caller's band and an interleaved copy of x with its halo.
+template <int K, typename T, bool REPLAY, bool IL = false> struct F2Step {
   static constexpr int K1 = Dim<K>::K1, NS = Dim<K>::NS;
   double W[NS], xw[K1];
   double Rb[K1][K1], Mb[NS];   // fused summary of the B1 pass (see row_b1())
@@ -285,14 +341,14 @@ template <int K, typename T, bool REPLAY> struct F2Step {
   // sensitivity of tr(Q^{-1} S) with respect to S's stored entries).
   BandP<T> So{nullptr, nullptr, 0};
   // Optional second copy of x (x2) with its own halo view (xh, rows j < jh).
-  VecP<T> x2, xh;
+  VecP<T, 64> x2, xh;
 
   BO_HD void set_halo(BandP<T> h, int64_t j_end) {
     Sh = h;
     jh = j_end;
   }
   BO_HD void set_sym_out(BandP<T> o) { So = o; }
-  BO_HD void set_x_copy(VecP<T> c, VecP<T> h, int64_t j_end) {
+  BO_HD void set_x_copy(VecP<T, 64> c, VecP<T, 64> h, int64_t j_end) {
     x2 = c;
     xh = h;
     jh = j_end;
@@ -385,13 +441,15 @@ template <int K, typename T, bool REPLAY> struct F2Step {
 #pragma unroll
         for (int p = 0; p < K; ++p) o[p + 1] = v[p];
         store_rec<K, T>(S.p, S.diag, S.ld, j, o);
-        if (Sh.p && j < jh) store_rec<K, T>(Sh.p, Sh.diag, Sh.ld, j, o);
-        if (So.p) {
-          double o2[K + 1];
-          o2[0] = o[0];
+        if constexpr (IL) {
+          if (Sh.p && j < jh) store_rec<K, T>(Sh.p, Sh.diag, Sh.ld, j, o);
+          if (So.p) {
+            double o2[K + 1];
+            o2[0] = o[0];
 #pragma unroll
-          for (int p = 1; p <= K; ++p) o2[p] = 2.0 * o[p];
-          store_rec<K, T>(So.p, So.diag, So.ld, j, o2);
+            for (int p = 1; p <= K; ++p) o2[p] = 2.0 * o[p];
+            store_rec<K, T>(So.p, So.diag, So.ld, j, o2);
+          }
         }
       }
 #pragma unroll
@@ -409,9 +467,11 @@ template <int K, typename T, bool REPLAY> struct F2Step {
       if (REPLAY) {
         const T xv = (T)(xscale * xj);
         x[j] = xv;
-        if (x2) {
-          x2[j] = xv;
-          if (xh && j < jh) xh[j] = xv;
+        if constexpr (IL) {
+          if (x2) {
+            x2[j] = xv;
+            if (xh && j < jh) xh[j] = xv;
+          }
         }
       }
 #pragma unroll
@@ -443,9 +503,9 @@ template <int K> struct B2MapAcc {
   double Rf[K1][K1], Mf[NS], yw[K + 1], glf;
 
   template <typename T> BO_HD void begin(int64_t a, int64_t n, const T *ybar, double gl) {
-    begin_v<T>(a, n, VecP<const T>(ybar), gl);
+    begin_v<T, 1>(a, n, VecP<const T>(ybar), gl);
   }
-  template <typename T> BO_HD void begin_v(int64_t a, int64_t n, VecP<const T> ybar, double gl) {
+  template <typename T, int S> BO_HD void begin_v(int64_t a, int64_t n, VecP<const T, S> ybar, double gl) {
     glf = gl;
 #pragma unroll
     for (int p = 0; p < K1; ++p)
@@ -538,10 +598,11 @@ template <int K, typename T, bool REPLAY, bool B2MAP = true> struct B1Step {
   bool want_b2;
   B2MapAcc<K> b2;
 
-  BO_HD void begin_b2(int64_t a, int64_t n, VecP<const T> ybar, double gl) {
+  template <int S> BO_HD void begin_b2(int64_t a, int64_t n, VecP<const T, S> ybar, double gl) {
     want_b2 = true;
-    b2.template begin_v<T>(a, n, ybar, gl);
+    b2.template begin_v<T, S>(a, n, ybar, gl);
   }
+  BO_HD void begin_b2(int64_t a, int64_t n, const T *ybar, double gl) { begin_b2<1>(a, n, VecP<const T>(ybar), gl); }
 
   BO_HD void end_b2(LinMap<K> &m) const { b2.end(m); }
 
@@ -665,8 +726,12 @@ template <int K, typename T, bool REPLAY> struct B2Step {
   BandP<T> Qb;
 
   // ybar[b .. b+K-1] is read directly (once per chunk).
-  BO_HD void begin(const LinMap<K> &st, int64_t b, int64_t n, VecP<const T> ybar, double gl_,
-                   BandP<T> Qb_) {
+  BO_HD void begin(const LinMap<K> &st, int64_t b, int64_t n, const T *ybar, double gl_, BandP<T> Qb_) {
+    begin_v<1>(st, b, n, VecP<const T>(ybar), gl_, Qb_);
+  }
+  template <int S>
+  BO_HD void begin_v(const LinMap<K> &st, int64_t b, int64_t n, VecP<const T, S> ybar, double gl_,
+                     BandP<T> Qb_) {
     gl = gl_;
     with_y = ybar.p != nullptr;
     Qb = Qb_;

@@ -173,38 +173,40 @@ __device__ __forceinline__ void il_fill(uint32_t *dst, const void *src, int byte
 // in the mixed format, its FP64 diagonal.  `shift` offsets the staged rows
 // from the processed rows (the B1 replay reads Sigma K+1 rows ahead).
 //
-// An interleaved band (il) holds the chunks of one wavefront row by row: row r
-// of the chunk of lane l (global row lo_l + r) is record r * 64 + l of the
-// array that p points at, so one tile of every lane is one contiguous block.
-// Interleaved bands are FP64 only (no diag).
+// An interleaved band (a bit of stream_rows' ILB mask) holds the chunks of one
+// wavefront row by row: row r of the chunk of lane l (global row lo_l + r) is
+// record r * 64 + l of the array that p points at, so one tile of every lane
+// is one contiguous block.  Interleaved bands are FP64 only (no diag).
 template <typename T> struct BandIn {
   const T *p;
   const double *diag;
   int shift;
-  bool il = false;
 };
 template <typename T> struct VecIn {
   const T *p;
   int shift;   // staged rows = processed rows + shift (values past n read 0)
-  bool il = false;   // interleaved like a band (element r * 64 + l), FP64 only
 };
 
 // Streams rows [lo, hi) of each lane (ascending, or descending when DESC) and
 // calls body(j, rec, val) per row with rec[b] = record j(+shift_b) of band b
 // (slots past the matrix end zeroed) and val[v] = vector v at row j.
 //
-// Tiles are laid out in chunk-relative rows r = j - lo, common to the wave:
-// ascending, tile i covers r in [i TR, (i+1) TR); descending, tile i covers
-// r in [top - (i+1) TR, top - i TR) with top the wave's longest chunk, so a
-// lane with a shorter chunk starts later.  Each lane takes the rows of a tile
-// that lie in [0, hi - lo).
+// Tiles are laid out in chunk-relative rows r = j - lo: ascending, tile i
+// covers r in [i TR, (i+1) TR); descending, tile i covers r in
+// [top - (i+1) TR, top - i TR), with top the lane's own chunk length, or the
+// wave's longest chunk when an interleaved array is staged (then a lane with a
+// shorter chunk starts later, and the tile's rows are common to the wave).
+// Each lane takes the rows of a tile that lie in [0, hi - lo).
 //
 // Tile i of every array goes to buffer i % kTileBufs.  With two buffers the
 // order per tile is: wait for tile i's loads, barrier, issue tile i+1's loads
 // into the other buffer (whose tile i-1 every lane has finished with at the
 // barrier), step through tile i.  A vector tile spans VM band tiles and
 // alternates between its own two buffers the same way.
-template <int K, typename T, int NB, int NV, bool DESC, class Body>
+//
+// ILB / ILV: bit b set when band (vector) b is interleaved (FP64 only); a
+// vector is then interleaved like a band of one element per record.
+template <int K, typename T, int NB, int NV, bool DESC, unsigned ILB = 0u, unsigned ILV = 0u, class Body>
 __device__ __forceinline__ void stream_rows(const BandIn<T> (&bands)[NB > 0 ? NB : 1],
                                             const VecIn<T> (&vecs)[NV > 0 ? NV : 1], int64_t lo,
                                             int64_t hi, int64_t n, int64_t ld, Body &&body) {
@@ -216,6 +218,7 @@ __device__ __forceinline__ void stream_rows(const BandIn<T> (&bands)[NB > 0 ? NB
   constexpr int NB1 = NB > 0 ? NB : 1, NV1 = NV > 0 ? NV : 1;
   constexpr int NBUF = kTileBufs;
   static_assert(NBUF == 1 || NBUF == 2, "one or two tile buffers");
+  static_assert((ILB == 0u && ILV == 0u) || !MIXED, "interleaved arrays are FP64");
   using GB = Geom<T, W, TR>;
   using GD = Geom<double, 1, TR>;
   using GV = Geom<T, 1, VR>;
@@ -228,25 +231,26 @@ __device__ __forceinline__ void stream_rows(const BandIn<T> (&bands)[NB > 0 ? NB
   const int lane = threadIdx.x;
   const int64_t len = hi > lo ? hi - lo : 0;
   const int64_t maxlen = wave_max(len);
-  const int64_t top = maxlen;   // descending tiles count down from here
+  // Descending tiles count down from `top`: the wave's longest chunk when an
+  // interleaved array is staged (its tiles are blocks common to the wave),
+  // else each lane's own chunk end.
+  constexpr bool any_il = (ILB | ILV) != 0u;
+  const int64_t top = any_il ? maxlen : len;
   // Per band: where the lane's rows of the current tile start in LDS (bytes)
   // and the LDS distance between consecutive rows.  A segment band keeps the
   // lane's rows together (pitch per lane); an interleaved band keeps the
   // block as loaded (64 records per row).
-  int rbase[NBUF][NB1], dbase[NBUF][NB1], rstride[NB1];
-  int pv0[NV1], pv1[NV1], vstride[NV1];   // vector: lane's start (bytes) per buffer, row stride
+  int rbase[NBUF][NB1], dbase[NBUF][NB1];
+  int pv0[NV1], pv1[NV1];   // vector: lane's start (bytes) per buffer
   int64_t vb0 = 0, vb1 = 0;
+  auto band_il = [](int bi) constexpr { return ((ILB >> bi) & 1u) != 0u; };
+  auto vec_il = [](int vi) constexpr { return ((ILV >> vi) & 1u) != 0u; };
 #pragma unroll
-  for (int vi = 0; vi < NV1; ++vi) {
-    pv0[vi] = pv1[vi] = 0;
-    vstride[vi] = (NV > 0 && !MIXED && vecs[vi].il ? kWave : 1) * (int)sizeof(T);
-  }
+  for (int vi = 0; vi < NV1; ++vi) pv0[vi] = pv1[vi] = 0;
 #pragma unroll
-  for (int bi = 0; bi < NB1; ++bi) {
-    rstride[bi] = (NB > 0 && bands[bi].il ? kWave * W : W) * (int)sizeof(T);
+  for (int bi = 0; bi < NB1; ++bi)
 #pragma unroll
     for (int u = 0; u < NBUF; ++u) rbase[u][bi] = dbase[u][bi] = 0;
-  }
   // chunk-relative rows [r_lo, r_hi) of tile `it` (the wave's block) and the
   // lane's share [r_lo, min(r_hi, len)) of it
   auto tile_span = [&](int64_t it, int rows, int64_t &r_lo, int64_t &r_hi) {
@@ -269,7 +273,7 @@ __device__ __forceinline__ void stream_rows(const BandIn<T> (&bands)[NB > 0 ? NB
     const int64_t r0 = lo + r_lo;
 #pragma unroll
     for (int bi = 0; bi < NB; ++bi) {
-      if (!MIXED && bands[bi].il) {
+      if (band_il(bi)) {
         // the wave's block of rows [r_lo, r_hi) (shifted), every lane's slot
         const int64_t b0 = r_lo + bands[bi].shift;
         const int rows = (int)(r_hi - r_lo);
@@ -302,7 +306,7 @@ __device__ __forceinline__ void stream_rows(const BandIn<T> (&bands)[NB > 0 ? NB
         // buffer 1 of vector vi lies NV1 * GV::WORDS words past buffer 0
         uint32_t *vdst = &sv[0][vi][0] + (v1 ? (NBUF - 1) * NV1 * GV::WORDS : 0);
         int pv;
-        if (!MIXED && vecs[vi].il) {
+        if (vec_il(vi)) {
           const int rows = (int)(v_hi - v_lo);
           if (vecs[vi].p && rows > 0)
             il_fill(vdst, vecs[vi].p + (v_lo + vecs[vi].shift) * kWave, rows * kWave * (int)sizeof(T), lane);
@@ -326,18 +330,24 @@ __device__ __forceinline__ void stream_rows(const BandIn<T> (&bands)[NB > 0 ? NB
     const int64_t vbase = v1 ? vb1 : vb0;
     int64_t r_lo, r_hi;
     tile_span(it, TR, r_lo, r_hi);
+    // the lane's rows of the tile: [r_lo, r_lo + cnt), visited downwards when
+    // descending (the per-row work below is 32-bit)
+    const int64_t mine = (r_hi < len ? r_hi : len) - r_lo;
+    const int cnt = (int)(mine > 0 ? mine : 0);
+    const int64_t row0 = lo + r_lo;
 #pragma unroll 1
     for (int t = 0; t < TR; ++t) {
-      const int64_t r = DESC ? r_hi - 1 - t : r_lo + t;
-      if (r >= r_lo && r < r_hi && r < len) {
-        const int lr = (int)(r - r_lo);   // row within the tile
-        const int64_t j = lo + r;
+      if (t < cnt) {
+        const int lr = DESC ? cnt - 1 - t : t;   // row within the tile
+        const int64_t j = row0 + lr;
         double rec[NB1][K + 1];
         double val[NV1];
 #pragma unroll
         for (int bi = 0; bi < NB; ++bi) {
           const int64_t js = j + bands[bi].shift;
-          lds_cptr<T> row = (lds_cptr<T>)((lds_cptr<char>)(lds_ptr_t)sb[U][bi] + rbase[U][bi] + lr * rstride[bi]);
+          constexpr int rs0 = W * (int)sizeof(T);
+          const int rstride = band_il(bi) ? kWave * rs0 : rs0;
+          lds_cptr<T> row = (lds_cptr<T>)((lds_cptr<char>)(lds_ptr_t)sb[U][bi] + rbase[U][bi] + lr * rstride);
 #pragma unroll
           for (int d = 0; d <= K; ++d) {
             double x = (double)row[d];
@@ -351,7 +361,8 @@ __device__ __forceinline__ void stream_rows(const BandIn<T> (&bands)[NB > 0 ? NB
         for (int vi = 0; vi < NV; ++vi) {
           // buffer 1 of vector vi lies NV1 * GV::WORDS words past buffer 0
           const int voff = v1 ? (NBUF - 1) * NV1 * GV::WORDS * 4 + pv1[vi] : pv0[vi];
-          lds_cptr<char> vrow = (lds_cptr<char>)(lds_ptr_t)sv[0][vi] + voff + rv * vstride[vi];
+          const int vstride = (vec_il(vi) ? kWave : 1) * (int)sizeof(T);
+          lds_cptr<char> vrow = (lds_cptr<char>)(lds_ptr_t)sv[0][vi] + voff + rv * vstride;
           val[vi] = (vecs[vi].p && j + vecs[vi].shift < n) ? (double)*(lds_cptr<T>)vrow : 0.0;
         }
         body(j, rec, val);

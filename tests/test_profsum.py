@@ -16,8 +16,10 @@ KERN = os.path.join(HERE, "..", "paper_1902_10078_amd", "csrc", "bandops_kern.hi
 EXPECTED = {
     ("k_f1_sum", ("false",)): "f1_summary",
     ("k_f1_sum", ("true",)): "f1_summary",
-    ("k_f1_rep", ("false",)): "f1_replay",
-    ("k_f1_rep", ("true",)): "f1_replay",
+    ("k_f1_rep", ("false", "false")): "f1_replay",
+    ("k_f1_rep", ("false", "true")): "f1_replay",
+    ("k_f1_rep", ("true", "false", "false")): "f1_replay",
+    ("k_f1_rep", ("true", "true", "false")): "f1_replay",
     ("k_pc", ()): "chunk_product",
     ("k_fs", ("false", "false")): "fs_summary",
     ("k_fs", ("true", "false")): "fs_replay",
