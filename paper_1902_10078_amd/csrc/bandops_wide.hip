@@ -844,14 +844,14 @@ __global__ void __launch_bounds__(NT) k_wb1_rep(const Args A) {
     }
     lds_barrier();
     if (!last) {
-      // Pbar = 2 W P Sbar - W Ebar   (A2)
-      gemm64<false, false>(Wf, Pf, 1.f, [&](int i, int j, float v) { A1[i][j] = v; });
-      gemm64<false, false>(A1, Sf, 2.f, [&](int i, int j, float v) { A2[i][j] = v; });
-      gemm64<false, false>(Wf, EMf, -1.f, [&](int i, int j, float v) { A2[i][j] += v; });
-      // carry to block b+1: P Sbar P^T - Ebar P^T   (Cf)
-      gemm64<false, false>(Pf, Sf, 1.f, [&](int i, int j, float v) { A1[i][j] = v; });
-      gemm64<false, true>(A1, Pf, 1.f, [&](int i, int j, float v) { Cf[i][j] = v; });
-      gemm64<false, true>(EMf, Pf, -1.f, [&](int i, int j, float v) { Cf[i][j] += v; });
+      // U = P Sbar once: Pbar = W (2 U - Ebar) (A2) and the carry to block
+      // b+1, (U - Ebar) P^T (Cf, whose incoming value is consumed above)
+      gemm64<false, false>(Pf, Sf, 1.f, [&](int i, int j, float v) {
+        A1[i][j] = 2.f * v - EMf[i][j];
+        Cf[i][j] = v - EMf[i][j];
+      });
+      gemm64<false, false>(Wf, A1, 1.f, [&](int i, int j, float v) { A2[i][j] = v; });
+      gemm64<false, true>(Cf, Pf, 1.f, [&](int i, int j, float v) { Cf[i][j] = v; });
       // Mbar = Pbar X^T: Lbar's coupling block (upper triangle kept), in A1
       gemm64<false, true>(A2, Xf, 1.f, [&](int i, int j, float v) { A1[i][j] = v; });
       // Xbar = 2 X Sbar + M^T Pbar   (Wf)
@@ -932,11 +932,10 @@ template <bool REPLAY> __global__ void __launch_bounds__(NT) k_wb2(const Args A,
     if (!last) {
       // Mbar -= 2 Sc M   (Sc: adjoint of S_{b+1}, symmetric)
       gemm64<false, false>(Sc, Mf, -2.f, [&](int i, int j, float v) { MBf[i][j] += v; });
-      // Cbar = Mbar X (upper triangle kept) -> Qbar's coupling block (A2)
-      if (REPLAY) gemm64<false, false>(MBf, Xf, 1.f, [&](int i, int j, float v) { A2[i][j] = v; });
-      // Lbar_bb -= X^T (Mbar^T M)
-      gemm64<true, false>(MBf, Mf, 1.f, [&](int i, int j, float v) { A1[i][j] = v; });
-      gemm64<true, false>(Xf, A1, -1.f, [&](int i, int j, float v) { LBf[i][j] += v; });
+      // Cbar = Mbar X (its upper triangle is Qbar's coupling block, A2)
+      gemm64<false, false>(MBf, Xf, 1.f, [&](int i, int j, float v) { A2[i][j] = v; });
+      // Lbar_bb -= X^T Mbar^T M = Cbar^T M
+      gemm64<true, false>(A2, Mf, -1.f, [&](int i, int j, float v) { LBf[i][j] += v; });
     }
     // Phi(L^T Lbar) with Lbar's lower triangle: lower part, halved diagonal
     for (int e = threadIdx.x; e < NB * NB; e += NT) {
