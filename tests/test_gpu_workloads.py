@@ -286,3 +286,136 @@ def test_matern52_loss_full_size_sampled(bo):
         for i in range(3):
             e_ref = rel(rp["parts"][i], r["parts"][i])
             assert rel(parts[b, i], r["parts"][i]) <= max(TOL, 10 * e_ref), (b, i)
+
+
+def loss_kept(bo, plan, Qs, ys, Ss):
+    """The loss unit as the benchmark runs it: L, Sigma, Lbar (and z) kept in
+    the workspace.  Returns (per-problem loss, Qbar, ybar, Sbar)."""
+    Qt = dev(np.concatenate([q.ravel() for q in Qs]))
+    E, N, nb = Qt.numel(), sum(q.shape[0] for q in Qs), len(Qs)
+    kw = dict(Q=Qt, y=dev(np.concatenate(ys)), S=dev(np.concatenate([s.ravel() for s in Ss])),
+              x=torch.zeros(N, dtype=torch.float64, device="cuda"),
+              Qbar=torch.zeros(E, dtype=torch.float64, device="cuda"),
+              Sbar=torch.zeros(E, dtype=torch.float64, device="cuda"),
+              parts=torch.zeros((nb, 3), dtype=torch.float64, device="cuda"),
+              loss=torch.zeros(nb, dtype=torch.float64, device="cuda"),
+              info=torch.zeros(nb, dtype=torch.int32, device="cuda"))
+    plan.gauss_loss(0, plan.io(**kw))
+    torch.cuda.synchronize()
+    assert np.all(host(kw["info"]) == 0)
+    return host(kw["loss"]), host(kw["Qbar"]), host(kw["x"]), host(kw["Sbar"])
+
+
+def test_matern52_loss_full_size_kept_intermediates(bo):
+    """The benchmark's configuration (intermediates kept in the workspace) on
+    two full-size Matérn-5/2 problems (3e6 rows each) against the oracle."""
+    Qs, ys, Ss = [], [], []
+    for b in (0, 15):
+        Q, y, S, _ = inputs.config3_problem(b)
+        Qs.append(Q)
+        ys.append(y)
+        Ss.append(S)
+    ns = [q.shape[0] for q in Qs]
+    plan = bo.Plan(ns, [5, 5])
+    loss, Qbar, ybar, Sbar = loss_kept(bo, plan, Qs, ys, Ss)
+    for p in range(2):
+        n, k = ns[p], 5
+        r = oracle.gauss_loss(Qs[p], k, ys[p], Ss[p])
+        rp = oracle.gauss_loss(ulp_perturbed(Qs[p], 21 + p), k, ys[p], Ss[p])
+        o, v = plan.boff[p], plan.voff[p]
+        m = band_mask(n, k)
+        sig = r["Sig"].copy()
+        sig[:, 1:] *= 2.0
+        sigp = rp["Sig"].copy()
+        sigp[:, 1:] *= 2.0
+        for g, ref, refp in ((Qbar[o:o + n * (k + 1)].reshape(n, k + 1) * m, r["Qbar"] * m, rp["Qbar"] * m),
+                             (ybar[v:v + n], r["ybar"], rp["ybar"]),
+                             (Sbar[o:o + n * (k + 1)].reshape(n, k + 1) * m, sig * m, sigp * m)):
+            assert rel_err(g, ref) <= max(TOL, 10 * rel_err(refp, ref))
+        lr = r["parts"][0] - r["parts"][1] + r["parts"][2]
+        lp = rp["parts"][0] - rp["parts"][1] + rp["parts"][2]
+        assert rel(loss[p], lr) <= max(TOL, 10 * rel(lp, lr)), (p, loss[p], lr)
+
+
+def test_matern52_loss_full_size_finite_differences(bo):
+    """Derivatives of the full-size loss (one Matérn-5/2 problem of 3e6 rows,
+    the benchmark's configuration):
+    * y: the loss is quadratic in y, so a central difference along a random
+      direction is exact up to rounding;
+    * S: the loss is linear in S, likewise;
+    * Q, globally: the loss is homogeneous, f(cQ) = f(Q) + N log c with the
+      two quadratic-form terms scaled by 1/c, so sum Qbar * Q over the stored
+      band equals N + y^T Q^{-1} y - tr(Q^{-1} S) (Euler's identity);
+    * Q, locally: along the congruence Q(h) = (I + hD) Q (I + hD) with D a
+      random diagonal on a slice of 64 inputs (banded for every h, and its
+      curvature does not grow with the condition number of Q), whose tangent
+      at h = 0 has stored entries (d_i + d_j) Q_ij; a central difference
+      Richardson-extrapolated over two steps.  The loss is ~1e7 and these
+      derivatives ~1e2, so this check is limited to about 1e-3 relative."""
+    Q, y, S, _ = inputs.config3_problem(7)
+    n, k = Q.shape[0], 5
+    m = band_mask(n, k)
+    plan = bo.Plan([n], [k])
+    loss0, Qbar, ybar, Sbar = loss_kept(bo, plan, [Q], [y], [S])
+    Qbar, Sbar = Qbar.reshape(n, k + 1), Sbar.reshape(n, k + 1)
+    f = lambda Qh, yh, Sh: loss_kept(bo, plan, [Qh], [yh], [Sh])[0][0]
+    rng = np.random.default_rng(72)
+    # y and S: exact central differences
+    dy = rng.normal(size=n)
+    an = float(ybar @ dy)
+    fd = (f(Q, y + 1e-2 * dy, S) - f(Q, y - 1e-2 * dy, S)) / 2e-2
+    assert abs(fd - an) <= 1e-6 * abs(an), (fd, an)
+    dS = rng.normal(size=(n, k + 1)) * m
+    an = float(np.sum(Sbar * dS))
+    fd = (f(Q, y, S + dS) - f(Q, y, S - dS)) / 2.0
+    assert abs(fd - an) <= 1e-6 * abs(an), (fd, an)
+    # Q, globally: Euler's identity for the homogeneous loss
+    r = oracle.gauss_loss(Q, k, y, S)
+    euler = n + r["parts"][1] - r["parts"][2]
+    assert abs(float(np.sum(Qbar * Q * m)) - euler) <= 1e-8 * abs(euler)
+    # Q, locally: congruences on slices of 64 inputs
+    rows = np.arange(n)
+    for lo in (10_000, 1_500_000, n - 192):
+        d = np.zeros(n)
+        d[lo:lo + 192] = rng.normal(size=192)
+        di = np.stack([d[np.minimum(rows + s, n - 1)] * (rows + s < n) for s in range(k + 1)], axis=1)
+        dj = d[:, None]
+        an = float(np.sum(Qbar * (di + dj) * Q * m))
+        g = lambda h: f((1 + h * di) * (1 + h * dj) * Q * m, y, S)
+        cd = lambda h: (g(h) - g(-h)) / (2 * h)
+        best = min(abs((4 * cd(h / 2) - cd(h)) / 3 - an) for h in (0.02, 0.01))
+        assert best <= 1e-3 * abs(an), (lo, best, an)
+
+
+def test_matern52_loss_slice_dense_autograd(bo):
+    """The loss on a 64-input slice of a full-size Matérn-5/2 precision (its
+    leading 192 x 192 principal block) against torch dense autograd on the
+    CPU: the loss and its gradients in Q, y and S."""
+    Qf, yf, Sf, _ = inputs.config3_problem(3)
+    n, k = 192, 5
+    m = band_mask(n, k)
+    Q, y, S = Qf[:n] * m, yf[:n].copy(), Sf[:n] * m
+    plan = bo.Plan([n], [k])
+    loss, Qbar, ybar, Sbar = loss_kept(bo, plan, [Q], [y], [S])
+    Qc = torch.tensor(Q, dtype=torch.float64, requires_grad=True)
+    yc = torch.tensor(y, dtype=torch.float64, requires_grad=True)
+    Sc = torch.tensor(S, dtype=torch.float64, requires_grad=True)
+
+    def sym(B):
+        M = torch.zeros((n, n), dtype=torch.float64)
+        for d in range(k + 1):
+            M = M + torch.diag(B[: n - d, d], -d)
+            if d:
+                M = M + torch.diag(B[: n - d, d], d)
+        return M
+    Qd, Sd = sym(Qc), sym(Sc)
+    Qi = torch.linalg.inv(Qd)
+    lr = torch.logdet(Qd) - yc @ Qi @ yc + torch.trace(Qi @ Sd)
+    lr.backward()
+    # dense references carry the rounding of a 192 x 192 inverse of an
+    # ill-conditioned precision: cond(Q) eps relative
+    tol = max(1e-10, float(torch.linalg.cond(Qd.detach())) * 2.0 ** -52)
+    assert rel(loss[0], lr.item()) <= tol
+    assert rel_err(Qbar.reshape(n, k + 1) * m, Qc.grad.numpy() * m) <= tol
+    assert rel_err(ybar, yc.grad.numpy()) <= tol
+    assert rel_err(Sbar.reshape(n, k + 1) * m, Sc.grad.numpy() * m) <= tol
