@@ -146,6 +146,155 @@ __global__ void __launch_bounds__(kBlock) k_f1_sum(const Args A, int64_t count) 
   if (on) st.end_w(mw);
 }
 
+// ------------------------------------------- F1 summary, a quad per chunk
+// From K = 10 the summary's state (window correction C, coupling X of the
+// window to the boundary rows, boundary correction Z: three K x K blocks)
+// does not fit one lane's registers.  Here the four lanes of a quad share one
+// chunk: every lane keeps C and g (each needs the row's pivot and l), lane t
+// keeps columns f = t, t + 4, t + 8 of X and rows f of Z and e, and the row's
+// coupling values xf pass between the quad's lanes by DPP broadcasts.  Each
+// entry is computed as in F1SumStep (same operands and order), so the maps
+// are the same bits; records stream straight from global memory, the next
+// row's loaded behind the current row's work.
+constexpr int kQuad = 4;
+
+template <int S> __device__ __forceinline__ double quad_bcast(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), S * 0x55, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), S * 0x55, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+template <int K, typename T, bool DIAG>
+__global__ void __launch_bounds__(kBlock) k_f1_sum_q(const Args A, int64_t count) {
+  constexpr int K1 = Dim<K>::K1, NS = Dim<K>::NS, NF = (K + kQuad - 1) / kQuad, KK = K1 * K1;
+  static_assert(K >= kQuad, "the quad summary needs a column per lane");
+  const int t = threadIdx.x & (kQuad - 1);
+  const int64_t ci = (int64_t)blockIdx.x * (kBlock / kQuad) + (threadIdx.x / kQuad);
+  const bool active = ci < count;
+  const int32_t c = A.c_beg + (int32_t)(active ? ci : count - 1);
+  const ProbDesc pd = prob_at(A, prob_of_chunk(A, c));
+  int64_t a, b;
+  chunk_rows(pd, c, a, b);
+  const bool on = active && c != pd.chunk0 + pd.nchunk - 1;   // quad-uniform
+  const int64_t n = pd.n;
+  BandP<const T> Q = cband<T>(A.Q, A.Qd, pd);
+  const T *y = cvec<T>(A.y, pd);
+  const T *dn = DIAG ? cvec<T>(A.qdn, pd) : nullptr;
+  const double ds = DIAG ? qdiag_scale(A, pd) : 0.0;
+  double *w = A.f1map + (int64_t)c * A.sw_f1map;
+  double C[NS], g[K1], X[K1][NF], Z[NF][K1], e[NF];
+#pragma unroll
+  for (int i = 0; i < NS; ++i) C[i] = 0.0;
+#pragma unroll
+  for (int p = 0; p < K1; ++p) {
+    g[p] = 0.0;
+#pragma unroll
+    for (int i = 0; i < NF; ++i) X[p][i] = Z[i][p] = 0.0;
+  }
+#pragma unroll
+  for (int i = 0; i < NF; ++i) e[i] = 0.0;
+  auto rec_at = [&](int64_t j, double (&r)[K + 1]) {
+    load_rec<K, T>(Q.p, Q.diag, Q.ld, j, n, r);
+    if (DIAG) r[0] += (double)dn[j] * ds;
+  };
+  if (on) {
+    // boundary rows a .. a+K-1: lane t writes A = Q_FF and r = y_F for its
+    // columns f, and takes its columns of X = Q[a+K+p, a+f]
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+      const int f = t + kQuad * i;
+      if (f < K) {
+        double rec[K + 1];
+        rec_at(a + f, rec);
+#pragma unroll
+        for (int p = 0; p < K; ++p)
+          if (p >= f) w[p * K1 + f] = w[f * K1 + p] = rec[p >= f ? p - f : 0];
+#pragma unroll
+        for (int p = 0; p < K; ++p) X[p][i] = p <= f ? rec[K + (p <= f ? p - f : 0)] : 0.0;
+        w[3 * KK + f] = y ? (double)y[a + f] : 0.0;
+      }
+    }
+  }
+  const int64_t len = on ? b - a - K : 0;
+  const int64_t maxlen = tile::wave_max(len);
+  double qn[K + 1], yn = 0.0;
+  if (len > 0) {
+    rec_at(a + K, qn);
+    yn = y ? (double)y[a + K] : 0.0;
+  }
+#pragma unroll 1
+  for (int64_t r = 0; r < maxlen; ++r) {
+    if (r < len) {   // uniform over the quad
+      double q[K + 1];
+#pragma unroll
+      for (int d = 0; d <= K; ++d) q[d] = qn[d];
+      const double yi = yn;
+      if (r + 1 < len) {   // the next row's loads, behind this row's work
+        rec_at(a + K + r + 1, qn);
+        yn = y ? (double)y[a + K + r + 1] : 0.0;
+      }
+      const double s0 = q[0] - C[0];
+      const double lii = s0 > 0.0 ? sqrt(s0) : NAN;
+      const double inv = 1.0 / lii;
+      double l[K1], xo[NF], xf[K1];
+#pragma unroll
+      for (int p = 0; p < K; ++p) l[p] = ((p + 1 < K) ? q[p + 1] - C[six(p + 1, 0)] : q[K]) * inv;
+#pragma unroll
+      for (int i = 0; i < NF; ++i) xo[i] = X[0][i] * inv;
+      const double zt = (yi - g[0]) * inv;
+#pragma unroll
+      for (int h = 0; h < K; ++h) {   // xf[h] from the lane that owns column h
+        const double v = xo[h / kQuad];
+        if constexpr (true) {
+          switch (h % kQuad) {
+            case 0: xf[h] = quad_bcast<0>(v); break;
+            case 1: xf[h] = quad_bcast<1>(v); break;
+            case 2: xf[h] = quad_bcast<2>(v); break;
+            default: xf[h] = quad_bcast<3>(v); break;
+          }
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < NF; ++i) {
+        e[i] += xo[i] * zt;
+#pragma unroll
+        for (int h = 0; h < K; ++h) Z[i][h] += xo[i] * xf[h];
+      }
+#pragma unroll
+      for (int p = 0; p < K; ++p) {
+#pragma unroll
+        for (int i = 0; i < NF; ++i) X[p][i] = ((p + 1 < K) ? X[p + 1][i] : 0.0) - l[p] * xo[i];
+        g[p] = ((p + 1 < K) ? g[p + 1] : 0.0) + l[p] * zt;
+      }
+#pragma unroll
+      for (int p = 0; p < K; ++p)
+#pragma unroll
+        for (int h = 0; h <= p; ++h) C[six(p, h)] = ((p + 1 < K) ? C[six(p + 1, h + 1)] : 0.0) + l[p] * l[h];
+    }
+  }
+  if (on) {
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+      const int f = t + kQuad * i;
+      if (f < K) {
+#pragma unroll
+        for (int p = 0; p < K; ++p) {
+          w[p * K1 + f] -= Z[i][p];   // A = Q_FF - Z (Z symmetric)
+          w[KK + p * K1 + f] = -X[p][i];
+        }
+        w[3 * KK + f] -= e[i];
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < K; ++p)
+      if (p % kQuad == t) {
+#pragma unroll
+        for (int h = 0; h < K; ++h) w[2 * KK + p * K1 + h] = C[six(p, h)];
+        w[3 * KK + K1 + p] = g[p];
+      }
+  }
+}
+
 // PC: accumulates the chunk products (A.Pc); launched without it when A.Pc
 // is null.
 template <int K, typename T, bool DIAG, bool PC, bool IL>
@@ -629,10 +778,14 @@ int run_tiled(int step, const Args &a, int64_t count, hipStream_t s, dim3 grid, 
   constexpr int K = BO_K;
   switch (step) {
     case ST_F1_SUM:
-      if (a.qdn)
-        hipLaunchKernelGGL((k_f1_sum<K, T, true>), grid, block, 0, s, a, count);
-      else
-        hipLaunchKernelGGL((k_f1_sum<K, T, false>), grid, block, 0, s, a, count);
+      if constexpr (K >= 10) {   // a quad per chunk (the state spills from one lane)
+        const dim3 qgrid((unsigned)((count * kQuad + kBlock - 1) / kBlock));
+        if (a.qdn) hipLaunchKernelGGL((k_f1_sum_q<K, T, true>), qgrid, block, 0, s, a, count);
+        else hipLaunchKernelGGL((k_f1_sum_q<K, T, false>), qgrid, block, 0, s, a, count);
+      } else {
+        if (a.qdn) hipLaunchKernelGGL((k_f1_sum<K, T, true>), grid, block, 0, s, a, count);
+        else hipLaunchKernelGGL((k_f1_sum<K, T, false>), grid, block, 0, s, a, count);
+      }
       break;
     case ST_F1_REP:
       if (a.qdn) {

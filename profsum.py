@@ -32,6 +32,7 @@ CSRC = os.path.join(HERE, "paper_1902_10078_amd", "csrc")
 # rocprofv3 kernel name -> the library's profiling slot name
 _KERNEL_SLOTS = [
     (r"k_f1_sum<", "f1_summary"),
+    (r"k_f1_sum_q<", "f1_summary"),
     (r"k_f1_rep<", "f1_replay"),
     (r"k_pc<", "chunk_product"),
     (r"k_fs<\d+, \w+, false", "fs_summary"),

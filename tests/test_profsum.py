@@ -16,6 +16,8 @@ KERN = os.path.join(HERE, "..", "paper_1902_10078_amd", "csrc", "bandops_kern.hi
 EXPECTED = {
     ("k_f1_sum", ("false",)): "f1_summary",
     ("k_f1_sum", ("true",)): "f1_summary",
+    ("k_f1_sum_q", ("false",)): "f1_summary",
+    ("k_f1_sum_q", ("true",)): "f1_summary",
     ("k_f1_rep", ("false", "false")): "f1_replay",
     ("k_f1_rep", ("false", "true")): "f1_replay",
     ("k_f1_rep", ("true", "false", "false")): "f1_replay",
