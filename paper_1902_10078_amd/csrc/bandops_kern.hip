@@ -688,6 +688,163 @@ template <int K, bool DESC> __global__ void __launch_bounds__(kBlock) k_lin_capp
   lin_store<K>(A.lst + (int64_t)c * A.sw_lin, st);
 }
 
+// F1 group maps from K = 10, a quad per group: the group's chunk maps are
+// composed in order as in F1GroupCompose (f1_compose, same operations per
+// entry, so the same bits), with the accumulated map's A, B, D columns and r,
+// d rows q = t, t + 4, t + 8 in lane t of the quad.  Each step every lane
+// factors the shared block R = A2 - D1 (D1 gathered through LDS), solves for
+// its own columns of Y1 = R^{-1} B1 and Y2 = R^{-1} B2^T, and publishes them in
+// LDS for the products of its own output columns.  Inactive quads still take
+// every barrier.
+template <int K> __global__ void __launch_bounds__(kBlock) k_f1_gcomp_q(const Args A, int64_t count) {
+  constexpr int K1 = Dim<K>::K1, NF = (K + kQuad - 1) / kQuad, KK = K1 * K1;
+  constexpr int NQ = kBlock / kQuad;
+  // the quad's accumulated B and D, d (column q written by its owner) and
+  // this step's Y1, Y2
+  __shared__ double sB[NQ][K1][K1], sD[NQ][K1][K1], sd[NQ][K1], sY1[NQ][K1][K1], sY2[NQ][K1][K1];
+  const int t = threadIdx.x & (kQuad - 1), qi = threadIdx.x / kQuad;
+  const int64_t gi = (int64_t)blockIdx.x * NQ + qi;
+  const int32_t g = A.g_beg + (int32_t)(gi < count ? gi : count - 1);
+  const ProbDesc pd = prob_at(A, prob_of_group(A, g));
+  int32_t c0, c1;
+  group_chunks(pd, g, c0, c1);
+  const bool on = gi < count && g != pd.group0 + pd.ngroup - 1;   // the last group's map is never applied
+  const int nsteps = on ? c1 - c0 - 1 : 0;
+  int maxsteps = nsteps;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const int o = __shfl_xor(maxsteps, off, kBlock);
+    maxsteps = o > maxsteps ? o : maxsteps;
+  }
+  auto col = [&](int i) { return t + kQuad * i; };
+  // the accumulated map: A and r in registers (own columns / rows), B, D, d
+  // in LDS
+  double aA[K1][NF], ar[NF];
+  {
+    const double *w = A.f1map + (int64_t)c0 * A.sw_f1map;
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+      const int q = col(i) < K ? col(i) : 0;
+#pragma unroll
+      for (int p = 0; p < K1; ++p) aA[p][i] = on ? w[p * K1 + q] : 0.0;
+      ar[i] = on ? w[3 * KK + q] : 0.0;
+      if (col(i) < K) {
+#pragma unroll
+        for (int p = 0; p < K1; ++p) {
+          sB[qi][p][q] = on ? w[KK + p * K1 + q] : 0.0;
+          sD[qi][p][q] = on ? w[2 * KK + p * K1 + q] : 0.0;
+        }
+        sd[qi][q] = on ? w[3 * KK + K1 + q] : 0.0;
+      }
+    }
+  }
+#pragma unroll 1
+  for (int st = 0; st < maxsteps; ++st) {
+    const bool act = st < nsteps;   // uniform over the quad
+    const double *w2 = A.f1map + (int64_t)(c0 + 1 + (act ? st : 0)) * A.sw_f1map;
+    __syncthreads();   // the accumulated B, D, d of every lane are in LDS
+    double R[K1][K1], tv[K1][1];
+#pragma unroll
+    for (int p = 0; p < K1; ++p) {
+#pragma unroll
+      for (int q = 0; q < K1; ++q) R[p][q] = act ? w2[p * K1 + q] - sD[qi][p][q] : (p == q ? 1.0 : 0.0);
+      tv[p][0] = act ? w2[3 * KK + p] - sd[qi][p] : 0.0;
+    }
+    chol_small<K>(R);
+    trsm_small<K, 1>(R, tv);
+    double Y1[K1][NF], Y2[K1][NF];
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+      const int q = col(i) < K ? col(i) : 0;
+      double y1[K1][1], y2[K1][1];
+#pragma unroll
+      for (int p = 0; p < K1; ++p) {
+        y1[p][0] = sB[qi][p][q];
+        y2[p][0] = act ? w2[KK + q * K1 + p] : 0.0;   // B2^T, column q
+      }
+      trsm_small<K, 1>(R, y1);
+      trsm_small<K, 1>(R, y2);
+#pragma unroll
+      for (int p = 0; p < K1; ++p) {
+        Y1[p][i] = y1[p][0];
+        Y2[p][i] = y2[p][0];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NF; ++i)
+      if (col(i) < K) {
+#pragma unroll
+        for (int p = 0; p < K1; ++p) {
+          sY1[qi][p][col(i)] = Y1[p][i];
+          sY2[qi][p][col(i)] = Y2[p][i];
+        }
+      }
+    __syncthreads();   // Y1, Y2 complete; the reads of B, D, d are done
+    if (act) {
+#pragma unroll
+      for (int i = 0; i < NF; ++i) {
+        if (col(i) >= K) continue;
+        const int q = col(i);
+        // rows p = q of r and d use this lane's own columns of Y1, Y2
+        double rr = ar[i], dd = w2[3 * KK + K1 + q];
+#pragma unroll
+        for (int f = 0; f < K; ++f) {
+          rr += Y1[f][i] * tv[f][0];
+          dd -= Y2[f][i] * tv[f][0];
+        }
+        ar[i] = rr;
+        sd[qi][q] = dd;
+      }
+      // row p of the new A, B, D for every own column: each shared Y entry is
+      // read once per row; per entry the sums run over f in order
+#pragma unroll 1
+      for (int p = 0; p < K; ++p) {
+        double a[NF], bb[NF], dm[NF];
+#pragma unroll
+        for (int i = 0; i < NF; ++i) {
+          a[i] = aA[p][i];
+          bb[i] = 0.0;
+          dm[i] = w2[2 * KK + p * K1 + (col(i) < K ? col(i) : 0)];
+        }
+#pragma unroll
+        for (int f = 0; f < K; ++f) {
+          const double y1p = sY1[qi][f][p], y2p = sY2[qi][f][p];
+#pragma unroll
+          for (int i = 0; i < NF; ++i) {
+            a[i] -= y1p * Y1[f][i];
+            bb[i] += y2p * Y1[f][i];
+            dm[i] += y2p * Y2[f][i];
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < NF; ++i)
+          if (col(i) < K) {
+            aA[p][i] = a[i];
+            sB[qi][p][col(i)] = bb[i];
+            sD[qi][p][col(i)] = dm[i];
+          }
+      }
+    }
+  }
+  __syncthreads();
+  if (on) {
+    double *w = A.f1gmap + (int64_t)g * A.sw_f1map;
+#pragma unroll
+    for (int i = 0; i < NF; ++i)
+      if (col(i) < K) {
+        const int q = col(i);
+#pragma unroll
+        for (int p = 0; p < K1; ++p) {
+          w[p * K1 + q] = aA[p][i];
+          w[KK + p * K1 + q] = sB[qi][p][q];
+          w[2 * KK + p * K1 + q] = sD[qi][p][q];
+        }
+        w[3 * KK + q] = ar[i];
+        w[3 * KK + K1 + q] = sd[qi][q];
+      }
+  }
+}
+
 // F1: the last chunk of a problem has no map (nothing follows it), so neither
 // does the last group; they are never read.
 template <int K> __global__ void __launch_bounds__(kBlock) k_f1_gscan(const Args A, int64_t) {
@@ -777,6 +934,15 @@ template <typename T, bool IL>
 int run_tiled(int step, const Args &a, int64_t count, hipStream_t s, dim3 grid, dim3 block) {
   constexpr int K = BO_K;
   switch (step) {
+    case ST_F1_GCOMP:
+      if constexpr (K >= 10) {   // a quad per group (the maps spill from one lane)
+        const dim3 qgrid((unsigned)((count * kQuad + kBlock - 1) / kBlock));
+        hipLaunchKernelGGL((k_f1_gcomp_q<K>), qgrid, block, 0, s, a, count);
+      } else {
+        Launch<T> l{a, count, s};
+        return with_item<K, T>(step, l);
+      }
+      break;
     case ST_F1_SUM:
       if constexpr (K >= 10) {   // a quad per chunk (the state spills from one lane)
         const dim3 qgrid((unsigned)((count * kQuad + kBlock - 1) / kBlock));

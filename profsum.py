@@ -44,6 +44,7 @@ _KERNEL_SLOTS = [
     (r"k_b2<\d+, \w+, false", "b2_summary"),
     (r"k_b2<\d+, \w+, true", "b2_replay"),
     (r"k_f1_gscan", "f1_group_compose"),
+    (r"k_f1_gcomp_q", "f1_group_compose"),
     (r"k_f1_pscan", "f1_group_sweep"),
     (r"k_f1_capply", "f1_chunk_sweep"),
     (r"k_lin_gscan<\d+, true>", "desc_group_compose"),

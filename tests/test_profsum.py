@@ -37,6 +37,7 @@ EXPECTED = {
     ("k_b2", ("true", "false")): "b2_replay",
     ("k_b2", ("true", "true")): "b2_replay",
     ("k_f1_gscan", ()): "f1_group_compose",
+    ("k_f1_gcomp_q", ()): "f1_group_compose",
     ("k_f1_pscan", ()): "f1_group_sweep",
     ("k_f1_capply", ()): "f1_chunk_sweep",
     ("k_lin_gscan", ("true",)): "desc_group_compose",
@@ -59,7 +60,7 @@ def launched_kernels():
 
 def printed_name(name, bools, t):
     # as rocprofv3 prints an instantiation at K = 5
-    args = ["5"] + ([t] if name not in ("k_f1_gscan", "k_f1_pscan", "k_f1_capply") and
+    args = ["5"] + ([t] if name not in ("k_f1_gscan", "k_f1_pscan", "k_f1_capply", "k_f1_gcomp_q") and
                     not name.startswith("k_lin_") else []) + list(bools)
     return f"void (anonymous namespace)::{name}<{', '.join(args)}>(bo::Args, long)"
 
