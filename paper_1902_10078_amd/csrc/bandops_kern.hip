@@ -797,7 +797,7 @@ template <int K> __global__ void __launch_bounds__(kBlock) k_f1_gcomp_q(const Ar
       }
       // row p of the new A, B, D for every own column: each shared Y entry is
       // read once per row; per entry the sums run over f in order
-#pragma unroll 1
+#pragma unroll
       for (int p = 0; p < K; ++p) {
         double a[NF], bb[NF], dm[NF];
 #pragma unroll
@@ -842,6 +842,131 @@ template <int K> __global__ void __launch_bounds__(kBlock) k_f1_gcomp_q(const Ar
         w[3 * KK + q] = ar[i];
         w[3 * KK + K1 + q] = sd[qi][q];
       }
+  }
+}
+
+// Linear group maps from K = 10, a quad per group: the group's chunk maps
+// applied in order as in LinGroupCompose (lin_apply and mat_mul_acc, same
+// operations per entry, so the same bits).  The accumulated M and the group
+// product G live in LDS (column q written by lane q % 4), with the step's
+// chunk product P; every lane keeps the vector v.
+template <int K, bool DESC> __global__ void __launch_bounds__(kBlock) k_lin_gcomp_q(const Args A, int64_t count) {
+  constexpr int K1 = Dim<K>::K1, NF = (K + kQuad - 1) / kQuad;
+  constexpr int NQ = kBlock / kQuad;
+  __shared__ double sS[NQ][K1][K1], sG[NQ][K1][K1], sP[NQ][K1][K1];
+  const int t = threadIdx.x & (kQuad - 1), qi = threadIdx.x / kQuad;
+  const int64_t gi = (int64_t)blockIdx.x * NQ + qi;
+  const int32_t g = A.g_beg + (int32_t)(gi < count ? gi : count - 1);
+  const ProbDesc pd = prob_at(A, prob_of_group(A, g));
+  int32_t c0, c1;
+  group_chunks(pd, g, c0, c1);
+  const bool on = gi < count;
+  const int nsteps = on ? c1 - c0 : 0;
+  int maxsteps = nsteps;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const int o = __shfl_xor(maxsteps, off, kBlock);
+    maxsteps = o > maxsteps ? o : maxsteps;
+  }
+  auto col = [&](int i) { return t + kQuad * i; };
+  double v[K1];
+#pragma unroll
+  for (int p = 0; p < K1; ++p) v[p] = 0.0;
+#pragma unroll
+  for (int i = 0; i < NF; ++i)
+    if (col(i) < K)
+#pragma unroll
+      for (int p = 0; p < K1; ++p) {
+        sS[qi][p][col(i)] = 0.0;
+        sG[qi][p][col(i)] = p == col(i) ? 1.0 : 0.0;
+      }
+#pragma unroll 1
+  for (int st = 0; st < maxsteps; ++st) {
+    const bool act = st < nsteps;   // uniform over the quad
+    const int32_t c = act ? (DESC ? c1 - 1 - st : c0 + st) : c0;
+    const double *Pw = A.Pc + (int64_t)c * A.sw_mat;
+    const double *mw = A.lmap + (int64_t)c * A.sw_lin;
+#pragma unroll
+    for (int i = 0; i < NF; ++i)
+      if (col(i) < K)
+#pragma unroll
+        for (int p = 0; p < K1; ++p) sP[qi][p][col(i)] = Pw[p * K1 + col(i)];
+    __syncthreads();   // P complete (and the previous step's M, G)
+    double vn[K1], W[K1][NF], Gn[K1][NF];
+    if (act) {
+#pragma unroll
+      for (int p = 0; p < K; ++p) {
+        double acc = mw[K1 * K1 + p];
+#pragma unroll
+        for (int q = 0; q < K; ++q) acc += (DESC ? sP[qi][q][p] : sP[qi][p][q]) * v[q];
+        vn[p] = acc;
+      }
+      // row p of W and of the new G for every own column: each shared entry
+      // of row p is read once; per entry the sums run over r in order
+#pragma unroll
+      for (int p = 0; p < K; ++p) {
+        double w[NF], gg[NF];
+#pragma unroll
+        for (int i = 0; i < NF; ++i) w[i] = gg[i] = 0.0;
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+          const double s_pr = sS[qi][p][r];
+          const double g_pr = DESC ? sG[qi][p][r] : sP[qi][p][r];
+#pragma unroll
+          for (int i = 0; i < NF; ++i) {
+            const int q = col(i) < K ? col(i) : 0;
+            w[i] += s_pr * (DESC ? sP[qi][r][q] : sP[qi][q][r]);
+            gg[i] += DESC ? g_pr * sP[qi][r][q] : g_pr * sG[qi][r][q];
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < NF; ++i) {
+          W[p][i] = w[i];
+          Gn[p][i] = gg[i];
+        }
+      }
+    }
+    __syncthreads();   // every read of M and G is done
+    if (act) {
+#pragma unroll
+      for (int p = 0; p < K; ++p) v[p] = vn[p];
+#pragma unroll
+      for (int p = 0; p < K; ++p) {
+        double acc[NF];
+#pragma unroll
+        for (int i = 0; i < NF; ++i) acc[i] = mw[p * K1 + (col(i) < K ? col(i) : 0)];
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+          const double pr = DESC ? sP[qi][r][p] : sP[qi][p][r];
+#pragma unroll
+          for (int i = 0; i < NF; ++i) acc[i] += pr * W[r][i];
+        }
+#pragma unroll
+        for (int i = 0; i < NF; ++i)
+          if (col(i) < K) {
+            sS[qi][p][col(i)] = acc[i];
+            sG[qi][p][col(i)] = Gn[p][i];
+          }
+      }
+    }
+    __syncthreads();   // every read of P is done
+  }
+  if (on) {
+    double *Gw = A.Pg + (int64_t)g * A.sw_mat;
+    double *lw = A.lgmap + (int64_t)g * A.sw_lin;
+#pragma unroll
+    for (int i = 0; i < NF; ++i)
+      if (col(i) < K) {
+        const int q = col(i);
+#pragma unroll
+        for (int p = 0; p < K1; ++p) {
+          Gw[p * K1 + q] = sG[qi][p][q];
+          lw[p * K1 + q] = sS[qi][p][q];
+        }
+      }
+    if (t == 0)
+#pragma unroll
+      for (int p = 0; p < K1; ++p) lw[K1 * K1 + p] = v[p];
   }
 }
 
@@ -934,6 +1059,17 @@ template <typename T, bool IL>
 int run_tiled(int step, const Args &a, int64_t count, hipStream_t s, dim3 grid, dim3 block) {
   constexpr int K = BO_K;
   switch (step) {
+    case ST_ASC_GCOMP:
+    case ST_DESC_GCOMP:
+      if constexpr (K >= 10) {   // a quad per group (the maps spill from one lane)
+        const dim3 qgrid((unsigned)((count * kQuad + kBlock - 1) / kBlock));
+        if (step == ST_DESC_GCOMP) hipLaunchKernelGGL((k_lin_gcomp_q<K, true>), qgrid, block, 0, s, a, count);
+        else hipLaunchKernelGGL((k_lin_gcomp_q<K, false>), qgrid, block, 0, s, a, count);
+      } else {
+        Launch<T> l{a, count, s};
+        return with_item<K, T>(step, l);
+      }
+      break;
     case ST_F1_GCOMP:
       if constexpr (K >= 10) {   // a quad per group (the maps spill from one lane)
         const dim3 qgrid((unsigned)((count * kQuad + kBlock - 1) / kBlock));

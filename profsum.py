@@ -48,6 +48,8 @@ _KERNEL_SLOTS = [
     (r"k_f1_pscan", "f1_group_sweep"),
     (r"k_f1_capply", "f1_chunk_sweep"),
     (r"k_lin_gscan<\d+, true>", "desc_group_compose"),
+    (r"k_lin_gcomp_q<\d+, true>", "desc_group_compose"),
+    (r"k_lin_gcomp_q<\d+, false>", "asc_group_compose"),
     (r"k_lin_pscan<\d+, true>", "desc_group_sweep"),
     (r"k_lin_capply<\d+, true>", "desc_chunk_sweep"),
     (r"k_lin_gscan<\d+, false>", "asc_group_compose"),

@@ -38,6 +38,8 @@ EXPECTED = {
     ("k_b2", ("true", "true")): "b2_replay",
     ("k_f1_gscan", ()): "f1_group_compose",
     ("k_f1_gcomp_q", ()): "f1_group_compose",
+    ("k_lin_gcomp_q", ("true",)): "desc_group_compose",
+    ("k_lin_gcomp_q", ("false",)): "asc_group_compose",
     ("k_f1_pscan", ()): "f1_group_sweep",
     ("k_f1_capply", ()): "f1_chunk_sweep",
     ("k_lin_gscan", ("true",)): "desc_group_compose",
