@@ -970,6 +970,251 @@ template <int K, bool DESC> __global__ void __launch_bounds__(kBlock) k_lin_gcom
   }
 }
 
+// The sweeps from K = 10, a quad per unit (GROUPS: a problem walking its
+// groups, as F1GroupSweep / LinGroupSweep; else a group walking its chunks,
+// as F1ChunkSweep / LinChunkSweep): each unit's state is stored, then the
+// unit's map applied to it (f1_apply / lin_apply, same operations per entry,
+// so the same bits).  The state lives in LDS, column q written by lane q % 4.
+template <int K, bool GROUPS> __global__ void __launch_bounds__(kBlock) k_f1_sweep_q(const Args A, int64_t count) {
+  constexpr int K1 = Dim<K>::K1, NF = (K + kQuad - 1) / kQuad, KK = K1 * K1;
+  constexpr int NQ = kBlock / kQuad;
+  __shared__ double sC[NQ][K1][K1], sg[NQ][K1], sY[NQ][K1][K1];
+  const int t = threadIdx.x & (kQuad - 1), qi = threadIdx.x / kQuad;
+  const int64_t ui = (int64_t)blockIdx.x * NQ + qi;
+  const bool on = ui < count;
+  const int64_t uu = on ? ui : count - 1;
+  ProbDesc pd;
+  int32_t first, nunits, last_map;   // items [first, first + nunits); items < last_map have a map
+  const double *maps;
+  double *states;
+  int32_t g = 0;
+  if (GROUPS) {
+    pd = prob_at(A, A.p_beg + (int32_t)uu);
+    first = pd.group0;
+    nunits = pd.ngroup;
+    last_map = pd.group0 + pd.ngroup - 1;
+    maps = A.f1gmap;
+    states = A.f1gst;
+  } else {
+    g = A.g_beg + (int32_t)uu;
+    pd = prob_at(A, prob_of_group(A, g));
+    int32_t c0, c1;
+    group_chunks(pd, g, c0, c1);
+    first = c0;
+    nunits = c1 - c0;
+    last_map = pd.chunk0 + pd.nchunk - 1;
+    maps = A.f1map;
+    states = A.f1st;
+  }
+  const int nsteps = on ? nunits : 0;
+  int maxsteps = nsteps;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const int o = __shfl_xor(maxsteps, off, kBlock);
+    maxsteps = o > maxsteps ? o : maxsteps;
+  }
+  auto col = [&](int i) { return t + kQuad * i; };
+  {
+    const double *w0 = A.f1gst + (int64_t)g * A.sw_f1st;   // the group's entering state (chunk sweep)
+#pragma unroll
+    for (int i = 0; i < NF; ++i)
+      if (col(i) < K) {
+        const int q = col(i);
+#pragma unroll
+        for (int p = 0; p < K1; ++p) sC[qi][p][q] = (!GROUPS && on) ? w0[p * K1 + q] : 0.0;
+        sg[qi][q] = (!GROUPS && on) ? w0[KK + q] : 0.0;
+      }
+  }
+#pragma unroll 1
+  for (int st = 0; st < maxsteps; ++st) {
+    const bool act = st < nsteps;   // uniform over the quad
+    const int32_t u = first + (act ? st : 0);
+    __syncthreads();   // the state of every lane is in LDS
+    if (act) {   // store the state entering item u
+      double *w = states + (int64_t)u * A.sw_f1st;
+#pragma unroll
+      for (int i = 0; i < NF; ++i)
+        if (col(i) < K) {
+          const int q = col(i);
+#pragma unroll
+          for (int p = 0; p < K1; ++p) w[p * K1 + q] = sC[qi][p][q];
+          w[KK + q] = sg[qi][q];
+        }
+    }
+    const bool app = act && u < last_map;
+    const double *m = maps + (int64_t)(app ? u : first) * A.sw_f1map;
+    double R[K1][K1], tv[K1][1], Y[K1][NF];
+#pragma unroll
+    for (int p = 0; p < K1; ++p) {
+#pragma unroll
+      for (int q = 0; q < K1; ++q) R[p][q] = app ? m[p * K1 + q] - sC[qi][p][q] : (p == q ? 1.0 : 0.0);
+      tv[p][0] = app ? m[3 * KK + p] - sg[qi][p] : 0.0;
+    }
+    chol_small<K>(R);
+    trsm_small<K, 1>(R, tv);
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+      const int q = col(i) < K ? col(i) : 0;
+      double y[K1][1];
+#pragma unroll
+      for (int p = 0; p < K1; ++p) y[p][0] = app ? m[KK + q * K1 + p] : 0.0;   // B^T, column q
+      trsm_small<K, 1>(R, y);
+#pragma unroll
+      for (int p = 0; p < K1; ++p) Y[p][i] = y[p][0];
+    }
+#pragma unroll
+    for (int i = 0; i < NF; ++i)
+      if (col(i) < K)
+#pragma unroll
+        for (int p = 0; p < K1; ++p) sY[qi][p][col(i)] = Y[p][i];
+    __syncthreads();   // Y complete; every read of the state is done
+    if (app) {
+#pragma unroll
+      for (int i = 0; i < NF; ++i)
+        if (col(i) < K) {
+          double acc = m[3 * KK + K1 + col(i)];
+#pragma unroll
+          for (int f = 0; f < K; ++f) acc -= Y[f][i] * tv[f][0];
+          sg[qi][col(i)] = acc;
+        }
+#pragma unroll
+      for (int p = 0; p < K; ++p) {
+        double c[NF];
+#pragma unroll
+        for (int i = 0; i < NF; ++i) c[i] = m[2 * KK + p * K1 + (col(i) < K ? col(i) : 0)];
+#pragma unroll
+        for (int f = 0; f < K; ++f) {
+          const double yfp = sY[qi][f][p];
+#pragma unroll
+          for (int i = 0; i < NF; ++i) c[i] += yfp * Y[f][i];
+        }
+#pragma unroll
+        for (int i = 0; i < NF; ++i)
+          if (col(i) < K) sC[qi][p][col(i)] = c[i];
+      }
+    }
+    __syncthreads();   // every read of Y is done
+  }
+}
+
+template <int K, bool DESC, bool GROUPS>
+__global__ void __launch_bounds__(kBlock) k_lin_sweep_q(const Args A, int64_t count) {
+  constexpr int K1 = Dim<K>::K1, NF = (K + kQuad - 1) / kQuad;
+  constexpr int NQ = kBlock / kQuad;
+  __shared__ double sS[NQ][K1][K1], sP[NQ][K1][K1];
+  const int t = threadIdx.x & (kQuad - 1), qi = threadIdx.x / kQuad;
+  const int64_t ui = (int64_t)blockIdx.x * NQ + qi;
+  const bool on = ui < count;
+  const int64_t uu = on ? ui : count - 1;
+  ProbDesc pd;
+  int32_t first, nunits;
+  int32_t g = 0;
+  if (GROUPS) {
+    pd = prob_at(A, A.p_beg + (int32_t)uu);
+    first = pd.group0;
+    nunits = pd.ngroup;
+  } else {
+    g = A.g_beg + (int32_t)uu;
+    pd = prob_at(A, prob_of_group(A, g));
+    int32_t c0, c1;
+    group_chunks(pd, g, c0, c1);
+    first = c0;
+    nunits = c1 - c0;
+  }
+  const int nsteps = on ? nunits : 0;
+  int maxsteps = nsteps;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const int o = __shfl_xor(maxsteps, off, kBlock);
+    maxsteps = o > maxsteps ? o : maxsteps;
+  }
+  auto col = [&](int i) { return t + kQuad * i; };
+  double v[K1];
+  {
+    const double *w0 = A.lgst + (int64_t)g * A.sw_lin;   // the group's entering state (chunk sweep)
+#pragma unroll
+    for (int p = 0; p < K1; ++p) v[p] = (!GROUPS && on) ? w0[K1 * K1 + p] : 0.0;
+#pragma unroll
+    for (int i = 0; i < NF; ++i)
+      if (col(i) < K)
+#pragma unroll
+        for (int p = 0; p < K1; ++p) sS[qi][p][col(i)] = (!GROUPS && on) ? w0[p * K1 + col(i)] : 0.0;
+  }
+#pragma unroll 1
+  for (int st = 0; st < maxsteps; ++st) {
+    const bool act = st < nsteps;   // uniform over the quad
+    const int32_t u = act ? (DESC ? first + nunits - 1 - st : first + st) : first;
+    const bool app = act && (!GROUPS || st + 1 < nunits);
+    const double *Pw = (GROUPS ? A.Pg : A.Pc) + (int64_t)u * A.sw_mat;
+    const double *mw = (GROUPS ? A.lgmap : A.lmap) + (int64_t)u * A.sw_lin;
+    double *sw = (GROUPS ? A.lgst : A.lst) + (int64_t)u * A.sw_lin;
+#pragma unroll
+    for (int i = 0; i < NF; ++i)
+      if (col(i) < K)
+#pragma unroll
+        for (int p = 0; p < K1; ++p) sP[qi][p][col(i)] = app ? Pw[p * K1 + col(i)] : 0.0;
+    __syncthreads();   // P and the state of every lane are in LDS
+    if (act) {   // store the state entering item u
+#pragma unroll
+      for (int i = 0; i < NF; ++i)
+        if (col(i) < K)
+#pragma unroll
+          for (int p = 0; p < K1; ++p) sw[p * K1 + col(i)] = sS[qi][p][col(i)];
+      if (t == 0)
+#pragma unroll
+        for (int p = 0; p < K1; ++p) sw[K1 * K1 + p] = v[p];
+    }
+    double vn[K1], W[K1][NF];
+    if (app) {
+#pragma unroll
+      for (int p = 0; p < K; ++p) {
+        double acc = mw[K1 * K1 + p];
+#pragma unroll
+        for (int q = 0; q < K; ++q) acc += (DESC ? sP[qi][q][p] : sP[qi][p][q]) * v[q];
+        vn[p] = acc;
+      }
+#pragma unroll
+      for (int p = 0; p < K; ++p) {
+        double w[NF];
+#pragma unroll
+        for (int i = 0; i < NF; ++i) w[i] = 0.0;
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+          const double s_pr = sS[qi][p][r];
+#pragma unroll
+          for (int i = 0; i < NF; ++i) {
+            const int q = col(i) < K ? col(i) : 0;
+            w[i] += s_pr * (DESC ? sP[qi][r][q] : sP[qi][q][r]);
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < NF; ++i) W[p][i] = w[i];
+      }
+    }
+    __syncthreads();   // every read of the state is done
+    if (app) {
+#pragma unroll
+      for (int p = 0; p < K; ++p) v[p] = vn[p];
+#pragma unroll
+      for (int p = 0; p < K; ++p) {
+        double acc[NF];
+#pragma unroll
+        for (int i = 0; i < NF; ++i) acc[i] = mw[p * K1 + (col(i) < K ? col(i) : 0)];
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+          const double pr = DESC ? sP[qi][r][p] : sP[qi][p][r];
+#pragma unroll
+          for (int i = 0; i < NF; ++i) acc[i] += pr * W[r][i];
+        }
+#pragma unroll
+        for (int i = 0; i < NF; ++i)
+          if (col(i) < K) sS[qi][p][col(i)] = acc[i];
+      }
+    }
+    __syncthreads();   // every read of P is done
+  }
+}
+
 // F1: the last chunk of a problem has no map (nothing follows it), so neither
 // does the last group; they are never read.
 template <int K> __global__ void __launch_bounds__(kBlock) k_f1_gscan(const Args A, int64_t) {
@@ -1059,6 +1304,27 @@ template <typename T, bool IL>
 int run_tiled(int step, const Args &a, int64_t count, hipStream_t s, dim3 grid, dim3 block) {
   constexpr int K = BO_K;
   switch (step) {
+    case ST_F1_GSWEEP:
+    case ST_F1_CSWEEP:
+    case ST_ASC_GSWEEP:
+    case ST_ASC_CSWEEP:
+    case ST_DESC_GSWEEP:
+    case ST_DESC_CSWEEP:
+      if constexpr (K >= 10) {   // a quad per problem or group
+        const dim3 qgrid((unsigned)((count * kQuad + kBlock - 1) / kBlock));
+        switch (step) {
+          case ST_F1_GSWEEP: hipLaunchKernelGGL((k_f1_sweep_q<K, true>), qgrid, block, 0, s, a, count); break;
+          case ST_F1_CSWEEP: hipLaunchKernelGGL((k_f1_sweep_q<K, false>), qgrid, block, 0, s, a, count); break;
+          case ST_ASC_GSWEEP: hipLaunchKernelGGL((k_lin_sweep_q<K, false, true>), qgrid, block, 0, s, a, count); break;
+          case ST_ASC_CSWEEP: hipLaunchKernelGGL((k_lin_sweep_q<K, false, false>), qgrid, block, 0, s, a, count); break;
+          case ST_DESC_GSWEEP: hipLaunchKernelGGL((k_lin_sweep_q<K, true, true>), qgrid, block, 0, s, a, count); break;
+          default: hipLaunchKernelGGL((k_lin_sweep_q<K, true, false>), qgrid, block, 0, s, a, count); break;
+        }
+      } else {
+        Launch<T> l{a, count, s};
+        return with_item<K, T>(step, l);
+      }
+      break;
     case ST_ASC_GCOMP:
     case ST_DESC_GCOMP:
       if constexpr (K >= 10) {   // a quad per group (the maps spill from one lane)

@@ -46,6 +46,12 @@ _KERNEL_SLOTS = [
     (r"k_f1_gscan", "f1_group_compose"),
     (r"k_f1_gcomp_q", "f1_group_compose"),
     (r"k_f1_pscan", "f1_group_sweep"),
+    (r"k_f1_sweep_q<\d+, true>", "f1_group_sweep"),
+    (r"k_f1_sweep_q<\d+, false>", "f1_chunk_sweep"),
+    (r"k_lin_sweep_q<\d+, true, true>", "desc_group_sweep"),
+    (r"k_lin_sweep_q<\d+, true, false>", "desc_chunk_sweep"),
+    (r"k_lin_sweep_q<\d+, false, true>", "asc_group_sweep"),
+    (r"k_lin_sweep_q<\d+, false, false>", "asc_chunk_sweep"),
     (r"k_f1_capply", "f1_chunk_sweep"),
     (r"k_lin_gscan<\d+, true>", "desc_group_compose"),
     (r"k_lin_gcomp_q<\d+, true>", "desc_group_compose"),

@@ -41,6 +41,12 @@ EXPECTED = {
     ("k_lin_gcomp_q", ("true",)): "desc_group_compose",
     ("k_lin_gcomp_q", ("false",)): "asc_group_compose",
     ("k_f1_pscan", ()): "f1_group_sweep",
+    ("k_f1_sweep_q", ("true",)): "f1_group_sweep",
+    ("k_f1_sweep_q", ("false",)): "f1_chunk_sweep",
+    ("k_lin_sweep_q", ("true", "true")): "desc_group_sweep",
+    ("k_lin_sweep_q", ("true", "false")): "desc_chunk_sweep",
+    ("k_lin_sweep_q", ("false", "true")): "asc_group_sweep",
+    ("k_lin_sweep_q", ("false", "false")): "asc_chunk_sweep",
     ("k_f1_capply", ()): "f1_chunk_sweep",
     ("k_lin_gscan", ("true",)): "desc_group_compose",
     ("k_lin_pscan", ("true",)): "desc_group_sweep",
@@ -62,7 +68,8 @@ def launched_kernels():
 
 def printed_name(name, bools, t):
     # as rocprofv3 prints an instantiation at K = 5
-    args = ["5"] + ([t] if name not in ("k_f1_gscan", "k_f1_pscan", "k_f1_capply", "k_f1_gcomp_q") and
+    args = ["5"] + ([t] if name not in ("k_f1_gscan", "k_f1_pscan", "k_f1_capply", "k_f1_gcomp_q",
+                                                  "k_f1_sweep_q") and
                     not name.startswith("k_lin_") else []) + list(bools)
     return f"void (anonymous namespace)::{name}<{', '.join(args)}>(bo::Args, long)"
 
