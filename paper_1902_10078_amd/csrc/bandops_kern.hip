@@ -150,12 +150,16 @@ __global__ void __launch_bounds__(kBlock) k_f1_sum(const Args A, int64_t count) 
 // From K = 10 the summary's state (window correction C, coupling X of the
 // window to the boundary rows, boundary correction Z: three K x K blocks)
 // does not fit one lane's registers.  Here the four lanes of a quad share one
-// chunk: every lane keeps C and g (each needs the row's pivot and l), lane t
-// keeps columns f = t, t + 4, t + 8 of X and rows f of Z and e, and the row's
-// coupling values xf pass between the quad's lanes by DPP broadcasts.  Each
-// entry is computed as in F1SumStep (same operands and order), so the maps
-// are the same bits; records stream straight from global memory, the next
-// row's loaded behind the current row's work.
+// chunk, and the window's rows live in fixed slots: row u of the chunk's
+// sweep sits in slot (u - a - K) mod K, so advancing by a row rewrites the
+// leaving row's slot for the entering one and no register moves.  The row
+// loop is unrolled K times so every slot index is a constant.  Lane t keeps
+// the C rows and g entries of slots t, t + 4, t + 8 (C stored whole, both
+// triangles), columns f = t, t + 4, t + 8 of X for every slot, and rows f of
+// Z (in LDS) and e.  The pivot row's C and g come from their owner by DPP broadcasts,
+// as do the row's coupling values xf.  Each entry is computed as in
+// F1SumStep (same operands and order; a product of two l values in either
+// order is the same number), so the maps are the same bits.
 constexpr int kQuad = 4;
 
 template <int S> __device__ __forceinline__ double quad_bcast(double v) {
@@ -164,9 +168,16 @@ template <int S> __device__ __forceinline__ double quad_bcast(double v) {
   return __hiloint2double(hi, lo);
 }
 
+template <int I, int N, class F> __device__ __forceinline__ void unroll_each(F &&f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    unroll_each<I + 1, N>(f);
+  }
+}
+
 template <int K, typename T, bool DIAG>
-__global__ void __launch_bounds__(kBlock) k_f1_sum_q(const Args A, int64_t count) {
-  constexpr int K1 = Dim<K>::K1, NS = Dim<K>::NS, NF = (K + kQuad - 1) / kQuad, KK = K1 * K1;
+__global__ void __launch_bounds__(kBlock, 2) k_f1_sum_q(const Args A, int64_t count) {
+  constexpr int K1 = Dim<K>::K1, NF = (K + kQuad - 1) / kQuad, KK = K1 * K1;
   static_assert(K >= kQuad, "the quad summary needs a column per lane");
   const int t = threadIdx.x & (kQuad - 1);
   const int64_t ci = (int64_t)blockIdx.x * (kBlock / kQuad) + (threadIdx.x / kQuad);
@@ -182,24 +193,29 @@ __global__ void __launch_bounds__(kBlock) k_f1_sum_q(const Args A, int64_t count
   const T *dn = DIAG ? cvec<T>(A.qdn, pd) : nullptr;
   const double ds = DIAG ? qdiag_scale(A, pd) : 0.0;
   double *w = A.f1map + (int64_t)c * A.sw_f1map;
-  double C[NS], g[K1], X[K1][NF], Z[NF][K1], e[NF];
+  // Cs[i][v]: C(slot t + 4i, slot v); gs[i]: g of slot t + 4i; X[s][i]:
+  // X(slot s, column t + 4i)
+  // Z(t + 4i, h) in LDS (only accumulated, so it leaves the registers to the
+  // window state), lane-interleaved
+  __shared__ double sZ[NF * K1][kBlock];
+  double Cs[NF][K1], gs[NF], X[K1][NF], e[NF];
+  const int lane = threadIdx.x;
 #pragma unroll
-  for (int i = 0; i < NS; ++i) C[i] = 0.0;
+  for (int i = 0; i < NF; ++i) {
+    gs[i] = e[i] = 0.0;
 #pragma unroll
-  for (int p = 0; p < K1; ++p) {
-    g[p] = 0.0;
-#pragma unroll
-    for (int i = 0; i < NF; ++i) X[p][i] = Z[i][p] = 0.0;
+    for (int v = 0; v < K1; ++v) {
+      Cs[i][v] = X[v][i] = 0.0;
+      sZ[i * K1 + v][lane] = 0.0;
+    }
   }
-#pragma unroll
-  for (int i = 0; i < NF; ++i) e[i] = 0.0;
   auto rec_at = [&](int64_t j, double (&r)[K + 1]) {
     load_rec<K, T>(Q.p, Q.diag, Q.ld, j, n, r);
     if (DIAG) r[0] += (double)dn[j] * ds;
   };
   if (on) {
     // boundary rows a .. a+K-1: lane t writes A = Q_FF and r = y_F for its
-    // columns f, and takes its columns of X = Q[a+K+p, a+f]
+    // columns f, and takes its columns of X = Q[a+K+p, a+f] (slot p)
 #pragma unroll
     for (int i = 0; i < NF; ++i) {
       const int f = t + kQuad * i;
@@ -217,81 +233,129 @@ __global__ void __launch_bounds__(kBlock) k_f1_sum_q(const Args A, int64_t count
   }
   const int64_t len = on ? b - a - K : 0;
   const int64_t maxlen = tile::wave_max(len);
-  double qn[K + 1], yn = 0.0;
+  // a row's record as load_rec reads it (entries past the problem's end are
+  // zero), with the entry test in 32 bits on the stored values
+  // (the off-diagonal entries stay in the stored type until the row is used)
+  auto rec_next = [&](int64_t j, double &r0, T (&r)[K + 1]) {
+    const T *rp = Q.p + j * Q.ld;
+    const int lim = (int)(n - j < K + 1 ? n - j : K + 1);
+#pragma unroll
+    for (int d = 1; d <= K; ++d) r[d] = d < lim ? rp[d] : T(0);
+    r0 = Q.diag ? Q.diag[j] : (double)rp[0];
+    if (DIAG) r0 += (double)dn[j] * ds;
+  };
+  T qn[K + 1];
+  double qn0 = 0.0, yn = 0.0;
   if (len > 0) {
-    rec_at(a + K, qn);
+    rec_next(a + K, qn0, qn);
     yn = y ? (double)y[a + K] : 0.0;
   }
-#pragma unroll 1
-  for (int64_t r = 0; r < maxlen; ++r) {
-    if (r < len) {   // uniform over the quad
-      double q[K + 1];
+  // one row with the window's first row in slot PH
+  auto row = [&](auto phc, int64_t r) {
+    constexpr int PH = decltype(phc)::value;
+    if (r >= len) return;   // uniform over the quad
+    double q[K + 1];
+    q[0] = qn0;
 #pragma unroll
-      for (int d = 0; d <= K; ++d) q[d] = qn[d];
-      const double yi = yn;
-      if (r + 1 < len) {   // the next row's loads, behind this row's work
-        rec_at(a + K + r + 1, qn);
-        yn = y ? (double)y[a + K + r + 1] : 0.0;
-      }
-      const double s0 = q[0] - C[0];
-      const double lii = s0 > 0.0 ? sqrt(s0) : NAN;
-      const double inv = 1.0 / lii;
-      double l[K1], xo[NF], xf[K1];
-#pragma unroll
-      for (int p = 0; p < K; ++p) l[p] = ((p + 1 < K) ? q[p + 1] - C[six(p + 1, 0)] : q[K]) * inv;
-#pragma unroll
-      for (int i = 0; i < NF; ++i) xo[i] = X[0][i] * inv;
-      const double zt = (yi - g[0]) * inv;
-#pragma unroll
-      for (int h = 0; h < K; ++h) {   // xf[h] from the lane that owns column h
-        const double v = xo[h / kQuad];
-        if constexpr (true) {
-          switch (h % kQuad) {
-            case 0: xf[h] = quad_bcast<0>(v); break;
-            case 1: xf[h] = quad_bcast<1>(v); break;
-            case 2: xf[h] = quad_bcast<2>(v); break;
-            default: xf[h] = quad_bcast<3>(v); break;
-          }
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < NF; ++i) {
-        e[i] += xo[i] * zt;
-#pragma unroll
-        for (int h = 0; h < K; ++h) Z[i][h] += xo[i] * xf[h];
-      }
-#pragma unroll
-      for (int p = 0; p < K; ++p) {
-#pragma unroll
-        for (int i = 0; i < NF; ++i) X[p][i] = ((p + 1 < K) ? X[p + 1][i] : 0.0) - l[p] * xo[i];
-        g[p] = ((p + 1 < K) ? g[p + 1] : 0.0) + l[p] * zt;
-      }
-#pragma unroll
-      for (int p = 0; p < K; ++p)
-#pragma unroll
-        for (int h = 0; h <= p; ++h) C[six(p, h)] = ((p + 1 < K) ? C[six(p + 1, h + 1)] : 0.0) + l[p] * l[h];
+    for (int d = 1; d <= K; ++d) q[d] = (double)qn[d];
+    const double yi = yn;
+    if (r + 1 < len) {   // the next row's loads, behind this row's work
+      rec_next(a + K + r + 1, qn0, qn);
+      yn = y ? (double)y[a + K + r + 1] : 0.0;
     }
-  }
+    double cp[K1];   // C(slot PH, slot v): the leaving row's C, from its owner
+#pragma unroll
+    for (int v = 0; v < K; ++v) cp[v] = quad_bcast<PH % kQuad>(Cs[PH / kQuad][v]);
+    const double gp = quad_bcast<PH % kQuad>(gs[PH / kQuad]);
+    const double s0 = q[0] - cp[PH];
+    const double lii = s0 > 0.0 ? sqrt(s0) : NAN;
+    const double inv = 1.0 / lii;
+    // ls[v]: l of the row in slot v (window row p = (v - PH - 1) mod K after
+    // the step; slot PH takes the entering row, p = K - 1)
+    double ls[K1];
+#pragma unroll
+    for (int v = 0; v < K; ++v) {
+      const int p = (v - PH - 1 + 2 * K) % K;
+      ls[v] = ((p + 1 < K) ? q[p + 1] - cp[v] : q[K]) * inv;   // slot v holds window row p
+    }
+    double lo[NF];   // l of the lane's own slots t + 4i
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+      const int v0 = kQuad * i;
+      const double l0 = ls[v0 < K ? v0 : 0], l1 = ls[v0 + 1 < K ? v0 + 1 : 0];
+      const double l2 = ls[v0 + 2 < K ? v0 + 2 : 0], l3 = ls[v0 + 3 < K ? v0 + 3 : 0];
+      lo[i] = t == 0 ? l0 : t == 1 ? l1 : t == 2 ? l2 : l3;
+    }
+    double xo[NF], xf[K1];
+#pragma unroll
+    for (int i = 0; i < NF; ++i) xo[i] = X[PH][i] * inv;
+    const double zt = (yi - gp) * inv;
+#pragma unroll
+    for (int h = 0; h < K; ++h) {   // xf[h] from the lane that owns column h
+      const double v = xo[h / kQuad];
+      switch (h % kQuad) {
+        case 0: xf[h] = quad_bcast<0>(v); break;
+        case 1: xf[h] = quad_bcast<1>(v); break;
+        case 2: xf[h] = quad_bcast<2>(v); break;
+        default: xf[h] = quad_bcast<3>(v); break;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+      e[i] += xo[i] * zt;
+#pragma unroll
+      for (int h = 0; h < K; ++h) sZ[i * K1 + h][lane] += xo[i] * xf[h];
+    }
+#pragma unroll
+    for (int v = 0; v < K; ++v)
+#pragma unroll
+      for (int i = 0; i < NF; ++i) X[v][i] = (v == PH ? 0.0 : X[v][i]) - ls[v] * xo[i];
+    const bool own_ph = t == PH % kQuad;   // the lane whose slot PH / 4 is the leaving row's
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+      const bool fresh = i == PH / kQuad && own_ph;
+      gs[i] = (fresh ? 0.0 : gs[i]) + lo[i] * zt;
+#pragma unroll
+      for (int v = 0; v < K; ++v) {
+        if (i == PH / kQuad)
+          Cs[i][v] = ((fresh || v == PH) ? 0.0 : Cs[i][v]) + lo[i] * ls[v];
+        else
+          Cs[i][v] = (v == PH ? 0.0 : Cs[i][v]) + lo[i] * ls[v];
+      }
+    }
+  };
+#pragma unroll 1
+  for (int64_t r0 = 0; r0 < maxlen; r0 += K)
+    unroll_each<0, K>([&](auto phc) { row(phc, r0 + decltype(phc)::value); });
   if (on) {
+    const int ph = (int)(len % K);   // the window's first row is in slot ph
 #pragma unroll
     for (int i = 0; i < NF; ++i) {
       const int f = t + kQuad * i;
       if (f < K) {
 #pragma unroll
-        for (int p = 0; p < K; ++p) {
-          w[p * K1 + f] -= Z[i][p];   // A = Q_FF - Z (Z symmetric)
-          w[KK + p * K1 + f] = -X[p][i];
+        for (int p = 0; p < K; ++p) w[p * K1 + f] -= sZ[i * K1 + p][lane];   // A = Q_FF - Z (Z symmetric)
+#pragma unroll
+        for (int v = 0; v < K; ++v) {
+          const int p = v >= ph ? v - ph : v - ph + K;
+          w[KK + p * K1 + f] = -X[v][i];
         }
         w[3 * KK + f] -= e[i];
       }
     }
 #pragma unroll
-    for (int p = 0; p < K; ++p)
-      if (p % kQuad == t) {
+    for (int i = 0; i < NF; ++i) {
+      const int s = t + kQuad * i;
+      if (s < K) {
+        const int p = s >= ph ? s - ph : s - ph + K;
 #pragma unroll
-        for (int h = 0; h < K; ++h) w[2 * KK + p * K1 + h] = C[six(p, h)];
-        w[3 * KK + K1 + p] = g[p];
+        for (int v = 0; v < K; ++v) {
+          const int h = v >= ph ? v - ph : v - ph + K;
+          w[2 * KK + p * K1 + h] = Cs[i][v];
+        }
+        w[3 * KK + K1 + p] = gs[i];
       }
+    }
   }
 }
 

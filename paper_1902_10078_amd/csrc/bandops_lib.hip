@@ -253,6 +253,15 @@ const int32_t *env_kscale() {
   }();
   return any ? v : nullptr;
 }
+// Launch order of the bandwidth ranges (BANDOPS_RANGE_ORDER=desc: widest
+// first, a switch for schedule experiments; default narrowest first).
+bool ranges_widest_first() {
+  static bool v = [] {
+    const char *e = std::getenv("BANDOPS_RANGE_ORDER");
+    return e && std::strcmp(e, "desc") == 0;
+  }();
+  return v;
+}
 // First bandwidth whose chunk products get a pass of their own after the F1
 // replay (BANDOPS_PC_SEPARATE, a switch for schedule experiments; 13: never).
 int32_t pc_separate_from() {
@@ -798,7 +807,9 @@ static int run_ranges(const bo_plan *plan, hipStream_t stream, const Args &A, F 
     return pipe(be);
   }
   if (hipEventRecord(plan->fork, stream) != hipSuccess) return -2;
-  for (int r = 0; r < nr; ++r) {
+  const bool desc = ranges_widest_first();
+  for (int i = 0; i < nr; ++i) {
+    const int r = desc ? nr - 1 - i : i;
     hipStream_t st = r == 0 ? stream : plan->aux[r - 1];
     if (r > 0 && hipStreamWaitEvent(st, plan->fork, 0) != hipSuccess) return -2;
     GpuBE be{st};
