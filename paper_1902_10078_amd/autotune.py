@@ -17,7 +17,7 @@ from typing import Callable, Dict, Iterable, Optional
 
 import torch
 
-DEFAULT_CANDIDATES = (16384, 32768, 65536, 131072, 262144)
+DEFAULT_CANDIDATES = (16384, 32768, 65536, 131072, 196608, 262144)
 
 
 def shape_key(ns, ks, op: str, prec: int) -> str:

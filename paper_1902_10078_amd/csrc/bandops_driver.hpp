@@ -112,10 +112,24 @@ inline bool build_sched(const ProbIn *in, int nprob, int64_t target_chunks, int6
     }
     d.nchunk = p.n > 0 ? (int32_t)((p.n + d.clen - 1) / d.clen) : 0;
     d.chunk0 = c;
-    // Two-level scan: about sqrt(nchunk) chunks per group balances the serial
-    // work of a group's composition against that of the problem's group sweep.
+    // Two-level scan: a group's composition takes gsize serial steps and the
+    // problem's group sweep ngroup, so the group size is the power of two
+    // (up to the first one >= G, with at most G groups) that minimises
+    // gsize + ngroup.
     d.gsize = 1;
-    while (d.gsize < G && (int64_t)d.gsize * d.gsize < d.nchunk) d.gsize *= 2;
+    {
+      int32_t gmax = 1;   // the smallest power of two >= G
+      while (gmax < G) gmax *= 2;
+      int64_t best = -1;
+      for (int32_t gs = 1; gs <= gmax; gs *= 2) {
+        const int64_t ng = (d.nchunk + gs - 1) / gs;
+        if (ng > G && gs < gmax) continue;
+        if (best < 0 || gs + ng < best) {
+          best = gs + ng;
+          d.gsize = gs;
+        }
+      }
+    }
     d.ngroup = (d.nchunk + d.gsize - 1) / d.gsize;
     d.group0 = g;
     for (int32_t t = 0; t < d.nchunk; ++t) s.chunk_prob.push_back(ii);

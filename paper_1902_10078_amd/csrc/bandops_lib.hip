@@ -220,7 +220,7 @@ int64_t default_target_chunks() {
   static int64_t v = [] {
     const char *e = std::getenv("BANDOPS_TARGET_CHUNKS");
     long long t = e ? std::atoll(e) : 0;
-    return (int64_t)(t > 0 ? t : 131072);
+    return (int64_t)(t > 0 ? t : 196608);
   }();
   return v;
 }
