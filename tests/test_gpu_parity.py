@@ -428,6 +428,57 @@ def test_padded_record_stride(bo, n, k):
     assert bands_close(Sg[:, :k + 1], oracle.subset_inv(Lref, k), n, k, TOL)
 
 
+@pytest.mark.parametrize("n,k,prec", [(100003, 10, 0), (100003, 11, 0), (70001, 12, 0), (100003, 11, 1)])
+def test_quad_scans_same_bits_as_items(bo, n, k, prec):
+    """From k = 10 the packed path runs the F1 summaries, group composes and
+    sweeps on quads of lanes (fixed window slots in the summary); records with
+    a padded stride run the one-lane work items on the same schedule.  Both
+    compute every entry with the same operands in the same order, so the
+    factor, z, log det and subset inverse agree bit for bit (and with the
+    oracle)."""
+    import ctypes
+    print(f"case quad vs items n={n} k={k} prec={prec}", flush=True)
+    Q, y, _ = problem(n, k, 7000 + n + k)
+    Lref, _ = oracle.chol(Q, k)
+    vdt = torch.float64 if prec == 0 else torch.float32
+    bdt = vdt
+
+    def run(ld):
+        Qp = np.zeros((n, ld))
+        Qp[:, :k + 1] = Q
+        diag = dev(Q[:, 0]) if prec == 1 else None
+        Qb = bo.Band(dev(Qp, bdt), k, 0, diag)
+        Lb = bo.Band(torch.zeros((n, ld), dtype=bdt, device="cuda"), k, 0,
+                     torch.zeros(n, dtype=torch.float64, device="cuda") if prec == 1 else None)
+        Sb = bo.Band(torch.zeros((n, ld), dtype=bdt, device="cuda"), k, 0,
+                     torch.zeros(n, dtype=torch.float64, device="cuda") if prec == 1 else None)
+        yd, z = dev(y, vdt), torch.empty(n, dtype=vdt, device="cuda")
+        logdet = torch.zeros(1, dtype=torch.float64, device="cuda")
+        info = torch.zeros(1, dtype=torch.int32, device="cuda")
+        ws = bo.workspace(n, k)
+        qc, lc, sc = Qb.c(), Lb.c(), Sb.c()
+        bo._check(bo.lib().bo_chol(prec, ctypes.byref(qc), ctypes.byref(lc), bo._ptr(yd), bo._ptr(z),
+                                   bo._ptr(logdet), bo._ptr(info), bo._ptr(ws), ws.numel(),
+                                   bo._stream()), "bo_chol")
+        bo._check(bo.lib().bo_subset_inv(prec, ctypes.byref(lc), ctypes.byref(sc), bo._ptr(ws),
+                                         ws.numel(), bo._stream()), "bo_subset_inv")
+        torch.cuda.synchronize()
+        assert int(info.item()) == 0
+        out = {"L": host(Lb.band)[:, :k + 1], "S": host(Sb.band)[:, :k + 1], "z": host(z),
+               "logdet": logdet.item()}
+        if prec == 1:
+            out["Ld"], out["Sd"] = host(Lb.diag), host(Sb.diag)
+        return out
+
+    quad, items = run(k + 1), run(k + 3)
+    for nm in quad:
+        assert np.array_equal(np.asarray(quad[nm]), np.asarray(items[nm])), nm
+    tol = TOL if prec == 0 else TOL_MIXED
+    assert abs(quad["logdet"] - oracle.logdet(Lref, k)) <= tol * abs(oracle.logdet(Lref, k))
+    if prec == 0:
+        assert bands_close(quad["L"], Lref, n, k, tol)
+
+
 def test_graph_capture_forward_four_ranges_mixed(bo):
     """The forward list over problems of four bandwidths in the mixed format
     (each bandwidth range on its own stream, forked from and joined to the
