@@ -1060,9 +1060,10 @@ def main():
         cfg = {"workload": f"natgp_co2_batch{len(ns)}_weeks{args.t_ng}_rows{ns[0]}_k11_fwd_bwd",
                "batch": len(ns), "rows_per_problem": ns[0], "k": 11}
         nsample = args.cpu_sample or len(ns)   # the whole batch: a few seconds of one core
-        # At k = 11 every chunk is one lane's serial work; 65536 chunks (64 per
-        # problem) fill one round of resident waves (4 per CU on 256 CUs)
-        # exactly, measured best against 32768, 72704 and 131072.
+        # At k = 11 every chunk's replays are one lane's serial work; 65536
+        # chunks (64 per problem) fill one round of resident waves (4 per CU
+        # on 256 CUs) exactly, measured best against 32768, 72704, 98304,
+        # 131072 and 196608 (also with the summaries and scans on quads).
         if not args.target_chunks and not args.autotune:
             args.target_chunks = 65536
     elif vi:
