@@ -939,18 +939,51 @@ def cpu_baseline(host_inputs, ns, ks, nsample: int, vi: bool = False):
     Qf = np.concatenate([Qs[i].ravel() for i in idx])
     yf = np.concatenate([ys[i] for i in idx])
     t0 = time.perf_counter()
+    full = None
     if Ss is not None:
         Sf = np.concatenate([Ss[i].ravel() for i in idx])
         ref, _, _, _, threads = oracle.gauss_loss_batch(sn, sk, Qf, yf, Sf)
     else:
-        _, _, _, _, ref, _, threads = oracle.forward_batch(sn, sk, Qf, yf)
+        Lr, zr, xr, Sr, ref, _, threads = oracle.forward_batch(sn, sk, Qf, yf)
+        full = dict(L=Lr, z=zr, x=xr, Sig=Sr, logdet=ref)
     dt = time.perf_counter() - t0
     rows = sum(sn)
     # OpenMP runs one problem per thread: the threads in use are at most the problems
     used = min(threads, len(idx))
-    return dict(value=rows / dt, unit="band-rows/s", kind="oracle", **host_info(used),
-                sample=f"{len(idx)} of the workload's {len(ns)} problems ({rows} rows), FP64 C oracle, "
-                       f"OpenMP across problems ({threads} threads, {used} busy), {dt:.2f} s wall"), ref
+    cb = dict(value=rows / dt, unit="band-rows/s", kind="oracle", **host_info(used),
+              sample=f"{len(idx)} of the workload's {len(ns)} problems ({rows} rows), FP64 C oracle, "
+                     f"OpenMP across problems ({threads} threads, {used} busy), {dt:.2f} s wall")
+    if full is not None:
+        cb["_full"] = full
+    return cb, ref
+
+
+def forward_output_errors(bo, kw, prec, ns, ks, full):
+    """Per-output error of the forward list on the oracle's sample (the first
+    problems of the batch): max |gpu - oracle| / max |oracle| for L, z, x and
+    Sigma, and the largest relative log-det error.  Mixed bands are compared
+    with their FP64 diagonals in slot 0."""
+    m = len(full["logdet"])
+    sn, sk = np.asarray(ns[:m], dtype=np.int64), np.asarray(ks[:m], dtype=np.int64)
+    E, N = int(np.sum(sn * (sk + 1))), int(np.sum(sn))
+    boff = np.concatenate([[0], np.cumsum(sn * (sk + 1))[:-1]])
+    pos = np.concatenate([boff[b] + np.arange(sn[b]) * (sk[b] + 1) for b in range(m)]) if N else np.zeros(0, int)
+
+    def band(nm):
+        g = kw[nm][:E].double().cpu().numpy()
+        if prec == bo.MIXED:
+            g[pos] = kw[nm + "d"][:N].cpu().numpy()
+        return g
+
+    def rel(g, r):
+        den = np.max(np.abs(r)) if r.size else 0.0
+        return float(np.max(np.abs(g - r)) / den) if den > 0 else 0.0
+
+    ld = kw["logdet"][:m].cpu().numpy()
+    return {"L": rel(band("L"), full["L"]), "Sig": rel(band("Sig"), full["Sig"]),
+            "z": rel(kw["z"][:N].double().cpu().numpy(), full["z"]),
+            "x": rel(kw["x"][:N].double().cpu().numpy(), full["x"]),
+            "logdet": float(np.max(np.abs(ld - full["logdet"]) / np.maximum(np.abs(full["logdet"]), 1e-300)))}
 
 
 def main():
@@ -1030,7 +1063,7 @@ def main():
         ns, ks, host_inputs = make_uneven(args, bo, torch, dev)
         cfg = {"workload": f"uneven_batch{len(ns)}_n256-65536_k1-3-5-11_forward",
                "batch": len(ns), "rows": sum(ns), "k": "1,3,5,11"}
-        nsample = args.cpu_sample or 256
+        nsample = args.cpu_sample or len(ns)   # the whole batch, OpenMP across problems
     elif alg5:
         ns, ks, host_inputs, widths = make_alg5(args)
         cfg = {"workload": f"solve_band_mat_rows{ns[0]}_k5_R2-5_fwd_bwd", "batch": 1,
@@ -1306,6 +1339,10 @@ def main():
         src = W.kw["logdet"] if forward_only else W.kw["parts"]
         gp = src.cpu().numpy()[: len(ref)]
         cb["max_rel_diff_vs_gpu"] = float(np.max(np.abs(gp - ref) / np.maximum(np.abs(ref), 1e-300)))
+        full = cb.pop("_full", None)
+        if full is not None and forward_only:
+            out["rel_err_vs_oracle"] = dict(forward_output_errors(bo, W.kw, prec, ns, ks, full),
+                                            sample=f"the first {len(ref)} problems")
         out["cpu_baseline"] = cb
         log(f"cpu baseline: {cb}")
     print(json.dumps(out), flush=True)
