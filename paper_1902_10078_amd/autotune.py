@@ -20,12 +20,23 @@ import torch
 DEFAULT_CANDIDATES = (16384, 32768, 65536, 131072, 196608, 262144)
 
 
-def shape_key(ns, ks, op: str, prec: int) -> str:
-    """Batch signature: problem count, total rows (2 significant digits) and
-    the set of bandwidths, plus the operation and storage format."""
+def device_arch() -> str:
+    """The current device's architecture name (gfx950 on MI355X), or "cpu"."""
+    if not torch.cuda.is_available():
+        return "cpu"
+    props = torch.cuda.get_device_properties(torch.cuda.current_device())
+    return getattr(props, "gcnArchName", props.name).split(":")[0]
+
+
+def shape_key(ns, ks, op: str, prec: int, arch: Optional[str] = None) -> str:
+    """Batch signature: device architecture, problem count, total rows (2
+    significant digits) and the set of bandwidths, plus the operation and
+    storage format."""
+    arch = device_arch() if arch is None else arch
     rows = sum(int(n) for n in ns)
     mag = 10 ** max(int(math.log10(rows)) - 1, 0) if rows > 0 else 1
-    return f"{op}|p{prec}|np{len(ns)}|rows{round(rows / mag) * mag}|k{','.join(map(str, sorted(set(ks))))}"
+    return (f"{arch}|{op}|p{prec}|np{len(ns)}|rows{round(rows / mag) * mag}"
+            f"|k{','.join(map(str, sorted(set(ks))))}")
 
 
 def time_step(step: Callable[[], None], reps: int = 3) -> float:

@@ -11,6 +11,9 @@ def test_shape_key_groups_similar_batches():
     assert a == b
     assert a != autotune.shape_key([1000, 2000], [3, 5], "op", 1)
     assert a != autotune.shape_key([1000, 2000, 5], [3, 5, 5], "op", 0)
+    assert a != autotune.shape_key([1000, 2000], [3, 5], "other", 0)
+    gfx = autotune.shape_key([1000, 2000], [3, 5], "op", 0, arch="gfx950")
+    assert gfx.startswith("gfx950|") and gfx != autotune.shape_key([1000, 2000], [3, 5], "op", 0, arch="gfx942")
 
 
 def test_cached_result_is_used_without_measuring(tmp_path):
