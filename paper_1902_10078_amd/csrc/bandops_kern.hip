@@ -638,9 +638,9 @@ __global__ void __launch_bounds__(kBlock) k_b2(const Args A, int64_t count) {
 // The chunk summaries of a pass are combined by parallel prefix scans of
 // depth log2(64): one wavefront per group scans its chunks' maps, one per
 // problem scans the group totals, and every chunk then applies its exclusive
-// prefix to its group's entering state.  (The serial work items do the same
-// with depth 64 per level.)  A map travels between lanes through LDS, 64
-// doubles per lane at a time.
+// prefix to its group's entering state.  (The serial work items and, from
+// K = 10, the quad kernels do the same with one step per chunk or group.)  A
+// map travels between lanes through LDS, 64 doubles per lane at a time.
 constexpr int kXch = 64;
 
 template <int N>
@@ -1496,7 +1496,8 @@ template <typename T> int run_step(int step, const Args &a, int64_t count, hipSt
   // Above K = 6 the maps spill in both forms; measured on gfx950 the
   // wavefront scans still win at K = 9 (a 16-problem batch of 10^6 rows:
   // 12 ms of scans down to 4.5) and lose at K = 11 (5 KB of scratch per
-  // lane), so K = 10 and up stay with the serial work items.
+  // lane), so K = 10 and up run on quads of lanes (run_tiled), or as serial
+  // work items for records with a padded stride.
   if (K <= 9 && a.G <= kBlock) {
     const dim3 wg((unsigned)count);
     switch (step) {
