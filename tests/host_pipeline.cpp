@@ -88,6 +88,21 @@ Outputs run(const std::vector<ProbIn> &probs, const std::vector<double> &Q, cons
     std::fprintf(stderr, "bad schedule\n");
     std::exit(2);
   }
+  // every problem's group size is a power of two with at most G = 8 groups
+  // whose two serial lengths, gsize + ngroup, no other such size beats
+  for (const ProbDesc &d : s.probs) {
+    const int64_t ng = d.nchunk > 0 ? (d.nchunk + d.gsize - 1) / d.gsize : 0;
+    bool ok = d.gsize >= 1 && d.gsize <= 8 && (d.gsize & (d.gsize - 1)) == 0 && d.ngroup == ng &&
+              (d.ngroup <= 8 || d.gsize == 8);
+    for (int32_t g = 1; g <= 8; g *= 2) {
+      const int64_t n2 = (d.nchunk + g - 1) / g;
+      if ((n2 <= 8 || g == 8) && g + n2 < d.gsize + d.ngroup) ok = false;
+    }
+    if (!ok) {
+      std::fprintf(stderr, "group size %d for %d chunks (%d groups)\n", d.gsize, d.nchunk, d.ngroup);
+      std::exit(2);
+    }
+  }
   std::vector<unsigned char> ws(s.bytes);
   std::memcpy(ws.data() + s.off_tables, s.table_blob.data(), s.table_blob.size());
   Outputs o;
